@@ -1,0 +1,718 @@
+/*
+ * DSMC oracle: a plain, sequential, FP64 implementation of one time step of
+ * unsteady DSMC -- Generation, Motion, Enumeration/Indexing, Interaction and
+ * Sampling -- in the order of the sequential algorithm of Sec. 1.1 (the
+ * "general flowchart of sequential algorithm" figure) of Bogdanov, Bykov,
+ * Grishin, Khanlarov, Lukianov and Zakharov, "Algorithms of Two-Level
+ * Parallelization for DSMC of Unsteady Flows in Molecular Gasdynamics".
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke entry point and
+ * the CPU-baseline leg of the benchmark may load this library.  It shares no
+ * code, header, table or constant generator with the GPU library.
+ *
+ * What the paper fixes (Sec. 1.1): the step order; the particle array P
+ * (coordinates, velocity); the readdressing array LCR built from the cell of
+ * every particle after the particle stage; the cell array C; removal of
+ * particles that leave the domain and insertion of generated ones each step;
+ * runs made independent by shifting the random number generator.  The
+ * kinetics the paper leaves to the DSMC literature it cites (Bird 1994) are
+ * written here from the mathematics:
+ *   - no-time-counter (NTC) pair selection with a per-cell remainder and an
+ *     immediate update of (sigma*c_r)_max;
+ *   - hard-sphere / variable-hard-sphere cross sections, isotropic scattering;
+ *   - specular and diffuse (full accommodation) walls, vacuum outflow, and
+ *     inflow of a drifting Maxwellian through the -x face.
+ * Random numbers come from the counter-based generator Philox4x32-10 of
+ * Salmon, Moraes, Dror and Shaw (SC'11), written from its published
+ * definition.  Build with -O2 -ffp-contract=off (no fast-math).
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_BC_SPECULAR 0
+#define OR_BC_DIFFUSE 1
+#define OR_BC_INFLOW 2
+#define OR_BC_OUTFLOW 3
+
+#define OR_OK 0
+#define OR_EINVAL -1
+#define OR_ECAPACITY -3
+#define OR_EBOUNCE -7
+#define OR_EREJECT -8
+#define OR_ENOMEM -9
+#define OR_EUNSUPPORTED -6
+
+#define PURPOSE_INIT 0u
+#define PURPOSE_GEN 1u
+#define PURPOSE_WALL 2u
+#define PURPOSE_COLL 3u
+
+#define MAX_WALL_HITS 64
+#define MAX_GEN_ATTEMPTS 1000
+#define MAX_INIT_ATTEMPTS 100
+
+static const double TWO_PI = 6.283185307179586476925286766559;
+static const double SQRT_PI = 1.7724538509055160272981674833411;
+
+typedef struct {
+    int32_t dim, nx, ny, nz;
+    double lx, ly, lz;
+    double dt;
+    double fnum_sigma;
+    double omega, c_ref;
+    int32_t face_bc[6];
+    double face_T[6];
+    double inflow_n, inflow_U, inflow_T;
+    const uint8_t *solid;
+    double solid_T;
+    int64_t capacity;
+    int64_t n_init;
+    double init_U[3];
+    double init_T;
+    uint32_t run_id, seed;
+} or_spec;
+
+typedef struct {
+    or_spec sp;
+    int64_t nc;          /* cells; the DEAD bin is nc */
+    int64_t nface;       /* inflow face elements, 0 without inflow */
+    double L[3];
+    double inv_d[3];     /* cells per unit length along each axis */
+    double coef;         /* Fnum*sigma_ref*dt/V_c */
+    double vhs_exp;      /* 1 - 2 omega */
+    double gmax0;
+    double mbar;         /* mean number entering through one face element per step */
+    double beta, s_inf, p_branch, dy, dz;
+    int64_t n;           /* particles in P */
+    double *p[6];        /* x, y, z, u, v, w (z is 0 in 2-D) */
+    double *q[6];        /* scratch for the permutation */
+    int32_t *cell;       /* cell of each slot after Motion (nc = DEAD) */
+    int32_t *lcr;        /* readdressing array */
+    int64_t n_sorted;    /* number of entries of lcr (particles before removal) */
+    int64_t *cstart;     /* nc + 2 */
+    int64_t *ccount;     /* nc + 1 */
+    double *rem_c, *gmax;
+    int64_t *ncoll;
+    double *rem_f;
+    uint32_t step;
+    int32_t err;
+    int64_t last_ncoll, last_ngen, last_nremoved, last_nmoved;
+} or_run;
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon et al., SC'11)                                       */
+/* ------------------------------------------------------------------------- */
+
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Uniform in (0,1) from two 32-bit words: 52 random bits, centred. */
+double or_u01(uint32_t a, uint32_t b)
+{
+    uint64_t m = ((uint64_t)a << 20) | (uint64_t)(b >> 12);
+    return ((double)m + 0.5) * 0x1p-52;
+}
+
+/* Index in [0, n) from one 32-bit word. */
+uint32_t or_index(uint32_t a, uint32_t n)
+{
+    return (uint32_t)(((uint64_t)a * (uint64_t)n) >> 32);
+}
+
+/* A stream of uniforms for one (key, step, purpose, index): uniform number k
+ * comes from block k/2, words 2(k%2) and 2(k%2)+1. */
+typedef struct {
+    uint32_t key[2];
+    uint32_t c0, c1, c2;
+    uint64_t next;
+} ustream;
+
+static double us_next(ustream *s)
+{
+    uint32_t ctr[4] = {s->c0, s->c1, s->c2, (uint32_t)(s->next >> 1)};
+    uint32_t blk[4];
+    or_philox4x32_10(ctr, s->key, blk);
+    int h = (int)(s->next & 1u);
+    s->next++;
+    return or_u01(blk[2 * h], blk[2 * h + 1]);
+}
+
+static void box_muller(double u1, double u2, double *n0, double *n1)
+{
+    double r = sqrt(-2.0 * log(u1));
+    double th = TWO_PI * u2;
+    *n0 = r * cos(th);
+    *n1 = r * sin(th);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Run set-up                                                                 */
+/* ------------------------------------------------------------------------- */
+
+static int64_t axis_index(double x, double inv, int32_t n)
+{
+    double f = floor(x * inv);
+    if (!(f > 0.0)) return 0;
+    if (f >= (double)(n - 1)) return n - 1;
+    return (int64_t)f;
+}
+
+static int64_t cell_of(const or_run *R, const double pos[3])
+{
+    int64_t ix = axis_index(pos[0], R->inv_d[0], R->sp.nx);
+    int64_t iy = axis_index(pos[1], R->inv_d[1], R->sp.ny);
+    int64_t iz = (R->sp.dim == 3) ? axis_index(pos[2], R->inv_d[2], R->sp.nz) : 0;
+    return (iz * R->sp.ny + iy) * R->sp.nx + ix;
+}
+
+/* g = sigma(c_r)/sigma_ref * c_r for HS / VHS. */
+static double g_of(const or_run *R, double cr)
+{
+    if (R->sp.omega == 0.5) return cr;
+    if (!(cr > 0.0)) return 0.0;
+    return cr * pow(cr / R->sp.c_ref, R->vhs_exp);
+}
+
+void or_run_free(or_run *R)
+{
+    if (!R) return;
+    for (int a = 0; a < 6; ++a) {
+        free(R->p[a]);
+        free(R->q[a]);
+    }
+    free(R->cell); free(R->lcr); free(R->cstart); free(R->ccount);
+    free(R->rem_c); free(R->gmax); free(R->ncoll); free(R->rem_f);
+    free(R);
+}
+
+or_run *or_run_new(const or_spec *sp, int32_t *status)
+{
+    *status = OR_OK;
+    if (sp->dim != 2 && sp->dim != 3) { *status = OR_EINVAL; return NULL; }
+    if (sp->nx < 1 || sp->ny < 1 || sp->nz < 1 || (sp->dim == 2 && sp->nz != 1)) {
+        *status = OR_EINVAL; return NULL;
+    }
+    if (!(sp->dt > 0.0) || sp->capacity < sp->n_init || sp->n_init < 0) {
+        *status = OR_EINVAL; return NULL;
+    }
+    if (sp->solid) { *status = OR_EUNSUPPORTED; return NULL; }
+    for (int f = 0; f < 6; ++f) {
+        int bc = sp->face_bc[f];
+        if (bc < 0 || bc > 3) { *status = OR_EINVAL; return NULL; }
+        if (bc == OR_BC_INFLOW && f != 0) { *status = OR_EINVAL; return NULL; }
+    }
+    or_run *R = (or_run *)calloc(1, sizeof(or_run));
+    if (!R) { *status = OR_ENOMEM; return NULL; }
+    R->sp = *sp;
+    R->sp.solid = NULL;
+    R->nc = (int64_t)sp->nx * sp->ny * sp->nz;
+    R->L[0] = sp->lx; R->L[1] = sp->ly; R->L[2] = sp->lz;
+    R->inv_d[0] = (double)sp->nx / sp->lx;
+    R->inv_d[1] = (double)sp->ny / sp->ly;
+    R->inv_d[2] = (double)sp->nz / sp->lz;
+    double vc = (sp->lx / sp->nx) * (sp->ly / sp->ny) * (sp->lz / sp->nz);
+    R->coef = sp->fnum_sigma * sp->dt / vc;
+    R->vhs_exp = 1.0 - 2.0 * sp->omega;
+
+    /* initial (sigma c_r)_max: g at c0 = |U| + 3 sqrt(2 T_max) */
+    int inflow = (sp->face_bc[0] == OR_BC_INFLOW);
+    double U0 = inflow ? sp->inflow_U : 0.0;
+    double Ui = sqrt(sp->init_U[0] * sp->init_U[0] + sp->init_U[1] * sp->init_U[1] +
+                     sp->init_U[2] * sp->init_U[2]);
+    if (Ui > U0) U0 = Ui;
+    double Tmax = sp->init_T;
+    if (inflow && sp->inflow_T > Tmax) Tmax = sp->inflow_T;
+    for (int f = 0; f < 2 * sp->dim; ++f)
+        if (sp->face_bc[f] == OR_BC_DIFFUSE && sp->face_T[f] > Tmax) Tmax = sp->face_T[f];
+    double c0 = U0 + 3.0 * sqrt(2.0 * Tmax);
+    R->gmax0 = g_of(R, c0);
+
+    R->dy = sp->ly / sp->ny;
+    R->dz = sp->lz / sp->nz;
+    if (inflow) {
+        R->nface = (int64_t)sp->ny * sp->nz;
+        R->beta = 1.0 / sqrt(2.0 * sp->inflow_T);
+        R->s_inf = sp->inflow_U * R->beta;
+        R->p_branch = 1.0 / (1.0 + SQRT_PI * R->s_inf);
+        double s = R->s_inf;
+        double flux = sp->inflow_n / (2.0 * SQRT_PI * R->beta) *
+                      (exp(-s * s) + SQRT_PI * s * (1.0 + erf(s)));
+        R->mbar = flux * (R->dy * R->dz) * sp->dt;
+    }
+
+    int64_t cap = sp->capacity > 0 ? sp->capacity : 1;
+    for (int a = 0; a < 6; ++a) {
+        R->p[a] = (double *)calloc((size_t)cap, sizeof(double));
+        R->q[a] = (double *)calloc((size_t)cap, sizeof(double));
+    }
+    R->cell = (int32_t *)calloc((size_t)cap, sizeof(int32_t));
+    R->lcr = (int32_t *)calloc((size_t)cap, sizeof(int32_t));
+    R->cstart = (int64_t *)calloc((size_t)(R->nc + 2), sizeof(int64_t));
+    R->ccount = (int64_t *)calloc((size_t)(R->nc + 1), sizeof(int64_t));
+    R->rem_c = (double *)calloc((size_t)R->nc, sizeof(double));
+    R->gmax = (double *)calloc((size_t)R->nc, sizeof(double));
+    R->ncoll = (int64_t *)calloc((size_t)R->nc, sizeof(int64_t));
+    R->rem_f = (double *)calloc((size_t)(R->nface > 0 ? R->nface : 1), sizeof(double));
+    int ok = R->cell && R->lcr && R->cstart && R->ccount && R->rem_c && R->gmax &&
+             R->ncoll && R->rem_f;
+    for (int a = 0; a < 6; ++a) ok = ok && R->p[a] && R->q[a];
+    if (!ok) { or_run_free(R); *status = OR_ENOMEM; return NULL; }
+    for (int64_t c = 0; c < R->nc; ++c) R->gmax[c] = R->gmax0;
+    return R;
+}
+
+/* Initial uniform Maxwellian fill: slot i draws from (step 0, INIT, i).
+ * Uniforms 0..3 give the three velocity normals (two Box-Muller pairs, the
+ * last output unused), uniforms 4.. give the position. */
+void or_init(or_run *R)
+{
+    const or_spec *sp = &R->sp;
+    double st = sqrt(sp->init_T);
+    for (int64_t i = 0; i < sp->n_init; ++i) {
+        ustream s = {{sp->run_id, sp->seed}, 0u, PURPOSE_INIT, (uint32_t)i, 0};
+        double u0 = us_next(&s), u1 = us_next(&s), u2 = us_next(&s), u3 = us_next(&s);
+        double n0, n1, n2, n3;
+        box_muller(u0, u1, &n0, &n1);
+        box_muller(u2, u3, &n2, &n3);
+        (void)n3;
+        R->p[3][i] = sp->init_U[0] + st * n0;
+        R->p[4][i] = sp->init_U[1] + st * n1;
+        R->p[5][i] = sp->init_U[2] + st * n2;
+        double ux = us_next(&s), uy = us_next(&s), uz = us_next(&s);
+        R->p[0][i] = ux * sp->lx;
+        R->p[1][i] = uy * sp->ly;
+        R->p[2][i] = (sp->dim == 3) ? uz * sp->lz : 0.0;
+    }
+    R->n = sp->n_init;
+    R->step = 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Generation: inflow of a drifting Maxwellian through the -x face            */
+/* ------------------------------------------------------------------------- */
+
+void or_generation(or_run *R)
+{
+    const or_spec *sp = &R->sp;
+    R->last_ngen = 0;
+    if (R->nface == 0) return;
+    double st = sqrt(sp->inflow_T);
+    for (int64_t j = 0; j < R->nface; ++j) {
+        double M = R->mbar + R->rem_f[j];
+        double fl = floor(M);
+        int64_t nemit = (int64_t)fl;
+        R->rem_f[j] = M - fl;
+        int64_t iy = j % sp->ny, iz = j / sp->ny;
+        ustream s = {{sp->run_id, sp->seed}, R->step, PURPOSE_GEN, (uint32_t)j, 0};
+        for (int64_t k = 0; k < nemit; ++k) {
+            /* normal velocity: z = beta*u has density ~ z exp(-(z-s)^2), z > 0 */
+            double z = 0.0;
+            int att;
+            for (att = 0; att < MAX_GEN_ATTEMPTS; ++att) {
+                double ub = us_next(&s), up = us_next(&s), uq = us_next(&s), ua = us_next(&s);
+                double r = sqrt(-log(up));
+                double x = (ub < R->p_branch) ? ((uq < 0.5) ? -r : r) : r * cos(TWO_PI * uq);
+                z = R->s_inf + x;
+                if (z > 0.0 && ua < z / (R->s_inf + fabs(x))) break;
+            }
+            if (att == MAX_GEN_ATTEMPTS) { R->err = OR_EREJECT; return; }
+            double u = z / R->beta;
+            double t0, t1;
+            double v1 = us_next(&s), v2 = us_next(&s);
+            box_muller(v1, v2, &t0, &t1);
+            double y = ((double)iy + us_next(&s)) * R->dy;
+            double zc = (sp->dim == 3) ? ((double)iz + us_next(&s)) * R->dz : 0.0;
+            double ut = us_next(&s);
+            double x0 = -(u * sp->dt) * (1.0 - ut);
+            if (R->n >= sp->capacity) { R->err = OR_ECAPACITY; return; }
+            int64_t d = R->n++;
+            R->p[0][d] = x0; R->p[1][d] = y; R->p[2][d] = zc;
+            R->p[3][d] = u; R->p[4][d] = st * t0; R->p[5][d] = st * t1;
+            R->last_ngen++;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Motion + Enumeration                                                       */
+/* ------------------------------------------------------------------------- */
+
+/* Moves one particle for dt; returns its new cell or nc (DEAD). */
+static int64_t move_one(or_run *R, int64_t slot, double pos[3], double vel[3])
+{
+    const or_spec *sp = &R->sp;
+    const int dim = sp->dim;
+    double trem = sp->dt;
+    int hits = 0;
+    ustream ws = {{sp->run_id, sp->seed}, R->step, PURPOSE_WALL, (uint32_t)slot, 0};
+    for (;;) {
+        double tmin = INFINITY;
+        int ax = -1, side = 0;
+        for (int a = 0; a < dim; ++a) {
+            double th;
+            int sd;
+            if (vel[a] > 0.0) { th = (R->L[a] - pos[a]) / vel[a]; sd = 1; }
+            else if (vel[a] < 0.0) { th = (0.0 - pos[a]) / vel[a]; sd = 0; }
+            else continue;
+            if (th < 0.0) th = 0.0;
+            if (th < tmin) { tmin = th; ax = a; side = sd; }
+        }
+        if (ax < 0 || tmin >= trem) {
+            for (int a = 0; a < dim; ++a) pos[a] = pos[a] + vel[a] * trem;
+            break;
+        }
+        for (int a = 0; a < dim; ++a)
+            pos[a] = (a == ax) ? (side ? R->L[a] : 0.0) : pos[a] + vel[a] * tmin;
+        trem = trem - tmin;
+        int f = 2 * ax + side;
+        int bc = sp->face_bc[f];
+        if (bc == OR_BC_SPECULAR) {
+            vel[ax] = -vel[ax];
+        } else if (bc == OR_BC_DIFFUSE) {
+            double Tw = sp->face_T[f];
+            ws.next = 4u * (uint64_t)hits;
+            double w0 = us_next(&ws), w1 = us_next(&ws), w2 = us_next(&ws);
+            double vn = sqrt(-2.0 * Tw * log(w0));
+            double n0, n1;
+            box_muller(w1, w2, &n0, &n1);
+            double stw = sqrt(Tw);
+            int t1 = (ax == 0) ? 1 : 0, t2 = (ax == 2) ? 1 : 2;
+            vel[ax] = side ? -vn : vn;
+            vel[t1] = stw * n0;
+            vel[t2] = stw * n1;
+        } else {
+            return R->nc; /* inflow plane crossed outward, or outflow */
+        }
+        if (++hits == MAX_WALL_HITS) { R->err = OR_EBOUNCE; break; }
+    }
+    if (pos[0] < 0.0) return R->nc; /* a generated particle that never entered */
+    return cell_of(R, pos);
+}
+
+void or_motion(or_run *R)
+{
+    int64_t removed = 0;
+    for (int64_t i = 0; i < R->n; ++i) {
+        double pos[3] = {R->p[0][i], R->p[1][i], R->p[2][i]};
+        double vel[3] = {R->p[3][i], R->p[4][i], R->p[5][i]};
+        int64_t c = move_one(R, i, pos, vel);
+        R->p[0][i] = pos[0]; R->p[1][i] = pos[1]; R->p[2][i] = pos[2];
+        R->p[3][i] = vel[0]; R->p[4][i] = vel[1]; R->p[5][i] = vel[2];
+        R->cell[i] = (int32_t)c;
+        if (c == R->nc) removed++;
+    }
+    R->last_nremoved = removed;
+    R->last_nmoved = R->n;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Indexing: stable counting sort of slots by cell (DEAD last)                */
+/* ------------------------------------------------------------------------- */
+
+/* The textbook stable counting sort: count, exclusive prefix sum, then place
+ * the slots in ascending order.  start has nbins+1 entries. */
+void or_counting_sort(const int32_t *key, int64_t n, int64_t nbins, int32_t *lcr,
+                      int64_t *start, int64_t *count)
+{
+    for (int64_t b = 0; b < nbins; ++b) count[b] = 0;
+    for (int64_t i = 0; i < n; ++i) count[key[i]]++;
+    start[0] = 0;
+    for (int64_t b = 0; b < nbins; ++b) start[b + 1] = start[b] + count[b];
+    int64_t *cursor = (int64_t *)malloc((size_t)(nbins > 0 ? nbins : 1) * sizeof(int64_t));
+    for (int64_t b = 0; b < nbins; ++b) cursor[b] = start[b];
+    for (int64_t i = 0; i < n; ++i) lcr[cursor[key[i]]++] = (int32_t)i;
+    free(cursor);
+}
+
+void or_indexing(or_run *R)
+{
+    or_counting_sort(R->cell, R->n, R->nc + 1, R->lcr, R->cstart, R->ccount);
+    R->n_sorted = R->n;
+}
+
+/* P <- P[LCR[0 : n - #DEAD]]: P becomes cell-sorted and the DEAD bin drops. */
+void or_permute(or_run *R)
+{
+    int64_t keep = R->n - R->ccount[R->nc];
+    for (int a = 0; a < 6; ++a) {
+        for (int64_t p = 0; p < keep; ++p) R->q[a][p] = R->p[a][R->lcr[p]];
+        double *t = R->p[a];
+        R->p[a] = R->q[a];
+        R->q[a] = t;
+    }
+    R->n = keep;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Interaction: NTC collisions in one cell                                    */
+/* ------------------------------------------------------------------------- */
+
+/* Collides the N particles whose velocities are u[0..N), v[..], w[..].
+ * trace (optional) receives (i, j, accepted) per selection, at most
+ * trace_cap selections. Returns the number of accepted collisions. */
+static int64_t collide_cell(const or_run *R, uint32_t cell, int64_t N, double *u, double *v,
+                            double *w, double *gmax, double *rem, int32_t *trace,
+                            int64_t trace_cap, int64_t *nsel_out)
+{
+    double npairs = 0.5 * (double)(N * (N - 1));
+    double M = npairs * R->coef * (*gmax) + *rem;
+    double fl = floor(M);
+    int64_t nsel = (int64_t)fl;
+    *rem = M - fl;
+    if (N < 2) nsel = 0;
+    if (nsel_out) *nsel_out = nsel;
+    int64_t ncol = 0;
+    for (int64_t k = 0; k < nsel; ++k) {
+        uint32_t c0[4] = {R->step, PURPOSE_COLL, cell, (uint32_t)(2 * k)};
+        uint32_t c1[4] = {R->step, PURPOSE_COLL, cell, (uint32_t)(2 * k + 1)};
+        uint32_t b0[4], b1[4];
+        or_philox4x32_10(c0, (const uint32_t[2]){R->sp.run_id, R->sp.seed}, b0);
+        or_philox4x32_10(c1, (const uint32_t[2]){R->sp.run_id, R->sp.seed}, b1);
+        int64_t i = or_index(b0[0], (uint32_t)N);
+        int64_t jp = or_index(b0[1], (uint32_t)(N - 1));
+        int64_t j = jp + (jp >= i ? 1 : 0);
+        double du = u[i] - u[j], dv = v[i] - v[j], dw = w[i] - w[j];
+        double cr = sqrt(du * du + dv * dv + dw * dw);
+        double g = g_of(R, cr);
+        if (g > *gmax) *gmax = g;
+        int acc = or_u01(b0[2], b0[3]) < g / *gmax;
+        if (trace && k < trace_cap) {
+            trace[3 * k] = (int32_t)i;
+            trace[3 * k + 1] = (int32_t)j;
+            trace[3 * k + 2] = acc;
+        }
+        if (!acc) continue;
+        double cosx = 2.0 * or_u01(b1[0], b1[1]) - 1.0;
+        double sinx = sqrt(1.0 - cosx * cosx);
+        double eps = TWO_PI * or_u01(b1[2], b1[3]);
+        double rx = cr * cosx, ry = cr * sinx * cos(eps), rz = cr * sinx * sin(eps);
+        double mx = 0.5 * (u[i] + u[j]), my = 0.5 * (v[i] + v[j]), mz = 0.5 * (w[i] + w[j]);
+        u[i] = mx + 0.5 * rx; v[i] = my + 0.5 * ry; w[i] = mz + 0.5 * rz;
+        u[j] = mx - 0.5 * rx; v[j] = my - 0.5 * ry; w[j] = mz - 0.5 * rz;
+        ncol++;
+    }
+    return ncol;
+}
+
+void or_interaction(or_run *R)
+{
+    int64_t total = 0;
+    for (int64_t c = 0; c < R->nc; ++c) {
+        int64_t b = R->cstart[c], N = R->ccount[c];
+        int64_t k = collide_cell(R, (uint32_t)c, N, R->p[3] + b, R->p[4] + b, R->p[5] + b,
+                                 &R->gmax[c], &R->rem_c[c], NULL, 0, NULL);
+        R->ncoll[c] += k;
+        total += k;
+    }
+    R->last_ncoll = total;
+}
+
+/* Stand-alone single-cell interaction for brute-force tests: the velocities
+ * are updated in place, (gmax, rem) are in/out, trace as in collide_cell. */
+int64_t or_collide_cell(const or_spec *sp, uint32_t step, uint32_t cell, int64_t N, double *u,
+                        double *v, double *w, double *gmax, double *rem, int32_t *trace,
+                        int64_t trace_cap, int64_t *nsel_out)
+{
+    int32_t st;
+    or_spec s2 = *sp;
+    s2.capacity = 1; s2.n_init = 0; s2.solid = NULL;
+    s2.face_bc[0] = OR_BC_SPECULAR;
+    or_run *R = or_run_new(&s2, &st);
+    if (!R) return st;
+    R->step = step;
+    int64_t k = collide_cell(R, cell, N, u, v, w, gmax, rem, trace, trace_cap, nsel_out);
+    or_run_free(R);
+    return k;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Sampling                                                                   */
+/* ------------------------------------------------------------------------- */
+
+/* out[c][7] = N, sum u, sum v, sum w, sum u^2, sum v^2, sum w^2 over cell c. */
+void or_sample(const or_run *R, double *out)
+{
+    for (int64_t c = 0; c < R->nc; ++c) {
+        double s[7] = {0, 0, 0, 0, 0, 0, 0};
+        int64_t b = R->cstart[c], N = R->ccount[c];
+        for (int64_t k = b; k < b + N; ++k) {
+            double u = R->p[3][k], v = R->p[4][k], w = R->p[5][k];
+            s[0] += 1.0;
+            s[1] += u; s[2] += v; s[3] += w;
+            s[4] += u * u; s[5] += v * v; s[6] += w * w;
+        }
+        for (int f = 0; f < 7; ++f) out[7 * c + f] = s[f];
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* One time step and accessors                                                */
+/* ------------------------------------------------------------------------- */
+
+void or_step(or_run *R)
+{
+    R->step++;
+    or_generation(R);
+    or_motion(R);
+    or_indexing(R);
+    or_permute(R);
+    or_interaction(R);
+}
+
+void or_step_begin(or_run *R) { R->step++; }
+
+/* info: n, step, err, nc, n_sorted, last_ncoll, last_ngen, last_nremoved, last_nmoved, nface */
+void or_get_info(const or_run *R, int64_t info[10])
+{
+    info[0] = R->n; info[1] = R->step; info[2] = R->err; info[3] = R->nc;
+    info[4] = R->n_sorted; info[5] = R->last_ncoll; info[6] = R->last_ngen;
+    info[7] = R->last_nremoved; info[8] = R->last_nmoved; info[9] = R->nface;
+}
+
+/* derived constants: coef, vhs_exp, gmax0, mbar, beta, s_inf, p_branch */
+void or_get_consts(const or_run *R, double out[7])
+{
+    out[0] = R->coef; out[1] = R->vhs_exp; out[2] = R->gmax0; out[3] = R->mbar;
+    out[4] = R->beta; out[5] = R->s_inf; out[6] = R->p_branch;
+}
+
+void or_get_state(const or_run *R, double *out /* [6][n] */)
+{
+    for (int a = 0; a < 6; ++a) memcpy(out + a * R->n, R->p[a], (size_t)R->n * sizeof(double));
+}
+
+int32_t or_set_state(or_run *R, int64_t n, const double *in /* [6][n] */)
+{
+    if (n < 0 || n > R->sp.capacity) return OR_EINVAL;
+    for (int a = 0; a < 6; ++a) memcpy(R->p[a], in + a * n, (size_t)n * sizeof(double));
+    R->n = n;
+    return OR_OK;
+}
+
+void or_set_step(or_run *R, uint32_t step) { R->step = step; }
+
+void or_get_cells(const or_run *R, int32_t *cell /* n_sorted */, int32_t *lcr /* n_sorted */,
+                  int64_t *cstart /* nc+2 */, int64_t *ccount /* nc+1 */)
+{
+    if (cell) memcpy(cell, R->cell, (size_t)R->n_sorted * sizeof(int32_t));
+    if (lcr) memcpy(lcr, R->lcr, (size_t)R->n_sorted * sizeof(int32_t));
+    if (cstart) memcpy(cstart, R->cstart, (size_t)(R->nc + 2) * sizeof(int64_t));
+    if (ccount) memcpy(ccount, R->ccount, (size_t)(R->nc + 1) * sizeof(int64_t));
+}
+
+void or_get_cell_state(const or_run *R, double *rem, double *gmax, int64_t *ncoll)
+{
+    if (rem) memcpy(rem, R->rem_c, (size_t)R->nc * sizeof(double));
+    if (gmax) memcpy(gmax, R->gmax, (size_t)R->nc * sizeof(double));
+    if (ncoll) memcpy(ncoll, R->ncoll, (size_t)R->nc * sizeof(int64_t));
+}
+
+void or_get_face_rem(const or_run *R, double *rem)
+{
+    memcpy(rem, R->rem_f, (size_t)R->nface * sizeof(double));
+}
+
+/* ------------------------------------------------------------------------- */
+/* Ensemble of independent runs (the outer loop), one thread per group        */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    const or_spec *specs;
+    int32_t n_runs, n_steps, n_samples, n_groups, n_threads, tid;
+    const int32_t *sample_steps;
+    double *acc;              /* [n_samples][n_groups][nc][7] */
+    int64_t nc;
+    int64_t psteps, ncoll;
+    int32_t status;
+} ens_job;
+
+static void *ens_worker(void *arg)
+{
+    ens_job *J = (ens_job *)arg;
+    double *tmp = (double *)malloc((size_t)J->nc * 7 * sizeof(double));
+    for (int32_t g = J->tid; g < J->n_groups; g += J->n_threads) {
+        for (int32_t r = g; r < J->n_runs; r += J->n_groups) {
+            int32_t st;
+            or_run *R = or_run_new(&J->specs[r], &st);
+            if (!R) { J->status = st; free(tmp); return NULL; }
+            or_init(R);
+            int32_t ks = 0;
+            for (int32_t s = 1; s <= J->n_steps; ++s) {
+                or_step(R);
+                J->psteps += R->last_nmoved;
+                J->ncoll += R->last_ncoll;
+                if (R->err) { J->status = R->err; or_run_free(R); free(tmp); return NULL; }
+                while (ks < J->n_samples && J->sample_steps[ks] < s) ks++;
+                if (ks < J->n_samples && J->sample_steps[ks] == s) {
+                    or_sample(R, tmp);
+                    double *dst = J->acc + ((size_t)ks * J->n_groups + g) * J->nc * 7;
+                    for (int64_t e = 0; e < J->nc * 7; ++e) dst[e] += tmp[e];
+                }
+            }
+            or_run_free(R);
+        }
+    }
+    free(tmp);
+    return NULL;
+}
+
+/* Runs every run from its initial state for n_steps steps; run r adds its
+ * per-cell sample sums into group r % n_groups, runs taken in ascending order
+ * inside a group (so the result does not depend on n_threads).  All runs must
+ * share one grid.  stats[0] = particle-steps (particles moved), stats[1] =
+ * collisions. */
+int32_t or_ensemble(const or_spec *specs, int32_t n_runs, int32_t n_steps,
+                    const int32_t *sample_steps, int32_t n_samples, int32_t n_groups,
+                    int32_t n_threads, double *acc, int64_t stats[2])
+{
+    if (n_runs < 1 || n_groups < 1 || n_threads < 1) return OR_EINVAL;
+    int64_t nc = (int64_t)specs[0].nx * specs[0].ny * specs[0].nz;
+    for (int32_t r = 1; r < n_runs; ++r)
+        if ((int64_t)specs[r].nx * specs[r].ny * specs[r].nz != nc) return OR_EINVAL;
+    memset(acc, 0, (size_t)n_samples * n_groups * nc * 7 * sizeof(double));
+    if (n_threads > n_groups) n_threads = n_groups;
+    ens_job *jobs = (ens_job *)calloc((size_t)n_threads, sizeof(ens_job));
+    pthread_t *th = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
+    for (int32_t t = 0; t < n_threads; ++t) {
+        ens_job *J = &jobs[t];
+        J->specs = specs; J->n_runs = n_runs; J->n_steps = n_steps;
+        J->n_samples = n_samples; J->n_groups = n_groups; J->n_threads = n_threads;
+        J->tid = t; J->sample_steps = sample_steps; J->acc = acc; J->nc = nc;
+        pthread_create(&th[t], NULL, ens_worker, J);
+    }
+    int32_t status = OR_OK;
+    stats[0] = stats[1] = 0;
+    for (int32_t t = 0; t < n_threads; ++t) {
+        pthread_join(th[t], NULL);
+        if (jobs[t].status) status = jobs[t].status;
+        stats[0] += jobs[t].psteps;
+        stats[1] += jobs[t].ncoll;
+    }
+    free(jobs);
+    free(th);
+    return status;
+}
