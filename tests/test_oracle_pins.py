@@ -504,5 +504,5 @@ def test_upstream_particle_that_never_enters_is_removed(oracle_lib):
     R.set_state(st)
     R.step_begin(); R.motion(); R.indexing()
     cl = R.cells()
-    assert cl["cell"].tolist() == [1024, 0, 1024]
+    assert cl["cell"].tolist() == [1024, 16 * 32, 1024]
     assert R.info()["nremoved"] == 2
