@@ -1,0 +1,189 @@
+/*
+ * dsmc.h -- C ABI of the MI355X (gfx950) library for the data-parallel inner
+ * loop of unsteady Direct Simulation Monte Carlo.
+ *
+ * The operation is the sequential unsteady-DSMC algorithm of Sec. 1.1 of
+ * Bogdanov, Bykov, Grishin, Khanlarov, Lukianov and Zakharov, "Algorithms of
+ * Two-Level Parallelization for DSMC of Unsteady Flows in Molecular
+ * Gasdynamics" (general flowchart of the sequential algorithm): an inner loop
+ * over time steps dt of one run -- Generation, Motion, Enumeration/Indexing
+ * (the readdressing array LCR), Interaction, and Sampling at given moments --
+ * and an outer loop over n statistically independent runs whose random number
+ * generator is shifted per run.  Every call below advances many runs at once
+ * (the paper's parallel independent runs, Sec. 1.3, inside one launch) with
+ * data parallelism over particles and cells inside each run (Sec. 1.4).
+ *
+ * Conventions
+ *  - Units are reduced: Boltzmann constant = molecular mass = 1.
+ *  - Memory: the caller owns ALL device memory.  dsmc_required_bytes gives the
+ *    size of one device arena; the caller allocates it (e.g. a torch tensor)
+ *    and passes it to dsmc_init_runs.  The arena must outlive the context.
+ *    The library allocates no device memory; it owns only the opaque context
+ *    (host heap) and copies the run specs and sample schedule.
+ *  - Streams: the caller's HIP stream is borrowed; every launch goes to it.
+ *  - Asynchrony: dsmc_step and dsmc_sample only enqueue work.
+ *    dsmc_read_moments, dsmc_read_accum, dsmc_sync and the dsmc_get_* /
+ *    dsmc_set_state calls synchronise the stream.
+ *  - Errors: every call returns a dsmc_status (0 = DSMC_OK).  Argument errors
+ *    are detected before anything is enqueued.  Device-side conditions
+ *    (capacity overflow during Generation, too many wall interactions, a
+ *    failed inflow draw, a HIP launch failure) latch an error that the next
+ *    synchronising call returns; after that only dsmc_destroy and
+ *    dsmc_last_error are valid.  No exception or abort crosses the ABI.
+ *  - Threading: a context is not thread-safe; distinct contexts are
+ *    independent.
+ */
+#ifndef DSMC_H
+#define DSMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dsmc_status;
+#define DSMC_OK 0
+#define DSMC_EINVAL (-1)       /* invalid argument */
+#define DSMC_ESIZE (-2)        /* buffer or arena too small */
+#define DSMC_ECAPACITY (-3)    /* a run ran out of particle slots */
+#define DSMC_EDEVICE (-4)      /* HIP error */
+#define DSMC_ESTATE (-5)       /* call not valid in the current state */
+#define DSMC_EUNSUPPORTED (-6) /* feature not supported */
+#define DSMC_EBOUNCE (-7)      /* more than 64 wall interactions of one particle in one step */
+#define DSMC_EREJECT (-8)      /* inflow velocity sampler exceeded its attempt limit */
+#define DSMC_ENUMERIC (-9)     /* non-finite particle state or >= 1e9 pair selections in one cell and step */
+
+/* Boundary kind of a face; faces are ordered -x, +x, -y, +y, -z, +z. */
+#define DSMC_BC_SPECULAR 0     /* mirror reflection */
+#define DSMC_BC_DIFFUSE 1      /* full accommodation at face_T */
+#define DSMC_BC_INFLOW 2       /* -x only: drifting-Maxwellian reservoir; leavers are removed */
+#define DSMC_BC_OUTFLOW 3      /* vacuum: leavers are removed */
+
+/* Sampled sums per cell (dsmc_read_accum) and moments (dsmc_read_moments). */
+#define DSMC_NSUM 7            /* N, sum u, sum v, sum w, sum u^2, sum v^2, sum w^2 */
+#define DSMC_NMOM 8            /* n (particles per cell per run), ux, uy, uz, T, Tx, Ty, Tz */
+
+typedef struct dsmc_ctx dsmc_ctx; /* opaque, library-owned */
+
+/* One independent run (one iteration of the outer loop of Sec. 1.1). */
+typedef struct {
+  int32_t dim;                  /* 2 or 3 (all runs of a context share it) */
+  int32_t nx, ny, nz;           /* uniform cell grid; nz = 1 in 2-D */
+  double lx, ly, lz;            /* box [0,lx] x [0,ly] x [0,lz]; lz = 1 in 2-D */
+  double dt;                    /* time step */
+  double fnum_sigma;            /* Fnum * sigma_ref (0 = collisionless) */
+  double omega;                 /* VHS viscosity index; 0.5 = hard sphere */
+  double c_ref;                 /* VHS reference relative speed */
+  int32_t face_bc[6];           /* DSMC_BC_* per face */
+  double face_T[6];             /* wall temperature of DIFFUSE faces */
+  double inflow_n, inflow_U, inflow_T; /* inflow density (simulated particles per unit volume), drift, T */
+  int64_t capacity;             /* particle slots reserved for this run */
+  int64_t n_init;               /* initial uniform Maxwellian fill (0 = empty) */
+  double init_U[3];             /* initial drift */
+  double init_T;                /* initial temperature */
+  uint32_t run_id, seed;        /* Philox key of the run: runs are independent and replayable */
+  int32_t ensemble;             /* runs with the same id are averaged together; they share a grid */
+  int32_t reserved;
+} dsmc_run_spec;
+
+typedef struct {
+  int32_t state_fp64;           /* 1: FP64 particle state and arithmetic; 0: FP32 */
+  int32_t n_groups;             /* run groups per ensemble for batch-means errors (>= 1) */
+  int32_t n_samples;            /* sample slots (>= 0) */
+  const int32_t *sample_steps;  /* host [n_samples]: 1-based step after which dsmc_step samples into slot k
+                                   (entry < 1: slot filled only by dsmc_sample); may be NULL */
+  int32_t use_graph;            /* 1: replay each step from a HIP graph */
+  int32_t tile_chunks;          /* tuning: 64-slot rounds per indexing tile (0 = default 256) */
+  int32_t reserved[2];
+} dsmc_options;
+
+/* Arena size for these runs/options.  Pure host computation.
+ * Returns DSMC_EINVAL for an invalid spec (same checks as dsmc_init_runs). */
+dsmc_status dsmc_required_bytes(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_options *opt,
+                                size_t *bytes);
+
+/* Create a context: lays the runs out in the arena (device memory of at
+ * least dsmc_required_bytes bytes, 256-byte aligned), fills each run with its
+ * initial state (Philox stream "INIT" of its key) and returns the context.
+ * hip_stream is a hipStream_t (NULL = default stream).  Synchronises. */
+dsmc_status dsmc_init_runs(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_options *opt, void *arena,
+                           size_t arena_bytes, void *hip_stream, dsmc_ctx **out);
+
+/* Advance every run by n_steps time steps (Sec. 1.1: Generation, Motion,
+ * Enumeration/Indexing, Interaction; Sampling at the scheduled steps).
+ * Asynchronous. */
+dsmc_status dsmc_step(dsmc_ctx *ctx, int32_t n_steps);
+
+/* Accumulate the current state of every run into sample slot k.  Valid after
+ * at least one step.  Asynchronous. */
+dsmc_status dsmc_sample(dsmc_ctx *ctx, int32_t sample_index);
+
+/* Cell moments of one ensemble at sample slot k, FP64 (the final division of
+ * the cross-run sums): out[cell][DSMC_NMOM] on the host; out_se (may be NULL)
+ * the batch-means standard error over the ensemble's run groups (NaN with one
+ * group).  capacity_doubles is the size of each host array.  Cells with no
+ * particles give NaN.  Synchronises. */
+dsmc_status dsmc_read_moments(dsmc_ctx *ctx, int32_t sample_index, int32_t ensemble, double *out,
+                              double *out_se, size_t capacity_doubles);
+
+/* Raw FP64 sums of one ensemble at slot k: out[group][cell][DSMC_NSUM].  Synchronises. */
+dsmc_status dsmc_read_accum(dsmc_ctx *ctx, int32_t sample_index, int32_t ensemble, double *out,
+                            size_t capacity_doubles);
+
+/* Wait for all enqueued work; returns the latched device error, if any. */
+dsmc_status dsmc_sync(dsmc_ctx *ctx);
+
+void dsmc_destroy(dsmc_ctx *ctx);
+
+/* Message of the last failed call on this context (NULL-safe; static text for NULL). */
+const char *dsmc_last_error(const dsmc_ctx *ctx);
+
+/* ---- inspection (tests, diagnostics); all synchronise ---------------------- */
+
+/* Context facts: info[0] steps done, [1] runs, [2] ensembles, [3] 1 if FP64,
+ * [4] indexing passes, [5] tiles, [6] slots, [7] latched device error. */
+dsmc_status dsmc_get_info(dsmc_ctx *ctx, int64_t info[8]);
+
+/* Particle state of one run in slot order (cell-sorted after a step):
+ * out[6][n] = x, y, z, u, v, w (z = 0 in 2-D), FP64.  *n receives the count;
+ * cap is the per-component capacity of out. */
+dsmc_status dsmc_get_state(dsmc_ctx *ctx, int32_t run, double *out, int64_t cap, int64_t *n);
+
+/* Replace the particle state of one run (in[6][n], FP64; converted to the
+ * state precision). */
+dsmc_status dsmc_set_state(dsmc_ctx *ctx, int32_t run, const double *in, int64_t n);
+
+/* Indexing of the last step of one run: lcr[n] (run-local slots in stable
+ * cell order, DEAD last) and cell[n] (cell of each slot, nc = DEAD) for the n
+ * particles present before removal; start[nc + 2] bin starts (may be NULL). */
+dsmc_status dsmc_get_lcr(dsmc_ctx *ctx, int32_t run, int32_t *lcr, int32_t *cell, int64_t *start,
+                         int64_t cap, int64_t *n);
+
+/* Per-cell interaction state of one run: remainder, (sigma c_r)_max in units
+ * of sigma_ref, cumulative accepted collisions (each array [nc], may be NULL). */
+dsmc_status dsmc_get_cell_state(dsmc_ctx *ctx, int32_t run, double *rem, double *gmax, int64_t *ncoll);
+
+/* Per run: [r][0] particles now, [r][1] particles generated in the last step. */
+dsmc_status dsmc_get_counts(dsmc_ctx *ctx, int64_t *out, int32_t n_runs);
+
+/* ---- Indexing alone ------------------------------------------------------ */
+
+/* Workspace bytes for dsmc_counting_sort. */
+dsmc_status dsmc_counting_sort_bytes(int64_t n, int32_t nbins, size_t *bytes);
+
+/* Stable counting sort (the Indexing step, Sec. 1.1/1.4) of n device keys in
+ * [0, nbins): lcr[n] receives the positions 0..n-1 in ascending key order,
+ * equal keys in ascending position; start[nbins + 1] the bin starts.  All
+ * pointers are device memory; work has dsmc_counting_sort_bytes bytes.
+ * Asynchronous on hip_stream.  Keys outside [0, nbins) are undefined
+ * behaviour and must be excluded by the caller. */
+dsmc_status dsmc_counting_sort(const int32_t *keys, int64_t n, int32_t nbins, int32_t *lcr, uint32_t *start,
+                               void *work, size_t work_bytes, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DSMC_H */

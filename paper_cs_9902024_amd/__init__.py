@@ -1,0 +1,364 @@
+"""MI355X-native unsteady-DSMC inner loop: Python binding of ``libdsmc.so``.
+
+The functions below carry the names of the C ABI in ``include/dsmc.h`` and do
+argument marshalling only: every step of the method runs in the HIP kernels
+of the library.  PyTorch supplies the device arena (one uint8 tensor) and the
+stream.  If the library is not built, importing works but every call raises
+``DsmcError`` -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdsmc.so")
+
+DSMC_OK = 0
+STATUS_NAMES = {0: "DSMC_OK", -1: "DSMC_EINVAL", -2: "DSMC_ESIZE", -3: "DSMC_ECAPACITY",
+                -4: "DSMC_EDEVICE", -5: "DSMC_ESTATE", -6: "DSMC_EUNSUPPORTED",
+                -7: "DSMC_EBOUNCE", -8: "DSMC_EREJECT", -9: "DSMC_ENUMERIC"}
+BC = {"specular": 0, "diffuse": 1, "inflow": 2, "outflow": 3}
+NSUM = 7
+NMOM = 8
+MOMENT_NAMES = ("n", "ux", "uy", "uz", "T", "Tx", "Ty", "Tz")
+
+# Every symbol declared in include/dsmc.h.
+EXPORTS = ("dsmc_required_bytes", "dsmc_init_runs", "dsmc_step", "dsmc_sample", "dsmc_read_moments",
+           "dsmc_read_accum", "dsmc_sync", "dsmc_destroy", "dsmc_last_error", "dsmc_get_info",
+           "dsmc_get_state", "dsmc_set_state", "dsmc_get_lcr", "dsmc_get_cell_state",
+           "dsmc_get_counts", "dsmc_counting_sort_bytes", "dsmc_counting_sort")
+
+
+class DsmcError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str = ""):
+        self.status = status
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)} {msg}".strip())
+
+
+class dsmc_run_spec(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double),
+                ("dt", C.c_double), ("fnum_sigma", C.c_double), ("omega", C.c_double),
+                ("c_ref", C.c_double), ("face_bc", C.c_int32 * 6), ("face_T", C.c_double * 6),
+                ("inflow_n", C.c_double), ("inflow_U", C.c_double), ("inflow_T", C.c_double),
+                ("capacity", C.c_int64), ("n_init", C.c_int64), ("init_U", C.c_double * 3),
+                ("init_T", C.c_double), ("run_id", C.c_uint32), ("seed", C.c_uint32),
+                ("ensemble", C.c_int32), ("reserved", C.c_int32)]
+
+
+class dsmc_options(C.Structure):
+    _fields_ = [("state_fp64", C.c_int32), ("n_groups", C.c_int32), ("n_samples", C.c_int32),
+                ("sample_steps", C.POINTER(C.c_int32)), ("use_graph", C.c_int32),
+                ("tile_chunks", C.c_int32), ("reserved", C.c_int32 * 2)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libdsmc.so (never builds it, never falls back)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise DsmcError(-4, "load", f"{LIB_PATH} is not built "
+                            "(run paper_cs_9902024_amd.build.build())")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+        dp = C.POINTER(C.c_double)
+        L.dsmc_required_bytes.argtypes = [C.POINTER(dsmc_run_spec), i32, C.POINTER(dsmc_options),
+                                          C.POINTER(sz)]
+        L.dsmc_init_runs.argtypes = [C.POINTER(dsmc_run_spec), i32, C.POINTER(dsmc_options), vp, sz,
+                                     vp, C.POINTER(vp)]
+        L.dsmc_step.argtypes = [vp, i32]
+        L.dsmc_sample.argtypes = [vp, i32]
+        L.dsmc_read_moments.argtypes = [vp, i32, i32, dp, dp, sz]
+        L.dsmc_read_accum.argtypes = [vp, i32, i32, dp, sz]
+        L.dsmc_sync.argtypes = [vp]
+        L.dsmc_destroy.argtypes = [vp]
+        L.dsmc_destroy.restype = None
+        L.dsmc_last_error.argtypes = [vp]
+        L.dsmc_last_error.restype = C.c_char_p
+        L.dsmc_get_info.argtypes = [vp, C.POINTER(i64)]
+        L.dsmc_get_state.argtypes = [vp, i32, dp, i64, C.POINTER(i64)]
+        L.dsmc_set_state.argtypes = [vp, i32, dp, i64]
+        L.dsmc_get_lcr.argtypes = [vp, i32, vp, vp, vp, i64, C.POINTER(i64)]
+        L.dsmc_get_cell_state.argtypes = [vp, i32, vp, vp, vp]
+        L.dsmc_get_counts.argtypes = [vp, C.POINTER(i64), i32]
+        L.dsmc_counting_sort_bytes.argtypes = [i64, i32, C.POINTER(sz)]
+        L.dsmc_counting_sort.argtypes = [vp, i64, i32, vp, vp, vp, sz, vp]
+        for f in EXPORTS:
+            if f not in ("dsmc_destroy", "dsmc_last_error"):
+                getattr(L, f).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _check(st: int, where: str, ctx=None):
+    if st != DSMC_OK:
+        msg = lib().dsmc_last_error(ctx).decode() if ctx else ""
+        raise DsmcError(st, where, msg)
+
+
+# ---------------------------------------------------------------------------
+# Argument structs
+# ---------------------------------------------------------------------------
+
+def make_run_spec(rs) -> dsmc_run_spec:
+    """dsmc_run_spec from a ``workloads.RunSpec``."""
+    if rs.solid is not None:
+        raise DsmcError(-6, "make_run_spec", "voxel obstacles are not supported by this library build")
+    s = dsmc_run_spec()
+    s.dim, s.nx, s.ny, s.nz = rs.dim, rs.nx, rs.ny, rs.nz
+    s.lx, s.ly, s.lz = rs.lx, rs.ly, rs.lz
+    s.dt, s.fnum_sigma, s.omega, s.c_ref = rs.dt, rs.fnum_sigma, rs.omega, rs.c_ref
+    for f in range(6):
+        s.face_bc[f] = BC[rs.face_bc[f]]
+        s.face_T[f] = rs.face_T[f]
+    s.inflow_n, s.inflow_U, s.inflow_T = rs.inflow_n, rs.inflow_U, rs.inflow_T
+    s.capacity, s.n_init = rs.capacity, rs.n_init
+    for a in range(3):
+        s.init_U[a] = rs.init_U[a]
+    s.init_T = rs.init_T
+    s.run_id, s.seed = rs.run_id & 0xFFFFFFFF, rs.seed & 0xFFFFFFFF
+    s.ensemble = rs.ensemble
+    return s
+
+
+def make_options(state_fp64: bool, n_groups: int, sample_steps: Sequence[int],
+                 use_graph: bool = False, tile_chunks: int = 0):
+    steps = (C.c_int32 * max(1, len(sample_steps)))(*sample_steps)
+    o = dsmc_options()
+    o.state_fp64 = int(bool(state_fp64))
+    o.n_groups = int(n_groups)
+    o.n_samples = len(sample_steps)
+    o.sample_steps = C.cast(steps, C.POINTER(C.c_int32))
+    o.use_graph = int(bool(use_graph))
+    o.tile_chunks = int(tile_chunks)
+    o._keep = steps
+    return o
+
+
+def _specs(runs):
+    arr = (dsmc_run_spec * len(runs))(*[make_run_spec(r) for r in runs])
+    return arr
+
+
+# ---------------------------------------------------------------------------
+# The C ABI, one wrapper per entry point
+# ---------------------------------------------------------------------------
+
+def dsmc_required_bytes(specs, opt) -> int:
+    n = C.c_size_t(0)
+    _check(lib().dsmc_required_bytes(specs, len(specs), C.byref(opt), C.byref(n)), "dsmc_required_bytes")
+    return n.value
+
+
+def dsmc_init_runs(specs, opt, arena_ptr: int, arena_bytes: int, stream: int):
+    ctx = C.c_void_p(0)
+    _check(lib().dsmc_init_runs(specs, len(specs), C.byref(opt), C.c_void_p(arena_ptr), arena_bytes,
+                                C.c_void_p(stream), C.byref(ctx)), "dsmc_init_runs")
+    return ctx
+
+
+def dsmc_step(ctx, n_steps: int = 1):
+    _check(lib().dsmc_step(ctx, n_steps), "dsmc_step", ctx)
+
+
+def dsmc_sample(ctx, sample_index: int):
+    _check(lib().dsmc_sample(ctx, sample_index), "dsmc_sample", ctx)
+
+
+def dsmc_read_moments(ctx, sample_index: int, ensemble: int, n_cells: int):
+    out = np.zeros((n_cells, NMOM))
+    se = np.zeros((n_cells, NMOM))
+    dp = C.POINTER(C.c_double)
+    _check(lib().dsmc_read_moments(ctx, sample_index, ensemble, out.ctypes.data_as(dp),
+                                   se.ctypes.data_as(dp), out.size), "dsmc_read_moments", ctx)
+    return out, se
+
+
+def dsmc_read_accum(ctx, sample_index: int, ensemble: int, n_groups: int, n_cells: int):
+    out = np.zeros((n_groups, n_cells, NSUM))
+    _check(lib().dsmc_read_accum(ctx, sample_index, ensemble,
+                                 out.ctypes.data_as(C.POINTER(C.c_double)), out.size),
+           "dsmc_read_accum", ctx)
+    return out
+
+
+def dsmc_sync(ctx):
+    _check(lib().dsmc_sync(ctx), "dsmc_sync", ctx)
+
+
+def dsmc_destroy(ctx):
+    lib().dsmc_destroy(ctx)
+
+
+def dsmc_last_error(ctx) -> str:
+    return lib().dsmc_last_error(ctx).decode()
+
+
+def dsmc_get_info(ctx) -> dict:
+    a = (C.c_int64 * 8)()
+    _check(lib().dsmc_get_info(ctx, a), "dsmc_get_info", ctx)
+    return dict(zip(("steps", "runs", "ensembles", "fp64", "passes", "tiles", "slots", "error"), list(a)))
+
+
+def dsmc_get_state(ctx, run: int) -> np.ndarray:
+    n = C.c_int64(0)
+    _check(lib().dsmc_get_state(ctx, run, None, 0, C.byref(n)), "dsmc_get_state", ctx)
+    out = np.zeros((6, n.value))
+    _check(lib().dsmc_get_state(ctx, run, out.ctypes.data_as(C.POINTER(C.c_double)), n.value,
+                                C.byref(n)), "dsmc_get_state", ctx)
+    return out[:, :n.value]
+
+
+def dsmc_set_state(ctx, run: int, state: np.ndarray):
+    st = np.ascontiguousarray(state, dtype=np.float64)
+    _check(lib().dsmc_set_state(ctx, run, st.ctypes.data_as(C.POINTER(C.c_double)), st.shape[1]),
+           "dsmc_set_state", ctx)
+
+
+def dsmc_get_lcr(ctx, run: int, capacity: int, n_cells: int):
+    lcr = np.zeros(capacity, np.int32)
+    cell = np.zeros(capacity, np.int32)
+    start = np.zeros(n_cells + 2, np.int64)
+    n = C.c_int64(0)
+    _check(lib().dsmc_get_lcr(ctx, run, lcr.ctypes.data, cell.ctypes.data, start.ctypes.data, capacity,
+                              C.byref(n)), "dsmc_get_lcr", ctx)
+    return lcr[:n.value], cell[:n.value], start
+
+
+def dsmc_get_cell_state(ctx, run: int, n_cells: int) -> dict:
+    rem, gmax = np.zeros(n_cells), np.zeros(n_cells)
+    ncoll = np.zeros(n_cells, np.int64)
+    _check(lib().dsmc_get_cell_state(ctx, run, rem.ctypes.data, gmax.ctypes.data, ncoll.ctypes.data),
+           "dsmc_get_cell_state", ctx)
+    return {"rem": rem, "gmax": gmax, "ncoll": ncoll}
+
+
+def dsmc_get_counts(ctx, n_runs: int) -> np.ndarray:
+    out = np.zeros((n_runs, 2), np.int64)
+    _check(lib().dsmc_get_counts(ctx, out.ctypes.data_as(C.POINTER(C.c_int64)), n_runs),
+           "dsmc_get_counts", ctx)
+    return out
+
+
+def dsmc_counting_sort_bytes(n: int, nbins: int) -> int:
+    b = C.c_size_t(0)
+    _check(lib().dsmc_counting_sort_bytes(n, nbins, C.byref(b)), "dsmc_counting_sort_bytes")
+    return b.value
+
+
+def dsmc_counting_sort(keys_ptr: int, n: int, nbins: int, lcr_ptr: int, start_ptr: int, work_ptr: int,
+                       work_bytes: int, stream: int):
+    _check(lib().dsmc_counting_sort(C.c_void_p(keys_ptr), n, nbins, C.c_void_p(lcr_ptr),
+                                    C.c_void_p(start_ptr), C.c_void_p(work_ptr), work_bytes,
+                                    C.c_void_p(stream)), "dsmc_counting_sort")
+
+
+# ---------------------------------------------------------------------------
+# Convenience: one context over torch-owned device memory
+# ---------------------------------------------------------------------------
+
+class Ensemble:
+    """Runs of a ``workloads.Workload`` (or an explicit run list) in one
+    context on the current CUDA/HIP device and stream."""
+
+    def __init__(self, runs, sample_steps: Sequence[int] = (), state_fp64: bool = False,
+                 n_groups: int = 1, use_graph: bool = False, tile_chunks: int = 0, device=None,
+                 stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise DsmcError(-4, "Ensemble", "no GPU visible to torch")
+        self.runs = list(runs)
+        self.specs = _specs(self.runs)
+        self.opt = make_options(state_fp64, n_groups, list(sample_steps), use_graph, tile_chunks)
+        self.nbytes = dsmc_required_bytes(self.specs, self.opt)
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.arena = torch.empty(self.nbytes, dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.ctx = dsmc_init_runs(self.specs, self.opt, self.arena.data_ptr(), self.nbytes,
+                                  self.stream.cuda_stream)
+        self.ensembles = []
+        for r in self.runs:
+            if r.ensemble not in self.ensembles:
+                self.ensembles.append(r.ensemble)
+
+    @classmethod
+    def from_workload(cls, wl, **kw):
+        kw.setdefault("state_fp64", wl.state_fp64)
+        kw.setdefault("n_groups", wl.n_groups)
+        return cls(wl.runs, wl.sample_steps, **kw)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            dsmc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int = 1):
+        dsmc_step(self.ctx, n)
+
+    def sample(self, k: int):
+        dsmc_sample(self.ctx, k)
+
+    def sync(self):
+        dsmc_sync(self.ctx)
+
+    def n_cells(self, ensemble: int = 0) -> int:
+        for r in self.runs:
+            if r.ensemble == ensemble:
+                return r.n_cells
+        raise KeyError(ensemble)
+
+    def moments(self, k: int, ensemble: int = 0):
+        return dsmc_read_moments(self.ctx, k, ensemble, self.n_cells(ensemble))
+
+    def accum(self, k: int, ensemble: int = 0) -> np.ndarray:
+        nr = sum(1 for r in self.runs if r.ensemble == ensemble)
+        G = min(self.opt.n_groups if self.opt.n_groups > 0 else 1, nr)
+        return dsmc_read_accum(self.ctx, k, ensemble, G, self.n_cells(ensemble))
+
+    def info(self) -> dict:
+        return dsmc_get_info(self.ctx)
+
+    def state(self, run: int) -> np.ndarray:
+        return dsmc_get_state(self.ctx, run)
+
+    def set_state(self, run: int, st: np.ndarray):
+        dsmc_set_state(self.ctx, run, st)
+
+    def lcr(self, run: int):
+        rs = self.runs[run]
+        return dsmc_get_lcr(self.ctx, run, rs.capacity + 64 * 1024, rs.n_cells)
+
+    def cell_state(self, run: int) -> dict:
+        return dsmc_get_cell_state(self.ctx, run, self.runs[run].n_cells)
+
+    def counts(self) -> np.ndarray:
+        return dsmc_get_counts(self.ctx, len(self.runs))
+
+
+def counting_sort(keys, nbins: int):
+    """Stable counting sort of a 1-D int32 CUDA tensor on the current stream:
+    returns (lcr, start) CUDA tensors."""
+    import torch
+    n = keys.numel()
+    keys = keys.contiguous()
+    lcr = torch.empty(max(n, 1), dtype=torch.int32, device=keys.device)
+    start = torch.empty(nbins + 1, dtype=torch.int32, device=keys.device)
+    wb = dsmc_counting_sort_bytes(n, nbins)
+    work = torch.empty(wb + 256, dtype=torch.uint8, device=keys.device)
+    wp = (work.data_ptr() + 255) & ~255
+    dsmc_counting_sort(keys.data_ptr(), n, nbins, lcr.data_ptr(), start.data_ptr(), wp, wb,
+                       torch.cuda.current_stream(keys.device).cuda_stream)
+    return lcr[:n], start

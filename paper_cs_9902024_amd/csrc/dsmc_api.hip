@@ -1,0 +1,743 @@
+// Host side of the C ABI declared in include/dsmc.h: validation, the layout of
+// the caller's device arena, the context, the step sequence (optionally
+// replayed from HIP graphs) and the inspection calls.
+#include "dsmc.h"
+#include "dsmc_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace dsmc;
+
+namespace {
+
+const double kSqrtPi = 1.7724538509055160272981674833411;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+int64_t round_up(int64_t x, int64_t m) { return ((x + m - 1) / m) * m; }
+
+struct Ensemble {
+  int32_t id;
+  std::vector<int32_t> runs;
+  int32_t nc;
+  int32_t G;
+  int32_t eg0;
+};
+
+struct Plan {
+  Geometry g{};
+  std::vector<RunDev> runs;
+  std::vector<int32_t> tile_run, face_run, cgroup_run, inflow_runs, eg_start, eg_runs, eg_nc, sample_steps;
+  std::vector<int64_t> eg_acc;
+  std::vector<Ensemble> ens;
+  std::vector<int64_t> spec_capacity;
+  size_t off_runs, off_tile_run, off_face_run, off_cgroup_run, off_inflow, off_eg_start, off_eg_runs, off_eg_acc,
+      off_eg_nc, off_samples;
+  size_t off_P[2][6];
+  size_t off_cell, off_lcr, off_lcr_tmp, off_hist, off_tot, off_bin_start, off_remc, off_gmax, off_ncoll, off_remf,
+      off_gencnt, off_stage, off_acc, off_mom, off_nalive, off_nsorted, off_ngen, off_scalars;
+  size_t total;
+};
+
+dsmc_status fail(std::string *msg, dsmc_status st, const char *fmt, int a = 0, int b = 0) {
+  if (msg) {
+    char buf[256];
+    snprintf(buf, sizeof buf, fmt, a, b);
+    *msg = buf;
+  }
+  return st;
+}
+
+dsmc_status validate(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_options *opt, std::string *msg) {
+  if (!runs || n_runs < 1) return fail(msg, DSMC_EINVAL, "need at least one run");
+  if (opt) {
+    if (opt->n_groups < 0 || opt->n_samples < 0) return fail(msg, DSMC_EINVAL, "negative n_groups or n_samples");
+    if (opt->tile_chunks < 0 || opt->tile_chunks > 4096) return fail(msg, DSMC_EINVAL, "tile_chunks out of range");
+  }
+  const int dim = runs[0].dim;
+  for (int r = 0; r < n_runs; ++r) {
+    const dsmc_run_spec &s = runs[r];
+    if (s.dim != 2 && s.dim != 3) return fail(msg, DSMC_EINVAL, "run %d: dim must be 2 or 3", r);
+    if (s.dim != dim) return fail(msg, DSMC_EINVAL, "run %d: all runs of a context share dim", r);
+    if (s.nx < 1 || s.ny < 1 || s.nz < 1 || (dim == 2 && s.nz != 1))
+      return fail(msg, DSMC_EINVAL, "run %d: bad grid", r);
+    const int64_t nc = (int64_t)s.nx * s.ny * s.nz;
+    if (nc + 2 >= ((int64_t)1 << 31)) return fail(msg, DSMC_EINVAL, "run %d: too many cells", r);
+    if (!(s.lx > 0) || !(s.ly > 0) || !(s.lz > 0)) return fail(msg, DSMC_EINVAL, "run %d: bad box size", r);
+    if (!(s.dt > 0) || !std::isfinite(s.dt)) return fail(msg, DSMC_EINVAL, "run %d: dt must be > 0", r);
+    if (!(s.fnum_sigma >= 0)) return fail(msg, DSMC_EINVAL, "run %d: fnum_sigma must be >= 0", r);
+    if (!(s.omega >= 0.5 && s.omega <= 1.0)) return fail(msg, DSMC_EINVAL, "run %d: omega must be in [0.5, 1]", r);
+    if (!(s.c_ref > 0)) return fail(msg, DSMC_EINVAL, "run %d: c_ref must be > 0", r);
+    for (int f = 0; f < 2 * dim; ++f) {
+      const int bc = s.face_bc[f];
+      if (bc < 0 || bc > 3) return fail(msg, DSMC_EINVAL, "run %d: face %d: unknown boundary", r, f);
+      if (bc == DSMC_BC_INFLOW && f != 0) return fail(msg, DSMC_EINVAL, "run %d: inflow only on -x (face %d)", r, f);
+      if (bc == DSMC_BC_DIFFUSE && !(s.face_T[f] > 0))
+        return fail(msg, DSMC_EINVAL, "run %d: face %d: diffuse wall needs T > 0", r, f);
+    }
+    if (s.face_bc[0] == DSMC_BC_INFLOW && (!(s.inflow_n >= 0) || !(s.inflow_U >= 0) || !(s.inflow_T > 0)))
+      return fail(msg, DSMC_EINVAL, "run %d: bad inflow state", r);
+    if (s.n_init < 0 || s.capacity < s.n_init || s.capacity >= ((int64_t)1 << 31) - (1 << 22))
+      return fail(msg, DSMC_EINVAL, "run %d: need 0 <= n_init <= capacity < 2^31 - 2^22", r);
+    if (s.n_init > 0 && !(s.init_T > 0)) return fail(msg, DSMC_EINVAL, "run %d: init_T must be > 0", r);
+    for (int q = 0; q < r; ++q)
+      if (runs[q].ensemble == s.ensemble &&
+          (runs[q].nx != s.nx || runs[q].ny != s.ny || runs[q].nz != s.nz || runs[q].lx != s.lx ||
+           runs[q].ly != s.ly || runs[q].lz != s.lz))
+        return fail(msg, DSMC_EINVAL, "runs %d and %d share an ensemble but not a grid", q, r);
+  }
+  return DSMC_OK;
+}
+
+// Same initial (sigma c_r)_max rule as everywhere: g at c0 = |U| + 3 sqrt(2 T_max).
+double initial_gmax(const dsmc_run_spec &s) {
+  const bool inflow = s.face_bc[0] == DSMC_BC_INFLOW;
+  double U0 = inflow ? s.inflow_U : 0.0;
+  const double Ui = std::sqrt(s.init_U[0] * s.init_U[0] + s.init_U[1] * s.init_U[1] + s.init_U[2] * s.init_U[2]);
+  if (Ui > U0) U0 = Ui;
+  double Tmax = s.init_T;
+  if (inflow && s.inflow_T > Tmax) Tmax = s.inflow_T;
+  for (int f = 0; f < 2 * s.dim; ++f)
+    if (s.face_bc[f] == DSMC_BC_DIFFUSE && s.face_T[f] > Tmax) Tmax = s.face_T[f];
+  const double c0 = U0 + 3.0 * std::sqrt(2.0 * Tmax);
+  if (s.omega == 0.5) return c0;
+  return c0 * std::pow(c0 / s.c_ref, 1.0 - 2.0 * s.omega);
+}
+
+dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_options *opt_in, Plan &P,
+                      std::string *msg) {
+  dsmc_status st = validate(runs, n_runs, opt_in, msg);
+  if (st) return st;
+  dsmc_options opt{};
+  if (opt_in) opt = *opt_in;
+  Geometry &g = P.g;
+  g.dim = runs[0].dim;
+  g.fp64 = opt.state_fp64 ? 1 : 0;
+  g.tile_chunks = opt.tile_chunks > 0 ? opt.tile_chunks : 256;
+  g.tile = (int64_t)g.tile_chunks * kWave;
+  g.n_runs = n_runs;
+  g.n_samples = opt.n_samples;
+  const int G = opt.n_groups > 0 ? opt.n_groups : 1;
+
+  int max_nc = 0;
+  for (int r = 0; r < n_runs; ++r) max_nc = std::max<int>(max_nc, runs[r].nx * runs[r].ny * runs[r].nz);
+  g.max_nc = max_nc;
+  const int64_t maxbins = (int64_t)max_nc + 1;
+  if (maxbins <= kDigits) {
+    g.npass = 1;
+  } else {
+    int bits = 0;
+    while (((int64_t)1 << bits) < maxbins) ++bits;
+    g.npass = (bits + kDigitBits - 1) / kDigitBits;
+  }
+  g.dstride = g.npass == 1 ? max_nc + 1 : kDigits;
+
+  P.runs.resize(n_runs);
+  P.spec_capacity.resize(n_runs);
+  int64_t so = 0, co = 0, bo = 0, mo = 0, cbo = 0, fo = 0;
+  int32_t to = 0;
+  for (int r = 0; r < n_runs; ++r) {
+    const dsmc_run_spec &s = runs[r];
+    RunDev &R = P.runs[r];
+    R = RunDev{};
+    const int64_t cap = std::max<int64_t>(g.tile, round_up(s.capacity, g.tile));
+    R.so = so;
+    R.cap = cap;
+    R.nc = s.nx * s.ny * s.nz;
+    R.nx = s.nx;
+    R.ny = s.ny;
+    R.nz = s.nz;
+    R.co = co;
+    R.bo = bo;
+    R.to = to;
+    R.nt = (int32_t)(cap / g.tile);
+    R.ndig = g.npass == 1 ? R.nc + 1 : kDigits;
+    R.mo = mo;
+    R.cbo = cbo;
+    R.n_init = s.n_init;
+    R.hs = s.omega == 0.5;
+    for (int f = 0; f < 6; ++f) {
+      R.bc[f] = (f < 2 * g.dim) ? s.face_bc[f] : DSMC_BC_SPECULAR;
+      R.face_T[f] = s.face_T[f];
+      R.face_sqrtT[f] = s.face_T[f] > 0 ? std::sqrt(s.face_T[f]) : 0.0;
+    }
+    R.key0 = s.run_id;
+    R.key1 = s.seed;
+    R.L[0] = s.lx;
+    R.L[1] = s.ly;
+    R.L[2] = s.lz;
+    R.inv_d[0] = (double)s.nx / s.lx;
+    R.inv_d[1] = (double)s.ny / s.ly;
+    R.inv_d[2] = (double)s.nz / s.lz;
+    R.dt = s.dt;
+    const double vc = (s.lx / s.nx) * (s.ly / s.ny) * (s.lz / s.nz);
+    R.coef = s.fnum_sigma * s.dt / vc;
+    R.vhs_exp = 1.0 - 2.0 * s.omega;
+    R.c_ref = s.c_ref;
+    R.gmax0 = initial_gmax(s);
+    R.dy = s.ly / s.ny;
+    R.dz = s.lz / s.nz;
+    R.fo = fo;
+    R.nface = 0;
+    if (s.face_bc[0] == DSMC_BC_INFLOW) {
+      R.nface = s.ny * s.nz;
+      R.beta = 1.0 / std::sqrt(2.0 * s.inflow_T);
+      R.s_inf = s.inflow_U * R.beta;
+      R.p_branch = 1.0 / (1.0 + kSqrtPi * R.s_inf);
+      const double sv = R.s_inf;
+      // flux of a drifting Maxwellian through a plane, per unit area
+      const double flux =
+          s.inflow_n / (2.0 * kSqrtPi * R.beta) * (std::exp(-sv * sv) + kSqrtPi * sv * (1.0 + std::erf(sv)));
+      R.mbar = flux * (R.dy * R.dz) * s.dt;
+      if (!(R.mbar < 1e8)) return fail(msg, DSMC_EINVAL, "run %d: inflow of >= 1e8 particles per face per step", r);
+      R.inflow_sqrtT = std::sqrt(s.inflow_T);
+      P.inflow_runs.push_back(r);
+      for (int j = 0; j < R.nface; ++j) P.face_run.push_back(r);
+    }
+    R.init_U[0] = s.init_U[0];
+    R.init_U[1] = s.init_U[1];
+    R.init_U[2] = s.init_U[2];
+    R.init_sqrtT = s.init_T > 0 ? std::sqrt(s.init_T) : 0.0;
+    for (int t = 0; t < R.nt; ++t) P.tile_run.push_back(r);
+    for (int64_t k = 0; k < round_up(R.nc, 64) / 64; ++k) P.cgroup_run.push_back(r);
+    P.spec_capacity[r] = s.capacity;
+    so += cap;
+    to += R.nt;
+    co += round_up(R.nc, 64);
+    bo += R.nc + 2;
+    mo += (int64_t)R.nt * R.ndig;
+    cbo += R.ndig;
+    fo += R.nface;
+  }
+  g.n_slots = so;
+  g.n_tiles = to;
+  g.n_cells = co;
+  g.n_faces = fo;
+  g.n_inflow_runs = (int32_t)P.inflow_runs.size();
+
+  // ensembles in order of first appearance; group of a run = its index in the ensemble mod G
+  for (int r = 0; r < n_runs; ++r) {
+    Ensemble *e = nullptr;
+    for (auto &x : P.ens)
+      if (x.id == runs[r].ensemble) e = &x;
+    if (!e) {
+      P.ens.push_back(Ensemble{runs[r].ensemble, {}, P.runs[r].nc, 0, 0});
+      e = &P.ens.back();
+    }
+    e->runs.push_back(r);
+  }
+  int32_t eg = 0;
+  int64_t acc = 0;
+  P.eg_start.push_back(0);
+  for (auto &e : P.ens) {
+    e.G = std::min<int32_t>(G, (int32_t)e.runs.size());
+    e.eg0 = eg;
+    for (int gi = 0; gi < e.G; ++gi) {
+      for (size_t k = gi; k < e.runs.size(); k += e.G) P.eg_runs.push_back(e.runs[k]);
+      P.eg_start.push_back((int32_t)P.eg_runs.size());
+      P.eg_acc.push_back(acc);
+      P.eg_nc.push_back(e.nc);
+      acc += (int64_t)e.nc * kFields;
+      ++eg;
+    }
+  }
+  P.eg_acc.push_back(acc);
+  g.n_eg = eg;
+  g.acc_stride = acc;
+  for (int k = 0; k < g.n_samples; ++k) P.sample_steps.push_back(opt.sample_steps ? opt.sample_steps[k] : 0);
+  if (P.sample_steps.empty()) P.sample_steps.push_back(0);
+
+  // arena layout
+  const size_t es = g.fp64 ? 8 : 4;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + std::max<size_t>(bytes, 1));
+    return at;
+  };
+  P.off_runs = take(sizeof(RunDev) * n_runs);
+  P.off_tile_run = take(4 * P.tile_run.size());
+  P.off_face_run = take(4 * P.face_run.size());
+  P.off_cgroup_run = take(4 * P.cgroup_run.size());
+  P.off_inflow = take(4 * P.inflow_runs.size());
+  P.off_eg_start = take(4 * P.eg_start.size());
+  P.off_eg_runs = take(4 * P.eg_runs.size());
+  P.off_eg_acc = take(8 * P.eg_acc.size());
+  P.off_eg_nc = take(4 * P.eg_nc.size());
+  P.off_samples = take(4 * P.sample_steps.size());
+  for (int b = 0; b < 2; ++b)
+    for (int a = 0; a < 6; ++a) P.off_P[b][a] = (a == 2 && g.dim == 2) ? (size_t)-1 : take(es * g.n_slots);
+  P.off_cell = take(4 * g.n_slots);
+  P.off_lcr = take(4 * g.n_slots);
+  P.off_lcr_tmp = g.npass > 1 ? take(4 * g.n_slots) : (size_t)-1;
+  P.off_hist = take(4 * (size_t)mo);
+  P.off_tot = take(4 * (size_t)cbo);
+  P.off_bin_start = take(4 * (size_t)bo);
+  P.off_remc = take(es * g.n_cells);
+  P.off_gmax = take(es * g.n_cells);
+  P.off_ncoll = take(4 * g.n_cells);
+  P.off_remf = take(8 * g.n_faces);
+  P.off_gencnt = take(4 * g.n_faces);
+  P.off_stage = take(8 * kFields * g.n_cells);
+  P.off_acc = take(8 * (size_t)g.acc_stride * g.n_samples);
+  P.off_mom = take(8 * 2 * (size_t)max_nc * kMoments);
+  P.off_nalive = take(4 * n_runs);
+  P.off_nsorted = take(4 * n_runs);
+  P.off_ngen = take(4 * n_runs);
+  P.off_scalars = take(256);
+  P.total = o;
+  return DSMC_OK;
+}
+
+template <typename real>
+DevPtrs<real> carve(const Plan &P, char *base) {
+  DevPtrs<real> d{};
+  d.runs = (const RunDev *)(base + P.off_runs);
+  d.tile_run = (const int32_t *)(base + P.off_tile_run);
+  d.face_run = (const int32_t *)(base + P.off_face_run);
+  d.cgroup_run = (const int32_t *)(base + P.off_cgroup_run);
+  d.inflow_runs = (const int32_t *)(base + P.off_inflow);
+  d.eg_start = (const int32_t *)(base + P.off_eg_start);
+  d.eg_runs = (const int32_t *)(base + P.off_eg_runs);
+  d.eg_acc = (const int64_t *)(base + P.off_eg_acc);
+  d.eg_nc = (const int32_t *)(base + P.off_eg_nc);
+  d.sample_steps = (const int32_t *)(base + P.off_samples);
+  for (int b = 0; b < 2; ++b) {
+    real **c[6] = {&d.P[b].x, &d.P[b].y, &d.P[b].z, &d.P[b].u, &d.P[b].v, &d.P[b].w};
+    for (int a = 0; a < 6; ++a) *c[a] = P.off_P[b][a] == (size_t)-1 ? nullptr : (real *)(base + P.off_P[b][a]);
+  }
+  d.cell = (int32_t *)(base + P.off_cell);
+  d.lcr = (int32_t *)(base + P.off_lcr);
+  d.lcr_tmp = P.off_lcr_tmp == (size_t)-1 ? nullptr : (int32_t *)(base + P.off_lcr_tmp);
+  d.hist = (uint32_t *)(base + P.off_hist);
+  d.digit_tot = (uint32_t *)(base + P.off_tot);
+  d.bin_start = (uint32_t *)(base + P.off_bin_start);
+  d.rem_c = (real *)(base + P.off_remc);
+  d.gmax = (real *)(base + P.off_gmax);
+  d.ncoll = (uint32_t *)(base + P.off_ncoll);
+  d.rem_f = (double *)(base + P.off_remf);
+  d.gen_count = (int32_t *)(base + P.off_gencnt);
+  d.stage = (double *)(base + P.off_stage);
+  d.acc = (double *)(base + P.off_acc);
+  d.mom = (double *)(base + P.off_mom);
+  d.n_alive = (int32_t *)(base + P.off_nalive);
+  d.n_sorted = (int32_t *)(base + P.off_nsorted);
+  d.n_gen = (int32_t *)(base + P.off_ngen);
+  d.step = (uint32_t *)(base + P.off_scalars);
+  d.sample_slot = (int32_t *)(base + P.off_scalars + 4);
+  d.err = (int32_t *)(base + P.off_scalars + 8);
+  return d;
+}
+
+const char *status_text(dsmc_status st) {
+  switch (st) {
+    case DSMC_OK: return "ok";
+    case DSMC_EINVAL: return "invalid argument";
+    case DSMC_ESIZE: return "buffer too small";
+    case DSMC_ECAPACITY: return "a run ran out of particle slots during Generation";
+    case DSMC_EDEVICE: return "HIP error";
+    case DSMC_ESTATE: return "call not valid in the current state";
+    case DSMC_EUNSUPPORTED: return "unsupported";
+    case DSMC_EBOUNCE: return "more than 64 wall interactions of one particle in one step";
+    case DSMC_EREJECT: return "inflow velocity sampler exceeded its attempt limit";
+    case DSMC_ENUMERIC: return "non-finite particle state or an excessive collision rate";
+    default: return "unknown error";
+  }
+}
+
+}  // namespace
+
+struct dsmc_ctx {
+  Plan plan;
+  char *arena = nullptr;
+  hipStream_t stream = nullptr;
+  DevPtrs<float> df{};
+  DevPtrs<double> dd{};
+  int buf = 0;
+  int64_t steps_done = 0;
+  bool sorted = false;
+  dsmc_status latched = DSMC_OK;
+  std::string msg;
+  bool use_graph = false;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+dsmc_status set_err(dsmc_ctx *c, dsmc_status st, const std::string &m) {
+  c->msg = m;
+  return st;
+}
+
+dsmc_status check_hip(dsmc_ctx *c, hipError_t e, const char *what) {
+  if (e == hipSuccess) return DSMC_OK;
+  c->latched = DSMC_EDEVICE;
+  return set_err(c, DSMC_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Synchronise and collect the device error latch.
+dsmc_status sync_ctx(dsmc_ctx *c) {
+  if (c->latched) return c->latched;
+  dsmc_status st = check_hip(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  if (st) return st;
+  int32_t err = 0;
+  const int32_t *derr = c->plan.g.fp64 ? c->dd.err : c->df.err;
+  st = check_hip(c, hipMemcpy(&err, derr, 4, hipMemcpyDeviceToHost), "hipMemcpy(err)");
+  if (st) return st;
+  if (err) {
+    c->latched = err;
+    return set_err(c, err, status_text(err));
+  }
+  return DSMC_OK;
+}
+
+template <typename T>
+dsmc_status upload(dsmc_ctx *c, size_t off, const std::vector<T> &v) {
+  if (v.empty()) return DSMC_OK;
+  return check_hip(c, hipMemcpyAsync(c->arena + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream),
+                   "hipMemcpyAsync(upload)");
+}
+
+template <typename T>
+dsmc_status download(dsmc_ctx *c, void *dst, const void *src, size_t n) {
+  return check_hip(c, hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToHost, c->stream),
+                   "hipMemcpyAsync(download)");
+}
+
+void launch_one_step(dsmc_ctx *c, int buf) {
+  if (c->plan.g.fp64) launch_step<double>(c->plan.g, c->dd, buf, c->stream);
+  else launch_step<float>(c->plan.g, c->df, buf, c->stream);
+}
+
+int find_ensemble(const dsmc_ctx *c, int32_t id) {
+  for (size_t e = 0; e < c->plan.ens.size(); ++e)
+    if (c->plan.ens[e].id == id) return (int)e;
+  return -1;
+}
+
+}  // namespace
+
+extern "C" {
+
+dsmc_status dsmc_required_bytes(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_options *opt, size_t *bytes) {
+  if (!bytes) return DSMC_EINVAL;
+  Plan P;
+  dsmc_status st = make_plan(runs, n_runs, opt, P, nullptr);
+  if (st) return st;
+  *bytes = P.total;
+  return DSMC_OK;
+}
+
+dsmc_status dsmc_init_runs(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_options *opt, void *arena,
+                           size_t arena_bytes, void *hip_stream, dsmc_ctx **out) {
+  if (!out) return DSMC_EINVAL;
+  *out = nullptr;
+  dsmc_ctx *c = new (std::nothrow) dsmc_ctx();
+  if (!c) return DSMC_EINVAL;
+  std::string msg;
+  dsmc_status st = make_plan(runs, n_runs, opt, c->plan, &msg);
+  if (st) {
+    delete c;
+    return st;
+  }
+  if (!arena || ((uintptr_t)arena & 255) || arena_bytes < c->plan.total) {
+    delete c;
+    return DSMC_ESIZE;
+  }
+  c->arena = (char *)arena;
+  c->stream = (hipStream_t)hip_stream;
+  c->use_graph = opt && opt->use_graph && c->stream != nullptr;
+  const Plan &P = c->plan;
+  if (P.g.fp64) c->dd = carve<double>(P, c->arena);
+  else c->df = carve<float>(P, c->arena);
+  st = upload(c, P.off_runs, P.runs);
+  if (!st) st = upload(c, P.off_tile_run, P.tile_run);
+  if (!st) st = upload(c, P.off_face_run, P.face_run);
+  if (!st) st = upload(c, P.off_cgroup_run, P.cgroup_run);
+  if (!st) st = upload(c, P.off_inflow, P.inflow_runs);
+  if (!st) st = upload(c, P.off_eg_start, P.eg_start);
+  if (!st) st = upload(c, P.off_eg_runs, P.eg_runs);
+  if (!st) st = upload(c, P.off_eg_acc, P.eg_acc);
+  if (!st) st = upload(c, P.off_eg_nc, P.eg_nc);
+  if (!st) st = upload(c, P.off_samples, P.sample_steps);
+  if (!st) {
+    if (P.g.fp64) launch_init<double>(P.g, c->dd, c->stream);
+    else launch_init<float>(P.g, c->df, c->stream);
+    st = check_hip(c, hipGetLastError(), "launch(init)");
+  }
+  if (!st) st = sync_ctx(c);
+  if (st) {
+    delete c;
+    return st;
+  }
+  *out = c;
+  return DSMC_OK;
+}
+
+dsmc_status dsmc_step(dsmc_ctx *c, int32_t n_steps) {
+  if (!c) return DSMC_EINVAL;
+  if (c->latched) return c->latched;
+  if (n_steps < 0) return set_err(c, DSMC_EINVAL, "n_steps must be >= 0");
+  for (int32_t i = 0; i < n_steps; ++i) {
+    if (c->use_graph) {
+      hipGraphExec_t &ge = c->graph[c->buf];
+      if (!ge) {
+        hipGraph_t gr = nullptr;
+        dsmc_status st = check_hip(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed), "capture");
+        if (st) return st;
+        launch_one_step(c, c->buf);
+        st = check_hip(c, hipStreamEndCapture(c->stream, &gr), "end capture");
+        if (st) return st;
+        st = check_hip(c, hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0), "graph instantiate");
+        (void)hipGraphDestroy(gr);
+        if (st) return st;
+      }
+      dsmc_status st = check_hip(c, hipGraphLaunch(ge, c->stream), "hipGraphLaunch");
+      if (st) return st;
+    } else {
+      launch_one_step(c, c->buf);
+      dsmc_status st = check_hip(c, hipGetLastError(), "launch(step)");
+      if (st) return st;
+    }
+    c->buf ^= 1;
+    c->steps_done++;
+    c->sorted = true;
+  }
+  return DSMC_OK;
+}
+
+dsmc_status dsmc_sample(dsmc_ctx *c, int32_t k) {
+  if (!c) return DSMC_EINVAL;
+  if (c->latched) return c->latched;
+  if (k < 0 || k >= c->plan.g.n_samples) return set_err(c, DSMC_EINVAL, "sample index out of range");
+  if (!c->sorted) return set_err(c, DSMC_ESTATE, "dsmc_sample needs a completed step after init/set_state");
+  if (c->plan.g.fp64) launch_sample<double>(c->plan.g, c->dd, c->buf, k, c->stream);
+  else launch_sample<float>(c->plan.g, c->df, c->buf, k, c->stream);
+  return check_hip(c, hipGetLastError(), "launch(sample)");
+}
+
+dsmc_status dsmc_read_moments(dsmc_ctx *c, int32_t k, int32_t ensemble, double *out, double *out_se,
+                              size_t capacity_doubles) {
+  if (!c || !out) return DSMC_EINVAL;
+  if (c->latched) return c->latched;
+  if (k < 0 || k >= c->plan.g.n_samples) return set_err(c, DSMC_EINVAL, "sample index out of range");
+  const int e = find_ensemble(c, ensemble);
+  if (e < 0) return set_err(c, DSMC_EINVAL, "unknown ensemble");
+  const Ensemble &E = c->plan.ens[e];
+  const size_t need = (size_t)E.nc * kMoments;
+  if (capacity_doubles < need) return set_err(c, DSMC_ESIZE, "output too small");
+  if (c->plan.g.fp64) launch_moments<double>(c->plan.g, c->dd, k, E.eg0, E.G, E.nc, (int)E.runs.size(), c->stream);
+  else launch_moments<float>(c->plan.g, c->df, k, E.eg0, E.G, E.nc, (int)E.runs.size(), c->stream);
+  dsmc_status st = check_hip(c, hipGetLastError(), "launch(moments)");
+  const double *mom = c->plan.g.fp64 ? c->dd.mom : c->df.mom;
+  if (!st) st = download<double>(c, out, mom, need);
+  if (!st && out_se) st = download<double>(c, out_se, mom + (size_t)c->plan.g.max_nc * kMoments, need);
+  if (!st) st = sync_ctx(c);
+  return st;
+}
+
+dsmc_status dsmc_read_accum(dsmc_ctx *c, int32_t k, int32_t ensemble, double *out, size_t capacity_doubles) {
+  if (!c || !out) return DSMC_EINVAL;
+  if (c->latched) return c->latched;
+  if (k < 0 || k >= c->plan.g.n_samples) return set_err(c, DSMC_EINVAL, "sample index out of range");
+  const int e = find_ensemble(c, ensemble);
+  if (e < 0) return set_err(c, DSMC_EINVAL, "unknown ensemble");
+  const Ensemble &E = c->plan.ens[e];
+  const size_t need = (size_t)E.G * E.nc * kFields;
+  if (capacity_doubles < need) return set_err(c, DSMC_ESIZE, "output too small");
+  const double *acc = (c->plan.g.fp64 ? c->dd.acc : c->df.acc) + (size_t)k * c->plan.g.acc_stride +
+                      c->plan.eg_acc[E.eg0];
+  dsmc_status st = download<double>(c, out, acc, need);
+  if (!st) st = sync_ctx(c);
+  return st;
+}
+
+dsmc_status dsmc_sync(dsmc_ctx *c) {
+  if (!c) return DSMC_EINVAL;
+  return sync_ctx(c);
+}
+
+void dsmc_destroy(dsmc_ctx *c) {
+  if (!c) return;
+  if (c->stream || c->arena) (void)hipStreamSynchronize(c->stream);
+  for (auto &g : c->graph)
+    if (g) (void)hipGraphExecDestroy(g);
+  delete c;
+}
+
+const char *dsmc_last_error(const dsmc_ctx *c) {
+  if (!c) return "no context";
+  return c->msg.empty() ? "ok" : c->msg.c_str();
+}
+
+dsmc_status dsmc_get_info(dsmc_ctx *c, int64_t info[8]) {
+  if (!c || !info) return DSMC_EINVAL;
+  dsmc_status st = sync_ctx(c);
+  const Geometry &g = c->plan.g;
+  info[0] = c->steps_done;
+  info[1] = g.n_runs;
+  info[2] = (int64_t)c->plan.ens.size();
+  info[3] = g.fp64;
+  info[4] = g.npass;
+  info[5] = g.n_tiles;
+  info[6] = g.n_slots;
+  info[7] = c->latched;
+  return st;
+}
+
+}  // extern "C"
+
+namespace {
+template <typename real>
+dsmc_status get_state_t(dsmc_ctx *c, const DevPtrs<real> &d, int32_t run, double *out, int64_t cap, int64_t *n) {
+  const RunDev &R = c->plan.runs[run];
+  int32_t na = 0;
+  dsmc_status st = download<int32_t>(c, &na, d.n_alive + run, 1);
+  if (!st) st = sync_ctx(c);
+  if (st) return st;
+  *n = na;
+  if (!out) return DSMC_OK;
+  if (cap < na) return set_err(c, DSMC_ESIZE, "output too small");
+  std::vector<real> tmp((size_t)na);
+  const Particles<real> &P = d.P[c->buf];
+  real *comp[6] = {P.x, P.y, P.z, P.u, P.v, P.w};
+  for (int a = 0; a < 6; ++a) {
+    if (!comp[a]) {
+      std::fill(out + (size_t)a * na, out + (size_t)(a + 1) * na, 0.0);
+      continue;
+    }
+    if (na) st = download<real>(c, tmp.data(), comp[a] + R.so, (size_t)na);
+    if (!st) st = check_hip(c, hipStreamSynchronize(c->stream), "sync");
+    if (st) return st;
+    for (int64_t i = 0; i < na; ++i) out[(size_t)a * na + i] = (double)tmp[i];
+  }
+  return DSMC_OK;
+}
+
+template <typename real>
+dsmc_status set_state_t(dsmc_ctx *c, const DevPtrs<real> &d, int32_t run, const double *in, int64_t n) {
+  const RunDev &R = c->plan.runs[run];
+  if (n < 0 || n > c->plan.spec_capacity[run]) return set_err(c, DSMC_EINVAL, "n exceeds the run's capacity");
+  dsmc_status st = sync_ctx(c);
+  if (st) return st;
+  std::vector<real> tmp((size_t)std::max<int64_t>(n, 1));
+  const Particles<real> &P = d.P[c->buf];
+  real *comp[6] = {P.x, P.y, P.z, P.u, P.v, P.w};
+  for (int a = 0; a < 6; ++a) {
+    if (!comp[a] || n == 0) continue;
+    for (int64_t i = 0; i < n; ++i) tmp[i] = (real)in[(size_t)a * n + i];
+    st = check_hip(c, hipMemcpyAsync(comp[a] + R.so, tmp.data(), n * sizeof(real), hipMemcpyHostToDevice, c->stream),
+                   "upload state");
+    if (!st) st = check_hip(c, hipStreamSynchronize(c->stream), "sync");
+    if (st) return st;
+  }
+  const int32_t nn = (int32_t)n;
+  st = check_hip(c, hipMemcpyAsync(d.n_alive + run, &nn, 4, hipMemcpyHostToDevice, c->stream), "upload n");
+  if (!st) st = sync_ctx(c);
+  c->sorted = false;
+  return st;
+}
+
+template <typename real>
+dsmc_status cell_state_t(dsmc_ctx *c, const DevPtrs<real> &d, int32_t run, double *rem, double *gmax,
+                         int64_t *ncoll) {
+  const RunDev &R = c->plan.runs[run];
+  std::vector<real> a((size_t)R.nc), b((size_t)R.nc);
+  std::vector<uint32_t> k((size_t)R.nc);
+  dsmc_status st = download<real>(c, a.data(), d.rem_c + R.co, R.nc);
+  if (!st) st = download<real>(c, b.data(), d.gmax + R.co, R.nc);
+  if (!st) st = download<uint32_t>(c, k.data(), d.ncoll + R.co, R.nc);
+  if (!st) st = sync_ctx(c);
+  if (st) return st;
+  for (int i = 0; i < R.nc; ++i) {
+    if (rem) rem[i] = (double)a[i];
+    if (gmax) gmax[i] = (double)b[i];
+    if (ncoll) ncoll[i] = (int64_t)k[i];
+  }
+  return DSMC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+dsmc_status dsmc_get_state(dsmc_ctx *c, int32_t run, double *out, int64_t cap, int64_t *n) {
+  if (!c || !n || run < 0 || run >= c->plan.g.n_runs) return DSMC_EINVAL;
+  if (c->latched) return c->latched;
+  return c->plan.g.fp64 ? get_state_t(c, c->dd, run, out, cap, n) : get_state_t(c, c->df, run, out, cap, n);
+}
+
+dsmc_status dsmc_set_state(dsmc_ctx *c, int32_t run, const double *in, int64_t n) {
+  if (!c || (!in && n > 0) || run < 0 || run >= c->plan.g.n_runs) return DSMC_EINVAL;
+  if (c->latched) return c->latched;
+  return c->plan.g.fp64 ? set_state_t(c, c->dd, run, in, n) : set_state_t(c, c->df, run, in, n);
+}
+
+dsmc_status dsmc_get_lcr(dsmc_ctx *c, int32_t run, int32_t *lcr, int32_t *cell, int64_t *start, int64_t cap,
+                         int64_t *n) {
+  if (!c || !n || run < 0 || run >= c->plan.g.n_runs) return DSMC_EINVAL;
+  if (c->latched) return c->latched;
+  if (c->steps_done == 0) return set_err(c, DSMC_ESTATE, "no step done yet");
+  const RunDev &R = c->plan.runs[run];
+  const bool f64 = c->plan.g.fp64;
+  const int32_t *d_ns = f64 ? c->dd.n_sorted : c->df.n_sorted;
+  const int32_t *d_lcr = f64 ? c->dd.lcr : c->df.lcr;
+  const int32_t *d_cell = f64 ? c->dd.cell : c->df.cell;
+  const uint32_t *d_start = f64 ? c->dd.bin_start : c->df.bin_start;
+  int32_t ns = 0;
+  dsmc_status st = download<int32_t>(c, &ns, d_ns + run, 1);
+  if (!st) st = sync_ctx(c);
+  if (st) return st;
+  *n = ns;
+  if (cap < ns) return set_err(c, DSMC_ESIZE, "output too small");
+  if (lcr && ns) st = download<int32_t>(c, lcr, d_lcr + R.so, ns);
+  if (!st && cell && ns) st = download<int32_t>(c, cell, d_cell + R.so, ns);
+  std::vector<uint32_t> s((size_t)R.nc + 2);
+  if (!st && start) st = download<uint32_t>(c, s.data(), d_start + R.bo, (size_t)R.nc + 2);
+  if (!st) st = sync_ctx(c);
+  if (!st && start)
+    for (int i = 0; i < R.nc + 2; ++i) start[i] = s[i];
+  return st;
+}
+
+dsmc_status dsmc_get_cell_state(dsmc_ctx *c, int32_t run, double *rem, double *gmax, int64_t *ncoll) {
+  if (!c || run < 0 || run >= c->plan.g.n_runs) return DSMC_EINVAL;
+  if (c->latched) return c->latched;
+  return c->plan.g.fp64 ? cell_state_t(c, c->dd, run, rem, gmax, ncoll) : cell_state_t(c, c->df, run, rem, gmax, ncoll);
+}
+
+dsmc_status dsmc_get_counts(dsmc_ctx *c, int64_t *out, int32_t n_runs) {
+  if (!c || !out || n_runs != c->plan.g.n_runs) return DSMC_EINVAL;
+  if (c->latched) return c->latched;
+  std::vector<int32_t> a((size_t)n_runs), b((size_t)n_runs);
+  const bool f64 = c->plan.g.fp64;
+  dsmc_status st = download<int32_t>(c, a.data(), f64 ? c->dd.n_alive : c->df.n_alive, n_runs);
+  if (!st) st = download<int32_t>(c, b.data(), f64 ? c->dd.n_gen : c->df.n_gen, n_runs);
+  if (!st) st = sync_ctx(c);
+  if (st) return st;
+  for (int r = 0; r < n_runs; ++r) {
+    out[2 * r] = a[r];
+    out[2 * r + 1] = b[r];
+  }
+  return DSMC_OK;
+}
+
+dsmc_status dsmc_counting_sort_bytes(int64_t n, int32_t nbins, size_t *bytes) {
+  if (!bytes || n < 0 || n >= ((int64_t)1 << 31) || nbins < 1) return DSMC_EINVAL;
+  *bytes = counting_sort_workspace(n, nbins, 256);
+  return DSMC_OK;
+}
+
+dsmc_status dsmc_counting_sort(const int32_t *keys, int64_t n, int32_t nbins, int32_t *lcr, uint32_t *start,
+                               void *work, size_t work_bytes, void *hip_stream) {
+  if (n < 0 || n >= ((int64_t)1 << 31) || nbins < 1 || !start || !work) return DSMC_EINVAL;
+  if (n > 0 && (!keys || !lcr)) return DSMC_EINVAL;
+  if (((uintptr_t)work & 255) || work_bytes < counting_sort_workspace(n, nbins, 256)) return DSMC_ESIZE;
+  launch_counting_sort(keys, n, nbins, lcr, start, work, 256, (hipStream_t)hip_stream);
+  return hipGetLastError() == hipSuccess ? DSMC_OK : DSMC_EDEVICE;
+}
+
+}  // extern "C"

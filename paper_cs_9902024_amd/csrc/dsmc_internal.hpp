@@ -1,0 +1,131 @@
+// Internal declarations shared by the kernels and the host side of the DSMC
+// library (gfx950).  Not part of the public C ABI (include/dsmc.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace dsmc {
+
+constexpr int kWave = 64;
+constexpr int kWavesPerBlock = 4;          // 256-thread blocks
+constexpr int kDigitBits = 11;             // indexing digit: 2048 bins per pass
+constexpr int kDigits = 1 << kDigitBits;
+constexpr int kMaxWallHits = 64;           // wall interactions per particle per step
+constexpr int kMaxGenAttempts = 1000;      // inflow normal-velocity rejection
+constexpr int kFields = 7;                 // N, sum u, v, w, u^2, v^2, w^2
+constexpr int kMoments = 8;                // n, ux, uy, uz, T, Tx, Ty, Tz
+
+// Philox counter word 1: what the stream is for.
+enum : uint32_t { kInit = 0, kGen = 1, kWall = 2, kColl = 3 };
+enum : int { kSpecular = 0, kDiffuse = 1, kInflow = 2, kOutflow = 3 };
+
+// Device error codes (same values as the public status codes).
+enum : int { kErrCapacity = -3, kErrBounce = -7, kErrReject = -8, kErrNumeric = -9 };
+constexpr double kMaxSelections = 1e9;  // per cell per step; more means non-finite state
+
+// Per-run constants and layout, read by every kernel (AoS in device memory).
+struct RunDev {
+  int64_t so;        // first particle slot of the run
+  int64_t cap;       // slots reserved (multiple of the tile)
+  int64_t co;        // first cell of the run in the global cell arrays (64-aligned)
+  int64_t bo;        // first entry of the run in the bin-start array (nc + 2 entries)
+  int64_t mo;        // first entry of the run in the tile histogram matrix
+  int64_t cbo;       // first entry of the run in the digit-total array
+  int64_t fo;        // first inflow face of the run
+  int64_t n_init;
+  int32_t to;        // first tile of the run
+  int32_t nt;        // tiles of the run
+  int32_t nc, nx, ny, nz;
+  int32_t nface;     // inflow face elements (0 without inflow)
+  int32_t ndig;      // digits of the first indexing pass
+  int32_t hs;        // hard sphere (omega == 0.5)
+  int32_t bc[6];
+  uint32_t key0, key1;   // Philox key: run id, seed
+  double L[3], inv_d[3];
+  double dt, coef, vhs_exp, c_ref, gmax0;
+  double face_T[6], face_sqrtT[6];
+  double mbar, beta, s_inf, p_branch, inflow_sqrtT, dy, dz;
+  double init_U[3], init_sqrtT;
+};
+
+template <typename real>
+struct Particles {
+  real *x, *y, *z, *u, *v, *w;
+};
+
+// Device pointers of one context, carved out of the caller's arena.
+template <typename real>
+struct DevPtrs {
+  const RunDev *runs;
+  const int32_t *tile_run;     // [n_tiles]
+  const int32_t *face_run;     // [n_faces]
+  const int32_t *cgroup_run;   // [n_cells_aligned / 64]
+  const int32_t *inflow_runs;  // [n_inflow_runs]
+  const int32_t *eg_start;     // [n_eg + 1] CSR of runs per (ensemble, group)
+  const int32_t *eg_runs;
+  const int64_t *eg_acc;       // [n_eg + 1] offset (doubles) of each (ensemble, group) block
+  const int32_t *eg_nc;        // [n_eg]
+  const int32_t *sample_steps; // [n_samples]
+  Particles<real> P[2];
+  int32_t *cell;               // [slots] cell (bin) of each slot after Motion
+  int32_t *lcr;                // [slots] run-local slot in cell order
+  int32_t *lcr_tmp;            // [slots] previous indexing pass (multi-pass only)
+  uint32_t *hist;              // tile histograms, tile-major
+  uint32_t *digit_tot;         // per run digit totals / digit starts
+  uint32_t *bin_start;         // per run nc + 2 entries, run-local
+  real *rem_c, *gmax;          // [cells]
+  uint32_t *ncoll;             // [cells] cumulative accepted collisions
+  double *rem_f;               // [faces]
+  int32_t *gen_count;          // [faces]
+  double *stage;               // [cells][7] per-run sample sums of one sample
+  double *acc;                 // [n_samples][acc_stride]
+  double *mom;                 // [2][max_nc][8]
+  int32_t *n_alive;            // [runs]
+  int32_t *n_sorted;           // [runs]
+  int32_t *n_gen;              // [runs]
+  uint32_t *step;              // device step counter
+  int32_t *sample_slot;        // sample slot of the current step or -1
+  int32_t *err;                // first device error (0 = none)
+};
+
+struct Geometry {
+  int dim;
+  int fp64;
+  int tile_chunks;       // 64-slot chunks per indexing tile
+  int64_t tile;          // slots per tile
+  int n_runs;
+  int32_t n_tiles;
+  int64_t n_slots;
+  int64_t n_cells;       // aligned total
+  int64_t n_faces;
+  int32_t n_inflow_runs;
+  int npass;             // indexing passes (1: digit = bin)
+  int dstride;           // LDS words per wave for one histogram
+  int max_nc;
+  int n_eg;
+  int64_t acc_stride;
+  int n_samples;
+  int collide_block;
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (dsmc_kernels.hip)
+// ---------------------------------------------------------------------------
+template <typename real>
+void launch_init(const Geometry &g, const DevPtrs<real> &d, hipStream_t s);
+template <typename real>
+void launch_step(const Geometry &g, const DevPtrs<real> &d, int buf, hipStream_t s);
+template <typename real>
+void launch_sample(const Geometry &g, const DevPtrs<real> &d, int buf, int slot, hipStream_t s);
+template <typename real>
+void launch_moments(const Geometry &g, const DevPtrs<real> &d, int slot, int eg0, int n_groups,
+                    int nc, int n_runs_ens, hipStream_t s);
+
+// Stand-alone stable counting sort of keys[0..n) into lcr (device pointers).
+size_t counting_sort_workspace(int64_t n, int32_t nbins, int tile_chunks);
+void launch_counting_sort(const int32_t *keys, int64_t n, int32_t nbins, int32_t *lcr,
+                          uint32_t *start, void *work, int tile_chunks, hipStream_t s);
+
+}  // namespace dsmc

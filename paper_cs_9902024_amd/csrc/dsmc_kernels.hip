@@ -1,0 +1,1094 @@
+// HIP kernels of the unsteady-DSMC inner loop for gfx950 (MI355X).
+//
+// One time step follows the order of the sequential algorithm of Sec. 1.1 of
+// the paper: Generation -> Motion (+Enumeration) -> Indexing (the LCR
+// readdressing array) -> Interaction -> Sampling.  The paper's data
+// parallelisation (Sec. 1.4: processor m takes elements m, m+p, m+2p, ... of
+// the particle array P and of the cell array C) becomes contiguous, coalesced
+// per-lane ownership of particles and cells; its parallel independent runs
+// (Sec. 1.3) become many runs advanced by every launch.  The one step the paper
+// runs sequentially (filling LCR, Sec. 1.4) is a parallel, stable counting sort
+// here: a per-tile LDS digit histogram (fused into Motion), a column scan over
+// tiles, a per-run digit scan, and a scatter whose within-tile ranks come from
+// wavefront ballots, so the result equals the sequential stable order exactly.
+//
+// Every kernel reads the step number and the sample slot from device memory,
+// so a whole step can be replayed from a HIP graph without host involvement.
+#include "dsmc_internal.hpp"
+
+#include <algorithm>
+
+namespace dsmc {
+
+// ---------------------------------------------------------------------------
+// Random numbers: Philox4x32-10 (Salmon et al., SC'11) and conversions
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+  }
+  return c;
+}
+
+// Uniform in (0,1).  FP64: 52 bits from a word pair, centred.  FP32: 23 bits
+// of the first word of the pair, centred.
+template <typename real> __device__ __forceinline__ real u01(uint32_t a, uint32_t b);
+template <> __device__ __forceinline__ double u01<double>(uint32_t a, uint32_t b) {
+  const uint64_t m = ((uint64_t)a << 20) | (uint64_t)(b >> 12);
+  return ((double)m + 0.5) * 0x1p-52;
+}
+template <> __device__ __forceinline__ float u01<float>(uint32_t a, uint32_t) {
+  return ((float)(a >> 9) + 0.5f) * 0x1p-23f;
+}
+
+template <typename real> __device__ __forceinline__ real two_pi();
+template <> __device__ __forceinline__ double two_pi<double>() { return 6.283185307179586476925286766559; }
+template <> __device__ __forceinline__ float two_pi<float>() { return 6.2831853071795864769f; }
+
+template <typename real> __device__ __forceinline__ real infinity();
+template <> __device__ __forceinline__ double infinity<double>() { return __builtin_inf(); }
+template <> __device__ __forceinline__ float infinity<float>() { return __builtin_inff(); }
+
+// Stream of uniforms for one (key, step, purpose, index): uniform k comes from
+// Philox block k/2 (counter word 3), words 2(k%2) and 2(k%2)+1.
+template <typename real>
+struct UStream {
+  uint32_t k0, k1, c0, c1, c2;
+  uint32_t next;
+  uint32_t blk_id;
+  uint4 blk;
+  __device__ UStream(uint32_t key0, uint32_t key1, uint32_t step, uint32_t purpose, uint32_t idx)
+      : k0(key0), k1(key1), c0(step), c1(purpose), c2(idx), next(0), blk_id(0xFFFFFFFFu) {}
+  __device__ __forceinline__ void seek(uint32_t k) { next = k; }
+  __device__ __forceinline__ real operator()() {
+    const uint32_t b = next >> 1;
+    if (b != blk_id) {
+      blk = philox(make_uint4(c0, c1, c2, b), k0, k1);
+      blk_id = b;
+    }
+    const bool hi = next & 1u;
+    next++;
+    return hi ? u01<real>(blk.z, blk.w) : u01<real>(blk.x, blk.y);
+  }
+};
+
+template <typename real>
+__device__ __forceinline__ void box_muller(real u1, real u2, real &n0, real &n1) {
+  const real r = sqrt((real)-2 * log(u1));
+  const real th = two_pi<real>() * u2;
+  n0 = r * cos(th);
+  n1 = r * sin(th);
+}
+
+__device__ __forceinline__ void set_error(int32_t *err, int code) { atomicCAS(err, 0, code); }
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <typename real>
+__device__ __forceinline__ int32_t axis_index(real x, real inv, int32_t n) {
+  const real f = floor(x * inv);
+  if (!(f > (real)0)) return 0;
+  if (f >= (real)(n - 1)) return n - 1;
+  return (int32_t)f;
+}
+
+// sigma(c_r)/sigma_ref * c_r: hard sphere or VHS.
+template <typename real>
+__device__ __forceinline__ real g_of(const RunDev &R, real cr) {
+  if (R.hs) return cr;
+  if (!(cr > (real)0)) return (real)0;
+  return cr * pow(cr / (real)R.c_ref, (real)R.vhs_exp);
+}
+
+__device__ __forceinline__ int32_t blocks_for(int64_t n, int per) { return (int32_t)((n + per - 1) / per); }
+
+// ---------------------------------------------------------------------------
+// Initialisation
+// ---------------------------------------------------------------------------
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_init_cells(DevPtrs<real> d, int64_t n_cells) {
+  for (int64_t gc = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; gc < n_cells;
+       gc += (int64_t)gridDim.x * blockDim.x) {
+    const RunDev &R = d.runs[d.cgroup_run[gc >> 6]];
+    if (gc - R.co >= R.nc) continue;
+    d.rem_c[gc] = (real)0;
+    d.gmax[gc] = (real)R.gmax0;
+    d.ncoll[gc] = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fill_f64(double *p, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_init_runs(DevPtrs<real> d, int n_runs) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n_runs) {
+    d.n_alive[r] = (int32_t)d.runs[r].n_init;
+    d.n_sorted[r] = 0;
+    d.n_gen[r] = 0;
+  }
+  if (r == 0) {
+    *d.step = 0;
+    *d.sample_slot = -1;
+    *d.err = 0;
+  }
+}
+
+// Uniform Maxwellian fill: slot i draws from (step 0, INIT, i).  Uniforms 0..3
+// are two Box-Muller pairs for the velocity (last output unused), 4..6 the
+// position.
+template <typename real, int DIM>
+__global__ __launch_bounds__(256) void k_init_particles(DevPtrs<real> d, int64_t n_slots, int64_t tile) {
+  Particles<real> P = d.P[0];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_slots;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const RunDev &R = d.runs[d.tile_run[i / tile]];
+    const int64_t loc = i - R.so;
+    if (loc >= R.n_init) continue;
+    UStream<real> s(R.key0, R.key1, 0u, kInit, (uint32_t)loc);
+    const real a0 = s(), a1 = s(), a2 = s(), a3 = s();
+    real n0, n1, n2, n3;
+    box_muller(a0, a1, n0, n1);
+    box_muller(a2, a3, n2, n3);
+    const real st = (real)R.init_sqrtT;
+    P.u[i] = (real)R.init_U[0] + st * n0;
+    P.v[i] = (real)R.init_U[1] + st * n1;
+    P.w[i] = (real)R.init_U[2] + st * n2;
+    const real ux = s(), uy = s(), uz = s();
+    P.x[i] = ux * (real)R.L[0];
+    P.y[i] = uy * (real)R.L[1];
+    if (DIM == 3) P.z[i] = uz * (real)R.L[2];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Step bookkeeping
+// ---------------------------------------------------------------------------
+
+__global__ void k_step_begin(uint32_t *step, int32_t *slot, const int32_t *sample_steps, int n_samples) {
+  const uint32_t s = *step + 1u;
+  *step = s;
+  int k = -1;
+  for (int i = 0; i < n_samples; ++i)
+    if ((uint32_t)sample_steps[i] == s) {
+      k = i;
+      break;
+    }
+  *slot = k;
+}
+
+// ---------------------------------------------------------------------------
+// Generation: drifting-Maxwellian inflow through the -x face
+// ---------------------------------------------------------------------------
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_gen_count(DevPtrs<real> d, int64_t n_faces) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n_faces;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const RunDev &R = d.runs[d.face_run[j]];
+    const double M = R.mbar + d.rem_f[j];
+    const double fl = floor(M);
+    d.rem_f[j] = M - fl;
+    d.gen_count[j] = (int32_t)fl;
+  }
+}
+
+template <typename real, int DIM>
+__device__ void emit_face(const RunDev &R, uint32_t step, int32_t jl, int32_t cnt, int64_t dst0,
+                          Particles<real> P, int32_t *err) {
+  UStream<real> s(R.key0, R.key1, step, kGen, (uint32_t)jl);
+  const real s_inf = (real)R.s_inf, p_branch = (real)R.p_branch, beta = (real)R.beta;
+  const real st = (real)R.inflow_sqrtT, dt = (real)R.dt, dy = (real)R.dy, dz = (real)R.dz;
+  const int32_t iy = jl % R.ny, iz = jl / R.ny;
+  for (int32_t k = 0; k < cnt; ++k) {
+    // normal velocity: z = beta*u has density ~ z exp(-(z-s)^2), z > 0
+    real z = 0;
+    int att;
+    for (att = 0; att < kMaxGenAttempts; ++att) {
+      const real ub = s(), up = s(), uq = s(), ua = s();
+      const real r = sqrt(-log(up));
+      const real x = (ub < p_branch) ? ((uq < (real)0.5) ? -r : r) : r * cos(two_pi<real>() * uq);
+      z = s_inf + x;
+      if (z > (real)0 && ua < z / (s_inf + fabs(x))) break;
+    }
+    if (att == kMaxGenAttempts) {
+      set_error(err, kErrReject);
+      return;
+    }
+    const real u = z / beta;
+    const real v1 = s(), v2 = s();
+    real t0, t1;
+    box_muller(v1, v2, t0, t1);
+    const real y = ((real)iy + s()) * dy;
+    real zc = 0;
+    if (DIM == 3) zc = ((real)iz + s()) * dz;
+    const real ut = s();
+    const real x0 = -(u * dt) * ((real)1 - ut);
+    const int64_t o = dst0 + k;
+    P.x[o] = x0;
+    P.y[o] = y;
+    if (DIM == 3) P.z[o] = zc;
+    P.u[o] = u;
+    P.v[o] = st * t0;
+    P.w[o] = st * t1;
+  }
+}
+
+// One block per run with inflow: scan the face counts, check capacity, append
+// the new particles in face order behind the run's live particles.
+template <typename real, int DIM>
+__global__ __launch_bounds__(256) void k_gen_emit(DevPtrs<real> d, int buf) {
+  __shared__ int64_t s_part[256];
+  __shared__ int32_t s_n0;
+  const int r = d.inflow_runs[blockIdx.x];
+  const RunDev &R = d.runs[r];
+  const int tid = threadIdx.x;
+  if (tid == 0) s_n0 = d.n_alive[r];
+  int64_t my = 0;
+  for (int j = tid; j < R.nface; j += 256) my += d.gen_count[R.fo + j];
+  s_part[tid] = my;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) s_part[tid] += s_part[tid + o];
+    __syncthreads();
+  }
+  const int64_t total = s_part[0];
+  const int64_t n0 = s_n0;
+  const bool ok = n0 + total <= R.cap;
+  __syncthreads();
+  if (!ok) {
+    if (tid == 0) {
+      set_error(d.err, kErrCapacity);
+      d.n_gen[r] = 0;
+    }
+    return;
+  }
+  const uint32_t step = *d.step;
+  int64_t carry = 0;
+  for (int base = 0; base < R.nface; base += 256) {
+    const int j = base + tid;
+    const int32_t cnt = (j < R.nface) ? d.gen_count[R.fo + j] : 0;
+    s_part[tid] = cnt;
+    __syncthreads();
+    // inclusive Hillis-Steele scan of 256 counts
+    for (int o = 1; o < 256; o <<= 1) {
+      const int64_t add = (tid >= o) ? s_part[tid - o] : 0;
+      __syncthreads();
+      s_part[tid] += add;
+      __syncthreads();
+    }
+    const int64_t excl = s_part[tid] - cnt;
+    const int64_t chunk = s_part[255];
+    if (j < R.nface && cnt > 0)
+      emit_face<real, DIM>(R, step, j, cnt, R.so + n0 + carry + excl, d.P[buf], d.err);
+    carry += chunk;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    d.n_alive[r] = (int32_t)(n0 + total);
+    d.n_gen[r] = (int32_t)total;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Motion + Enumeration
+// ---------------------------------------------------------------------------
+
+// Moves one particle for dt (specular / diffuse / open faces); returns the new
+// cell, or nc (DEAD) when it leaves.  hit reports a velocity change.
+template <typename real, int DIM>
+__device__ __forceinline__ int32_t move_one(const RunDev &R, uint32_t step, uint32_t slot, real (&pos)[3],
+                                            real (&vel)[3], bool &hit, int32_t *err) {
+  real L[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) L[a] = (real)R.L[a];
+  real trem = (real)R.dt;
+  int hits = 0;
+  hit = false;
+  for (;;) {
+    real tmin = infinity<real>();
+    int ax = -1, side = 0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      real th;
+      int sd;
+      if (vel[a] > (real)0) {
+        th = (L[a] - pos[a]) / vel[a];
+        sd = 1;
+      } else if (vel[a] < (real)0) {
+        th = ((real)0 - pos[a]) / vel[a];
+        sd = 0;
+      } else {
+        continue;
+      }
+      if (th < (real)0) th = (real)0;
+      if (th < tmin) {
+        tmin = th;
+        ax = a;
+        side = sd;
+      }
+    }
+    if (ax < 0 || tmin >= trem) {
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) pos[a] = pos[a] + vel[a] * trem;
+      break;
+    }
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) pos[a] = (a == ax) ? (side ? L[a] : (real)0) : pos[a] + vel[a] * tmin;
+    trem = trem - tmin;
+    const int f = 2 * ax + side;
+    const int bc = R.bc[f];
+    hit = true;
+    if (bc == kSpecular) {
+#pragma unroll
+      for (int a = 0; a < DIM; ++a)
+        if (a == ax) vel[a] = -vel[a];
+    } else if (bc == kDiffuse) {
+      const real Tw = (real)R.face_T[f];
+      UStream<real> ws(R.key0, R.key1, step, kWall, slot);
+      ws.seek(4u * (uint32_t)hits);
+      const real w0 = ws(), w1 = ws(), w2 = ws();
+      const real vn = sqrt((real)-2 * Tw * log(w0));
+      real n0, n1;
+      box_muller(w1, w2, n0, n1);
+      const real stw = (real)R.face_sqrtT[f];
+      const int t1 = (ax == 0) ? 1 : 0, t2 = (ax == 2) ? 1 : 2;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (a == ax) vel[a] = side ? -vn : vn;
+        else if (a == t1) vel[a] = stw * n0;
+        else if (a == t2) vel[a] = stw * n1;
+      }
+    } else {
+      return R.nc;  // inflow plane crossed outward, or outflow
+    }
+    if (++hits == kMaxWallHits) {
+      set_error(err, kErrBounce);
+      break;
+    }
+  }
+  if (pos[0] < (real)0) return R.nc;  // generated upstream and never entered
+  const int32_t ix = axis_index(pos[0], (real)R.inv_d[0], R.nx);
+  const int32_t iy = axis_index(pos[1], (real)R.inv_d[1], R.ny);
+  const int32_t iz = (DIM == 3) ? axis_index(pos[2], (real)R.inv_d[2], R.nz) : 0;
+  return (iz * R.ny + iy) * R.nx + ix;
+}
+
+// One wavefront per tile of tile_chunks*64 consecutive slots of one run:
+// coalesced SoA loads/stores, the new cell of every slot, and the tile's
+// histogram of the first indexing digit in wave-private LDS.
+template <typename real, int DIM, bool SINGLE>
+__global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_t n_tiles, int64_t tile,
+                                                int dstride) {
+  extern __shared__ uint32_t lds[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int t = blockIdx.x * kWavesPerBlock + wave;
+  if (t >= n_tiles) return;
+  const int r = d.tile_run[t];
+  const RunDev &R = d.runs[r];
+  const int64_t tl = t - R.to;
+  const int D = SINGLE ? R.nc + 1 : kDigits;
+  uint32_t *h = lds + wave * dstride;
+  for (int q = lane; q < D; q += kWave) h[q] = 0;
+  wave_sync();
+  const int64_t n = d.n_alive[r];
+  const int64_t begin = tl * tile, end = min(begin + tile, n);
+  const uint32_t step = *d.step;
+  Particles<real> P = d.P[buf];
+  for (int64_t b = begin; b < end; b += kWave) {
+    const int64_t loc = b + lane;
+    if (loc < end) {
+      const int64_t gi = R.so + loc;
+      real pos[3] = {P.x[gi], P.y[gi], DIM == 3 ? P.z[gi] : (real)0};
+      real vel[3] = {P.u[gi], P.v[gi], P.w[gi]};
+      bool hit;
+      const int32_t c = move_one<real, DIM>(R, step, (uint32_t)loc, pos, vel, hit, d.err);
+      P.x[gi] = pos[0];
+      P.y[gi] = pos[1];
+      if (DIM == 3) P.z[gi] = pos[2];
+      if (hit) {
+        P.u[gi] = vel[0];
+        P.v[gi] = vel[1];
+        P.w[gi] = vel[2];
+      }
+      d.cell[gi] = c;
+      atomicAdd(&h[SINGLE ? (uint32_t)c : ((uint32_t)c & (kDigits - 1))], 1u);
+    }
+  }
+  wave_sync();
+  uint32_t *Mt = d.hist + R.mo + tl * D;
+  for (int q = lane; q < D; q += kWave) Mt[q] = h[q];
+}
+
+// ---------------------------------------------------------------------------
+// Indexing: stable counting sort (LSD over 11-bit digits when a run has more
+// than 2048 bins)
+// ---------------------------------------------------------------------------
+
+struct IndexArgs {
+  const RunDev *runs;
+  const int32_t *tile_run;
+  const int32_t *cell;     // bin of each slot (slot order)
+  const int32_t *in;       // previous pass order (run-local slots) or null: identity
+  int32_t *out;            // this pass' order
+  uint32_t *hist;          // tile histograms, tile-major: [tile][digit]
+  uint32_t *tot;           // per run digit totals -> digit starts
+  uint32_t *bin_start;     // per run nc + 2 bin starts (single pass / bounds)
+  int32_t *n_sorted;
+  int32_t *n_alive;
+  int32_t n_tiles;
+  int64_t tile;
+  int dstride;
+  int pass;
+  int single;
+};
+
+__device__ __forceinline__ uint32_t digit_of(int32_t bin, int pass, bool single) {
+  return single ? (uint32_t)bin : (((uint32_t)bin >> (kDigitBits * pass)) & (kDigits - 1));
+}
+
+// Tile histogram of one digit over an existing order (passes after the first,
+// and the stand-alone sort).
+__global__ __launch_bounds__(256) void k_digcount(IndexArgs a, int use_n_alive) {
+  extern __shared__ uint32_t lds[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int t = blockIdx.x * kWavesPerBlock + wave;
+  if (t >= a.n_tiles) return;
+  const int r = a.tile_run[t];
+  const RunDev &R = a.runs[r];
+  const int64_t tl = t - R.to;
+  const bool single = a.single;
+  const int D = single ? R.nc + 1 : kDigits;
+  uint32_t *h = lds + wave * a.dstride;
+  for (int q = lane; q < D; q += kWave) h[q] = 0;
+  wave_sync();
+  const int64_t n = use_n_alive ? a.n_alive[r] : a.n_sorted[r];
+  const int64_t begin = tl * a.tile, end = min(begin + a.tile, n);
+  for (int64_t b = begin; b < end; b += kWave) {
+    const int64_t loc = b + lane;
+    if (loc < end) {
+      const int32_t v = a.in ? a.in[R.so + loc] : (int32_t)loc;
+      atomicAdd(&h[digit_of(a.cell[R.so + v], a.pass, single)], 1u);
+    }
+  }
+  wave_sync();
+  uint32_t *Mt = a.hist + R.mo + tl * D;
+  for (int q = lane; q < D; q += kWave) Mt[q] = h[q];
+}
+
+// Per (run, digit): exclusive scan of the digit's counts over the run's tiles
+// (in place) and the digit total.  Coalesced across digits.
+__global__ __launch_bounds__(256) void k_colscan(IndexArgs a) {
+  const RunDev &R = a.runs[blockIdx.y];
+  const int D = a.single ? R.nc + 1 : kDigits;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= D) return;
+  uint32_t *col = a.hist + R.mo + q;
+  uint32_t sum = 0;
+  int t = 0;
+  for (; t + 8 <= R.nt; t += 8) {
+    uint32_t v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = col[(int64_t)(t + k) * D];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      col[(int64_t)(t + k) * D] = sum;
+      sum += v[k];
+    }
+  }
+  for (; t < R.nt; ++t) {
+    const uint32_t v = col[(int64_t)t * D];
+    col[(int64_t)t * D] = sum;
+    sum += v;
+  }
+  a.tot[R.cbo + q] = sum;
+}
+
+// One block per run: exclusive scan of the digit totals -> digit starts.  With
+// a single pass the digits are the bins: also the run's bin starts and its
+// live count (everything before the DEAD bin).
+__global__ __launch_bounds__(256) void k_digscan(IndexArgs a) {
+  __shared__ uint32_t s[256];
+  const int r = blockIdx.x;
+  const RunDev &R = a.runs[r];
+  const bool single = a.single;
+  const int D = single ? R.nc + 1 : kDigits;
+  uint32_t *tot = a.tot + R.cbo;
+  const int per = (D + 255) / 256;  // <= 8
+  const int tid = threadIdx.x;
+  const int q0 = tid * per;
+  uint32_t v[8];
+  uint32_t local = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    v[k] = (k < per && q0 + k < D) ? tot[q0 + k] : 0u;
+    local += v[k];
+  }
+  s[tid] = local;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const uint32_t add = (tid >= o) ? s[tid - o] : 0u;
+    __syncthreads();
+    s[tid] += add;
+    __syncthreads();
+  }
+  uint32_t run = s[tid] - local;
+  const uint32_t total = s[255];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (k < per && q0 + k < D) {
+      tot[q0 + k] = run;
+      if (single) {
+        a.bin_start[R.bo + q0 + k] = run;
+        if (q0 + k == R.nc) a.n_alive[r] = (int32_t)run;  // everything before the DEAD bin
+      }
+      run += v[k];
+    }
+  }
+  if (tid == 0) {
+    a.n_sorted[r] = (int32_t)total;
+    if (single) a.bin_start[R.bo + R.nc + 1] = total;
+  }
+}
+
+// Lanes holding the same digit: intersect one ballot per digit bit.
+__device__ __forceinline__ uint64_t match_digit(uint32_t q, bool active, int nbits) {
+  uint64_t m = __ballot(active);
+  for (int b = 0; b < nbits; ++b) {
+    const bool bit = (q >> b) & 1u;
+    const uint64_t t = __ballot(bit);
+    m &= bit ? t : ~t;
+  }
+  return m;
+}
+
+// One wavefront per tile, 64 consecutive positions per round in order: the
+// rank of a position among equal digits is (digit start) + (count in earlier
+// tiles) + (count in earlier rounds of this tile, LDS) + (earlier lanes with
+// the same digit, ballots).  That is exactly the sequential stable order.
+__global__ __launch_bounds__(256) void k_scatter(IndexArgs a, int nbits) {
+  extern __shared__ uint32_t lds[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int t = blockIdx.x * kWavesPerBlock + wave;
+  if (t >= a.n_tiles) return;
+  const int r = a.tile_run[t];
+  const RunDev &R = a.runs[r];
+  const int64_t tl = t - R.to;
+  const bool single = a.single;
+  const int D = single ? R.nc + 1 : kDigits;
+  uint32_t *run_cnt = lds + wave * a.dstride;
+  for (int q = lane; q < D; q += kWave) run_cnt[q] = 0;
+  wave_sync();
+  const int64_t n = a.n_sorted[r];
+  const int64_t begin = tl * a.tile, end = min(begin + a.tile, n);
+  const uint32_t *Mt = a.hist + R.mo + tl * D;
+  const uint32_t *S = a.tot + R.cbo;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  for (int64_t b = begin; b < end; b += kWave) {
+    const int64_t loc = b + lane;
+    const bool active = loc < end;
+    int32_t v = 0;
+    uint32_t q = 0;
+    if (active) {
+      v = a.in ? a.in[R.so + loc] : (int32_t)loc;
+      q = digit_of(a.cell[R.so + v], a.pass, single);
+    }
+    const uint64_t peers = match_digit(q, active, nbits);
+    if (active) {
+      const uint32_t rank = __popcll(peers & lt);
+      const uint32_t cnt = __popcll(peers);
+      const uint32_t prior = run_cnt[q];
+      const uint32_t dst = S[q] + Mt[q] + prior + rank;
+      a.out[R.so + dst] = v;
+      if (rank == cnt - 1) run_cnt[q] = prior + cnt;
+    }
+    wave_sync();
+  }
+}
+
+// Bin starts from the final order (multi-pass): position p starts every bin in
+// (bin(p-1), bin(p)].
+__global__ __launch_bounds__(256) void k_bin_bounds(IndexArgs a, const int32_t *lcr, int64_t n_slots) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_slots;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const RunDev &R = a.runs[a.tile_run[i / a.tile]];
+    const int64_t loc = i - R.so;
+    const int64_t n = a.n_sorted[a.tile_run[i / a.tile]];
+    if (loc >= n) continue;
+    const int32_t b = a.cell[R.so + lcr[i]];
+    const int32_t bp = loc > 0 ? a.cell[R.so + lcr[i - 1]] : -1;
+    for (int32_t q = bp + 1; q <= b; ++q) a.bin_start[R.bo + q] = (uint32_t)loc;
+    if (loc == n - 1)
+      for (int32_t q = b + 1; q <= R.nc + 1; ++q) a.bin_start[R.bo + q] = (uint32_t)n;
+  }
+}
+
+__global__ void k_bin_finalize(IndexArgs a, int n_runs, int set_alive) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_runs) return;
+  const RunDev &R = a.runs[r];
+  if (a.n_sorted[r] == 0)
+    for (int32_t q = 0; q <= R.nc + 1; ++q) a.bin_start[R.bo + q] = 0;
+  if (set_alive) a.n_alive[r] = (int32_t)a.bin_start[R.bo + R.nc];
+}
+
+// ---------------------------------------------------------------------------
+// Permutation: P' = P[LCR] (cell-sorted, DEAD bin dropped)
+// ---------------------------------------------------------------------------
+
+template <typename real, int DIM>
+__global__ __launch_bounds__(256) void k_permute(DevPtrs<real> d, int src, int64_t n_slots, int64_t tile) {
+  const Particles<real> A = d.P[src];
+  const Particles<real> B = d.P[1 - src];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_slots;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int r = d.tile_run[i / tile];
+    const RunDev &R = d.runs[r];
+    if (i - R.so >= d.n_alive[r]) continue;
+    const int64_t s = R.so + d.lcr[i];
+    B.x[i] = A.x[s];
+    B.y[i] = A.y[s];
+    if (DIM == 3) B.z[i] = A.z[s];
+    B.u[i] = A.u[s];
+    B.v[i] = A.v[s];
+    B.w[i] = A.w[s];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Interaction (NTC) + Sampling, one lane per cell
+// ---------------------------------------------------------------------------
+
+template <typename real>
+__device__ __forceinline__ void sample_cell(const real *u, const real *v, const real *w, int64_t N, double *out) {
+  double s[kFields] = {0, 0, 0, 0, 0, 0, 0};
+  for (int64_t k = 0; k < N; ++k) {
+    const double a = (double)u[k], b = (double)v[k], c = (double)w[k];
+    s[0] += 1.0;
+    s[1] += a;
+    s[2] += b;
+    s[3] += c;
+    s[4] += a * a;
+    s[5] += b * b;
+    s[6] += c * c;
+  }
+#pragma unroll
+  for (int f = 0; f < kFields; ++f) out[f] = s[f];
+}
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_collide(DevPtrs<real> d, int buf, int64_t n_cells) {
+  const int64_t gc = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (gc >= n_cells) return;
+  const RunDev &R = d.runs[d.cgroup_run[gc >> 6]];
+  const int32_t c = (int32_t)(gc - R.co);
+  if (c >= R.nc) return;
+  const int64_t b = d.bin_start[R.bo + c];
+  const int64_t N = (int64_t)d.bin_start[R.bo + c + 1] - b;
+  const Particles<real> P = d.P[buf];
+  real *u = P.u + R.so + b, *v = P.v + R.so + b, *w = P.w + R.so + b;
+  const uint32_t step = *d.step;
+  real gm = d.gmax[gc];
+  real rem = d.rem_c[gc];
+  const real npairs = (real)0.5 * (real)(N * (N - 1));
+  const real M = npairs * (real)R.coef * gm + rem;
+  int64_t nsel = 0;
+  if (M >= (real)0 && M < (real)kMaxSelections) {
+    const real fl = floor(M);
+    nsel = (int64_t)fl;
+    rem = M - fl;
+  } else {  // non-finite velocities or an absurd rate: stop, report
+    set_error(d.err, kErrNumeric);
+    rem = (real)0;
+  }
+  if (N < 2) nsel = 0;
+  uint32_t ncol = 0;
+  for (int64_t k = 0; k < nsel; ++k) {
+    const uint4 b0 = philox(make_uint4(step, kColl, (uint32_t)c, (uint32_t)(2 * k)), R.key0, R.key1);
+    const uint4 b1 = philox(make_uint4(step, kColl, (uint32_t)c, (uint32_t)(2 * k + 1)), R.key0, R.key1);
+    const uint32_t i = __umulhi(b0.x, (uint32_t)N);
+    const uint32_t jp = __umulhi(b0.y, (uint32_t)(N - 1));
+    const uint32_t j = jp + (jp >= i ? 1u : 0u);
+    const real du = u[i] - u[j], dv = v[i] - v[j], dw = w[i] - w[j];
+    const real cr = sqrt(du * du + dv * dv + dw * dw);
+    const real g = g_of<real>(R, cr);
+    if (g > gm) gm = g;
+    if (!(u01<real>(b0.z, b0.w) < g / gm)) continue;
+    const real cosx = (real)2 * u01<real>(b1.x, b1.y) - (real)1;
+    const real sinx = sqrt((real)1 - cosx * cosx);
+    const real eps = two_pi<real>() * u01<real>(b1.z, b1.w);
+    const real rx = cr * cosx, ry = cr * sinx * cos(eps), rz = cr * sinx * sin(eps);
+    const real mx = (real)0.5 * (u[i] + u[j]), my = (real)0.5 * (v[i] + v[j]), mz = (real)0.5 * (w[i] + w[j]);
+    u[i] = mx + (real)0.5 * rx;
+    v[i] = my + (real)0.5 * ry;
+    w[i] = mz + (real)0.5 * rz;
+    u[j] = mx - (real)0.5 * rx;
+    v[j] = my - (real)0.5 * ry;
+    w[j] = mz - (real)0.5 * rz;
+    ncol++;
+  }
+  d.gmax[gc] = gm;
+  d.rem_c[gc] = rem;
+  d.ncoll[gc] += ncol;
+  if (*d.sample_slot >= 0) sample_cell(u, v, w, N, d.stage + gc * kFields);
+}
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_sample_cells(DevPtrs<real> d, int buf, int64_t n_cells) {
+  const int64_t gc = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (gc >= n_cells) return;
+  const RunDev &R = d.runs[d.cgroup_run[gc >> 6]];
+  const int32_t c = (int32_t)(gc - R.co);
+  if (c >= R.nc) return;
+  const int64_t b = d.bin_start[R.bo + c];
+  const int64_t N = (int64_t)d.bin_start[R.bo + c + 1] - b;
+  const Particles<real> P = d.P[buf];
+  sample_cell(P.u + R.so + b, P.v + R.so + b, P.w + R.so + b, N, d.stage + gc * kFields);
+}
+
+// acc[slot][eg][c][f] += sum over the runs of (ensemble, group) eg, in run order.
+template <typename real>
+__global__ __launch_bounds__(256) void k_accumulate(DevPtrs<real> d, int slot_arg, int64_t stride, int n_eg) {
+  const int slot = slot_arg >= 0 ? slot_arg : *d.sample_slot;
+  if (slot < 0) return;
+  double *acc = d.acc + (int64_t)slot * stride;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < stride;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = n_eg;  // eg_acc[lo] <= i < eg_acc[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (d.eg_acc[mid] <= i) lo = mid;
+      else hi = mid;
+    }
+    const int64_t local = i - d.eg_acc[lo];
+    const int64_t c = local / kFields;
+    const int f = (int)(local - c * kFields);
+    double a = acc[i];
+    for (int k = d.eg_start[lo]; k < d.eg_start[lo + 1]; ++k) {
+      const RunDev &R = d.runs[d.eg_runs[k]];
+      a += d.stage[(R.co + c) * kFields + f];
+    }
+    acc[i] = a;
+  }
+}
+
+// FP64 division of sums into n (per run), mean velocity and temperatures.
+__device__ __forceinline__ void moments_of(const double *S, double n_runs, double *m) {
+  const double N = S[0];
+  const double inv = N > 0.0 ? 1.0 / N : __builtin_nan("");
+  const double ux = S[1] * inv, uy = S[2] * inv, uz = S[3] * inv;
+  const double Tx = S[4] * inv - ux * ux;
+  const double Ty = S[5] * inv - uy * uy;
+  const double Tz = S[6] * inv - uz * uz;
+  m[0] = N / n_runs;
+  m[1] = ux;
+  m[2] = uy;
+  m[3] = uz;
+  m[4] = (Tx + Ty + Tz) / 3.0;
+  m[5] = Tx;
+  m[6] = Ty;
+  m[7] = Tz;
+}
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_moments(DevPtrs<real> d, int slot, int64_t stride, int eg0, int G,
+                                                 int nc, int n_runs_ens, int max_nc) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const double *acc = d.acc + (int64_t)slot * stride;
+  double S[kFields] = {0, 0, 0, 0, 0, 0, 0};
+  for (int g = 0; g < G; ++g) {
+    const double *e = acc + d.eg_acc[eg0 + g] + (int64_t)c * kFields;
+#pragma unroll
+    for (int f = 0; f < kFields; ++f) S[f] += e[f];
+  }
+  double m[kMoments];
+  moments_of(S, (double)n_runs_ens, m);
+  double *out = d.mom + (int64_t)c * kMoments;
+  double *se = d.mom + (int64_t)max_nc * kMoments + (int64_t)c * kMoments;
+#pragma unroll
+  for (int f = 0; f < kMoments; ++f) out[f] = m[f];
+  // batch means over the run groups
+  double mean[kMoments] = {0, 0, 0, 0, 0, 0, 0, 0}, m2[kMoments] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int g = 0; g < G; ++g) {
+    const double *e = acc + d.eg_acc[eg0 + g] + (int64_t)c * kFields;
+    double mg[kMoments];
+    moments_of(e, (double)(d.eg_start[eg0 + g + 1] - d.eg_start[eg0 + g]), mg);
+#pragma unroll
+    for (int f = 0; f < kMoments; ++f) {
+      const double delta = mg[f] - mean[f];
+      mean[f] += delta / (double)(g + 1);
+      m2[f] += delta * (mg[f] - mean[f]);
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < kMoments; ++f)
+    se[f] = G > 1 ? sqrt(m2[f] / (double)(G - 1) / (double)G) : __builtin_nan("");
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+static inline int grid_for(int64_t n, int cap_blocks = 65536) {
+  int64_t b = (n + 255) / 256;
+  if (b < 1) b = 1;
+  if (b > cap_blocks) b = cap_blocks;
+  return (int)b;
+}
+
+template <typename real>
+static IndexArgs index_args(const Geometry &g, const DevPtrs<real> &d) {
+  IndexArgs a;
+  a.runs = d.runs;
+  a.tile_run = d.tile_run;
+  a.cell = d.cell;
+  a.in = nullptr;
+  a.out = d.lcr;
+  a.hist = d.hist;
+  a.tot = d.digit_tot;
+  a.bin_start = d.bin_start;
+  a.n_sorted = d.n_sorted;
+  a.n_alive = d.n_alive;
+  a.n_tiles = g.n_tiles;
+  a.tile = g.tile;
+  a.dstride = g.dstride;
+  a.pass = 0;
+  a.single = g.npass == 1;
+  return a;
+}
+
+static int digit_bits(int D) {
+  int b = 0;
+  while ((1 << b) < D) ++b;
+  return b;
+}
+
+// Scans and scatter of pass `pass`; the tile histograms are already in place.
+static void index_pass(IndexArgs a, int max_digits, int n_runs, int pass, const int32_t *in, int32_t *out,
+                       hipStream_t s) {
+  a.pass = pass;
+  a.in = in;
+  a.out = out;
+  const size_t lds = (size_t)kWavesPerBlock * a.dstride * sizeof(uint32_t);
+  const int wblocks = (a.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  hipLaunchKernelGGL(k_colscan, dim3((max_digits + 255) / 256, n_runs), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_digscan, dim3(n_runs), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_scatter, dim3(wblocks), dim3(256), lds, s, a,
+                     a.single ? digit_bits(max_digits) : kDigitBits);
+}
+
+template <typename real>
+void launch_init(const Geometry &g, const DevPtrs<real> &d, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_runs<real>, dim3((g.n_runs + 255) / 256), dim3(256), 0, s, d, g.n_runs);
+  hipLaunchKernelGGL(k_init_cells<real>, dim3(grid_for(g.n_cells)), dim3(256), 0, s, d, g.n_cells);
+  if (g.n_faces > 0)
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(g.n_faces)), dim3(256), 0, s, d.rem_f, g.n_faces, 0.0);
+  if (g.n_samples > 0)
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(g.acc_stride * g.n_samples)), dim3(256), 0, s, d.acc,
+                       g.acc_stride * g.n_samples, 0.0);
+  if (g.dim == 3)
+    hipLaunchKernelGGL((k_init_particles<real, 3>), dim3(grid_for(g.n_slots)), dim3(256), 0, s, d, g.n_slots,
+                       g.tile);
+  else
+    hipLaunchKernelGGL((k_init_particles<real, 2>), dim3(grid_for(g.n_slots)), dim3(256), 0, s, d, g.n_slots,
+                       g.tile);
+}
+
+template <typename real, int DIM>
+static void step_dim(const Geometry &g, const DevPtrs<real> &d, int buf, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(1), 0, s, d.step, d.sample_slot, d.sample_steps, g.n_samples);
+  if (g.n_inflow_runs > 0) {
+    hipLaunchKernelGGL(k_gen_count<real>, dim3(grid_for(g.n_faces)), dim3(256), 0, s, d, g.n_faces);
+    hipLaunchKernelGGL((k_gen_emit<real, DIM>), dim3(g.n_inflow_runs), dim3(256), 0, s, d, buf);
+  }
+  const size_t lds = (size_t)kWavesPerBlock * g.dstride * sizeof(uint32_t);
+  const int wblocks = (g.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  IndexArgs a = index_args(g, d);
+  if (g.npass == 1) {
+    hipLaunchKernelGGL((k_motion<real, DIM, true>), dim3(wblocks), dim3(256), lds, s, d, buf, g.n_tiles, g.tile,
+                       g.dstride);
+    index_pass(a, g.max_nc + 1, g.n_runs, 0, nullptr, d.lcr, s);
+  } else {
+    hipLaunchKernelGGL((k_motion<real, DIM, false>), dim3(wblocks), dim3(256), lds, s, d, buf, g.n_tiles, g.tile,
+                       g.dstride);
+    const int32_t *in = nullptr;
+    for (int p = 0; p < g.npass; ++p) {
+      int32_t *out = ((g.npass - 1 - p) % 2 == 0) ? d.lcr : d.lcr_tmp;
+      if (p > 0) {
+        a.pass = p;
+        a.in = in;
+        hipLaunchKernelGGL(k_digcount, dim3(wblocks), dim3(256), lds, s, a, 0);
+      }
+      index_pass(a, kDigits, g.n_runs, p, in, out, s);
+      in = out;
+    }
+    hipLaunchKernelGGL(k_bin_bounds, dim3(grid_for(g.n_slots)), dim3(256), 0, s, a, d.lcr, g.n_slots);
+    hipLaunchKernelGGL(k_bin_finalize, dim3((g.n_runs + 255) / 256), dim3(256), 0, s, a, g.n_runs, 1);
+  }
+  hipLaunchKernelGGL((k_permute<real, DIM>), dim3(grid_for(g.n_slots)), dim3(256), 0, s, d, buf, g.n_slots,
+                     g.tile);
+  hipLaunchKernelGGL(k_collide<real>, dim3((unsigned)((g.n_cells + 255) / 256)), dim3(256), 0, s, d, 1 - buf,
+                     g.n_cells);
+  if (g.n_samples > 0)
+    hipLaunchKernelGGL(k_accumulate<real>, dim3(grid_for(g.acc_stride)), dim3(256), 0, s, d, -1, g.acc_stride,
+                       g.n_eg);
+}
+
+template <typename real>
+void launch_step(const Geometry &g, const DevPtrs<real> &d, int buf, hipStream_t s) {
+  if (g.dim == 3) step_dim<real, 3>(g, d, buf, s);
+  else step_dim<real, 2>(g, d, buf, s);
+}
+
+template <typename real>
+void launch_sample(const Geometry &g, const DevPtrs<real> &d, int buf, int slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_sample_cells<real>, dim3((unsigned)((g.n_cells + 255) / 256)), dim3(256), 0, s, d, buf,
+                     g.n_cells);
+  hipLaunchKernelGGL(k_accumulate<real>, dim3(grid_for(g.acc_stride)), dim3(256), 0, s, d, slot, g.acc_stride,
+                     g.n_eg);
+}
+
+template <typename real>
+void launch_moments(const Geometry &g, const DevPtrs<real> &d, int slot, int eg0, int n_groups, int nc,
+                    int n_runs_ens, hipStream_t s) {
+  hipLaunchKernelGGL(k_moments<real>, dim3((nc + 255) / 256), dim3(256), 0, s, d, slot, g.acc_stride, eg0,
+                     n_groups, nc, n_runs_ens, g.max_nc);
+}
+
+template void launch_init<float>(const Geometry &, const DevPtrs<float> &, hipStream_t);
+template void launch_init<double>(const Geometry &, const DevPtrs<double> &, hipStream_t);
+template void launch_step<float>(const Geometry &, const DevPtrs<float> &, int, hipStream_t);
+template void launch_step<double>(const Geometry &, const DevPtrs<double> &, int, hipStream_t);
+template void launch_sample<float>(const Geometry &, const DevPtrs<float> &, int, int, hipStream_t);
+template void launch_sample<double>(const Geometry &, const DevPtrs<double> &, int, int, hipStream_t);
+template void launch_moments<float>(const Geometry &, const DevPtrs<float> &, int, int, int, int, int, hipStream_t);
+template void launch_moments<double>(const Geometry &, const DevPtrs<double> &, int, int, int, int, int,
+                                     hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Stand-alone stable counting sort (same kernels as the step's Indexing)
+// ---------------------------------------------------------------------------
+
+namespace {
+struct SortLayout {
+  int64_t tile;
+  int32_t nt;
+  int npass;
+  int D;
+  size_t off_run, off_tile_run, off_hist, off_tot, off_ns, off_na, off_tmp, total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+SortLayout sort_layout(int64_t n, int32_t nbins, int tile_chunks) {
+  SortLayout L;
+  L.tile = (int64_t)tile_chunks * kWave;
+  L.nt = (int32_t)std::max<int64_t>(1, (n + L.tile - 1) / L.tile);
+  L.npass = 1;
+  if (nbins > kDigits) {
+    int bits = digit_bits(nbins);
+    L.npass = (bits + kDigitBits - 1) / kDigitBits;
+  }
+  L.D = L.npass == 1 ? nbins : kDigits;
+  size_t o = 0;
+  L.off_run = o;
+  o = align256(o + sizeof(RunDev));
+  L.off_tile_run = o;
+  o = align256(o + (size_t)L.nt * 4);
+  L.off_hist = o;
+  o = align256(o + (size_t)L.nt * L.D * 4);
+  L.off_tot = o;
+  o = align256(o + (size_t)L.D * 4);
+  L.off_ns = o;
+  o = align256(o + 4);
+  L.off_na = o;
+  o = align256(o + 4);
+  L.off_tmp = o;
+  o = align256(o + (L.npass > 1 ? (size_t)n * 4 : 0));
+  L.total = o;
+  return L;
+}
+
+__global__ void k_sort_setup(RunDev rd, RunDev *dst, int32_t *tile_run, int32_t nt, int32_t *ns, int32_t n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    *dst = rd;
+    *ns = n;
+  }
+  for (int t = i; t < nt; t += gridDim.x * blockDim.x) tile_run[t] = 0;
+}
+}  // namespace
+
+size_t counting_sort_workspace(int64_t n, int32_t nbins, int tile_chunks) {
+  return sort_layout(n, nbins, tile_chunks).total;
+}
+
+void launch_counting_sort(const int32_t *keys, int64_t n, int32_t nbins, int32_t *lcr, uint32_t *start,
+                          void *work, int tile_chunks, hipStream_t s) {
+  SortLayout L = sort_layout(n, nbins, tile_chunks);
+  char *w = (char *)work;
+  RunDev rd = {};
+  rd.so = 0;
+  rd.cap = (int64_t)L.nt * L.tile;
+  rd.nc = nbins - 1;
+  rd.nt = L.nt;
+  RunDev *runs = (RunDev *)(w + L.off_run);
+  int32_t *tile_run = (int32_t *)(w + L.off_tile_run);
+  int32_t *ns = (int32_t *)(w + L.off_ns);
+  hipLaunchKernelGGL(k_sort_setup, dim3(grid_for(L.nt, 1024)), dim3(256), 0, s, rd, runs, tile_run, L.nt, ns,
+                     (int32_t)n);
+  IndexArgs a;
+  a.runs = runs;
+  a.tile_run = tile_run;
+  a.cell = keys;
+  a.in = nullptr;
+  a.out = lcr;
+  a.hist = (uint32_t *)(w + L.off_hist);
+  a.tot = (uint32_t *)(w + L.off_tot);
+  a.bin_start = start;
+  a.n_sorted = ns;
+  a.n_alive = (int32_t *)(w + L.off_na);
+  a.n_tiles = L.nt;
+  a.tile = L.tile;
+  a.dstride = L.D;
+  a.single = L.npass == 1;
+  const size_t lds = (size_t)kWavesPerBlock * a.dstride * sizeof(uint32_t);
+  const int wblocks = (L.nt + kWavesPerBlock - 1) / kWavesPerBlock;
+  int32_t *tmp = (int32_t *)(w + L.off_tmp);
+  const int32_t *in = nullptr;
+  for (int p = 0; p < L.npass; ++p) {
+    int32_t *out = ((L.npass - 1 - p) % 2 == 0) ? lcr : tmp;
+    a.pass = p;
+    a.in = in;
+    hipLaunchKernelGGL(k_digcount, dim3(wblocks), dim3(256), lds, s, a, 0);
+    index_pass(a, L.D, 1, p, in, out, s);
+    in = out;
+  }
+  if (L.npass > 1) {
+    hipLaunchKernelGGL(k_bin_bounds, dim3(grid_for(n)), dim3(256), 0, s, a, lcr, (int64_t)L.nt * L.tile);
+    hipLaunchKernelGGL(k_bin_finalize, dim3(1), dim3(256), 0, s, a, 1, 0);
+  }
+}
+
+}  // namespace dsmc

@@ -17,3 +17,16 @@ def oracle_lib():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+@pytest.fixture(scope="session")
+def dsmc_gpu():
+    """The HIP library on a visible GPU; fails loudly (no fallback) otherwise."""
+    import torch
+    import paper_cs_9902024_amd as P
+    if not torch.cuda.is_available():
+        raise RuntimeError("GPU test run without a visible GPU")
+    if not os.path.exists(P.LIB_PATH):
+        raise RuntimeError(f"{P.LIB_PATH} is not built")
+    P.lib()
+    return P

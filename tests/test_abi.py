@@ -1,0 +1,114 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+include/dsmc.h declares, and validates / sizes run specs on the host."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def dsmc():
+    import paper_cs_9902024_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        from paper_cs_9902024_amd import build
+        build.build()
+    return P
+
+
+def _header_symbols():
+    src = open(os.path.join(ROOT, "include", "dsmc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dsmc_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(dsmc):
+    syms = _header_symbols()
+    assert len(syms) >= 17
+    L = C.CDLL(dsmc.LIB_PATH)
+    for s in syms:
+        assert hasattr(L, s), s
+    assert sorted(dsmc.EXPORTS) == syms
+
+
+def test_struct_sizes_match_header(dsmc):
+    # layout of the two public structs (x86-64 SysV ABI)
+    assert C.sizeof(dsmc.dsmc_run_spec) == 232
+    assert C.sizeof(dsmc.dsmc_options) == 40
+
+
+def _bytes(dsmc, wl, fp64=False, groups=None):
+    specs = dsmc._specs(wl.runs)
+    opt = dsmc.make_options(fp64, groups or wl.n_groups, wl.sample_steps)
+    return dsmc.dsmc_required_bytes(specs, opt)
+
+
+def test_required_bytes_scale_with_the_workload(dsmc):
+    small = _bytes(dsmc, W.plain_box(), fp64=True)
+    assert 1e6 < small < 1e8
+    big = _bytes(dsmc, W.ensemble_box())
+    # 512 runs x ~1M slots x (2 x 5 fp32 + cell + lcr) ~ 25 GB
+    assert 20e9 < big < 32e9
+    big64 = _bytes(dsmc, W.ensemble_box(), fp64=True)
+    assert big64 > 1.6 * big
+
+
+@pytest.mark.parametrize("field,value", [("dim", 4), ("nx", 0), ("dt", 0.0), ("dt", -1.0),
+                                         ("omega", 0.3), ("capacity", 10), ("n_init", -1),
+                                         ("fnum_sigma", -1.0)])
+def test_invalid_specs_are_rejected_on_the_host(dsmc, field, value):
+    from dataclasses import replace
+    rs = replace(W.plain_box().runs[0], **{field: value})
+    with pytest.raises(dsmc.DsmcError) as e:
+        _bytes(dsmc, W.plain_box().with_runs([rs]))
+    assert e.value.status == -1
+
+
+def test_inflow_only_on_minus_x(dsmc):
+    from dataclasses import replace
+    rs = W.channel_run(nx=16, ny=8, lx=1.0)
+    bad = replace(rs, face_bc=("specular", "inflow") + rs.face_bc[2:])
+    with pytest.raises(dsmc.DsmcError):
+        _bytes(dsmc, W.plain_box().with_runs([bad]))
+
+
+def test_ensemble_runs_must_share_a_grid(dsmc):
+    from dataclasses import replace
+    a = W.plain_box().runs[0]
+    b = replace(a, nx=16, run_id=1)
+    with pytest.raises(dsmc.DsmcError):
+        _bytes(dsmc, W.plain_box().with_runs([a, b]))
+    _bytes(dsmc, W.plain_box().with_runs([a, replace(b, ensemble=1)]))
+
+
+def test_init_rejects_before_touching_the_device(dsmc):
+    specs = dsmc._specs(W.plain_box().runs)
+    opt = dsmc.make_options(True, 1, [])
+    ctx = C.c_void_p(0)
+    # arena missing -> size error, nothing enqueued
+    st = dsmc.lib().dsmc_init_runs(specs, 1, C.byref(opt), None, 0, None, C.byref(ctx))
+    assert st == -2 and not ctx.value
+    st = dsmc.lib().dsmc_init_runs(specs, 0, C.byref(opt), None, 0, None, C.byref(ctx))
+    assert st == -1
+
+
+def test_counting_sort_workspace_query(dsmc):
+    assert dsmc.dsmc_counting_sort_bytes(0, 1) > 0
+    assert dsmc.dsmc_counting_sort_bytes(1 << 20, 1025) < dsmc.dsmc_counting_sort_bytes(1 << 20, 20000)
+    with pytest.raises(dsmc.DsmcError):
+        dsmc.dsmc_counting_sort_bytes(-1, 5)
+
+
+def test_no_oracle_in_the_product():
+    """The product path never imports, links or loads the oracle."""
+    pkg = os.path.join(ROOT, "paper_cs_9902024_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+                assert "dsmc_oracle" not in txt and "liboracle" not in txt, f
