@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Throughput of the unsteady-DSMC inner loop on one MI355X.
+
+A step is one pass of the whole inner loop (Generation, Motion,
+Enumeration/Indexing, Interaction, Sampling at the scheduled steps) over every
+run of the batch.  The default workload is the batched ensemble: 512
+independent runs of the 32x32-cell specular box at 1M hard-sphere particles
+each (512M particle slots, FP32 SoA state, FP64 sampling accumulators, a
+sample every 20 steps), stepped by HIP-graph replay with inputs resident in
+HBM.  ``value`` = particle-steps per second over the timed steps (particles
+moved per step, summed over runs and steps, divided by the wall time between
+two device synchronisations).
+
+Beside it the line carries:
+  roofline      the dominant kernel's algorithmic bytes per launch over its
+                mean HIP-event duration (events recorded on the library's own
+                stream), against MI355X's 8 TB/s HBM peak;
+  plain_fp64    the plain path: the same problem, one run at a time, FP64
+                state, one launch per kernel;
+  cpu_baseline  the FP64 oracle timed on the host cores on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/sec (batched FP32 vs plain FP64) at 3σ/1% oracle match; HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(kind: str, n_particles: int, n_cells: int, dim: int, es: int) -> float:
+    """Bytes a kernel must move per launch (no re-reads, no write-allocate).
+
+    motion   reads position and the in-plane velocity (2*dim*es), writes the
+             position (dim*es) and the cell index (4)
+    scatter  reads the cell index (4), writes the LCR entry (4)
+    permute  reads the LCR entry (4) and the particle (dim+3)*es, writes it
+    collide  reads and writes every velocity once (2*3*es), per cell the bin
+             starts (4), remainder and (sigma c_r)_max (2*2*es), counter (8)
+    """
+    if kind == "motion":
+        return n_particles * (2 * dim * es + dim * es + 4)
+    if kind == "scatter":
+        return n_particles * 8
+    if kind == "permute":
+        return n_particles * (4 + 2 * (dim + 3) * es)
+    if kind == "collide":
+        return n_particles * 6 * es + n_cells * (4 + 4 * es + 8)
+    return 0.0
+
+
+def run_gpu(args):
+    import torch
+    import paper_cs_9902024_amd as P
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    wl = W.ensemble_box(n_runs=args.runs, n_per_run=args.per_run, n_steps=1000, sample_every=20,
+                        seed=3, state_fp64=False)
+    E = P.Ensemble.from_workload(wl, use_graph=True)
+    n_runs = wl.n_runs
+    nc = wl.runs[0].n_cells
+
+    E.step(args.warmup)
+    E.sync()
+    torch.cuda.synchronize()
+    n0 = int(E.counts()[:, 0].sum())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E.step(args.steps)
+    E.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    n1 = int(E.counts()[:, 0].sum())
+    assert n0 == n1, "closed box must keep its particle count"
+    elapsed = t1 - t0
+    psteps = n0 * args.steps
+    value = psteps / elapsed
+
+    # per-kernel HIP-event durations over a second, profiled window
+    E.profiling(True)
+    E.step(args.prof_steps)
+    kt = E.kernel_times()
+    E.profiling(False)
+    info = E.info()
+    E.close()
+    del E
+    torch.cuda.empty_cache()
+
+    kernels = {k: {"ms_total": ms, "launches": n, "ms_avg": ms / n} for k, (ms, n) in kt.items()}
+    dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
+    rl = None
+    ab = algorithmic_bytes(dom, n0, n_runs * nc, 2, 4)
+    if ab > 0:
+        ach = ab / (kernels[dom]["ms_avg"] * 1e-3) / 1e9
+        rl = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+              "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+              "algorithmic_bytes_per_launch": ab, "avg_launch_ms": kernels[dom]["ms_avg"]}
+    for k, v in kernels.items():
+        b = algorithmic_bytes(k, n0, n_runs * nc, 2, 4)
+        if b > 0:
+            v["algorithmic_GBs"] = round(b / (v["ms_avg"] * 1e-3) / 1e9, 1)
+            v["frac_of_hbm_peak"] = round(v["algorithmic_GBs"] / HBM_PEAK_GBS, 4)
+
+    plain = None
+    if args.plain_runs > 0:
+        plain = run_plain_fp64(args, P, W)
+    return {"value": value, "elapsed": elapsed, "psteps": psteps, "n_runs": n_runs, "nc": nc,
+            "kernels": kernels, "roofline": rl, "plain": plain, "info": info}
+
+
+def run_plain_fp64(args, P, W):
+    """The plain path: one run at a time, FP64 state, a launch per kernel."""
+    import torch
+    total_ps, total_t = 0, 0.0
+    for r in range(args.plain_runs):
+        wl = W.ensemble_box(n_runs=1, n_per_run=args.per_run, n_steps=1000, sample_every=20, seed=3,
+                            state_fp64=True)
+        from dataclasses import replace
+        runs = [replace(wl.runs[0], run_id=r)]
+        E = P.Ensemble(runs, wl.sample_steps, state_fp64=True, n_groups=1, use_graph=False)
+        E.step(2)
+        E.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        E.step(args.plain_steps)
+        E.sync()
+        torch.cuda.synchronize()
+        total_t += time.perf_counter() - t0
+        total_ps += args.per_run * args.plain_steps
+        E.close()
+    return {"value": total_ps / total_t, "unit": "particle-steps/s", "runs_timed": args.plain_runs,
+            "steps_per_run": args.plain_steps, "dtype": "f64",
+            "note": "same box problem, one run per context, FP64 state, no graph"}
+
+
+def cpu_baseline(args):
+    """The FP64 oracle on the host cores, on a bounded sample of the same
+    problem: `threads` runs of per_run particles, S steps each (init
+    included), one thread per run."""
+    import oracle
+    import workloads as W
+    oracle.build(force=False)
+    cores = len(os.sched_getaffinity(0))
+    threads = max(1, min(16, cores))
+    # calibrate on one run: time of 1 and of 3 steps (init included in both)
+    wl1 = W.ensemble_box(n_runs=1, n_per_run=args.per_run, n_steps=3, sample_every=1000, seed=3)
+    t0 = time.perf_counter()
+    oracle.ensemble(wl1, n_threads=1, n_steps=1)
+    t1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.ensemble(wl1, n_threads=1, n_steps=3)
+    t3 = time.perf_counter() - t0
+    per_step = max((t3 - t1) / 2, 1e-3)
+    steps = int(max(2, min(300, (args.cpu_seconds - t1) / per_step)))
+    wl = W.ensemble_box(n_runs=threads, n_per_run=args.per_run, n_steps=steps, sample_every=1000,
+                        seed=3)
+    t0 = time.perf_counter()
+    _, st = oracle.ensemble(wl, n_threads=threads, n_steps=steps)
+    el = time.perf_counter() - t0
+    return {"value": st["particle_steps"] / el, "unit": "particle-steps/s", "cores": st["threads"],
+            "kind": "oracle",
+            "sample": f"{threads} runs x {args.per_run} particles x {steps} steps of the same box "
+                      f"problem (init included), one thread per run, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--runs", type=int, default=512)
+    ap.add_argument("--per-run", type=int, default=1_000_000)
+    ap.add_argument("--prof-steps", type=int, default=5)
+    ap.add_argument("--plain-runs", type=int, default=2)
+    ap.add_argument("--plain-steps", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(runs would shard across GPUs with one final reduction; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    g = run_gpu(args)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args)
+    ms_per_step = g["elapsed"] / args.steps * 1e3
+    line = {
+        "metric": METRIC,
+        "value": g["value"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"ensemble_box: {g['n_runs']} independent runs x {args.per_run} "
+                               f"hard-sphere particles, 2-D 1x1 specular box, 32x32 cells, "
+                               f"Kn 0.05, dt = 0.2 mean collision times, FP32 state, FP64 "
+                               f"sampling accumulators, sample every 20 steps, HIP graph",
+                   "runs": g["n_runs"], "particles_per_run": args.per_run,
+                   "cells_per_run": g["nc"], "parallelism": "one GPU; runs batched in each launch"},
+        "roofline": g["roofline"],
+        "cpu_baseline": cpu,
+        "plain_fp64": g["plain"],
+        "batched_over_plain": (g["value"] / g["plain"]["value"]) if g["plain"] else None,
+        "kernels": g["kernels"],
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -168,6 +168,23 @@ dsmc_status dsmc_get_cell_state(dsmc_ctx *ctx, int32_t run, double *rem, double 
 /* Per run: [r][0] particles now, [r][1] particles generated in the last step. */
 dsmc_status dsmc_get_counts(dsmc_ctx *ctx, int64_t *out, int32_t n_runs);
 
+/* ---- per-kernel timing ----------------------------------------------------- */
+
+#define DSMC_NKERNELS 15 /* kernel kinds; names from dsmc_kernel_name */
+
+/* Turn per-kernel timing on or off (synchronises).  While on, every launch is
+ * bracketed by two HIP events on the context's stream and steps are not
+ * replayed from graphs. */
+dsmc_status dsmc_set_profiling(dsmc_ctx *ctx, int32_t on);
+
+/* Accumulated event time (ms) and launch count per kernel kind since the last
+ * call, for the first n kinds (n <= DSMC_NKERNELS); resets the totals.
+ * Synchronises. */
+dsmc_status dsmc_kernel_times(dsmc_ctx *ctx, double *ms, int64_t *launches, int32_t n);
+
+/* Name of kernel kind k (static string), NULL if out of range. */
+const char *dsmc_kernel_name(int32_t kind);
+
 /* ---- Indexing alone ------------------------------------------------------ */
 
 /* Workspace bytes for dsmc_counting_sort. */

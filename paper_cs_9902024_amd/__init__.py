@@ -30,7 +30,9 @@ MOMENT_NAMES = ("n", "ux", "uy", "uz", "T", "Tx", "Ty", "Tz")
 EXPORTS = ("dsmc_required_bytes", "dsmc_init_runs", "dsmc_step", "dsmc_sample", "dsmc_read_moments",
            "dsmc_read_accum", "dsmc_sync", "dsmc_destroy", "dsmc_last_error", "dsmc_get_info",
            "dsmc_get_state", "dsmc_set_state", "dsmc_get_lcr", "dsmc_get_cell_state",
-           "dsmc_get_counts", "dsmc_counting_sort_bytes", "dsmc_counting_sort")
+           "dsmc_get_counts", "dsmc_counting_sort_bytes", "dsmc_counting_sort",
+           "dsmc_set_profiling", "dsmc_kernel_times", "dsmc_kernel_name")
+NKERNELS = 15
 
 
 class DsmcError(RuntimeError):
@@ -90,8 +92,12 @@ def lib():
         L.dsmc_get_counts.argtypes = [vp, C.POINTER(i64), i32]
         L.dsmc_counting_sort_bytes.argtypes = [i64, i32, C.POINTER(sz)]
         L.dsmc_counting_sort.argtypes = [vp, i64, i32, vp, vp, vp, sz, vp]
+        L.dsmc_set_profiling.argtypes = [vp, i32]
+        L.dsmc_kernel_times.argtypes = [vp, dp, C.POINTER(i64), i32]
+        L.dsmc_kernel_name.argtypes = [i32]
+        L.dsmc_kernel_name.restype = C.c_char_p
         for f in EXPORTS:
-            if f not in ("dsmc_destroy", "dsmc_last_error"):
+            if f not in ("dsmc_destroy", "dsmc_last_error", "dsmc_kernel_name"):
                 getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -247,6 +253,25 @@ def dsmc_get_counts(ctx, n_runs: int) -> np.ndarray:
     return out
 
 
+def dsmc_set_profiling(ctx, on: bool):
+    _check(lib().dsmc_set_profiling(ctx, int(bool(on))), "dsmc_set_profiling", ctx)
+
+
+def dsmc_kernel_name(kind: int) -> Optional[str]:
+    n = lib().dsmc_kernel_name(kind)
+    return n.decode() if n else None
+
+
+def dsmc_kernel_times(ctx) -> dict:
+    """{kernel name: (total ms, launches)} since the last call (resets)."""
+    ms = np.zeros(NKERNELS)
+    k = np.zeros(NKERNELS, np.int64)
+    _check(lib().dsmc_kernel_times(ctx, ms.ctypes.data_as(C.POINTER(C.c_double)),
+                                   k.ctypes.data_as(C.POINTER(C.c_int64)), NKERNELS),
+           "dsmc_kernel_times", ctx)
+    return {dsmc_kernel_name(i): (float(ms[i]), int(k[i])) for i in range(NKERNELS) if k[i]}
+
+
 def dsmc_counting_sort_bytes(n: int, nbins: int) -> int:
     b = C.c_size_t(0)
     _check(lib().dsmc_counting_sort_bytes(n, nbins, C.byref(b)), "dsmc_counting_sort_bytes")
@@ -346,6 +371,12 @@ class Ensemble:
 
     def counts(self) -> np.ndarray:
         return dsmc_get_counts(self.ctx, len(self.runs))
+
+    def profiling(self, on: bool):
+        dsmc_set_profiling(self.ctx, on)
+
+    def kernel_times(self) -> dict:
+        return dsmc_kernel_times(self.ctx)
 
 
 def counting_sort(keys, nbins: int):

@@ -364,6 +364,17 @@ struct dsmc_ctx {
   std::string msg;
   bool use_graph = false;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
+  // per-kernel event timing
+  bool profiling = false;
+  std::vector<hipEvent_t> pool;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> pending;
+  hipEvent_t open_ev = nullptr;
+  double ms[kNumKinds] = {};
+  int64_t launches[kNumKinds] = {};
 };
 
 namespace {
@@ -408,9 +419,49 @@ dsmc_status download(dsmc_ctx *c, void *dst, const void *src, size_t n) {
                    "hipMemcpyAsync(download)");
 }
 
+hipEvent_t take_event(dsmc_ctx *c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+// Prof hook: an event before and after every launch on the context's stream.
+void prof_mark(void *user, int kind, int begin) {
+  dsmc_ctx *c = (dsmc_ctx *)user;
+  hipEvent_t e = take_event(c);
+  (void)hipEventRecord(e, c->stream);
+  if (begin) {
+    c->open_ev = e;
+  } else {
+    c->pending.push_back({kind, c->open_ev, e});
+    c->open_ev = nullptr;
+  }
+}
+
+// Resolve recorded event pairs into per-kind totals (stream must be idle).
+void prof_collect(dsmc_ctx *c) {
+  for (auto &r : c->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      c->ms[r.kind] += ms;
+      c->launches[r.kind] += 1;
+    }
+    c->pool.push_back(r.a);
+    c->pool.push_back(r.b);
+  }
+  c->pending.clear();
+}
+
 void launch_one_step(dsmc_ctx *c, int buf) {
-  if (c->plan.g.fp64) launch_step<double>(c->plan.g, c->dd, buf, c->stream);
-  else launch_step<float>(c->plan.g, c->df, buf, c->stream);
+  Prof pr{c, prof_mark};
+  const Prof *prof = c->profiling ? &pr : nullptr;
+  if (c->plan.g.fp64) launch_step<double>(c->plan.g, c->dd, buf, c->stream, prof);
+  else launch_step<float>(c->plan.g, c->df, buf, c->stream, prof);
 }
 
 int find_ensemble(const dsmc_ctx *c, int32_t id) {
@@ -483,7 +534,7 @@ dsmc_status dsmc_step(dsmc_ctx *c, int32_t n_steps) {
   if (c->latched) return c->latched;
   if (n_steps < 0) return set_err(c, DSMC_EINVAL, "n_steps must be >= 0");
   for (int32_t i = 0; i < n_steps; ++i) {
-    if (c->use_graph) {
+    if (c->use_graph && !c->profiling) {
       hipGraphExec_t &ge = c->graph[c->buf];
       if (!ge) {
         hipGraph_t gr = nullptr;
@@ -515,8 +566,10 @@ dsmc_status dsmc_sample(dsmc_ctx *c, int32_t k) {
   if (c->latched) return c->latched;
   if (k < 0 || k >= c->plan.g.n_samples) return set_err(c, DSMC_EINVAL, "sample index out of range");
   if (!c->sorted) return set_err(c, DSMC_ESTATE, "dsmc_sample needs a completed step after init/set_state");
-  if (c->plan.g.fp64) launch_sample<double>(c->plan.g, c->dd, c->buf, k, c->stream);
-  else launch_sample<float>(c->plan.g, c->df, c->buf, k, c->stream);
+  Prof pr{c, prof_mark};
+  const Prof *prof = c->profiling ? &pr : nullptr;
+  if (c->plan.g.fp64) launch_sample<double>(c->plan.g, c->dd, c->buf, k, c->stream, prof);
+  else launch_sample<float>(c->plan.g, c->df, c->buf, k, c->stream, prof);
   return check_hip(c, hipGetLastError(), "launch(sample)");
 }
 
@@ -566,6 +619,11 @@ void dsmc_destroy(dsmc_ctx *c) {
   if (c->stream || c->arena) (void)hipStreamSynchronize(c->stream);
   for (auto &g : c->graph)
     if (g) (void)hipGraphExecDestroy(g);
+  for (auto &r : c->pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : c->pool) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -723,6 +781,39 @@ dsmc_status dsmc_get_counts(dsmc_ctx *c, int64_t *out, int32_t n_runs) {
     out[2 * r + 1] = b[r];
   }
   return DSMC_OK;
+}
+
+dsmc_status dsmc_set_profiling(dsmc_ctx *c, int32_t on) {
+  if (!c) return DSMC_EINVAL;
+  dsmc_status st = sync_ctx(c);
+  if (st) return st;
+  prof_collect(c);
+  c->profiling = on != 0;
+  return DSMC_OK;
+}
+
+dsmc_status dsmc_kernel_times(dsmc_ctx *c, double *ms, int64_t *launches, int32_t n) {
+  if (!c || n < 0 || (n > 0 && (!ms || !launches))) return DSMC_EINVAL;
+  dsmc_status st = sync_ctx(c);
+  if (st) return st;
+  prof_collect(c);
+  for (int k = 0; k < n && k < kNumKinds; ++k) {
+    ms[k] = c->ms[k];
+    launches[k] = c->launches[k];
+  }
+  for (int k = 0; k < kNumKinds; ++k) {
+    c->ms[k] = 0;
+    c->launches[k] = 0;
+  }
+  return DSMC_OK;
+}
+
+const char *dsmc_kernel_name(int32_t kind) {
+  static const char *names[kNumKinds] = {"step_begin", "gen_count", "gen_emit", "motion", "digcount",
+                                         "colscan", "digscan", "scatter", "bin_bounds", "bin_finalize",
+                                         "permute", "collide", "accumulate", "sample", "moments"};
+  if (kind < 0 || kind >= kNumKinds) return nullptr;
+  return names[kind];
 }
 
 dsmc_status dsmc_counting_sort_bytes(int64_t n, int32_t nbins, size_t *bytes) {

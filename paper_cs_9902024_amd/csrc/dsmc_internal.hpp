@@ -110,15 +110,28 @@ struct Geometry {
   int collide_block;
 };
 
+// Kernel kinds for per-kernel event timing (order = dsmc_kernel_name).
+enum KernelKind : int {
+  kKStepBegin, kKGenCount, kKGenEmit, kKMotion, kKDigCount, kKColScan, kKDigScan, kKScatter,
+  kKBinBounds, kKBinFinalize, kKPermute, kKCollide, kKAccumulate, kKSample, kKMoments, kNumKinds
+};
+
+// Optional hook around every launch (event timing); null = no hook.
+struct Prof {
+  void *user;
+  void (*mark)(void *user, int kind, int begin);
+};
+
 // ---------------------------------------------------------------------------
 // Kernel launchers (dsmc_kernels.hip)
 // ---------------------------------------------------------------------------
 template <typename real>
 void launch_init(const Geometry &g, const DevPtrs<real> &d, hipStream_t s);
 template <typename real>
-void launch_step(const Geometry &g, const DevPtrs<real> &d, int buf, hipStream_t s);
+void launch_step(const Geometry &g, const DevPtrs<real> &d, int buf, hipStream_t s, const Prof *prof);
 template <typename real>
-void launch_sample(const Geometry &g, const DevPtrs<real> &d, int buf, int slot, hipStream_t s);
+void launch_sample(const Geometry &g, const DevPtrs<real> &d, int buf, int slot, hipStream_t s,
+                   const Prof *prof);
 template <typename real>
 void launch_moments(const Geometry &g, const DevPtrs<real> &d, int slot, int eg0, int n_groups,
                     int nc, int n_runs_ens, hipStream_t s);

@@ -420,7 +420,8 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
     if (loc < end) {
       const int64_t gi = R.so + loc;
       real pos[3] = {P.x[gi], P.y[gi], DIM == 3 ? P.z[gi] : (real)0};
-      real vel[3] = {P.u[gi], P.v[gi], P.w[gi]};
+      // in 2-D Motion never reads w (a diffuse wall only overwrites it)
+      real vel[3] = {P.u[gi], P.v[gi], DIM == 3 ? P.w[gi] : (real)0};
       bool hit;
       const int32_t c = move_one<real, DIM>(R, step, (uint32_t)loc, pos, vel, hit, d.err);
       P.x[gi] = pos[0];
@@ -884,18 +885,25 @@ static int digit_bits(int D) {
   return b;
 }
 
+#define TIMED(kind, ...)                           \
+  do {                                             \
+    if (prof) prof->mark(prof->user, (kind), 1);   \
+    __VA_ARGS__;                                   \
+    if (prof) prof->mark(prof->user, (kind), 0);   \
+  } while (0)
+
 // Scans and scatter of pass `pass`; the tile histograms are already in place.
 static void index_pass(IndexArgs a, int max_digits, int n_runs, int pass, const int32_t *in, int32_t *out,
-                       hipStream_t s) {
+                       hipStream_t s, const Prof *prof = nullptr) {
   a.pass = pass;
   a.in = in;
   a.out = out;
   const size_t lds = (size_t)kWavesPerBlock * a.dstride * sizeof(uint32_t);
   const int wblocks = (a.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
-  hipLaunchKernelGGL(k_colscan, dim3((max_digits + 255) / 256, n_runs), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_digscan, dim3(n_runs), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_scatter, dim3(wblocks), dim3(256), lds, s, a,
-                     a.single ? digit_bits(max_digits) : kDigitBits);
+  TIMED(kKColScan, hipLaunchKernelGGL(k_colscan, dim3((max_digits + 255) / 256, n_runs), dim3(256), 0, s, a));
+  TIMED(kKDigScan, hipLaunchKernelGGL(k_digscan, dim3(n_runs), dim3(256), 0, s, a));
+  TIMED(kKScatter, hipLaunchKernelGGL(k_scatter, dim3(wblocks), dim3(256), lds, s, a,
+                                      a.single ? digit_bits(max_digits) : kDigitBits));
 }
 
 template <typename real>
@@ -916,57 +924,61 @@ void launch_init(const Geometry &g, const DevPtrs<real> &d, hipStream_t s) {
 }
 
 template <typename real, int DIM>
-static void step_dim(const Geometry &g, const DevPtrs<real> &d, int buf, hipStream_t s) {
-  hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(1), 0, s, d.step, d.sample_slot, d.sample_steps, g.n_samples);
+static void step_dim(const Geometry &g, const DevPtrs<real> &d, int buf, hipStream_t s, const Prof *prof) {
+  TIMED(kKStepBegin, hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(1), 0, s, d.step, d.sample_slot,
+                                        d.sample_steps, g.n_samples));
   if (g.n_inflow_runs > 0) {
-    hipLaunchKernelGGL(k_gen_count<real>, dim3(grid_for(g.n_faces)), dim3(256), 0, s, d, g.n_faces);
-    hipLaunchKernelGGL((k_gen_emit<real, DIM>), dim3(g.n_inflow_runs), dim3(256), 0, s, d, buf);
+    TIMED(kKGenCount,
+          hipLaunchKernelGGL(k_gen_count<real>, dim3(grid_for(g.n_faces)), dim3(256), 0, s, d, g.n_faces));
+    TIMED(kKGenEmit, hipLaunchKernelGGL((k_gen_emit<real, DIM>), dim3(g.n_inflow_runs), dim3(256), 0, s, d, buf));
   }
   const size_t lds = (size_t)kWavesPerBlock * g.dstride * sizeof(uint32_t);
   const int wblocks = (g.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
   IndexArgs a = index_args(g, d);
   if (g.npass == 1) {
-    hipLaunchKernelGGL((k_motion<real, DIM, true>), dim3(wblocks), dim3(256), lds, s, d, buf, g.n_tiles, g.tile,
-                       g.dstride);
-    index_pass(a, g.max_nc + 1, g.n_runs, 0, nullptr, d.lcr, s);
+    TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, true>), dim3(wblocks), dim3(256), lds, s, d, buf,
+                                       g.n_tiles, g.tile, g.dstride));
+    index_pass(a, g.max_nc + 1, g.n_runs, 0, nullptr, d.lcr, s, prof);
   } else {
-    hipLaunchKernelGGL((k_motion<real, DIM, false>), dim3(wblocks), dim3(256), lds, s, d, buf, g.n_tiles, g.tile,
-                       g.dstride);
+    TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, false>), dim3(wblocks), dim3(256), lds, s, d, buf,
+                                       g.n_tiles, g.tile, g.dstride));
     const int32_t *in = nullptr;
     for (int p = 0; p < g.npass; ++p) {
       int32_t *out = ((g.npass - 1 - p) % 2 == 0) ? d.lcr : d.lcr_tmp;
       if (p > 0) {
         a.pass = p;
         a.in = in;
-        hipLaunchKernelGGL(k_digcount, dim3(wblocks), dim3(256), lds, s, a, 0);
+        TIMED(kKDigCount, hipLaunchKernelGGL(k_digcount, dim3(wblocks), dim3(256), lds, s, a, 0));
       }
-      index_pass(a, kDigits, g.n_runs, p, in, out, s);
+      index_pass(a, kDigits, g.n_runs, p, in, out, s, prof);
       in = out;
     }
-    hipLaunchKernelGGL(k_bin_bounds, dim3(grid_for(g.n_slots)), dim3(256), 0, s, a, d.lcr, g.n_slots);
-    hipLaunchKernelGGL(k_bin_finalize, dim3((g.n_runs + 255) / 256), dim3(256), 0, s, a, g.n_runs, 1);
+    TIMED(kKBinBounds,
+          hipLaunchKernelGGL(k_bin_bounds, dim3(grid_for(g.n_slots)), dim3(256), 0, s, a, d.lcr, g.n_slots));
+    TIMED(kKBinFinalize,
+          hipLaunchKernelGGL(k_bin_finalize, dim3((g.n_runs + 255) / 256), dim3(256), 0, s, a, g.n_runs, 1));
   }
-  hipLaunchKernelGGL((k_permute<real, DIM>), dim3(grid_for(g.n_slots)), dim3(256), 0, s, d, buf, g.n_slots,
-                     g.tile);
-  hipLaunchKernelGGL(k_collide<real>, dim3((unsigned)((g.n_cells + 255) / 256)), dim3(256), 0, s, d, 1 - buf,
-                     g.n_cells);
+  TIMED(kKPermute, hipLaunchKernelGGL((k_permute<real, DIM>), dim3(grid_for(g.n_slots)), dim3(256), 0, s, d, buf,
+                                      g.n_slots, g.tile));
+  TIMED(kKCollide, hipLaunchKernelGGL(k_collide<real>, dim3((unsigned)((g.n_cells + 255) / 256)), dim3(256), 0, s,
+                                      d, 1 - buf, g.n_cells));
   if (g.n_samples > 0)
-    hipLaunchKernelGGL(k_accumulate<real>, dim3(grid_for(g.acc_stride)), dim3(256), 0, s, d, -1, g.acc_stride,
-                       g.n_eg);
+    TIMED(kKAccumulate, hipLaunchKernelGGL(k_accumulate<real>, dim3(grid_for(g.acc_stride)), dim3(256), 0, s, d,
+                                           -1, g.acc_stride, g.n_eg));
 }
 
 template <typename real>
-void launch_step(const Geometry &g, const DevPtrs<real> &d, int buf, hipStream_t s) {
-  if (g.dim == 3) step_dim<real, 3>(g, d, buf, s);
-  else step_dim<real, 2>(g, d, buf, s);
+void launch_step(const Geometry &g, const DevPtrs<real> &d, int buf, hipStream_t s, const Prof *prof) {
+  if (g.dim == 3) step_dim<real, 3>(g, d, buf, s, prof);
+  else step_dim<real, 2>(g, d, buf, s, prof);
 }
 
 template <typename real>
-void launch_sample(const Geometry &g, const DevPtrs<real> &d, int buf, int slot, hipStream_t s) {
-  hipLaunchKernelGGL(k_sample_cells<real>, dim3((unsigned)((g.n_cells + 255) / 256)), dim3(256), 0, s, d, buf,
-                     g.n_cells);
-  hipLaunchKernelGGL(k_accumulate<real>, dim3(grid_for(g.acc_stride)), dim3(256), 0, s, d, slot, g.acc_stride,
-                     g.n_eg);
+void launch_sample(const Geometry &g, const DevPtrs<real> &d, int buf, int slot, hipStream_t s, const Prof *prof) {
+  TIMED(kKSample, hipLaunchKernelGGL(k_sample_cells<real>, dim3((unsigned)((g.n_cells + 255) / 256)), dim3(256), 0,
+                                     s, d, buf, g.n_cells));
+  TIMED(kKAccumulate, hipLaunchKernelGGL(k_accumulate<real>, dim3(grid_for(g.acc_stride)), dim3(256), 0, s, d, slot,
+                                         g.acc_stride, g.n_eg));
 }
 
 template <typename real>
@@ -978,10 +990,12 @@ void launch_moments(const Geometry &g, const DevPtrs<real> &d, int slot, int eg0
 
 template void launch_init<float>(const Geometry &, const DevPtrs<float> &, hipStream_t);
 template void launch_init<double>(const Geometry &, const DevPtrs<double> &, hipStream_t);
-template void launch_step<float>(const Geometry &, const DevPtrs<float> &, int, hipStream_t);
-template void launch_step<double>(const Geometry &, const DevPtrs<double> &, int, hipStream_t);
-template void launch_sample<float>(const Geometry &, const DevPtrs<float> &, int, int, hipStream_t);
-template void launch_sample<double>(const Geometry &, const DevPtrs<double> &, int, int, hipStream_t);
+template void launch_step<float>(const Geometry &, const DevPtrs<float> &, int, hipStream_t, const Prof *);
+template void launch_step<double>(const Geometry &, const DevPtrs<double> &, int, hipStream_t, const Prof *);
+template void launch_sample<float>(const Geometry &, const DevPtrs<float> &, int, int, hipStream_t,
+                                   const Prof *);
+template void launch_sample<double>(const Geometry &, const DevPtrs<double> &, int, int, hipStream_t,
+                                    const Prof *);
 template void launch_moments<float>(const Geometry &, const DevPtrs<float> &, int, int, int, int, int, hipStream_t);
 template void launch_moments<double>(const Geometry &, const DevPtrs<double> &, int, int, int, int, int,
                                      hipStream_t);
