@@ -33,24 +33,47 @@ HBM_PEAK_GBS = 8000.0
 
 
 def algorithmic_bytes(kind: str, n_particles: int, n_cells: int, dim: int, es: int) -> float:
-    """Bytes a kernel must move per launch (no re-reads, no write-allocate).
+    """Bytes a kernel must move per launch (each byte once, no re-reads).
 
-    motion   reads position and the in-plane velocity (2*dim*es), writes the
-             position (dim*es) and the cell index (4)
-    scatter  reads the cell index (4), writes the LCR entry (4)
-    permute  reads the LCR entry (4) and the particle (dim+3)*es, writes it
-    collide  reads and writes every velocity once (2*3*es), per cell the bin
-             starts (4), remainder and (sigma c_r)_max (2*2*es), counter (8)
+    motion         reads the position and the in-plane velocity (2*dim*es),
+                   writes the position (dim*es) and the cell index (4)
+    scatter        reads the cell index (4), writes the LCR entry (4)
+    collide_cells  (Interaction fused with the permutation P' = P[LCR] and
+    collide_lanes   Sampling) reads the LCR entry (4) and the particle
+                   (dim+3)*es, writes it to P'; per cell the two bin starts (4),
+                   remainder and (sigma c_r)_max read and written (4*es) and
+                   the collision counter read and written (8)
     """
     if kind == "motion":
         return n_particles * (2 * dim * es + dim * es + 4)
     if kind == "scatter":
         return n_particles * 8
-    if kind == "permute":
-        return n_particles * (4 + 2 * (dim + 3) * es)
-    if kind == "collide":
-        return n_particles * 6 * es + n_cells * (4 + 4 * es + 8)
+    if kind in ("collide_cells", "collide_lanes"):
+        return n_particles * (4 + 2 * (dim + 3) * es) + n_cells * (4 + 4 * es + 8)
     return 0.0
+
+
+def copy_calibration(nbytes: int = 1 << 31):
+    """A plain device-to-device copy of known size (torch's copy kernel):
+    the streaming bandwidth this GPU delivers, and the reference kernel whose
+    FETCH_SIZE / WRITE_SIZE counters scale the traffic of the DSMC kernels."""
+    import torch
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(2):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n = 5
+    a.record()
+    for _ in range(n):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / n
+    del x, y
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": 2 * nbytes, "ms": ms, "GBs": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
 def run_gpu(args):
@@ -59,6 +82,7 @@ def run_gpu(args):
     import workloads as W
 
     torch.cuda.set_device(0)
+    calib = copy_calibration()
     wl = W.ensemble_box(n_runs=args.runs, n_per_run=args.per_run, n_steps=1000, sample_every=20,
                         seed=3, state_fp64=False)
     E = P.Ensemble.from_workload(wl, use_graph=True)
@@ -110,7 +134,7 @@ def run_gpu(args):
     if args.plain_runs > 0:
         plain = run_plain_fp64(args, P, W)
     return {"value": value, "elapsed": elapsed, "psteps": psteps, "n_runs": n_runs, "nc": nc,
-            "kernels": kernels, "roofline": rl, "plain": plain, "info": info}
+            "kernels": kernels, "roofline": rl, "plain": plain, "info": info, "calib": calib}
 
 
 def run_plain_fp64(args, P, W):
@@ -214,6 +238,7 @@ def main():
         "plain_fp64": g["plain"],
         "batched_over_plain": (g["value"] / g["plain"]["value"]) if g["plain"] else None,
         "kernels": g["kernels"],
+        "stream_copy": g["calib"],
     }
     print(json.dumps(line))
 

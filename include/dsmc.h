@@ -96,7 +96,10 @@ typedef struct {
                                    (entry < 1: slot filled only by dsmc_sample); may be NULL */
   int32_t use_graph;            /* 1: replay each step from a HIP graph */
   int32_t tile_chunks;          /* tuning: 64-slot rounds per indexing tile (0 = default 256) */
-  int32_t reserved[2];
+  int32_t collide_mode;         /* tuning: 0 auto, 1 one lane per cell (64 cells per wavefront),
+                                   2 one 256-thread block per cell; auto takes 2 when the expected
+                                   particles per cell (initial fill or inflow fill) reach 64 */
+  int32_t reserved;
 } dsmc_options;
 
 /* Arena size for these runs/options.  Pure host computation.
@@ -170,7 +173,7 @@ dsmc_status dsmc_get_counts(dsmc_ctx *ctx, int64_t *out, int32_t n_runs);
 
 /* ---- per-kernel timing ----------------------------------------------------- */
 
-#define DSMC_NKERNELS 15 /* kernel kinds; names from dsmc_kernel_name */
+#define DSMC_NKERNELS 16 /* kernel kinds; names from dsmc_kernel_name */
 
 /* Turn per-kernel timing on or off (synchronises).  While on, every launch is
  * bracketed by two HIP events on the context's stream and steps are not

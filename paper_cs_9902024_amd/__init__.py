@@ -32,7 +32,7 @@ EXPORTS = ("dsmc_required_bytes", "dsmc_init_runs", "dsmc_step", "dsmc_sample", 
            "dsmc_get_state", "dsmc_set_state", "dsmc_get_lcr", "dsmc_get_cell_state",
            "dsmc_get_counts", "dsmc_counting_sort_bytes", "dsmc_counting_sort",
            "dsmc_set_profiling", "dsmc_kernel_times", "dsmc_kernel_name")
-NKERNELS = 15
+NKERNELS = 16
 
 
 class DsmcError(RuntimeError):
@@ -55,7 +55,7 @@ class dsmc_run_spec(C.Structure):
 class dsmc_options(C.Structure):
     _fields_ = [("state_fp64", C.c_int32), ("n_groups", C.c_int32), ("n_samples", C.c_int32),
                 ("sample_steps", C.POINTER(C.c_int32)), ("use_graph", C.c_int32),
-                ("tile_chunks", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("tile_chunks", C.c_int32), ("collide_mode", C.c_int32), ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -135,7 +135,7 @@ def make_run_spec(rs) -> dsmc_run_spec:
 
 
 def make_options(state_fp64: bool, n_groups: int, sample_steps: Sequence[int],
-                 use_graph: bool = False, tile_chunks: int = 0):
+                 use_graph: bool = False, tile_chunks: int = 0, collide_mode: int = 0):
     steps = (C.c_int32 * max(1, len(sample_steps)))(*sample_steps)
     o = dsmc_options()
     o.state_fp64 = int(bool(state_fp64))
@@ -144,6 +144,7 @@ def make_options(state_fp64: bool, n_groups: int, sample_steps: Sequence[int],
     o.sample_steps = C.cast(steps, C.POINTER(C.c_int32))
     o.use_graph = int(bool(use_graph))
     o.tile_chunks = int(tile_chunks)
+    o.collide_mode = int(collide_mode)
     o._keep = steps
     return o
 
@@ -294,14 +295,15 @@ class Ensemble:
     context on the current CUDA/HIP device and stream."""
 
     def __init__(self, runs, sample_steps: Sequence[int] = (), state_fp64: bool = False,
-                 n_groups: int = 1, use_graph: bool = False, tile_chunks: int = 0, device=None,
-                 stream=None):
+                 n_groups: int = 1, use_graph: bool = False, tile_chunks: int = 0,
+                 collide_mode: int = 0, device=None, stream=None):
         import torch
         if not torch.cuda.is_available():
             raise DsmcError(-4, "Ensemble", "no GPU visible to torch")
         self.runs = list(runs)
         self.specs = _specs(self.runs)
-        self.opt = make_options(state_fp64, n_groups, list(sample_steps), use_graph, tile_chunks)
+        self.opt = make_options(state_fp64, n_groups, list(sample_steps), use_graph, tile_chunks,
+                                collide_mode)
         self.nbytes = dsmc_required_bytes(self.specs, self.opt)
         dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.arena = torch.empty(self.nbytes, dtype=torch.uint8, device=dev)

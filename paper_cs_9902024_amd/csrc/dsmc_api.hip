@@ -33,13 +33,14 @@ struct Plan {
   std::vector<RunDev> runs;
   std::vector<int32_t> tile_run, face_run, cgroup_run, inflow_runs, eg_start, eg_runs, eg_nc, sample_steps;
   std::vector<int64_t> eg_acc;
+  std::vector<int2> items, cell_items;
   std::vector<Ensemble> ens;
   std::vector<int64_t> spec_capacity;
   size_t off_runs, off_tile_run, off_face_run, off_cgroup_run, off_inflow, off_eg_start, off_eg_runs, off_eg_acc,
-      off_eg_nc, off_samples;
+      off_eg_nc, off_samples, off_items, off_cell_items;
   size_t off_P[2][6];
   size_t off_cell, off_lcr, off_lcr_tmp, off_hist, off_tot, off_bin_start, off_remc, off_gmax, off_ncoll, off_remf,
-      off_gencnt, off_stage, off_acc, off_mom, off_nalive, off_nsorted, off_ngen, off_scalars;
+      off_gencnt, off_stage, off_acc, off_mom, off_nalive, off_nsorted, off_ngen, off_scalars, off_wallq, off_wallq_n;
   size_t total;
 };
 
@@ -57,6 +58,7 @@ dsmc_status validate(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_optio
   if (opt) {
     if (opt->n_groups < 0 || opt->n_samples < 0) return fail(msg, DSMC_EINVAL, "negative n_groups or n_samples");
     if (opt->tile_chunks < 0 || opt->tile_chunks > 4096) return fail(msg, DSMC_EINVAL, "tile_chunks out of range");
+    if (opt->collide_mode < 0 || opt->collide_mode > 2) return fail(msg, DSMC_EINVAL, "collide_mode out of range");
   }
   const int dim = runs[0].dim;
   for (int r = 0; r < n_runs; ++r) {
@@ -160,6 +162,20 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
     R.cbo = cbo;
     R.n_init = s.n_init;
     R.hs = s.omega == 0.5;
+    {
+      // interaction work item: a whole wave per cell for crowded cells
+      double fill = (double)s.n_init;
+      if (s.face_bc[0] == DSMC_BC_INFLOW) fill = std::max(fill, s.inflow_n * s.lx * s.ly * s.lz);
+      const double ppc = fill / (double)R.nc;
+      R.coll_wave = opt.collide_mode == 2 || (opt.collide_mode == 0 && ppc >= 64.0);
+      // lane mode: as many cells per wavefront (<= 64) as fit 3/4 of the LDS stage
+      const int cap = g.fp64 ? kCollideCapF64 : kCollideCapF32;
+      R.lane_cells = (int32_t)std::max(1.0, std::min(64.0, std::floor(0.75 * cap / std::max(ppc, 1.0))));
+      if (R.coll_wave)
+        for (int32_t c = 0; c < R.nc; ++c) P.cell_items.push_back(make_int2(r, c));
+      else
+        for (int32_t c = 0; c < R.nc; c += R.lane_cells) P.items.push_back(make_int2(r, c));
+    }
     for (int f = 0; f < 6; ++f) {
       R.bc[f] = (f < 2 * g.dim) ? s.face_bc[f] : DSMC_BC_SPECULAR;
       R.face_T[f] = s.face_T[f];
@@ -218,6 +234,9 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
   g.n_cells = co;
   g.n_faces = fo;
   g.n_inflow_runs = (int32_t)P.inflow_runs.size();
+  g.n_items = (int64_t)P.items.size();
+  g.n_cell_items = (int64_t)P.cell_items.size();
+  g.collide_mode = opt.collide_mode;
 
   // ensembles in order of first appearance; group of a run = its index in the ensemble mod G
   for (int r = 0; r < n_runs; ++r) {
@@ -269,10 +288,14 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
   P.off_eg_acc = take(8 * P.eg_acc.size());
   P.off_eg_nc = take(4 * P.eg_nc.size());
   P.off_samples = take(4 * P.sample_steps.size());
+  P.off_items = take(sizeof(int2) * P.items.size());
+  P.off_cell_items = take(sizeof(int2) * P.cell_items.size());
   for (int b = 0; b < 2; ++b)
     for (int a = 0; a < 6; ++a) P.off_P[b][a] = (a == 2 && g.dim == 2) ? (size_t)-1 : take(es * g.n_slots);
   P.off_cell = take(4 * g.n_slots);
   P.off_lcr = take(4 * g.n_slots);
+  P.off_wallq = take(4 * g.n_slots);
+  P.off_wallq_n = take(4 * (size_t)g.n_tiles);
   P.off_lcr_tmp = g.npass > 1 ? take(4 * g.n_slots) : (size_t)-1;
   P.off_hist = take(4 * (size_t)mo);
   P.off_tot = take(4 * (size_t)cbo);
@@ -306,6 +329,8 @@ DevPtrs<real> carve(const Plan &P, char *base) {
   d.eg_acc = (const int64_t *)(base + P.off_eg_acc);
   d.eg_nc = (const int32_t *)(base + P.off_eg_nc);
   d.sample_steps = (const int32_t *)(base + P.off_samples);
+  d.items = (const int2 *)(base + P.off_items);
+  d.cell_items = (const int2 *)(base + P.off_cell_items);
   for (int b = 0; b < 2; ++b) {
     real **c[6] = {&d.P[b].x, &d.P[b].y, &d.P[b].z, &d.P[b].u, &d.P[b].v, &d.P[b].w};
     for (int a = 0; a < 6; ++a) *c[a] = P.off_P[b][a] == (size_t)-1 ? nullptr : (real *)(base + P.off_P[b][a]);
@@ -330,6 +355,8 @@ DevPtrs<real> carve(const Plan &P, char *base) {
   d.step = (uint32_t *)(base + P.off_scalars);
   d.sample_slot = (int32_t *)(base + P.off_scalars + 4);
   d.err = (int32_t *)(base + P.off_scalars + 8);
+  d.wallq_n = (uint32_t *)(base + P.off_wallq_n);
+  d.wallq = (uint32_t *)(base + P.off_wallq);
   return d;
 }
 
@@ -515,6 +542,8 @@ dsmc_status dsmc_init_runs(const dsmc_run_spec *runs, int32_t n_runs, const dsmc
   if (!st) st = upload(c, P.off_eg_acc, P.eg_acc);
   if (!st) st = upload(c, P.off_eg_nc, P.eg_nc);
   if (!st) st = upload(c, P.off_samples, P.sample_steps);
+  if (!st) st = upload(c, P.off_items, P.items);
+  if (!st) st = upload(c, P.off_cell_items, P.cell_items);
   if (!st) {
     if (P.g.fp64) launch_init<double>(P.g, c->dd, c->stream);
     else launch_init<float>(P.g, c->df, c->stream);
@@ -809,9 +838,9 @@ dsmc_status dsmc_kernel_times(dsmc_ctx *c, double *ms, int64_t *launches, int32_
 }
 
 const char *dsmc_kernel_name(int32_t kind) {
-  static const char *names[kNumKinds] = {"step_begin", "gen_count", "gen_emit", "motion", "digcount",
+  static const char *names[kNumKinds] = {"step_begin", "gen_count", "gen_emit", "motion", "motion_walls", "digcount",
                                          "colscan", "digscan", "scatter", "bin_bounds", "bin_finalize",
-                                         "permute", "collide", "accumulate", "sample", "moments"};
+                                         "collide_lanes", "collide_cells", "accumulate", "sample", "moments"};
   if (kind < 0 || kind >= kNumKinds) return nullptr;
   return names[kind];
 }

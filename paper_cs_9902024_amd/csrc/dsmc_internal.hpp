@@ -10,6 +10,9 @@ namespace dsmc {
 
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;          // 256-thread blocks
+constexpr int kCollideWaves = 2;           // waves per block of the collide kernel
+constexpr int kCollideCapF32 = 1280;       // particles staged in LDS per collide wavefront
+constexpr int kCollideCapF64 = 1024;
 constexpr int kDigitBits = 11;             // indexing digit: 2048 bins per pass
 constexpr int kDigits = 1 << kDigitBits;
 constexpr int kMaxWallHits = 64;           // wall interactions per particle per step
@@ -41,6 +44,8 @@ struct RunDev {
   int32_t nface;     // inflow face elements (0 without inflow)
   int32_t ndig;      // digits of the first indexing pass
   int32_t hs;        // hard sphere (omega == 0.5)
+  int32_t coll_wave; // interaction work item = one cell per block (else lane_cells cells, a lane each)
+  int32_t lane_cells;
   int32_t bc[6];
   uint32_t key0, key1;   // Philox key: run id, seed
   double L[3], inv_d[3];
@@ -68,6 +73,8 @@ struct DevPtrs {
   const int64_t *eg_acc;       // [n_eg + 1] offset (doubles) of each (ensemble, group) block
   const int32_t *eg_nc;        // [n_eg]
   const int32_t *sample_steps; // [n_samples]
+  const int2 *items;           // [n_items] lane-per-cell interaction items: (run, first cell)
+  const int2 *cell_items;      // [n_cell_items] block-per-cell interaction items: (run, cell)
   Particles<real> P[2];
   int32_t *cell;               // [slots] cell (bin) of each slot after Motion
   int32_t *lcr;                // [slots] run-local slot in cell order
@@ -88,6 +95,8 @@ struct DevPtrs {
   uint32_t *step;              // device step counter
   int32_t *sample_slot;        // sample slot of the current step or -1
   int32_t *err;                // first device error (0 = none)
+  uint32_t *wallq;             // [slots] per tile: run-local slots of particles that reach a face
+  uint32_t *wallq_n;           // [tiles] queue length per tile
 };
 
 struct Geometry {
@@ -107,13 +116,15 @@ struct Geometry {
   int n_eg;
   int64_t acc_stride;
   int n_samples;
-  int collide_block;
+  int64_t n_items;      // lane-per-cell interaction items (up to 64 cells each)
+  int64_t n_cell_items; // block-per-cell interaction items
+  int collide_mode;      // 0 auto, 1 lane per cell, 2 wave per cell
 };
 
 // Kernel kinds for per-kernel event timing (order = dsmc_kernel_name).
 enum KernelKind : int {
-  kKStepBegin, kKGenCount, kKGenEmit, kKMotion, kKDigCount, kKColScan, kKDigScan, kKScatter,
-  kKBinBounds, kKBinFinalize, kKPermute, kKCollide, kKAccumulate, kKSample, kKMoments, kNumKinds
+  kKStepBegin, kKGenCount, kKGenEmit, kKMotion, kKMotionWalls, kKDigCount, kKColScan, kKDigScan, kKScatter,
+  kKBinBounds, kKBinFinalize, kKCollide, kKCollideCell, kKAccumulate, kKSample, kKMoments, kNumKinds
 };
 
 // Optional hook around every launch (event timing); null = no hook.

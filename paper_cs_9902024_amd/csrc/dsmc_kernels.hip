@@ -318,13 +318,14 @@ __global__ __launch_bounds__(256) void k_gen_emit(DevPtrs<real> d, int buf) {
 // cell, or nc (DEAD) when it leaves.  hit reports a velocity change.
 template <typename real, int DIM>
 __device__ __forceinline__ int32_t move_one(const RunDev &R, uint32_t step, uint32_t slot, real (&pos)[3],
-                                            real (&vel)[3], bool &hit, int32_t *err) {
+                                            real (&vel)[3], bool &hit, bool &reemit, int32_t *err) {
   real L[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) L[a] = (real)R.L[a];
   real trem = (real)R.dt;
   int hits = 0;
   hit = false;
+  reemit = false;
   for (;;) {
     real tmin = infinity<real>();
     int ax = -1, side = 0;
@@ -365,6 +366,7 @@ __device__ __forceinline__ int32_t move_one(const RunDev &R, uint32_t step, uint
         if (a == ax) vel[a] = -vel[a];
     } else if (bc == kDiffuse) {
       const real Tw = (real)R.face_T[f];
+      reemit = true;
       UStream<real> ws(R.key0, R.key1, step, kWall, slot);
       ws.seek(4u * (uint32_t)hits);
       const real w0 = ws(), w1 = ws(), w2 = ws();
@@ -394,9 +396,64 @@ __device__ __forceinline__ int32_t move_one(const RunDev &R, uint32_t step, uint
   return (iz * R.ny + iy) * R.nx + ix;
 }
 
-// One wavefront per tile of tile_chunks*64 consecutive slots of one run:
-// coalesced SoA loads/stores, the new cell of every slot, and the tile's
-// histogram of the first indexing digit in wave-private LDS.
+// Free flight with no face reached this step, decided without divisions:
+// the end point lies inside the box by a margin far above the rounding of the
+// full face-time test, so both tests agree and the result is identical.
+template <typename real> __device__ __forceinline__ real flight_margin_eps();
+template <> __device__ __forceinline__ double flight_margin_eps<double>() { return 64.0 * 0x1p-53; }
+template <> __device__ __forceinline__ float flight_margin_eps<float>() { return 64.0f * 0x1p-24f; }
+
+template <typename real, int DIM>
+__device__ __forceinline__ bool free_flight(const RunDev &R, const real (&pos)[3], const real (&vel)[3],
+                                            real (&out)[3]) {
+  const real dt = (real)R.dt;
+  bool inside = true;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const real L = (real)R.L[a];
+    out[a] = pos[a] + vel[a] * dt;
+    const real m = flight_margin_eps<real>() * (L + fabs(vel[a]) * dt);
+    inside = inside && (pos[a] >= (real)0) && (pos[a] <= L) && (out[a] >= m) && (out[a] <= L - m);
+  }
+  return inside;
+}
+
+// Adds 1 per active lane to h[key]: one LDS atomic per run of equal keys in
+// consecutive active lanes (an inactive lane ends a run).
+__device__ __forceinline__ void histogram_add(uint32_t *h, uint32_t key, bool active) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t k = active ? key : 0xFFFFFFFFu;  // never equal to a live key
+  const uint32_t prev = __shfl_up(k, 1);
+  const bool boundary = !active || lane == 0 || prev != k;
+  const uint64_t bm = __ballot(boundary);
+  const uint64_t after = lane == 63 ? 0ull : (bm & ~((2ull << lane) - 1ull));
+  const int nxt = after ? __ffsll((unsigned long long)after) - 1 : 64;
+  if (active && boundary) atomicAdd(&h[key], (uint32_t)(nxt - lane));
+}
+
+template <typename real> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+
+template <typename real>
+__device__ __forceinline__ void load4(const real *p, int64_t i, real (&o)[4]) {
+  const typename Vec4<real>::type t = *reinterpret_cast<const typename Vec4<real>::type *>(p + i);
+  o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w;
+}
+template <typename real>
+__device__ __forceinline__ void store4(real *p, int64_t i, const real (&o)[4]) {
+  typename Vec4<real>::type t;
+  t.x = o[0]; t.y = o[1]; t.z = o[2]; t.w = o[3];
+  *reinterpret_cast<typename Vec4<real>::type *>(p + i) = t;
+}
+
+// One wavefront per tile of tile_chunks*64 consecutive slots of one run.
+// Each round covers 256 slots, four consecutive ones per lane, moved with
+// 128-bit loads and stores (only a run's last, partial round goes slot by
+// slot).  A particle that reaches no face this step is moved here; the others
+// go to the tile's wall queue (k_motion_walls).  The new cell of every free
+// particle is counted in the tile's histogram of the first indexing digit,
+// kept in wave-private LDS.
 template <typename real, int DIM, bool SINGLE>
 __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_t n_tiles, int64_t tile,
                                                 int dstride) {
@@ -413,32 +470,134 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
   wave_sync();
   const int64_t n = d.n_alive[r];
   const int64_t begin = tl * tile, end = min(begin + tile, n);
-  const uint32_t step = *d.step;
-  Particles<real> P = d.P[buf];
-  for (int64_t b = begin; b < end; b += kWave) {
-    const int64_t loc = b + lane;
-    if (loc < end) {
-      const int64_t gi = R.so + loc;
-      real pos[3] = {P.x[gi], P.y[gi], DIM == 3 ? P.z[gi] : (real)0};
-      // in 2-D Motion never reads w (a diffuse wall only overwrites it)
-      real vel[3] = {P.u[gi], P.v[gi], DIM == 3 ? P.w[gi] : (real)0};
-      bool hit;
-      const int32_t c = move_one<real, DIM>(R, step, (uint32_t)loc, pos, vel, hit, d.err);
-      P.x[gi] = pos[0];
-      P.y[gi] = pos[1];
-      if (DIM == 3) P.z[gi] = pos[2];
-      if (hit) {
-        P.u[gi] = vel[0];
-        P.v[gi] = vel[1];
-        P.w[gi] = vel[2];
+  real *__restrict__ X = d.P[buf].x + R.so;
+  real *__restrict__ Y = d.P[buf].y + R.so;
+  real *__restrict__ Z = d.P[buf].z + R.so;
+  real *__restrict__ Uv = d.P[buf].u + R.so;
+  real *__restrict__ Vv = d.P[buf].v + R.so;
+  real *__restrict__ Wv = d.P[buf].w + R.so;
+  int32_t *__restrict__ cell = d.cell + R.so;
+  uint32_t *__restrict__ wq = d.wallq + (int64_t)t * tile;  // this tile's queue segment
+  uint32_t qn = 0;
+  for (int64_t b = begin; b < end; b += 4 * kWave) {
+    const int64_t i0 = b + 4 * lane;
+    const bool full = b + 4 * kWave <= end;  // wave-uniform
+    real px[4], py[4], pz[4], vx[4], vy[4], vz[4];
+    bool act[4];
+    if (full) {
+      load4(X, i0, px);
+      load4(Y, i0, py);
+      if (DIM == 3) load4(Z, i0, pz);
+      load4(Uv, i0, vx);
+      load4(Vv, i0, vy);
+      if (DIM == 3) load4(Wv, i0, vz);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) act[e] = true;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        act[e] = i0 + e < end;
+        if (act[e]) {
+          px[e] = X[i0 + e];
+          py[e] = Y[i0 + e];
+          if (DIM == 3) pz[e] = Z[i0 + e];
+          vx[e] = Uv[i0 + e];
+          vy[e] = Vv[i0 + e];
+          if (DIM == 3) vz[e] = Wv[i0 + e];
+        }
       }
-      d.cell[gi] = c;
-      atomicAdd(&h[SINGLE ? (uint32_t)c : ((uint32_t)c & (kDigits - 1))], 1u);
+    }
+    real ox[4], oy[4], oz[4];
+    int32_t oc[4];
+    uint32_t key[4];
+    bool fast[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      // in 2-D Motion never reads w: only a diffuse re-emission sets it
+      const real pos[3] = {px[e], py[e], DIM == 3 ? pz[e] : (real)0};
+      const real vel[3] = {vx[e], vy[e], DIM == 3 ? vz[e] : (real)0};
+      real out[3];
+      fast[e] = act[e] && free_flight<real, DIM>(R, pos, vel, out);
+      ox[e] = fast[e] ? out[0] : px[e];
+      oy[e] = fast[e] ? out[1] : py[e];
+      oz[e] = (DIM == 3 && fast[e]) ? out[2] : (DIM == 3 ? pz[e] : (real)0);
+      int32_t c = 0;
+      if (fast[e]) {
+        const int32_t ix = axis_index(out[0], (real)R.inv_d[0], R.nx);
+        const int32_t iy = axis_index(out[1], (real)R.inv_d[1], R.ny);
+        const int32_t iz = (DIM == 3) ? axis_index(out[2], (real)R.inv_d[2], R.nz) : 0;
+        c = (iz * R.ny + iy) * R.nx + ix;
+      }
+      oc[e] = c;
+      key[e] = SINGLE ? (uint32_t)c : ((uint32_t)c & (kDigits - 1));
+    }
+    // (a queued particle's position and cell are rewritten by k_motion_walls)
+    if (full) {
+      store4(X, i0, ox);
+      store4(Y, i0, oy);
+      if (DIM == 3) store4(Z, i0, oz);
+      *reinterpret_cast<int4 *>(cell + i0) = make_int4(oc[0], oc[1], oc[2], oc[3]);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (act[e]) {
+          X[i0 + e] = ox[e];
+          Y[i0 + e] = oy[e];
+          if (DIM == 3) Z[i0 + e] = oz[e];
+          cell[i0 + e] = oc[e];
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) histogram_add(h, key[e], fast[e]);
+    // particles that reach a face go to the tile's segment of the wall queue
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const bool mine = act[e] && !fast[e];
+      const uint64_t m = __ballot(mine);
+      if (m == 0ull) continue;
+      if (mine) wq[qn + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)(i0 + e);
+      qn += (uint32_t)__popcll(m);
     }
   }
+  if (lane == 0) d.wallq_n[t] = qn;
   wave_sync();
   uint32_t *Mt = d.hist + R.mo + tl * D;
   for (int q = lane; q < D; q += kWave) Mt[q] = h[q];
+}
+
+// The particles Motion queued because they reach a face this step (one block
+// per tile): the full face-by-face flight (specular, diffuse, open faces) and
+// their cells added to the tile histogram of the first indexing digit.
+template <typename real, int DIM, bool SINGLE>
+__global__ __launch_bounds__(256) void k_motion_walls(DevPtrs<real> d, int buf, int32_t n_tiles, int64_t tile) {
+  const int32_t t = blockIdx.x;
+  if (t >= n_tiles) return;
+  const uint32_t nq = d.wallq_n[t];
+  if (nq == 0) return;
+  const RunDev &R = d.runs[d.tile_run[t]];
+  const uint32_t step = *d.step;
+  const int D = SINGLE ? R.nc + 1 : kDigits;
+  uint32_t *Mt = d.hist + R.mo + (int64_t)(t - R.to) * D;
+  const uint32_t *wq = d.wallq + (int64_t)t * tile;
+  const Particles<real> P = d.P[buf];
+  for (uint32_t i = threadIdx.x; i < nq; i += blockDim.x) {
+    const int64_t loc = wq[i];
+    const int64_t gs = R.so + loc;
+    real p3[3] = {P.x[gs], P.y[gs], DIM == 3 ? P.z[gs] : (real)0};
+    real v3[3] = {P.u[gs], P.v[gs], DIM == 3 ? P.w[gs] : (real)0};
+    bool hit, reemit;
+    const int32_t c = move_one<real, DIM>(R, step, (uint32_t)loc, p3, v3, hit, reemit, d.err);
+    P.x[gs] = p3[0];
+    P.y[gs] = p3[1];
+    if (DIM == 3) P.z[gs] = p3[2];
+    if (hit) {
+      P.u[gs] = v3[0];
+      P.v[gs] = v3[1];
+      if (DIM == 3 || reemit) P.w[gs] = v3[2];
+    }
+    d.cell[gs] = c;
+    atomicAdd(&Mt[SINGLE ? (uint32_t)c : ((uint32_t)c & (kDigits - 1))], 1u);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -572,23 +731,14 @@ __global__ __launch_bounds__(256) void k_digscan(IndexArgs a) {
   }
 }
 
-// Lanes holding the same digit: intersect one ballot per digit bit.
-__device__ __forceinline__ uint64_t match_digit(uint32_t q, bool active, int nbits) {
-  uint64_t m = __ballot(active);
-  for (int b = 0; b < nbits; ++b) {
-    const bool bit = (q >> b) & 1u;
-    const uint64_t t = __ballot(bit);
-    m &= bit ? t : ~t;
-  }
-  return m;
-}
-
 // One wavefront per tile, 64 consecutive positions per round in order: the
 // rank of a position among equal digits is (digit start) + (count in earlier
-// tiles) + (count in earlier rounds of this tile, LDS) + (earlier lanes with
-// the same digit, ballots).  That is exactly the sequential stable order.
-__global__ __launch_bounds__(256) void k_scatter(IndexArgs a, int nbits) {
+// tiles) + (count in earlier rounds of this tile) + (earlier lanes with the
+// same digit, from ballots).  That is exactly the sequential stable order.
+// The first two terms are summed into the wave's LDS cursor table up front.
+__global__ __launch_bounds__(256) void k_scatter(IndexArgs a) {
   extern __shared__ uint32_t lds[];
+  constexpr int U = 16;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int t = blockIdx.x * kWavesPerBlock + wave;
   if (t >= a.n_tiles) return;
@@ -597,33 +747,53 @@ __global__ __launch_bounds__(256) void k_scatter(IndexArgs a, int nbits) {
   const int64_t tl = t - R.to;
   const bool single = a.single;
   const int D = single ? R.nc + 1 : kDigits;
-  uint32_t *run_cnt = lds + wave * a.dstride;
-  for (int q = lane; q < D; q += kWave) run_cnt[q] = 0;
+  uint32_t *cursor = lds + wave * a.dstride;
+  {
+    const uint32_t *Mt = a.hist + R.mo + tl * D;
+    const uint32_t *S = a.tot + R.cbo;
+    for (int q = lane; q < D; q += kWave) cursor[q] = S[q] + Mt[q];
+  }
   wave_sync();
   const int64_t n = a.n_sorted[r];
   const int64_t begin = tl * a.tile, end = min(begin + a.tile, n);
-  const uint32_t *Mt = a.hist + R.mo + tl * D;
-  const uint32_t *S = a.tot + R.cbo;
   const uint64_t lt = (1ull << lane) - 1ull;
-  for (int64_t b = begin; b < end; b += kWave) {
-    const int64_t loc = b + lane;
-    const bool active = loc < end;
-    int32_t v = 0;
-    uint32_t q = 0;
-    if (active) {
-      v = a.in ? a.in[R.so + loc] : (int32_t)loc;
-      q = digit_of(a.cell[R.so + v], a.pass, single);
+  const int32_t *__restrict__ in = a.in ? a.in + R.so : nullptr;
+  const int32_t *__restrict__ cell = a.cell + R.so;
+  int32_t *__restrict__ out = a.out + R.so;
+  for (int64_t b = begin; b < end; b += U * kWave) {
+    int32_t v[U];
+    uint32_t key[U];
+    bool act[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int64_t loc = b + q * kWave + lane;
+      act[q] = loc < end;
+      v[q] = act[q] ? (in ? in[loc] : (int32_t)loc) : 0;
     }
-    const uint64_t peers = match_digit(q, active, nbits);
-    if (active) {
-      const uint32_t rank = __popcll(peers & lt);
-      const uint32_t cnt = __popcll(peers);
-      const uint32_t prior = run_cnt[q];
-      const uint32_t dst = S[q] + Mt[q] + prior + rank;
-      a.out[R.so + dst] = v;
-      if (rank == cnt - 1) run_cnt[q] = prior + cnt;
+#pragma unroll
+    for (int q = 0; q < U; ++q) key[q] = act[q] ? digit_of(cell[v[q]], a.pass, single) : 0u;
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      // lanes holding the same digit: one ballot per distinct digit present
+      uint64_t rest = __ballot(act[q]);
+      uint64_t peers = 0;
+      while (rest) {
+        const int leader = __ffsll((unsigned long long)rest) - 1;
+        const uint32_t dl = (uint32_t)__builtin_amdgcn_readlane((int)key[q], leader);
+        const bool same = act[q] && key[q] == dl;
+        const uint64_t pm = __ballot(same);
+        if (same) peers = pm;
+        rest &= ~pm;
+      }
+      if (act[q]) {
+        const uint32_t rank = __popcll(peers & lt);
+        const uint32_t cnt = __popcll(peers);
+        const uint32_t prior = cursor[key[q]];
+        out[prior + rank] = v[q];
+        if (rank == cnt - 1) cursor[key[q]] = prior + cnt;
+      }
+      wave_sync();
     }
-    wave_sync();
   }
 }
 
@@ -654,32 +824,117 @@ __global__ void k_bin_finalize(IndexArgs a, int n_runs, int set_alive) {
 }
 
 // ---------------------------------------------------------------------------
-// Permutation: P' = P[LCR] (cell-sorted, DEAD bin dropped)
+// Interaction (NTC) fused with the permutation P' = P[LCR] and Sampling
 // ---------------------------------------------------------------------------
+//
+// Work items: up to 64 consecutive sparse cells of one run per wavefront (a
+// lane per cell, k_collide), or one crowded cell per 256-thread block
+// (k_collide_cell).  The item gathers its cells' particles through LCR (that
+// is the permutation: positions go straight to P', velocities are staged in
+// LDS), runs the collisions on LDS, writes the velocities back to P'
+// coalesced and samples from LDS.  Results are those of the sequential
+// per-cell order: the block mode runs 256 selections at a time in
+// conflict-free levels and replays a window sequentially whenever
+// (sigma c_r)_max grows inside it.
 
-template <typename real, int DIM>
-__global__ __launch_bounds__(256) void k_permute(DevPtrs<real> d, int src, int64_t n_slots, int64_t tile) {
-  const Particles<real> A = d.P[src];
-  const Particles<real> B = d.P[1 - src];
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_slots;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int r = d.tile_run[i / tile];
-    const RunDev &R = d.runs[r];
-    if (i - R.so >= d.n_alive[r]) continue;
-    const int64_t s = R.so + d.lcr[i];
-    B.x[i] = A.x[s];
-    B.y[i] = A.y[s];
-    if (DIM == 3) B.z[i] = A.z[s];
-    B.u[i] = A.u[s];
-    B.v[i] = A.v[s];
-    B.w[i] = A.w[s];
-  }
+template <typename real> struct CollideCap;
+template <> struct CollideCap<float> { static constexpr int value = kCollideCapF32; };
+template <> struct CollideCap<double> { static constexpr int value = kCollideCapF64; };
+
+template <typename real>
+constexpr int collide_wave_bytes() {
+  return ((CollideCap<real>::value * (3 * (int)sizeof(real) + 4)) + 15) & ~15;
 }
 
-// ---------------------------------------------------------------------------
-// Interaction (NTC) + Sampling, one lane per cell
-// ---------------------------------------------------------------------------
+// Block index remapped so that each XCD (blocks are dealt round-robin over
+// the 8 XCDs) works on one contiguous range of items: neighbouring cells read
+// overlapping source ranges of P, which then meet in the same L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblk) {
+  const int64_t q = nblk / 8, rmd = nblk % 8;
+  const int64_t x = b % 8, pos = b / 8;
+  return x < rmd ? x * (q + 1) + pos : rmd * (q + 1) + (x - rmd) * q + pos;
+}
 
+template <typename real>
+struct Selection {
+  uint32_t i, j;
+  real ua, uc, ue;
+};
+
+// Selection k of cell c: pair (i, j != i) and the acceptance and scattering
+// uniforms, from Philox blocks (step, COLL, c, 2k) and (step, COLL, c, 2k+1).
+template <typename real>
+__device__ __forceinline__ Selection<real> draw_selection(const RunDev &R, uint32_t step, uint32_t c, int64_t k,
+                                                          uint32_t N) {
+  const uint4 b0 = philox(make_uint4(step, kColl, c, (uint32_t)(2 * k)), R.key0, R.key1);
+  const uint4 b1 = philox(make_uint4(step, kColl, c, (uint32_t)(2 * k + 1)), R.key0, R.key1);
+  Selection<real> s;
+  s.i = __umulhi(b0.x, N);
+  const uint32_t jp = __umulhi(b0.y, N - 1u);
+  s.j = jp + (jp >= s.i ? 1u : 0u);
+  s.ua = u01<real>(b0.z, b0.w);
+  s.uc = u01<real>(b1.x, b1.y);
+  s.ue = u01<real>(b1.z, b1.w);
+  return s;
+}
+
+// Isotropic scattering of one accepted pair.
+template <typename real>
+__device__ __forceinline__ void scatter_pair(real cr, real uc, real ue, real &ui, real &vi, real &wi, real &uj,
+                                             real &vj, real &wj) {
+  const real cosx = (real)2 * uc - (real)1;
+  const real sinx = sqrt((real)1 - cosx * cosx);
+  const real eps = two_pi<real>() * ue;
+  const real rx = cr * cosx, ry = cr * sinx * cos(eps), rz = cr * sinx * sin(eps);
+  const real mx = (real)0.5 * (ui + uj), my = (real)0.5 * (vi + vj), mz = (real)0.5 * (wi + wj);
+  ui = mx + (real)0.5 * rx;
+  vi = my + (real)0.5 * ry;
+  wi = mz + (real)0.5 * rz;
+  uj = mx - (real)0.5 * rx;
+  vj = my - (real)0.5 * ry;
+  wj = mz - (real)0.5 * rz;
+}
+
+// Selections [k0, k1) of one cell in order, by one lane, on arrays u/v/w
+// (LDS or global).  Returns the accepted collisions; updates gm.
+template <typename real>
+__device__ uint32_t chain_serial(const RunDev &R, uint32_t step, uint32_t c, uint32_t N, int64_t k0, int64_t k1,
+                                 real *u, real *v, real *w, real &gm) {
+  uint32_t ncol = 0;
+  for (int64_t k = k0; k < k1; ++k) {
+    const Selection<real> s = draw_selection<real>(R, step, c, k, N);
+    const real du = u[s.i] - u[s.j], dv = v[s.i] - v[s.j], dw = w[s.i] - w[s.j];
+    const real cr = sqrt(du * du + dv * dv + dw * dw);
+    const real g = g_of<real>(R, cr);
+    if (g > gm) gm = g;
+    if (!(s.ua < g / gm)) continue;
+    real ui = u[s.i], vi = v[s.i], wi = w[s.i], uj = u[s.j], vj = v[s.j], wj = w[s.j];
+    scatter_pair(cr, s.uc, s.ue, ui, vi, wi, uj, vj, wj);
+    u[s.i] = ui; v[s.i] = vi; w[s.i] = wi;
+    u[s.j] = uj; v[s.j] = vj; w[s.j] = wj;
+    ncol++;
+  }
+  return ncol;
+}
+
+// NTC bookkeeping: number of selections this step and the new remainder.
+template <typename real>
+__device__ __forceinline__ int64_t ntc_selections(const RunDev &R, int64_t N, real gm, real &rem, int32_t *err) {
+  const real npairs = (real)0.5 * (real)(N * (N - 1));
+  const real M = npairs * (real)R.coef * gm + rem;
+  int64_t nsel = 0;
+  if (M >= (real)0 && M < (real)kMaxSelections) {
+    const real fl = floor(M);
+    nsel = (int64_t)fl;
+    rem = M - fl;
+  } else {  // non-finite velocities or an absurd rate: stop, report
+    set_error(err, kErrNumeric);
+    rem = (real)0;
+  }
+  return N < 2 ? 0 : nsel;
+}
+
+// Sums of one cell (sequential order, one lane).
 template <typename real>
 __device__ __forceinline__ void sample_cell(const real *u, const real *v, const real *w, int64_t N, double *out) {
   double s[kFields] = {0, 0, 0, 0, 0, 0, 0};
@@ -697,61 +952,375 @@ __device__ __forceinline__ void sample_cell(const real *u, const real *v, const 
   for (int f = 0; f < kFields; ++f) out[f] = s[f];
 }
 
+// Sums of one cell by a whole wave (strided partial sums, butterfly reduce).
 template <typename real>
-__global__ __launch_bounds__(256) void k_collide(DevPtrs<real> d, int buf, int64_t n_cells) {
-  const int64_t gc = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (gc >= n_cells) return;
-  const RunDev &R = d.runs[d.cgroup_run[gc >> 6]];
-  const int32_t c = (int32_t)(gc - R.co);
-  if (c >= R.nc) return;
-  const int64_t b = d.bin_start[R.bo + c];
-  const int64_t N = (int64_t)d.bin_start[R.bo + c + 1] - b;
-  const Particles<real> P = d.P[buf];
-  real *u = P.u + R.so + b, *v = P.v + R.so + b, *w = P.w + R.so + b;
+__device__ __forceinline__ void sample_cell_wave(const real *u, const real *v, const real *w, int64_t N,
+                                                 double *out) {
+  const int lane = threadIdx.x & 63;
+  double s[kFields] = {0, 0, 0, 0, 0, 0, 0};
+  for (int64_t k = lane; k < N; k += kWave) {
+    const double a = (double)u[k], b = (double)v[k], c = (double)w[k];
+    s[0] += 1.0;
+    s[1] += a;
+    s[2] += b;
+    s[3] += c;
+    s[4] += a * a;
+    s[5] += b * b;
+    s[6] += c * c;
+  }
+#pragma unroll
+  for (int f = 0; f < kFields; ++f) {
+    double x = s[f];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    s[f] = x;
+  }
+  if (lane == 0)
+#pragma unroll
+    for (int f = 0; f < kFields; ++f) out[f] = s[f];
+}
+
+// Gather particles [b, b+n) of a run (sorted positions) through LCR: positions
+// to P', velocities to LDS (or to P' when to_lds is false).
+template <typename real, int DIM>
+__device__ __forceinline__ void gather_through_lcr(const RunDev &R, const int32_t *lcr, const Particles<real> &A,
+                                                   const Particles<real> &B, int64_t b, int64_t n, bool to_lds,
+                                                   real *su, real *sv, real *sw) {
+  const int lane = threadIdx.x & 63;
+  constexpr int U = 4;
+  for (int64_t k0 = 0; k0 < n; k0 += U * kWave) {
+    int64_t src[U];
+    bool ok[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int64_t k = k0 + q * kWave + lane;
+      ok[q] = k < n;
+      src[q] = ok[q] ? R.so + lcr[R.so + b + k] : R.so;
+    }
+    real x[U], y[U], z[U], uu[U], vv[U], ww[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      if (ok[q]) {
+        x[q] = A.x[src[q]];
+        y[q] = A.y[src[q]];
+        if (DIM == 3) z[q] = A.z[src[q]];
+        uu[q] = A.u[src[q]];
+        vv[q] = A.v[src[q]];
+        ww[q] = A.w[src[q]];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      if (!ok[q]) continue;
+      const int64_t k = k0 + q * kWave + lane;
+      const int64_t dst = R.so + b + k;
+      B.x[dst] = x[q];
+      B.y[dst] = y[q];
+      if (DIM == 3) B.z[dst] = z[q];
+      if (to_lds) {
+        su[k] = uu[q];
+        sv[k] = vv[q];
+        sw[k] = ww[q];
+      } else {
+        B.u[dst] = uu[q];
+        B.v[dst] = vv[q];
+        B.w[dst] = ww[q];
+      }
+    }
+  }
+}
+
+template <typename real>
+__device__ __forceinline__ void store_velocities(const RunDev &R, const Particles<real> &B, int64_t b, int64_t n,
+                                                 const real *su, const real *sv, const real *sw) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t k = lane; k < n; k += kWave) {
+    const int64_t dst = R.so + b + k;
+    B.u[dst] = su[k];
+    B.v[dst] = sv[k];
+    B.w[dst] = sw[k];
+  }
+}
+
+__device__ __forceinline__ void global_sync_wave() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <typename real, int DIM>
+__global__ __launch_bounds__(kCollideWaves * 64) void k_collide(DevPtrs<real> d, int src, int64_t n_items) {
+  extern __shared__ __align__(16) unsigned char lds_bytes[];
+  constexpr int CAP = CollideCap<real>::value;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t item = xcd_block(blockIdx.x, gridDim.x) * kCollideWaves + wave;
+  if (item >= n_items) return;
+  const int2 it = d.items[item];
+  const RunDev &R = d.runs[it.x];
+  const int32_t c0 = it.y;
+  const int32_t ncell = min(R.lane_cells, R.nc - c0);
+  real *su = (real *)(lds_bytes + wave * collide_wave_bytes<real>());
+  real *sv = su + CAP, *sw = sv + CAP;
+  int32_t *own = (int32_t *)(sw + CAP);
+  const Particles<real> A = d.P[src], B = d.P[1 - src];
+  const int64_t b0 = d.bin_start[R.bo + c0];
+  const int64_t n = (int64_t)d.bin_start[R.bo + c0 + ncell] - b0;
+  const bool in_lds = n <= CAP;
+  gather_through_lcr<real, DIM>(R, d.lcr, A, B, b0, n, in_lds, su, sv, sw);
+  if (in_lds) wave_sync();
+  else global_sync_wave();
   const uint32_t step = *d.step;
-  real gm = d.gmax[gc];
-  real rem = d.rem_c[gc];
-  const real npairs = (real)0.5 * (real)(N * (N - 1));
-  const real M = npairs * (real)R.coef * gm + rem;
-  int64_t nsel = 0;
-  if (M >= (real)0 && M < (real)kMaxSelections) {
-    const real fl = floor(M);
-    nsel = (int64_t)fl;
-    rem = M - fl;
-  } else {  // non-finite velocities or an absurd rate: stop, report
-    set_error(d.err, kErrNumeric);
-    rem = (real)0;
+  const bool sample = *d.sample_slot >= 0;
+  // one lane per cell
+  if (lane < ncell) {
+    const int32_t c = c0 + lane;
+    const int64_t gc = R.co + c;
+    const int64_t cb = (int64_t)d.bin_start[R.bo + c] - b0;
+    const int64_t N = (int64_t)d.bin_start[R.bo + c + 1] - b0 - cb;
+    real *u = in_lds ? su + cb : B.u + R.so + b0 + cb;
+    real *v = in_lds ? sv + cb : B.v + R.so + b0 + cb;
+    real *w = in_lds ? sw + cb : B.w + R.so + b0 + cb;
+    real gm = d.gmax[gc], rem = d.rem_c[gc];
+    const int64_t nsel = ntc_selections<real>(R, N, gm, rem, d.err);
+    const uint32_t ncol = chain_serial<real>(R, step, (uint32_t)c, (uint32_t)N, 0, nsel, u, v, w, gm);
+    d.gmax[gc] = gm;
+    d.rem_c[gc] = rem;
+    d.ncoll[gc] += ncol;
+    if (sample) sample_cell(u, v, w, N, d.stage + gc * kFields);
   }
-  if (N < 2) nsel = 0;
+  if (in_lds) {
+    wave_sync();
+    store_velocities<real>(R, B, b0, n, su, sv, sw);
+  }
+}
+
+// One cell per 256-thread block (crowded cells): the gather, the write-back
+// and the sampling use all 256 threads.  Selections run 256 at a time: thread
+// k draws selection w0 + k; among the pending selections touching a
+// particle, the lowest-numbered one owns it (LDS atomicMin), and a selection
+// owning both its particles runs now.  So every selection runs after all
+// earlier ones sharing a particle with it and sees exactly the velocities of
+// the sequential order.  The window assumes (sigma c_r)_max stays put; if
+// some g exceeds it, the selections from the first such one (ks) on are undone
+// in reverse order of execution, ks is applied with the raised maximum, and
+// the window restarts at ks + 1.
+template <typename real>
+struct BlockScratch {
+  double red[4][kFields];
+  int32_t ks;
+  uint32_t ncol;
+  real gm;
+};
+
+template <typename real>
+constexpr int collide_cell_bytes() {
+  return ((CollideCap<real>::value * (3 * (int)sizeof(real) + 4)) + 15) & ~15;
+}
+
+template <typename real>
+__device__ uint32_t chain_block(const RunDev &R, uint32_t step, uint32_t c, uint32_t N, int64_t nsel, real *u,
+                                real *v, real *w, int32_t *own, BlockScratch<real> &sh, real &gm) {
+  const int tid = threadIdx.x;
   uint32_t ncol = 0;
-  for (int64_t k = 0; k < nsel; ++k) {
-    const uint4 b0 = philox(make_uint4(step, kColl, (uint32_t)c, (uint32_t)(2 * k)), R.key0, R.key1);
-    const uint4 b1 = philox(make_uint4(step, kColl, (uint32_t)c, (uint32_t)(2 * k + 1)), R.key0, R.key1);
-    const uint32_t i = __umulhi(b0.x, (uint32_t)N);
-    const uint32_t jp = __umulhi(b0.y, (uint32_t)(N - 1));
-    const uint32_t j = jp + (jp >= i ? 1u : 0u);
-    const real du = u[i] - u[j], dv = v[i] - v[j], dw = w[i] - w[j];
-    const real cr = sqrt(du * du + dv * dv + dw * dw);
-    const real g = g_of<real>(R, cr);
-    if (g > gm) gm = g;
-    if (!(u01<real>(b0.z, b0.w) < g / gm)) continue;
-    const real cosx = (real)2 * u01<real>(b1.x, b1.y) - (real)1;
-    const real sinx = sqrt((real)1 - cosx * cosx);
-    const real eps = two_pi<real>() * u01<real>(b1.z, b1.w);
-    const real rx = cr * cosx, ry = cr * sinx * cos(eps), rz = cr * sinx * sin(eps);
-    const real mx = (real)0.5 * (u[i] + u[j]), my = (real)0.5 * (v[i] + v[j]), mz = (real)0.5 * (w[i] + w[j]);
-    u[i] = mx + (real)0.5 * rx;
-    v[i] = my + (real)0.5 * ry;
-    w[i] = mz + (real)0.5 * rz;
-    u[j] = mx - (real)0.5 * rx;
-    v[j] = my - (real)0.5 * ry;
-    w[j] = mz - (real)0.5 * rz;
-    ncol++;
+  int64_t w0 = 0;
+  while (w0 < nsel) {
+    const bool act = w0 + tid < nsel;
+    Selection<real> s{0u, 0u, (real)0, (real)0, (real)0};
+    if (act) s = draw_selection<real>(R, step, c, w0 + tid, N);
+    bool pending = act, accepted = false;
+    int my_round = -1;
+    real g = (real)0;
+    real bu_i = 0, bv_i = 0, bw_i = 0, bu_j = 0, bv_j = 0, bw_j = 0;
+    int rounds = 0;
+    while (__syncthreads_or(pending)) {
+      if (pending) {
+        own[s.i] = 0x7fffffff;
+        own[s.j] = 0x7fffffff;
+      }
+      __syncthreads();
+      if (pending) {
+        atomicMin(&own[s.i], tid);
+        atomicMin(&own[s.j], tid);
+      }
+      __syncthreads();
+      const bool ready = pending && own[s.i] == tid && own[s.j] == tid;
+      __syncthreads();
+      if (ready) {
+        real ui = u[s.i], vi = v[s.i], wi = w[s.i], uj = u[s.j], vj = v[s.j], wj = w[s.j];
+        bu_i = ui; bv_i = vi; bw_i = wi; bu_j = uj; bv_j = vj; bw_j = wj;
+        const real du = ui - uj, dv = vi - vj, dw = wi - wj;
+        const real cr = sqrt(du * du + dv * dv + dw * dw);
+        g = g_of<real>(R, cr);
+        accepted = s.ua < g / gm;
+        if (accepted) {
+          scatter_pair(cr, s.uc, s.ue, ui, vi, wi, uj, vj, wj);
+          u[s.i] = ui; v[s.i] = vi; w[s.i] = wi;
+          u[s.j] = uj; v[s.j] = vj; w[s.j] = wj;
+        }
+        my_round = rounds;
+        pending = false;
+      }
+      ++rounds;
+    }
+    if (tid == 0) sh.ks = 0x7fffffff;
+    __syncthreads();
+    if (act && g > gm) atomicMin(&sh.ks, tid);
+    __syncthreads();
+    const int ks = sh.ks;
+    if (ks == 0x7fffffff) {
+      ncol += __syncthreads_count(accepted);
+      w0 += 256;
+      continue;
+    }
+    // undo selections ks.. in reverse order of execution
+    for (int r = rounds - 1; r >= 0; --r) {
+      if (act && tid >= ks && my_round == r && accepted) {
+        u[s.i] = bu_i; v[s.i] = bv_i; w[s.i] = bw_i;
+        u[s.j] = bu_j; v[s.j] = bv_j; w[s.j] = bw_j;
+      }
+      __syncthreads();
+    }
+    ncol += __syncthreads_count(accepted && tid < ks);
+    // selection ks raises (sigma c_r)_max to its own g, so it is accepted
+    // (U < g/g = 1); it ran on exactly its sequential inputs, so apply it again
+    // from the restored state and restart the window right after it
+    if (tid == ks) {
+      real ui = u[s.i], vi = v[s.i], wi = w[s.i], uj = u[s.j], vj = v[s.j], wj = w[s.j];
+      const real du = ui - uj, dv = vi - vj, dw = wi - wj;
+      const real cr = sqrt(du * du + dv * dv + dw * dw);
+      const real gg = g_of<real>(R, cr);
+      const real gnew = gg > gm ? gg : gm;
+      const bool acc = s.ua < gg / gnew;
+      if (acc) {
+        scatter_pair(cr, s.uc, s.ue, ui, vi, wi, uj, vj, wj);
+        u[s.i] = ui; v[s.i] = vi; w[s.i] = wi;
+        u[s.j] = uj; v[s.j] = vj; w[s.j] = wj;
+      }
+      sh.gm = gnew;
+      sh.ncol = acc ? 1u : 0u;
+    }
+    __syncthreads();
+    gm = sh.gm;
+    ncol += sh.ncol;
+    w0 += ks + 1;
+    __syncthreads();
   }
-  d.gmax[gc] = gm;
-  d.rem_c[gc] = rem;
-  d.ncoll[gc] += ncol;
-  if (*d.sample_slot >= 0) sample_cell(u, v, w, N, d.stage + gc * kFields);
+  return ncol;
+}
+
+template <typename real, int DIM>
+__global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, int64_t n_items) {
+  extern __shared__ __align__(16) unsigned char lds_bytes[];
+  __shared__ BlockScratch<real> sh;
+  constexpr int CAP = CollideCap<real>::value;
+  const int tid = threadIdx.x;
+  const int64_t item = xcd_block(blockIdx.x, gridDim.x);
+  if (item >= n_items) return;
+  const int2 it = d.cell_items[item];
+  const RunDev &R = d.runs[it.x];
+  const int32_t c = it.y;
+  const int64_t gc = R.co + c;
+  real *su = (real *)lds_bytes;
+  real *sv = su + CAP, *sw = sv + CAP;
+  int32_t *own = (int32_t *)(sw + CAP);
+  const Particles<real> A = d.P[src], B = d.P[1 - src];
+  const int64_t b0 = d.bin_start[R.bo + c];
+  const int64_t n = (int64_t)d.bin_start[R.bo + c + 1] - b0;
+  const bool in_lds = n <= CAP;
+  // gather through LCR: positions to P', velocities to LDS (or P')
+  {
+    constexpr int U = 4;
+    for (int64_t k0 = 0; k0 < n; k0 += U * 256) {
+      int64_t sidx[U];
+      bool ok[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int64_t k = k0 + q * 256 + tid;
+        ok[q] = k < n;
+        sidx[q] = ok[q] ? R.so + d.lcr[R.so + b0 + k] : R.so;
+      }
+      real x[U], y[U], z[U], uu[U], vv[U], ww[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        if (ok[q]) {
+          x[q] = A.x[sidx[q]];
+          y[q] = A.y[sidx[q]];
+          if (DIM == 3) z[q] = A.z[sidx[q]];
+          uu[q] = A.u[sidx[q]];
+          vv[q] = A.v[sidx[q]];
+          ww[q] = A.w[sidx[q]];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        if (!ok[q]) continue;
+        const int64_t k = k0 + q * 256 + tid;
+        const int64_t dst = R.so + b0 + k;
+        B.x[dst] = x[q];
+        B.y[dst] = y[q];
+        if (DIM == 3) B.z[dst] = z[q];
+        if (in_lds) {
+          su[k] = uu[q];
+          sv[k] = vv[q];
+          sw[k] = ww[q];
+        } else {
+          B.u[dst] = uu[q];
+          B.v[dst] = vv[q];
+          B.w[dst] = ww[q];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t step = *d.step;
+  real gm = d.gmax[gc], rem = d.rem_c[gc];
+  const int64_t nsel = ntc_selections<real>(R, n, gm, rem, d.err);
+  real *u = in_lds ? su : B.u + R.so + b0;
+  real *v = in_lds ? sv : B.v + R.so + b0;
+  real *w = in_lds ? sw : B.w + R.so + b0;
+  uint32_t ncol = 0;
+  if (in_lds) {
+    ncol = chain_block<real>(R, step, (uint32_t)c, (uint32_t)n, nsel, su, sv, sw, own, sh, gm);
+  } else {
+    if (tid == 0) {
+      ncol = chain_serial<real>(R, step, (uint32_t)c, (uint32_t)n, 0, nsel, u, v, w, gm);
+      sh.gm = gm;
+    }
+    __syncthreads();
+    gm = sh.gm;
+  }
+  __syncthreads();
+  if (in_lds)
+    for (int64_t k = tid; k < n; k += 256) {
+      const int64_t dst = R.so + b0 + k;
+      B.u[dst] = su[k];
+      B.v[dst] = sv[k];
+      B.w[dst] = sw[k];
+    }
+  if (*d.sample_slot >= 0) {
+    double sm[kFields] = {0, 0, 0, 0, 0, 0, 0};
+    for (int64_t k = tid; k < n; k += 256) {
+      const double a = (double)u[k], b = (double)v[k], e = (double)w[k];
+      sm[0] += 1.0;
+      sm[1] += a;
+      sm[2] += b;
+      sm[3] += e;
+      sm[4] += a * a;
+      sm[5] += b * b;
+      sm[6] += e * e;
+    }
+#pragma unroll
+    for (int f = 0; f < kFields; ++f) {
+      double x = sm[f];
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+      if ((tid & 63) == 0) sh.red[tid >> 6][f] = x;
+    }
+    __syncthreads();
+    if (tid < kFields) d.stage[gc * kFields + tid] = ((sh.red[0][tid] + sh.red[1][tid]) + sh.red[2][tid]) + sh.red[3][tid];
+  }
+  if (tid == 0) {
+    d.gmax[gc] = gm;
+    d.rem_c[gc] = rem;
+    d.ncoll[gc] += ncol;
+  }
 }
 
 template <typename real>
@@ -902,8 +1471,7 @@ static void index_pass(IndexArgs a, int max_digits, int n_runs, int pass, const 
   const int wblocks = (a.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
   TIMED(kKColScan, hipLaunchKernelGGL(k_colscan, dim3((max_digits + 255) / 256, n_runs), dim3(256), 0, s, a));
   TIMED(kKDigScan, hipLaunchKernelGGL(k_digscan, dim3(n_runs), dim3(256), 0, s, a));
-  TIMED(kKScatter, hipLaunchKernelGGL(k_scatter, dim3(wblocks), dim3(256), lds, s, a,
-                                      a.single ? digit_bits(max_digits) : kDigitBits));
+  TIMED(kKScatter, hipLaunchKernelGGL(k_scatter, dim3(wblocks), dim3(256), lds, s, a));
 }
 
 template <typename real>
@@ -938,10 +1506,14 @@ static void step_dim(const Geometry &g, const DevPtrs<real> &d, int buf, hipStre
   if (g.npass == 1) {
     TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, true>), dim3(wblocks), dim3(256), lds, s, d, buf,
                                        g.n_tiles, g.tile, g.dstride));
+    TIMED(kKMotionWalls, hipLaunchKernelGGL((k_motion_walls<real, DIM, true>), dim3(g.n_tiles), dim3(256), 0, s,
+                                            d, buf, g.n_tiles, g.tile));
     index_pass(a, g.max_nc + 1, g.n_runs, 0, nullptr, d.lcr, s, prof);
   } else {
     TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, false>), dim3(wblocks), dim3(256), lds, s, d, buf,
                                        g.n_tiles, g.tile, g.dstride));
+    TIMED(kKMotionWalls, hipLaunchKernelGGL((k_motion_walls<real, DIM, false>), dim3(g.n_tiles), dim3(256), 0, s,
+                                            d, buf, g.n_tiles, g.tile));
     const int32_t *in = nullptr;
     for (int p = 0; p < g.npass; ++p) {
       int32_t *out = ((g.npass - 1 - p) % 2 == 0) ? d.lcr : d.lcr_tmp;
@@ -958,10 +1530,14 @@ static void step_dim(const Geometry &g, const DevPtrs<real> &d, int buf, hipStre
     TIMED(kKBinFinalize,
           hipLaunchKernelGGL(k_bin_finalize, dim3((g.n_runs + 255) / 256), dim3(256), 0, s, a, g.n_runs, 1));
   }
-  TIMED(kKPermute, hipLaunchKernelGGL((k_permute<real, DIM>), dim3(grid_for(g.n_slots)), dim3(256), 0, s, d, buf,
-                                      g.n_slots, g.tile));
-  TIMED(kKCollide, hipLaunchKernelGGL(k_collide<real>, dim3((unsigned)((g.n_cells + 255) / 256)), dim3(256), 0, s,
-                                      d, 1 - buf, g.n_cells));
+  if (g.n_items > 0) {
+    const int64_t nblk = (g.n_items + kCollideWaves - 1) / kCollideWaves;
+    TIMED(kKCollide, hipLaunchKernelGGL((k_collide<real, DIM>), dim3((unsigned)nblk), dim3(kCollideWaves * 64),
+                                        (size_t)kCollideWaves * collide_wave_bytes<real>(), s, d, buf, g.n_items));
+  }
+  if (g.n_cell_items > 0)
+    TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_cell<real, DIM>), dim3((unsigned)g.n_cell_items), dim3(256),
+                                            (size_t)collide_cell_bytes<real>(), s, d, buf, g.n_cell_items));
   if (g.n_samples > 0)
     TIMED(kKAccumulate, hipLaunchKernelGGL(k_accumulate<real>, dim3(grid_for(g.acc_stride)), dim3(256), 0, s, d,
                                            -1, g.acc_stride, g.n_eg));

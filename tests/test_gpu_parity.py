@@ -35,12 +35,16 @@ def _compare_run(E, r, O, rs, where):
     np.testing.assert_allclose(cg["rem"], co["rem"], rtol=0, atol=TOL, err_msg=where)
 
 
-def _parity(dsmc_gpu, oracle_lib, runs, n_steps, check_every=1):
-    E = dsmc_gpu.Ensemble(runs, sample_steps=[n_steps], state_fp64=True, n_groups=len(runs))
+def _parity(dsmc_gpu, oracle_lib, runs, n_steps, check_every=1, squeeze=None, **kw):
+    E = dsmc_gpu.Ensemble(runs, sample_steps=[n_steps], state_fp64=True, n_groups=len(runs), **kw)
     O = [oracle_lib.OracleRun(r) for r in runs]
     for r, rs in enumerate(runs):
         g, o = E.state(r), O[r].state()
         np.testing.assert_allclose(g, o, rtol=0, atol=1e-13)
+        if squeeze is not None:      # same crowded initial state on both sides
+            o[1] *= squeeze
+            O[r].set_state(o)
+            E.set_state(r, o)
     for s in range(1, n_steps + 1):
         E.step(1)
         for o in O:
@@ -106,3 +110,32 @@ def test_uneven_runs_fp64(dsmc_gpu, oracle_lib):
             _compare_run(E, r, O[r], rs, f"run {r} step {s}")
     for r in range(3):
         np.testing.assert_allclose(E.accum(0, ensemble=r)[0], O[r].sample(), rtol=TOL, atol=TOL)
+
+
+def test_dense_cells_one_wave_per_cell_fp64(dsmc_gpu, oracle_lib):
+    """~390 particles per cell: one wavefront per cell, 64 selections per
+    window in conflict-free levels; the first steps exceed (sigma c_r)_max
+    often, so windows are undone and replayed."""
+    wl = W.box(100_000, 2, 5, 5, seed=15, grid=(16, 16))
+    O = _parity(dsmc_gpu, oracle_lib, wl.runs, 5)
+    assert O[0].info()["ncoll"] > 5000
+
+
+def test_sparse_cells_forced_wave_mode_fp64(dsmc_gpu, oracle_lib):
+    _parity(dsmc_gpu, oracle_lib, W.plain_box().runs, 4, collide_mode=2)
+
+
+def test_dense_cells_forced_lane_mode_fp64(dsmc_gpu, oracle_lib):
+    wl = W.box(60_000, 1, 3, 3, seed=16, grid=(16, 16))
+    _parity(dsmc_gpu, oracle_lib, wl.runs, 3, collide_mode=1)
+
+
+def test_cells_beyond_lds_capacity_fp64(dsmc_gpu, oracle_lib):
+    """A cell (wave mode) and a 64-cell group (lane mode) holding more
+    particles than the LDS stage: the global-memory fallbacks."""
+    big_cell = W.box(20_000, 1, 3, 3, seed=17, grid=(4, 4)).runs      # 1250 per cell
+    _parity(dsmc_gpu, oracle_lib, big_cell, 3)
+    # 31 per cell on average, but every particle starts in the bottom rows:
+    # the first lane-mode group holds all 2000
+    big_group = W.box(2_000, 1, 3, 3, seed=18, grid=(8, 8)).runs
+    _parity(dsmc_gpu, oracle_lib, big_group, 3, squeeze=0.2)
