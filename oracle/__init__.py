@@ -89,6 +89,7 @@ def lib():
         L.or_get_cells.argtypes = [P, P, P, P, P]
         L.or_get_cell_state.argtypes = [P, P, P, P]
         L.or_get_face_rem.argtypes = [P, dp]
+        L.or_set_cell_state.argtypes = [P, dp, dp]
         L.or_counting_sort.argtypes = [P, C.c_int64, C.c_int64, P, P, P]
         L.or_collide_cell.argtypes = [C.POINTER(OrSpec), C.c_uint32, C.c_uint32, C.c_int64,
                                       dp, dp, dp, dp, dp, P, C.c_int64, C.POINTER(C.c_int64)]
@@ -245,6 +246,12 @@ class OracleRun:
         rem = np.zeros(self.nc); gmax = np.zeros(self.nc); ncoll = np.zeros(self.nc, np.int64)
         lib().or_get_cell_state(self._h, rem.ctypes.data, gmax.ctypes.data, ncoll.ctypes.data)
         return {"rem": rem, "gmax": gmax, "ncoll": ncoll}
+
+    def set_cell_state(self, rem: np.ndarray, gmax: np.ndarray):
+        rem = np.ascontiguousarray(rem, dtype=np.float64)
+        gmax = np.ascontiguousarray(gmax, dtype=np.float64)
+        assert rem.size == self.nc and gmax.size == self.nc
+        lib().or_set_cell_state(self._h, _dp(rem), _dp(gmax))
 
     def face_rem(self) -> np.ndarray:
         nf = self.info()["nface"]

@@ -631,6 +631,12 @@ void or_get_cell_state(const or_run *R, double *rem, double *gmax, int64_t *ncol
     if (ncoll) memcpy(ncoll, R->ncoll, (size_t)R->nc * sizeof(int64_t));
 }
 
+void or_set_cell_state(or_run *R, const double *rem, const double *gmax)
+{
+    if (rem) memcpy(R->rem_c, rem, (size_t)R->nc * sizeof(double));
+    if (gmax) memcpy(R->gmax, gmax, (size_t)R->nc * sizeof(double));
+}
+
 void or_get_face_rem(const or_run *R, double *rem)
 {
     memcpy(rem, R->rem_f, (size_t)R->nface * sizeof(double));

@@ -149,6 +149,7 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
     const int64_t cap = std::max<int64_t>(g.tile, round_up(s.capacity, g.tile));
     R.so = so;
     R.cap = cap;
+    R.cap_spec = s.capacity;
     R.nc = s.nx * s.ny * s.nz;
     R.nx = s.nx;
     R.ny = s.ny;

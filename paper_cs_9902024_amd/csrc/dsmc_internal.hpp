@@ -32,6 +32,7 @@ constexpr double kMaxSelections = 1e9;  // per cell per step; more means non-fin
 struct RunDev {
   int64_t so;        // first particle slot of the run
   int64_t cap;       // slots reserved (multiple of the tile)
+  int64_t cap_spec;  // particle capacity the caller asked for (<= cap)
   int64_t co;        // first cell of the run in the global cell arrays (64-aligned)
   int64_t bo;        // first entry of the run in the bin-start array (nc + 2 entries)
   int64_t mo;        // first entry of the run in the tile histogram matrix

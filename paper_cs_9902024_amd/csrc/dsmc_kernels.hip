@@ -274,7 +274,7 @@ __global__ __launch_bounds__(256) void k_gen_emit(DevPtrs<real> d, int buf) {
   }
   const int64_t total = s_part[0];
   const int64_t n0 = s_n0;
-  const bool ok = n0 + total <= R.cap;
+  const bool ok = n0 + total <= R.cap_spec;
   __syncthreads();
   if (!ok) {
     if (tid == 0) {

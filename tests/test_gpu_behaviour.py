@@ -1,0 +1,122 @@
+"""Behaviour of the batched GPU path: bitwise determinism, independence of a
+run from the rest of its batch (runs are the paper's statistically
+independent runs, Sec. 1.3), HIP-graph replay equal to eager launches, and
+device-side error reporting through the C ABI."""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_channel_runs(n, seed=31):
+    return [replace(W.channel_run(nx=64, ny=16, lx=4.0, ly=1.0, ppc_inf=30.0, run_id=r, seed=seed),
+                    n_init=8000, init_U=(2.5, 0.0, 0.0))
+            for r in range(n)]
+
+
+def test_bitwise_determinism_fp32(dsmc_gpu):
+    runs = _small_channel_runs(6)
+    A = dsmc_gpu.Ensemble(runs, [5, 10], state_fp64=False, n_groups=3)
+    B = dsmc_gpu.Ensemble(runs, [5, 10], state_fp64=False, n_groups=3)
+    A.step(10)
+    B.step(10)
+    for r in range(6):
+        np.testing.assert_array_equal(A.state(r), B.state(r))
+    np.testing.assert_array_equal(A.accum(1), B.accum(1))
+
+
+def test_run_does_not_depend_on_its_batch(dsmc_gpu):
+    """A run advanced alone and inside a batch of other runs (other grids,
+    other sizes) follows the identical trajectory."""
+    runs = _small_channel_runs(3)
+    other = replace(W.box(30_000, 1, 1, 1, seed=9, grid=(20, 10)).runs[0], run_id=99, ensemble=7)
+    alone = dsmc_gpu.Ensemble([runs[1]], [8], state_fp64=False)
+    batch = dsmc_gpu.Ensemble([runs[0], other, runs[1], runs[2]], [8], state_fp64=False)
+    alone.step(8)
+    batch.step(8)
+    np.testing.assert_array_equal(alone.state(0), batch.state(2))
+    np.testing.assert_array_equal(alone.cell_state(0)["ncoll"], batch.cell_state(2)["ncoll"])
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_graph_replay_equals_eager(dsmc_gpu, fp64):
+    """Every replay of the captured step graph (two graphs: even and odd
+    steps) gives the state the eager launch sequence gives."""
+    import torch
+    runs = _small_channel_runs(4)
+    E = dsmc_gpu.Ensemble(runs, [3, 6, 9], state_fp64=fp64, n_groups=2, use_graph=False)
+    G = dsmc_gpu.Ensemble(runs, [3, 6, 9], state_fp64=fp64, n_groups=2, use_graph=True)
+    for s in range(9):
+        E.step(1)
+        G.step(1)
+        torch.cuda.synchronize()
+        for r in range(4):
+            np.testing.assert_array_equal(E.state(r), G.state(r), err_msg=f"step {s + 1}")
+    for k in range(3):
+        np.testing.assert_array_equal(E.accum(k), G.accum(k))
+        m1, _ = E.moments(k)
+        m2, _ = G.moments(k)
+        np.testing.assert_array_equal(m1, m2)
+
+
+def test_capacity_overflow_is_reported(dsmc_gpu):
+    rs = replace(W.channel_run(nx=32, ny=8, lx=2.0, ly=0.5, ppc_inf=40.0, seed=3), capacity=2000)
+    E = dsmc_gpu.Ensemble([rs], [], state_fp64=False)
+    E.step(50)          # enqueues fine; the device latches the overflow
+    with pytest.raises(dsmc_gpu.DsmcError) as e:
+        E.sync()
+    assert e.value.status == -3
+    with pytest.raises(dsmc_gpu.DsmcError) as e:
+        E.step(1)
+    assert e.value.status == -3
+    assert "slots" in dsmc_gpu.dsmc_last_error(E.ctx)
+
+
+def test_argument_errors(dsmc_gpu):
+    E = dsmc_gpu.Ensemble(W.plain_box().runs, [2], state_fp64=True)
+    with pytest.raises(dsmc_gpu.DsmcError) as e:
+        E.sample(0)                  # no step yet: state not cell-sorted
+    assert e.value.status == -5
+    with pytest.raises(dsmc_gpu.DsmcError) as e:
+        E.sample(3)
+    assert e.value.status == -1
+    with pytest.raises(dsmc_gpu.DsmcError) as e:
+        dsmc_gpu.dsmc_read_moments(E.ctx, 0, 12345, 1024)
+    assert e.value.status == -1
+    E.step(2)
+    m, se = E.moments(0)
+    assert abs(np.nansum(m[:, 0]) - 20_000) < 1e-9
+    assert np.all(np.isnan(se))      # one group: no batch-means error
+
+
+def test_manual_sample_equals_scheduled_sample(dsmc_gpu):
+    runs = _small_channel_runs(2)
+    A = dsmc_gpu.Ensemble(runs, [4], state_fp64=True, n_groups=2)
+    B = dsmc_gpu.Ensemble(runs, [-1], state_fp64=True, n_groups=2)
+    A.step(4)
+    B.step(4)
+    B.sample(0)
+    np.testing.assert_allclose(A.accum(0), B.accum(0), rtol=1e-13, atol=1e-13)
+
+
+def test_fp32_tracks_fp64_statistically(dsmc_gpu):
+    """Same Philox streams, FP32 vs FP64 state: the trajectories separate
+    (chaos), but conserved totals and collision rates agree."""
+    wl = W.box(20_000, 8, 30, 30, seed=41)
+    E32 = dsmc_gpu.Ensemble(wl.runs, [30], state_fp64=False, n_groups=8)
+    E64 = dsmc_gpu.Ensemble(wl.runs, [30], state_fp64=True, n_groups=8)
+    e0 = [float((E64.state(r)[3:] ** 2).sum()) for r in range(8)]
+    E32.step(30)
+    E64.step(30)
+    for r in range(8):
+        s32, s64 = E32.state(r), E64.state(r)
+        assert s32.shape == s64.shape == (6, 20_000)
+        assert abs((s32[3:] ** 2).sum() - e0[r]) < 1e-4 * e0[r]
+        assert abs((s64[3:] ** 2).sum() - e0[r]) < 1e-12 * e0[r]
+    n32 = sum(int(E32.cell_state(r)["ncoll"].sum()) for r in range(8))
+    n64 = sum(int(E64.cell_state(r)["ncoll"].sum()) for r in range(8))
+    assert abs(n32 - n64) < 5 * np.sqrt(n64)

@@ -315,6 +315,8 @@ def random_cells(n: int, n_bins: int, seed: int, near_sorted: bool = False,
     entries get the DEAD bin ``n_bins - 1``."""
     rng = np.random.default_rng(seed)
     live = n_bins - 1
+    if live < 1:
+        return np.zeros(n, np.int32)
     if near_sorted:
         c = np.sort(rng.integers(0, live, size=n))
         c = np.clip(c + rng.integers(-jump, jump + 1, size=n), 0, live - 1)
