@@ -53,6 +53,28 @@ def algorithmic_bytes(kind: str, n_particles: int, n_cells: int, dim: int, es: i
     return 0.0
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ensemble_box_512x1M_fp32_traffic.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_cs_9902024_amd", "csrc", "dsmc_kernels.hip")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of ``kernel`` from the committed FETCH_SIZE /
+    WRITE_SIZE summary (scaled by the copy-kernel calibration), or None when
+    there is none or the kernel source changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    found, ok = None, False
+    for line in open(TRAFFIC_FILE):
+        f = line.split()
+        if len(f) == 3 and f[0] == "traffic" and f[1] == kernel:
+            found = float(f[2])
+        if len(f) == 2 and f[0] == "source_sha256":
+            ok = f[1] == sha
+    return found if ok else None
+
+
 def copy_calibration(nbytes: int = 1 << 31):
     """A plain device-to-device copy of known size (torch's copy kernel):
     the streaming bandwidth this GPU delivers, and the reference kernel whose
@@ -122,7 +144,7 @@ def run_gpu(args):
     if ab > 0:
         ach = ab / (kernels[dom]["ms_avg"] * 1e-3) / 1e9
         rl = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-              "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+              "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom), "kernel": dom,
               "algorithmic_bytes_per_launch": ab, "avg_launch_ms": kernels[dom]["ms_avg"]}
     for k, v in kernels.items():
         b = algorithmic_bytes(k, n0, n_runs * nc, 2, 4)
