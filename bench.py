@@ -57,22 +57,25 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ensemble_box_512x1M_fp32_traffic.
 KERNEL_SRC = os.path.join(ROOT, "paper_cs_9902024_amd", "csrc", "dsmc_kernels.hip")
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, lanes: int):
     """HBM bytes per launch of ``kernel`` from the committed FETCH_SIZE /
     WRITE_SIZE summary (scaled by the copy-kernel calibration), or None when
-    there is none or the kernel source changed since the counters were taken."""
+    there is none, the kernel source changed since the counters were taken,
+    or the counters were taken with another split of the batch into lanes."""
     import hashlib
     if not os.path.exists(TRAFFIC_FILE):
         return None
     sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-    found, ok = None, False
+    found, ok, same_lanes = None, False, False
     for line in open(TRAFFIC_FILE):
         f = line.split()
         if len(f) == 3 and f[0] == "traffic" and f[1] == kernel:
             found = float(f[2])
         if len(f) == 2 and f[0] == "source_sha256":
             ok = f[1] == sha
-    return found if ok else None
+        if len(f) == 2 and f[0] == "lanes":
+            same_lanes = int(f[1]) == lanes
+    return found if ok and same_lanes else None
 
 
 def copy_calibration(nbytes: int = 1 << 31):
@@ -107,7 +110,7 @@ def run_gpu(args):
     calib = copy_calibration()
     wl = W.ensemble_box(n_runs=args.runs, n_per_run=args.per_run, n_steps=1000, sample_every=20,
                         seed=3, state_fp64=False)
-    E = P.Ensemble.from_workload(wl, use_graph=True)
+    E = P.Ensemble.from_workload(wl, use_graph=True, n_streams=args.streams)
     n_runs = wl.n_runs
     nc = wl.runs[0].n_cells
 
@@ -137,19 +140,24 @@ def run_gpu(args):
     del E
     torch.cuda.empty_cache()
 
+    # a step launches each kernel once per lane (run group); the lanes split
+    # the runs, so a launch's algorithmic bytes are the step's over the
+    # launches per step
     kernels = {k: {"ms_total": ms, "launches": n, "ms_avg": ms / n} for k, (ms, n) in kt.items()}
     dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
     rl = None
-    ab = algorithmic_bytes(dom, n0, n_runs * nc, 2, 4)
-    if ab > 0:
+    per_step = algorithmic_bytes(dom, n0, n_runs * nc, 2, 4)
+    if per_step > 0:
+        ab = per_step * args.prof_steps / kernels[dom]["launches"]
         ach = ab / (kernels[dom]["ms_avg"] * 1e-3) / 1e9
+        tr = measured_traffic(dom, info["lanes"])
         rl = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-              "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom), "kernel": dom,
+              "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": tr, "kernel": dom,
               "algorithmic_bytes_per_launch": ab, "avg_launch_ms": kernels[dom]["ms_avg"]}
     for k, v in kernels.items():
         b = algorithmic_bytes(k, n0, n_runs * nc, 2, 4)
         if b > 0:
-            v["algorithmic_GBs"] = round(b / (v["ms_avg"] * 1e-3) / 1e9, 1)
+            v["algorithmic_GBs"] = round(b * args.prof_steps / (v["ms_total"] * 1e-3) / 1e9, 1)
             v["frac_of_hbm_peak"] = round(v["algorithmic_GBs"] / HBM_PEAK_GBS, 4)
 
     plain = None
@@ -222,6 +230,8 @@ def main():
     ap.add_argument("--runs", type=int, default=512)
     ap.add_argument("--per-run", type=int, default=1_000_000)
     ap.add_argument("--prof-steps", type=int, default=5)
+    ap.add_argument("--streams", type=int, default=0,
+                    help="run groups stepped concurrently (0 = the library's choice)")
     ap.add_argument("--plain-runs", type=int, default=2)
     ap.add_argument("--plain-steps", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -254,7 +264,9 @@ def main():
                                f"Kn 0.05, dt = 0.2 mean collision times, FP32 state, FP64 "
                                f"sampling accumulators, sample every 20 steps, HIP graph",
                    "runs": g["n_runs"], "particles_per_run": args.per_run,
-                   "cells_per_run": g["nc"], "parallelism": "one GPU; runs batched in each launch"},
+                   "cells_per_run": g["nc"], "lanes": g["info"]["lanes"],
+                   "parallelism": "one GPU; runs batched in each launch, split into "
+                                  f"{g['info']['lanes']} concurrent stream lanes"},
         "roofline": g["roofline"],
         "cpu_baseline": cpu,
         "plain_fp64": g["plain"],

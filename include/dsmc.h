@@ -94,12 +94,18 @@ typedef struct {
   int32_t n_samples;            /* sample slots (>= 0) */
   const int32_t *sample_steps;  /* host [n_samples]: 1-based step after which dsmc_step samples into slot k
                                    (entry < 1: slot filled only by dsmc_sample); may be NULL */
-  int32_t use_graph;            /* 1: replay each step from a HIP graph */
+  int32_t use_graph;            /* 1: replay each step from a HIP graph (captured on hip_stream, or on a
+                                   stream of the library's own ordered after it by events when
+                                   hip_stream is the null stream) */
   int32_t tile_chunks;          /* tuning: 64-slot rounds per indexing tile (0 = default 256) */
   int32_t collide_mode;         /* tuning: 0 auto, 1 one lane per cell (64 cells per wavefront),
                                    2 one 256-thread block per cell; auto takes 2 when the expected
                                    particles per cell (initial fill or inflow fill) reach 64 */
-  int32_t reserved;
+  int32_t n_streams;            /* tuning: run groups stepped concurrently, each on a HIP stream of the
+                                   library's own (0 = auto = 1, 1..4; 1 = every launch on hip_stream).
+                                   The runs are split into contiguous groups of about equal slot
+                                   counts; one group's Indexing and Interaction overlap the next
+                                   group's Motion.  Results do not depend on it. */
 } dsmc_options;
 
 /* Arena size for these runs/options.  Pure host computation.
@@ -146,8 +152,10 @@ const char *dsmc_last_error(const dsmc_ctx *ctx);
 /* ---- inspection (tests, diagnostics); all synchronise ---------------------- */
 
 /* Context facts: info[0] steps done, [1] runs, [2] ensembles, [3] 1 if FP64,
- * [4] indexing passes, [5] tiles, [6] slots, [7] latched device error. */
-dsmc_status dsmc_get_info(dsmc_ctx *ctx, int64_t info[8]);
+ * [4] indexing passes, [5] tiles, [6] slots, [7] latched device error,
+ * [8] stream lanes, [9] 1 if steps replay from HIP graphs (outside profiling). */
+#define DSMC_NINFO 10
+dsmc_status dsmc_get_info(dsmc_ctx *ctx, int64_t info[DSMC_NINFO]);
 
 /* Particle state of one run in slot order (cell-sorted after a step):
  * out[6][n] = x, y, z, u, v, w (z = 0 in 2-D), FP64.  *n receives the count;

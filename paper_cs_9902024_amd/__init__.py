@@ -33,6 +33,7 @@ EXPORTS = ("dsmc_required_bytes", "dsmc_init_runs", "dsmc_step", "dsmc_sample", 
            "dsmc_get_counts", "dsmc_counting_sort_bytes", "dsmc_counting_sort",
            "dsmc_set_profiling", "dsmc_kernel_times", "dsmc_kernel_name")
 NKERNELS = 16
+NINFO = 10
 
 
 class DsmcError(RuntimeError):
@@ -55,7 +56,7 @@ class dsmc_run_spec(C.Structure):
 class dsmc_options(C.Structure):
     _fields_ = [("state_fp64", C.c_int32), ("n_groups", C.c_int32), ("n_samples", C.c_int32),
                 ("sample_steps", C.POINTER(C.c_int32)), ("use_graph", C.c_int32),
-                ("tile_chunks", C.c_int32), ("collide_mode", C.c_int32), ("reserved", C.c_int32)]
+                ("tile_chunks", C.c_int32), ("collide_mode", C.c_int32), ("n_streams", C.c_int32)]
 
 
 _lib = None
@@ -135,7 +136,8 @@ def make_run_spec(rs) -> dsmc_run_spec:
 
 
 def make_options(state_fp64: bool, n_groups: int, sample_steps: Sequence[int],
-                 use_graph: bool = False, tile_chunks: int = 0, collide_mode: int = 0):
+                 use_graph: bool = False, tile_chunks: int = 0, collide_mode: int = 0,
+                 n_streams: int = 0):
     steps = (C.c_int32 * max(1, len(sample_steps)))(*sample_steps)
     o = dsmc_options()
     o.state_fp64 = int(bool(state_fp64))
@@ -145,6 +147,7 @@ def make_options(state_fp64: bool, n_groups: int, sample_steps: Sequence[int],
     o.use_graph = int(bool(use_graph))
     o.tile_chunks = int(tile_chunks)
     o.collide_mode = int(collide_mode)
+    o.n_streams = int(n_streams)
     o._keep = steps
     return o
 
@@ -209,9 +212,10 @@ def dsmc_last_error(ctx) -> str:
 
 
 def dsmc_get_info(ctx) -> dict:
-    a = (C.c_int64 * 8)()
+    a = (C.c_int64 * NINFO)()
     _check(lib().dsmc_get_info(ctx, a), "dsmc_get_info", ctx)
-    return dict(zip(("steps", "runs", "ensembles", "fp64", "passes", "tiles", "slots", "error"), list(a)))
+    return dict(zip(("steps", "runs", "ensembles", "fp64", "passes", "tiles", "slots", "error", "lanes",
+                     "graph"), list(a)))
 
 
 def dsmc_get_state(ctx, run: int) -> np.ndarray:
@@ -296,14 +300,14 @@ class Ensemble:
 
     def __init__(self, runs, sample_steps: Sequence[int] = (), state_fp64: bool = False,
                  n_groups: int = 1, use_graph: bool = False, tile_chunks: int = 0,
-                 collide_mode: int = 0, device=None, stream=None):
+                 collide_mode: int = 0, n_streams: int = 0, device=None, stream=None):
         import torch
         if not torch.cuda.is_available():
             raise DsmcError(-4, "Ensemble", "no GPU visible to torch")
         self.runs = list(runs)
         self.specs = _specs(self.runs)
         self.opt = make_options(state_fp64, n_groups, list(sample_steps), use_graph, tile_chunks,
-                                collide_mode)
+                                collide_mode, n_streams)
         self.nbytes = dsmc_required_bytes(self.specs, self.opt)
         dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.arena = torch.empty(self.nbytes, dtype=torch.uint8, device=dev)

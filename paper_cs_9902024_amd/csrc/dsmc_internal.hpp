@@ -27,6 +27,7 @@ enum : int { kSpecular = 0, kDiffuse = 1, kInflow = 2, kOutflow = 3 };
 // Device error codes (same values as the public status codes).
 enum : int { kErrCapacity = -3, kErrBounce = -7, kErrReject = -8, kErrNumeric = -9 };
 constexpr double kMaxSelections = 1e9;  // per cell per step; more means non-finite state
+constexpr int kMaxLanes = 4;            // run groups stepped concurrently on their own streams
 
 // Per-run constants and layout, read by every kernel (AoS in device memory).
 struct RunDev {
@@ -100,6 +101,18 @@ struct DevPtrs {
   uint32_t *wallq_n;           // [tiles] queue length per tile
 };
 
+// The contiguous share of one stream lane: runs [r0, r1) and everything laid
+// out per run in run order (tiles, inflow faces, inflow runs, interaction
+// items).
+struct LaneRange {
+  int32_t r0, r1;    // runs
+  int32_t t0, t1;    // tiles
+  int64_t f0, f1;    // inflow faces
+  int32_t i0, i1;    // entries of the inflow-run list
+  int64_t it0, it1;  // lane-per-cell interaction items
+  int64_t ci0, ci1;  // block-per-cell interaction items
+};
+
 struct Geometry {
   int dim;
   int fp64;
@@ -120,6 +133,19 @@ struct Geometry {
   int64_t n_items;      // lane-per-cell interaction items (up to 64 cells each)
   int64_t n_cell_items; // block-per-cell interaction items
   int collide_mode;      // 0 auto, 1 lane per cell, 2 wave per cell
+  int n_lanes;           // run groups per step (1: everything on the caller's stream)
+  LaneRange lane[kMaxLanes];
+};
+
+// Streams and events of a step split over lanes.  Lane L waits for the fork
+// (step counter advanced) and for lane L-1 to finish Motion, so one lane's
+// Indexing and Interaction overlap the next lane's Motion; the caller's
+// stream joins every lane before Sampling's accumulation.
+struct LaneStreams {
+  hipStream_t s[kMaxLanes];
+  hipEvent_t fork;
+  hipEvent_t moved[kMaxLanes];
+  hipEvent_t done[kMaxLanes];
 };
 
 // Kernel kinds for per-kernel event timing (order = dsmc_kernel_name).
@@ -131,7 +157,7 @@ enum KernelKind : int {
 // Optional hook around every launch (event timing); null = no hook.
 struct Prof {
   void *user;
-  void (*mark)(void *user, int kind, int begin);
+  void (*mark)(void *user, int kind, int begin, hipStream_t s);
 };
 
 // ---------------------------------------------------------------------------
@@ -140,7 +166,8 @@ struct Prof {
 template <typename real>
 void launch_init(const Geometry &g, const DevPtrs<real> &d, hipStream_t s);
 template <typename real>
-void launch_step(const Geometry &g, const DevPtrs<real> &d, int buf, hipStream_t s, const Prof *prof);
+void launch_step(const Geometry &g, const DevPtrs<real> &d, int buf, hipStream_t s, const LaneStreams *lanes,
+                 const Prof *prof);
 template <typename real>
 void launch_sample(const Geometry &g, const DevPtrs<real> &d, int buf, int slot, hipStream_t s,
                    const Prof *prof);

@@ -202,8 +202,8 @@ __global__ void k_step_begin(uint32_t *step, int32_t *slot, const int32_t *sampl
 // ---------------------------------------------------------------------------
 
 template <typename real>
-__global__ __launch_bounds__(256) void k_gen_count(DevPtrs<real> d, int64_t n_faces) {
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n_faces;
+__global__ __launch_bounds__(256) void k_gen_count(DevPtrs<real> d, int64_t f0, int64_t f1) {
+  for (int64_t j = f0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < f1;
        j += (int64_t)gridDim.x * blockDim.x) {
     const RunDev &R = d.runs[d.face_run[j]];
     const double M = R.mbar + d.rem_f[j];
@@ -257,10 +257,10 @@ __device__ void emit_face(const RunDev &R, uint32_t step, int32_t jl, int32_t cn
 // One block per run with inflow: scan the face counts, check capacity, append
 // the new particles in face order behind the run's live particles.
 template <typename real, int DIM>
-__global__ __launch_bounds__(256) void k_gen_emit(DevPtrs<real> d, int buf) {
+__global__ __launch_bounds__(256) void k_gen_emit(DevPtrs<real> d, int buf, int32_t i0) {
   __shared__ int64_t s_part[256];
   __shared__ int32_t s_n0;
-  const int r = d.inflow_runs[blockIdx.x];
+  const int r = d.inflow_runs[i0 + blockIdx.x];
   const RunDev &R = d.runs[r];
   const int tid = threadIdx.x;
   if (tid == 0) s_n0 = d.n_alive[r];
@@ -455,12 +455,12 @@ __device__ __forceinline__ void store4(real *p, int64_t i, const real (&o)[4]) {
 // particle is counted in the tile's histogram of the first indexing digit,
 // kept in wave-private LDS.
 template <typename real, int DIM, bool SINGLE>
-__global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_t n_tiles, int64_t tile,
+__global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_t t0, int32_t t1, int64_t tile,
                                                 int dstride) {
   extern __shared__ uint32_t lds[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int t = blockIdx.x * kWavesPerBlock + wave;
-  if (t >= n_tiles) return;
+  const int t = t0 + (int)blockIdx.x * kWavesPerBlock + wave;
+  if (t >= t1) return;
   const int r = d.tile_run[t];
   const RunDev &R = d.runs[r];
   const int64_t tl = t - R.to;
@@ -569,9 +569,10 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
 // per tile): the full face-by-face flight (specular, diffuse, open faces) and
 // their cells added to the tile histogram of the first indexing digit.
 template <typename real, int DIM, bool SINGLE>
-__global__ __launch_bounds__(256) void k_motion_walls(DevPtrs<real> d, int buf, int32_t n_tiles, int64_t tile) {
-  const int32_t t = blockIdx.x;
-  if (t >= n_tiles) return;
+__global__ __launch_bounds__(256) void k_motion_walls(DevPtrs<real> d, int buf, int32_t t0, int32_t t1,
+                                                      int64_t tile) {
+  const int32_t t = t0 + (int32_t)blockIdx.x;
+  if (t >= t1) return;
   const uint32_t nq = d.wallq_n[t];
   if (nq == 0) return;
   const RunDev &R = d.runs[d.tile_run[t]];
@@ -616,7 +617,8 @@ struct IndexArgs {
   uint32_t *bin_start;     // per run nc + 2 bin starts (single pass / bounds)
   int32_t *n_sorted;
   int32_t *n_alive;
-  int32_t n_tiles;
+  int32_t t0, t1;          // tiles [t0, t1)
+  int32_t r0;              // first run (grid y / x of the per-run scans)
   int64_t tile;
   int dstride;
   int pass;
@@ -632,8 +634,8 @@ __device__ __forceinline__ uint32_t digit_of(int32_t bin, int pass, bool single)
 __global__ __launch_bounds__(256) void k_digcount(IndexArgs a, int use_n_alive) {
   extern __shared__ uint32_t lds[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int t = blockIdx.x * kWavesPerBlock + wave;
-  if (t >= a.n_tiles) return;
+  const int t = a.t0 + (int)blockIdx.x * kWavesPerBlock + wave;
+  if (t >= a.t1) return;
   const int r = a.tile_run[t];
   const RunDev &R = a.runs[r];
   const int64_t tl = t - R.to;
@@ -659,7 +661,7 @@ __global__ __launch_bounds__(256) void k_digcount(IndexArgs a, int use_n_alive) 
 // Per (run, digit): exclusive scan of the digit's counts over the run's tiles
 // (in place) and the digit total.  Coalesced across digits.
 __global__ __launch_bounds__(256) void k_colscan(IndexArgs a) {
-  const RunDev &R = a.runs[blockIdx.y];
+  const RunDev &R = a.runs[a.r0 + blockIdx.y];
   const int D = a.single ? R.nc + 1 : kDigits;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= D) return;
@@ -689,7 +691,7 @@ __global__ __launch_bounds__(256) void k_colscan(IndexArgs a) {
 // live count (everything before the DEAD bin).
 __global__ __launch_bounds__(256) void k_digscan(IndexArgs a) {
   __shared__ uint32_t s[256];
-  const int r = blockIdx.x;
+  const int r = a.r0 + (int)blockIdx.x;
   const RunDev &R = a.runs[r];
   const bool single = a.single;
   const int D = single ? R.nc + 1 : kDigits;
@@ -740,8 +742,8 @@ __global__ __launch_bounds__(256) void k_scatter(IndexArgs a) {
   extern __shared__ uint32_t lds[];
   constexpr int U = 16;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int t = blockIdx.x * kWavesPerBlock + wave;
-  if (t >= a.n_tiles) return;
+  const int t = a.t0 + (int)blockIdx.x * kWavesPerBlock + wave;
+  if (t >= a.t1) return;
   const int r = a.tile_run[t];
   const RunDev &R = a.runs[r];
   const int64_t tl = t - R.to;
@@ -799,8 +801,8 @@ __global__ __launch_bounds__(256) void k_scatter(IndexArgs a) {
 
 // Bin starts from the final order (multi-pass): position p starts every bin in
 // (bin(p-1), bin(p)].
-__global__ __launch_bounds__(256) void k_bin_bounds(IndexArgs a, const int32_t *lcr, int64_t n_slots) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_slots;
+__global__ __launch_bounds__(256) void k_bin_bounds(IndexArgs a, const int32_t *lcr, int64_t s0, int64_t s1) {
+  for (int64_t i = s0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < s1;
        i += (int64_t)gridDim.x * blockDim.x) {
     const RunDev &R = a.runs[a.tile_run[i / a.tile]];
     const int64_t loc = i - R.so;
@@ -814,9 +816,9 @@ __global__ __launch_bounds__(256) void k_bin_bounds(IndexArgs a, const int32_t *
   }
 }
 
-__global__ void k_bin_finalize(IndexArgs a, int n_runs, int set_alive) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n_runs) return;
+__global__ void k_bin_finalize(IndexArgs a, int r1, int set_alive) {
+  const int r = a.r0 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (r >= r1) return;
   const RunDev &R = a.runs[r];
   if (a.n_sorted[r] == 0)
     for (int32_t q = 0; q <= R.nc + 1; ++q) a.bin_start[R.bo + q] = 0;
@@ -1047,12 +1049,12 @@ __device__ __forceinline__ void global_sync_wave() {
 }
 
 template <typename real, int DIM>
-__global__ __launch_bounds__(kCollideWaves * 64) void k_collide(DevPtrs<real> d, int src, int64_t n_items) {
+__global__ __launch_bounds__(kCollideWaves * 64) void k_collide(DevPtrs<real> d, int src, int64_t it0, int64_t it1) {
   extern __shared__ __align__(16) unsigned char lds_bytes[];
   constexpr int CAP = CollideCap<real>::value;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t item = xcd_block(blockIdx.x, gridDim.x) * kCollideWaves + wave;
-  if (item >= n_items) return;
+  const int64_t item = it0 + xcd_block(blockIdx.x, gridDim.x) * kCollideWaves + wave;
+  if (item >= it1) return;
   const int2 it = d.items[item];
   const RunDev &R = d.runs[it.x];
   const int32_t c0 = it.y;
@@ -1207,13 +1209,13 @@ __device__ uint32_t chain_block(const RunDev &R, uint32_t step, uint32_t c, uint
 }
 
 template <typename real, int DIM>
-__global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, int64_t n_items) {
+__global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, int64_t ci0, int64_t ci1) {
   extern __shared__ __align__(16) unsigned char lds_bytes[];
   __shared__ BlockScratch<real> sh;
   constexpr int CAP = CollideCap<real>::value;
   const int tid = threadIdx.x;
-  const int64_t item = xcd_block(blockIdx.x, gridDim.x);
-  if (item >= n_items) return;
+  const int64_t item = ci0 + xcd_block(blockIdx.x, gridDim.x);
+  if (item >= ci1) return;
   const int2 it = d.cell_items[item];
   const RunDev &R = d.runs[it.x];
   const int32_t c = it.y;
@@ -1225,6 +1227,11 @@ __global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, 
   const int64_t b0 = d.bin_start[R.bo + c];
   const int64_t n = (int64_t)d.bin_start[R.bo + c + 1] - b0;
   const bool in_lds = n <= CAP;
+  // cell state and step facts are loaded up front, their latency hidden
+  // behind the gather
+  const uint32_t step = *d.step;
+  const bool sample = *d.sample_slot >= 0;
+  real gm = d.gmax[gc], rem = d.rem_c[gc];
   // gather through LCR: positions to P', velocities to LDS (or P')
   {
     constexpr int U = 4;
@@ -1270,8 +1277,6 @@ __global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, 
     }
   }
   __syncthreads();
-  const uint32_t step = *d.step;
-  real gm = d.gmax[gc], rem = d.rem_c[gc];
   const int64_t nsel = ntc_selections<real>(R, n, gm, rem, d.err);
   real *u = in_lds ? su : B.u + R.so + b0;
   real *v = in_lds ? sv : B.v + R.so + b0;
@@ -1295,7 +1300,7 @@ __global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, 
       B.v[dst] = sv[k];
       B.w[dst] = sw[k];
     }
-  if (*d.sample_slot >= 0) {
+  if (sample) {
     double sm[kFields] = {0, 0, 0, 0, 0, 0, 0};
     for (int64_t k = tid; k < n; k += 256) {
       const double a = (double)u[k], b = (double)v[k], e = (double)w[k];
@@ -1440,7 +1445,9 @@ static IndexArgs index_args(const Geometry &g, const DevPtrs<real> &d) {
   a.bin_start = d.bin_start;
   a.n_sorted = d.n_sorted;
   a.n_alive = d.n_alive;
-  a.n_tiles = g.n_tiles;
+  a.t0 = 0;
+  a.t1 = g.n_tiles;
+  a.r0 = 0;
   a.tile = g.tile;
   a.dstride = g.dstride;
   a.pass = 0;
@@ -1454,21 +1461,23 @@ static int digit_bits(int D) {
   return b;
 }
 
-#define TIMED(kind, ...)                           \
-  do {                                             \
-    if (prof) prof->mark(prof->user, (kind), 1);   \
-    __VA_ARGS__;                                   \
-    if (prof) prof->mark(prof->user, (kind), 0);   \
+// Brackets a launch on stream `s` (in scope) with the profiling hook.
+#define TIMED(kind, ...)                              \
+  do {                                                \
+    if (prof) prof->mark(prof->user, (kind), 1, s);   \
+    __VA_ARGS__;                                      \
+    if (prof) prof->mark(prof->user, (kind), 0, s);   \
   } while (0)
 
-// Scans and scatter of pass `pass`; the tile histograms are already in place.
+// Scans and scatter of pass `pass` over the runs [a.r0, a.r0 + n_runs) and
+// tiles [a.t0, a.t1); the tile histograms are already in place.
 static void index_pass(IndexArgs a, int max_digits, int n_runs, int pass, const int32_t *in, int32_t *out,
                        hipStream_t s, const Prof *prof = nullptr) {
   a.pass = pass;
   a.in = in;
   a.out = out;
   const size_t lds = (size_t)kWavesPerBlock * a.dstride * sizeof(uint32_t);
-  const int wblocks = (a.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  const int wblocks = (a.t1 - a.t0 + kWavesPerBlock - 1) / kWavesPerBlock;
   TIMED(kKColScan, hipLaunchKernelGGL(k_colscan, dim3((max_digits + 255) / 256, n_runs), dim3(256), 0, s, a));
   TIMED(kKDigScan, hipLaunchKernelGGL(k_digscan, dim3(n_runs), dim3(256), 0, s, a));
   TIMED(kKScatter, hipLaunchKernelGGL(k_scatter, dim3(wblocks), dim3(256), lds, s, a));
@@ -1491,29 +1500,38 @@ void launch_init(const Geometry &g, const DevPtrs<real> &d, hipStream_t s) {
                        g.tile);
 }
 
+// One lane's share of a step: Generation, Motion, Indexing and Interaction of
+// the runs [L.r0, L.r1) on stream s.  `moved` (may be null) is recorded once
+// Motion is complete.
 template <typename real, int DIM>
-static void step_dim(const Geometry &g, const DevPtrs<real> &d, int buf, hipStream_t s, const Prof *prof) {
-  TIMED(kKStepBegin, hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(1), 0, s, d.step, d.sample_slot,
-                                        d.sample_steps, g.n_samples));
-  if (g.n_inflow_runs > 0) {
-    TIMED(kKGenCount,
-          hipLaunchKernelGGL(k_gen_count<real>, dim3(grid_for(g.n_faces)), dim3(256), 0, s, d, g.n_faces));
-    TIMED(kKGenEmit, hipLaunchKernelGGL((k_gen_emit<real, DIM>), dim3(g.n_inflow_runs), dim3(256), 0, s, d, buf));
+static void lane_step(const Geometry &g, const LaneRange &L, const DevPtrs<real> &d, int buf, hipStream_t s,
+                      hipEvent_t moved, const Prof *prof) {
+  const int n_runs = L.r1 - L.r0;
+  const int32_t n_tiles = L.t1 - L.t0;
+  if (L.i1 > L.i0) {
+    TIMED(kKGenCount, hipLaunchKernelGGL(k_gen_count<real>, dim3(grid_for(L.f1 - L.f0)), dim3(256), 0, s, d, L.f0,
+                                         L.f1));
+    TIMED(kKGenEmit, hipLaunchKernelGGL((k_gen_emit<real, DIM>), dim3(L.i1 - L.i0), dim3(256), 0, s, d, buf, L.i0));
   }
   const size_t lds = (size_t)kWavesPerBlock * g.dstride * sizeof(uint32_t);
-  const int wblocks = (g.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  const int wblocks = (n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
   IndexArgs a = index_args(g, d);
+  a.t0 = L.t0;
+  a.t1 = L.t1;
+  a.r0 = L.r0;
   if (g.npass == 1) {
-    TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, true>), dim3(wblocks), dim3(256), lds, s, d, buf,
-                                       g.n_tiles, g.tile, g.dstride));
-    TIMED(kKMotionWalls, hipLaunchKernelGGL((k_motion_walls<real, DIM, true>), dim3(g.n_tiles), dim3(256), 0, s,
-                                            d, buf, g.n_tiles, g.tile));
-    index_pass(a, g.max_nc + 1, g.n_runs, 0, nullptr, d.lcr, s, prof);
+    TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, true>), dim3(wblocks), dim3(256), lds, s, d, buf, L.t0,
+                                       L.t1, g.tile, g.dstride));
+    TIMED(kKMotionWalls, hipLaunchKernelGGL((k_motion_walls<real, DIM, true>), dim3(n_tiles), dim3(256), 0, s, d,
+                                            buf, L.t0, L.t1, g.tile));
+    if (moved) (void)hipEventRecord(moved, s);
+    index_pass(a, g.max_nc + 1, n_runs, 0, nullptr, d.lcr, s, prof);
   } else {
-    TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, false>), dim3(wblocks), dim3(256), lds, s, d, buf,
-                                       g.n_tiles, g.tile, g.dstride));
-    TIMED(kKMotionWalls, hipLaunchKernelGGL((k_motion_walls<real, DIM, false>), dim3(g.n_tiles), dim3(256), 0, s,
-                                            d, buf, g.n_tiles, g.tile));
+    TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, false>), dim3(wblocks), dim3(256), lds, s, d, buf, L.t0,
+                                       L.t1, g.tile, g.dstride));
+    TIMED(kKMotionWalls, hipLaunchKernelGGL((k_motion_walls<real, DIM, false>), dim3(n_tiles), dim3(256), 0, s, d,
+                                            buf, L.t0, L.t1, g.tile));
+    if (moved) (void)hipEventRecord(moved, s);
     const int32_t *in = nullptr;
     for (int p = 0; p < g.npass; ++p) {
       int32_t *out = ((g.npass - 1 - p) % 2 == 0) ? d.lcr : d.lcr_tmp;
@@ -1522,31 +1540,64 @@ static void step_dim(const Geometry &g, const DevPtrs<real> &d, int buf, hipStre
         a.in = in;
         TIMED(kKDigCount, hipLaunchKernelGGL(k_digcount, dim3(wblocks), dim3(256), lds, s, a, 0));
       }
-      index_pass(a, kDigits, g.n_runs, p, in, out, s, prof);
+      index_pass(a, kDigits, n_runs, p, in, out, s, prof);
       in = out;
     }
+    const int64_t s0 = (int64_t)L.t0 * g.tile, s1 = (int64_t)L.t1 * g.tile;
     TIMED(kKBinBounds,
-          hipLaunchKernelGGL(k_bin_bounds, dim3(grid_for(g.n_slots)), dim3(256), 0, s, a, d.lcr, g.n_slots));
+          hipLaunchKernelGGL(k_bin_bounds, dim3(grid_for(s1 - s0)), dim3(256), 0, s, a, d.lcr, s0, s1));
     TIMED(kKBinFinalize,
-          hipLaunchKernelGGL(k_bin_finalize, dim3((g.n_runs + 255) / 256), dim3(256), 0, s, a, g.n_runs, 1));
+          hipLaunchKernelGGL(k_bin_finalize, dim3((n_runs + 255) / 256), dim3(256), 0, s, a, L.r1, 1));
   }
-  if (g.n_items > 0) {
-    const int64_t nblk = (g.n_items + kCollideWaves - 1) / kCollideWaves;
+  if (L.it1 > L.it0) {
+    const int64_t nblk = (L.it1 - L.it0 + kCollideWaves - 1) / kCollideWaves;
     TIMED(kKCollide, hipLaunchKernelGGL((k_collide<real, DIM>), dim3((unsigned)nblk), dim3(kCollideWaves * 64),
-                                        (size_t)kCollideWaves * collide_wave_bytes<real>(), s, d, buf, g.n_items));
+                                        (size_t)kCollideWaves * collide_wave_bytes<real>(), s, d, buf, L.it0,
+                                        L.it1));
   }
-  if (g.n_cell_items > 0)
-    TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_cell<real, DIM>), dim3((unsigned)g.n_cell_items), dim3(256),
-                                            (size_t)collide_cell_bytes<real>(), s, d, buf, g.n_cell_items));
+  if (L.ci1 > L.ci0)
+    TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_cell<real, DIM>), dim3((unsigned)(L.ci1 - L.ci0)),
+                                            dim3(256), (size_t)collide_cell_bytes<real>(), s, d, buf, L.ci0,
+                                            L.ci1));
+}
+
+template <typename real, int DIM>
+static void step_dim(const Geometry &g, const DevPtrs<real> &d, int buf, hipStream_t s, const LaneStreams *ls,
+                     const Prof *prof) {
+  TIMED(kKStepBegin, hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(1), 0, s, d.step, d.sample_slot,
+                                        d.sample_steps, g.n_samples));
+  if (g.n_lanes <= 1 || !ls) {
+    LaneRange all = g.lane[0];
+    if (g.n_lanes > 1) {
+      all.r1 = g.lane[g.n_lanes - 1].r1;
+      all.t1 = g.lane[g.n_lanes - 1].t1;
+      all.f1 = g.lane[g.n_lanes - 1].f1;
+      all.i1 = g.lane[g.n_lanes - 1].i1;
+      all.it1 = g.lane[g.n_lanes - 1].it1;
+      all.ci1 = g.lane[g.n_lanes - 1].ci1;
+    }
+    lane_step<real, DIM>(g, all, d, buf, s, nullptr, prof);
+  } else {
+    (void)hipEventRecord(ls->fork, s);
+    for (int l = 0; l < g.n_lanes; ++l) {
+      hipStream_t q = ls->s[l];
+      (void)hipStreamWaitEvent(q, ls->fork, 0);
+      if (l > 0) (void)hipStreamWaitEvent(q, ls->moved[l - 1], 0);
+      lane_step<real, DIM>(g, g.lane[l], d, buf, q, ls->moved[l], prof);
+      (void)hipEventRecord(ls->done[l], q);
+    }
+    for (int l = 0; l < g.n_lanes; ++l) (void)hipStreamWaitEvent(s, ls->done[l], 0);
+  }
   if (g.n_samples > 0)
     TIMED(kKAccumulate, hipLaunchKernelGGL(k_accumulate<real>, dim3(grid_for(g.acc_stride)), dim3(256), 0, s, d,
                                            -1, g.acc_stride, g.n_eg));
 }
 
 template <typename real>
-void launch_step(const Geometry &g, const DevPtrs<real> &d, int buf, hipStream_t s, const Prof *prof) {
-  if (g.dim == 3) step_dim<real, 3>(g, d, buf, s, prof);
-  else step_dim<real, 2>(g, d, buf, s, prof);
+void launch_step(const Geometry &g, const DevPtrs<real> &d, int buf, hipStream_t s, const LaneStreams *ls,
+                 const Prof *prof) {
+  if (g.dim == 3) step_dim<real, 3>(g, d, buf, s, ls, prof);
+  else step_dim<real, 2>(g, d, buf, s, ls, prof);
 }
 
 template <typename real>
@@ -1566,8 +1617,10 @@ void launch_moments(const Geometry &g, const DevPtrs<real> &d, int slot, int eg0
 
 template void launch_init<float>(const Geometry &, const DevPtrs<float> &, hipStream_t);
 template void launch_init<double>(const Geometry &, const DevPtrs<double> &, hipStream_t);
-template void launch_step<float>(const Geometry &, const DevPtrs<float> &, int, hipStream_t, const Prof *);
-template void launch_step<double>(const Geometry &, const DevPtrs<double> &, int, hipStream_t, const Prof *);
+template void launch_step<float>(const Geometry &, const DevPtrs<float> &, int, hipStream_t, const LaneStreams *,
+                                 const Prof *);
+template void launch_step<double>(const Geometry &, const DevPtrs<double> &, int, hipStream_t, const LaneStreams *,
+                                  const Prof *);
 template void launch_sample<float>(const Geometry &, const DevPtrs<float> &, int, int, hipStream_t,
                                    const Prof *);
 template void launch_sample<double>(const Geometry &, const DevPtrs<double> &, int, int, hipStream_t,
@@ -1659,7 +1712,9 @@ void launch_counting_sort(const int32_t *keys, int64_t n, int32_t nbins, int32_t
   a.bin_start = start;
   a.n_sorted = ns;
   a.n_alive = (int32_t *)(w + L.off_na);
-  a.n_tiles = L.nt;
+  a.t0 = 0;
+  a.t1 = L.nt;
+  a.r0 = 0;
   a.tile = L.tile;
   a.dstride = L.D;
   a.single = L.npass == 1;
@@ -1676,7 +1731,7 @@ void launch_counting_sort(const int32_t *keys, int64_t n, int32_t nbins, int32_t
     in = out;
   }
   if (L.npass > 1) {
-    hipLaunchKernelGGL(k_bin_bounds, dim3(grid_for(n)), dim3(256), 0, s, a, lcr, (int64_t)L.nt * L.tile);
+    hipLaunchKernelGGL(k_bin_bounds, dim3(grid_for(n)), dim3(256), 0, s, a, lcr, (int64_t)0, (int64_t)L.nt * L.tile);
     hipLaunchKernelGGL(k_bin_finalize, dim3(1), dim3(256), 0, s, a, 1, 0);
   }
 }

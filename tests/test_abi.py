@@ -41,6 +41,24 @@ def test_struct_sizes_match_header(dsmc):
     assert C.sizeof(dsmc.dsmc_options) == 40
 
 
+def test_array_lengths_match_header(dsmc):
+    src = open(os.path.join(ROOT, "include", "dsmc.h")).read()
+    defs = dict(re.findall(r"#define (DSMC_N[A-Z]+) (\d+)", src))
+    assert int(defs["DSMC_NINFO"]) == dsmc.NINFO
+    assert int(defs["DSMC_NKERNELS"]) == dsmc.NKERNELS
+
+
+def test_stream_lane_option_is_validated(dsmc):
+    specs = dsmc._specs(W.plain_box().runs)
+    for bad in (-1, 5):
+        opt = dsmc.make_options(True, 1, [], n_streams=bad)
+        with pytest.raises(dsmc.DsmcError) as e:
+            dsmc.dsmc_required_bytes(specs, opt)
+        assert e.value.status == -1
+    for ok in range(5):
+        dsmc.dsmc_required_bytes(specs, dsmc.make_options(True, 1, [], n_streams=ok))
+
+
 def _bytes(dsmc, wl, fp64=False, groups=None):
     specs = dsmc._specs(wl.runs)
     opt = dsmc.make_options(fp64, groups or wl.n_groups, wl.sample_steps)
