@@ -89,6 +89,8 @@ def lib():
         L.or_get_cells.argtypes = [P, P, P, P, P]
         L.or_get_cell_state.argtypes = [P, P, P, P]
         L.or_get_face_rem.argtypes = [P, dp]
+        L.or_get_solid_hits.argtypes = [P]
+        L.or_get_solid_hits.restype = C.c_int64
         L.or_set_cell_state.argtypes = [P, dp, dp]
         L.or_counting_sort.argtypes = [P, C.c_int64, C.c_int64, P, P, P]
         L.or_collide_cell.argtypes = [C.POINTER(OrSpec), C.c_uint32, C.c_uint32, C.c_int64,
@@ -115,7 +117,15 @@ def make_spec(rs) -> OrSpec:
         s.face_bc[f] = BC_CODES[rs.face_bc[f]]
         s.face_T[f] = rs.face_T[f]
     s.inflow_n, s.inflow_U, s.inflow_T = rs.inflow_n, rs.inflow_U, rs.inflow_T
-    s.solid = None if rs.solid is None else rs.solid.ctypes.data
+    if rs.solid is None:
+        s.solid = None
+    else:
+        # one byte per cell, cell index (iz * ny + iy) * nx + ix; the run copies it
+        mask = np.ascontiguousarray(rs.solid, dtype=np.uint8).ravel()
+        if mask.size != rs.n_cells:
+            raise ValueError("solid mask must have one entry per cell")
+        s._mask = mask
+        s.solid = mask.ctypes.data
     s.solid_T = rs.solid_T
     s.capacity, s.n_init = rs.capacity, rs.n_init
     for a in range(3):
@@ -162,6 +172,7 @@ class OracleRun:
         self.nc = rs.n_cells
         if init:
             lib().or_init(self._h)
+            self._check()
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -192,6 +203,10 @@ class OracleRun:
 
     def interaction(self):
         lib().or_interaction(self._h)
+
+    def solid_hits(self) -> int:
+        """Solid-cell faces hit in the last Motion."""
+        return int(lib().or_get_solid_hits(self._h))
 
     def _check(self):
         err = self.info()["err"]
@@ -311,7 +326,8 @@ def ensemble(workload, n_threads: int = 0, runs: Optional[Sequence] = None,
     G = workload.n_groups if n_groups is None else n_groups
     G = max(1, min(G, len(runs)))
     samples = np.array([s for s in workload.sample_steps if s <= n_steps], np.int32)
-    specs = (OrSpec * len(runs))(*[make_spec(r) for r in runs])
+    keep = [make_spec(r) for r in runs]       # holds the masks while the C side copies them
+    specs = (OrSpec * len(runs))(*keep)
     nc = runs[0].n_cells
     acc = np.zeros((len(samples), G, nc, NFIELD))
     stats = (C.c_int64 * 2)()

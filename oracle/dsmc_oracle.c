@@ -21,7 +21,12 @@
  *     immediate update of (sigma*c_r)_max;
  *   - hard-sphere / variable-hard-sphere cross sections, isotropic scattering;
  *   - specular and diffuse (full accommodation) walls, vacuum outflow, and
- *     inflow of a drifting Maxwellian through the -x face.
+ *     inflow of a drifting Maxwellian through the -x face;
+ *   - an optional obstacle made of solid cells (voxels of the cell grid) with
+ *     diffuse faces: the straight path is followed from cell to cell in the
+ *     time order of its plane crossings (the voxel traversal of Amanatides
+ *     and Woo, 1987) and the first solid cell it enters is hit on the face it
+ *     crosses.
  * Random numbers come from the counter-based generator Philox4x32-10 of
  * Salmon, Moraes, Dror and Shaw (SC'11), written from its published
  * definition.  Build with -O2 -ffp-contract=off (no fast-math).
@@ -100,6 +105,10 @@ typedef struct {
     uint32_t step;
     int32_t err;
     int64_t last_ncoll, last_ngen, last_nremoved, last_nmoved;
+    uint8_t *solid;      /* [nc] 1 = solid cell (copy of the spec's mask), or NULL */
+    int has_solid;       /* at least one solid cell */
+    int64_t last_nsolid; /* solid faces hit in the last Motion */
+    double d[3];         /* cell size along each axis */
 } or_run;
 
 /* ------------------------------------------------------------------------- */
@@ -206,6 +215,7 @@ void or_run_free(or_run *R)
     }
     free(R->cell); free(R->lcr); free(R->cstart); free(R->ccount);
     free(R->rem_c); free(R->gmax); free(R->ncoll); free(R->rem_f);
+    free(R->solid);
     free(R);
 }
 
@@ -219,7 +229,7 @@ or_run *or_run_new(const or_spec *sp, int32_t *status)
     if (!(sp->dt > 0.0) || sp->capacity < sp->n_init || sp->n_init < 0) {
         *status = OR_EINVAL; return NULL;
     }
-    if (sp->solid) { *status = OR_EUNSUPPORTED; return NULL; }
+    if (sp->solid && !(sp->solid_T > 0.0)) { *status = OR_EINVAL; return NULL; }
     for (int f = 0; f < 6; ++f) {
         int bc = sp->face_bc[f];
         if (bc < 0 || bc > 3) { *status = OR_EINVAL; return NULL; }
@@ -234,6 +244,21 @@ or_run *or_run_new(const or_spec *sp, int32_t *status)
     R->inv_d[0] = (double)sp->nx / sp->lx;
     R->inv_d[1] = (double)sp->ny / sp->ly;
     R->inv_d[2] = (double)sp->nz / sp->lz;
+    R->d[0] = sp->lx / sp->nx;
+    R->d[1] = sp->ly / sp->ny;
+    R->d[2] = sp->lz / sp->nz;
+    if (sp->solid) {
+        R->solid = (uint8_t *)malloc((size_t)R->nc);
+        if (!R->solid) { or_run_free(R); *status = OR_ENOMEM; return NULL; }
+        for (int64_t c = 0; c < R->nc; ++c) {
+            R->solid[c] = sp->solid[c] ? 1 : 0;
+            if (R->solid[c]) R->has_solid = 1;
+            /* inflow enters through the first layer of cells: it must be fluid */
+            if (R->solid[c] && sp->face_bc[0] == OR_BC_INFLOW && c % sp->nx == 0) {
+                or_run_free(R); *status = OR_EINVAL; return NULL;
+            }
+        }
+    }
     double vc = (sp->lx / sp->nx) * (sp->ly / sp->ny) * (sp->lz / sp->nz);
     R->coef = sp->fnum_sigma * sp->dt / vc;
     R->vhs_exp = 1.0 - 2.0 * sp->omega;
@@ -248,6 +273,7 @@ or_run *or_run_new(const or_spec *sp, int32_t *status)
     if (inflow && sp->inflow_T > Tmax) Tmax = sp->inflow_T;
     for (int f = 0; f < 2 * sp->dim; ++f)
         if (sp->face_bc[f] == OR_BC_DIFFUSE && sp->face_T[f] > Tmax) Tmax = sp->face_T[f];
+    if (R->has_solid && sp->solid_T > Tmax) Tmax = sp->solid_T;
     double c0 = U0 + 3.0 * sqrt(2.0 * Tmax);
     R->gmax0 = g_of(R, c0);
 
@@ -287,7 +313,8 @@ or_run *or_run_new(const or_spec *sp, int32_t *status)
 
 /* Initial uniform Maxwellian fill: slot i draws from (step 0, INIT, i).
  * Uniforms 0..3 give the three velocity normals (two Box-Muller pairs, the
- * last output unused), uniforms 4.. give the position. */
+ * last output unused), uniforms 4.. give the position: three at a time, drawn
+ * again while the position lies in a solid cell (uniform over the fluid). */
 void or_init(or_run *R)
 {
     const or_spec *sp = &R->sp;
@@ -302,10 +329,18 @@ void or_init(or_run *R)
         R->p[3][i] = sp->init_U[0] + st * n0;
         R->p[4][i] = sp->init_U[1] + st * n1;
         R->p[5][i] = sp->init_U[2] + st * n2;
-        double ux = us_next(&s), uy = us_next(&s), uz = us_next(&s);
-        R->p[0][i] = ux * sp->lx;
-        R->p[1][i] = uy * sp->ly;
-        R->p[2][i] = (sp->dim == 3) ? uz * sp->lz : 0.0;
+        double pos[3];
+        for (int att = 0;; ++att) {
+            if (att == MAX_INIT_ATTEMPTS) { R->err = OR_EREJECT; return; }
+            double ux = us_next(&s), uy = us_next(&s), uz = us_next(&s);
+            pos[0] = ux * sp->lx;
+            pos[1] = uy * sp->ly;
+            pos[2] = (sp->dim == 3) ? uz * sp->lz : 0.0;
+            if (!R->has_solid || !R->solid[cell_of(R, pos)]) break;
+        }
+        R->p[0][i] = pos[0];
+        R->p[1][i] = pos[1];
+        R->p[2][i] = pos[2];
     }
     R->n = sp->n_init;
     R->step = 0;
@@ -361,6 +396,76 @@ void or_generation(or_run *R)
 /* Motion + Enumeration                                                       */
 /* ------------------------------------------------------------------------- */
 
+static int64_t cell_at(const or_run *R, const int64_t v[3])
+{
+    return (v[2] * R->sp.ny + v[1]) * R->sp.nx + v[0];
+}
+
+/* Follows the straight path from pos (in cell vox) with velocity vel for a
+ * time tlim, crossing cell planes in time order (ties: lower axis first).
+ * Returns the axis of the face of the first solid cell entered and its time
+ * in *th, or -1 if none is entered; vox follows the path up to that face (or
+ * up to tlim).  A plane is at k * d (k = 0..n). */
+static int solid_walk(const or_run *R, const double pos[3], const double vel[3], double tlim,
+                      int64_t vox[3], double *th)
+{
+    const int32_t n[3] = {R->sp.nx, R->sp.ny, R->sp.nz};
+    for (;;) {
+        double tn = INFINITY;
+        int ax = -1;
+        for (int a = 0; a < R->sp.dim; ++a) {
+            double t;
+            if (vel[a] > 0.0) t = ((double)(vox[a] + 1) * R->d[a] - pos[a]) / vel[a];
+            else if (vel[a] < 0.0) t = ((double)vox[a] * R->d[a] - pos[a]) / vel[a];
+            else continue;
+            if (t < tn) { tn = t; ax = a; }
+        }
+        if (ax < 0 || !(tn < tlim)) return -1;
+        int64_t next[3] = {vox[0], vox[1], vox[2]};
+        next[ax] += (vel[ax] > 0.0) ? 1 : -1;
+        if (next[ax] < 0 || next[ax] >= n[ax]) return -1; /* a domain face: not this walk's */
+        if (R->solid[cell_at(R, next)]) {
+            *th = tn > 0.0 ? tn : 0.0;
+            return ax;
+        }
+        vox[ax] = next[ax];
+    }
+}
+
+/* Coordinate x moved by rounding steps only until axis_index puts it in cell
+ * i along axis a (used when a position rounds into a solid cell next to the
+ * fluid cell the path ended in). */
+static double snap_into(const or_run *R, int a, double x, int64_t i)
+{
+    const int32_t n[3] = {R->sp.nx, R->sp.ny, R->sp.nz};
+    if (axis_index(x, R->inv_d[a], n[a]) > i) {
+        x = (double)(i + 1) * R->d[a];
+        while (axis_index(x, R->inv_d[a], n[a]) > i) x = nextafter(x, -INFINITY);
+    } else {
+        x = (double)i * R->d[a];
+        while (axis_index(x, R->inv_d[a], n[a]) < i) x = nextafter(x, INFINITY);
+    }
+    return x;
+}
+
+/* Re-emission from a diffuse surface at temperature Tw whose normal is axis
+ * ax (side 1: the particle arrived moving +, so it leaves moving -): normal
+ * speed sqrt(-2 Tw ln U), tangentials sqrt(Tw) N(0,1), from the WALL stream
+ * of the slot at uniforms 4h .. 4h+2 for the h-th wall interaction. */
+static void diffuse_emit(ustream *ws, int hits, double Tw, int ax, int side, double vel[3])
+{
+    ws->next = 4u * (uint64_t)hits;
+    double w0 = us_next(ws), w1 = us_next(ws), w2 = us_next(ws);
+    double vn = sqrt(-2.0 * Tw * log(w0));
+    double n0, n1;
+    box_muller(w1, w2, &n0, &n1);
+    double stw = sqrt(Tw);
+    int t1 = (ax == 0) ? 1 : 0, t2 = (ax == 2) ? 1 : 2;
+    vel[ax] = side ? -vn : vn;
+    vel[t1] = stw * n0;
+    vel[t2] = stw * n1;
+}
+
 /* Moves one particle for dt; returns its new cell or nc (DEAD). */
 static int64_t move_one(or_run *R, int64_t slot, double pos[3], double vel[3])
 {
@@ -369,6 +474,8 @@ static int64_t move_one(or_run *R, int64_t slot, double pos[3], double vel[3])
     double trem = sp->dt;
     int hits = 0;
     ustream ws = {{sp->run_id, sp->seed}, R->step, PURPOSE_WALL, (uint32_t)slot, 0};
+    int64_t vox[3] = {axis_index(pos[0], R->inv_d[0], sp->nx), axis_index(pos[1], R->inv_d[1], sp->ny),
+                      (dim == 3) ? axis_index(pos[2], R->inv_d[2], sp->nz) : 0};
     for (;;) {
         double tmin = INFINITY;
         int ax = -1, side = 0;
@@ -380,6 +487,21 @@ static int64_t move_one(or_run *R, int64_t slot, double pos[3], double vel[3])
             else continue;
             if (th < 0.0) th = 0.0;
             if (th < tmin) { tmin = th; ax = a; side = sd; }
+        }
+        if (R->has_solid) {
+            /* a solid cell entered before the domain face (or the end of the step) */
+            double ts;
+            int sa = solid_walk(R, pos, vel, (ax < 0 || tmin >= trem) ? trem : tmin, vox, &ts);
+            if (sa >= 0) {
+                int up = vel[sa] > 0.0;
+                double plane = (double)(up ? vox[sa] + 1 : vox[sa]) * R->d[sa];
+                for (int a = 0; a < dim; ++a) pos[a] = (a == sa) ? plane : pos[a] + vel[a] * ts;
+                trem = trem - ts;
+                diffuse_emit(&ws, hits, sp->solid_T, sa, up, vel);
+                R->last_nsolid++;
+                if (++hits == MAX_WALL_HITS) { R->err = OR_EBOUNCE; break; }
+                continue;
+            }
         }
         if (ax < 0 || tmin >= trem) {
             for (int a = 0; a < dim; ++a) pos[a] = pos[a] + vel[a] * trem;
@@ -393,29 +515,29 @@ static int64_t move_one(or_run *R, int64_t slot, double pos[3], double vel[3])
         if (bc == OR_BC_SPECULAR) {
             vel[ax] = -vel[ax];
         } else if (bc == OR_BC_DIFFUSE) {
-            double Tw = sp->face_T[f];
-            ws.next = 4u * (uint64_t)hits;
-            double w0 = us_next(&ws), w1 = us_next(&ws), w2 = us_next(&ws);
-            double vn = sqrt(-2.0 * Tw * log(w0));
-            double n0, n1;
-            box_muller(w1, w2, &n0, &n1);
-            double stw = sqrt(Tw);
-            int t1 = (ax == 0) ? 1 : 0, t2 = (ax == 2) ? 1 : 2;
-            vel[ax] = side ? -vn : vn;
-            vel[t1] = stw * n0;
-            vel[t2] = stw * n1;
+            diffuse_emit(&ws, hits, sp->face_T[f], ax, side, vel);
         } else {
             return R->nc; /* inflow plane crossed outward, or outflow */
         }
         if (++hits == MAX_WALL_HITS) { R->err = OR_EBOUNCE; break; }
     }
     if (pos[0] < 0.0) return R->nc; /* a generated particle that never entered */
-    return cell_of(R, pos);
+    int64_t c = cell_of(R, pos);
+    if (R->has_solid && R->solid[c]) {
+        /* rounding put the end point across the face of a solid cell: it
+         * belongs to the fluid cell the path ended in */
+        for (int a = 0; a < dim; ++a)
+            if (axis_index(pos[a], R->inv_d[a], (a == 0) ? sp->nx : (a == 1) ? sp->ny : sp->nz) != vox[a])
+                pos[a] = snap_into(R, a, pos[a], vox[a]);
+        c = cell_of(R, pos);
+    }
+    return c;
 }
 
 void or_motion(or_run *R)
 {
     int64_t removed = 0;
+    R->last_nsolid = 0;
     for (int64_t i = 0; i < R->n; ++i) {
         double pos[3] = {R->p[0][i], R->p[1][i], R->p[2][i]};
         double vel[3] = {R->p[3][i], R->p[4][i], R->p[5][i]};
@@ -636,6 +758,8 @@ void or_set_cell_state(or_run *R, const double *rem, const double *gmax)
     if (rem) memcpy(R->rem_c, rem, (size_t)R->nc * sizeof(double));
     if (gmax) memcpy(R->gmax, gmax, (size_t)R->nc * sizeof(double));
 }
+
+int64_t or_get_solid_hits(const or_run *R) { return R->last_nsolid; }
 
 void or_get_face_rem(const or_run *R, double *rem)
 {
