@@ -20,7 +20,11 @@
  *    and passes it to dsmc_init_runs.  The arena must outlive the context.
  *    The library allocates no device memory; it owns only the opaque context
  *    (host heap) and copies the run specs and sample schedule.
- *  - Streams: the caller's HIP stream is borrowed; every launch goes to it.
+ *  - Streams: the caller's HIP stream is borrowed and every launch goes to
+ *    it, except (a) with dsmc_options.n_streams > 1, where run groups go to
+ *    streams of the library's own forked from and joined back into it by
+ *    events, and (b) graph replay when it is the null stream, which runs on a
+ *    library stream ordered after it by events.
  *  - Asynchrony: dsmc_step and dsmc_sample only enqueue work.
  *    dsmc_read_moments, dsmc_read_accum, dsmc_sync and the dsmc_get_* /
  *    dsmc_set_state calls synchronise the stream.
@@ -52,7 +56,8 @@ typedef int32_t dsmc_status;
 #define DSMC_ESTATE (-5)       /* call not valid in the current state */
 #define DSMC_EUNSUPPORTED (-6) /* feature not supported */
 #define DSMC_EBOUNCE (-7)      /* more than 64 wall interactions of one particle in one step */
-#define DSMC_EREJECT (-8)      /* inflow velocity sampler exceeded its attempt limit */
+#define DSMC_EREJECT (-8)      /* inflow velocity sampler or the fill of a run with solid cells exceeded
+                                  its attempt limit */
 #define DSMC_ENUMERIC (-9)     /* non-finite particle state or >= 1e9 pair selections in one cell and step */
 
 /* Boundary kind of a face; faces are ordered -x, +x, -y, +y, -z, +z. */
@@ -86,6 +91,13 @@ typedef struct {
   uint32_t run_id, seed;        /* Philox key of the run: runs are independent and replayable */
   int32_t ensemble;             /* runs with the same id are averaged together; they share a grid */
   int32_t reserved;
+  const uint8_t *solid_mask;    /* host [nz][ny][nx] (cell (iz*ny + iy)*nx + ix), nonzero = solid cell, or
+                                   NULL.  Solid cells are an obstacle with diffuse faces at solid_T: a
+                                   path is followed cell by cell in the time order of its plane crossings
+                                   (ties: x, then y, then z) and the first solid cell it enters is hit on
+                                   the crossed face.  Copied by dsmc_init_runs.  With inflow, the first
+                                   layer of cells (ix = 0) must be fluid. */
+  double solid_T;               /* temperature of the solid faces (> 0 when solid_mask is given) */
 } dsmc_run_spec;
 
 typedef struct {

@@ -50,7 +50,8 @@ class dsmc_run_spec(C.Structure):
                 ("inflow_n", C.c_double), ("inflow_U", C.c_double), ("inflow_T", C.c_double),
                 ("capacity", C.c_int64), ("n_init", C.c_int64), ("init_U", C.c_double * 3),
                 ("init_T", C.c_double), ("run_id", C.c_uint32), ("seed", C.c_uint32),
-                ("ensemble", C.c_int32), ("reserved", C.c_int32)]
+                ("ensemble", C.c_int32), ("reserved", C.c_int32), ("solid_mask", C.c_void_p),
+                ("solid_T", C.c_double)]
 
 
 class dsmc_options(C.Structure):
@@ -115,10 +116,16 @@ def _check(st: int, where: str, ctx=None):
 # ---------------------------------------------------------------------------
 
 def make_run_spec(rs) -> dsmc_run_spec:
-    """dsmc_run_spec from a ``workloads.RunSpec``."""
-    if rs.solid is not None:
-        raise DsmcError(-6, "make_run_spec", "voxel obstacles are not supported by this library build")
+    """dsmc_run_spec from a ``workloads.RunSpec``.  A solid mask is passed as
+    a pointer to a contiguous byte copy that the returned struct keeps alive."""
     s = dsmc_run_spec()
+    if rs.solid is not None:
+        mask = np.ascontiguousarray(rs.solid, dtype=np.uint8).ravel()
+        if mask.size != rs.nx * rs.ny * rs.nz:
+            raise DsmcError(-1, "make_run_spec", "solid mask must have one entry per cell")
+        s._mask = mask
+        s.solid_mask = mask.ctypes.data
+        s.solid_T = rs.solid_T
     s.dim, s.nx, s.ny, s.nz = rs.dim, rs.nx, rs.ny, rs.nz
     s.lx, s.ly, s.lz = rs.lx, rs.ly, rs.lz
     s.dt, s.fnum_sigma, s.omega, s.c_ref = rs.dt, rs.fnum_sigma, rs.omega, rs.c_ref
@@ -153,7 +160,9 @@ def make_options(state_fp64: bool, n_groups: int, sample_steps: Sequence[int],
 
 
 def _specs(runs):
-    arr = (dsmc_run_spec * len(runs))(*[make_run_spec(r) for r in runs])
+    keep = [make_run_spec(r) for r in runs]
+    arr = (dsmc_run_spec * len(runs))(*keep)
+    arr._keep = keep          # the masks the array points to
     return arr
 
 

@@ -34,10 +34,11 @@ struct Plan {
   std::vector<int32_t> tile_run, face_run, cgroup_run, inflow_runs, eg_start, eg_runs, eg_nc, sample_steps;
   std::vector<int64_t> eg_acc;
   std::vector<int2> items, cell_items;
+  std::vector<uint8_t> solid;
   std::vector<Ensemble> ens;
   std::vector<int64_t> spec_capacity;
   size_t off_runs, off_tile_run, off_face_run, off_cgroup_run, off_inflow, off_eg_start, off_eg_runs, off_eg_acc,
-      off_eg_nc, off_samples, off_items, off_cell_items;
+      off_eg_nc, off_samples, off_items, off_cell_items, off_solid;
   size_t off_P[2][6];
   size_t off_cell, off_lcr, off_lcr_tmp, off_hist, off_tot, off_bin_start, off_remc, off_gmax, off_ncoll, off_remf,
       off_gencnt, off_stage, off_acc, off_mom, off_nalive, off_nsorted, off_ngen, off_scalars, off_wallq, off_wallq_n;
@@ -87,6 +88,13 @@ dsmc_status validate(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_optio
     if (s.n_init < 0 || s.capacity < s.n_init || s.capacity >= ((int64_t)1 << 31) - (1 << 22))
       return fail(msg, DSMC_EINVAL, "run %d: need 0 <= n_init <= capacity < 2^31 - 2^22", r);
     if (s.n_init > 0 && !(s.init_T > 0)) return fail(msg, DSMC_EINVAL, "run %d: init_T must be > 0", r);
+    if (s.solid_mask) {
+      if (!(s.solid_T > 0) || !std::isfinite(s.solid_T))
+        return fail(msg, DSMC_EINVAL, "run %d: solid_T must be > 0", r);
+      if (s.face_bc[0] == DSMC_BC_INFLOW)
+        for (int64_t c = 0; c < nc; c += s.nx)
+          if (s.solid_mask[c]) return fail(msg, DSMC_EINVAL, "run %d: inflow needs fluid cells at ix = 0", r);
+    }
     for (int q = 0; q < r; ++q)
       if (runs[q].ensemble == s.ensemble &&
           (runs[q].nx != s.nx || runs[q].ny != s.ny || runs[q].nz != s.nz || runs[q].lx != s.lx ||
@@ -96,7 +104,16 @@ dsmc_status validate(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_optio
   return DSMC_OK;
 }
 
-// Same initial (sigma c_r)_max rule as everywhere: g at c0 = |U| + 3 sqrt(2 T_max).
+bool any_solid(const dsmc_run_spec &s) {
+  if (!s.solid_mask) return false;
+  const int64_t nc = (int64_t)s.nx * s.ny * s.nz;
+  for (int64_t c = 0; c < nc; ++c)
+    if (s.solid_mask[c]) return true;
+  return false;
+}
+
+// Same initial (sigma c_r)_max rule as everywhere: g at c0 = |U| + 3 sqrt(2 T_max),
+// T_max over the initial gas, the inflow, the diffuse faces and the obstacle.
 double initial_gmax(const dsmc_run_spec &s) {
   const bool inflow = s.face_bc[0] == DSMC_BC_INFLOW;
   double U0 = inflow ? s.inflow_U : 0.0;
@@ -106,6 +123,7 @@ double initial_gmax(const dsmc_run_spec &s) {
   if (inflow && s.inflow_T > Tmax) Tmax = s.inflow_T;
   for (int f = 0; f < 2 * s.dim; ++f)
     if (s.face_bc[f] == DSMC_BC_DIFFUSE && s.face_T[f] > Tmax) Tmax = s.face_T[f];
+  if (any_solid(s) && s.solid_T > Tmax) Tmax = s.solid_T;
   const double c0 = U0 + 3.0 * std::sqrt(2.0 * Tmax);
   if (s.omega == 0.5) return c0;
   return c0 * std::pow(c0 / s.c_ref, 1.0 - 2.0 * s.omega);
@@ -222,6 +240,33 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
     R.init_U[1] = s.init_U[1];
     R.init_U[2] = s.init_U[2];
     R.init_sqrtT = s.init_T > 0 ? std::sqrt(s.init_T) : 0.0;
+    R.d[0] = s.lx / s.nx;
+    R.d[1] = s.ly / s.ny;
+    R.d[2] = s.lz / s.nz;
+    R.has_solid = any_solid(s) ? 1 : 0;
+    if (R.has_solid) g.any_solid = 1;
+    if (R.has_solid) {
+      R.solid_T = s.solid_T;
+      R.solid_sqrtT = std::sqrt(s.solid_T);
+      R.sdo = (int64_t)P.solid.size();
+      for (int a = 0; a < 3; ++a) {
+        R.sb_lo[a] = 1 << 30;
+        R.sb_hi[a] = -1;
+      }
+      for (int32_t iz = 0; iz < s.nz; ++iz)
+        for (int32_t iy = 0; iy < s.ny; ++iy)
+          for (int32_t ix = 0; ix < s.nx; ++ix) {
+            const bool so = s.solid_mask[((int64_t)iz * s.ny + iy) * s.nx + ix] != 0;
+            P.solid.push_back(so ? 1 : 0);
+            if (!so) continue;
+            const int32_t v[3] = {ix, iy, iz};
+            for (int a = 0; a < 3; ++a) {
+              R.sb_lo[a] = std::min(R.sb_lo[a], v[a]);
+              R.sb_hi[a] = std::max(R.sb_hi[a], v[a]);
+            }
+          }
+      P.solid.resize(round_up((int64_t)P.solid.size(), 256), 0);
+    }
     for (int t = 0; t < R.nt; ++t) P.tile_run.push_back(r);
     for (int64_t k = 0; k < round_up(R.nc, 64) / 64; ++k) P.cgroup_run.push_back(r);
     P.spec_capacity[r] = s.capacity;
@@ -334,6 +379,7 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
   P.off_samples = take(4 * P.sample_steps.size());
   P.off_items = take(sizeof(int2) * P.items.size());
   P.off_cell_items = take(sizeof(int2) * P.cell_items.size());
+  P.off_solid = take(P.solid.size());
   for (int b = 0; b < 2; ++b)
     for (int a = 0; a < 6; ++a) P.off_P[b][a] = (a == 2 && g.dim == 2) ? (size_t)-1 : take(es * g.n_slots);
   P.off_cell = take(4 * g.n_slots);
@@ -375,6 +421,7 @@ DevPtrs<real> carve(const Plan &P, char *base) {
   d.sample_steps = (const int32_t *)(base + P.off_samples);
   d.items = (const int2 *)(base + P.off_items);
   d.cell_items = (const int2 *)(base + P.off_cell_items);
+  d.solid = (const uint8_t *)(base + P.off_solid);
   for (int b = 0; b < 2; ++b) {
     real **c[6] = {&d.P[b].x, &d.P[b].y, &d.P[b].z, &d.P[b].u, &d.P[b].v, &d.P[b].w};
     for (int a = 0; a < 6; ++a) *c[a] = P.off_P[b][a] == (size_t)-1 ? nullptr : (real *)(base + P.off_P[b][a]);
@@ -635,6 +682,7 @@ dsmc_status dsmc_init_runs(const dsmc_run_spec *runs, int32_t n_runs, const dsmc
   if (!st) st = upload(c, P.off_samples, P.sample_steps);
   if (!st) st = upload(c, P.off_items, P.items);
   if (!st) st = upload(c, P.off_cell_items, P.cell_items);
+  if (!st) st = upload(c, P.off_solid, P.solid);
   if (!st) st = make_streams(c);
   if (!st) {
     if (P.g.fp64) launch_init<double>(P.g, c->dd, c->stream);

@@ -17,6 +17,7 @@ constexpr int kDigitBits = 11;             // indexing digit: 2048 bins per pass
 constexpr int kDigits = 1 << kDigitBits;
 constexpr int kMaxWallHits = 64;           // wall interactions per particle per step
 constexpr int kMaxGenAttempts = 1000;      // inflow normal-velocity rejection
+constexpr int kMaxInitAttempts = 100;      // initial position draws that land in solid cells
 constexpr int kFields = 7;                 // N, sum u, v, w, u^2, v^2, w^2
 constexpr int kMoments = 8;                // n, ux, uy, uz, T, Tx, Ty, Tz
 
@@ -55,6 +56,12 @@ struct RunDev {
   double face_T[6], face_sqrtT[6];
   double mbar, beta, s_inf, p_branch, inflow_sqrtT, dy, dz;
   double init_U[3], init_sqrtT;
+  // voxel obstacle
+  int32_t has_solid;     // any solid cell
+  int32_t sb_lo[3], sb_hi[3];  // bounding box (cell indices, inclusive) of the solid cells
+  int64_t sdo;           // first byte of the run's solid mask in the mask array
+  double d[3];           // cell size per axis
+  double solid_T, solid_sqrtT;
 };
 
 template <typename real>
@@ -77,6 +84,7 @@ struct DevPtrs {
   const int32_t *sample_steps; // [n_samples]
   const int2 *items;           // [n_items] lane-per-cell interaction items: (run, first cell)
   const int2 *cell_items;      // [n_cell_items] block-per-cell interaction items: (run, cell)
+  const uint8_t *solid;        // solid masks of the runs with obstacles (1 byte per cell)
   Particles<real> P[2];
   int32_t *cell;               // [slots] cell (bin) of each slot after Motion
   int32_t *lcr;                // [slots] run-local slot in cell order
@@ -133,6 +141,7 @@ struct Geometry {
   int64_t n_items;      // lane-per-cell interaction items (up to 64 cells each)
   int64_t n_cell_items; // block-per-cell interaction items
   int collide_mode;      // 0 auto, 1 lane per cell, 2 wave per cell
+  int any_solid;         // some run has solid cells (Motion checks paths against them)
   int n_lanes;           // run groups per step (1: everything on the caller's stream)
   LaneRange lane[kMaxLanes];
 };

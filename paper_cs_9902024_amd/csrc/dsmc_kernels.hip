@@ -113,6 +113,15 @@ __device__ __forceinline__ real g_of(const RunDev &R, real cr) {
 
 __device__ __forceinline__ int32_t blocks_for(int64_t n, int per) { return (int32_t)((n + per - 1) / per); }
 
+// Run-local cell of a position (floor per axis, clamped to the grid).
+template <typename real, int DIM>
+__device__ __forceinline__ int32_t cell_of(const RunDev &R, const real (&pos)[3]) {
+  const int32_t ix = axis_index(pos[0], (real)R.inv_d[0], R.nx);
+  const int32_t iy = axis_index(pos[1], (real)R.inv_d[1], R.ny);
+  const int32_t iz = (DIM == 3) ? axis_index(pos[2], (real)R.inv_d[2], R.nz) : 0;
+  return (iz * R.ny + iy) * R.nx + ix;
+}
+
 // ---------------------------------------------------------------------------
 // Initialisation
 // ---------------------------------------------------------------------------
@@ -156,7 +165,7 @@ __global__ __launch_bounds__(256) void k_init_runs(DevPtrs<real> d, int n_runs) 
 
 // Uniform Maxwellian fill: slot i draws from (step 0, INIT, i).  Uniforms 0..3
 // are two Box-Muller pairs for the velocity (last output unused), 4..6 the
-// position.
+// position, drawn again (7..9, ...) while it lies in a solid cell.
 template <typename real, int DIM>
 __global__ __launch_bounds__(256) void k_init_particles(DevPtrs<real> d, int64_t n_slots, int64_t tile) {
   Particles<real> P = d.P[0];
@@ -174,10 +183,21 @@ __global__ __launch_bounds__(256) void k_init_particles(DevPtrs<real> d, int64_t
     P.u[i] = (real)R.init_U[0] + st * n0;
     P.v[i] = (real)R.init_U[1] + st * n1;
     P.w[i] = (real)R.init_U[2] + st * n2;
-    const real ux = s(), uy = s(), uz = s();
-    P.x[i] = ux * (real)R.L[0];
-    P.y[i] = uy * (real)R.L[1];
-    if (DIM == 3) P.z[i] = uz * (real)R.L[2];
+    real pos[3];
+    for (int att = 0;; ++att) {
+      if (att == kMaxInitAttempts) {
+        set_error(d.err, kErrReject);
+        break;
+      }
+      const real ux = s(), uy = s(), uz = s();
+      pos[0] = ux * (real)R.L[0];
+      pos[1] = uy * (real)R.L[1];
+      pos[2] = DIM == 3 ? uz * (real)R.L[2] : (real)0;
+      if (!R.has_solid || !d.solid[R.sdo + cell_of<real, DIM>(R, pos)]) break;
+    }
+    P.x[i] = pos[0];
+    P.y[i] = pos[1];
+    if (DIM == 3) P.z[i] = pos[2];
   }
 }
 
@@ -314,11 +334,104 @@ __global__ __launch_bounds__(256) void k_gen_emit(DevPtrs<real> d, int buf, int3
 // Motion + Enumeration
 // ---------------------------------------------------------------------------
 
-// Moves one particle for dt (specular / diffuse / open faces); returns the new
-// cell, or nc (DEAD) when it leaves.  hit reports a velocity change.
+// Voxel obstacle: follows the straight path from pos (in cell vox) with
+// velocity vel for a time tlim, crossing cell planes (k * d, k = 0..n) in time
+// order, ties to the lower axis.  Returns the axis of the face of the first
+// solid cell entered and its time in th, or -1 if none; vox follows the path
+// up to that face (or up to tlim).
 template <typename real, int DIM>
-__device__ __forceinline__ int32_t move_one(const RunDev &R, uint32_t step, uint32_t slot, real (&pos)[3],
-                                            real (&vel)[3], bool &hit, bool &reemit, int32_t *err) {
+__device__ __forceinline__ int solid_walk(const RunDev &R, const uint8_t *solid, const real (&pos)[3],
+                                          const real (&vel)[3], real tlim, int32_t (&vox)[3], real &th) {
+  const int32_t n[3] = {R.nx, R.ny, R.nz};
+  for (;;) {
+    real tn = infinity<real>();
+    int ax = -1;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      real t;
+      if (vel[a] > (real)0) t = ((real)(vox[a] + 1) * (real)R.d[a] - pos[a]) / vel[a];
+      else if (vel[a] < (real)0) t = ((real)vox[a] * (real)R.d[a] - pos[a]) / vel[a];
+      else continue;
+      if (t < tn) {
+        tn = t;
+        ax = a;
+      }
+    }
+    if (ax < 0 || !(tn < tlim)) return -1;
+    int32_t nv[3] = {vox[0], vox[1], vox[2]};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+      if (a == ax) nv[a] += vel[a] > (real)0 ? 1 : -1;
+    int32_t na = 0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+      if (a == ax) na = nv[a];
+    if (na < 0 || na >= n[ax]) return -1;  // a domain face: not the walk's
+    if (solid[R.sdo + ((int64_t)nv[2] * R.ny + nv[1]) * R.nx + nv[0]]) {
+      th = tn > (real)0 ? tn : (real)0;
+      return ax;
+    }
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) vox[a] = nv[a];
+  }
+}
+
+// Neighbouring representable values of a finite x (IEEE bit patterns are
+// ordered like the magnitudes they encode).
+__device__ __forceinline__ double next_toward(double x, bool up) {
+  if (x == 0.0) return up ? 0x1p-1074 : -0x1p-1074;
+  const int64_t b = __double_as_longlong(x);
+  return __longlong_as_double(((x > 0.0) == up) ? b + 1 : b - 1);
+}
+__device__ __forceinline__ float next_toward(float x, bool up) {
+  if (x == 0.0f) return up ? 0x1p-149f : -0x1p-149f;
+  const int32_t b = __float_as_int(x);
+  return __int_as_float(((x > 0.0f) == up) ? b + 1 : b - 1);
+}
+
+// Coordinate x moved by rounding steps into cell i along an axis (cell size
+// d, n cells): used when an end point rounds across the face of a solid cell
+// next to the fluid cell its path ended in.
+template <typename real>
+__device__ __forceinline__ real snap_into(real x, int32_t i, real d, real inv, int32_t n) {
+  if (axis_index(x, inv, n) > i) {
+    x = (real)(i + 1) * d;
+    while (axis_index(x, inv, n) > i) x = next_toward(x, false);
+  } else {
+    x = (real)i * d;
+    while (axis_index(x, inv, n) < i) x = next_toward(x, true);
+  }
+  return x;
+}
+
+// Diffuse re-emission at temperature Tw (sqrt stw) from a surface with normal
+// axis ax; side 1: the particle arrived moving +, so it leaves moving -.
+// Uniforms 4h .. 4h+2 of the slot's WALL stream for the h-th wall interaction.
+template <typename real>
+__device__ __forceinline__ void diffuse_emit(const RunDev &R, uint32_t step, uint32_t slot, int hits, real Tw,
+                                             real stw, int ax, int side, real (&vel)[3]) {
+  UStream<real> ws(R.key0, R.key1, step, kWall, slot);
+  ws.seek(4u * (uint32_t)hits);
+  const real w0 = ws(), w1 = ws(), w2 = ws();
+  const real vn = sqrt((real)-2 * Tw * log(w0));
+  real n0, n1;
+  box_muller(w1, w2, n0, n1);
+  const int t1 = (ax == 0) ? 1 : 0, t2 = (ax == 2) ? 1 : 2;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (a == ax) vel[a] = side ? -vn : vn;
+    else if (a == t1) vel[a] = stw * n0;
+    else if (a == t2) vel[a] = stw * n1;
+  }
+}
+
+// Moves one particle for dt (specular / diffuse / open faces, solid cells);
+// returns the new cell, or nc (DEAD) when it leaves.  hit reports a velocity
+// change, reemit a diffuse re-emission (w changed in 2-D).
+template <typename real, int DIM>
+__device__ __forceinline__ int32_t move_one(const RunDev &R, const uint8_t *solid, uint32_t step, uint32_t slot,
+                                            real (&pos)[3], real (&vel)[3], bool &hit, bool &reemit,
+                                            int32_t *err) {
   real L[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) L[a] = (real)R.L[a];
@@ -326,6 +439,8 @@ __device__ __forceinline__ int32_t move_one(const RunDev &R, uint32_t step, uint
   int hits = 0;
   hit = false;
   reemit = false;
+  int32_t vox[3] = {axis_index(pos[0], (real)R.inv_d[0], R.nx), axis_index(pos[1], (real)R.inv_d[1], R.ny),
+                    DIM == 3 ? axis_index(pos[2], (real)R.inv_d[2], R.nz) : 0};
   for (;;) {
     real tmin = infinity<real>();
     int ax = -1, side = 0;
@@ -349,6 +464,32 @@ __device__ __forceinline__ int32_t move_one(const RunDev &R, uint32_t step, uint
         side = sd;
       }
     }
+    if (R.has_solid) {
+      // a solid cell entered before the domain face (or the end of the step)
+      real ts;
+      const int sa = solid_walk<real, DIM>(R, solid, pos, vel, (ax < 0 || tmin >= trem) ? trem : tmin, vox, ts);
+      if (sa >= 0) {
+        int up = 0;
+        real plane = (real)0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+          if (a == sa) {
+            up = vel[a] > (real)0;
+            plane = (real)(up ? vox[a] + 1 : vox[a]) * (real)R.d[a];
+          }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) pos[a] = (a == sa) ? plane : pos[a] + vel[a] * ts;
+        trem = trem - ts;
+        hit = true;
+        reemit = true;
+        diffuse_emit<real>(R, step, slot, hits, (real)R.solid_T, (real)R.solid_sqrtT, sa, up, vel);
+        if (++hits == kMaxWallHits) {
+          set_error(err, kErrBounce);
+          break;
+        }
+        continue;
+      }
+    }
     if (ax < 0 || tmin >= trem) {
 #pragma unroll
       for (int a = 0; a < DIM; ++a) pos[a] = pos[a] + vel[a] * trem;
@@ -365,22 +506,8 @@ __device__ __forceinline__ int32_t move_one(const RunDev &R, uint32_t step, uint
       for (int a = 0; a < DIM; ++a)
         if (a == ax) vel[a] = -vel[a];
     } else if (bc == kDiffuse) {
-      const real Tw = (real)R.face_T[f];
       reemit = true;
-      UStream<real> ws(R.key0, R.key1, step, kWall, slot);
-      ws.seek(4u * (uint32_t)hits);
-      const real w0 = ws(), w1 = ws(), w2 = ws();
-      const real vn = sqrt((real)-2 * Tw * log(w0));
-      real n0, n1;
-      box_muller(w1, w2, n0, n1);
-      const real stw = (real)R.face_sqrtT[f];
-      const int t1 = (ax == 0) ? 1 : 0, t2 = (ax == 2) ? 1 : 2;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        if (a == ax) vel[a] = side ? -vn : vn;
-        else if (a == t1) vel[a] = stw * n0;
-        else if (a == t2) vel[a] = stw * n1;
-      }
+      diffuse_emit<real>(R, step, slot, hits, (real)R.face_T[f], (real)R.face_sqrtT[f], ax, side, vel);
     } else {
       return R.nc;  // inflow plane crossed outward, or outflow
     }
@@ -390,10 +517,44 @@ __device__ __forceinline__ int32_t move_one(const RunDev &R, uint32_t step, uint
     }
   }
   if (pos[0] < (real)0) return R.nc;  // generated upstream and never entered
-  const int32_t ix = axis_index(pos[0], (real)R.inv_d[0], R.nx);
-  const int32_t iy = axis_index(pos[1], (real)R.inv_d[1], R.ny);
-  const int32_t iz = (DIM == 3) ? axis_index(pos[2], (real)R.inv_d[2], R.nz) : 0;
-  return (iz * R.ny + iy) * R.nx + ix;
+  int32_t c = cell_of<real, DIM>(R, pos);
+  if (R.has_solid && solid[R.sdo + c]) {
+    // rounding put the end point across the face of a solid cell: it belongs
+    // to the fluid cell the path ended in
+    const int32_t n[3] = {R.nx, R.ny, R.nz};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      const real inv = (real)R.inv_d[a];
+      if (axis_index(pos[a], inv, n[a]) != vox[a]) pos[a] = snap_into<real>(pos[a], vox[a], (real)R.d[a], inv, n[a]);
+    }
+    c = cell_of<real, DIM>(R, pos);
+  }
+  return c;
+}
+
+// Fast-path check for runs with solid cells: the straight flight for dt from
+// pos to out (no domain face reached) enters no solid cell and ends in a
+// fluid cell.  Exactly the decision move_one takes: its walk is run whenever
+// the cells around the path (one cell of margin for rounding) meet the
+// bounding box of the solid cells.
+template <typename real, int DIM>
+__device__ __forceinline__ bool clear_of_solid(const RunDev &R, const uint8_t *solid, const real (&pos)[3],
+                                               const real (&vel)[3], const real (&out)[3]) {
+  const int32_t n[3] = {R.nx, R.ny, R.nz};
+  int32_t v0[3] = {0, 0, 0}, v1[3] = {0, 0, 0};
+  bool meets = true;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const real inv = (real)R.inv_d[a];
+    v0[a] = axis_index(pos[a], inv, n[a]);
+    v1[a] = axis_index(out[a], inv, n[a]);
+    const int32_t lo = min(v0[a], v1[a]) - 1, hi = max(v0[a], v1[a]) + 1;
+    meets = meets && hi >= R.sb_lo[a] && lo <= R.sb_hi[a];
+  }
+  if (!meets) return true;
+  real th;
+  if (solid_walk<real, DIM>(R, solid, pos, vel, (real)R.dt, v0, th) >= 0) return false;
+  return !solid[R.sdo + ((int64_t)v1[2] * R.ny + v1[1]) * R.nx + v1[0]];
 }
 
 // Free flight with no face reached this step, decided without divisions:
@@ -454,7 +615,7 @@ __device__ __forceinline__ void store4(real *p, int64_t i, const real (&o)[4]) {
 // go to the tile's wall queue (k_motion_walls).  The new cell of every free
 // particle is counted in the tile's histogram of the first indexing digit,
 // kept in wave-private LDS.
-template <typename real, int DIM, bool SINGLE>
+template <typename real, int DIM, bool SINGLE, bool OBST>
 __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_t t0, int32_t t1, int64_t tile,
                                                 int dstride) {
   extern __shared__ uint32_t lds[];
@@ -518,6 +679,7 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
       const real vel[3] = {vx[e], vy[e], DIM == 3 ? vz[e] : (real)0};
       real out[3];
       fast[e] = act[e] && free_flight<real, DIM>(R, pos, vel, out);
+      if (OBST && R.has_solid && fast[e]) fast[e] = clear_of_solid<real, DIM>(R, d.solid, pos, vel, out);
       ox[e] = fast[e] ? out[0] : px[e];
       oy[e] = fast[e] ? out[1] : py[e];
       oz[e] = (DIM == 3 && fast[e]) ? out[2] : (DIM == 3 ? pz[e] : (real)0);
@@ -587,7 +749,7 @@ __global__ __launch_bounds__(256) void k_motion_walls(DevPtrs<real> d, int buf, 
     real p3[3] = {P.x[gs], P.y[gs], DIM == 3 ? P.z[gs] : (real)0};
     real v3[3] = {P.u[gs], P.v[gs], DIM == 3 ? P.w[gs] : (real)0};
     bool hit, reemit;
-    const int32_t c = move_one<real, DIM>(R, step, (uint32_t)loc, p3, v3, hit, reemit, d.err);
+    const int32_t c = move_one<real, DIM>(R, d.solid, step, (uint32_t)loc, p3, v3, hit, reemit, d.err);
     P.x[gs] = p3[0];
     P.y[gs] = p3[1];
     if (DIM == 3) P.z[gs] = p3[2];
@@ -882,12 +1044,26 @@ __device__ __forceinline__ Selection<real> draw_selection(const RunDev &R, uint3
 
 // Isotropic scattering of one accepted pair.
 template <typename real>
-__device__ __forceinline__ void scatter_pair(real cr, real uc, real ue, real &ui, real &vi, real &wi, real &uj,
-                                             real &vj, real &wj) {
-  const real cosx = (real)2 * uc - (real)1;
-  const real sinx = sqrt((real)1 - cosx * cosx);
+struct Angles {
+  real cosx, sinx, ce, se;  // cos chi, sin chi, cos eps, sin eps
+};
+
+// Deflection angles of a selection from its two scattering uniforms.
+template <typename real>
+__device__ __forceinline__ Angles<real> angles_of(real uc, real ue) {
+  Angles<real> a;
+  a.cosx = (real)2 * uc - (real)1;
+  a.sinx = sqrt((real)1 - a.cosx * a.cosx);
   const real eps = two_pi<real>() * ue;
-  const real rx = cr * cosx, ry = cr * sinx * cos(eps), rz = cr * sinx * sin(eps);
+  a.ce = cos(eps);
+  a.se = sin(eps);
+  return a;
+}
+
+template <typename real>
+__device__ __forceinline__ void scatter_pair(real cr, const Angles<real> &an, real &ui, real &vi, real &wi,
+                                             real &uj, real &vj, real &wj) {
+  const real rx = cr * an.cosx, ry = cr * an.sinx * an.ce, rz = cr * an.sinx * an.se;
   const real mx = (real)0.5 * (ui + uj), my = (real)0.5 * (vi + vj), mz = (real)0.5 * (wi + wj);
   ui = mx + (real)0.5 * rx;
   vi = my + (real)0.5 * ry;
@@ -911,7 +1087,7 @@ __device__ uint32_t chain_serial(const RunDev &R, uint32_t step, uint32_t c, uin
     if (g > gm) gm = g;
     if (!(s.ua < g / gm)) continue;
     real ui = u[s.i], vi = v[s.i], wi = w[s.i], uj = u[s.j], vj = v[s.j], wj = w[s.j];
-    scatter_pair(cr, s.uc, s.ue, ui, vi, wi, uj, vj, wj);
+    scatter_pair(cr, angles_of(s.uc, s.ue), ui, vi, wi, uj, vj, wj);
     u[s.i] = ui; v[s.i] = vi; w[s.i] = wi;
     u[s.j] = uj; v[s.j] = vj; w[s.j] = wj;
     ncol++;
@@ -1126,7 +1302,12 @@ __device__ uint32_t chain_block(const RunDev &R, uint32_t step, uint32_t c, uint
   while (w0 < nsel) {
     const bool act = w0 + tid < nsel;
     Selection<real> s{0u, 0u, (real)0, (real)0, (real)0};
-    if (act) s = draw_selection<real>(R, step, c, w0 + tid, N);
+    Angles<real> an{(real)1, (real)0, (real)1, (real)0};
+    if (act) {
+      s = draw_selection<real>(R, step, c, w0 + tid, N);
+      // deflection angles once per selection, not once per conflict round
+      an = angles_of(s.uc, s.ue);
+    }
     bool pending = act, accepted = false;
     int my_round = -1;
     real g = (real)0;
@@ -1153,7 +1334,7 @@ __device__ uint32_t chain_block(const RunDev &R, uint32_t step, uint32_t c, uint
         g = g_of<real>(R, cr);
         accepted = s.ua < g / gm;
         if (accepted) {
-          scatter_pair(cr, s.uc, s.ue, ui, vi, wi, uj, vj, wj);
+          scatter_pair(cr, an, ui, vi, wi, uj, vj, wj);
           u[s.i] = ui; v[s.i] = vi; w[s.i] = wi;
           u[s.j] = uj; v[s.j] = vj; w[s.j] = wj;
         }
@@ -1192,7 +1373,7 @@ __device__ uint32_t chain_block(const RunDev &R, uint32_t step, uint32_t c, uint
       const real gnew = gg > gm ? gg : gm;
       const bool acc = s.ua < gg / gnew;
       if (acc) {
-        scatter_pair(cr, s.uc, s.ue, ui, vi, wi, uj, vj, wj);
+        scatter_pair(cr, an, ui, vi, wi, uj, vj, wj);
         u[s.i] = ui; v[s.i] = vi; w[s.i] = wi;
         u[s.j] = uj; v[s.j] = vj; w[s.j] = wj;
       }
@@ -1520,15 +1701,23 @@ static void lane_step(const Geometry &g, const LaneRange &L, const DevPtrs<real>
   a.t1 = L.t1;
   a.r0 = L.r0;
   if (g.npass == 1) {
-    TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, true>), dim3(wblocks), dim3(256), lds, s, d, buf, L.t0,
-                                       L.t1, g.tile, g.dstride));
+    if (g.any_solid)
+      TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, true, true>), dim3(wblocks), dim3(256), lds, s, d, buf,
+                                         L.t0, L.t1, g.tile, g.dstride));
+    else
+      TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, true, false>), dim3(wblocks), dim3(256), lds, s, d,
+                                         buf, L.t0, L.t1, g.tile, g.dstride));
     TIMED(kKMotionWalls, hipLaunchKernelGGL((k_motion_walls<real, DIM, true>), dim3(n_tiles), dim3(256), 0, s, d,
                                             buf, L.t0, L.t1, g.tile));
     if (moved) (void)hipEventRecord(moved, s);
     index_pass(a, g.max_nc + 1, n_runs, 0, nullptr, d.lcr, s, prof);
   } else {
-    TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, false>), dim3(wblocks), dim3(256), lds, s, d, buf, L.t0,
-                                       L.t1, g.tile, g.dstride));
+    if (g.any_solid)
+      TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, false, true>), dim3(wblocks), dim3(256), lds, s, d,
+                                         buf, L.t0, L.t1, g.tile, g.dstride));
+    else
+      TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, false, false>), dim3(wblocks), dim3(256), lds, s, d,
+                                         buf, L.t0, L.t1, g.tile, g.dstride));
     TIMED(kKMotionWalls, hipLaunchKernelGGL((k_motion_walls<real, DIM, false>), dim3(n_tiles), dim3(256), 0, s, d,
                                             buf, L.t0, L.t1, g.tile));
     if (moved) (void)hipEventRecord(moved, s);

@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported(dsmc):
 
 def test_struct_sizes_match_header(dsmc):
     # layout of the two public structs (x86-64 SysV ABI)
-    assert C.sizeof(dsmc.dsmc_run_spec) == 232
+    assert C.sizeof(dsmc.dsmc_run_spec) == 248
     assert C.sizeof(dsmc.dsmc_options) == 40
 
 
@@ -112,6 +112,26 @@ def test_init_rejects_before_touching_the_device(dsmc):
     assert st == -2 and not ctx.value
     st = dsmc.lib().dsmc_init_runs(specs, 0, C.byref(opt), None, 0, None, C.byref(ctx))
     assert st == -1
+
+
+def test_obstacle_specs(dsmc):
+    """Solid masks are sized into the arena and validated on the host."""
+    from dataclasses import replace
+    wl = W.body3d(n_runs=2, grid=(40, 20, 20), n_per_run=100_000, n_steps=1, n_samples=1)
+    with_mask = _bytes(dsmc, wl)
+    without = _bytes(dsmc, wl.with_runs([replace(r, solid=None) for r in wl.runs]))
+    assert with_mask - without >= 2 * 40 * 20 * 20
+    bad_T = replace(wl.runs[0], solid_T=0.0)
+    with pytest.raises(dsmc.DsmcError) as e:
+        _bytes(dsmc, wl.with_runs([bad_T]))
+    assert e.value.status == -1
+    m = wl.runs[0].solid.copy()
+    m[3, 4, 0] = 1                      # a solid cell in the inflow layer
+    with pytest.raises(dsmc.DsmcError) as e:
+        _bytes(dsmc, wl.with_runs([replace(wl.runs[0], solid=m)]))
+    assert e.value.status == -1
+    with pytest.raises(dsmc.DsmcError):
+        dsmc.make_run_spec(replace(wl.runs[0], solid=m[:, :, :5]))
 
 
 def test_counting_sort_workspace_query(dsmc):
