@@ -41,7 +41,8 @@ struct Plan {
       off_eg_nc, off_samples, off_items, off_cell_items, off_solid;
   size_t off_P[2][6];
   size_t off_cell, off_lcr, off_lcr_tmp, off_hist, off_tot, off_bin_start, off_remc, off_gmax, off_ncoll, off_remf,
-      off_gencnt, off_stage, off_acc, off_mom, off_nalive, off_nsorted, off_ngen, off_scalars, off_wallq, off_wallq_n;
+      off_gencnt, off_stage, off_acc, off_mom, off_nalive, off_nsorted, off_ngen, off_scalars, off_wallq, off_wallq_n,
+      off_key_tmp;
   size_t total;
 };
 
@@ -387,6 +388,7 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
   P.off_wallq = take(4 * g.n_slots);
   P.off_wallq_n = take(4 * (size_t)g.n_tiles);
   P.off_lcr_tmp = g.npass > 1 ? take(4 * g.n_slots) : (size_t)-1;
+  P.off_key_tmp = g.npass > 1 ? take(4 * g.n_slots) : (size_t)-1;
   P.off_hist = take(4 * (size_t)mo);
   P.off_tot = take(4 * (size_t)cbo);
   P.off_bin_start = take(4 * (size_t)bo);
@@ -429,6 +431,7 @@ DevPtrs<real> carve(const Plan &P, char *base) {
   d.cell = (int32_t *)(base + P.off_cell);
   d.lcr = (int32_t *)(base + P.off_lcr);
   d.lcr_tmp = P.off_lcr_tmp == (size_t)-1 ? nullptr : (int32_t *)(base + P.off_lcr_tmp);
+  d.key_tmp = P.off_key_tmp == (size_t)-1 ? nullptr : (int32_t *)(base + P.off_key_tmp);
   d.hist = (uint32_t *)(base + P.off_hist);
   d.digit_tot = (uint32_t *)(base + P.off_tot);
   d.bin_start = (uint32_t *)(base + P.off_bin_start);

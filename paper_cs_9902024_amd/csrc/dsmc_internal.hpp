@@ -89,6 +89,7 @@ struct DevPtrs {
   int32_t *cell;               // [slots] cell (bin) of each slot after Motion
   int32_t *lcr;                // [slots] run-local slot in cell order
   int32_t *lcr_tmp;            // [slots] previous indexing pass (multi-pass only)
+  int32_t *key_tmp;            // [slots] bins carried between indexing passes (multi-pass only)
   uint32_t *hist;              // tile histograms, tile-major
   uint32_t *digit_tot;         // per run digit totals / digit starts
   uint32_t *bin_start;         // per run nc + 2 entries, run-local

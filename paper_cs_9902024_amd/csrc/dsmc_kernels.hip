@@ -774,6 +774,9 @@ struct IndexArgs {
   const int32_t *cell;     // bin of each slot (slot order)
   const int32_t *in;       // previous pass order (run-local slots) or null: identity
   int32_t *out;            // this pass' order
+  const int32_t *kin;      // bins in the order of `in` (carried from the previous pass), or null:
+                           // read cell[in[k]]
+  int32_t *kout;           // bins in the order of `out`, or null
   uint32_t *hist;          // tile histograms, tile-major: [tile][digit]
   uint32_t *tot;           // per run digit totals -> digit starts
   uint32_t *bin_start;     // per run nc + 2 bin starts (single pass / bounds)
@@ -808,11 +811,29 @@ __global__ __launch_bounds__(256) void k_digcount(IndexArgs a, int use_n_alive) 
   wave_sync();
   const int64_t n = use_n_alive ? a.n_alive[r] : a.n_sorted[r];
   const int64_t begin = tl * a.tile, end = min(begin + a.tile, n);
-  for (int64_t b = begin; b < end; b += kWave) {
-    const int64_t loc = b + lane;
-    if (loc < end) {
-      const int32_t v = a.in ? a.in[R.so + loc] : (int32_t)loc;
-      atomicAdd(&h[digit_of(a.cell[R.so + v], a.pass, single)], 1u);
+  if (a.kin) {
+    // carried bins: a sequential read, 4 consecutive per lane
+    const int32_t *__restrict__ kin = a.kin + R.so;
+    for (int64_t b = begin; b < end; b += 4 * kWave) {
+      const int64_t i0 = b + 4 * lane;
+      if (b + 4 * kWave <= end) {
+        const int4 k4 = *reinterpret_cast<const int4 *>(kin + i0);
+        atomicAdd(&h[digit_of(k4.x, a.pass, single)], 1u);
+        atomicAdd(&h[digit_of(k4.y, a.pass, single)], 1u);
+        atomicAdd(&h[digit_of(k4.z, a.pass, single)], 1u);
+        atomicAdd(&h[digit_of(k4.w, a.pass, single)], 1u);
+      } else {
+        for (int e = 0; e < 4; ++e)
+          if (i0 + e < end) atomicAdd(&h[digit_of(kin[i0 + e], a.pass, single)], 1u);
+      }
+    }
+  } else {
+    for (int64_t b = begin; b < end; b += kWave) {
+      const int64_t loc = b + lane;
+      if (loc < end) {
+        const int32_t v = a.in ? a.in[R.so + loc] : (int32_t)loc;
+        atomicAdd(&h[digit_of(a.cell[R.so + v], a.pass, single)], 1u);
+      }
     }
   }
   wave_sync();
@@ -900,6 +921,10 @@ __global__ __launch_bounds__(256) void k_digscan(IndexArgs a) {
 // tiles) + (count in earlier rounds of this tile) + (earlier lanes with the
 // same digit, from ballots).  That is exactly the sequential stable order.
 // The first two terms are summed into the wave's LDS cursor table up front.
+// KEYS: the bins come from a.kin (or cell[] in pass 0) and are written to
+// a.kout in the output order, so later passes and the bin bounds read them
+// sequentially instead of gathering cell[] through the order.
+template <bool KEYS>
 __global__ __launch_bounds__(256) void k_scatter(IndexArgs a) {
   extern __shared__ uint32_t lds[];
   constexpr int U = 16;
@@ -924,8 +949,11 @@ __global__ __launch_bounds__(256) void k_scatter(IndexArgs a) {
   const int32_t *__restrict__ in = a.in ? a.in + R.so : nullptr;
   const int32_t *__restrict__ cell = a.cell + R.so;
   int32_t *__restrict__ out = a.out + R.so;
+  const int32_t *__restrict__ kin = KEYS && a.kin ? a.kin + R.so : nullptr;
+  int32_t *__restrict__ kout = KEYS ? a.kout + R.so : nullptr;
   for (int64_t b = begin; b < end; b += U * kWave) {
     int32_t v[U];
+    int32_t bin[U];
     uint32_t key[U];
     bool act[U];
 #pragma unroll
@@ -933,9 +961,13 @@ __global__ __launch_bounds__(256) void k_scatter(IndexArgs a) {
       const int64_t loc = b + q * kWave + lane;
       act[q] = loc < end;
       v[q] = act[q] ? (in ? in[loc] : (int32_t)loc) : 0;
+      if (KEYS && kin) bin[q] = act[q] ? kin[loc] : 0;
     }
 #pragma unroll
-    for (int q = 0; q < U; ++q) key[q] = act[q] ? digit_of(cell[v[q]], a.pass, single) : 0u;
+    for (int q = 0; q < U; ++q) {
+      if (!(KEYS && kin)) bin[q] = act[q] ? cell[v[q]] : 0;
+      key[q] = act[q] ? digit_of(bin[q], a.pass, single) : 0u;
+    }
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       // lanes holding the same digit: one ballot per distinct digit present
@@ -954,6 +986,7 @@ __global__ __launch_bounds__(256) void k_scatter(IndexArgs a) {
         const uint32_t cnt = __popcll(peers);
         const uint32_t prior = cursor[key[q]];
         out[prior + rank] = v[q];
+        if (KEYS) kout[prior + rank] = bin[q];
         if (rank == cnt - 1) cursor[key[q]] = prior + cnt;
       }
       wave_sync();
@@ -962,19 +995,35 @@ __global__ __launch_bounds__(256) void k_scatter(IndexArgs a) {
 }
 
 // Bin starts from the final order (multi-pass): position p starts every bin in
-// (bin(p-1), bin(p)].
-__global__ __launch_bounds__(256) void k_bin_bounds(IndexArgs a, const int32_t *lcr, int64_t s0, int64_t s1) {
-  for (int64_t i = s0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < s1;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const RunDev &R = a.runs[a.tile_run[i / a.tile]];
-    const int64_t loc = i - R.so;
-    const int64_t n = a.n_sorted[a.tile_run[i / a.tile]];
-    if (loc >= n) continue;
-    const int32_t b = a.cell[R.so + lcr[i]];
-    const int32_t bp = loc > 0 ? a.cell[R.so + lcr[i - 1]] : -1;
-    for (int32_t q = bp + 1; q <= b; ++q) a.bin_start[R.bo + q] = (uint32_t)loc;
-    if (loc == n - 1)
-      for (int32_t q = b + 1; q <= R.nc + 1; ++q) a.bin_start[R.bo + q] = (uint32_t)n;
+// (bin(p-1), bin(p)].  sorted[] holds the bin at each sorted position (the
+// keys the last pass carried).  One wavefront per tile of tiles [a.t0, a.t1),
+// four consecutive positions per lane.
+__global__ __launch_bounds__(256) void k_bin_bounds(IndexArgs a, const int32_t *sorted) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int t = a.t0 + (int)blockIdx.x * kWavesPerBlock + wave;
+  if (t >= a.t1) return;
+  const int r = a.tile_run[t];
+  const RunDev &R = a.runs[r];
+  const int64_t n = a.n_sorted[r];
+  const int64_t begin = (int64_t)(t - R.to) * a.tile, end = min(begin + a.tile, n);
+  const int32_t *__restrict__ key = sorted + R.so;
+  uint32_t *__restrict__ bs = a.bin_start + R.bo;
+  for (int64_t b = begin; b < end; b += 4 * kWave) {
+    const int64_t i0 = b + 4 * lane;
+    int32_t k[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) k[e] = i0 + e < end ? key[i0 + e] : 0;
+    int32_t prev = __shfl_up(k[3], 1);
+    if (lane == 0) prev = b > 0 ? key[b - 1] : -1;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t loc = i0 + e;
+      if (loc >= end) break;
+      for (int32_t q = prev + 1; q <= k[e]; ++q) bs[q] = (uint32_t)loc;
+      if (loc == n - 1)
+        for (int32_t q = k[e] + 1; q <= R.nc + 1; ++q) bs[q] = (uint32_t)n;
+      prev = k[e];
+    }
   }
 }
 
@@ -1621,6 +1670,8 @@ static IndexArgs index_args(const Geometry &g, const DevPtrs<real> &d) {
   a.cell = d.cell;
   a.in = nullptr;
   a.out = d.lcr;
+  a.kin = nullptr;
+  a.kout = nullptr;
   a.hist = d.hist;
   a.tot = d.digit_tot;
   a.bin_start = d.bin_start;
@@ -1661,7 +1712,10 @@ static void index_pass(IndexArgs a, int max_digits, int n_runs, int pass, const 
   const int wblocks = (a.t1 - a.t0 + kWavesPerBlock - 1) / kWavesPerBlock;
   TIMED(kKColScan, hipLaunchKernelGGL(k_colscan, dim3((max_digits + 255) / 256, n_runs), dim3(256), 0, s, a));
   TIMED(kKDigScan, hipLaunchKernelGGL(k_digscan, dim3(n_runs), dim3(256), 0, s, a));
-  TIMED(kKScatter, hipLaunchKernelGGL(k_scatter, dim3(wblocks), dim3(256), lds, s, a));
+  if (a.kout)
+    TIMED(kKScatter, hipLaunchKernelGGL(k_scatter<true>, dim3(wblocks), dim3(256), lds, s, a));
+  else
+    TIMED(kKScatter, hipLaunchKernelGGL(k_scatter<false>, dim3(wblocks), dim3(256), lds, s, a));
 }
 
 template <typename real>
@@ -1721,20 +1775,26 @@ static void lane_step(const Geometry &g, const LaneRange &L, const DevPtrs<real>
     TIMED(kKMotionWalls, hipLaunchKernelGGL((k_motion_walls<real, DIM, false>), dim3(n_tiles), dim3(256), 0, s, d,
                                             buf, L.t0, L.t1, g.tile));
     if (moved) (void)hipEventRecord(moved, s);
-    const int32_t *in = nullptr;
+    // bins are carried through the passes: key_tmp and (free after Motion)
+    // the wall queue alternate as key buffers
+    int32_t *kbuf[2] = {d.key_tmp, (int32_t *)d.wallq};
+    const int32_t *in = nullptr, *kin = nullptr;
     for (int p = 0; p < g.npass; ++p) {
       int32_t *out = ((g.npass - 1 - p) % 2 == 0) ? d.lcr : d.lcr_tmp;
+      int32_t *kout = kbuf[p % 2];
       if (p > 0) {
         a.pass = p;
         a.in = in;
+        a.kin = kin;
         TIMED(kKDigCount, hipLaunchKernelGGL(k_digcount, dim3(wblocks), dim3(256), lds, s, a, 0));
       }
+      a.kin = kin;
+      a.kout = kout;
       index_pass(a, kDigits, n_runs, p, in, out, s, prof);
       in = out;
+      kin = kout;
     }
-    const int64_t s0 = (int64_t)L.t0 * g.tile, s1 = (int64_t)L.t1 * g.tile;
-    TIMED(kKBinBounds,
-          hipLaunchKernelGGL(k_bin_bounds, dim3(grid_for(s1 - s0)), dim3(256), 0, s, a, d.lcr, s0, s1));
+    TIMED(kKBinBounds, hipLaunchKernelGGL(k_bin_bounds, dim3(wblocks), dim3(256), 0, s, a, kin));
     TIMED(kKBinFinalize,
           hipLaunchKernelGGL(k_bin_finalize, dim3((n_runs + 255) / 256), dim3(256), 0, s, a, L.r1, 1));
   }
@@ -1828,7 +1888,7 @@ struct SortLayout {
   int32_t nt;
   int npass;
   int D;
-  size_t off_run, off_tile_run, off_hist, off_tot, off_ns, off_na, off_tmp, total;
+  size_t off_run, off_tile_run, off_hist, off_tot, off_ns, off_na, off_tmp, off_k0, off_k1, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -1857,6 +1917,10 @@ SortLayout sort_layout(int64_t n, int32_t nbins, int tile_chunks) {
   L.off_na = o;
   o = align256(o + 4);
   L.off_tmp = o;
+  o = align256(o + (L.npass > 1 ? (size_t)n * 4 : 0));
+  L.off_k0 = o;
+  o = align256(o + (L.npass > 1 ? (size_t)n * 4 : 0));
+  L.off_k1 = o;
   o = align256(o + (L.npass > 1 ? (size_t)n * 4 : 0));
   L.total = o;
   return L;
@@ -1896,6 +1960,8 @@ void launch_counting_sort(const int32_t *keys, int64_t n, int32_t nbins, int32_t
   a.cell = keys;
   a.in = nullptr;
   a.out = lcr;
+  a.kin = nullptr;
+  a.kout = nullptr;
   a.hist = (uint32_t *)(w + L.off_hist);
   a.tot = (uint32_t *)(w + L.off_tot);
   a.bin_start = start;
@@ -1910,17 +1976,22 @@ void launch_counting_sort(const int32_t *keys, int64_t n, int32_t nbins, int32_t
   const size_t lds = (size_t)kWavesPerBlock * a.dstride * sizeof(uint32_t);
   const int wblocks = (L.nt + kWavesPerBlock - 1) / kWavesPerBlock;
   int32_t *tmp = (int32_t *)(w + L.off_tmp);
-  const int32_t *in = nullptr;
+  int32_t *kbuf[2] = {(int32_t *)(w + L.off_k0), (int32_t *)(w + L.off_k1)};
+  const int32_t *in = nullptr, *kin = nullptr;
   for (int p = 0; p < L.npass; ++p) {
     int32_t *out = ((L.npass - 1 - p) % 2 == 0) ? lcr : tmp;
+    int32_t *kout = L.npass > 1 ? kbuf[p % 2] : nullptr;
     a.pass = p;
     a.in = in;
+    a.kin = kin;
     hipLaunchKernelGGL(k_digcount, dim3(wblocks), dim3(256), lds, s, a, 0);
+    a.kout = kout;
     index_pass(a, L.D, 1, p, in, out, s);
     in = out;
+    kin = kout;
   }
   if (L.npass > 1) {
-    hipLaunchKernelGGL(k_bin_bounds, dim3(grid_for(n)), dim3(256), 0, s, a, lcr, (int64_t)0, (int64_t)L.nt * L.tile);
+    hipLaunchKernelGGL(k_bin_bounds, dim3(wblocks), dim3(256), 0, s, a, kin);
     hipLaunchKernelGGL(k_bin_finalize, dim3(1), dim3(256), 0, s, a, 1, 0);
   }
 }
