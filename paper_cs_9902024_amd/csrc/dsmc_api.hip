@@ -41,8 +41,8 @@ struct Plan {
       off_eg_nc, off_samples, off_items, off_cell_items, off_solid;
   size_t off_P[2][6];
   size_t off_cell, off_lcr, off_lcr_tmp, off_hist, off_tot, off_bin_start, off_remc, off_gmax, off_ncoll, off_remf,
-      off_gencnt, off_stage, off_acc, off_mom, off_nalive, off_nsorted, off_ngen, off_scalars,
-      off_wallq, off_key[2];
+      off_gencnt, off_stage, off_acc, off_mom, off_nalive, off_nsorted, off_ngen, off_scalars, off_wallq, off_wallq_n,
+      off_key_tmp;
   size_t total;
 };
 
@@ -385,10 +385,10 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
     for (int a = 0; a < 6; ++a) P.off_P[b][a] = (a == 2 && g.dim == 2) ? (size_t)-1 : take(es * g.n_slots);
   P.off_cell = take(4 * g.n_slots);
   P.off_lcr = take(4 * g.n_slots);
-  P.off_lcr_tmp = g.npass > 1 ? take(4 * g.n_slots) : (size_t)-1;
   P.off_wallq = take(4 * g.n_slots);
-  P.off_key[0] = g.npass > 1 ? take(4 * g.n_slots) : (size_t)-1;
-  P.off_key[1] = g.npass > 1 ? P.off_wallq : (size_t)-1;  // the wall queue is idle once Motion is done
+  P.off_wallq_n = take(4 * (size_t)g.n_tiles);
+  P.off_lcr_tmp = g.npass > 1 ? take(4 * g.n_slots) : (size_t)-1;
+  P.off_key_tmp = g.npass > 1 ? take(4 * g.n_slots) : (size_t)-1;
   P.off_hist = take(4 * (size_t)mo);
   P.off_tot = take(4 * (size_t)cbo);
   P.off_bin_start = take(4 * (size_t)bo);
@@ -431,9 +431,7 @@ DevPtrs<real> carve(const Plan &P, char *base) {
   d.cell = (int32_t *)(base + P.off_cell);
   d.lcr = (int32_t *)(base + P.off_lcr);
   d.lcr_tmp = P.off_lcr_tmp == (size_t)-1 ? nullptr : (int32_t *)(base + P.off_lcr_tmp);
-  for (int k = 0; k < 2; ++k)
-    d.key_buf[k] = P.off_key[k] == (size_t)-1 ? nullptr : (int32_t *)(base + P.off_key[k]);
-  d.wallq = (uint32_t *)(base + P.off_wallq);
+  d.key_tmp = P.off_key_tmp == (size_t)-1 ? nullptr : (int32_t *)(base + P.off_key_tmp);
   d.hist = (uint32_t *)(base + P.off_hist);
   d.digit_tot = (uint32_t *)(base + P.off_tot);
   d.bin_start = (uint32_t *)(base + P.off_bin_start);
@@ -451,6 +449,8 @@ DevPtrs<real> carve(const Plan &P, char *base) {
   d.step = (uint32_t *)(base + P.off_scalars);
   d.sample_slot = (int32_t *)(base + P.off_scalars + 4);
   d.err = (int32_t *)(base + P.off_scalars + 8);
+  d.wallq_n = (uint32_t *)(base + P.off_wallq_n);
+  d.wallq = (uint32_t *)(base + P.off_wallq);
   return d;
 }
 

@@ -89,8 +89,7 @@ struct DevPtrs {
   int32_t *cell;               // [slots] cell (bin) of each slot after Motion
   int32_t *lcr;                // [slots] run-local slot in cell order
   int32_t *lcr_tmp;            // [slots] previous indexing pass (multi-pass only)
-  int32_t *key_buf[2];         // [slots] bins carried between indexing passes (multi-pass only)
-  uint32_t *wallq;             // [slots] per tile: run-local slots of particles that reach a face
+  int32_t *key_tmp;            // [slots] bins carried between indexing passes (multi-pass only)
   uint32_t *hist;              // tile histograms, tile-major
   uint32_t *digit_tot;         // per run digit totals / digit starts
   uint32_t *bin_start;         // per run nc + 2 entries, run-local
@@ -107,6 +106,8 @@ struct DevPtrs {
   uint32_t *step;              // device step counter
   int32_t *sample_slot;        // sample slot of the current step or -1
   int32_t *err;                // first device error (0 = none)
+  uint32_t *wallq;             // [slots] per tile: run-local slots of particles that reach a face
+  uint32_t *wallq_n;           // [tiles] queue length per tile
 };
 
 // The contiguous share of one stream lane: runs [r0, r1) and everything laid

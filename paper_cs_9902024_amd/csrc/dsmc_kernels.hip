@@ -611,33 +611,10 @@ __device__ __forceinline__ void store4(real *p, int64_t i, const real (&o)[4]) {
 // One wavefront per tile of tile_chunks*64 consecutive slots of one run.
 // Each round covers 256 slots, four consecutive ones per lane, moved with
 // 128-bit loads and stores (only a run's last, partial round goes slot by
-// slot).  A particle that reaches no face (and no solid cell) this step is
-// moved by the straight flight; the others are queued in the tile's segment
-// of the wall queue and, after the tile, moved 64 at a time by the full
-// face-by-face flight (move_one) by the same wavefront.  The new cell of
-// every particle is counted in the tile's histogram of the first indexing
-// digit, kept in wave-private LDS.
-template <typename real, int DIM, bool SINGLE>
-__device__ __forceinline__ void move_queued(const RunDev &R, const DevPtrs<real> &d, int buf, uint32_t step,
-                                            uint32_t loc, uint32_t *h) {
-  const int64_t gs = R.so + loc;
-  const Particles<real> P = d.P[buf];
-  real p3[3] = {P.x[gs], P.y[gs], DIM == 3 ? P.z[gs] : (real)0};
-  real v3[3] = {P.u[gs], P.v[gs], DIM == 3 ? P.w[gs] : (real)0};
-  bool hit, reemit;
-  const int32_t c = move_one<real, DIM>(R, d.solid, step, loc, p3, v3, hit, reemit, d.err);
-  P.x[gs] = p3[0];
-  P.y[gs] = p3[1];
-  if (DIM == 3) P.z[gs] = p3[2];
-  if (hit) {
-    P.u[gs] = v3[0];
-    P.v[gs] = v3[1];
-    if (DIM == 3 || reemit) P.w[gs] = v3[2];
-  }
-  d.cell[gs] = c;
-  atomicAdd(&h[SINGLE ? (uint32_t)c : ((uint32_t)c & (kDigits - 1))], 1u);
-}
-
+// slot).  A particle that reaches no face this step is moved here; the others
+// go to the tile's wall queue (k_motion_walls).  The new cell of every free
+// particle is counted in the tile's histogram of the first indexing digit,
+// kept in wave-private LDS.
 template <typename real, int DIM, bool SINGLE, bool OBST>
 __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_t t0, int32_t t1, int64_t tile,
                                                 int dstride) {
@@ -652,7 +629,6 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
   uint32_t *h = lds + wave * dstride;
   for (int q = lane; q < D; q += kWave) h[q] = 0;
   wave_sync();
-  const uint32_t step = *d.step;
   const int64_t n = d.n_alive[r];
   const int64_t begin = tl * tile, end = min(begin + tile, n);
   real *__restrict__ X = d.P[buf].x + R.so;
@@ -717,7 +693,7 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
       oc[e] = c;
       key[e] = SINGLE ? (uint32_t)c : ((uint32_t)c & (kDigits - 1));
     }
-    // (a queued particle's position and cell are rewritten when it is moved)
+    // (a queued particle's position and cell are rewritten by k_motion_walls)
     if (full) {
       store4(X, i0, ox);
       store4(Y, i0, oy);
@@ -735,7 +711,7 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) histogram_add(h, key[e], fast[e]);
-    // particles that reach a face go to the queue
+    // particles that reach a face go to the tile's segment of the wall queue
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const bool mine = act[e] && !fast[e];
@@ -745,13 +721,46 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
       qn += (uint32_t)__popcll(m);
     }
   }
-  // the tile's stores (queued slots: unchanged values) and queue entries
-  // complete before the queued moves read them and store the new values
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-  for (uint32_t i = lane; i < qn; i += kWave) move_queued<real, DIM, SINGLE>(R, d, buf, step, wq[i], h);
+  if (lane == 0) d.wallq_n[t] = qn;
   wave_sync();
   uint32_t *Mt = d.hist + R.mo + tl * D;
   for (int q = lane; q < D; q += kWave) Mt[q] = h[q];
+}
+
+// The particles Motion queued because they reach a face this step (one block
+// per tile): the full face-by-face flight (specular, diffuse, open faces) and
+// their cells added to the tile histogram of the first indexing digit.
+template <typename real, int DIM, bool SINGLE>
+__global__ __launch_bounds__(256) void k_motion_walls(DevPtrs<real> d, int buf, int32_t t0, int32_t t1,
+                                                      int64_t tile) {
+  const int32_t t = t0 + (int32_t)blockIdx.x;
+  if (t >= t1) return;
+  const uint32_t nq = d.wallq_n[t];
+  if (nq == 0) return;
+  const RunDev &R = d.runs[d.tile_run[t]];
+  const uint32_t step = *d.step;
+  const int D = SINGLE ? R.nc + 1 : kDigits;
+  uint32_t *Mt = d.hist + R.mo + (int64_t)(t - R.to) * D;
+  const uint32_t *wq = d.wallq + (int64_t)t * tile;
+  const Particles<real> P = d.P[buf];
+  for (uint32_t i = threadIdx.x; i < nq; i += blockDim.x) {
+    const int64_t loc = wq[i];
+    const int64_t gs = R.so + loc;
+    real p3[3] = {P.x[gs], P.y[gs], DIM == 3 ? P.z[gs] : (real)0};
+    real v3[3] = {P.u[gs], P.v[gs], DIM == 3 ? P.w[gs] : (real)0};
+    bool hit, reemit;
+    const int32_t c = move_one<real, DIM>(R, d.solid, step, (uint32_t)loc, p3, v3, hit, reemit, d.err);
+    P.x[gs] = p3[0];
+    P.y[gs] = p3[1];
+    if (DIM == 3) P.z[gs] = p3[2];
+    if (hit) {
+      P.u[gs] = v3[0];
+      P.v[gs] = v3[1];
+      if (DIM == 3 || reemit) P.w[gs] = v3[2];
+    }
+    d.cell[gs] = c;
+    atomicAdd(&Mt[SINGLE ? (uint32_t)c : ((uint32_t)c & (kDigits - 1))], 1u);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1740,7 +1749,6 @@ static void lane_step(const Geometry &g, const LaneRange &L, const DevPtrs<real>
     TIMED(kKGenEmit, hipLaunchKernelGGL((k_gen_emit<real, DIM>), dim3(L.i1 - L.i0), dim3(256), 0, s, d, buf, L.i0));
   }
   const size_t lds = (size_t)kWavesPerBlock * g.dstride * sizeof(uint32_t);
-  const size_t mlds = lds;
   const int wblocks = (n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
   IndexArgs a = index_args(g, d);
   a.t0 = L.t0;
@@ -1748,23 +1756,28 @@ static void lane_step(const Geometry &g, const LaneRange &L, const DevPtrs<real>
   a.r0 = L.r0;
   if (g.npass == 1) {
     if (g.any_solid)
-      TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, true, true>), dim3(wblocks), dim3(256), mlds, s, d,
-                                         buf, L.t0, L.t1, g.tile, g.dstride));
+      TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, true, true>), dim3(wblocks), dim3(256), lds, s, d, buf,
+                                         L.t0, L.t1, g.tile, g.dstride));
     else
-      TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, true, false>), dim3(wblocks), dim3(256), mlds, s, d,
+      TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, true, false>), dim3(wblocks), dim3(256), lds, s, d,
                                          buf, L.t0, L.t1, g.tile, g.dstride));
+    TIMED(kKMotionWalls, hipLaunchKernelGGL((k_motion_walls<real, DIM, true>), dim3(n_tiles), dim3(256), 0, s, d,
+                                            buf, L.t0, L.t1, g.tile));
     if (moved) (void)hipEventRecord(moved, s);
     index_pass(a, g.max_nc + 1, n_runs, 0, nullptr, d.lcr, s, prof);
   } else {
     if (g.any_solid)
-      TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, false, true>), dim3(wblocks), dim3(256), mlds, s, d,
+      TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, false, true>), dim3(wblocks), dim3(256), lds, s, d,
                                          buf, L.t0, L.t1, g.tile, g.dstride));
     else
-      TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, false, false>), dim3(wblocks), dim3(256), mlds, s, d,
+      TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, false, false>), dim3(wblocks), dim3(256), lds, s, d,
                                          buf, L.t0, L.t1, g.tile, g.dstride));
+    TIMED(kKMotionWalls, hipLaunchKernelGGL((k_motion_walls<real, DIM, false>), dim3(n_tiles), dim3(256), 0, s, d,
+                                            buf, L.t0, L.t1, g.tile));
     if (moved) (void)hipEventRecord(moved, s);
-    // bins are carried through the passes in two alternating key buffers
-    int32_t *kbuf[2] = {d.key_buf[0], d.key_buf[1]};
+    // bins are carried through the passes: key_tmp and (free after Motion)
+    // the wall queue alternate as key buffers
+    int32_t *kbuf[2] = {d.key_tmp, (int32_t *)d.wallq};
     const int32_t *in = nullptr, *kin = nullptr;
     for (int p = 0; p < g.npass; ++p) {
       int32_t *out = ((g.npass - 1 - p) % 2 == 0) ? d.lcr : d.lcr_tmp;
