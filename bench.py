@@ -11,13 +11,21 @@ HBM.  ``value`` = particle-steps per second over the timed steps (particles
 moved per step, summed over runs and steps, divided by the wall time between
 two device synchronisations).
 
+Before the timed region the library's autotuner (dsmc_autotune) picks the
+tuning settings (Indexing tile, interaction mode, stream lanes) by timing its
+candidates on the same batch in a scratch arena; tuning never changes results.
+
 Beside it the line carries:
   roofline      the dominant kernel's algorithmic bytes per launch over its
-                mean HIP-event duration (events recorded on the library's own
-                stream), against MI355X's 8 TB/s HBM peak;
+                mean HIP-event duration (events recorded on the streams the
+                kernels run on), against MI355X's 8 TB/s HBM peak;
   plain_fp64    the plain path: the same problem, one run at a time, FP64
                 state, one launch per kernel;
   cpu_baseline  the FP64 oracle timed on the host cores on a bounded sample.
+
+``--workload body3d`` times the flow past a body at full size instead (32 runs
+x 60M particles, 2M cells, solid-cell obstacle); it is informational, not the
+benchmark line.
 """
 import argparse
 import json
@@ -57,16 +65,17 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ensemble_box_512x1M_fp32_traffic.
 KERNEL_SRC = os.path.join(ROOT, "paper_cs_9902024_amd", "csrc", "dsmc_kernels.hip")
 
 
-def measured_traffic(kernel: str, lanes: int):
+def measured_traffic(kernel: str, lanes: int, tile: int):
     """HBM bytes per launch of ``kernel`` from the committed FETCH_SIZE /
     WRITE_SIZE summary (scaled by the copy-kernel calibration), or None when
     there is none, the kernel source changed since the counters were taken,
-    or the counters were taken with another split of the batch into lanes."""
+    or the counters were taken with another split of the batch into lanes or
+    another Indexing tile size."""
     import hashlib
     if not os.path.exists(TRAFFIC_FILE):
         return None
     sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-    found, ok, same_lanes = None, False, False
+    found, ok, same_lanes, same_tile = None, False, False, False
     for line in open(TRAFFIC_FILE):
         f = line.split()
         if len(f) == 3 and f[0] == "traffic" and f[1] == kernel:
@@ -75,7 +84,9 @@ def measured_traffic(kernel: str, lanes: int):
             ok = f[1] == sha
         if len(f) == 2 and f[0] == "lanes":
             same_lanes = int(f[1]) == lanes
-    return found if ok and same_lanes else None
+        if len(f) == 2 and f[0] == "tile":
+            same_tile = int(f[1]) == tile
+    return found if ok and same_lanes and same_tile else None
 
 
 def copy_calibration(nbytes: int = 1 << 31):
@@ -108,9 +119,21 @@ def run_gpu(args):
 
     torch.cuda.set_device(0)
     calib = copy_calibration()
-    wl = W.ensemble_box(n_runs=args.runs, n_per_run=args.per_run, n_steps=1000, sample_every=20,
-                        seed=3, state_fp64=False)
-    E = P.Ensemble.from_workload(wl, use_graph=True, n_streams=args.streams)
+    if args.workload == "body3d":
+        wl = W.body3d()
+    else:
+        wl = W.ensemble_box(n_runs=args.runs, n_per_run=args.per_run, n_steps=1000, sample_every=20,
+                            seed=3, state_fp64=False)
+    dim = wl.runs[0].dim
+    tuned = None
+    kw = {"n_streams": args.streams, "tile_chunks": args.tile_chunks, "collide_mode": args.collide_mode}
+    if not args.no_tune:
+        # the library's autotuner times its candidate settings on this batch
+        # (a scratch arena, before the timed region); tuning never changes results
+        tuned = P.Ensemble.autotune(wl.runs, wl.sample_steps, state_fp64=False, n_groups=wl.n_groups,
+                                    use_graph=True, n_steps=3)
+        kw = {k: tuned[k] for k in ("tile_chunks", "collide_mode", "n_streams")}
+    E = P.Ensemble.from_workload(wl, use_graph=True, **kw)
     n_runs = wl.n_runs
     nc = wl.runs[0].n_cells
 
@@ -125,9 +148,14 @@ def run_gpu(args):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     n1 = int(E.counts()[:, 0].sum())
-    assert n0 == n1, "closed box must keep its particle count"
     elapsed = t1 - t0
-    psteps = n0 * args.steps
+    if args.workload == "ensemble_box":
+        assert n0 == n1, "closed box must keep its particle count"
+        psteps = n0 * args.steps
+    else:
+        # inflow and outflow change the count by ~0.01 % per step: the mean of
+        # the counts before and after the timed steps
+        psteps = (n0 + n1) // 2 * args.steps
     value = psteps / elapsed
 
     # per-kernel HIP-event durations over a second, profiled window
@@ -146,24 +174,25 @@ def run_gpu(args):
     kernels = {k: {"ms_total": ms, "launches": n, "ms_avg": ms / n} for k, (ms, n) in kt.items()}
     dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
     rl = None
-    per_step = algorithmic_bytes(dom, n0, n_runs * nc, 2, 4)
+    per_step = algorithmic_bytes(dom, n0, n_runs * nc, dim, 4)
     if per_step > 0:
         ab = per_step * args.prof_steps / kernels[dom]["launches"]
         ach = ab / (kernels[dom]["ms_avg"] * 1e-3) / 1e9
-        tr = measured_traffic(dom, info["lanes"])
+        tr = measured_traffic(dom, info["lanes"], info["slots"] // info["tiles"]) \
+            if args.workload == "ensemble_box" else None
         rl = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
               "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": tr, "kernel": dom,
               "algorithmic_bytes_per_launch": ab, "avg_launch_ms": kernels[dom]["ms_avg"]}
     for k, v in kernels.items():
-        b = algorithmic_bytes(k, n0, n_runs * nc, 2, 4)
+        b = algorithmic_bytes(k, n0, n_runs * nc, dim, 4)
         if b > 0:
             v["algorithmic_GBs"] = round(b * args.prof_steps / (v["ms_total"] * 1e-3) / 1e9, 1)
             v["frac_of_hbm_peak"] = round(v["algorithmic_GBs"] / HBM_PEAK_GBS, 4)
 
     plain = None
-    if args.plain_runs > 0:
+    if args.plain_runs > 0 and args.workload == "ensemble_box":
         plain = run_plain_fp64(args, P, W)
-    return {"value": value, "elapsed": elapsed, "psteps": psteps, "n_runs": n_runs, "nc": nc,
+    return {"value": value, "elapsed": elapsed, "psteps": psteps, "n_runs": n_runs, "nc": nc, "tuned": tuned,
             "kernels": kernels, "roofline": rl, "plain": plain, "info": info, "calib": calib}
 
 
@@ -231,7 +260,13 @@ def main():
     ap.add_argument("--per-run", type=int, default=1_000_000)
     ap.add_argument("--prof-steps", type=int, default=5)
     ap.add_argument("--streams", type=int, default=0,
-                    help="run groups stepped concurrently (0 = the library's choice)")
+                    help="run groups stepped concurrently (0 = the library's choice; with --no-tune)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner; use --streams / --tile-chunks / --collide-mode (0 = default)")
+    ap.add_argument("--tile-chunks", type=int, default=0)
+    ap.add_argument("--workload", choices=("ensemble_box", "body3d"), default="ensemble_box",
+                    help="ensemble_box (the benchmark) or body3d (the flow past a body at full size)")
+    ap.add_argument("--collide-mode", type=int, default=0)
     ap.add_argument("--plain-runs", type=int, default=2)
     ap.add_argument("--plain-steps", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -244,7 +279,7 @@ def main():
         sys.exit(2)
 
     g = run_gpu(args)
-    cpu = None if args.no_cpu_baseline else cpu_baseline(args)
+    cpu = None if (args.no_cpu_baseline or args.workload != "ensemble_box") else cpu_baseline(args)
     ms_per_step = g["elapsed"] / args.steps * 1e3
     line = {
         "metric": METRIC,
@@ -259,12 +294,18 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"ensemble_box: {g['n_runs']} independent runs x {args.per_run} "
-                               f"hard-sphere particles, 2-D 1x1 specular box, 32x32 cells, "
-                               f"Kn 0.05, dt = 0.2 mean collision times, FP32 state, FP64 "
-                               f"sampling accumulators, sample every 20 steps, HIP graph",
-                   "runs": g["n_runs"], "particles_per_run": args.per_run,
+        "config": {"workload": (f"ensemble_box: {g['n_runs']} independent runs x {args.per_run} "
+                                f"hard-sphere particles, 2-D 1x1 specular box, 32x32 cells, "
+                                f"Kn 0.05, dt = 0.2 mean collision times, FP32 state, FP64 "
+                                f"sampling accumulators, sample every 20 steps, HIP graph")
+                   if args.workload == "ensemble_box" else
+                   ("body3d: 32 independent runs x 60M hard-sphere particles, 3-D 2x1x1 box, "
+                    "200x100x100 cells, Mach-5 inflow past a sphere of solid cells (diffuse, T = 3), "
+                    "FP32 state, FP64 sampling accumulators, HIP graph"),
+                   "runs": g["n_runs"],
+                   "particles_per_run": args.per_run if args.workload == "ensemble_box" else 60_000_000,
                    "cells_per_run": g["nc"], "lanes": g["info"]["lanes"],
+                   "tile_slots": g["info"]["slots"] // g["info"]["tiles"], "tuned": g["tuned"],
                    "parallelism": "one GPU; runs batched in each launch, split into "
                                   f"{g['info']['lanes']} concurrent stream lanes"},
         "roofline": g["roofline"],

@@ -208,6 +208,29 @@ dsmc_status dsmc_kernel_times(dsmc_ctx *ctx, double *ms, int64_t *launches, int3
 /* Name of kernel kind k (static string), NULL if out of range. */
 const char *dsmc_kernel_name(int32_t kind);
 
+/* ---- autotuning ------------------------------------------------------------ */
+
+/* Arena size dsmc_autotune needs for these runs: the largest dsmc_required_bytes
+ * over its candidate settings.  Pure host computation; DSMC_EINVAL as
+ * dsmc_required_bytes. */
+dsmc_status dsmc_autotune_bytes(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_options *opt,
+                                size_t *bytes);
+
+/* Chooses the tuning fields of dsmc_options (tile_chunks, collide_mode,
+ * n_streams) for these runs by measurement.  None of them changes any result
+ * (every setting computes the same sequential order bit for bit); they only
+ * change speed.  Candidates: tiles of 4096, 8192 and 16384 slots; both
+ * interaction modes when a run's expected particles per cell lie in 16..256;
+ * one or two stream lanes when n_runs >= 8.  Each candidate is initialised in
+ * the caller's arena (at least dsmc_autotune_bytes, 256-byte aligned), stepped
+ * once to warm up (graph capture included when opt->use_graph), then n_steps
+ * (>= 1) steps are timed with HIP events on hip_stream.  *best receives *opt
+ * with the fastest tuning fields; *best_ms_per_step (may be NULL) its time per
+ * step.  The arena holds no usable context afterwards.  Synchronises. */
+dsmc_status dsmc_autotune(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_options *opt, void *arena,
+                          size_t arena_bytes, void *hip_stream, int32_t n_steps, dsmc_options *best,
+                          double *best_ms_per_step);
+
 /* ---- Indexing alone ------------------------------------------------------ */
 
 /* Workspace bytes for dsmc_counting_sort. */

@@ -31,7 +31,8 @@ EXPORTS = ("dsmc_required_bytes", "dsmc_init_runs", "dsmc_step", "dsmc_sample", 
            "dsmc_read_accum", "dsmc_sync", "dsmc_destroy", "dsmc_last_error", "dsmc_get_info",
            "dsmc_get_state", "dsmc_set_state", "dsmc_get_lcr", "dsmc_get_cell_state",
            "dsmc_get_counts", "dsmc_counting_sort_bytes", "dsmc_counting_sort",
-           "dsmc_set_profiling", "dsmc_kernel_times", "dsmc_kernel_name")
+           "dsmc_set_profiling", "dsmc_kernel_times", "dsmc_kernel_name", "dsmc_autotune_bytes",
+           "dsmc_autotune")
 NKERNELS = 16
 NINFO = 10
 
@@ -97,6 +98,10 @@ def lib():
         L.dsmc_set_profiling.argtypes = [vp, i32]
         L.dsmc_kernel_times.argtypes = [vp, dp, C.POINTER(i64), i32]
         L.dsmc_kernel_name.argtypes = [i32]
+        L.dsmc_autotune_bytes.argtypes = [C.POINTER(dsmc_run_spec), i32, C.POINTER(dsmc_options),
+                                          C.POINTER(sz)]
+        L.dsmc_autotune.argtypes = [C.POINTER(dsmc_run_spec), i32, C.POINTER(dsmc_options), vp, sz, vp, i32,
+                                    C.POINTER(dsmc_options), dp]
         L.dsmc_kernel_name.restype = C.c_char_p
         for f in EXPORTS:
             if f not in ("dsmc_destroy", "dsmc_last_error", "dsmc_kernel_name"):
@@ -169,6 +174,22 @@ def _specs(runs):
 # ---------------------------------------------------------------------------
 # The C ABI, one wrapper per entry point
 # ---------------------------------------------------------------------------
+
+def dsmc_autotune_bytes(specs, opt) -> int:
+    n = C.c_size_t(0)
+    _check(lib().dsmc_autotune_bytes(specs, len(specs), C.byref(opt), C.byref(n)), "dsmc_autotune_bytes")
+    return n.value
+
+
+def dsmc_autotune(specs, opt, arena_ptr: int, arena_bytes: int, stream: int, n_steps: int):
+    """Returns (best dsmc_options, ms per step)."""
+    best = dsmc_options()
+    ms = C.c_double(0)
+    _check(lib().dsmc_autotune(specs, len(specs), C.byref(opt), C.c_void_p(arena_ptr), arena_bytes,
+                               C.c_void_p(stream), n_steps, C.byref(best), C.byref(ms)), "dsmc_autotune")
+    best._keep = getattr(opt, "_keep", None)
+    return best, ms.value
+
 
 def dsmc_required_bytes(specs, opt) -> int:
     n = C.c_size_t(0)
@@ -327,6 +348,28 @@ class Ensemble:
         for r in self.runs:
             if r.ensemble not in self.ensembles:
                 self.ensembles.append(r.ensemble)
+
+    @staticmethod
+    def autotune(runs, sample_steps: Sequence[int] = (), state_fp64: bool = False, n_groups: int = 1,
+                 use_graph: bool = False, n_steps: int = 5, device=None, stream=None) -> dict:
+        """Measures the library's candidate tuning settings on these runs
+        (dsmc_autotune) in a scratch arena; returns the fastest as keyword
+        arguments for Ensemble (tile_chunks, collide_mode, n_streams) plus its
+        ms_per_step.  Tuning never changes results."""
+        import torch
+        if not torch.cuda.is_available():
+            raise DsmcError(-4, "autotune", "no GPU visible to torch")
+        specs = _specs(list(runs))
+        opt = make_options(state_fp64, n_groups, list(sample_steps), use_graph)
+        nbytes = dsmc_autotune_bytes(specs, opt)
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        arena = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        best, ms = dsmc_autotune(specs, opt, arena.data_ptr(), nbytes, st.cuda_stream, n_steps)
+        del arena
+        torch.cuda.empty_cache()
+        return {"tile_chunks": best.tile_chunks, "collide_mode": best.collide_mode,
+                "n_streams": best.n_streams, "ms_per_step": ms}
 
     @classmethod
     def from_workload(cls, wl, **kw):

@@ -1022,3 +1022,124 @@ dsmc_status dsmc_counting_sort(const int32_t *keys, int64_t n, int32_t nbins, in
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Autotuning of the tuning fields of dsmc_options
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// Candidate settings of (tile_chunks, collide_mode, n_streams) for these runs,
+// the default first: tile sizes of 16384, 8192 and 4096 slots; both
+// interaction modes when some run's expected particles per cell lie where
+// either could win (16..256); two stream lanes when there are enough runs to
+// split.
+// True when auto picks the block-per-cell mode for the first run's fill
+// (the run that decides for the batch is not important: the candidate list
+// holds both modes either way).
+bool auto_block(const dsmc_run_spec *runs, int32_t n_runs) {
+  (void)n_runs;
+  const dsmc_run_spec &s = runs[0];
+  double fill = (double)s.n_init;
+  if (s.face_bc[0] == DSMC_BC_INFLOW) fill = std::max(fill, s.inflow_n * s.lx * s.ly * s.lz);
+  return fill / ((double)s.nx * s.ny * s.nz) >= 64.0;
+}
+
+std::vector<dsmc_options> tune_candidates(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_options &base) {
+  bool ambiguous = false;
+  for (int r = 0; r < n_runs; ++r) {
+    const dsmc_run_spec &s = runs[r];
+    double fill = (double)s.n_init;
+    if (s.face_bc[0] == DSMC_BC_INFLOW) fill = std::max(fill, s.inflow_n * s.lx * s.ly * s.lz);
+    const double ppc = fill / ((double)s.nx * s.ny * s.nz);
+    if (ppc >= 16.0 && ppc <= 256.0) ambiguous = true;
+  }
+  std::vector<int32_t> modes = ambiguous ? std::vector<int32_t>{0, 3} : std::vector<int32_t>{0};
+  std::vector<int32_t> lanes = n_runs >= 8 ? std::vector<int32_t>{1, 2} : std::vector<int32_t>{1};
+  std::vector<dsmc_options> out;
+  for (int32_t tc : {256, 128, 64})
+    for (int32_t m : modes)
+      for (int32_t l : lanes) {
+        dsmc_options o = base;
+        o.tile_chunks = tc;
+        // 3 stands for the mode auto does not take
+        o.collide_mode = m == 3 ? (auto_block(runs, n_runs) ? 1 : 2) : 0;
+        o.n_streams = l;
+        out.push_back(o);
+      }
+  return out;
+}
+
+}  // namespace
+
+extern "C" {
+
+dsmc_status dsmc_autotune_bytes(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_options *opt, size_t *bytes) {
+  if (!bytes) return DSMC_EINVAL;
+  dsmc_options base{};
+  if (opt) base = *opt;
+  std::string msg;
+  dsmc_status st = validate(runs, n_runs, &base, &msg);
+  if (st) return st;
+  size_t most = 0;
+  for (const dsmc_options &o : tune_candidates(runs, n_runs, base)) {
+    size_t b = 0;
+    st = dsmc_required_bytes(runs, n_runs, &o, &b);
+    if (st) return st;
+    most = std::max(most, b);
+  }
+  *bytes = most;
+  return DSMC_OK;
+}
+
+dsmc_status dsmc_autotune(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_options *opt, void *arena,
+                          size_t arena_bytes, void *hip_stream, int32_t n_steps, dsmc_options *best,
+                          double *best_ms_per_step) {
+  if (!best || n_steps < 1) return DSMC_EINVAL;
+  size_t need = 0;
+  dsmc_status st = dsmc_autotune_bytes(runs, n_runs, opt, &need);
+  if (st) return st;
+  if (!arena || ((uintptr_t)arena & 255) || arena_bytes < need) return DSMC_ESIZE;
+  dsmc_options base{};
+  if (opt) base = *opt;
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return DSMC_EDEVICE;
+  }
+  double best_ms = -1.0;
+  dsmc_options pick = base;
+  for (const dsmc_options &o : tune_candidates(runs, n_runs, base)) {
+    dsmc_ctx *c = nullptr;
+    st = dsmc_init_runs(runs, n_runs, &o, arena, arena_bytes, hip_stream, &c);
+    if (!st) st = dsmc_step(c, 1);  // warm-up (and graph capture)
+    if (!st) st = dsmc_sync(c);
+    float ms = 0.f;
+    if (!st) {
+      (void)hipEventRecord(e0, s);
+      st = dsmc_step(c, n_steps);
+      (void)hipEventRecord(e1, s);
+      if (!st) st = dsmc_sync(c);
+      if (!st && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
+        const double per = (double)ms / n_steps;
+        // a later candidate must beat the best so far by 2 % (timing noise
+        // is about 1 %), so the default wins ties
+        if (best_ms < 0 || per < 0.98 * best_ms) {
+          best_ms = per;
+          pick = o;
+        }
+      }
+    }
+    if (c) dsmc_destroy(c);
+    if (st) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  *best = pick;
+  if (best_ms_per_step) *best_ms_per_step = best_ms;
+  return DSMC_OK;
+}
+
+}  // extern "C"

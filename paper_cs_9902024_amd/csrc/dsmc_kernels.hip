@@ -17,6 +17,7 @@
 #include "dsmc_internal.hpp"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace dsmc {
 
@@ -88,7 +89,9 @@ __device__ __forceinline__ void box_muller(real u1, real u2, real &n0, real &n1)
   n1 = r * sin(th);
 }
 
-__device__ __forceinline__ void set_error(int32_t *err, int code) { atomicCAS(err, 0, code); }
+// Latches a device error: the lowest code wins (deterministic whatever the
+// order of the failures); a non-returning atomic, so no register waits on it.
+__device__ __forceinline__ void set_error(int32_t *err, int code) { (void)atomicMin(err, code); }
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -104,8 +107,8 @@ __device__ __forceinline__ int32_t axis_index(real x, real inv, int32_t n) {
 }
 
 // sigma(c_r)/sigma_ref * c_r: hard sphere or VHS.
-template <typename real>
-__device__ __forceinline__ real g_of(const RunDev &R, real cr) {
+template <typename real, typename RunT>
+__device__ __forceinline__ real g_of(const RunT &R, real cr) {
   if (R.hs) return cr;
   if (!(cr > (real)0)) return (real)0;
   return cr * pow(cr / (real)R.c_ref, (real)R.vhs_exp);
@@ -1076,8 +1079,8 @@ struct Selection {
 
 // Selection k of cell c: pair (i, j != i) and the acceptance and scattering
 // uniforms, from Philox blocks (step, COLL, c, 2k) and (step, COLL, c, 2k+1).
-template <typename real>
-__device__ __forceinline__ Selection<real> draw_selection(const RunDev &R, uint32_t step, uint32_t c, int64_t k,
+template <typename real, typename RunT>
+__device__ __forceinline__ Selection<real> draw_selection(const RunT &R, uint32_t step, uint32_t c, int64_t k,
                                                           uint32_t N) {
   const uint4 b0 = philox(make_uint4(step, kColl, c, (uint32_t)(2 * k)), R.key0, R.key1);
   const uint4 b1 = philox(make_uint4(step, kColl, c, (uint32_t)(2 * k + 1)), R.key0, R.key1);
@@ -1124,8 +1127,8 @@ __device__ __forceinline__ void scatter_pair(real cr, const Angles<real> &an, re
 
 // Selections [k0, k1) of one cell in order, by one lane, on arrays u/v/w
 // (LDS or global).  Returns the accepted collisions; updates gm.
-template <typename real>
-__device__ uint32_t chain_serial(const RunDev &R, uint32_t step, uint32_t c, uint32_t N, int64_t k0, int64_t k1,
+template <typename real, typename RunT>
+__device__ uint32_t chain_serial(const RunT &R, uint32_t step, uint32_t c, uint32_t N, int64_t k0, int64_t k1,
                                  real *u, real *v, real *w, real &gm) {
   uint32_t ncol = 0;
   for (int64_t k = k0; k < k1; ++k) {
@@ -1145,8 +1148,8 @@ __device__ uint32_t chain_serial(const RunDev &R, uint32_t step, uint32_t c, uin
 }
 
 // NTC bookkeeping: number of selections this step and the new remainder.
-template <typename real>
-__device__ __forceinline__ int64_t ntc_selections(const RunDev &R, int64_t N, real gm, real &rem, int32_t *err) {
+template <typename real, typename RunT>
+__device__ __forceinline__ int64_t ntc_selections(const RunT &R, int64_t N, real gm, real &rem, int32_t *err) {
   const real npairs = (real)0.5 * (real)(N * (N - 1));
   const real M = npairs * (real)R.coef * gm + rem;
   int64_t nsel = 0;
@@ -1332,9 +1335,50 @@ __global__ __launch_bounds__(kCollideWaves * 64) void k_collide(DevPtrs<real> d,
 template <typename real>
 struct BlockScratch {
   double red[4][kFields];
+  int32_t vote[2][kWavesPerBlock];  // per-wavefront partial results of LdsSync::any / count
   int32_t ks;
   uint32_t ncol;
   real gm;
+};
+
+// Block synchronisation of the collision chain.  FullSync: __syncthreads
+// (which also waits for the thread's outstanding global loads).  LdsSync:
+// orders LDS only -- it waits for the wavefront's LDS operations, not for its
+// global loads, so a gather into another LDS buffer (global_load_lds) stays in
+// flight across it; the empty asm statements keep the compiler from moving
+// memory accesses across the barrier.
+struct FullSync {
+  __device__ static void bar() { __syncthreads(); }
+  __device__ static int any(int p, int32_t (&)[2][kWavesPerBlock], int) { return __syncthreads_or(p); }
+  __device__ static int count(int p, int32_t (&)[2][kWavesPerBlock], int) { return __syncthreads_count(p); }
+};
+struct LdsSync {
+  __device__ static void bar() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt, expcnt left open
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  }
+  // `slot` alternates between calls; every use is followed by another bar()
+  // before the same slot is written again
+  __device__ static int any(int p, int32_t (&v)[2][kWavesPerBlock], int slot) {
+    const uint64_t m = __ballot(p);
+    if ((threadIdx.x & 63) == 0) v[slot][threadIdx.x >> 6] = m != 0ull;
+    bar();
+    int r = 0;
+#pragma unroll
+    for (int w = 0; w < kWavesPerBlock; ++w) r |= v[slot][w];
+    return r;
+  }
+  __device__ static int count(int p, int32_t (&v)[2][kWavesPerBlock], int slot) {
+    const uint64_t m = __ballot(p);
+    if ((threadIdx.x & 63) == 0) v[slot][threadIdx.x >> 6] = __popcll(m);
+    bar();
+    int r = 0;
+#pragma unroll
+    for (int w = 0; w < kWavesPerBlock; ++w) r += v[slot][w];
+    return r;
+  }
 };
 
 template <typename real>
@@ -1342,12 +1386,13 @@ constexpr int collide_cell_bytes() {
   return ((CollideCap<real>::value * (3 * (int)sizeof(real) + 4)) + 15) & ~15;
 }
 
-template <typename real>
-__device__ uint32_t chain_block(const RunDev &R, uint32_t step, uint32_t c, uint32_t N, int64_t nsel, real *u,
+template <typename real, typename Sync = FullSync, typename RunT = RunDev>
+__device__ uint32_t chain_block(const RunT &R, uint32_t step, uint32_t c, uint32_t N, int64_t nsel, real *u,
                                 real *v, real *w, int32_t *own, BlockScratch<real> &sh, real &gm) {
   const int tid = threadIdx.x;
   uint32_t ncol = 0;
   int64_t w0 = 0;
+  int slot = 0;
   while (w0 < nsel) {
     const bool act = w0 + tid < nsel;
     Selection<real> s{0u, 0u, (real)0, (real)0, (real)0};
@@ -1362,19 +1407,19 @@ __device__ uint32_t chain_block(const RunDev &R, uint32_t step, uint32_t c, uint
     real g = (real)0;
     real bu_i = 0, bv_i = 0, bw_i = 0, bu_j = 0, bv_j = 0, bw_j = 0;
     int rounds = 0;
-    while (__syncthreads_or(pending)) {
+    while (Sync::any(pending, sh.vote, slot ^= 1)) {
       if (pending) {
         own[s.i] = 0x7fffffff;
         own[s.j] = 0x7fffffff;
       }
-      __syncthreads();
+      Sync::bar();
       if (pending) {
         atomicMin(&own[s.i], tid);
         atomicMin(&own[s.j], tid);
       }
-      __syncthreads();
+      Sync::bar();
       const bool ready = pending && own[s.i] == tid && own[s.j] == tid;
-      __syncthreads();
+      Sync::bar();
       if (ready) {
         real ui = u[s.i], vi = v[s.i], wi = w[s.i], uj = u[s.j], vj = v[s.j], wj = w[s.j];
         bu_i = ui; bv_i = vi; bw_i = wi; bu_j = uj; bv_j = vj; bw_j = wj;
@@ -1393,12 +1438,12 @@ __device__ uint32_t chain_block(const RunDev &R, uint32_t step, uint32_t c, uint
       ++rounds;
     }
     if (tid == 0) sh.ks = 0x7fffffff;
-    __syncthreads();
+    Sync::bar();
     if (act && g > gm) atomicMin(&sh.ks, tid);
-    __syncthreads();
+    Sync::bar();
     const int ks = sh.ks;
     if (ks == 0x7fffffff) {
-      ncol += __syncthreads_count(accepted);
+      ncol += Sync::count(accepted, sh.vote, slot ^= 1);
       w0 += 256;
       continue;
     }
@@ -1408,9 +1453,9 @@ __device__ uint32_t chain_block(const RunDev &R, uint32_t step, uint32_t c, uint
         u[s.i] = bu_i; v[s.i] = bv_i; w[s.i] = bw_i;
         u[s.j] = bu_j; v[s.j] = bv_j; w[s.j] = bw_j;
       }
-      __syncthreads();
+      Sync::bar();
     }
-    ncol += __syncthreads_count(accepted && tid < ks);
+    ncol += Sync::count(accepted && tid < ks, sh.vote, slot ^= 1);
     // selection ks raises (sigma c_r)_max to its own g, so it is accepted
     // (U < g/g = 1); it ran on exactly its sequential inputs, so apply it again
     // from the restored state and restart the window right after it
@@ -1429,11 +1474,11 @@ __device__ uint32_t chain_block(const RunDev &R, uint32_t step, uint32_t c, uint
       sh.gm = gnew;
       sh.ncol = acc ? 1u : 0u;
     }
-    __syncthreads();
+    Sync::bar();
     gm = sh.gm;
     ncol += sh.ncol;
     w0 += ks + 1;
-    __syncthreads();
+    Sync::bar();
   }
   return ncol;
 }
@@ -1555,6 +1600,232 @@ __global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, 
     d.gmax[gc] = gm;
     d.rem_c[gc] = rem;
     d.ncoll[gc] += ncol;
+  }
+}
+
+// Crowded cells in FP32, pipelined: one 256-thread block walks kPipeCells
+// consecutive cell items.  While the collisions of cell j run in LDS, the
+// whole of cell j+1 (positions and velocities) is being gathered through LCR
+// into registers and the LCR entries of cell j+2 are loaded; the collision
+// chain synchronises with LDS-only barriers, so these loads stay in flight
+// (a vector load is waited for only where its register is read).  Each cell
+// is processed exactly as k_collide_cell does (same selections, order and
+// arithmetic).  The items' bookkeeping (slots, bin range, NTC state, the
+// run's constants) is read once per block into LDS, so the collisions read
+// no global memory.
+constexpr int kPipeCells = 8;
+constexpr int kPipeChunks = kCollideCapF32 / 256;
+
+// The run constants the collisions need.
+struct RunView {
+  uint32_t key0, key1;
+  int32_t hs;
+  double c_ref, vhs_exp, coef;
+};
+
+struct PipeMeta {
+  int64_t so, b0, n, gc;
+  int32_t c;
+  uint32_t ncoll;
+  float gm, rem;
+  RunView rv;
+};
+
+// The particles of the cell in flight, kPipeChunks per thread (k = q*256 + tid).
+struct PipeRegs {
+  int32_t l[kPipeChunks];
+  float x[kPipeChunks], y[kPipeChunks], z[kPipeChunks], u[kPipeChunks], v[kPipeChunks], w[kPipeChunks];
+};
+
+// LCR entries (run-local slots) of the particles this thread handles in an
+// item that fits in LDS; beyond n any valid entry (unused).  Unconditional
+// loads: no branch whose join would make the compiler wait for them.
+__device__ __forceinline__ void pipe_lcr(const int32_t *lcr, const PipeMeta &m, bool valid,
+                                         int32_t (&l)[kPipeChunks]) {
+  const bool use = valid && m.n > 0 && m.n <= kCollideCapF32;
+  const int32_t *lp = use ? lcr + m.so + m.b0 : lcr;
+  const int64_t lim = use ? m.n - 1 : 0;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < kPipeChunks; ++q) {
+    const int64_t k = q * 256 + tid;
+    l[q] = lp[k < lim ? k : lim];
+  }
+}
+
+// Starts the gather of an item into registers (LDS items), or moves an item
+// beyond the LDS capacity straight to P' (synchronously).
+template <int DIM>
+__device__ __forceinline__ void pipe_gather(const int32_t *lcr, const Particles<float> &A, const Particles<float> &B,
+                                            const PipeMeta &m, bool valid, PipeRegs &pr) {
+  if (!valid) return;
+  const int tid = threadIdx.x;
+  if (m.n <= kCollideCapF32) {
+#pragma unroll
+    for (int q = 0; q < kPipeChunks; ++q) {
+      const int64_t sidx = m.so + pr.l[q];  // a valid slot beyond n (unused)
+      pr.x[q] = A.x[sidx];
+      pr.y[q] = A.y[sidx];
+      if (DIM == 3) pr.z[q] = A.z[sidx];
+      pr.u[q] = A.u[sidx];
+      pr.v[q] = A.v[sidx];
+      pr.w[q] = A.w[sidx];
+    }
+  } else {
+    for (int64_t k = tid; k < m.n; k += 256) {
+      const int64_t sidx = m.so + lcr[m.so + m.b0 + k];
+      const int64_t dst = m.so + m.b0 + k;
+      B.x[dst] = A.x[sidx];
+      B.y[dst] = A.y[sidx];
+      if (DIM == 3) B.z[dst] = A.z[sidx];
+      B.u[dst] = A.u[sidx];
+      B.v[dst] = A.v[sidx];
+      B.w[dst] = A.w[sidx];
+    }
+  }
+}
+
+// An LDS item's gathered particles: positions to P', velocities to LDS.
+template <int DIM>
+__device__ __forceinline__ void pipe_place(const Particles<float> &B, const PipeMeta &m, const PipeRegs &pr,
+                                           float *su, float *sv, float *sw) {
+  if (m.n > kCollideCapF32) return;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < kPipeChunks; ++q) {
+    const int64_t k = q * 256 + tid;
+    if (k < m.n) {
+      const int64_t dst = m.so + m.b0 + k;
+      B.x[dst] = pr.x[q];
+      B.y[dst] = pr.y[q];
+      if (DIM == 3) B.z[dst] = pr.z[q];
+      su[k] = pr.u[q];
+      sv[k] = pr.v[q];
+      sw[k] = pr.w[q];
+    }
+  }
+}
+
+// Collisions, write-back, sampling and cell state of one item whose data is
+// in place (LDS su/sv/sw, or P' for an item beyond the LDS capacity).
+__device__ __forceinline__ void pipe_collide(const DevPtrs<float> &d, const Particles<float> &B, const PipeMeta &m,
+                                             float *su, float *sv, float *sw, int32_t *own,
+                                             BlockScratch<float> &sh, uint32_t step, bool sample) {
+  const int tid = threadIdx.x;
+  const int64_t n = m.n;
+  const bool lds = n <= kCollideCapF32;
+  float gm = m.gm, rem = m.rem;
+  const int64_t nsel = ntc_selections<float>(m.rv, n, gm, rem, d.err);
+  uint32_t ncol = 0;
+  float *gu = B.u + m.so + m.b0, *gv = B.v + m.so + m.b0, *gw = B.w + m.so + m.b0;
+  if (lds) {
+    ncol = chain_block<float, LdsSync>(m.rv, step, (uint32_t)m.c, (uint32_t)n, nsel, su, sv, sw, own, sh, gm);
+  } else {
+    __syncthreads();  // every thread's stores to P' are visible
+    if (tid == 0) {
+      ncol = chain_serial<float>(m.rv, step, (uint32_t)m.c, (uint32_t)n, 0, nsel, gu, gv, gw, gm);
+      sh.gm = gm;
+    }
+    __syncthreads();
+    gm = sh.gm;
+  }
+  LdsSync::bar();
+  if (lds)
+    for (int64_t k = tid; k < n; k += 256) {
+      gu[k] = su[k];
+      gv[k] = sv[k];
+      gw[k] = sw[k];
+    }
+  if (sample) {
+    // LDS and global are summed by separate loops: a pointer to either would
+    // be a flat access the compiler must also wait for as a global one
+    double sm[kFields] = {0, 0, 0, 0, 0, 0, 0};
+    auto add = [&](float uu, float vv, float ww) {
+      const double a = (double)uu, b = (double)vv, e = (double)ww;
+      sm[0] += 1.0;
+      sm[1] += a;
+      sm[2] += b;
+      sm[3] += e;
+      sm[4] += a * a;
+      sm[5] += b * b;
+      sm[6] += e * e;
+    };
+    if (lds)
+      for (int64_t k = tid; k < n; k += 256) add(su[k], sv[k], sw[k]);
+    else
+      for (int64_t k = tid; k < n; k += 256) add(gu[k], gv[k], gw[k]);
+#pragma unroll
+    for (int f = 0; f < kFields; ++f) {
+      double x = sm[f];
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+      if ((tid & 63) == 0) sh.red[tid >> 6][f] = x;
+    }
+    LdsSync::bar();
+    if (tid < kFields)
+      d.stage[m.gc * kFields + tid] = ((sh.red[0][tid] + sh.red[1][tid]) + sh.red[2][tid]) + sh.red[3][tid];
+  }
+  if (tid == 0) {
+    d.gmax[m.gc] = gm;
+    d.rem_c[m.gc] = rem;
+    d.ncoll[m.gc] = m.ncoll + ncol;
+  }
+  LdsSync::bar();  // LDS, own[] and sh are free again
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_collide_pipe(DevPtrs<float> d, int src, int64_t ci0, int64_t ci1) {
+  constexpr int CAP = kCollideCapF32;
+  __shared__ __align__(16) float vel[3 * CAP];
+  __shared__ int32_t own[CAP];
+  __shared__ PipeMeta meta[kPipeCells];
+  __shared__ BlockScratch<float> sh;
+  const int tid = threadIdx.x;
+  const int64_t first = ci0 + xcd_block(blockIdx.x, gridDim.x) * kPipeCells;
+  if (first >= ci1) return;
+  const int count = (int)min((int64_t)kPipeCells, ci1 - first);
+  const Particles<float> A = d.P[src], B = d.P[1 - src];
+  const uint32_t step = *d.step;
+  const bool sample = *d.sample_slot >= 0;
+  // bookkeeping of the block's items, once
+  if (tid < count) {
+    const int2 it = d.cell_items[first + tid];
+    const RunDev &R = d.runs[it.x];
+    PipeMeta m;
+    m.so = R.so;
+    m.c = it.y;
+    m.b0 = d.bin_start[R.bo + it.y];
+    m.n = (int64_t)d.bin_start[R.bo + it.y + 1] - m.b0;
+    m.gc = R.co + it.y;
+    m.ncoll = d.ncoll[m.gc];
+    m.gm = d.gmax[m.gc];
+    m.rem = d.rem_c[m.gc];
+    m.rv.key0 = R.key0;
+    m.rv.key1 = R.key1;
+    m.rv.hs = R.hs;
+    m.rv.c_ref = R.c_ref;
+    m.rv.vhs_exp = R.vhs_exp;
+    m.rv.coef = R.coef;
+    meta[tid] = m;
+  }
+  __syncthreads();
+  PipeRegs pr;
+  int32_t lc[kPipeChunks];
+  pipe_lcr(d.lcr, meta[0], true, pr.l);
+  pipe_gather<DIM>(d.lcr, A, B, meta[0], true, pr);
+  pipe_lcr(d.lcr, meta[count > 1 ? 1 : 0], count > 1, lc);
+  for (int j = 0; j < count; ++j) {
+    const PipeMeta m = meta[j];
+    const bool has1 = j + 1 < count, has2 = j + 2 < count;
+    // item j: positions to P', velocities to LDS (its gathers return here)
+    pipe_place<DIM>(B, m, pr, vel, vel + CAP, vel + 2 * CAP);
+    if (m.n > CAP) __threadfence_block();
+    LdsSync::bar();
+    // item j+1's gathers and item j+2's LCR entries start, then item j collides
+#pragma unroll
+    for (int q = 0; q < kPipeChunks; ++q) pr.l[q] = lc[q];
+    pipe_gather<DIM>(d.lcr, A, B, meta[has1 ? j + 1 : j], has1, pr);
+    pipe_lcr(d.lcr, meta[has2 ? j + 2 : j], has2, lc);
+    pipe_collide(d, B, m, vel, vel + CAP, vel + 2 * CAP, own, sh, step, sample);
   }
 }
 
@@ -1804,10 +2075,17 @@ static void lane_step(const Geometry &g, const LaneRange &L, const DevPtrs<real>
                                         (size_t)kCollideWaves * collide_wave_bytes<real>(), s, d, buf, L.it0,
                                         L.it1));
   }
-  if (L.ci1 > L.ci0)
-    TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_cell<real, DIM>), dim3((unsigned)(L.ci1 - L.ci0)),
-                                            dim3(256), (size_t)collide_cell_bytes<real>(), s, d, buf, L.ci0,
-                                            L.ci1));
+  if (L.ci1 > L.ci0) {
+    if constexpr (std::is_same<real, float>::value) {
+      const int64_t nblk = (L.ci1 - L.ci0 + kPipeCells - 1) / kPipeCells;
+      TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_pipe<DIM>), dim3((unsigned)nblk), dim3(256), 0, s, d, buf,
+                                              L.ci0, L.ci1));
+    } else {
+      TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_cell<real, DIM>), dim3((unsigned)(L.ci1 - L.ci0)),
+                                              dim3(256), (size_t)collide_cell_bytes<real>(), s, d, buf, L.ci0,
+                                              L.ci1));
+    }
+  }
 }
 
 template <typename real, int DIM>

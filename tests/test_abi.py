@@ -134,6 +134,25 @@ def test_obstacle_specs(dsmc):
         dsmc.make_run_spec(replace(wl.runs[0], solid=m[:, :, :5]))
 
 
+def test_autotune_workspace_covers_every_candidate(dsmc):
+    wl = W.channel(n_runs=8, nx=64, ny=16, ppc_inf=40.0, n_steps=10, sample_every=5)
+    specs = dsmc._specs(wl.runs)
+    opt = dsmc.make_options(False, 2, wl.sample_steps)
+    tune = dsmc.dsmc_autotune_bytes(specs, opt)
+    for tc in (64, 128, 256):
+        for mode in (1, 2):
+            for lanes in (1, 2):
+                o = dsmc.make_options(False, 2, wl.sample_steps, tile_chunks=tc, collide_mode=mode,
+                                      n_streams=lanes)
+                assert dsmc.dsmc_required_bytes(specs, o) <= tune
+    # argument errors before any device work
+    best = dsmc.dsmc_options()
+    assert dsmc.lib().dsmc_autotune(specs, len(specs), C.byref(opt), None, 0, None, 0, C.byref(best),
+                                    None) == -1
+    assert dsmc.lib().dsmc_autotune(specs, len(specs), C.byref(opt), None, 0, None, 3, C.byref(best),
+                                    None) == -2
+
+
 def test_counting_sort_workspace_query(dsmc):
     assert dsmc.dsmc_counting_sort_bytes(0, 1) > 0
     assert dsmc.dsmc_counting_sort_bytes(1 << 20, 1025) < dsmc.dsmc_counting_sort_bytes(1 << 20, 20000)

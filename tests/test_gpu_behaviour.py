@@ -91,6 +91,42 @@ def test_stream_lanes_do_not_change_results(dsmc_gpu, fp64, graph):
         E.close()
 
 
+def test_autotuned_settings_give_identical_results(dsmc_gpu):
+    """dsmc_autotune picks tuning fields by timing; a context built with them
+    follows the default context bit for bit."""
+    import torch
+    runs = _small_channel_runs(8)
+    tuned = dsmc_gpu.Ensemble.autotune(runs, [3, 6], state_fp64=False, n_groups=2, use_graph=True, n_steps=2)
+    assert tuned["tile_chunks"] in (64, 128, 256) and tuned["n_streams"] in (1, 2)
+    assert tuned["collide_mode"] in (0, 1, 2) and tuned["ms_per_step"] > 0
+    kw = {k: tuned[k] for k in ("tile_chunks", "collide_mode", "n_streams")}
+    A = dsmc_gpu.Ensemble(runs, [3, 6], state_fp64=False, n_groups=2, use_graph=True)
+    B = dsmc_gpu.Ensemble(runs, [3, 6], state_fp64=False, n_groups=2, use_graph=True, **kw)
+    A.step(6)
+    B.step(6)
+    torch.cuda.synchronize()
+    for r in range(len(runs)):
+        np.testing.assert_array_equal(A.state(r), B.state(r))
+    for k in range(2):
+        np.testing.assert_array_equal(A.accum(k), B.accum(k))
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_interaction_modes_give_identical_results(dsmc_gpu, mode):
+    """The lane-per-cell and block-per-cell interaction kernels both run each
+    cell's selections in the sequential order: FP32 results are identical."""
+    import torch
+    runs = _small_channel_runs(3)
+    A = dsmc_gpu.Ensemble(runs, [4], state_fp64=False, n_groups=1, collide_mode=0)
+    B = dsmc_gpu.Ensemble(runs, [4], state_fp64=False, n_groups=1, collide_mode=mode)
+    A.step(4)
+    B.step(4)
+    torch.cuda.synchronize()
+    for r in range(len(runs)):
+        np.testing.assert_array_equal(A.state(r), B.state(r))
+        np.testing.assert_array_equal(A.cell_state(r)["ncoll"], B.cell_state(r)["ncoll"])
+
+
 def test_capacity_overflow_is_reported(dsmc_gpu):
     rs = replace(W.channel_run(nx=32, ny=8, lx=2.0, ly=0.5, ppc_inf=40.0, seed=3), capacity=2000)
     E = dsmc_gpu.Ensemble([rs], [], state_fp64=False)
