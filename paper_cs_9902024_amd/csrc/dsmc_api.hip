@@ -192,7 +192,7 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
       const double ppc = fill / (double)R.nc;
       R.coll_wave = opt.collide_mode == 2 || (opt.collide_mode == 0 && ppc >= 64.0);
       // lane mode: as many cells per wavefront (<= 64) as fit 3/4 of the LDS stage
-      const int cap = g.fp64 ? kCollideCapF64 : kCollideCapF32;
+      const int cap = g.fp64 ? kLaneCapF64 : kLaneCapF32;
       R.lane_cells = (int32_t)std::max(1.0, std::min(64.0, std::floor(0.75 * cap / std::max(ppc, 1.0))));
       if (R.coll_wave)
         for (int32_t c = 0; c < R.nc; ++c) P.cell_items.push_back(make_int2(r, c));

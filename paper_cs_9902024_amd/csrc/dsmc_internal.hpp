@@ -13,6 +13,8 @@ constexpr int kWavesPerBlock = 4;          // 256-thread blocks
 constexpr int kCollideWaves = 2;           // waves per block of the collide kernel
 constexpr int kCollideCapF32 = 1280;       // particles staged in LDS per collide wavefront
 constexpr int kCollideCapF64 = 1024;
+constexpr int kLaneCapF32 = 640;           // particles staged in LDS per lane-per-cell wavefront
+constexpr int kLaneCapF64 = 512;
 constexpr int kDigitBits = 11;             // indexing digit: 2048 bins per pass
 constexpr int kDigits = 1 << kDigitBits;
 constexpr int kMaxWallHits = 64;           // wall interactions per particle per step

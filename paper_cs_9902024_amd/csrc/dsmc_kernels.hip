@@ -1057,9 +1057,15 @@ template <typename real> struct CollideCap;
 template <> struct CollideCap<float> { static constexpr int value = kCollideCapF32; };
 template <> struct CollideCap<double> { static constexpr int value = kCollideCapF64; };
 
+// Lane-per-cell items: a smaller stage per wavefront (velocities only), so
+// more wavefronts fit a CU for the gather.
+template <typename real> struct LaneCap;
+template <> struct LaneCap<float> { static constexpr int value = kLaneCapF32; };
+template <> struct LaneCap<double> { static constexpr int value = kLaneCapF64; };
+
 template <typename real>
 constexpr int collide_wave_bytes() {
-  return ((CollideCap<real>::value * (3 * (int)sizeof(real) + 4)) + 15) & ~15;
+  return ((LaneCap<real>::value * 3 * (int)sizeof(real)) + 15) & ~15;
 }
 
 // Block index remapped so that each XCD (blocks are dealt round-robin over
@@ -1279,7 +1285,7 @@ __device__ __forceinline__ void global_sync_wave() {
 template <typename real, int DIM>
 __global__ __launch_bounds__(kCollideWaves * 64) void k_collide(DevPtrs<real> d, int src, int64_t it0, int64_t it1) {
   extern __shared__ __align__(16) unsigned char lds_bytes[];
-  constexpr int CAP = CollideCap<real>::value;
+  constexpr int CAP = LaneCap<real>::value;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t item = it0 + xcd_block(blockIdx.x, gridDim.x) * kCollideWaves + wave;
   if (item >= it1) return;
@@ -1289,7 +1295,6 @@ __global__ __launch_bounds__(kCollideWaves * 64) void k_collide(DevPtrs<real> d,
   const int32_t ncell = min(R.lane_cells, R.nc - c0);
   real *su = (real *)(lds_bytes + wave * collide_wave_bytes<real>());
   real *sv = su + CAP, *sw = sv + CAP;
-  int32_t *own = (int32_t *)(sw + CAP);
   const Particles<real> A = d.P[src], B = d.P[1 - src];
   const int64_t b0 = d.bin_start[R.bo + c0];
   const int64_t n = (int64_t)d.bin_start[R.bo + c0 + ncell] - b0;
@@ -1613,7 +1618,7 @@ __global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, 
 // arithmetic).  The items' bookkeeping (slots, bin range, NTC state, the
 // run's constants) is read once per block into LDS, so the collisions read
 // no global memory.
-constexpr int kPipeCells = 8;
+constexpr int kPipeCells = 16;
 constexpr int kPipeChunks = kCollideCapF32 / 256;
 
 // The run constants the collisions need.
