@@ -919,18 +919,44 @@ __global__ __launch_bounds__(256) void k_digscan(IndexArgs a) {
   }
 }
 
+// Rank of each lane among the active lanes holding the same digit (lanes
+// below it) and the size of that group, from one ballot per distinct digit
+// present.  Inactive lanes hold kNoDigit.
+constexpr uint32_t kNoDigit = 0xFFFFFFFFu;
+
+__device__ __forceinline__ void rank_in_wave(uint32_t key, uint64_t rest, uint32_t &rank, uint32_t &cnt) {
+  rank = 0;
+  cnt = 0;
+  while (rest) {
+    const int leader = (int)__builtin_ctzll(rest);
+    const uint32_t dl = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
+    const bool same = key == dl;
+    const uint64_t pm = __builtin_amdgcn_ballot_w64(same);
+    if (same) {
+      rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(pm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)pm, 0u));
+      cnt = (uint32_t)__popcll(pm);
+    }
+    rest &= ~pm;
+  }
+}
+
 // One wavefront per tile, 64 consecutive positions per round in order: the
 // rank of a position among equal digits is (digit start) + (count in earlier
 // tiles) + (count in earlier rounds of this tile) + (earlier lanes with the
 // same digit, from ballots).  That is exactly the sequential stable order.
 // The first two terms are summed into the wave's LDS cursor table up front.
-// KEYS: the bins come from a.kin (or cell[] in pass 0) and are written to
-// a.kout in the output order, so later passes and the bin bounds read them
-// sequentially instead of gathering cell[] through the order.
-template <bool KEYS>
+// CARRIED: positions and bins come from the previous pass (a.in, a.kin);
+// otherwise the positions are the slots and the bins are read from cell[].
+// KOUT: the bins are also written to a.kout in the output order, so the next
+// pass and the bin bounds read them sequentially.
+// The sources are read sequentially with no per-lane condition, and the next
+// chunk's reads are issued before the current chunk is ranked, so their
+// latency overlaps the ranking; the ragged last chunk is handled apart.
+template <bool KOUT, bool CARRIED>
 __global__ __launch_bounds__(256) void k_scatter(IndexArgs a) {
   extern __shared__ uint32_t lds[];
   constexpr int U = 16;
+  constexpr int CH = U * kWave;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int t = a.t0 + (int)blockIdx.x * kWavesPerBlock + wave;
   if (t >= a.t1) return;
@@ -938,6 +964,7 @@ __global__ __launch_bounds__(256) void k_scatter(IndexArgs a) {
   const RunDev &R = a.runs[r];
   const int64_t tl = t - R.to;
   const bool single = a.single;
+  const int pass = a.pass;
   const int D = single ? R.nc + 1 : kDigits;
   uint32_t *cursor = lds + wave * a.dstride;
   {
@@ -948,49 +975,59 @@ __global__ __launch_bounds__(256) void k_scatter(IndexArgs a) {
   wave_sync();
   const int64_t n = a.n_sorted[r];
   const int64_t begin = tl * a.tile, end = min(begin + a.tile, n);
-  const uint64_t lt = (1ull << lane) - 1ull;
-  const int32_t *__restrict__ in = a.in ? a.in + R.so : nullptr;
-  const int32_t *__restrict__ cell = a.cell + R.so;
+  if (begin >= end) return;
+  const uint64_t all = ~0ull;
+  const int32_t *__restrict__ src_v = CARRIED ? a.in + R.so : nullptr;
+  const int32_t *__restrict__ src_b = CARRIED ? a.kin + R.so : a.cell + R.so;
   int32_t *__restrict__ out = a.out + R.so;
-  const int32_t *__restrict__ kin = KEYS && a.kin ? a.kin + R.so : nullptr;
-  int32_t *__restrict__ kout = KEYS ? a.kout + R.so : nullptr;
-  for (int64_t b = begin; b < end; b += U * kWave) {
-    int32_t v[U];
-    int32_t bin[U];
-    uint32_t key[U];
-    bool act[U];
+  int32_t *__restrict__ kout = KOUT ? a.kout + R.so : nullptr;
+  const int64_t nfull = (end - begin) / CH;
+  const int64_t full_end = begin + nfull * CH;
+  int32_t nv[U], nb[U];
+  // reads of the chunk at b, clamped into the tile so they never branch
+#define SCATTER_LOAD(b)                                        \
+  _Pragma("unroll") for (int q = 0; q < U; ++q) {              \
+    const int64_t loc = min((b) + q * kWave + lane, end - 1);  \
+    nb[q] = src_b[loc];                                        \
+    if (CARRIED) nv[q] = src_v[loc];                           \
+  }
+  SCATTER_LOAD(begin);
+  for (int64_t b = begin; b < full_end; b += CH) {
+    int32_t v[U], bin[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      const int64_t loc = b + q * kWave + lane;
-      act[q] = loc < end;
-      v[q] = act[q] ? (in ? in[loc] : (int32_t)loc) : 0;
-      if (KEYS && kin) bin[q] = act[q] ? kin[loc] : 0;
+      v[q] = CARRIED ? nv[q] : (int32_t)(b + q * kWave + lane);
+      bin[q] = nb[q];
     }
+    SCATTER_LOAD(b + CH);
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      if (!(KEYS && kin)) bin[q] = act[q] ? cell[v[q]] : 0;
-      key[q] = act[q] ? digit_of(bin[q], a.pass, single) : 0u;
+      const uint32_t key = digit_of(bin[q], pass, single);
+      uint32_t rank, cnt;
+      rank_in_wave(key, all, rank, cnt);
+      const uint32_t prior = cursor[key];
+      out[prior + rank] = v[q];
+      if (KOUT) kout[prior + rank] = bin[q];
+      if (rank == cnt - 1) cursor[key] = prior + cnt;
+      wave_sync();
     }
+  }
+#undef SCATTER_LOAD
+  if (full_end < end) {
+    // the ragged last chunk: its reads were issued by the last full chunk
+    // (or before the loop)
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      // lanes holding the same digit: one ballot per distinct digit present
-      uint64_t rest = __ballot(act[q]);
-      uint64_t peers = 0;
-      while (rest) {
-        const int leader = __ffsll((unsigned long long)rest) - 1;
-        const uint32_t dl = (uint32_t)__builtin_amdgcn_readlane((int)key[q], leader);
-        const bool same = act[q] && key[q] == dl;
-        const uint64_t pm = __ballot(same);
-        if (same) peers = pm;
-        rest &= ~pm;
-      }
-      if (act[q]) {
-        const uint32_t rank = __popcll(peers & lt);
-        const uint32_t cnt = __popcll(peers);
-        const uint32_t prior = cursor[key[q]];
-        out[prior + rank] = v[q];
-        if (KEYS) kout[prior + rank] = bin[q];
-        if (rank == cnt - 1) cursor[key[q]] = prior + cnt;
+      const int64_t loc = full_end + q * kWave + lane;
+      const bool act = loc < end;
+      const uint32_t key = act ? digit_of(nb[q], pass, single) : kNoDigit;
+      uint32_t rank, cnt;
+      rank_in_wave(key, __builtin_amdgcn_ballot_w64(act), rank, cnt);
+      if (act) {
+        const uint32_t prior = cursor[key];
+        out[prior + rank] = CARRIED ? nv[q] : (int32_t)loc;
+        if (KOUT) kout[prior + rank] = nb[q];
+        if (rank == cnt - 1) cursor[key] = prior + cnt;
       }
       wave_sync();
     }
@@ -1988,10 +2025,16 @@ static void index_pass(IndexArgs a, int max_digits, int n_runs, int pass, const 
   const int wblocks = (a.t1 - a.t0 + kWavesPerBlock - 1) / kWavesPerBlock;
   TIMED(kKColScan, hipLaunchKernelGGL(k_colscan, dim3((max_digits + 255) / 256, n_runs), dim3(256), 0, s, a));
   TIMED(kKDigScan, hipLaunchKernelGGL(k_digscan, dim3(n_runs), dim3(256), 0, s, a));
-  if (a.kout)
-    TIMED(kKScatter, hipLaunchKernelGGL(k_scatter<true>, dim3(wblocks), dim3(256), lds, s, a));
+  // positions come either from the slots (first pass) or, with their bins
+  // (a.kin, always set together with a.in), from the previous pass
+  if (a.kout && a.in)
+    TIMED(kKScatter, hipLaunchKernelGGL((k_scatter<true, true>), dim3(wblocks), dim3(256), lds, s, a));
+  else if (a.kout)
+    TIMED(kKScatter, hipLaunchKernelGGL((k_scatter<true, false>), dim3(wblocks), dim3(256), lds, s, a));
+  else if (a.in)
+    TIMED(kKScatter, hipLaunchKernelGGL((k_scatter<false, true>), dim3(wblocks), dim3(256), lds, s, a));
   else
-    TIMED(kKScatter, hipLaunchKernelGGL(k_scatter<false>, dim3(wblocks), dim3(256), lds, s, a));
+    TIMED(kKScatter, hipLaunchKernelGGL((k_scatter<false, false>), dim3(wblocks), dim3(256), lds, s, a));
 }
 
 template <typename real>
