@@ -193,7 +193,7 @@ dsmc_status dsmc_get_counts(dsmc_ctx *ctx, int64_t *out, int32_t n_runs);
 
 /* ---- per-kernel timing ----------------------------------------------------- */
 
-#define DSMC_NKERNELS 16 /* kernel kinds; names from dsmc_kernel_name */
+#define DSMC_NKERNELS 18 /* kernel kinds; names from dsmc_kernel_name */
 
 /* Turn per-kernel timing on or off (synchronises).  While on, every launch is
  * bracketed by two HIP events on the context's stream and steps are not

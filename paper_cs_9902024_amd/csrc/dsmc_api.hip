@@ -31,7 +31,8 @@ struct Ensemble {
 struct Plan {
   Geometry g{};
   std::vector<RunDev> runs;
-  std::vector<int32_t> tile_run, face_run, cgroup_run, inflow_runs, eg_start, eg_runs, eg_nc, sample_steps;
+  std::vector<int32_t> tile_run, face_run, cgroup_run, inflow_runs, eg_start, eg_runs, eg_nc, sample_steps,
+      bitem_run;
   std::vector<int64_t> eg_acc;
   std::vector<int2> items, cell_items;
   std::vector<uint8_t> solid;
@@ -42,7 +43,7 @@ struct Plan {
   size_t off_P[2][6];
   size_t off_cell, off_lcr, off_lcr_tmp, off_hist, off_tot, off_bin_start, off_remc, off_gmax, off_ncoll, off_remf,
       off_gencnt, off_stage, off_acc, off_mom, off_nalive, off_nsorted, off_ngen, off_scalars, off_wallq, off_wallq_n,
-      off_key_tmp;
+      off_key_tmp, off_bitem, off_bitem_run, off_bfirst;
   size_t total;
 };
 
@@ -157,13 +158,16 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
     g.npass = (bits + kDigitBits - 1) / kDigitBits;
   }
   g.dstride = g.npass == 1 ? max_nc + 1 : kDigits;
+  // two passes: buckets of 2048 bins first (the bins of nearly sorted input
+  // then reach a few buckets per tile), then each bucket by its low digit
+  g.bucketed = g.npass == 2;
 
   P.runs.resize(n_runs);
   P.spec_capacity.resize(n_runs);
   // end of each run's share of the per-run lists (for the lane split)
   std::vector<LaneRange> ends(n_runs);
   int64_t so = 0, co = 0, bo = 0, mo = 0, cbo = 0, fo = 0;
-  int32_t to = 0;
+  int32_t to = 0, io = 0;
   for (int r = 0; r < n_runs; ++r) {
     const dsmc_run_spec &s = runs[r];
     RunDev &R = P.runs[r];
@@ -182,6 +186,14 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
     R.nt = (int32_t)(cap / g.tile);
     R.ndig = g.npass == 1 ? R.nc + 1 : kDigits;
     R.mo = mo;
+    if (g.bucketed) {
+      // the run's histogram rows: its tiles (first pass), then its bucket
+      // items (second pass) in the same private region
+      R.nb = (R.nc >> kDigitBits) + 1;
+      R.icap = R.nt + R.nb;
+      R.io = io;
+      R.mo = (int64_t)io * kDigits;
+    }
     R.cbo = cbo;
     R.n_init = s.n_init;
     R.hs = s.omega == 0.5;
@@ -269,6 +281,7 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
       P.solid.resize(round_up((int64_t)P.solid.size(), 256), 0);
     }
     for (int t = 0; t < R.nt; ++t) P.tile_run.push_back(r);
+    for (int i = 0; i < R.icap; ++i) P.bitem_run.push_back(r);
     for (int64_t k = 0; k < round_up(R.nc, 64) / 64; ++k) P.cgroup_run.push_back(r);
     P.spec_capacity[r] = s.capacity;
     ends[r].t1 = to + R.nt;
@@ -276,11 +289,14 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
     ends[r].i1 = (int32_t)P.inflow_runs.size();
     ends[r].it1 = (int64_t)P.items.size();
     ends[r].ci1 = (int64_t)P.cell_items.size();
+    ends[r].b1 = io + R.icap;
     so += cap;
     to += R.nt;
     co += round_up(R.nc, 64);
     bo += R.nc + 2;
     mo += (int64_t)R.nt * R.ndig;
+    io += R.icap;
+    if (g.bucketed) mo = (int64_t)io * kDigits;
     cbo += R.ndig;
     fo += R.nface;
   }
@@ -288,6 +304,7 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
   g.n_tiles = to;
   g.n_cells = co;
   g.n_faces = fo;
+  g.n_bitems = io;
   g.n_inflow_runs = (int32_t)P.inflow_runs.size();
   g.n_items = (int64_t)P.items.size();
   g.n_cell_items = (int64_t)P.cell_items.size();
@@ -319,12 +336,14 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
       L.i0 = prev ? prev->i1 : 0;
       L.it0 = prev ? prev->it1 : 0;
       L.ci0 = prev ? prev->ci1 : 0;
+      L.b0 = prev ? prev->b1 : 0;
       const LaneRange &e = ends[L.r1 - 1];
       L.t1 = e.t1;
       L.f1 = e.f1;
       L.i1 = e.i1;
       L.it1 = e.it1;
       L.ci1 = e.ci1;
+      L.b1 = e.b1;
     }
   }
 
@@ -390,6 +409,9 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
   P.off_lcr_tmp = g.npass > 1 ? take(4 * g.n_slots) : (size_t)-1;
   P.off_key_tmp = g.npass > 1 ? take(4 * g.n_slots) : (size_t)-1;
   P.off_hist = take(4 * (size_t)mo);
+  P.off_bitem = take(sizeof(int2) * (size_t)g.n_bitems);
+  P.off_bitem_run = take(4 * P.bitem_run.size());
+  P.off_bfirst = take(g.bucketed ? 4 * (size_t)n_runs * (kDigits + 1) : 0);
   P.off_tot = take(4 * (size_t)cbo);
   P.off_bin_start = take(4 * (size_t)bo);
   P.off_remc = take(es * g.n_cells);
@@ -451,6 +473,9 @@ DevPtrs<real> carve(const Plan &P, char *base) {
   d.err = (int32_t *)(base + P.off_scalars + 8);
   d.wallq_n = (uint32_t *)(base + P.off_wallq_n);
   d.wallq = (uint32_t *)(base + P.off_wallq);
+  d.bitem = (int2 *)(base + P.off_bitem);
+  d.bitem_run = (const int32_t *)(base + P.off_bitem_run);
+  d.bfirst = (int32_t *)(base + P.off_bfirst);
   return d;
 }
 
@@ -675,6 +700,7 @@ dsmc_status dsmc_init_runs(const dsmc_run_spec *runs, int32_t n_runs, const dsmc
   else c->df = carve<float>(P, c->arena);
   st = upload(c, P.off_runs, P.runs);
   if (!st) st = upload(c, P.off_tile_run, P.tile_run);
+  if (!st) st = upload(c, P.off_bitem_run, P.bitem_run);
   if (!st) st = upload(c, P.off_face_run, P.face_run);
   if (!st) st = upload(c, P.off_cgroup_run, P.cgroup_run);
   if (!st) st = upload(c, P.off_inflow, P.inflow_runs);
@@ -1001,7 +1027,8 @@ dsmc_status dsmc_kernel_times(dsmc_ctx *c, double *ms, int64_t *launches, int32_
 const char *dsmc_kernel_name(int32_t kind) {
   static const char *names[kNumKinds] = {"step_begin", "gen_count", "gen_emit", "motion", "motion_walls", "digcount",
                                          "colscan", "digscan", "scatter", "bin_bounds", "bin_finalize",
-                                         "collide_lanes", "collide_cells", "accumulate", "sample", "moments"};
+                                         "collide_lanes", "collide_cells", "accumulate", "sample", "moments",
+                                         "bucket_items", "bucket_scan"};
   if (kind < 0 || kind >= kNumKinds) return nullptr;
   return names[kind];
 }

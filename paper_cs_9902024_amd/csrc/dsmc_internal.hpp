@@ -41,6 +41,9 @@ struct RunDev {
   int64_t bo;        // first entry of the run in the bin-start array (nc + 2 entries)
   int64_t mo;        // first entry of the run in the tile histogram matrix
   int64_t cbo;       // first entry of the run in the digit-total array
+  int64_t io;        // two-level Indexing: first bucket-item slot of the run
+  int32_t nb;        // two-level Indexing: buckets (bins >> 11) of the run
+  int32_t icap;      // two-level Indexing: bucket-item slots of the run (tiles + buckets)
   int64_t fo;        // first inflow face of the run
   int64_t n_init;
   int32_t to;        // first tile of the run
@@ -110,6 +113,10 @@ struct DevPtrs {
   int32_t *err;                // first device error (0 = none)
   uint32_t *wallq;             // [slots] per tile: run-local slots of particles that reach a face
   uint32_t *wallq_n;           // [tiles] queue length per tile
+  // two-level Indexing (runs with 2049 .. 2^22 bins)
+  int2 *bitem;                 // [bucket-item slots] (bucket, chunk), bucket -1 = unused slot
+  const int32_t *bitem_run;    // [bucket-item slots] run of the slot
+  int32_t *bfirst;             // [runs][2049] first item (run-local) of each bucket; [nb] = items
 };
 
 // The contiguous share of one stream lane: runs [r0, r1) and everything laid
@@ -122,6 +129,7 @@ struct LaneRange {
   int32_t i0, i1;    // entries of the inflow-run list
   int64_t it0, it1;  // lane-per-cell interaction items
   int64_t ci0, ci1;  // block-per-cell interaction items
+  int32_t b0, b1;    // bucket-item slots (two-level Indexing)
 };
 
 struct Geometry {
@@ -136,6 +144,8 @@ struct Geometry {
   int64_t n_faces;
   int32_t n_inflow_runs;
   int npass;             // indexing passes (1: digit = bin)
+  int bucketed;          // two passes: high digit first, then the low digit within each bucket
+  int32_t n_bitems;      // bucket-item slots
   int dstride;           // LDS words per wave for one histogram
   int max_nc;
   int n_eg;
@@ -163,7 +173,8 @@ struct LaneStreams {
 // Kernel kinds for per-kernel event timing (order = dsmc_kernel_name).
 enum KernelKind : int {
   kKStepBegin, kKGenCount, kKGenEmit, kKMotion, kKMotionWalls, kKDigCount, kKColScan, kKDigScan, kKScatter,
-  kKBinBounds, kKBinFinalize, kKCollide, kKCollideCell, kKAccumulate, kKSample, kKMoments, kNumKinds
+  kKBinBounds, kKBinFinalize, kKCollide, kKCollideCell, kKAccumulate, kKSample, kKMoments, kKBucketItems,
+  kKBucketScan, kNumKinds
 };
 
 // Optional hook around every launch (event timing); null = no hook.

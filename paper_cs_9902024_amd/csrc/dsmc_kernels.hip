@@ -32,8 +32,10 @@ __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
-    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    // one 32x32->64 multiply gives both halves of each product
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
+    const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+    const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
     c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
   }
   return c;
@@ -620,7 +622,7 @@ __device__ __forceinline__ void store4(real *p, int64_t i, const real (&o)[4]) {
 // kept in wave-private LDS.
 template <typename real, int DIM, bool SINGLE, bool OBST>
 __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_t t0, int32_t t1, int64_t tile,
-                                                int dstride) {
+                                                int dstride, int shift0) {
   extern __shared__ uint32_t lds[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int t = t0 + (int)blockIdx.x * kWavesPerBlock + wave;
@@ -694,7 +696,7 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
         c = (iz * R.ny + iy) * R.nx + ix;
       }
       oc[e] = c;
-      key[e] = SINGLE ? (uint32_t)c : ((uint32_t)c & (kDigits - 1));
+      key[e] = SINGLE ? (uint32_t)c : (((uint32_t)c >> shift0) & (kDigits - 1));
     }
     // (a queued particle's position and cell are rewritten by k_motion_walls)
     if (full) {
@@ -735,7 +737,7 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
 // their cells added to the tile histogram of the first indexing digit.
 template <typename real, int DIM, bool SINGLE>
 __global__ __launch_bounds__(256) void k_motion_walls(DevPtrs<real> d, int buf, int32_t t0, int32_t t1,
-                                                      int64_t tile) {
+                                                      int64_t tile, int shift0) {
   const int32_t t = t0 + (int32_t)blockIdx.x;
   if (t >= t1) return;
   const uint32_t nq = d.wallq_n[t];
@@ -762,7 +764,7 @@ __global__ __launch_bounds__(256) void k_motion_walls(DevPtrs<real> d, int buf, 
       if (DIM == 3 || reemit) P.w[gs] = v3[2];
     }
     d.cell[gs] = c;
-    atomicAdd(&Mt[SINGLE ? (uint32_t)c : ((uint32_t)c & (kDigits - 1))], 1u);
+    atomicAdd(&Mt[SINGLE ? (uint32_t)c : (((uint32_t)c >> shift0) & (kDigits - 1))], 1u);
   }
 }
 
@@ -789,12 +791,18 @@ struct IndexArgs {
   int32_t r0;              // first run (grid y / x of the per-run scans)
   int64_t tile;
   int dstride;
-  int pass;
+  int shift;               // digit = (bin >> shift) & (kDigits - 1), unless single
   int single;
+  // second pass of the two-level sort: work items = chunks of `tile`
+  // positions of one bucket (the positions whose bins share bin >> 11)
+  int2 *bitem;             // (bucket, chunk) per item slot, bucket -1 = unused
+  const int32_t *bitem_run;
+  int32_t *bfirst;         // per run kDigits + 1: first item (run-local) of each bucket
+  int32_t b0, b1;          // item slots [b0, b1)
 };
 
-__device__ __forceinline__ uint32_t digit_of(int32_t bin, int pass, bool single) {
-  return single ? (uint32_t)bin : (((uint32_t)bin >> (kDigitBits * pass)) & (kDigits - 1));
+__device__ __forceinline__ uint32_t digit_of(int32_t bin, int shift, bool single) {
+  return single ? (uint32_t)bin : (((uint32_t)bin >> shift) & (kDigits - 1));
 }
 
 // Tile histogram of one digit over an existing order (passes after the first,
@@ -821,13 +829,13 @@ __global__ __launch_bounds__(256) void k_digcount(IndexArgs a, int use_n_alive) 
       const int64_t i0 = b + 4 * lane;
       if (b + 4 * kWave <= end) {
         const int4 k4 = *reinterpret_cast<const int4 *>(kin + i0);
-        atomicAdd(&h[digit_of(k4.x, a.pass, single)], 1u);
-        atomicAdd(&h[digit_of(k4.y, a.pass, single)], 1u);
-        atomicAdd(&h[digit_of(k4.z, a.pass, single)], 1u);
-        atomicAdd(&h[digit_of(k4.w, a.pass, single)], 1u);
+        atomicAdd(&h[digit_of(k4.x, a.shift, single)], 1u);
+        atomicAdd(&h[digit_of(k4.y, a.shift, single)], 1u);
+        atomicAdd(&h[digit_of(k4.z, a.shift, single)], 1u);
+        atomicAdd(&h[digit_of(k4.w, a.shift, single)], 1u);
       } else {
         for (int e = 0; e < 4; ++e)
-          if (i0 + e < end) atomicAdd(&h[digit_of(kin[i0 + e], a.pass, single)], 1u);
+          if (i0 + e < end) atomicAdd(&h[digit_of(kin[i0 + e], a.shift, single)], 1u);
       }
     }
   } else {
@@ -835,7 +843,7 @@ __global__ __launch_bounds__(256) void k_digcount(IndexArgs a, int use_n_alive) 
       const int64_t loc = b + lane;
       if (loc < end) {
         const int32_t v = a.in ? a.in[R.so + loc] : (int32_t)loc;
-        atomicAdd(&h[digit_of(a.cell[R.so + v], a.pass, single)], 1u);
+        atomicAdd(&h[digit_of(a.cell[R.so + v], a.shift, single)], 1u);
       }
     }
   }
@@ -919,6 +927,169 @@ __global__ __launch_bounds__(256) void k_digscan(IndexArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Two-level sort (2049 .. 2^22 bins): the first pass orders the positions by
+// bucket (bin >> 11) with the tile machinery above; the second sorts every
+// bucket by its low digit.  Its work items are chunks of `tile` positions of
+// one bucket, listed per run by k_bucket_items.  Each bucket's digit starts
+// are the bin starts of its 2048 cells, so no bin bounds pass is needed.
+// ---------------------------------------------------------------------------
+
+// End of bucket h's positions [A_h, A_{h+1}) in run r: A_h are the first
+// pass' digit starts, the last bucket ends at the run's count.
+__device__ __forceinline__ int64_t bucket_end(const IndexArgs &a, const RunDev &R, int r, int h) {
+  return h + 1 < R.nb ? (int64_t)a.tot[R.cbo + h + 1] : (int64_t)a.n_sorted[r];
+}
+
+// Run, bucket and position range of bucket item slot i; false for an unused slot.
+__device__ __forceinline__ bool bucket_item(const IndexArgs &a, int32_t i, int &r, int &h, int64_t &begin,
+                                            int64_t &end) {
+  const int2 hk = a.bitem[i];
+  if (hk.x < 0) return false;
+  r = a.bitem_run[i];
+  const RunDev &R = a.runs[r];
+  h = hk.x;
+  begin = (int64_t)a.tot[R.cbo + h] + (int64_t)hk.y * a.tile;
+  end = min(begin + a.tile, bucket_end(a, R, r, h));
+  return true;
+}
+
+// Exclusive scan of one value per thread across a 256-thread block.
+__device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t *part) {
+  const int tid = threadIdx.x;
+  part[tid] = v;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const int64_t add = tid >= o ? part[tid - o] : 0;
+    __syncthreads();
+    part[tid] += add;
+    __syncthreads();
+  }
+  const int64_t incl = part[tid];
+  __syncthreads();
+  return incl - v;
+}
+
+// One block per run: the bucket items (bucket, chunk) of the run in bucket
+// order, each bucket's first item, and -1 in the run's unused item slots.
+__global__ __launch_bounds__(256) void k_bucket_items(IndexArgs a) {
+  __shared__ int64_t part[256];
+  const int r = a.r0 + (int)blockIdx.x;
+  const RunDev &R = a.runs[r];
+  const int tid = threadIdx.x;
+  const int per = (R.nb + 255) / 256;  // <= 8
+  const int h0 = tid * per;
+  int32_t nch[8];
+  int64_t sum = 0;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int h = h0 + e;
+    int32_t c = 0;
+    if (e < per && h < R.nb) {
+      const int64_t size = bucket_end(a, R, r, h) - (int64_t)a.tot[R.cbo + h];
+      c = (int32_t)((size + a.tile - 1) / a.tile);
+    }
+    nch[e] = c;
+    sum += c;
+  }
+  const int64_t excl = block_exclusive_scan(sum, part);
+  int32_t first = (int32_t)excl;
+  int32_t *bf = a.bfirst + (int64_t)r * (kDigits + 1);
+  int2 *items = a.bitem + R.io;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int h = h0 + e;
+    if (e < per && h < R.nb) {
+      bf[h] = first;
+      for (int32_t k = 0; k < nch[e]; ++k) items[first + k] = make_int2(h, k);
+      first += nch[e];
+    }
+  }
+  const int32_t total = (int32_t)(part[255]);  // inclusive sum of the last thread
+  if (tid == 0) bf[R.nb] = total;
+  for (int32_t i = total + tid; i < R.icap; i += 256) items[i] = make_int2(-1, 0);
+}
+
+// Low-digit histogram of one bucket item (one wavefront per item slot).
+__global__ __launch_bounds__(256) void k_digcount_bucket(IndexArgs a) {
+  extern __shared__ uint32_t lds[];
+  constexpr int U = 8;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int32_t i = a.b0 + (int)blockIdx.x * kWavesPerBlock + wave;
+  if (i >= a.b1) return;
+  int r, h;
+  int64_t begin, end;
+  if (!bucket_item(a, i, r, h, begin, end)) return;
+  const RunDev &R = a.runs[r];
+  uint32_t *hs = lds + wave * kDigits;
+  for (int q = lane; q < kDigits; q += kWave) hs[q] = 0;
+  wave_sync();
+  const int32_t *__restrict__ kin = a.kin + R.so;
+  for (int64_t b = begin; b < end; b += U * kWave) {
+    int32_t k[U];
+#pragma unroll
+    for (int e = 0; e < U; ++e) k[e] = kin[min(b + e * kWave + lane, end - 1)];
+#pragma unroll
+    for (int e = 0; e < U; ++e)
+      if (b + e * kWave + lane < end) atomicAdd(&hs[(uint32_t)k[e] & (kDigits - 1)], 1u);
+  }
+  wave_sync();
+  uint32_t *M = a.hist + (int64_t)i * kDigits;
+  for (int q = lane; q < kDigits; q += kWave) M[q] = hs[q];
+}
+
+// One block per (bucket, run): for every low digit, the counts of the
+// bucket's earlier items in place of its item counts (a scan down the
+// column) and its total; the totals' exclusive scan over the digits, from the
+// bucket's first position, gives the bin starts of the bucket's cells.
+__global__ __launch_bounds__(256) void k_bucket_scan(IndexArgs a) {
+  __shared__ uint32_t col[kDigits];
+  __shared__ int64_t part[256];
+  const int r = a.r0 + (int)blockIdx.y;
+  const RunDev &R = a.runs[r];
+  const int h = (int)blockIdx.x;
+  if (h >= R.nb) return;
+  const int tid = threadIdx.x;
+  const int32_t *bf = a.bfirst + (int64_t)r * (kDigits + 1);
+  const int64_t f0 = R.io + bf[h], f1 = R.io + bf[h + 1];
+  uint32_t s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t it = f0; it < f1; ++it) {
+    uint32_t *M = a.hist + it * kDigits;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int q = tid + 256 * e;
+      const uint32_t v = M[q];
+      M[q] = s[e];
+      s[e] += v;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 8; ++e) col[tid + 256 * e] = s[e];
+  __syncthreads();
+  // digits 8 tid .. 8 tid + 7 are this thread's in the scan
+  uint32_t v[8];
+  int64_t sum = 0;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    v[e] = col[8 * tid + e];
+    sum += v[e];
+  }
+  int64_t run = block_exclusive_scan(sum, part) + (int64_t)a.tot[R.cbo + h];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    col[8 * tid + e] = (uint32_t)run;
+    run += v[e];
+  }
+  __syncthreads();
+  const int64_t c0 = (int64_t)h << kDigitBits;
+  uint32_t *bs = a.bin_start + R.bo + c0;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int q = tid + 256 * e;
+    if (c0 + q <= R.nc) bs[q] = col[q];
+  }
+}
+
 // Rank of each lane among the active lanes holding the same digit (lanes
 // below it) and the size of that group, from one ballot per distinct digit
 // present.  Inactive lanes hold kNoDigit.
@@ -949,33 +1120,50 @@ __device__ __forceinline__ void rank_in_wave(uint32_t key, uint64_t rest, uint32
 // otherwise the positions are the slots and the bins are read from cell[].
 // KOUT: the bins are also written to a.kout in the output order, so the next
 // pass and the bin bounds read them sequentially.
+// BUCKETED: the second pass of the two-level sort; the wave's work is a bucket
+// item (a chunk of one bucket's positions) and its cursors are the bin starts
+// of the bucket's cells plus the counts of earlier chunks of the bucket.
 // The sources are read sequentially with no per-lane condition, and the next
 // chunk's reads are issued before the current chunk is ranked, so their
 // latency overlaps the ranking; the ragged last chunk is handled apart.
-template <bool KOUT, bool CARRIED>
+template <bool KOUT, bool CARRIED, bool BUCKETED>
 __global__ __launch_bounds__(256) void k_scatter(IndexArgs a) {
   extern __shared__ uint32_t lds[];
   constexpr int U = 16;
   constexpr int CH = U * kWave;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int t = a.t0 + (int)blockIdx.x * kWavesPerBlock + wave;
-  if (t >= a.t1) return;
-  const int r = a.tile_run[t];
-  const RunDev &R = a.runs[r];
-  const int64_t tl = t - R.to;
   const bool single = a.single;
-  const int pass = a.pass;
-  const int D = single ? R.nc + 1 : kDigits;
+  const int shift = a.shift;
   uint32_t *cursor = lds + wave * a.dstride;
-  {
+  int r;
+  int64_t begin, end;
+  if (BUCKETED) {
+    const int32_t i = a.b0 + (int)blockIdx.x * kWavesPerBlock + wave;
+    if (i >= a.b1) return;
+    int h;
+    if (!bucket_item(a, i, r, h, begin, end)) return;
+    const RunDev &R = a.runs[r];
+    const uint32_t *M = a.hist + (int64_t)i * kDigits;
+    const int64_t c0 = (int64_t)h << kDigitBits;
+    const uint32_t *S = a.bin_start + R.bo + c0;
+    const int64_t last = R.nc - c0;  // digits beyond are no bins of the run
+    for (int q = lane; q < kDigits; q += kWave) cursor[q] = q <= last ? S[q] + M[q] : 0u;
+  } else {
+    const int t = a.t0 + (int)blockIdx.x * kWavesPerBlock + wave;
+    if (t >= a.t1) return;
+    r = a.tile_run[t];
+    const RunDev &R = a.runs[r];
+    const int64_t tl = t - R.to;
+    const int D = single ? R.nc + 1 : kDigits;
     const uint32_t *Mt = a.hist + R.mo + tl * D;
     const uint32_t *S = a.tot + R.cbo;
     for (int q = lane; q < D; q += kWave) cursor[q] = S[q] + Mt[q];
+    begin = tl * a.tile;
+    end = min(begin + a.tile, (int64_t)a.n_sorted[r]);
   }
   wave_sync();
-  const int64_t n = a.n_sorted[r];
-  const int64_t begin = tl * a.tile, end = min(begin + a.tile, n);
   if (begin >= end) return;
+  const RunDev &R = a.runs[r];
   const uint64_t all = ~0ull;
   const int32_t *__restrict__ src_v = CARRIED ? a.in + R.so : nullptr;
   const int32_t *__restrict__ src_b = CARRIED ? a.kin + R.so : a.cell + R.so;
@@ -1002,7 +1190,7 @@ __global__ __launch_bounds__(256) void k_scatter(IndexArgs a) {
     SCATTER_LOAD(b + CH);
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      const uint32_t key = digit_of(bin[q], pass, single);
+      const uint32_t key = digit_of(bin[q], shift, single);
       uint32_t rank, cnt;
       rank_in_wave(key, all, rank, cnt);
       const uint32_t prior = cursor[key];
@@ -1020,7 +1208,7 @@ __global__ __launch_bounds__(256) void k_scatter(IndexArgs a) {
     for (int q = 0; q < U; ++q) {
       const int64_t loc = full_end + q * kWave + lane;
       const bool act = loc < end;
-      const uint32_t key = act ? digit_of(nb[q], pass, single) : kNoDigit;
+      const uint32_t key = act ? digit_of(nb[q], shift, single) : kNoDigit;
       uint32_t rank, cnt;
       rank_in_wave(key, __builtin_amdgcn_ballot_w64(act), rank, cnt);
       if (act) {
@@ -1073,6 +1261,8 @@ __global__ void k_bin_finalize(IndexArgs a, int r1, int set_alive) {
   const RunDev &R = a.runs[r];
   if (a.n_sorted[r] == 0)
     for (int32_t q = 0; q <= R.nc + 1; ++q) a.bin_start[R.bo + q] = 0;
+  // (the two-level sort's bucket scans end at bin nc)
+  a.bin_start[R.bo + R.nc + 1] = (uint32_t)a.n_sorted[r];
   if (set_alive) a.n_alive[r] = (int32_t)a.bin_start[R.bo + R.nc];
 }
 
@@ -1143,6 +1333,10 @@ struct Angles {
   real cosx, sinx, ce, se;  // cos chi, sin chi, cos eps, sin eps
 };
 
+// sin and cos of one angle with one shared argument reduction.
+__device__ __forceinline__ void sin_cos(float x, float &s, float &c) { sincosf(x, &s, &c); }
+__device__ __forceinline__ void sin_cos(double x, double &s, double &c) { sincos(x, &s, &c); }
+
 // Deflection angles of a selection from its two scattering uniforms.
 template <typename real>
 __device__ __forceinline__ Angles<real> angles_of(real uc, real ue) {
@@ -1150,8 +1344,7 @@ __device__ __forceinline__ Angles<real> angles_of(real uc, real ue) {
   a.cosx = (real)2 * uc - (real)1;
   a.sinx = sqrt((real)1 - a.cosx * a.cosx);
   const real eps = two_pi<real>() * ue;
-  a.ce = cos(eps);
-  a.se = sin(eps);
+  sin_cos(eps, a.se, a.ce);
   return a;
 }
 
@@ -1995,8 +2188,13 @@ static IndexArgs index_args(const Geometry &g, const DevPtrs<real> &d) {
   a.r0 = 0;
   a.tile = g.tile;
   a.dstride = g.dstride;
-  a.pass = 0;
+  a.shift = 0;
   a.single = g.npass == 1;
+  a.bitem = d.bitem;
+  a.bitem_run = d.bitem_run;
+  a.bfirst = d.bfirst;
+  a.b0 = 0;
+  a.b1 = g.n_bitems;
   return a;
 }
 
@@ -2014,11 +2212,11 @@ static int digit_bits(int D) {
     if (prof) prof->mark(prof->user, (kind), 0, s);   \
   } while (0)
 
-// Scans and scatter of pass `pass` over the runs [a.r0, a.r0 + n_runs) and
-// tiles [a.t0, a.t1); the tile histograms are already in place.
-static void index_pass(IndexArgs a, int max_digits, int n_runs, int pass, const int32_t *in, int32_t *out,
+// Scans and scatter of the digit at bit `shift` over the runs [a.r0, a.r0 +
+// n_runs) and tiles [a.t0, a.t1); the tile histograms are already in place.
+static void index_pass(IndexArgs a, int max_digits, int n_runs, int shift, const int32_t *in, int32_t *out,
                        hipStream_t s, const Prof *prof = nullptr) {
-  a.pass = pass;
+  a.shift = shift;
   a.in = in;
   a.out = out;
   const size_t lds = (size_t)kWavesPerBlock * a.dstride * sizeof(uint32_t);
@@ -2028,13 +2226,13 @@ static void index_pass(IndexArgs a, int max_digits, int n_runs, int pass, const 
   // positions come either from the slots (first pass) or, with their bins
   // (a.kin, always set together with a.in), from the previous pass
   if (a.kout && a.in)
-    TIMED(kKScatter, hipLaunchKernelGGL((k_scatter<true, true>), dim3(wblocks), dim3(256), lds, s, a));
+    TIMED(kKScatter, hipLaunchKernelGGL((k_scatter<true, true, false>), dim3(wblocks), dim3(256), lds, s, a));
   else if (a.kout)
-    TIMED(kKScatter, hipLaunchKernelGGL((k_scatter<true, false>), dim3(wblocks), dim3(256), lds, s, a));
+    TIMED(kKScatter, hipLaunchKernelGGL((k_scatter<true, false, false>), dim3(wblocks), dim3(256), lds, s, a));
   else if (a.in)
-    TIMED(kKScatter, hipLaunchKernelGGL((k_scatter<false, true>), dim3(wblocks), dim3(256), lds, s, a));
+    TIMED(kKScatter, hipLaunchKernelGGL((k_scatter<false, true, false>), dim3(wblocks), dim3(256), lds, s, a));
   else
-    TIMED(kKScatter, hipLaunchKernelGGL((k_scatter<false, false>), dim3(wblocks), dim3(256), lds, s, a));
+    TIMED(kKScatter, hipLaunchKernelGGL((k_scatter<false, false, false>), dim3(wblocks), dim3(256), lds, s, a));
 }
 
 template <typename real>
@@ -2076,44 +2274,68 @@ static void lane_step(const Geometry &g, const LaneRange &L, const DevPtrs<real>
   if (g.npass == 1) {
     if (g.any_solid)
       TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, true, true>), dim3(wblocks), dim3(256), lds, s, d, buf,
-                                         L.t0, L.t1, g.tile, g.dstride));
+                                         L.t0, L.t1, g.tile, g.dstride, 0));
     else
       TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, true, false>), dim3(wblocks), dim3(256), lds, s, d,
-                                         buf, L.t0, L.t1, g.tile, g.dstride));
+                                         buf, L.t0, L.t1, g.tile, g.dstride, 0));
     TIMED(kKMotionWalls, hipLaunchKernelGGL((k_motion_walls<real, DIM, true>), dim3(n_tiles), dim3(256), 0, s, d,
-                                            buf, L.t0, L.t1, g.tile));
+                                            buf, L.t0, L.t1, g.tile, 0));
     if (moved) (void)hipEventRecord(moved, s);
     index_pass(a, g.max_nc + 1, n_runs, 0, nullptr, d.lcr, s, prof);
   } else {
+    // the first digit: the bucket (two-level sort) or the lowest 11 bits
+    const int shift0 = g.bucketed ? kDigitBits : 0;
     if (g.any_solid)
       TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, false, true>), dim3(wblocks), dim3(256), lds, s, d,
-                                         buf, L.t0, L.t1, g.tile, g.dstride));
+                                         buf, L.t0, L.t1, g.tile, g.dstride, shift0));
     else
       TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, false, false>), dim3(wblocks), dim3(256), lds, s, d,
-                                         buf, L.t0, L.t1, g.tile, g.dstride));
+                                         buf, L.t0, L.t1, g.tile, g.dstride, shift0));
     TIMED(kKMotionWalls, hipLaunchKernelGGL((k_motion_walls<real, DIM, false>), dim3(n_tiles), dim3(256), 0, s, d,
-                                            buf, L.t0, L.t1, g.tile));
+                                            buf, L.t0, L.t1, g.tile, shift0));
     if (moved) (void)hipEventRecord(moved, s);
-    // bins are carried through the passes: key_tmp and (free after Motion)
-    // the wall queue alternate as key buffers
-    int32_t *kbuf[2] = {d.key_tmp, (int32_t *)d.wallq};
-    const int32_t *in = nullptr, *kin = nullptr;
-    for (int p = 0; p < g.npass; ++p) {
-      int32_t *out = ((g.npass - 1 - p) % 2 == 0) ? d.lcr : d.lcr_tmp;
-      int32_t *kout = kbuf[p % 2];
-      if (p > 0) {
-        a.pass = p;
-        a.in = in;
-        a.kin = kin;
-        TIMED(kKDigCount, hipLaunchKernelGGL(k_digcount, dim3(wblocks), dim3(256), lds, s, a, 0));
+    if (g.bucketed) {
+      // pass 1: positions by bucket, bins carried; pass 2: each bucket by its
+      // low digit, straight into LCR and the bin starts
+      a.kout = d.key_tmp;
+      index_pass(a, kDigits, n_runs, kDigitBits, nullptr, d.lcr_tmp, s, prof);
+      a.b0 = L.b0;
+      a.b1 = L.b1;
+      a.in = d.lcr_tmp;
+      a.kin = d.key_tmp;
+      a.kout = nullptr;
+      a.out = d.lcr;
+      a.shift = 0;
+      const int iblocks = (L.b1 - L.b0 + kWavesPerBlock - 1) / kWavesPerBlock;
+      TIMED(kKBucketItems, hipLaunchKernelGGL(k_bucket_items, dim3(n_runs), dim3(256), 0, s, a));
+      if (iblocks > 0) {
+        TIMED(kKDigCount, hipLaunchKernelGGL(k_digcount_bucket, dim3(iblocks), dim3(256), lds, s, a));
+        const int max_nb = (g.max_nc >> kDigitBits) + 1;
+        TIMED(kKBucketScan, hipLaunchKernelGGL(k_bucket_scan, dim3(max_nb, n_runs), dim3(256), 0, s, a));
+        TIMED(kKScatter, hipLaunchKernelGGL((k_scatter<false, true, true>), dim3(iblocks), dim3(256), lds, s, a));
       }
-      a.kin = kin;
-      a.kout = kout;
-      index_pass(a, kDigits, n_runs, p, in, out, s, prof);
-      in = out;
-      kin = kout;
+    } else {
+      // bins are carried through the passes: key_tmp and (free after Motion)
+      // the wall queue alternate as key buffers
+      int32_t *kbuf[2] = {d.key_tmp, (int32_t *)d.wallq};
+      const int32_t *in = nullptr, *kin = nullptr;
+      for (int p = 0; p < g.npass; ++p) {
+        int32_t *out = ((g.npass - 1 - p) % 2 == 0) ? d.lcr : d.lcr_tmp;
+        int32_t *kout = kbuf[p % 2];
+        if (p > 0) {
+          a.shift = kDigitBits * p;
+          a.in = in;
+          a.kin = kin;
+          TIMED(kKDigCount, hipLaunchKernelGGL(k_digcount, dim3(wblocks), dim3(256), lds, s, a, 0));
+        }
+        a.kin = kin;
+        a.kout = kout;
+        index_pass(a, kDigits, n_runs, kDigitBits * p, in, out, s, prof);
+        in = out;
+        kin = kout;
+      }
+      TIMED(kKBinBounds, hipLaunchKernelGGL(k_bin_bounds, dim3(wblocks), dim3(256), 0, s, a, kin));
     }
-    TIMED(kKBinBounds, hipLaunchKernelGGL(k_bin_bounds, dim3(wblocks), dim3(256), 0, s, a, kin));
     TIMED(kKBinFinalize,
           hipLaunchKernelGGL(k_bin_finalize, dim3((n_runs + 255) / 256), dim3(256), 0, s, a, L.r1, 1));
   }
@@ -2298,7 +2520,12 @@ void launch_counting_sort(const int32_t *keys, int64_t n, int32_t nbins, int32_t
   a.r0 = 0;
   a.tile = L.tile;
   a.dstride = L.D;
+  a.shift = 0;
   a.single = L.npass == 1;
+  a.bitem = nullptr;
+  a.bitem_run = nullptr;
+  a.bfirst = nullptr;
+  a.b0 = a.b1 = 0;
   const size_t lds = (size_t)kWavesPerBlock * a.dstride * sizeof(uint32_t);
   const int wblocks = (L.nt + kWavesPerBlock - 1) / kWavesPerBlock;
   int32_t *tmp = (int32_t *)(w + L.off_tmp);
@@ -2307,12 +2534,12 @@ void launch_counting_sort(const int32_t *keys, int64_t n, int32_t nbins, int32_t
   for (int p = 0; p < L.npass; ++p) {
     int32_t *out = ((L.npass - 1 - p) % 2 == 0) ? lcr : tmp;
     int32_t *kout = L.npass > 1 ? kbuf[p % 2] : nullptr;
-    a.pass = p;
+    a.shift = kDigitBits * p;
     a.in = in;
     a.kin = kin;
     hipLaunchKernelGGL(k_digcount, dim3(wblocks), dim3(256), lds, s, a, 0);
     a.kout = kout;
-    index_pass(a, L.D, 1, p, in, out, s);
+    index_pass(a, L.D, 1, kDigitBits * p, in, out, s);
     in = out;
     kin = kout;
   }

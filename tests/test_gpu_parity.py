@@ -81,11 +81,35 @@ def test_channel_inflow_diffuse_vhs_fp64(dsmc_gpu, oracle_lib):
 
 
 def test_two_pass_indexing_fp64(dsmc_gpu, oracle_lib):
-    """> 2047 cells: the LSD counting sort takes two 11-bit passes."""
+    """> 2047 cells: Indexing sorts by bucket (bin >> 11), then each bucket by
+    its low 11 bits."""
     a = W.channel_run(nx=64, ny=40, lx=1.6, ly=1.0, ppc_inf=12.0, mach=1.0, run_id=3, seed=12)
     a = replace(a, n_init=20000, init_U=(a.inflow_U, 0.0, 0.0))
     b = replace(a, run_id=4)
     _parity(dsmc_gpu, oracle_lib, [a, b], 5)
+
+
+def test_two_pass_indexing_edges_fp64(dsmc_gpu, oracle_lib):
+    """Two-level Indexing edge cases in one batch: 4095 cells (the bin after
+    the DEAD bin starts a bucket that does not exist), a channel filling from
+    empty (most buckets empty at first, one bucket item holding the inflow
+    layer), and a run of 100 cells (one bucket) beside them."""
+    edge = replace(W.box(12000, 1, 3, 3, seed=21, grid=(91, 45)).runs[0], run_id=0)
+    empty = replace(W.channel_run(nx=96, ny=48, lx=2.0, ly=1.0, ppc_inf=6.0, mach=2.0, run_id=1, seed=21),
+                    n_init=0, ensemble=1)
+    small = replace(W.box(3000, 1, 3, 3, seed=21, grid=(10, 10)).runs[0], run_id=2, ensemble=2)
+    runs = [edge, empty, small]
+    E = dsmc_gpu.Ensemble(runs, sample_steps=[4], state_fp64=True, n_groups=1)
+    O = [oracle_lib.OracleRun(r) for r in runs]
+    for s in range(1, 5):
+        E.step(1)
+        for o in O:
+            o.step()
+        for r, rs in enumerate(runs):
+            _compare_run(E, r, O[r], rs, f"run {r} step {s}")
+    for r in range(3):
+        np.testing.assert_allclose(E.accum(0, ensemble=r)[0], O[r].sample(), rtol=TOL, atol=TOL)
+    E.close()
 
 
 def test_box3d_diffuse_fp64(dsmc_gpu, oracle_lib):
