@@ -748,23 +748,31 @@ __global__ __launch_bounds__(256) void k_motion_walls(DevPtrs<real> d, int buf, 
   uint32_t *Mt = d.hist + R.mo + (int64_t)(t - R.to) * D;
   const uint32_t *wq = d.wallq + (int64_t)t * tile;
   const Particles<real> P = d.P[buf];
-  for (uint32_t i = threadIdx.x; i < nq; i += blockDim.x) {
-    const int64_t loc = wq[i];
-    const int64_t gs = R.so + loc;
-    real p3[3] = {P.x[gs], P.y[gs], DIM == 3 ? P.z[gs] : (real)0};
-    real v3[3] = {P.u[gs], P.v[gs], DIM == 3 ? P.w[gs] : (real)0};
-    bool hit, reemit;
-    const int32_t c = move_one<real, DIM>(R, d.solid, step, (uint32_t)loc, p3, v3, hit, reemit, d.err);
-    P.x[gs] = p3[0];
-    P.y[gs] = p3[1];
-    if (DIM == 3) P.z[gs] = p3[2];
-    if (hit) {
-      P.u[gs] = v3[0];
-      P.v[gs] = v3[1];
-      if (DIM == 3 || reemit) P.w[gs] = v3[2];
+  // every lane takes part in each round (the histogram adds are aggregated
+  // over runs of equal digits across the wavefront)
+  for (uint32_t i0 = 0; i0 < nq; i0 += blockDim.x) {
+    const uint32_t i = i0 + threadIdx.x;
+    const bool active = i < nq;
+    uint32_t key = 0;
+    if (active) {
+      const int64_t loc = wq[i];
+      const int64_t gs = R.so + loc;
+      real p3[3] = {P.x[gs], P.y[gs], DIM == 3 ? P.z[gs] : (real)0};
+      real v3[3] = {P.u[gs], P.v[gs], DIM == 3 ? P.w[gs] : (real)0};
+      bool hit, reemit;
+      const int32_t c = move_one<real, DIM>(R, d.solid, step, (uint32_t)loc, p3, v3, hit, reemit, d.err);
+      P.x[gs] = p3[0];
+      P.y[gs] = p3[1];
+      if (DIM == 3) P.z[gs] = p3[2];
+      if (hit) {
+        P.u[gs] = v3[0];
+        P.v[gs] = v3[1];
+        if (DIM == 3 || reemit) P.w[gs] = v3[2];
+      }
+      d.cell[gs] = c;
+      key = SINGLE ? (uint32_t)c : (((uint32_t)c >> shift0) & (kDigits - 1));
     }
-    d.cell[gs] = c;
-    atomicAdd(&Mt[SINGLE ? (uint32_t)c : (((uint32_t)c >> shift0) & (kDigits - 1))], 1u);
+    histogram_add(Mt, key, active);
   }
 }
 
@@ -1030,8 +1038,7 @@ __global__ __launch_bounds__(256) void k_digcount_bucket(IndexArgs a) {
 #pragma unroll
     for (int e = 0; e < U; ++e) k[e] = kin[min(b + e * kWave + lane, end - 1)];
 #pragma unroll
-    for (int e = 0; e < U; ++e)
-      if (b + e * kWave + lane < end) atomicAdd(&hs[(uint32_t)k[e] & (kDigits - 1)], 1u);
+    for (int e = 0; e < U; ++e) histogram_add(hs, (uint32_t)k[e] & (kDigits - 1), b + e * kWave + lane < end);
   }
   wave_sync();
   uint32_t *M = a.hist + (int64_t)i * kDigits;
