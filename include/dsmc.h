@@ -31,9 +31,11 @@
  *  - Errors: every call returns a dsmc_status (0 = DSMC_OK).  Argument errors
  *    are detected before anything is enqueued.  Device-side conditions
  *    (capacity overflow during Generation, too many wall interactions, a
- *    failed inflow draw, a HIP launch failure) latch an error that the next
- *    synchronising call returns; after that only dsmc_destroy and
- *    dsmc_last_error are valid.  No exception or abort crosses the ABI.
+ *    failed inflow draw, non-finite state, a HIP launch failure) latch an
+ *    error that the next synchronising call returns; when several occur, the
+ *    lowest (most negative) status is the one latched, whatever their order.
+ *    After that only dsmc_destroy and dsmc_last_error are valid.  No
+ *    exception or abort crosses the ABI.
  *  - Threading: a context is not thread-safe; distinct contexts are
  *    independent.
  */

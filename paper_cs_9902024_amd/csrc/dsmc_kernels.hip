@@ -1460,31 +1460,28 @@ __device__ __forceinline__ void gather_through_lcr(const RunDev &R, const int32_
                                                    real *su, real *sv, real *sw) {
   const int lane = threadIdx.x & 63;
   constexpr int U = 4;
+  // reads clamped into [0, n) instead of masked: no branch whose join would
+  // make the compiler wait for each load before issuing the next
+  const int32_t *__restrict__ lp = lcr + R.so + b;
   for (int64_t k0 = 0; k0 < n; k0 += U * kWave) {
-    int64_t src[U];
-    bool ok[U];
+    int32_t l[U];
 #pragma unroll
-    for (int q = 0; q < U; ++q) {
-      const int64_t k = k0 + q * kWave + lane;
-      ok[q] = k < n;
-      src[q] = ok[q] ? R.so + lcr[R.so + b + k] : R.so;
-    }
+    for (int q = 0; q < U; ++q) l[q] = lp[min(k0 + q * kWave + lane, n - 1)];
     real x[U], y[U], z[U], uu[U], vv[U], ww[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      if (ok[q]) {
-        x[q] = A.x[src[q]];
-        y[q] = A.y[src[q]];
-        if (DIM == 3) z[q] = A.z[src[q]];
-        uu[q] = A.u[src[q]];
-        vv[q] = A.v[src[q]];
-        ww[q] = A.w[src[q]];
-      }
+      const int64_t src = R.so + l[q];
+      x[q] = A.x[src];
+      y[q] = A.y[src];
+      if (DIM == 3) z[q] = A.z[src];
+      uu[q] = A.u[src];
+      vv[q] = A.v[src];
+      ww[q] = A.w[src];
     }
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      if (!ok[q]) continue;
       const int64_t k = k0 + q * kWave + lane;
+      if (k >= n) continue;
       const int64_t dst = R.so + b + k;
       B.x[dst] = x[q];
       B.y[dst] = y[q];
