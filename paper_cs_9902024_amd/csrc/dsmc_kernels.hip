@@ -1842,17 +1842,24 @@ __global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, 
   }
 }
 
-// Crowded cells in FP32, pipelined: one 256-thread block walks kPipeCells
-// consecutive cell items.  While the collisions of cell j run in LDS, the
-// whole of cell j+1 (positions and velocities) is being gathered through LCR
+// Crowded cells in FP32: one 256-thread block walks kPipeCells consecutive
+// cell items.  With more than one, while the collisions of cell j run in LDS
+// the whole of cell j+1 (positions and velocities) is gathered through LCR
 // into registers and the LCR entries of cell j+2 are loaded; the collision
 // chain synchronises with LDS-only barriers, so these loads stay in flight
 // (a vector load is waited for only where its register is read).  Each cell
 // is processed exactly as k_collide_cell does (same selections, order and
 // arithmetic).  The items' bookkeeping (slots, bin range, NTC state, the
 // run's constants) is read once per block into LDS, so the collisions read
-// no global memory.
-constexpr int kPipeCells = 16;
+// no global memory; the gather reads are clamped, never masked, so they are
+// issued back to back.
+// One cell per block measured fastest: a cell's gather also reads its
+// neighbours' source ranges, and the blocks of consecutive cells, running at
+// once on one XCD, then find those lines in its L2.  A block that walks its
+// own consecutive cells reads each range again a cell's time later, after
+// the L2 has turned over (16 cells per block: 7.2 ms and 3x the bytes read
+// from memory on the 512 x 1M box, against 6.3 ms and 1x with one).
+constexpr int kPipeCells = 1;
 constexpr int kPipeChunks = kCollideCapF32 / 256;
 
 // The run constants the collisions need.
