@@ -206,10 +206,26 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
       // lane mode: as many cells per wavefront (<= 64) as fit 3/4 of the LDS stage
       const int cap = g.fp64 ? kLaneCapF64 : kLaneCapF32;
       R.lane_cells = (int32_t)std::max(1.0, std::min(64.0, std::floor(0.75 * cap / std::max(ppc, 1.0))));
-      if (R.coll_wave)
-        for (int32_t c = 0; c < R.nc; ++c) P.cell_items.push_back(make_int2(r, c));
-      else
-        for (int32_t c = 0; c < R.nc; c += R.lane_cells) P.items.push_back(make_int2(r, c));
+      // Item order: items run in list order, a few thousand at once.  A
+      // cell's gather also reads its neighbours' source ranges; in 3-D the
+      // items go plane block by plane block (kItemPlanes planes of z, rows
+      // of y outermost inside a block), so that z neighbours, like x and y
+      // ones, tend to be gathered at the same time and meet in L2.
+      const int32_t step_c = R.coll_wave ? 1 : R.lane_cells;
+      std::vector<int32_t> starts;
+      for (int32_t c = 0; c < R.nc; c += step_c) starts.push_back(c);
+      if (s.nz > 1) {
+        const int64_t plane = (int64_t)s.nx * s.ny;
+        std::vector<std::pair<int64_t, int32_t>> keyed;
+        keyed.reserve(starts.size());
+        for (int32_t c : starts) {
+          const int64_t iz = c / plane, iy = (c / s.nx) % s.ny, ix = c % s.nx;
+          keyed.emplace_back((((iz / kItemPlanes) * s.ny + iy) * kItemPlanes + iz % kItemPlanes) * s.nx + ix, c);
+        }
+        std::sort(keyed.begin(), keyed.end());
+        for (size_t k = 0; k < keyed.size(); ++k) starts[k] = keyed[k].second;
+      }
+      for (int32_t c : starts) (R.coll_wave ? P.cell_items : P.items).push_back(make_int2(r, c));
     }
     for (int f = 0; f < 6; ++f) {
       R.bc[f] = (f < 2 * g.dim) ? s.face_bc[f] : DSMC_BC_SPECULAR;

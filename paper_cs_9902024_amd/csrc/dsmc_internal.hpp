@@ -31,6 +31,7 @@ enum : int { kSpecular = 0, kDiffuse = 1, kInflow = 2, kOutflow = 3 };
 enum : int { kErrCapacity = -3, kErrBounce = -7, kErrReject = -8, kErrNumeric = -9 };
 constexpr double kMaxSelections = 1e9;  // per cell per step; more means non-finite state
 constexpr int kMaxLanes = 4;            // run groups stepped concurrently on their own streams
+constexpr int kItemPlanes = 4;          // z planes per block of the 3-D interaction item order
 
 // Per-run constants and layout, read by every kernel (AoS in device memory).
 struct RunDev {
