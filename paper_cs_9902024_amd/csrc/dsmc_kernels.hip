@@ -537,29 +537,19 @@ __device__ __forceinline__ int32_t move_one(const RunDev &R, const uint8_t *soli
   return c;
 }
 
-// Fast-path check for runs with solid cells: the straight flight for dt from
-// pos to out (no domain face reached) enters no solid cell and ends in a
-// fluid cell.  Exactly the decision move_one takes: its walk is run whenever
-// the cells around the path (one cell of margin for rounding) meet the
-// bounding box of the solid cells.
+// Fast-path check for runs with solid cells, on coordinates: whether the
+// bounding box of the straight flight from pos to out meets the bounding box
+// of the solid cells widened by two cells on each side (lo, hi).  A flight
+// that does not cannot enter a solid cell or end in one (the widening also
+// covers the rounding of positions to cells); Motion sends the others to the
+// wall queue, whose full flight (move_one) walks their cells.
 template <typename real, int DIM>
-__device__ __forceinline__ bool clear_of_solid(const RunDev &R, const uint8_t *solid, const real (&pos)[3],
-                                               const real (&vel)[3], const real (&out)[3]) {
-  const int32_t n[3] = {R.nx, R.ny, R.nz};
-  int32_t v0[3] = {0, 0, 0}, v1[3] = {0, 0, 0};
-  bool meets = true;
+__device__ __forceinline__ bool near_solid(const real (&pos)[3], const real (&out)[3], const real (&lo)[3],
+                                           const real (&hi)[3]) {
+  bool near = true;
 #pragma unroll
-  for (int a = 0; a < DIM; ++a) {
-    const real inv = (real)R.inv_d[a];
-    v0[a] = axis_index(pos[a], inv, n[a]);
-    v1[a] = axis_index(out[a], inv, n[a]);
-    const int32_t lo = min(v0[a], v1[a]) - 1, hi = max(v0[a], v1[a]) + 1;
-    meets = meets && hi >= R.sb_lo[a] && lo <= R.sb_hi[a];
-  }
-  if (!meets) return true;
-  real th;
-  if (solid_walk<real, DIM>(R, solid, pos, vel, (real)R.dt, v0, th) >= 0) return false;
-  return !solid[R.sdo + ((int64_t)v1[2] * R.ny + v1[1]) * R.nx + v1[0]];
+  for (int a = 0; a < DIM; ++a) near = near && fmax(pos[a], out[a]) >= lo[a] && fmin(pos[a], out[a]) <= hi[a];
+  return near;
 }
 
 // Free flight with no face reached this step, decided without divisions:
@@ -645,6 +635,15 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
   int32_t *__restrict__ cell = d.cell + R.so;
   uint32_t *__restrict__ wq = d.wallq + (int64_t)t * tile;  // this tile's queue segment
   uint32_t qn = 0;
+  // the solid cells' bounding box, widened by two cells, in coordinates
+  real slo[3] = {0, 0, 0}, shi[3] = {0, 0, 0};
+  const bool solid = OBST && R.has_solid;
+  if (solid)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      slo[a] = (real)((R.sb_lo[a] - 2) * R.d[a]);
+      shi[a] = (real)((R.sb_hi[a] + 3) * R.d[a]);
+    }
   for (int64_t b = begin; b < end; b += 4 * kWave) {
     const int64_t i0 = b + 4 * lane;
     const bool full = b + 4 * kWave <= end;  // wave-uniform
@@ -684,7 +683,7 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
       const real vel[3] = {vx[e], vy[e], DIM == 3 ? vz[e] : (real)0};
       real out[3];
       fast[e] = act[e] && free_flight<real, DIM>(R, pos, vel, out);
-      if (OBST && R.has_solid && fast[e]) fast[e] = clear_of_solid<real, DIM>(R, d.solid, pos, vel, out);
+      if (solid && fast[e]) fast[e] = !near_solid<real, DIM>(pos, out, slo, shi);
       ox[e] = fast[e] ? out[0] : px[e];
       oy[e] = fast[e] ? out[1] : py[e];
       oz[e] = (DIM == 3 && fast[e]) ? out[2] : (DIM == 3 ? pz[e] : (real)0);
