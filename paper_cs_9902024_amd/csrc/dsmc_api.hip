@@ -272,6 +272,11 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
     R.d[0] = s.lx / s.nx;
     R.d[1] = s.ly / s.ny;
     R.d[2] = s.lz / s.nz;
+    R.dt_f = (float)R.dt;
+    for (int a = 0; a < 3; ++a) {
+      R.L_f[a] = (float)R.L[a];
+      R.inv_f[a] = (float)R.inv_d[a];
+    }
     R.has_solid = any_solid(s) ? 1 : 0;
     if (R.has_solid) g.any_solid = 1;
     if (R.has_solid) {
@@ -295,6 +300,12 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
             }
           }
       P.solid.resize(round_up((int64_t)P.solid.size(), 256), 0);
+      for (int a = 0; a < 3; ++a) {
+        R.slo[a] = (R.sb_lo[a] - 2) * R.d[a];
+        R.shi[a] = (R.sb_hi[a] + 3) * R.d[a];
+        R.slo_f[a] = (float)R.slo[a];
+        R.shi_f[a] = (float)R.shi[a];
+      }
     }
     for (int t = 0; t < R.nt; ++t) P.tile_run.push_back(r);
     for (int i = 0; i < R.icap; ++i) P.bitem_run.push_back(r);

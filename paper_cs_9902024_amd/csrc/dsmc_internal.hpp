@@ -68,6 +68,11 @@ struct RunDev {
   int64_t sdo;           // first byte of the run's solid mask in the mask array
   double d[3];           // cell size per axis
   double solid_T, solid_sqrtT;
+  // Motion's constants in both precisions, rounded once on the host (so a
+  // kernel keeps them in scalar registers): dt, domain size, cells per unit
+  // length, and the solid cells' bounding box widened by two cells
+  float dt_f, L_f[3], inv_f[3], slo_f[3], shi_f[3];
+  double slo[3], shi[3];
 };
 
 template <typename real>

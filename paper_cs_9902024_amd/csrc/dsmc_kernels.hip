@@ -95,6 +95,12 @@ __device__ __forceinline__ void box_muller(real u1, real u2, real &n0, real &n1)
 // order of the failures); a non-returning atomic, so no register waits on it.
 __device__ __forceinline__ void set_error(int32_t *err, int code) { (void)atomicMin(err, code); }
 
+// The wavefront's index in its block, as a wave-uniform (scalar) value, so
+// that what is indexed by it (a tile, its run's constants) is read with
+// scalar loads: a vector load would make the next wait for vector memory
+// also wait for it.
+__device__ __forceinline__ int wave_index() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -555,21 +561,24 @@ __device__ __forceinline__ bool near_solid(const real (&pos)[3], const real (&ou
 // Free flight with no face reached this step, decided without divisions:
 // the end point lies inside the box by a margin far above the rounding of the
 // full face-time test, so both tests agree and the result is identical.
+// A run constant in the state precision (both roundings are made on the host).
+template <typename real> __device__ __forceinline__ real in_precision(double d, float f);
+template <> __device__ __forceinline__ double in_precision<double>(double d, float) { return d; }
+template <> __device__ __forceinline__ float in_precision<float>(double, float f) { return f; }
+
 template <typename real> __device__ __forceinline__ real flight_margin_eps();
 template <> __device__ __forceinline__ double flight_margin_eps<double>() { return 64.0 * 0x1p-53; }
 template <> __device__ __forceinline__ float flight_margin_eps<float>() { return 64.0f * 0x1p-24f; }
 
 template <typename real, int DIM>
-__device__ __forceinline__ bool free_flight(const RunDev &R, const real (&pos)[3], const real (&vel)[3],
+__device__ __forceinline__ bool free_flight(real dt, const real (&L)[3], const real (&pos)[3], const real (&vel)[3],
                                             real (&out)[3]) {
-  const real dt = (real)R.dt;
   bool inside = true;
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
-    const real L = (real)R.L[a];
     out[a] = pos[a] + vel[a] * dt;
-    const real m = flight_margin_eps<real>() * (L + fabs(vel[a]) * dt);
-    inside = inside && (pos[a] >= (real)0) && (pos[a] <= L) && (out[a] >= m) && (out[a] <= L - m);
+    const real m = flight_margin_eps<real>() * (L[a] + fabs(vel[a]) * dt);
+    inside = inside && (pos[a] >= (real)0) && (pos[a] <= L[a]) && (out[a] >= m) && (out[a] <= L[a] - m);
   }
   return inside;
 }
@@ -614,7 +623,7 @@ template <typename real, int DIM, bool SINGLE, bool OBST>
 __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_t t0, int32_t t1, int64_t tile,
                                                 int dstride, int shift0) {
   extern __shared__ uint32_t lds[];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wave_index(), lane = threadIdx.x & 63;
   const int t = t0 + (int)blockIdx.x * kWavesPerBlock + wave;
   if (t >= t1) return;
   const int r = d.tile_run[t];
@@ -635,15 +644,19 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
   int32_t *__restrict__ cell = d.cell + R.so;
   uint32_t *__restrict__ wq = d.wallq + (int64_t)t * tile;  // this tile's queue segment
   uint32_t qn = 0;
+  // the run's constants, rounded to the state precision on the host
+  const real dt = in_precision<real>(R.dt, R.dt_f);
+  const real Lr[3] = {in_precision<real>(R.L[0], R.L_f[0]), in_precision<real>(R.L[1], R.L_f[1]),
+                      in_precision<real>(R.L[2], R.L_f[2])};
+  const real inv[3] = {in_precision<real>(R.inv_d[0], R.inv_f[0]), in_precision<real>(R.inv_d[1], R.inv_f[1]),
+                       in_precision<real>(R.inv_d[2], R.inv_f[2])};
+  const int32_t nx = R.nx, ny = R.ny, nz = R.nz;
   // the solid cells' bounding box, widened by two cells, in coordinates
-  real slo[3] = {0, 0, 0}, shi[3] = {0, 0, 0};
   const bool solid = OBST && R.has_solid;
-  if (solid)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      slo[a] = (real)((R.sb_lo[a] - 2) * R.d[a]);
-      shi[a] = (real)((R.sb_hi[a] + 3) * R.d[a]);
-    }
+  const real slo[3] = {in_precision<real>(R.slo[0], R.slo_f[0]), in_precision<real>(R.slo[1], R.slo_f[1]),
+                       in_precision<real>(R.slo[2], R.slo_f[2])};
+  const real shi[3] = {in_precision<real>(R.shi[0], R.shi_f[0]), in_precision<real>(R.shi[1], R.shi_f[1]),
+                       in_precision<real>(R.shi[2], R.shi_f[2])};
   for (int64_t b = begin; b < end; b += 4 * kWave) {
     const int64_t i0 = b + 4 * lane;
     const bool full = b + 4 * kWave <= end;  // wave-uniform
@@ -682,17 +695,17 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
       const real pos[3] = {px[e], py[e], DIM == 3 ? pz[e] : (real)0};
       const real vel[3] = {vx[e], vy[e], DIM == 3 ? vz[e] : (real)0};
       real out[3];
-      fast[e] = act[e] && free_flight<real, DIM>(R, pos, vel, out);
+      fast[e] = act[e] && free_flight<real, DIM>(dt, Lr, pos, vel, out);
       if (solid && fast[e]) fast[e] = !near_solid<real, DIM>(pos, out, slo, shi);
       ox[e] = fast[e] ? out[0] : px[e];
       oy[e] = fast[e] ? out[1] : py[e];
       oz[e] = (DIM == 3 && fast[e]) ? out[2] : (DIM == 3 ? pz[e] : (real)0);
       int32_t c = 0;
       if (fast[e]) {
-        const int32_t ix = axis_index(out[0], (real)R.inv_d[0], R.nx);
-        const int32_t iy = axis_index(out[1], (real)R.inv_d[1], R.ny);
-        const int32_t iz = (DIM == 3) ? axis_index(out[2], (real)R.inv_d[2], R.nz) : 0;
-        c = (iz * R.ny + iy) * R.nx + ix;
+        const int32_t ix = axis_index(out[0], inv[0], nx);
+        const int32_t iy = axis_index(out[1], inv[1], ny);
+        const int32_t iz = (DIM == 3) ? axis_index(out[2], inv[2], nz) : 0;
+        c = (iz * ny + iy) * nx + ix;
       }
       oc[e] = c;
       key[e] = SINGLE ? (uint32_t)c : (((uint32_t)c >> shift0) & (kDigits - 1));
@@ -816,7 +829,7 @@ __device__ __forceinline__ uint32_t digit_of(int32_t bin, int shift, bool single
 // and the stand-alone sort).
 __global__ __launch_bounds__(256) void k_digcount(IndexArgs a, int use_n_alive) {
   extern __shared__ uint32_t lds[];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wave_index(), lane = threadIdx.x & 63;
   const int t = a.t0 + (int)blockIdx.x * kWavesPerBlock + wave;
   if (t >= a.t1) return;
   const int r = a.tile_run[t];
@@ -1021,7 +1034,7 @@ __global__ __launch_bounds__(256) void k_bucket_items(IndexArgs a) {
 __global__ __launch_bounds__(256) void k_digcount_bucket(IndexArgs a) {
   extern __shared__ uint32_t lds[];
   constexpr int U = 8;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wave_index(), lane = threadIdx.x & 63;
   const int32_t i = a.b0 + (int)blockIdx.x * kWavesPerBlock + wave;
   if (i >= a.b1) return;
   int r, h;
@@ -1137,7 +1150,7 @@ __global__ __launch_bounds__(256) void k_scatter(IndexArgs a) {
   extern __shared__ uint32_t lds[];
   constexpr int U = 16;
   constexpr int CH = U * kWave;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wave_index(), lane = threadIdx.x & 63;
   const bool single = a.single;
   const int shift = a.shift;
   uint32_t *cursor = lds + wave * a.dstride;
@@ -1233,7 +1246,7 @@ __global__ __launch_bounds__(256) void k_scatter(IndexArgs a) {
 // keys the last pass carried).  One wavefront per tile of tiles [a.t0, a.t1),
 // four consecutive positions per lane.
 __global__ __launch_bounds__(256) void k_bin_bounds(IndexArgs a, const int32_t *sorted) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wave_index(), lane = threadIdx.x & 63;
   const int t = a.t0 + (int)blockIdx.x * kWavesPerBlock + wave;
   if (t >= a.t1) return;
   const int r = a.tile_run[t];
@@ -1519,7 +1532,7 @@ template <typename real, int DIM>
 __global__ __launch_bounds__(kCollideWaves * 64) void k_collide(DevPtrs<real> d, int src, int64_t it0, int64_t it1) {
   extern __shared__ __align__(16) unsigned char lds_bytes[];
   constexpr int CAP = LaneCap<real>::value;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wave_index(), lane = threadIdx.x & 63;
   const int64_t item = it0 + xcd_block(blockIdx.x, gridDim.x) * kCollideWaves + wave;
   if (item >= it1) return;
   const int2 it = d.items[item];
