@@ -1115,19 +1115,19 @@ __global__ __launch_bounds__(256) void k_bucket_scan(IndexArgs a) {
 constexpr uint32_t kNoDigit = 0xFFFFFFFFu;
 
 __device__ __forceinline__ void rank_in_wave(uint32_t key, uint64_t rest, uint32_t &rank, uint32_t &cnt) {
-  rank = 0;
-  cnt = 0;
+  // each lane keeps the ballot of its digit (a select, no branch: the loop
+  // costs a few scalar and vector instructions per distinct digit)
+  uint64_t peers = 0;
   while (rest) {
     const int leader = (int)__builtin_ctzll(rest);
     const uint32_t dl = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
     const bool same = key == dl;
     const uint64_t pm = __builtin_amdgcn_ballot_w64(same);
-    if (same) {
-      rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(pm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)pm, 0u));
-      cnt = (uint32_t)__popcll(pm);
-    }
+    peers = same ? pm : peers;
     rest &= ~pm;
   }
+  rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
+  cnt = (uint32_t)__popcll(peers);
 }
 
 // One wavefront per tile, 64 consecutive positions per round in order: the
