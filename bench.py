@@ -61,32 +61,33 @@ def algorithmic_bytes(kind: str, n_particles: int, n_cells: int, dim: int, es: i
     return 0.0
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ensemble_box_512x1M_fp32_traffic.md")
+TRAFFIC_GLOB = os.path.join(ROOT, "profiles", "ensemble_box_512x1M_fp32_tile*_traffic.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_cs_9902024_amd", "csrc", "dsmc_kernels.hip")
 
 
 def measured_traffic(kernel: str, lanes: int, tile: int):
-    """HBM bytes per launch of ``kernel`` from the committed FETCH_SIZE /
-    WRITE_SIZE summary (scaled by the copy-kernel calibration), or None when
-    there is none, the kernel source changed since the counters were taken,
-    or the counters were taken with another split of the batch into lanes or
-    another Indexing tile size."""
+    """HBM bytes per launch of ``kernel`` from a committed FETCH_SIZE /
+    WRITE_SIZE summary (scaled by the copy-kernel calibration) taken with the
+    same kernel source, the same split of the batch into lanes and the same
+    Indexing tile size as this run; None when there is none."""
+    import glob
     import hashlib
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
     sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-    found, ok, same_lanes, same_tile = None, False, False, False
-    for line in open(TRAFFIC_FILE):
-        f = line.split()
-        if len(f) == 3 and f[0] == "traffic" and f[1] == kernel:
-            found = float(f[2])
-        if len(f) == 2 and f[0] == "source_sha256":
-            ok = f[1] == sha
-        if len(f) == 2 and f[0] == "lanes":
-            same_lanes = int(f[1]) == lanes
-        if len(f) == 2 and f[0] == "tile":
-            same_tile = int(f[1]) == tile
-    return found if ok and same_lanes and same_tile else None
+    for path in sorted(glob.glob(TRAFFIC_GLOB)):
+        found, ok, same_lanes, same_tile = None, False, False, False
+        for line in open(path):
+            f = line.split()
+            if len(f) == 3 and f[0] == "traffic" and f[1] == kernel:
+                found = float(f[2])
+            if len(f) == 2 and f[0] == "source_sha256":
+                ok = f[1] == sha
+            if len(f) == 2 and f[0] == "lanes":
+                same_lanes = int(f[1]) == lanes
+            if len(f) == 2 and f[0] == "tile":
+                same_tile = int(f[1]) == tile
+        if found is not None and ok and same_lanes and same_tile:
+            return found
+    return None
 
 
 def copy_calibration(nbytes: int = 1 << 31):
