@@ -24,8 +24,12 @@ Beside it the line carries:
   cpu_baseline  the FP64 oracle timed on the host cores on a bounded sample.
 
 ``--workload body3d`` times the flow past a body at full size instead (32 runs
-x 60M particles, 2M cells, solid-cell obstacle); it is informational, not the
-benchmark line.
+x 60M particles, 2M cells, solid-cell obstacle); ``channel`` (16 runs of the
+impulsively started Mach-2 channel, 256x64 cells, ~2M particles each at fill)
+and ``uneven`` (256 runs of uneven grids, particle counts, collision models
+and inflow speeds) start from vacuum and are timed after FILL_STEPS steps, by
+when the flow has crossed the domain.  These are informational, not the
+benchmark line; they run untuned (the autotuner would time the empty start).
 """
 import argparse
 import json
@@ -38,6 +42,20 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle-steps/sec (batched FP32 vs plain FP64) at 3σ/1% oracle match; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+FILL_STEPS = 600  # steps from vacuum before the unsteady workloads are timed
+WORKLOAD_TEXT = {
+    "ensemble_box": ("ensemble_box: {runs} independent runs x {per_run} hard-sphere particles, 2-D 1x1 "
+                     "specular box, 32x32 cells, Kn 0.05, dt = 0.2 mean collision times, FP32 state, FP64 "
+                     "sampling accumulators, sample every 20 steps, HIP graph"),
+    "body3d": ("body3d: 32 independent runs x 60M hard-sphere particles, 3-D 2x1x1 box, 200x100x100 "
+               "cells, Mach-5 inflow past a sphere of solid cells (diffuse, T = 3), FP32 state, FP64 "
+               "sampling accumulators, HIP graph"),
+    "channel": ("channel: 16 independent runs of the impulsively started Mach-2 channel, 4x1 domain, "
+                "256x64 cells, VHS omega 0.74, diffuse wall at T = 2, ~2M particles per run at fill, "
+                "timed after 600 steps from vacuum, FP32 state, HIP graph"),
+    "uneven": ("uneven: 256 independent runs, grids 64x64..512x256, 50k..4M particles, HS/VHS, Mach "
+               "0.5..5 inflow, timed after 600 steps from vacuum, FP32 state, HIP graph"),
+}
 
 
 def algorithmic_bytes(kind: str, n_particles: int, n_cells: int, dim: int, es: int) -> float:
@@ -122,13 +140,18 @@ def run_gpu(args):
     calib = copy_calibration()
     if args.workload == "body3d":
         wl = W.body3d()
+    elif args.workload == "channel":
+        wl = W.channel()
+    elif args.workload == "uneven":
+        wl = W.uneven()
     else:
         wl = W.ensemble_box(n_runs=args.runs, n_per_run=args.per_run, n_steps=1000, sample_every=20,
                             seed=3, state_fp64=False)
     dim = wl.runs[0].dim
     tuned = None
     kw = {"n_streams": args.streams, "tile_chunks": args.tile_chunks, "collide_mode": args.collide_mode}
-    if not args.no_tune:
+    unsteady = args.workload in ("channel", "uneven")
+    if not args.no_tune and not unsteady:
         # the library's autotuner times its candidate settings on this batch
         # (a scratch arena, before the timed region); tuning never changes results
         tuned = P.Ensemble.autotune(wl.runs, wl.sample_steps, state_fp64=False, n_groups=wl.n_groups,
@@ -138,7 +161,8 @@ def run_gpu(args):
     n_runs = wl.n_runs
     nc = wl.runs[0].n_cells
 
-    E.step(args.warmup)
+    warmup = max(args.warmup, FILL_STEPS) if unsteady else args.warmup
+    E.step(warmup)
     E.sync()
     torch.cuda.synchronize()
     n0 = int(E.counts()[:, 0].sum())
@@ -194,6 +218,7 @@ def run_gpu(args):
     if args.plain_runs > 0 and args.workload == "ensemble_box":
         plain = run_plain_fp64(args, P, W)
     return {"value": value, "elapsed": elapsed, "psteps": psteps, "n_runs": n_runs, "nc": nc, "tuned": tuned,
+            "warmup": warmup, "n_mean": psteps // args.steps,
             "kernels": kernels, "roofline": rl, "plain": plain, "info": info, "calib": calib}
 
 
@@ -265,8 +290,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner; use --streams / --tile-chunks / --collide-mode (0 = default)")
     ap.add_argument("--tile-chunks", type=int, default=0)
-    ap.add_argument("--workload", choices=("ensemble_box", "body3d"), default="ensemble_box",
-                    help="ensemble_box (the benchmark) or body3d (the flow past a body at full size)")
+    ap.add_argument("--workload", choices=("ensemble_box", "body3d", "channel", "uneven"), default="ensemble_box",
+                    help="ensemble_box (the benchmark); body3d, channel or uneven (informational)")
     ap.add_argument("--collide-mode", type=int, default=0)
     ap.add_argument("--plain-runs", type=int, default=2)
     ap.add_argument("--plain-steps", type=int, default=10)
@@ -275,7 +300,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              "(runs would shard across GPUs with one final reduction; see the design notes)",
+              "(runs would shard across GPUs, with one final reduction of the accumulators)",
               file=sys.stderr)
         sys.exit(2)
 
@@ -288,23 +313,17 @@ def main():
         "unit": "particle-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
-        "warmup": args.warmup,
+        "warmup": g["warmup"],
         "ms_per_step": ms_per_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": (f"ensemble_box: {g['n_runs']} independent runs x {args.per_run} "
-                                f"hard-sphere particles, 2-D 1x1 specular box, 32x32 cells, "
-                                f"Kn 0.05, dt = 0.2 mean collision times, FP32 state, FP64 "
-                                f"sampling accumulators, sample every 20 steps, HIP graph")
-                   if args.workload == "ensemble_box" else
-                   ("body3d: 32 independent runs x 60M hard-sphere particles, 3-D 2x1x1 box, "
-                    "200x100x100 cells, Mach-5 inflow past a sphere of solid cells (diffuse, T = 3), "
-                    "FP32 state, FP64 sampling accumulators, HIP graph"),
+        "config": {"workload": WORKLOAD_TEXT[args.workload].format(runs=g["n_runs"], per_run=args.per_run),
                    "runs": g["n_runs"],
-                   "particles_per_run": args.per_run if args.workload == "ensemble_box" else 60_000_000,
+                   "particles_per_run": args.per_run if args.workload == "ensemble_box" else None,
+                   "mean_particles": g["n_mean"],
                    "cells_per_run": g["nc"], "lanes": g["info"]["lanes"],
                    "tile_slots": g["info"]["slots"] // g["info"]["tiles"], "tuned": g["tuned"],
                    "parallelism": "one GPU; runs batched in each launch, split into "
