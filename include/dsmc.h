@@ -112,9 +112,10 @@ typedef struct {
                                    stream of the library's own ordered after it by events when
                                    hip_stream is the null stream) */
   int32_t tile_chunks;          /* tuning: 64-slot rounds per indexing tile (0 = default 256) */
-  int32_t collide_mode;         /* tuning: 0 auto, 1 one lane per cell (64 cells per wavefront),
-                                   2 one 256-thread block per cell; auto takes 2 when the expected
-                                   particles per cell (initial fill or inflow fill) reach 64 */
+  int32_t collide_mode;         /* tuning: 0 auto, 1 one lane per cell (up to 64 cells per
+                                   wavefront), 2 one 256-thread block per cell; auto takes 2 when
+                                   the expected particles per cell (initial fill or inflow fill)
+                                   reach 256 */
   int32_t n_streams;            /* tuning: run groups stepped concurrently, each on a HIP stream of the
                                    library's own (0 = auto = 1, 1..4; 1 = every launch on hip_stream).
                                    The runs are split into contiguous groups of about equal slot
@@ -222,7 +223,7 @@ dsmc_status dsmc_autotune_bytes(const dsmc_run_spec *runs, int32_t n_runs, const
  * n_streams) for these runs by measurement.  None of them changes any result
  * (every setting computes the same sequential order bit for bit); they only
  * change speed.  Candidates: tiles of 4096, 8192 and 16384 slots; both
- * interaction modes when a run's expected particles per cell lie in 16..256;
+ * interaction modes when a run's expected particles per cell lie in 64..512;
  * one or two stream lanes when n_runs >= 8.  Each candidate is initialised in
  * the caller's arena (at least dsmc_autotune_bytes, 256-byte aligned), stepped
  * once to warm up (graph capture included when opt->use_graph), then n_steps

@@ -202,7 +202,7 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
       double fill = (double)s.n_init;
       if (s.face_bc[0] == DSMC_BC_INFLOW) fill = std::max(fill, s.inflow_n * s.lx * s.ly * s.lz);
       const double ppc = fill / (double)R.nc;
-      R.coll_wave = opt.collide_mode == 2 || (opt.collide_mode == 0 && ppc >= 64.0);
+      R.coll_wave = opt.collide_mode == 2 || (opt.collide_mode == 0 && ppc >= kCrowdedPpc);
       // lane mode: as many cells per wavefront (<= 64) as fit 3/4 of the LDS stage
       const int cap = g.fp64 ? kLaneCapF64 : kLaneCapF32;
       R.lane_cells = (int32_t)std::max(1.0, std::min(64.0, std::floor(0.75 * cap / std::max(ppc, 1.0))));
@@ -1096,7 +1096,7 @@ bool auto_block(const dsmc_run_spec *runs, int32_t n_runs) {
   const dsmc_run_spec &s = runs[0];
   double fill = (double)s.n_init;
   if (s.face_bc[0] == DSMC_BC_INFLOW) fill = std::max(fill, s.inflow_n * s.lx * s.ly * s.lz);
-  return fill / ((double)s.nx * s.ny * s.nz) >= 64.0;
+  return fill / ((double)s.nx * s.ny * s.nz) >= kCrowdedPpc;
 }
 
 std::vector<dsmc_options> tune_candidates(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_options &base) {
@@ -1106,7 +1106,7 @@ std::vector<dsmc_options> tune_candidates(const dsmc_run_spec *runs, int32_t n_r
     double fill = (double)s.n_init;
     if (s.face_bc[0] == DSMC_BC_INFLOW) fill = std::max(fill, s.inflow_n * s.lx * s.ly * s.lz);
     const double ppc = fill / ((double)s.nx * s.ny * s.nz);
-    if (ppc >= 16.0 && ppc <= 256.0) ambiguous = true;
+    if (ppc >= 0.25 * kCrowdedPpc && ppc <= 2.0 * kCrowdedPpc) ambiguous = true;
   }
   std::vector<int32_t> modes = ambiguous ? std::vector<int32_t>{0, 3} : std::vector<int32_t>{0};
   std::vector<int32_t> lanes = n_runs >= 8 ? std::vector<int32_t>{1, 2} : std::vector<int32_t>{1};

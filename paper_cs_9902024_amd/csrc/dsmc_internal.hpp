@@ -32,6 +32,7 @@ enum : int { kErrCapacity = -3, kErrBounce = -7, kErrReject = -8, kErrNumeric = 
 constexpr double kMaxSelections = 1e9;  // per cell per step; more means non-finite state
 constexpr int kMaxLanes = 4;            // run groups stepped concurrently on their own streams
 constexpr int kItemPlanes = 4;          // z planes per block of the 3-D interaction item order
+constexpr double kCrowdedPpc = 256.0;   // expected particles per cell from which a cell gets a whole block
 
 // Per-run constants and layout, read by every kernel (AoS in device memory).
 struct RunDev {

@@ -135,7 +135,8 @@ def test_obstacle_specs(dsmc):
 
 
 def test_autotune_workspace_covers_every_candidate(dsmc):
-    wl = W.channel(n_runs=8, nx=64, ny=16, ppc_inf=40.0, n_steps=10, sample_every=5)
+    # 100 expected particles per cell: both interaction modes are candidates
+    wl = W.channel(n_runs=8, nx=64, ny=16, ppc_inf=100.0, n_steps=10, sample_every=5)
     specs = dsmc._specs(wl.runs)
     opt = dsmc.make_options(False, 2, wl.sample_steps)
     tune = dsmc.dsmc_autotune_bytes(specs, opt)

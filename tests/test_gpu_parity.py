@@ -137,9 +137,9 @@ def test_uneven_runs_fp64(dsmc_gpu, oracle_lib):
 
 
 def test_dense_cells_one_wave_per_cell_fp64(dsmc_gpu, oracle_lib):
-    """~390 particles per cell: one wavefront per cell, 64 selections per
-    window in conflict-free levels; the first steps exceed (sigma c_r)_max
-    often, so windows are undone and replayed."""
+    """~390 particles per cell: one 256-thread block per cell (the auto
+    mode), 256 selections per window in conflict-free levels; the first steps
+    exceed (sigma c_r)_max often, so windows are undone and replayed."""
     wl = W.box(100_000, 2, 5, 5, seed=15, grid=(16, 16))
     O = _parity(dsmc_gpu, oracle_lib, wl.runs, 5)
     assert O[0].info()["ncoll"] > 5000
