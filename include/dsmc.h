@@ -113,9 +113,10 @@ typedef struct {
                                    hip_stream is the null stream) */
   int32_t tile_chunks;          /* tuning: 64-slot rounds per indexing tile (0 = default 256) */
   int32_t collide_mode;         /* tuning: 0 auto, 1 one lane per cell (up to 64 cells per
-                                   wavefront), 2 one 256-thread block per cell; auto takes 2 when
-                                   the expected particles per cell (initial fill or inflow fill)
-                                   reach 256 */
+                                   wavefront), 2 one 256-thread block per cell, 3 one 64-lane
+                                   wavefront per cell; auto takes 3 when the expected particles
+                                   per cell (initial fill or inflow fill) reach 112 and 2 when
+                                   they reach 288 */
   int32_t n_streams;            /* tuning: run groups stepped concurrently, each on a HIP stream of the
                                    library's own (0 = auto = 1, 1..4; 1 = every launch on hip_stream).
                                    The runs are split into contiguous groups of about equal slot
@@ -196,7 +197,7 @@ dsmc_status dsmc_get_counts(dsmc_ctx *ctx, int64_t *out, int32_t n_runs);
 
 /* ---- per-kernel timing ----------------------------------------------------- */
 
-#define DSMC_NKERNELS 18 /* kernel kinds; names from dsmc_kernel_name */
+#define DSMC_NKERNELS 19 /* kernel kinds; names from dsmc_kernel_name */
 
 /* Turn per-kernel timing on or off (synchronises).  While on, every launch is
  * bracketed by two HIP events on the context's stream and steps are not
@@ -222,8 +223,8 @@ dsmc_status dsmc_autotune_bytes(const dsmc_run_spec *runs, int32_t n_runs, const
 /* Chooses the tuning fields of dsmc_options (tile_chunks, collide_mode,
  * n_streams) for these runs by measurement.  None of them changes any result
  * (every setting computes the same sequential order bit for bit); they only
- * change speed.  Candidates: tiles of 4096, 8192 and 16384 slots; both
- * interaction modes when a run's expected particles per cell lie in 64..512;
+ * change speed.  Candidates: tiles of 4096, 8192 and 16384 slots; all three
+ * interaction modes when a run's expected particles per cell lie in 28..576;
  * one or two stream lanes when n_runs >= 8.  Each candidate is initialised in
  * the caller's arena (at least dsmc_autotune_bytes, 256-byte aligned), stepped
  * once to warm up (graph capture included when opt->use_graph), then n_steps

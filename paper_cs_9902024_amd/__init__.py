@@ -33,7 +33,7 @@ EXPORTS = ("dsmc_required_bytes", "dsmc_init_runs", "dsmc_step", "dsmc_sample", 
            "dsmc_get_counts", "dsmc_counting_sort_bytes", "dsmc_counting_sort",
            "dsmc_set_profiling", "dsmc_kernel_times", "dsmc_kernel_name", "dsmc_autotune_bytes",
            "dsmc_autotune")
-NKERNELS = 18
+NKERNELS = 19
 NINFO = 10
 
 

@@ -34,12 +34,12 @@ struct Plan {
   std::vector<int32_t> tile_run, face_run, cgroup_run, inflow_runs, eg_start, eg_runs, eg_nc, sample_steps,
       bitem_run;
   std::vector<int64_t> eg_acc;
-  std::vector<int2> items, cell_items;
+  std::vector<int2> items, cell_items, wave_items;
   std::vector<uint8_t> solid;
   std::vector<Ensemble> ens;
   std::vector<int64_t> spec_capacity;
   size_t off_runs, off_tile_run, off_face_run, off_cgroup_run, off_inflow, off_eg_start, off_eg_runs, off_eg_acc,
-      off_eg_nc, off_samples, off_items, off_cell_items, off_solid;
+      off_eg_nc, off_samples, off_items, off_cell_items, off_wave_items, off_solid;
   size_t off_P[2][6];
   size_t off_cell, off_lcr, off_lcr_tmp, off_hist, off_tot, off_bin_start, off_remc, off_gmax, off_ncoll, off_remf,
       off_gencnt, off_stage, off_acc, off_mom, off_nalive, off_nsorted, off_ngen, off_scalars, off_wallq, off_wallq_n,
@@ -61,7 +61,7 @@ dsmc_status validate(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_optio
   if (opt) {
     if (opt->n_groups < 0 || opt->n_samples < 0) return fail(msg, DSMC_EINVAL, "negative n_groups or n_samples");
     if (opt->tile_chunks < 0 || opt->tile_chunks > 4096) return fail(msg, DSMC_EINVAL, "tile_chunks out of range");
-    if (opt->collide_mode < 0 || opt->collide_mode > 2) return fail(msg, DSMC_EINVAL, "collide_mode out of range");
+    if (opt->collide_mode < 0 || opt->collide_mode > 3) return fail(msg, DSMC_EINVAL, "collide_mode out of range");
     if (opt->n_streams < 0 || opt->n_streams > kMaxLanes) return fail(msg, DSMC_EINVAL, "n_streams out of range");
   }
   const int dim = runs[0].dim;
@@ -198,11 +198,16 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
     R.n_init = s.n_init;
     R.hs = s.omega == 0.5;
     {
-      // interaction work item: a whole wave per cell for crowded cells
+      // interaction work item, by expected particles per cell: a lane, a
+      // wavefront or a whole block per cell
       double fill = (double)s.n_init;
       if (s.face_bc[0] == DSMC_BC_INFLOW) fill = std::max(fill, s.inflow_n * s.lx * s.ly * s.lz);
       const double ppc = fill / (double)R.nc;
-      R.coll_wave = opt.collide_mode == 2 || (opt.collide_mode == 0 && ppc >= kCrowdedPpc);
+      // collide_mode: 0 auto, 1 lane per cell, 2 block per cell, 3 wavefront per cell
+      if (opt.collide_mode == 1) R.coll_mode = 0;
+      else if (opt.collide_mode == 2) R.coll_mode = 2;
+      else if (opt.collide_mode == 3) R.coll_mode = 1;
+      else R.coll_mode = ppc >= kCrowdedPpc ? 2 : (ppc >= kWavePpc ? 1 : 0);
       // lane mode: as many cells per wavefront (<= 64) as fit 3/4 of the LDS stage
       const int cap = g.fp64 ? kLaneCapF64 : kLaneCapF32;
       R.lane_cells = (int32_t)std::max(1.0, std::min(64.0, std::floor(0.75 * cap / std::max(ppc, 1.0))));
@@ -211,7 +216,7 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
       // items go plane block by plane block (kItemPlanes planes of z, rows
       // of y outermost inside a block), so that z neighbours, like x and y
       // ones, tend to be gathered at the same time and meet in L2.
-      const int32_t step_c = R.coll_wave ? 1 : R.lane_cells;
+      const int32_t step_c = R.coll_mode ? 1 : R.lane_cells;
       std::vector<int32_t> starts;
       for (int32_t c = 0; c < R.nc; c += step_c) starts.push_back(c);
       if (s.nz > 1) {
@@ -225,7 +230,8 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
         std::sort(keyed.begin(), keyed.end());
         for (size_t k = 0; k < keyed.size(); ++k) starts[k] = keyed[k].second;
       }
-      for (int32_t c : starts) (R.coll_wave ? P.cell_items : P.items).push_back(make_int2(r, c));
+      std::vector<int2> &list = R.coll_mode == 2 ? P.cell_items : (R.coll_mode == 1 ? P.wave_items : P.items);
+      for (int32_t c : starts) list.push_back(make_int2(r, c));
     }
     for (int f = 0; f < 6; ++f) {
       R.bc[f] = (f < 2 * g.dim) ? s.face_bc[f] : DSMC_BC_SPECULAR;
@@ -316,6 +322,7 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
     ends[r].i1 = (int32_t)P.inflow_runs.size();
     ends[r].it1 = (int64_t)P.items.size();
     ends[r].ci1 = (int64_t)P.cell_items.size();
+    ends[r].wi1 = (int64_t)P.wave_items.size();
     ends[r].b1 = io + R.icap;
     so += cap;
     to += R.nt;
@@ -335,6 +342,7 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
   g.n_inflow_runs = (int32_t)P.inflow_runs.size();
   g.n_items = (int64_t)P.items.size();
   g.n_cell_items = (int64_t)P.cell_items.size();
+  g.n_wave_items = (int64_t)P.wave_items.size();
   g.collide_mode = opt.collide_mode;
 
   // Lanes: contiguous run groups of about equal slot counts, stepped
@@ -363,6 +371,7 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
       L.i0 = prev ? prev->i1 : 0;
       L.it0 = prev ? prev->it1 : 0;
       L.ci0 = prev ? prev->ci1 : 0;
+      L.wi0 = prev ? prev->wi1 : 0;
       L.b0 = prev ? prev->b1 : 0;
       const LaneRange &e = ends[L.r1 - 1];
       L.t1 = e.t1;
@@ -370,6 +379,7 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
       L.i1 = e.i1;
       L.it1 = e.it1;
       L.ci1 = e.ci1;
+      L.wi1 = e.wi1;
       L.b1 = e.b1;
     }
   }
@@ -426,6 +436,7 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
   P.off_samples = take(4 * P.sample_steps.size());
   P.off_items = take(sizeof(int2) * P.items.size());
   P.off_cell_items = take(sizeof(int2) * P.cell_items.size());
+  P.off_wave_items = take(sizeof(int2) * P.wave_items.size());
   P.off_solid = take(P.solid.size());
   for (int b = 0; b < 2; ++b)
     for (int a = 0; a < 6; ++a) P.off_P[b][a] = (a == 2 && g.dim == 2) ? (size_t)-1 : take(es * g.n_slots);
@@ -472,6 +483,7 @@ DevPtrs<real> carve(const Plan &P, char *base) {
   d.sample_steps = (const int32_t *)(base + P.off_samples);
   d.items = (const int2 *)(base + P.off_items);
   d.cell_items = (const int2 *)(base + P.off_cell_items);
+  d.wave_items = (const int2 *)(base + P.off_wave_items);
   d.solid = (const uint8_t *)(base + P.off_solid);
   for (int b = 0; b < 2; ++b) {
     real **c[6] = {&d.P[b].x, &d.P[b].y, &d.P[b].z, &d.P[b].u, &d.P[b].v, &d.P[b].w};
@@ -738,6 +750,7 @@ dsmc_status dsmc_init_runs(const dsmc_run_spec *runs, int32_t n_runs, const dsmc
   if (!st) st = upload(c, P.off_samples, P.sample_steps);
   if (!st) st = upload(c, P.off_items, P.items);
   if (!st) st = upload(c, P.off_cell_items, P.cell_items);
+  if (!st) st = upload(c, P.off_wave_items, P.wave_items);
   if (!st) st = upload(c, P.off_solid, P.solid);
   if (!st) st = make_streams(c);
   if (!st) {
@@ -1055,7 +1068,7 @@ const char *dsmc_kernel_name(int32_t kind) {
   static const char *names[kNumKinds] = {"step_begin", "gen_count", "gen_emit", "motion", "motion_walls", "digcount",
                                          "colscan", "digscan", "scatter", "bin_bounds", "bin_finalize",
                                          "collide_lanes", "collide_cells", "accumulate", "sample", "moments",
-                                         "bucket_items", "bucket_scan"};
+                                         "bucket_items", "bucket_scan", "collide_waves"};
   if (kind < 0 || kind >= kNumKinds) return nullptr;
   return names[kind];
 }
@@ -1088,27 +1101,23 @@ namespace {
 // interaction modes when some run's expected particles per cell lie where
 // either could win (16..256); two stream lanes when there are enough runs to
 // split.
-// True when auto picks the block-per-cell mode for the first run's fill
-// (the run that decides for the batch is not important: the candidate list
-// holds both modes either way).
-bool auto_block(const dsmc_run_spec *runs, int32_t n_runs) {
-  (void)n_runs;
-  const dsmc_run_spec &s = runs[0];
+// Expected particles per cell of a run (initial fill, or the inflow's fill).
+double fill_ppc(const dsmc_run_spec &s) {
   double fill = (double)s.n_init;
   if (s.face_bc[0] == DSMC_BC_INFLOW) fill = std::max(fill, s.inflow_n * s.lx * s.ly * s.lz);
-  return fill / ((double)s.nx * s.ny * s.nz) >= kCrowdedPpc;
+  return fill / ((double)s.nx * s.ny * s.nz);
 }
 
+// The interaction modes worth timing: auto, plus every explicit mode when
+// some run's cells lie near a threshold of the auto rule (a quarter of the
+// wavefront threshold up to twice the block threshold).
 std::vector<dsmc_options> tune_candidates(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_options &base) {
   bool ambiguous = false;
   for (int r = 0; r < n_runs; ++r) {
-    const dsmc_run_spec &s = runs[r];
-    double fill = (double)s.n_init;
-    if (s.face_bc[0] == DSMC_BC_INFLOW) fill = std::max(fill, s.inflow_n * s.lx * s.ly * s.lz);
-    const double ppc = fill / ((double)s.nx * s.ny * s.nz);
-    if (ppc >= 0.25 * kCrowdedPpc && ppc <= 2.0 * kCrowdedPpc) ambiguous = true;
+    const double ppc = fill_ppc(runs[r]);
+    if (ppc >= 0.25 * kWavePpc && ppc <= 2.0 * kCrowdedPpc) ambiguous = true;
   }
-  std::vector<int32_t> modes = ambiguous ? std::vector<int32_t>{0, 3} : std::vector<int32_t>{0};
+  std::vector<int32_t> modes = ambiguous ? std::vector<int32_t>{0, 1, 3, 2} : std::vector<int32_t>{0};
   std::vector<int32_t> lanes = n_runs >= 8 ? std::vector<int32_t>{1, 2} : std::vector<int32_t>{1};
   std::vector<dsmc_options> out;
   for (int32_t tc : {256, 128, 64})
@@ -1116,8 +1125,7 @@ std::vector<dsmc_options> tune_candidates(const dsmc_run_spec *runs, int32_t n_r
       for (int32_t l : lanes) {
         dsmc_options o = base;
         o.tile_chunks = tc;
-        // 3 stands for the mode auto does not take
-        o.collide_mode = m == 3 ? (auto_block(runs, n_runs) ? 1 : 2) : 0;
+        o.collide_mode = m;
         o.n_streams = l;
         out.push_back(o);
       }

@@ -13,6 +13,8 @@ constexpr int kWavesPerBlock = 4;          // 256-thread blocks
 constexpr int kCollideWaves = 2;           // waves per block of the collide kernel
 constexpr int kCollideCapF32 = 1280;       // particles staged in LDS per collide wavefront
 constexpr int kCollideCapF64 = 1024;
+constexpr int kWaveCapF32 = 512;           // particles staged in LDS per wavefront-per-cell item
+constexpr int kWaveCapF64 = 256;
 constexpr int kLaneCapF32 = 640;           // particles staged in LDS per lane-per-cell wavefront
 constexpr int kLaneCapF64 = 512;
 constexpr int kDigitBits = 11;             // indexing digit: 2048 bins per pass
@@ -32,7 +34,8 @@ enum : int { kErrCapacity = -3, kErrBounce = -7, kErrReject = -8, kErrNumeric = 
 constexpr double kMaxSelections = 1e9;  // per cell per step; more means non-finite state
 constexpr int kMaxLanes = 4;            // run groups stepped concurrently on their own streams
 constexpr int kItemPlanes = 4;          // z planes per block of the 3-D interaction item order
-constexpr double kCrowdedPpc = 256.0;   // expected particles per cell from which a cell gets a whole block
+constexpr double kWavePpc = 112.0;      // expected particles per cell from which a cell gets a wavefront
+constexpr double kCrowdedPpc = 288.0;   // ... and from which it gets a whole block
 
 // Per-run constants and layout, read by every kernel (AoS in device memory).
 struct RunDev {
@@ -54,7 +57,8 @@ struct RunDev {
   int32_t nface;     // inflow face elements (0 without inflow)
   int32_t ndig;      // digits of the first indexing pass
   int32_t hs;        // hard sphere (omega == 0.5)
-  int32_t coll_wave; // interaction work item = one cell per block (else lane_cells cells, a lane each)
+  int32_t coll_mode; // interaction work item: 0 lane_cells cells (a lane each), 1 one cell per
+                     // wavefront, 2 one cell per block
   int32_t lane_cells;
   int32_t bc[6];
   uint32_t key0, key1;   // Philox key: run id, seed
@@ -96,6 +100,7 @@ struct DevPtrs {
   const int32_t *sample_steps; // [n_samples]
   const int2 *items;           // [n_items] lane-per-cell interaction items: (run, first cell)
   const int2 *cell_items;      // [n_cell_items] block-per-cell interaction items: (run, cell)
+  const int2 *wave_items;      // [n_wave_items] wavefront-per-cell interaction items: (run, cell)
   const uint8_t *solid;        // solid masks of the runs with obstacles (1 byte per cell)
   Particles<real> P[2];
   int32_t *cell;               // [slots] cell (bin) of each slot after Motion
@@ -136,6 +141,7 @@ struct LaneRange {
   int32_t i0, i1;    // entries of the inflow-run list
   int64_t it0, it1;  // lane-per-cell interaction items
   int64_t ci0, ci1;  // block-per-cell interaction items
+  int64_t wi0, wi1;  // wavefront-per-cell interaction items
   int32_t b0, b1;    // bucket-item slots (two-level Indexing)
 };
 
@@ -160,6 +166,7 @@ struct Geometry {
   int n_samples;
   int64_t n_items;      // lane-per-cell interaction items (up to 64 cells each)
   int64_t n_cell_items; // block-per-cell interaction items
+  int64_t n_wave_items; // wavefront-per-cell interaction items
   int collide_mode;      // 0 auto, 1 lane per cell, 2 wave per cell
   int any_solid;         // some run has solid cells (Motion checks paths against them)
   int n_lanes;           // run groups per step (1: everything on the caller's stream)
@@ -181,7 +188,7 @@ struct LaneStreams {
 enum KernelKind : int {
   kKStepBegin, kKGenCount, kKGenEmit, kKMotion, kKMotionWalls, kKDigCount, kKColScan, kKDigScan, kKScatter,
   kKBinBounds, kKBinFinalize, kKCollide, kKCollideCell, kKAccumulate, kKSample, kKMoments, kKBucketItems,
-  kKBucketScan, kNumKinds
+  kKBucketScan, kKCollideWave, kNumKinds
 };
 
 // Optional hook around every launch (event timing); null = no hook.

@@ -1599,11 +1599,15 @@ struct BlockScratch {
 // flight across it; the empty asm statements keep the compiler from moving
 // memory accesses across the barrier.
 struct FullSync {
+  static constexpr int kSize = 256;  // threads sharing one chain
+  __device__ static int tid() { return (int)threadIdx.x; }
   __device__ static void bar() { __syncthreads(); }
   __device__ static int any(int p, int32_t (&)[2][kWavesPerBlock], int) { return __syncthreads_or(p); }
   __device__ static int count(int p, int32_t (&)[2][kWavesPerBlock], int) { return __syncthreads_count(p); }
 };
 struct LdsSync {
+  static constexpr int kSize = 256;
+  __device__ static int tid() { return (int)threadIdx.x; }
   __device__ static void bar() {
     asm volatile("" ::: "memory");
     __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt, expcnt left open
@@ -1632,6 +1636,28 @@ struct LdsSync {
   }
 };
 
+// One wavefront per chain: its lanes run in lockstep and its LDS operations
+// complete in order, so a barrier is only a compiler fence and a wait for
+// the wavefront's own LDS operations; votes are ballots.
+struct WaveSync {
+  static constexpr int kSize = kWave;
+  __device__ static int tid() { return (int)(threadIdx.x & (kWave - 1)); }
+  __device__ static void bar() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+  }
+  __device__ static int any(int p, int32_t (&)[2][kWavesPerBlock], int) {
+    bar();
+    return __builtin_amdgcn_ballot_w64(p != 0) != 0ull;
+  }
+  __device__ static int count(int p, int32_t (&)[2][kWavesPerBlock], int) {
+    bar();
+    return (int)__popcll(__builtin_amdgcn_ballot_w64(p != 0));
+  }
+};
+
 template <typename real>
 constexpr int collide_cell_bytes() {
   return ((CollideCap<real>::value * (3 * (int)sizeof(real) + 4)) + 15) & ~15;
@@ -1640,7 +1666,7 @@ constexpr int collide_cell_bytes() {
 template <typename real, typename Sync = FullSync, typename RunT = RunDev>
 __device__ uint32_t chain_block(const RunT &R, uint32_t step, uint32_t c, uint32_t N, int64_t nsel, real *u,
                                 real *v, real *w, int32_t *own, BlockScratch<real> &sh, real &gm) {
-  const int tid = threadIdx.x;
+  const int tid = Sync::tid();
   uint32_t ncol = 0;
   int64_t w0 = 0;
   int slot = 0;
@@ -1695,7 +1721,7 @@ __device__ uint32_t chain_block(const RunT &R, uint32_t step, uint32_t c, uint32
     const int ks = sh.ks;
     if (ks == 0x7fffffff) {
       ncol += Sync::count(accepted, sh.vote, slot ^= 1);
-      w0 += 256;
+      w0 += Sync::kSize;
       continue;
     }
     // undo selections ks.. in reverse order of execution
@@ -1848,6 +1874,62 @@ __global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, 
     if (tid < kFields) d.stage[gc * kFields + tid] = ((sh.red[0][tid] + sh.red[1][tid]) + sh.red[2][tid]) + sh.red[3][tid];
   }
   if (tid == 0) {
+    d.gmax[gc] = gm;
+    d.rem_c[gc] = rem;
+    d.ncoll[gc] += ncol;
+  }
+}
+
+// Cells of a few hundred particles: one wavefront per cell, four cells per
+// block.  The wavefront gathers its cell through LCR (positions to P',
+// velocities to its LDS stage), runs the same collision chain as the block
+// mode, 64 selections per window, synchronised within the wavefront only,
+// writes the velocities back and samples.  A cell beyond the stage runs the
+// sequential chain on P' in one lane.
+template <typename real> struct WaveCap;
+template <> struct WaveCap<float> { static constexpr int value = kWaveCapF32; };
+template <> struct WaveCap<double> { static constexpr int value = kWaveCapF64; };
+
+template <typename real, int DIM>
+__global__ __launch_bounds__(256) void k_collide_wave(DevPtrs<real> d, int src, int64_t wi0, int64_t wi1) {
+  constexpr int CAP = WaveCap<real>::value;
+  __shared__ __align__(16) real vel[kWavesPerBlock][3 * CAP];
+  __shared__ int32_t own[kWavesPerBlock][CAP];
+  __shared__ BlockScratch<real> shs[kWavesPerBlock];
+  const int wave = wave_index(), lane = threadIdx.x & 63;
+  const int64_t item = wi0 + xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wave;
+  if (item >= wi1) return;
+  const int2 it = d.wave_items[item];
+  const RunDev &R = d.runs[it.x];
+  const int32_t c = it.y;
+  const int64_t gc = R.co + c;
+  const int64_t b0 = d.bin_start[R.bo + c];
+  const int64_t n = (int64_t)d.bin_start[R.bo + c + 1] - b0;
+  const bool in_lds = n <= CAP;
+  real *su = vel[wave], *sv = su + CAP, *sw = sv + CAP;
+  const Particles<real> A = d.P[src], B = d.P[1 - src];
+  gather_through_lcr<real, DIM>(R, d.lcr, A, B, b0, n, in_lds, su, sv, sw);
+  if (in_lds) WaveSync::bar();
+  else global_sync_wave();
+  const uint32_t step = *d.step;
+  const bool sample = *d.sample_slot >= 0;
+  real gm = d.gmax[gc], rem = d.rem_c[gc];
+  const int64_t nsel = ntc_selections<real>(R, n, gm, rem, d.err);
+  real *u = in_lds ? su : B.u + R.so + b0;
+  real *v = in_lds ? sv : B.v + R.so + b0;
+  real *w = in_lds ? sw : B.w + R.so + b0;
+  uint32_t ncol = 0;
+  if (in_lds) {
+    ncol = chain_block<real, WaveSync>(R, step, (uint32_t)c, (uint32_t)n, nsel, su, sv, sw, own[wave], shs[wave],
+                                       gm);
+    WaveSync::bar();
+    store_velocities<real>(R, B, b0, n, su, sv, sw);
+  } else {
+    if (lane == 0) ncol = chain_serial<real>(R, step, (uint32_t)c, (uint32_t)n, 0, nsel, u, v, w, gm);
+    global_sync_wave();
+  }
+  if (sample) sample_cell_wave(u, v, w, n, d.stage + gc * kFields);
+  if (lane == 0) {
     d.gmax[gc] = gm;
     d.rem_c[gc] = rem;
     d.ncoll[gc] += ncol;
@@ -2367,6 +2449,11 @@ static void lane_step(const Geometry &g, const LaneRange &L, const DevPtrs<real>
     TIMED(kKCollide, hipLaunchKernelGGL((k_collide<real, DIM>), dim3((unsigned)nblk), dim3(kCollideWaves * 64),
                                         (size_t)kCollideWaves * collide_wave_bytes<real>(), s, d, buf, L.it0,
                                         L.it1));
+  }
+  if (L.wi1 > L.wi0) {
+    const int64_t nblk = (L.wi1 - L.wi0 + kWavesPerBlock - 1) / kWavesPerBlock;
+    TIMED(kKCollideWave, hipLaunchKernelGGL((k_collide_wave<real, DIM>), dim3((unsigned)nblk), dim3(256), 0, s, d,
+                                            buf, L.wi0, L.wi1));
   }
   if (L.ci1 > L.ci0) {
     if constexpr (std::is_same<real, float>::value) {

@@ -135,13 +135,13 @@ def test_obstacle_specs(dsmc):
 
 
 def test_autotune_workspace_covers_every_candidate(dsmc):
-    # 100 expected particles per cell: both interaction modes are candidates
+    # 100 expected particles per cell: all three interaction modes are candidates
     wl = W.channel(n_runs=8, nx=64, ny=16, ppc_inf=100.0, n_steps=10, sample_every=5)
     specs = dsmc._specs(wl.runs)
     opt = dsmc.make_options(False, 2, wl.sample_steps)
     tune = dsmc.dsmc_autotune_bytes(specs, opt)
     for tc in (64, 128, 256):
-        for mode in (1, 2):
+        for mode in (1, 2, 3):
             for lanes in (1, 2):
                 o = dsmc.make_options(False, 2, wl.sample_steps, tile_chunks=tc, collide_mode=mode,
                                       n_streams=lanes)

@@ -98,7 +98,7 @@ def test_autotuned_settings_give_identical_results(dsmc_gpu):
     runs = _small_channel_runs(8)
     tuned = dsmc_gpu.Ensemble.autotune(runs, [3, 6], state_fp64=False, n_groups=2, use_graph=True, n_steps=2)
     assert tuned["tile_chunks"] in (64, 128, 256) and tuned["n_streams"] in (1, 2)
-    assert tuned["collide_mode"] in (0, 1, 2) and tuned["ms_per_step"] > 0
+    assert tuned["collide_mode"] in (0, 1, 2, 3) and tuned["ms_per_step"] > 0
     kw = {k: tuned[k] for k in ("tile_chunks", "collide_mode", "n_streams")}
     A = dsmc_gpu.Ensemble(runs, [3, 6], state_fp64=False, n_groups=2, use_graph=True)
     B = dsmc_gpu.Ensemble(runs, [3, 6], state_fp64=False, n_groups=2, use_graph=True, **kw)
@@ -111,10 +111,11 @@ def test_autotuned_settings_give_identical_results(dsmc_gpu):
         np.testing.assert_array_equal(A.accum(k), B.accum(k))
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 def test_interaction_modes_give_identical_results(dsmc_gpu, mode):
-    """The lane-per-cell and block-per-cell interaction kernels both run each
-    cell's selections in the sequential order: FP32 results are identical."""
+    """The lane-per-cell, block-per-cell and wavefront-per-cell interaction
+    kernels all run each cell's selections in the sequential order: FP32
+    results are identical."""
     import torch
     runs = _small_channel_runs(3)
     A = dsmc_gpu.Ensemble(runs, [4], state_fp64=False, n_groups=1, collide_mode=0)

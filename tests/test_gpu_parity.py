@@ -145,8 +145,24 @@ def test_dense_cells_one_wave_per_cell_fp64(dsmc_gpu, oracle_lib):
     assert O[0].info()["ncoll"] > 5000
 
 
-def test_sparse_cells_forced_wave_mode_fp64(dsmc_gpu, oracle_lib):
+def test_sparse_cells_forced_block_mode_fp64(dsmc_gpu, oracle_lib):
     _parity(dsmc_gpu, oracle_lib, W.plain_box().runs, 4, collide_mode=2)
+
+
+def test_wavefront_per_cell_fp64(dsmc_gpu, oracle_lib):
+    """~130 particles per cell: one wavefront per cell (the auto mode), 64
+    selections per window with wavefront-level synchronisation, undone and
+    replayed when (sigma c_r)_max grows inside a window."""
+    wl = W.box(33_000, 2, 5, 5, seed=19, grid=(16, 16))
+    O = _parity(dsmc_gpu, oracle_lib, wl.runs, 5)
+    assert O[0].info()["ncoll"] > 1000
+
+
+def test_wavefront_per_cell_beyond_its_stage_fp64(dsmc_gpu, oracle_lib):
+    """~390 particles per cell forced into the wavefront mode, whose FP64
+    stage holds 256: every cell takes the sequential fallback on P'."""
+    wl = W.box(100_000, 1, 3, 3, seed=20, grid=(16, 16))
+    _parity(dsmc_gpu, oracle_lib, wl.runs, 3, collide_mode=3)
 
 
 def test_dense_cells_forced_lane_mode_fp64(dsmc_gpu, oracle_lib):
@@ -155,7 +171,7 @@ def test_dense_cells_forced_lane_mode_fp64(dsmc_gpu, oracle_lib):
 
 
 def test_cells_beyond_lds_capacity_fp64(dsmc_gpu, oracle_lib):
-    """A cell (wave mode) and a 64-cell group (lane mode) holding more
+    """A cell (block mode) and a 64-cell group (lane mode) holding more
     particles than the LDS stage: the global-memory fallbacks."""
     big_cell = W.box(20_000, 1, 3, 3, seed=17, grid=(4, 4)).runs      # 1250 per cell
     _parity(dsmc_gpu, oracle_lib, big_cell, 3)
