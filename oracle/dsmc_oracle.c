@@ -57,6 +57,13 @@
 
 #define MAX_WALL_HITS 64
 #define MAX_GEN_ATTEMPTS 1000
+/* Each inflow particle draws from its own stretch of its face element's
+ * stream: particle k starts at uniform k * GEN_UNIFORMS (at most
+ * 4 * MAX_GEN_ATTEMPTS + 5 are used), so particles are independent of one
+ * another's rejections.  The 32-bit block counter bounds k below 2^21; runs
+ * expecting 2^20 or more entrants per face element per step are refused. */
+#define GEN_UNIFORMS 4096
+#define MAX_GEN_PER_FACE 1048576.0
 #define MAX_INIT_ATTEMPTS 100
 
 static const double TWO_PI = 6.283185307179586476925286766559;
@@ -288,6 +295,7 @@ or_run *or_run_new(const or_spec *sp, int32_t *status)
         double flux = sp->inflow_n / (2.0 * SQRT_PI * R->beta) *
                       (exp(-s * s) + SQRT_PI * s * (1.0 + erf(s)));
         R->mbar = flux * (R->dy * R->dz) * sp->dt;
+        if (!(R->mbar < MAX_GEN_PER_FACE)) { or_run_free(R); *status = OR_EINVAL; return NULL; }
     }
 
     int64_t cap = sp->capacity > 0 ? sp->capacity : 1;
@@ -364,6 +372,7 @@ void or_generation(or_run *R)
         int64_t iy = j % sp->ny, iz = j / sp->ny;
         ustream s = {{sp->run_id, sp->seed}, R->step, PURPOSE_GEN, (uint32_t)j, 0};
         for (int64_t k = 0; k < nemit; ++k) {
+            s.next = (uint64_t)k * GEN_UNIFORMS;
             /* normal velocity: z = beta*u has density ~ z exp(-(z-s)^2), z > 0 */
             double z = 0.0;
             int att;

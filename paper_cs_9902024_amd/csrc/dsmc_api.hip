@@ -31,14 +31,15 @@ struct Ensemble {
 struct Plan {
   Geometry g{};
   std::vector<RunDev> runs;
-  std::vector<int32_t> tile_run, face_run, cgroup_run, inflow_runs, eg_start, eg_runs, eg_nc, sample_steps,
-      bitem_run;
+  std::vector<int32_t> tile_run, face_run, cgroup_run, inflow_runs, gen_blk, eg_start, eg_runs, eg_nc,
+      sample_steps, bitem_run;
   std::vector<int64_t> eg_acc;
   std::vector<int2> items, cell_items, wave_items;
   std::vector<uint8_t> solid;
   std::vector<Ensemble> ens;
   std::vector<int64_t> spec_capacity;
-  size_t off_runs, off_tile_run, off_face_run, off_cgroup_run, off_inflow, off_eg_start, off_eg_runs, off_eg_acc,
+  size_t off_runs, off_tile_run, off_face_run, off_cgroup_run, off_inflow, off_gen_blk, off_eg_start, off_eg_runs,
+      off_eg_acc,
       off_eg_nc, off_samples, off_items, off_cell_items, off_wave_items, off_solid;
   size_t off_P[2][6];
   size_t off_cell, off_lcr, off_lcr_tmp, off_hist, off_tot, off_bin_start, off_remc, off_gmax, off_ncoll, off_remf,
@@ -266,8 +267,16 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
       const double flux =
           s.inflow_n / (2.0 * kSqrtPi * R.beta) * (std::exp(-sv * sv) + kSqrtPi * sv * (1.0 + std::erf(sv)));
       R.mbar = flux * (R.dy * R.dz) * s.dt;
-      if (!(R.mbar < 1e8)) return fail(msg, DSMC_EINVAL, "run %d: inflow of >= 1e8 particles per face per step", r);
+      if (!(R.mbar < kMaxGenPerFace))
+        return fail(msg, DSMC_EINVAL, "run %d: inflow of >= 2^20 particles per face element per step", r);
       R.inflow_sqrtT = std::sqrt(s.inflow_T);
+      if (P.gen_blk.empty()) P.gen_blk.push_back(0);
+      // a face element takes at most floor(mbar) + 1 entrants a step (the
+      // carried remainder is below one), and a run no more than its capacity
+      const int64_t most = std::min<int64_t>((int64_t)R.nface * ((int64_t)R.mbar + 1), s.capacity);
+      const int64_t blk = P.gen_blk.back() + std::max<int64_t>(1, (most + 255) / 256);
+      if (blk > INT32_MAX) return fail(msg, DSMC_EINVAL, "inflow of the batch exceeds 2^31 emission blocks");
+      P.gen_blk.push_back((int32_t)blk);
       P.inflow_runs.push_back(r);
       for (int j = 0; j < R.nface; ++j) P.face_run.push_back(r);
     }
@@ -320,6 +329,7 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
     ends[r].t1 = to + R.nt;
     ends[r].f1 = fo + R.nface;
     ends[r].i1 = (int32_t)P.inflow_runs.size();
+    ends[r].g1 = P.gen_blk.empty() ? 0 : P.gen_blk.back();
     ends[r].it1 = (int64_t)P.items.size();
     ends[r].ci1 = (int64_t)P.cell_items.size();
     ends[r].wi1 = (int64_t)P.wave_items.size();
@@ -369,6 +379,7 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
       L.t0 = prev ? prev->t1 : 0;
       L.f0 = prev ? prev->f1 : 0;
       L.i0 = prev ? prev->i1 : 0;
+      L.g0 = prev ? prev->g1 : 0;
       L.it0 = prev ? prev->it1 : 0;
       L.ci0 = prev ? prev->ci1 : 0;
       L.wi0 = prev ? prev->wi1 : 0;
@@ -377,6 +388,7 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
       L.t1 = e.t1;
       L.f1 = e.f1;
       L.i1 = e.i1;
+      L.g1 = e.g1;
       L.it1 = e.it1;
       L.ci1 = e.ci1;
       L.wi1 = e.wi1;
@@ -429,6 +441,7 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
   P.off_face_run = take(4 * P.face_run.size());
   P.off_cgroup_run = take(4 * P.cgroup_run.size());
   P.off_inflow = take(4 * P.inflow_runs.size());
+  P.off_gen_blk = take(4 * P.gen_blk.size());
   P.off_eg_start = take(4 * P.eg_start.size());
   P.off_eg_runs = take(4 * P.eg_runs.size());
   P.off_eg_acc = take(8 * P.eg_acc.size());
@@ -476,6 +489,7 @@ DevPtrs<real> carve(const Plan &P, char *base) {
   d.face_run = (const int32_t *)(base + P.off_face_run);
   d.cgroup_run = (const int32_t *)(base + P.off_cgroup_run);
   d.inflow_runs = (const int32_t *)(base + P.off_inflow);
+  d.gen_blk = (const int32_t *)(base + P.off_gen_blk);
   d.eg_start = (const int32_t *)(base + P.off_eg_start);
   d.eg_runs = (const int32_t *)(base + P.off_eg_runs);
   d.eg_acc = (const int64_t *)(base + P.off_eg_acc);
@@ -743,6 +757,7 @@ dsmc_status dsmc_init_runs(const dsmc_run_spec *runs, int32_t n_runs, const dsmc
   if (!st) st = upload(c, P.off_face_run, P.face_run);
   if (!st) st = upload(c, P.off_cgroup_run, P.cgroup_run);
   if (!st) st = upload(c, P.off_inflow, P.inflow_runs);
+  if (!st) st = upload(c, P.off_gen_blk, P.gen_blk);
   if (!st) st = upload(c, P.off_eg_start, P.eg_start);
   if (!st) st = upload(c, P.off_eg_runs, P.eg_runs);
   if (!st) st = upload(c, P.off_eg_acc, P.eg_acc);

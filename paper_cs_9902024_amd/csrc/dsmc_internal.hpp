@@ -21,6 +21,14 @@ constexpr int kDigitBits = 11;             // indexing digit: 2048 bins per pass
 constexpr int kDigits = 1 << kDigitBits;
 constexpr int kMaxWallHits = 64;           // wall interactions per particle per step
 constexpr int kMaxGenAttempts = 1000;      // inflow normal-velocity rejection
+// Each inflow particle draws from its own stretch of its face element's
+// stream, from uniform k * kGenUniforms for particle k, so particles do not
+// depend on one another's rejections and are generated in parallel.  The
+// 32-bit block counter bounds k below 2^21: runs expecting kMaxGenPerFace or
+// more entrants per face element per step are refused.
+constexpr uint32_t kGenUniforms = 4096;
+constexpr double kMaxGenPerFace = 1048576.0;
+static_assert(4 * kMaxGenAttempts + 5 <= (int)kGenUniforms, "a particle's draws must fit its stretch");
 constexpr int kMaxInitAttempts = 100;      // initial position draws that land in solid cells
 constexpr int kFields = 7;                 // N, sum u, v, w, u^2, v^2, w^2
 constexpr int kMoments = 8;                // n, ux, uy, uz, T, Tx, Ty, Tz
@@ -93,6 +101,7 @@ struct DevPtrs {
   const int32_t *face_run;     // [n_faces]
   const int32_t *cgroup_run;   // [n_cells_aligned / 64]
   const int32_t *inflow_runs;  // [n_inflow_runs]
+  const int32_t *gen_blk;      // [n_inflow_runs + 1] first emission block of each inflow run
   const int32_t *eg_start;     // [n_eg + 1] CSR of runs per (ensemble, group)
   const int32_t *eg_runs;
   const int64_t *eg_acc;       // [n_eg + 1] offset (doubles) of each (ensemble, group) block
@@ -113,7 +122,7 @@ struct DevPtrs {
   real *rem_c, *gmax;          // [cells]
   uint32_t *ncoll;             // [cells] cumulative accepted collisions
   double *rem_f;               // [faces]
-  int32_t *gen_count;          // [faces]
+  int32_t *gen_count;          // [faces] this step's first entrant of each face element (run-local)
   double *stage;               // [cells][7] per-run sample sums of one sample
   double *acc;                 // [n_samples][acc_stride]
   double *mom;                 // [2][max_nc][8]
@@ -139,6 +148,7 @@ struct LaneRange {
   int32_t t0, t1;    // tiles
   int64_t f0, f1;    // inflow faces
   int32_t i0, i1;    // entries of the inflow-run list
+  int32_t g0, g1;    // emission blocks
   int64_t it0, it1;  // lane-per-cell interaction items
   int64_t ci0, ci1;  // block-per-cell interaction items
   int64_t wi0, wi1;  // wavefront-per-cell interaction items

@@ -232,93 +232,26 @@ __global__ void k_step_begin(uint32_t *step, int32_t *slot, const int32_t *sampl
 // Generation: drifting-Maxwellian inflow through the -x face
 // ---------------------------------------------------------------------------
 
+// One block per run with inflow: the number entering through each face
+// element this step (the mean plus the carried remainder, rounded down),
+// turned in place into each element's first entrant in the run's emission
+// order (face order); then the capacity check and the run's new live count.
 template <typename real>
-__global__ __launch_bounds__(256) void k_gen_count(DevPtrs<real> d, int64_t f0, int64_t f1) {
-  for (int64_t j = f0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < f1;
-       j += (int64_t)gridDim.x * blockDim.x) {
-    const RunDev &R = d.runs[d.face_run[j]];
-    const double M = R.mbar + d.rem_f[j];
-    const double fl = floor(M);
-    d.rem_f[j] = M - fl;
-    d.gen_count[j] = (int32_t)fl;
-  }
-}
-
-template <typename real, int DIM>
-__device__ void emit_face(const RunDev &R, uint32_t step, int32_t jl, int32_t cnt, int64_t dst0,
-                          Particles<real> P, int32_t *err) {
-  UStream<real> s(R.key0, R.key1, step, kGen, (uint32_t)jl);
-  const real s_inf = (real)R.s_inf, p_branch = (real)R.p_branch, beta = (real)R.beta;
-  const real st = (real)R.inflow_sqrtT, dt = (real)R.dt, dy = (real)R.dy, dz = (real)R.dz;
-  const int32_t iy = jl % R.ny, iz = jl / R.ny;
-  for (int32_t k = 0; k < cnt; ++k) {
-    // normal velocity: z = beta*u has density ~ z exp(-(z-s)^2), z > 0
-    real z = 0;
-    int att;
-    for (att = 0; att < kMaxGenAttempts; ++att) {
-      const real ub = s(), up = s(), uq = s(), ua = s();
-      const real r = sqrt(-log(up));
-      const real x = (ub < p_branch) ? ((uq < (real)0.5) ? -r : r) : r * cos(two_pi<real>() * uq);
-      z = s_inf + x;
-      if (z > (real)0 && ua < z / (s_inf + fabs(x))) break;
-    }
-    if (att == kMaxGenAttempts) {
-      set_error(err, kErrReject);
-      return;
-    }
-    const real u = z / beta;
-    const real v1 = s(), v2 = s();
-    real t0, t1;
-    box_muller(v1, v2, t0, t1);
-    const real y = ((real)iy + s()) * dy;
-    real zc = 0;
-    if (DIM == 3) zc = ((real)iz + s()) * dz;
-    const real ut = s();
-    const real x0 = -(u * dt) * ((real)1 - ut);
-    const int64_t o = dst0 + k;
-    P.x[o] = x0;
-    P.y[o] = y;
-    if (DIM == 3) P.z[o] = zc;
-    P.u[o] = u;
-    P.v[o] = st * t0;
-    P.w[o] = st * t1;
-  }
-}
-
-// One block per run with inflow: scan the face counts, check capacity, append
-// the new particles in face order behind the run's live particles.
-template <typename real, int DIM>
-__global__ __launch_bounds__(256) void k_gen_emit(DevPtrs<real> d, int buf, int32_t i0) {
+__global__ __launch_bounds__(256) void k_gen_count(DevPtrs<real> d, int32_t i0) {
   __shared__ int64_t s_part[256];
-  __shared__ int32_t s_n0;
   const int r = d.inflow_runs[i0 + blockIdx.x];
   const RunDev &R = d.runs[r];
   const int tid = threadIdx.x;
-  if (tid == 0) s_n0 = d.n_alive[r];
-  int64_t my = 0;
-  for (int j = tid; j < R.nface; j += 256) my += d.gen_count[R.fo + j];
-  s_part[tid] = my;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (tid < o) s_part[tid] += s_part[tid + o];
-    __syncthreads();
-  }
-  const int64_t total = s_part[0];
-  const int64_t n0 = s_n0;
-  const bool ok = n0 + total <= R.cap_spec;
-  __syncthreads();
-  if (!ok) {
-    if (tid == 0) {
-      set_error(d.err, kErrCapacity);
-      d.n_gen[r] = 0;
-    }
-    return;
-  }
-  const uint32_t step = *d.step;
   int64_t carry = 0;
   for (int base = 0; base < R.nface; base += 256) {
     const int j = base + tid;
-    const int32_t cnt = (j < R.nface) ? d.gen_count[R.fo + j] : 0;
+    int32_t cnt = 0;
+    if (j < R.nface) {
+      const double M = R.mbar + d.rem_f[R.fo + j];
+      const double fl = floor(M);
+      d.rem_f[R.fo + j] = M - fl;
+      cnt = (int32_t)fl;
+    }
     s_part[tid] = cnt;
     __syncthreads();
     // inclusive Hillis-Steele scan of 256 counts
@@ -328,17 +261,98 @@ __global__ __launch_bounds__(256) void k_gen_emit(DevPtrs<real> d, int buf, int3
       s_part[tid] += add;
       __syncthreads();
     }
-    const int64_t excl = s_part[tid] - cnt;
-    const int64_t chunk = s_part[255];
-    if (j < R.nface && cnt > 0)
-      emit_face<real, DIM>(R, step, j, cnt, R.so + n0 + carry + excl, d.P[buf], d.err);
-    carry += chunk;
+    // a start beyond 2^31 only arises when the capacity check below fails,
+    // and then nothing is emitted
+    if (j < R.nface) d.gen_count[R.fo + j] = (int32_t)(carry + s_part[tid] - cnt);
+    carry += s_part[255];
     __syncthreads();
   }
   if (tid == 0) {
-    d.n_alive[r] = (int32_t)(n0 + total);
-    d.n_gen[r] = (int32_t)total;
+    const int64_t n0 = d.n_alive[r];
+    if (n0 + carry <= R.cap_spec) {
+      d.n_alive[r] = (int32_t)(n0 + carry);
+      d.n_gen[r] = (int32_t)carry;
+    } else {
+      set_error(d.err, kErrCapacity);
+      d.n_gen[r] = 0;
+    }
   }
+}
+
+// Entrant k of face element j (drawing from uniform k * kGenUniforms of the
+// element's stream for this step), written to slot o.
+template <typename real, int DIM>
+__device__ __forceinline__ void emit_one(const RunDev &R, uint32_t step, int32_t j, int32_t k, int64_t o,
+                                         Particles<real> P, int32_t *err) {
+  UStream<real> s(R.key0, R.key1, step, kGen, (uint32_t)j);
+  s.seek((uint32_t)k * kGenUniforms);
+  const real s_inf = (real)R.s_inf, p_branch = (real)R.p_branch, beta = (real)R.beta;
+  // normal velocity: z = beta*u has density ~ z exp(-(z-s)^2), z > 0
+  real z = 0;
+  int att;
+  for (att = 0; att < kMaxGenAttempts; ++att) {
+    const real ub = s(), up = s(), uq = s(), ua = s();
+    const real r = sqrt(-log(up));
+    const real x = (ub < p_branch) ? ((uq < (real)0.5) ? -r : r) : r * cos(two_pi<real>() * uq);
+    z = s_inf + x;
+    if (z > (real)0 && ua < z / (s_inf + fabs(x))) break;
+  }
+  if (att == kMaxGenAttempts) {
+    set_error(err, kErrReject);
+    return;
+  }
+  const real u = z / beta;
+  const real v1 = s(), v2 = s();
+  real t0, t1;
+  box_muller(v1, v2, t0, t1);
+  const int32_t iy = j % R.ny, iz = j / R.ny;
+  const real y = ((real)iy + s()) * (real)R.dy;
+  real zc = 0;
+  if (DIM == 3) zc = ((real)iz + s()) * (real)R.dz;
+  const real ut = s();
+  const real x0 = -(u * (real)R.dt) * ((real)1 - ut);
+  const real st = (real)R.inflow_sqrtT;
+  P.x[o] = x0;
+  P.y[o] = y;
+  if (DIM == 3) P.z[o] = zc;
+  P.u[o] = u;
+  P.v[o] = st * t0;
+  P.w[o] = st * t1;
+}
+
+// The last index in [lo, hi] whose start is <= t (start[lo] <= t).
+__device__ __forceinline__ int32_t last_start_le(const int32_t *start, int32_t lo, int32_t hi, int64_t t) {
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Particle-parallel emission: the inflow runs own consecutive ranges of
+// blocks (gen_blk, sized from each run's largest possible entrant count).
+// A thread takes one entrant t of its run, finds its face element among the
+// starts and writes it behind the run's live particles, in face order.
+template <typename real, int DIM>
+__global__ __launch_bounds__(256) void k_gen_emit(DevPtrs<real> d, int buf, int32_t i0, int32_t i1) {
+  const int32_t b = d.gen_blk[i0] + (int32_t)blockIdx.x;
+  const int32_t i = last_start_le(d.gen_blk, i0, i1 - 1, b);
+  const int r = d.inflow_runs[i];
+  const RunDev &R = d.runs[r];
+  const int32_t total = d.n_gen[r];
+  const int64_t t0 = (int64_t)(b - d.gen_blk[i]) * 256;
+  if (t0 >= total) return;
+  const int32_t *start = d.gen_count + R.fo;
+  // the face elements of the block's first and last entrants bound every
+  // thread's search
+  const int32_t ja = last_start_le(start, 0, R.nface - 1, t0);
+  const int32_t jb = last_start_le(start, ja, R.nface - 1, min<int64_t>(t0 + 255, total - 1));
+  const int64_t t = t0 + threadIdx.x;
+  if (t >= total) return;
+  const int32_t j = last_start_le(start, ja, jb, t);
+  const int64_t n0 = (int64_t)d.n_alive[r] - total;
+  emit_one<real, DIM>(R, *d.step, j, (int32_t)(t - start[j]), R.so + n0 + t, d.P[buf], d.err);
 }
 
 // ---------------------------------------------------------------------------
@@ -2366,9 +2380,9 @@ static void lane_step(const Geometry &g, const LaneRange &L, const DevPtrs<real>
   const int n_runs = L.r1 - L.r0;
   const int32_t n_tiles = L.t1 - L.t0;
   if (L.i1 > L.i0) {
-    TIMED(kKGenCount, hipLaunchKernelGGL(k_gen_count<real>, dim3(grid_for(L.f1 - L.f0)), dim3(256), 0, s, d, L.f0,
-                                         L.f1));
-    TIMED(kKGenEmit, hipLaunchKernelGGL((k_gen_emit<real, DIM>), dim3(L.i1 - L.i0), dim3(256), 0, s, d, buf, L.i0));
+    TIMED(kKGenCount, hipLaunchKernelGGL(k_gen_count<real>, dim3(L.i1 - L.i0), dim3(256), 0, s, d, L.i0));
+    TIMED(kKGenEmit, hipLaunchKernelGGL((k_gen_emit<real, DIM>), dim3(L.g1 - L.g0), dim3(256), 0, s, d, buf, L.i0,
+                                        L.i1));
   }
   const size_t lds = (size_t)kWavesPerBlock * g.dstride * sizeof(uint32_t);
   const int wblocks = (n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;

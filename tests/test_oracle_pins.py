@@ -399,6 +399,14 @@ def test_inflow_velocity_distributions(oracle_lib, mach):
     # placed upstream so that a full step carries it in at a uniform time
     frac = 1 + st[0] / (st[3] * rs.dt)
     assert (st[0] <= 0).all() and stats.kstest(frac, "uniform").pvalue > 1e-3
+    # entrants are independent draws: no two alike, and successive entrants
+    # (mostly of one face element) uncorrelated
+    n = st.shape[1]
+    assert len(np.unique(st[3])) == n and len(np.unique(st[4])) == n
+    yf = np.mod(st[1] * rs.ny / rs.ly, 1.0)        # offset within the face element
+    for name, q in (("u", st[3]), ("v", st[4]), ("y offset", yf)):
+        r1 = np.corrcoef(q[:-1], q[1:])[0, 1]
+        assert abs(r1) < 4.5 / math.sqrt(n), (name, r1)
 
 
 def test_collisionless_impulsive_start_density(oracle_lib):
