@@ -292,7 +292,9 @@ def main():
     ap.add_argument("--tile-chunks", type=int, default=0)
     ap.add_argument("--workload", choices=("ensemble_box", "body3d", "channel", "uneven"), default="ensemble_box",
                     help="ensemble_box (the benchmark); body3d, channel or uneven (informational)")
-    ap.add_argument("--collide-mode", type=int, default=0)
+    ap.add_argument("--collide-mode", type=int, default=0,
+                    help="interaction work item: 0 auto, 1 a lane per cell, 2 a block per cell, "
+                         "3 a wavefront per cell")
     ap.add_argument("--plain-runs", type=int, default=2)
     ap.add_argument("--plain-steps", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
