@@ -1029,6 +1029,11 @@ dsmc_status dsmc_get_lcr(dsmc_ctx *c, int32_t run, int32_t *lcr, int32_t *cell, 
   if (!st) st = sync_ctx(c);
   if (!st && start)
     for (int i = 0; i < R.nc + 2; ++i) start[i] = s[i];
+  // without the marks of particles the wall queue moved
+  for (int64_t i = 0; !st && i < ns; ++i) {
+    if (lcr) lcr[i] &= kSlotMask;
+    if (cell) cell[i] &= kSlotMask;
+  }
   return st;
 }
 

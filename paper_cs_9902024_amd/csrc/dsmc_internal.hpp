@@ -21,6 +21,13 @@ constexpr int kDigitBits = 11;             // indexing digit: 2048 bins per pass
 constexpr int kDigits = 1 << kDigitBits;
 constexpr int kMaxWallHits = 64;           // wall interactions per particle per step
 constexpr int kMaxGenAttempts = 1000;      // inflow normal-velocity rejection
+// Motion writes only the new cell of a particle in free flight: Interaction,
+// which gathers every particle anyway, applies its flight (the same
+// expression) as it permutes the particles.  A particle that met a face was
+// moved in place by the wall queue: its cell, and so its LCR entry, carries
+// kMovedBit; the low 31 bits are the cell and the run-local slot.
+constexpr uint32_t kMovedBit = 0x80000000u;
+constexpr int32_t kSlotMask = 0x7FFFFFFF;
 // Each inflow particle draws from its own stretch of its face element's
 // stream, from uniform k * kGenUniforms for particle k, so particles do not
 // depend on one another's rejections and are generated in parallel.  The

@@ -627,12 +627,13 @@ __device__ __forceinline__ void store4(real *p, int64_t i, const real (&o)[4]) {
 }
 
 // One wavefront per tile of tile_chunks*64 consecutive slots of one run.
-// Each round covers 256 slots, four consecutive ones per lane, moved with
-// 128-bit loads and stores (only a run's last, partial round goes slot by
-// slot).  A particle that reaches no face this step is moved here; the others
-// go to the tile's wall queue (k_motion_walls).  The new cell of every free
-// particle is counted in the tile's histogram of the first indexing digit,
-// kept in wave-private LDS.
+// Each round covers 256 slots, four consecutive ones per lane, read with
+// 128-bit loads (only a run's last, partial round goes slot by slot).  For a
+// particle that reaches no face this step only its new cell is written (its
+// flight is applied by Interaction, which moves every particle to its sorted
+// place anyway); the others go to the tile's wall queue (k_motion_walls).
+// The new cell of every free particle is counted in the tile's histogram of
+// the first indexing digit, kept in wave-private LDS.
 template <typename real, int DIM, bool SINGLE, bool OBST>
 __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_t t0, int32_t t1, int64_t tile,
                                                 int dstride, int shift0) {
@@ -699,7 +700,6 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
         }
       }
     }
-    real ox[4], oy[4], oz[4];
     int32_t oc[4];
     uint32_t key[4];
     bool fast[4];
@@ -711,9 +711,6 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
       real out[3];
       fast[e] = act[e] && free_flight<real, DIM>(dt, Lr, pos, vel, out);
       if (solid && fast[e]) fast[e] = !near_solid<real, DIM>(pos, out, slo, shi);
-      ox[e] = fast[e] ? out[0] : px[e];
-      oy[e] = fast[e] ? out[1] : py[e];
-      oz[e] = (DIM == 3 && fast[e]) ? out[2] : (DIM == 3 ? pz[e] : (real)0);
       int32_t c = 0;
       if (fast[e]) {
         const int32_t ix = axis_index(out[0], inv[0], nx);
@@ -724,21 +721,13 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
       oc[e] = c;
       key[e] = SINGLE ? (uint32_t)c : (((uint32_t)c >> shift0) & (kDigits - 1));
     }
-    // (a queued particle's position and cell are rewritten by k_motion_walls)
+    // (a queued particle's cell is rewritten by k_motion_walls)
     if (full) {
-      store4(X, i0, ox);
-      store4(Y, i0, oy);
-      if (DIM == 3) store4(Z, i0, oz);
       *reinterpret_cast<int4 *>(cell + i0) = make_int4(oc[0], oc[1], oc[2], oc[3]);
     } else {
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        if (act[e]) {
-          X[i0 + e] = ox[e];
-          Y[i0 + e] = oy[e];
-          if (DIM == 3) Z[i0 + e] = oz[e];
-          cell[i0 + e] = oc[e];
-        }
+        if (act[e]) cell[i0 + e] = oc[e];
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) histogram_add(h, key[e], fast[e]);
@@ -795,7 +784,7 @@ __global__ __launch_bounds__(256) void k_motion_walls(DevPtrs<real> d, int buf, 
         P.v[gs] = v3[1];
         if (DIM == 3 || reemit) P.w[gs] = v3[2];
       }
-      d.cell[gs] = c;
+      d.cell[gs] = (int32_t)((uint32_t)c | kMovedBit);  // moved here, not by Interaction
       key = SINGLE ? (uint32_t)c : (((uint32_t)c >> shift0) & (kDigits - 1));
     }
     histogram_add(Mt, key, active);
@@ -876,8 +865,8 @@ __global__ __launch_bounds__(256) void k_digcount(IndexArgs a, int use_n_alive) 
     for (int64_t b = begin; b < end; b += kWave) {
       const int64_t loc = b + lane;
       if (loc < end) {
-        const int32_t v = a.in ? a.in[R.so + loc] : (int32_t)loc;
-        atomicAdd(&h[digit_of(a.cell[R.so + v], a.shift, single)], 1u);
+        const int32_t v = (a.in ? a.in[R.so + loc] : (int32_t)loc) & kSlotMask;
+        atomicAdd(&h[digit_of(a.cell[R.so + v] & kSlotMask, a.shift, single)], 1u);
       }
     }
   }
@@ -1217,8 +1206,9 @@ __global__ __launch_bounds__(256) void k_scatter(IndexArgs a) {
     int32_t v[U], bin[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      v[q] = CARRIED ? nv[q] : (int32_t)(b + q * kWave + lane);
-      bin[q] = nb[q];
+      // a first pass reads Motion's cells: their moved bit goes with the slot
+      v[q] = CARRIED ? nv[q] : (int32_t)(b + q * kWave + lane) | (nb[q] & ~kSlotMask);
+      bin[q] = CARRIED ? nb[q] : nb[q] & kSlotMask;
     }
     SCATTER_LOAD(b + CH);
 #pragma unroll
@@ -1241,13 +1231,14 @@ __global__ __launch_bounds__(256) void k_scatter(IndexArgs a) {
     for (int q = 0; q < U; ++q) {
       const int64_t loc = full_end + q * kWave + lane;
       const bool act = loc < end;
-      const uint32_t key = act ? digit_of(nb[q], shift, single) : kNoDigit;
+      const int32_t bn = CARRIED ? nb[q] : nb[q] & kSlotMask;
+      const uint32_t key = act ? digit_of(bn, shift, single) : kNoDigit;
       uint32_t rank, cnt;
       rank_in_wave(key, __builtin_amdgcn_ballot_w64(act), rank, cnt);
       if (act) {
         const uint32_t prior = cursor[key];
-        out[prior + rank] = CARRIED ? nv[q] : (int32_t)loc;
-        if (KOUT) kout[prior + rank] = nb[q];
+        out[prior + rank] = CARRIED ? nv[q] : (int32_t)loc | (nb[q] & ~kSlotMask);
+        if (KOUT) kout[prior + rank] = bn;
         if (rank == cnt - 1) cursor[key] = prior + cnt;
       }
       wave_sync();
@@ -1478,8 +1469,17 @@ __device__ __forceinline__ void sample_cell_wave(const real *u, const real *v, c
     for (int f = 0; f < kFields; ++f) out[f] = s[f];
 }
 
-// Gather particles [b, b+n) of a run (sorted positions) through LCR: positions
-// to P', velocities to LDS (or to P' when to_lds is false).
+// A gathered coordinate at the end of the step's flight: Motion left a free
+// particle where it began (its entry lacks kMovedBit), and its flight is the
+// same expression as Motion's test used.
+template <typename real>
+__device__ __forceinline__ real flown(real p, real v, real dt, int32_t entry) {
+  return entry < 0 ? p : p + v * dt;
+}
+
+// Gather particles [b, b+n) of a run (sorted positions) through LCR, moving
+// the free ones: positions to P', velocities to LDS (or to P' when to_lds is
+// false).
 template <typename real, int DIM>
 __device__ __forceinline__ void gather_through_lcr(const RunDev &R, const int32_t *lcr, const Particles<real> &A,
                                                    const Particles<real> &B, int64_t b, int64_t n, bool to_lds,
@@ -1489,6 +1489,7 @@ __device__ __forceinline__ void gather_through_lcr(const RunDev &R, const int32_
   // reads clamped into [0, n) instead of masked: no branch whose join would
   // make the compiler wait for each load before issuing the next
   const int32_t *__restrict__ lp = lcr + R.so + b;
+  const real dt = in_precision<real>(R.dt, R.dt_f);
   for (int64_t k0 = 0; k0 < n; k0 += U * kWave) {
     int32_t l[U];
 #pragma unroll
@@ -1496,7 +1497,7 @@ __device__ __forceinline__ void gather_through_lcr(const RunDev &R, const int32_
     real x[U], y[U], z[U], uu[U], vv[U], ww[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      const int64_t src = R.so + l[q];
+      const int64_t src = R.so + (l[q] & kSlotMask);
       x[q] = A.x[src];
       y[q] = A.y[src];
       if (DIM == 3) z[q] = A.z[src];
@@ -1509,9 +1510,9 @@ __device__ __forceinline__ void gather_through_lcr(const RunDev &R, const int32_
       const int64_t k = k0 + q * kWave + lane;
       if (k >= n) continue;
       const int64_t dst = R.so + b + k;
-      B.x[dst] = x[q];
-      B.y[dst] = y[q];
-      if (DIM == 3) B.z[dst] = z[q];
+      B.x[dst] = flown(x[q], uu[q], dt, l[q]);
+      B.y[dst] = flown(y[q], vv[q], dt, l[q]);
+      if (DIM == 3) B.z[dst] = flown(z[q], ww[q], dt, l[q]);
       if (to_lds) {
         su[k] = uu[q];
         sv[k] = vv[q];
@@ -1801,14 +1802,17 @@ __global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, 
   // gather through LCR: positions to P', velocities to LDS (or P')
   {
     constexpr int U = 4;
+    const real dt = in_precision<real>(R.dt, R.dt_f);
     for (int64_t k0 = 0; k0 < n; k0 += U * 256) {
       int64_t sidx[U];
+      int32_t ent[U];
       bool ok[U];
 #pragma unroll
       for (int q = 0; q < U; ++q) {
         const int64_t k = k0 + q * 256 + tid;
         ok[q] = k < n;
-        sidx[q] = ok[q] ? R.so + d.lcr[R.so + b0 + k] : R.so;
+        ent[q] = ok[q] ? d.lcr[R.so + b0 + k] : 0;
+        sidx[q] = R.so + (ent[q] & kSlotMask);
       }
       real x[U], y[U], z[U], uu[U], vv[U], ww[U];
 #pragma unroll
@@ -1827,9 +1831,9 @@ __global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, 
         if (!ok[q]) continue;
         const int64_t k = k0 + q * 256 + tid;
         const int64_t dst = R.so + b0 + k;
-        B.x[dst] = x[q];
-        B.y[dst] = y[q];
-        if (DIM == 3) B.z[dst] = z[q];
+        B.x[dst] = flown(x[q], uu[q], dt, ent[q]);
+        B.y[dst] = flown(y[q], vv[q], dt, ent[q]);
+        if (DIM == 3) B.z[dst] = flown(z[q], ww[q], dt, ent[q]);
         if (in_lds) {
           su[k] = uu[q];
           sv[k] = vv[q];
@@ -1981,7 +1985,7 @@ struct PipeMeta {
   int64_t so, b0, n, gc;
   int32_t c;
   uint32_t ncoll;
-  float gm, rem;
+  float gm, rem, dt;
   RunView rv;
 };
 
@@ -1992,8 +1996,9 @@ struct PipeRegs {
 };
 
 // LCR entries (run-local slots) of the particles this thread handles in an
-// item that fits in LDS; beyond n any valid entry (unused).  Unconditional
-// loads: no branch whose join would make the compiler wait for them.
+// item that fits in LDS; beyond n an entry of the item (unused), and slot 0
+// of the run for an empty or unused item.  Unconditional loads: no branch
+// whose join would make the compiler wait for them.
 __device__ __forceinline__ void pipe_lcr(const int32_t *lcr, const PipeMeta &m, bool valid,
                                          int32_t (&l)[kPipeChunks]) {
   const bool use = valid && m.n > 0 && m.n <= kCollideCapF32;
@@ -2003,7 +2008,8 @@ __device__ __forceinline__ void pipe_lcr(const int32_t *lcr, const PipeMeta &m, 
 #pragma unroll
   for (int q = 0; q < kPipeChunks; ++q) {
     const int64_t k = q * 256 + tid;
-    l[q] = lp[k < lim ? k : lim];
+    const int32_t e = lp[k < lim ? k : lim];
+    l[q] = use ? e : 0;
   }
 }
 
@@ -2017,7 +2023,7 @@ __device__ __forceinline__ void pipe_gather(const int32_t *lcr, const Particles<
   if (m.n <= kCollideCapF32) {
 #pragma unroll
     for (int q = 0; q < kPipeChunks; ++q) {
-      const int64_t sidx = m.so + pr.l[q];  // a valid slot beyond n (unused)
+      const int64_t sidx = m.so + (pr.l[q] & kSlotMask);  // a valid slot beyond n (unused)
       pr.x[q] = A.x[sidx];
       pr.y[q] = A.y[sidx];
       if (DIM == 3) pr.z[q] = A.z[sidx];
@@ -2027,14 +2033,16 @@ __device__ __forceinline__ void pipe_gather(const int32_t *lcr, const Particles<
     }
   } else {
     for (int64_t k = tid; k < m.n; k += 256) {
-      const int64_t sidx = m.so + lcr[m.so + m.b0 + k];
+      const int32_t e = lcr[m.so + m.b0 + k];
+      const int64_t sidx = m.so + (e & kSlotMask);
       const int64_t dst = m.so + m.b0 + k;
-      B.x[dst] = A.x[sidx];
-      B.y[dst] = A.y[sidx];
-      if (DIM == 3) B.z[dst] = A.z[sidx];
-      B.u[dst] = A.u[sidx];
-      B.v[dst] = A.v[sidx];
-      B.w[dst] = A.w[sidx];
+      const float u = A.u[sidx], v = A.v[sidx], w = A.w[sidx];
+      B.x[dst] = flown(A.x[sidx], u, m.dt, e);
+      B.y[dst] = flown(A.y[sidx], v, m.dt, e);
+      if (DIM == 3) B.z[dst] = flown(A.z[sidx], w, m.dt, e);
+      B.u[dst] = u;
+      B.v[dst] = v;
+      B.w[dst] = w;
     }
   }
 }
@@ -2050,9 +2058,9 @@ __device__ __forceinline__ void pipe_place(const Particles<float> &B, const Pipe
     const int64_t k = q * 256 + tid;
     if (k < m.n) {
       const int64_t dst = m.so + m.b0 + k;
-      B.x[dst] = pr.x[q];
-      B.y[dst] = pr.y[q];
-      if (DIM == 3) B.z[dst] = pr.z[q];
+      B.x[dst] = flown(pr.x[q], pr.u[q], m.dt, pr.l[q]);
+      B.y[dst] = flown(pr.y[q], pr.v[q], m.dt, pr.l[q]);
+      if (DIM == 3) B.z[dst] = flown(pr.z[q], pr.w[q], m.dt, pr.l[q]);
       su[k] = pr.u[q];
       sv[k] = pr.v[q];
       sw[k] = pr.w[q];
@@ -2153,6 +2161,7 @@ __global__ __launch_bounds__(256) void k_collide_pipe(DevPtrs<float> d, int src,
     m.ncoll = d.ncoll[m.gc];
     m.gm = d.gmax[m.gc];
     m.rem = d.rem_c[m.gc];
+    m.dt = R.dt_f;
     m.rv.key0 = R.key0;
     m.rv.key1 = R.key1;
     m.rv.hs = R.hs;
