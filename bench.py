@@ -61,22 +61,23 @@ WORKLOAD_TEXT = {
 def algorithmic_bytes(kind: str, n_particles: int, n_cells: int, dim: int, es: int) -> float:
     """Bytes a kernel must move per launch (each byte once, no re-reads).
 
-    motion         reads the position and the in-plane velocity (2*dim*es),
-                   writes the cell index (4); the free flight itself is
-                   applied when Interaction moves the particle to P'
+    motion         reads the cell the last Interaction found for the
+                   particle's flight (4); only particles generated in the
+                   step (none in a closed box) are read whole and tested here
     scatter        reads the cell index (4), writes the LCR entry (4)
     collide_cells  (Interaction fused with the flight, the permutation
-    collide_waves   P' = P[LCR] and Sampling) reads the LCR entry (4) and the
-    collide_lanes   particle (dim+3)*es, writes it to P'; per cell the two bin
+    collide_waves   P' = P[LCR], Sampling and the next flight's test) reads
+    collide_lanes   the LCR entry (4) and the particle (dim+3)*es, writes it to
+                   P' and its next flight cell (4); per cell the two bin
                    starts (4), remainder and (sigma c_r)_max read and written
                    (4*es) and the collision counter read and written (8)
     """
     if kind == "motion":
-        return n_particles * (2 * dim * es + 4)
+        return n_particles * 4
     if kind == "scatter":
         return n_particles * 8
     if kind in ("collide_cells", "collide_waves", "collide_lanes"):
-        return n_particles * (4 + 2 * (dim + 3) * es) + n_cells * (4 + 4 * es + 8)
+        return n_particles * (8 + 2 * (dim + 3) * es) + n_cells * (4 + 4 * es + 8)
     return 0.0
 
 

@@ -73,7 +73,7 @@ dsmc_status validate(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_optio
     if (s.nx < 1 || s.ny < 1 || s.nz < 1 || (dim == 2 && s.nz != 1))
       return fail(msg, DSMC_EINVAL, "run %d: bad grid", r);
     const int64_t nc = (int64_t)s.nx * s.ny * s.nz;
-    if (nc + 2 >= ((int64_t)1 << 31)) return fail(msg, DSMC_EINVAL, "run %d: too many cells", r);
+    if (nc + 2 >= ((int64_t)1 << 30)) return fail(msg, DSMC_EINVAL, "run %d: too many cells", r);  // kQueueBit
     if (!(s.lx > 0) || !(s.ly > 0) || !(s.lz > 0)) return fail(msg, DSMC_EINVAL, "run %d: bad box size", r);
     if (!(s.dt > 0) || !std::isfinite(s.dt)) return fail(msg, DSMC_EINVAL, "run %d: dt must be > 0", r);
     if (!(s.fnum_sigma >= 0)) return fail(msg, DSMC_EINVAL, "run %d: fnum_sigma must be >= 0", r);
@@ -209,6 +209,8 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
       else if (opt.collide_mode == 2) R.coll_mode = 2;
       else if (opt.collide_mode == 3) R.coll_mode = 1;
       else R.coll_mode = ppc >= kCrowdedPpc ? 2 : (ppc >= kWavePpc ? 1 : 0);
+      // Interaction's look-ahead of the next flight (every mode)
+      R.ahead = 1;
       // lane mode: as many cells per wavefront (<= 64) as fit 3/4 of the LDS stage
       const int cap = g.fp64 ? kLaneCapF64 : kLaneCapF32;
       R.lane_cells = (int32_t)std::max(1.0, std::min(64.0, std::floor(0.75 * cap / std::max(ppc, 1.0))));
@@ -966,6 +968,11 @@ dsmc_status set_state_t(dsmc_ctx *c, const DevPtrs<real> &d, int32_t run, const 
   }
   const int32_t nn = (int32_t)n;
   st = check_hip(c, hipMemcpyAsync(d.n_alive + run, &nn, 4, hipMemcpyHostToDevice, c->stream), "upload n");
+  if (!st) {
+    // the next Motion reads these particles' flight cells
+    launch_next_cells<real>(c->plan.g, d, c->buf, R.so, n, c->stream);
+    st = check_hip(c, hipGetLastError(), "launch(next cells)");
+  }
   if (!st) st = sync_ctx(c);
   c->sorted = false;
   return st;
@@ -1014,7 +1021,6 @@ dsmc_status dsmc_get_lcr(dsmc_ctx *c, int32_t run, int32_t *lcr, int32_t *cell, 
   const bool f64 = c->plan.g.fp64;
   const int32_t *d_ns = f64 ? c->dd.n_sorted : c->df.n_sorted;
   const int32_t *d_lcr = f64 ? c->dd.lcr : c->df.lcr;
-  const int32_t *d_cell = f64 ? c->dd.cell : c->df.cell;
   const uint32_t *d_start = f64 ? c->dd.bin_start : c->df.bin_start;
   int32_t ns = 0;
   dsmc_status st = download<int32_t>(c, &ns, d_ns + run, 1);
@@ -1022,19 +1028,28 @@ dsmc_status dsmc_get_lcr(dsmc_ctx *c, int32_t run, int32_t *lcr, int32_t *cell, 
   if (st) return st;
   *n = ns;
   if (cap < ns) return set_err(c, DSMC_ESIZE, "output too small");
-  if (lcr && ns) st = download<int32_t>(c, lcr, d_lcr + R.so, ns);
-  if (!st && cell && ns) st = download<int32_t>(c, cell, d_cell + R.so, ns);
+  std::vector<int32_t> l((size_t)std::max(ns, 1));
   std::vector<uint32_t> s((size_t)R.nc + 2);
-  if (!st && start) st = download<uint32_t>(c, s.data(), d_start + R.bo, (size_t)R.nc + 2);
+  if (ns) st = download<int32_t>(c, l.data(), d_lcr + R.so, ns);
+  if (!st) st = download<uint32_t>(c, s.data(), d_start + R.bo, (size_t)R.nc + 2);
   if (!st) st = sync_ctx(c);
-  if (!st && start)
+  if (st) return st;
+  // the slots without the marks of particles the wall queue moved
+  for (int64_t p = 0; p < ns; ++p) l[p] &= kSlotMask;
+  if (lcr)
+    for (int64_t p = 0; p < ns; ++p) lcr[p] = l[p];
+  if (start)
     for (int i = 0; i < R.nc + 2; ++i) start[i] = s[i];
-  // without the marks of particles the wall queue moved
-  for (int64_t i = 0; !st && i < ns; ++i) {
-    if (lcr) lcr[i] &= kSlotMask;
-    if (cell) cell[i] &= kSlotMask;
+  if (cell) {
+    // the cell array now holds the next step's flight cells: each slot's cell
+    // of this step is the bin whose range of LCR holds it (nc = DEAD)
+    for (int32_t b = 0; b <= R.nc; ++b) {
+      const int64_t hi = b < R.nc ? (int64_t)s[b + 1] : ns;
+      for (int64_t p = s[b]; p < hi; ++p)
+        if (l[p] < ns) cell[l[p]] = b;
+    }
   }
-  return st;
+  return DSMC_OK;
 }
 
 dsmc_status dsmc_get_cell_state(dsmc_ctx *c, int32_t run, double *rem, double *gmax, int64_t *ncoll) {

@@ -28,6 +28,12 @@ constexpr int kMaxGenAttempts = 1000;      // inflow normal-velocity rejection
 // kMovedBit; the low 31 bits are the cell and the run-local slot.
 constexpr uint32_t kMovedBit = 0x80000000u;
 constexpr int32_t kSlotMask = 0x7FFFFFFF;
+// Interaction also runs the next step's free-flight test on each particle it
+// writes to P' (final position and velocity) and stores the cell the flight
+// ends in, or kQueueBit when the particle must take the full flight (a face,
+// or near a body).  Motion then reads that cell instead of the particle,
+// except for particles generated since, which it tests itself.
+constexpr int32_t kQueueBit = 0x40000000;
 // Each inflow particle draws from its own stretch of its face element's
 // stream, from uniform k * kGenUniforms for particle k, so particles do not
 // depend on one another's rejections and are generated in parallel.  The
@@ -75,6 +81,8 @@ struct RunDev {
   int32_t coll_mode; // interaction work item: 0 lane_cells cells (a lane each), 1 one cell per
                      // wavefront, 2 one cell per block
   int32_t lane_cells;
+  int32_t ahead;     // 1: Interaction writes each particle's next flight cell (kQueueBit) and
+                     // Motion reads it; 0: Motion tests every particle itself
   int32_t bc[6];
   uint32_t key0, key1;   // Philox key: run id, seed
   double L[3], inv_d[3];
@@ -219,6 +227,11 @@ struct Prof {
 // ---------------------------------------------------------------------------
 template <typename real>
 void launch_init(const Geometry &g, const DevPtrs<real> &d, hipStream_t s);
+// The flight cells (see kQueueBit) of the live particles in slots
+// [so, so + n) of buffer buf: after the initial fill, or after a run's state
+// is replaced.
+template <typename real>
+void launch_next_cells(const Geometry &g, const DevPtrs<real> &d, int buf, int64_t so, int64_t n, hipStream_t s);
 template <typename real>
 void launch_step(const Geometry &g, const DevPtrs<real> &d, int buf, hipStream_t s, const LaneStreams *lanes,
                  const Prof *prof);

@@ -597,6 +597,46 @@ __device__ __forceinline__ bool free_flight(real dt, const real (&L)[3], const r
   return inside;
 }
 
+// A run's constants for Motion's test, in the state precision (rounded on
+// the host), copied to registers once per loop: read through the run table
+// inside a loop that stores, they would be read again for every particle.
+template <typename real>
+struct Flight {
+  real dt, L[3], inv[3], slo[3], shi[3];
+  int32_t n[3];
+  bool solid;
+  __device__ __forceinline__ explicit Flight(const RunDev &R) {
+    dt = in_precision<real>(R.dt, R.dt_f);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      L[a] = in_precision<real>(R.L[a], R.L_f[a]);
+      inv[a] = in_precision<real>(R.inv_d[a], R.inv_f[a]);
+      slo[a] = in_precision<real>(R.slo[a], R.slo_f[a]);
+      shi[a] = in_precision<real>(R.shi[a], R.shi_f[a]);
+    }
+    n[0] = R.nx;
+    n[1] = R.ny;
+    n[2] = R.nz;
+    solid = R.has_solid;
+  }
+};
+
+// Motion's test for one particle: the cell its free flight ends in, or
+// kQueueBit when it must take the full flight (it reaches a face, or passes
+// near a body).  Motion and Interaction's look-ahead both call this, so they
+// decide identically.
+template <typename real, int DIM>
+__device__ __forceinline__ int32_t flight_cell(const Flight<real> &F, const real (&pos)[3], const real (&vel)[3]) {
+  real out[3];
+  bool fast = free_flight<real, DIM>(F.dt, F.L, pos, vel, out);
+  if (F.solid && fast) fast = !near_solid<real, DIM>(pos, out, F.slo, F.shi);
+  if (!fast) return kQueueBit;
+  const int32_t ix = axis_index(out[0], F.inv[0], F.n[0]);
+  const int32_t iy = axis_index(out[1], F.inv[1], F.n[1]);
+  const int32_t iz = (DIM == 3) ? axis_index(out[2], F.inv[2], F.n[2]) : 0;
+  return (iz * F.n[1] + iy) * F.n[0] + ix;
+}
+
 // Adds 1 per active lane to h[key]: one LDS atomic per run of equal keys in
 // consecutive active lanes (an inactive lane ends a run).
 __device__ __forceinline__ void histogram_add(uint32_t *h, uint32_t key, bool active) {
@@ -628,12 +668,14 @@ __device__ __forceinline__ void store4(real *p, int64_t i, const real (&o)[4]) {
 
 // One wavefront per tile of tile_chunks*64 consecutive slots of one run.
 // Each round covers 256 slots, four consecutive ones per lane, read with
-// 128-bit loads (only a run's last, partial round goes slot by slot).  For a
-// particle that reaches no face this step only its new cell is written (its
-// flight is applied by Interaction, which moves every particle to its sorted
-// place anyway); the others go to the tile's wall queue (k_motion_walls).
-// The new cell of every free particle is counted in the tile's histogram of
-// the first indexing digit, kept in wave-private LDS.
+// 128-bit loads (only a run's last, partial round goes slot by slot).  The
+// particles written by the last Interaction already have their cell (or the
+// queue mark) in place: for them Motion reads only that.  The others (those
+// generated this step) are tested here and their cell written.  No position
+// is written: Interaction applies the flight when it moves every particle to
+// its sorted place anyway.  Particles that reach a face go to the tile's wall
+// queue (k_motion_walls).  The new cell of every free particle is counted in
+// the tile's histogram of the first indexing digit, kept in wave-private LDS.
 template <typename real, int DIM, bool SINGLE, bool OBST>
 __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_t t0, int32_t t1, int64_t tile,
                                                 int dstride, int shift0) {
@@ -649,6 +691,7 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
   for (int q = lane; q < D; q += kWave) h[q] = 0;
   wave_sync();
   const int64_t n = d.n_alive[r];
+  const int64_t npre = R.ahead ? n - d.n_gen[r] : 0;  // cells in place from the last Interaction
   const int64_t begin = tl * tile, end = min(begin + tile, n);
   real *__restrict__ X = d.P[buf].x + R.so;
   real *__restrict__ Y = d.P[buf].y + R.so;
@@ -659,24 +702,30 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
   int32_t *__restrict__ cell = d.cell + R.so;
   uint32_t *__restrict__ wq = d.wallq + (int64_t)t * tile;  // this tile's queue segment
   uint32_t qn = 0;
-  // the run's constants, rounded to the state precision on the host
-  const real dt = in_precision<real>(R.dt, R.dt_f);
-  const real Lr[3] = {in_precision<real>(R.L[0], R.L_f[0]), in_precision<real>(R.L[1], R.L_f[1]),
-                      in_precision<real>(R.L[2], R.L_f[2])};
-  const real inv[3] = {in_precision<real>(R.inv_d[0], R.inv_f[0]), in_precision<real>(R.inv_d[1], R.inv_f[1]),
-                       in_precision<real>(R.inv_d[2], R.inv_f[2])};
-  const int32_t nx = R.nx, ny = R.ny, nz = R.nz;
-  // the solid cells' bounding box, widened by two cells, in coordinates
-  const bool solid = OBST && R.has_solid;
-  const real slo[3] = {in_precision<real>(R.slo[0], R.slo_f[0]), in_precision<real>(R.slo[1], R.slo_f[1]),
-                       in_precision<real>(R.slo[2], R.slo_f[2])};
-  const real shi[3] = {in_precision<real>(R.shi[0], R.shi_f[0]), in_precision<real>(R.shi[1], R.shi_f[1]),
-                       in_precision<real>(R.shi[2], R.shi_f[2])};
+  Flight<real> F(R);
+  F.solid = OBST && R.has_solid;
   for (int64_t b = begin; b < end; b += 4 * kWave) {
     const int64_t i0 = b + 4 * lane;
     const bool full = b + 4 * kWave <= end;  // wave-uniform
-    real px[4], py[4], pz[4], vx[4], vy[4], vz[4];
+    int32_t oc[4];
+    uint32_t key[4];
+    bool fast[4];
     bool act[4];
+    if (b + 4 * kWave <= npre) {
+      // every cell of the round is in place
+      const int4 c4 = *reinterpret_cast<const int4 *>(cell + i0);
+      oc[0] = c4.x;
+      oc[1] = c4.y;
+      oc[2] = c4.z;
+      oc[3] = c4.w;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        act[e] = true;
+        fast[e] = !(oc[e] & kQueueBit);
+        key[e] = SINGLE ? (uint32_t)oc[e] : (((uint32_t)oc[e] >> shift0) & (kDigits - 1));
+      }
+    } else {
+    real px[4], py[4], pz[4], vx[4], vy[4], vz[4];
     if (full) {
       load4(X, i0, px);
       load4(Y, i0, py);
@@ -700,24 +749,13 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
         }
       }
     }
-    int32_t oc[4];
-    uint32_t key[4];
-    bool fast[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       // in 2-D Motion never reads w: only a diffuse re-emission sets it
       const real pos[3] = {px[e], py[e], DIM == 3 ? pz[e] : (real)0};
       const real vel[3] = {vx[e], vy[e], DIM == 3 ? vz[e] : (real)0};
-      real out[3];
-      fast[e] = act[e] && free_flight<real, DIM>(dt, Lr, pos, vel, out);
-      if (solid && fast[e]) fast[e] = !near_solid<real, DIM>(pos, out, slo, shi);
-      int32_t c = 0;
-      if (fast[e]) {
-        const int32_t ix = axis_index(out[0], inv[0], nx);
-        const int32_t iy = axis_index(out[1], inv[1], ny);
-        const int32_t iz = (DIM == 3) ? axis_index(out[2], inv[2], nz) : 0;
-        c = (iz * ny + iy) * nx + ix;
-      }
+      const int32_t c = act[e] ? flight_cell<real, DIM>(F, pos, vel) : kQueueBit;
+      fast[e] = act[e] && !(c & kQueueBit);
       oc[e] = c;
       key[e] = SINGLE ? (uint32_t)c : (((uint32_t)c >> shift0) & (kDigits - 1));
     }
@@ -728,6 +766,7 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
 #pragma unroll
       for (int e = 0; e < 4; ++e)
         if (act[e]) cell[i0 + e] = oc[e];
+    }
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) histogram_add(h, key[e], fast[e]);
@@ -1526,6 +1565,74 @@ __device__ __forceinline__ void gather_through_lcr(const RunDev &R, const int32_
   }
 }
 
+// The LDS case of gather_through_lcr for a stage of at most NH*64 particles,
+// also keeping each lane's final positions (particle j*64 + lane at index j,
+// constant indices: the chunk loop is unrolled) for the look-ahead.
+template <typename real, int DIM, int NH>
+__device__ __forceinline__ void gather_hold(const RunDev &R, const int32_t *lcr, const Particles<real> &A,
+                                            const Particles<real> &B, int64_t b, int64_t n, real *su, real *sv,
+                                            real *sw, real (&hx)[NH], real (&hy)[NH], real (&hz)[NH]) {
+  const int lane = threadIdx.x & 63;
+  constexpr int U = 4;
+  static_assert(NH % U == 0, "whole chunks");
+  const int32_t *__restrict__ lp = lcr + R.so + b;
+  const real dt = in_precision<real>(R.dt, R.dt_f);
+#pragma unroll
+  for (int ch = 0; ch < NH / U; ++ch) {
+    const int64_t k0 = (int64_t)ch * U * kWave;
+    if (k0 >= n) break;
+    int32_t l[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) l[q] = lp[min(k0 + q * kWave + lane, n - 1)];
+    real x[U], y[U], z[U], uu[U], vv[U], ww[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int64_t src = R.so + (l[q] & kSlotMask);
+      x[q] = A.x[src];
+      y[q] = A.y[src];
+      if (DIM == 3) z[q] = A.z[src];
+      uu[q] = A.u[src];
+      vv[q] = A.v[src];
+      ww[q] = A.w[src];
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int64_t k = k0 + q * kWave + lane;
+      const int j = ch * U + q;
+      hx[j] = flown(x[q], uu[q], dt, l[q]);
+      hy[j] = flown(y[q], vv[q], dt, l[q]);
+      hz[j] = DIM == 3 ? flown(z[q], ww[q], dt, l[q]) : (real)0;
+      if (k >= n) continue;
+      const int64_t dst = R.so + b + k;
+      B.x[dst] = hx[j];
+      B.y[dst] = hy[j];
+      if (DIM == 3) B.z[dst] = hz[j];
+      su[k] = uu[q];
+      sv[k] = vv[q];
+      sw[k] = ww[q];
+    }
+  }
+}
+
+// The look-ahead (next_cells) from the positions gather_hold kept.
+template <typename real, int DIM, int NH>
+__device__ __forceinline__ void next_cells_held(const RunDev &R, int32_t *cell, int64_t b, int64_t n,
+                                                const real *u, const real *v, const real *w, const real (&hx)[NH],
+                                                const real (&hy)[NH], const real (&hz)[NH]) {
+  const int lane = threadIdx.x & 63;
+  const Flight<real> F(R);
+  int32_t *gc = cell + R.so + b;
+#pragma unroll
+  for (int j = 0; j < NH; ++j) {
+    const int64_t k = (int64_t)j * kWave + lane;
+    if (k < n) {
+      const real pos[3] = {hx[j], hy[j], hz[j]};
+      const real vel[3] = {u[k], v[k], DIM == 3 ? w[k] : (real)0};
+      gc[k] = flight_cell<real, DIM>(F, pos, vel);
+    }
+  }
+}
+
 template <typename real>
 __device__ __forceinline__ void store_velocities(const RunDev &R, const Particles<real> &B, int64_t b, int64_t n,
                                                  const real *su, const real *sv, const real *sw) {
@@ -1535,6 +1642,24 @@ __device__ __forceinline__ void store_velocities(const RunDev &R, const Particle
     B.u[dst] = su[k];
     B.v[dst] = sv[k];
     B.w[dst] = sw[k];
+  }
+}
+
+// Look-ahead for the next step's Motion over P' positions [b, b+n) of a run
+// (this thread's share: t, t + nt, ...): the cell each particle's next free
+// flight ends in, or the queue mark, from its final position (read back: this
+// same thread wrote it to P' in the gather) and final velocity (u, v, w: the
+// LDS stage or P').
+template <typename real, int DIM>
+__device__ __forceinline__ void next_cells(const RunDev &R, const Particles<real> &B, int32_t *cell, int64_t b,
+                                           int64_t n, const real *u, const real *v, const real *w, int t, int nt) {
+  const Flight<real> F(R);
+  const int64_t base = R.so + b;
+  for (int64_t k = t; k < n; k += nt) {
+    const int64_t dst = base + k;
+    const real pos[3] = {B.x[dst], B.y[dst], DIM == 3 ? B.z[dst] : (real)0};
+    const real vel[3] = {u[k], v[k], DIM == 3 ? w[k] : (real)0};
+    cell[dst] = flight_cell<real, DIM>(F, pos, vel);
   }
 }
 
@@ -1560,7 +1685,10 @@ __global__ __launch_bounds__(kCollideWaves * 64) void k_collide(DevPtrs<real> d,
   const int64_t b0 = d.bin_start[R.bo + c0];
   const int64_t n = (int64_t)d.bin_start[R.bo + c0 + ncell] - b0;
   const bool in_lds = n <= CAP;
-  gather_through_lcr<real, DIM>(R, d.lcr, A, B, b0, n, in_lds, su, sv, sw);
+  constexpr int NH = (CAP + 4 * kWave - 1) / (4 * kWave) * 4;
+  real hx[NH], hy[NH], hz[NH];
+  if (in_lds) gather_hold<real, DIM, NH>(R, d.lcr, A, B, b0, n, su, sv, sw, hx, hy, hz);
+  else gather_through_lcr<real, DIM>(R, d.lcr, A, B, b0, n, false, su, sv, sw);
   if (in_lds) wave_sync();
   else global_sync_wave();
   const uint32_t step = *d.step;
@@ -1585,6 +1713,10 @@ __global__ __launch_bounds__(kCollideWaves * 64) void k_collide(DevPtrs<real> d,
   if (in_lds) {
     wave_sync();
     store_velocities<real>(R, B, b0, n, su, sv, sw);
+    if (R.ahead) next_cells_held<real, DIM, NH>(R, d.cell, b0, n, su, sv, sw, hx, hy, hz);
+  } else if (R.ahead) {
+    global_sync_wave();  // every lane's chain on P' is visible
+    next_cells<real, DIM>(R, B, d.cell, b0, n, B.u + R.so + b0, B.v + R.so + b0, B.w + R.so + b0, lane, kWave);
   }
 }
 
@@ -1863,13 +1995,17 @@ __global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, 
     gm = sh.gm;
   }
   __syncthreads();
-  if (in_lds)
+  if (in_lds) {
     for (int64_t k = tid; k < n; k += 256) {
       const int64_t dst = R.so + b0 + k;
       B.u[dst] = su[k];
       B.v[dst] = sv[k];
       B.w[dst] = sw[k];
     }
+    if (R.ahead) next_cells<real, DIM>(R, B, d.cell, b0, n, su, sv, sw, tid, 256);
+  } else if (R.ahead) {
+    next_cells<real, DIM>(R, B, d.cell, b0, n, B.u + R.so + b0, B.v + R.so + b0, B.w + R.so + b0, tid, 256);
+  }
   if (sample) {
     double sm[kFields] = {0, 0, 0, 0, 0, 0, 0};
     for (int64_t k = tid; k < n; k += 256) {
@@ -1926,7 +2062,10 @@ __global__ __launch_bounds__(256) void k_collide_wave(DevPtrs<real> d, int src, 
   const bool in_lds = n <= CAP;
   real *su = vel[wave], *sv = su + CAP, *sw = sv + CAP;
   const Particles<real> A = d.P[src], B = d.P[1 - src];
-  gather_through_lcr<real, DIM>(R, d.lcr, A, B, b0, n, in_lds, su, sv, sw);
+  constexpr int NH = (CAP + 4 * kWave - 1) / (4 * kWave) * 4;
+  real hx[NH], hy[NH], hz[NH];
+  if (in_lds) gather_hold<real, DIM, NH>(R, d.lcr, A, B, b0, n, su, sv, sw, hx, hy, hz);
+  else gather_through_lcr<real, DIM>(R, d.lcr, A, B, b0, n, false, su, sv, sw);
   if (in_lds) WaveSync::bar();
   else global_sync_wave();
   const uint32_t step = *d.step;
@@ -1942,9 +2081,11 @@ __global__ __launch_bounds__(256) void k_collide_wave(DevPtrs<real> d, int src, 
                                        gm);
     WaveSync::bar();
     store_velocities<real>(R, B, b0, n, su, sv, sw);
+    if (R.ahead) next_cells_held<real, DIM, NH>(R, d.cell, b0, n, su, sv, sw, hx, hy, hz);
   } else {
     if (lane == 0) ncol = chain_serial<real>(R, step, (uint32_t)c, (uint32_t)n, 0, nsel, u, v, w, gm);
     global_sync_wave();
+    if (R.ahead) next_cells<real, DIM>(R, B, d.cell, b0, n, u, v, w, lane, kWave);
   }
   if (sample) sample_cell_wave(u, v, w, n, d.stage + gc * kFields);
   if (lane == 0) {
@@ -1986,13 +2127,21 @@ struct PipeMeta {
   int32_t c;
   uint32_t ncoll;
   float gm, rem, dt;
+  int32_t ahead;
   RunView rv;
+  const RunDev *run;
 };
 
 // The particles of the cell in flight, kPipeChunks per thread (k = q*256 + tid).
 struct PipeRegs {
   int32_t l[kPipeChunks];
   float x[kPipeChunks], y[kPipeChunks], z[kPipeChunks], u[kPipeChunks], v[kPipeChunks], w[kPipeChunks];
+};
+
+// Final positions of the particles this thread placed (k = q*256 + tid), kept
+// for the look-ahead at the write-back.
+struct PipePos {
+  float x[kPipeChunks], y[kPipeChunks], z[kPipeChunks];
 };
 
 // LCR entries (run-local slots) of the particles this thread handles in an
@@ -2050,17 +2199,20 @@ __device__ __forceinline__ void pipe_gather(const int32_t *lcr, const Particles<
 // An LDS item's gathered particles: positions to P', velocities to LDS.
 template <int DIM>
 __device__ __forceinline__ void pipe_place(const Particles<float> &B, const PipeMeta &m, const PipeRegs &pr,
-                                           float *su, float *sv, float *sw) {
+                                           float *su, float *sv, float *sw, PipePos &pp) {
   if (m.n > kCollideCapF32) return;
   const int tid = threadIdx.x;
 #pragma unroll
   for (int q = 0; q < kPipeChunks; ++q) {
     const int64_t k = q * 256 + tid;
+    pp.x[q] = flown(pr.x[q], pr.u[q], m.dt, pr.l[q]);
+    pp.y[q] = flown(pr.y[q], pr.v[q], m.dt, pr.l[q]);
+    pp.z[q] = DIM == 3 ? flown(pr.z[q], pr.w[q], m.dt, pr.l[q]) : 0.0f;
     if (k < m.n) {
       const int64_t dst = m.so + m.b0 + k;
-      B.x[dst] = flown(pr.x[q], pr.u[q], m.dt, pr.l[q]);
-      B.y[dst] = flown(pr.y[q], pr.v[q], m.dt, pr.l[q]);
-      if (DIM == 3) B.z[dst] = flown(pr.z[q], pr.w[q], m.dt, pr.l[q]);
+      B.x[dst] = pp.x[q];
+      B.y[dst] = pp.y[q];
+      if (DIM == 3) B.z[dst] = pp.z[q];
       su[k] = pr.u[q];
       sv[k] = pr.v[q];
       sw[k] = pr.w[q];
@@ -2068,10 +2220,12 @@ __device__ __forceinline__ void pipe_place(const Particles<float> &B, const Pipe
   }
 }
 
-// Collisions, write-back, sampling and cell state of one item whose data is
-// in place (LDS su/sv/sw, or P' for an item beyond the LDS capacity).
+// Collisions, write-back (with the next step's flight cells), sampling and
+// cell state of one item whose data is in place (LDS su/sv/sw, or P' for an
+// item beyond the LDS capacity).
+template <int DIM>
 __device__ __forceinline__ void pipe_collide(const DevPtrs<float> &d, const Particles<float> &B, const PipeMeta &m,
-                                             float *su, float *sv, float *sw, int32_t *own,
+                                             const PipePos &pp, float *su, float *sv, float *sw, int32_t *own,
                                              BlockScratch<float> &sh, uint32_t step, bool sample) {
   const int tid = threadIdx.x;
   const int64_t n = m.n;
@@ -2092,12 +2246,29 @@ __device__ __forceinline__ void pipe_collide(const DevPtrs<float> &d, const Part
     gm = sh.gm;
   }
   LdsSync::bar();
-  if (lds)
+  if (lds) {
     for (int64_t k = tid; k < n; k += 256) {
       gu[k] = su[k];
       gv[k] = sv[k];
       gw[k] = sw[k];
     }
+    if (m.ahead) {
+      // the positions this thread placed are still in its registers
+      const Flight<float> F(*m.run);
+      int32_t *gc = d.cell + m.so + m.b0;
+#pragma unroll
+      for (int q = 0; q < kPipeChunks; ++q) {
+        const int64_t k = q * 256 + tid;
+        if (k < n) {
+          const float pos[3] = {pp.x[q], pp.y[q], pp.z[q]};
+          const float vel[3] = {su[k], sv[k], sw[k]};
+          gc[k] = flight_cell<float, DIM>(F, pos, vel);
+        }
+      }
+    }
+  } else if (m.ahead) {
+    next_cells<float, DIM>(*m.run, B, d.cell, m.b0, n, gu, gv, gw, tid, 256);
+  }
   if (sample) {
     // LDS and global are summed by separate loops: a pointer to either would
     // be a flat access the compiler must also wait for as a global one
@@ -2162,6 +2333,8 @@ __global__ __launch_bounds__(256) void k_collide_pipe(DevPtrs<float> d, int src,
     m.gm = d.gmax[m.gc];
     m.rem = d.rem_c[m.gc];
     m.dt = R.dt_f;
+    m.ahead = R.ahead;
+    m.run = &R;
     m.rv.key0 = R.key0;
     m.rv.key1 = R.key1;
     m.rv.hs = R.hs;
@@ -2180,7 +2353,8 @@ __global__ __launch_bounds__(256) void k_collide_pipe(DevPtrs<float> d, int src,
     const PipeMeta m = meta[j];
     const bool has1 = j + 1 < count, has2 = j + 2 < count;
     // item j: positions to P', velocities to LDS (its gathers return here)
-    pipe_place<DIM>(B, m, pr, vel, vel + CAP, vel + 2 * CAP);
+    PipePos pp;
+    pipe_place<DIM>(B, m, pr, vel, vel + CAP, vel + 2 * CAP, pp);
     if (m.n > CAP) __threadfence_block();
     LdsSync::bar();
     // item j+1's gathers and item j+2's LCR entries start, then item j collides
@@ -2188,7 +2362,7 @@ __global__ __launch_bounds__(256) void k_collide_pipe(DevPtrs<float> d, int src,
     for (int q = 0; q < kPipeChunks; ++q) pr.l[q] = lc[q];
     pipe_gather<DIM>(d.lcr, A, B, meta[has1 ? j + 1 : j], has1, pr);
     pipe_lcr(d.lcr, meta[has2 ? j + 2 : j], has2, lc);
-    pipe_collide(d, B, m, vel, vel + CAP, vel + 2 * CAP, own, sh, step, sample);
+    pipe_collide<DIM>(d, B, m, pp, vel, vel + CAP, vel + 2 * CAP, own, sh, step, sample);
   }
 }
 
@@ -2363,6 +2537,32 @@ static void index_pass(IndexArgs a, int max_digits, int n_runs, int shift, const
     TIMED(kKScatter, hipLaunchKernelGGL((k_scatter<false, false, false>), dim3(wblocks), dim3(256), lds, s, a));
 }
 
+// The flight cells of the live particles in slots [s0, s1) (their run's
+// first n_alive slots) of buffer buf, as Interaction leaves them after a step:
+// after the initial fill and after a run's state is replaced.
+template <typename real, int DIM>
+__global__ __launch_bounds__(256) void k_next_cells(DevPtrs<real> d, int buf, int64_t s0, int64_t s1, int64_t tile) {
+  const Particles<real> P = d.P[buf];
+  for (int64_t i = s0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < s1;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int r = d.tile_run[i / tile];
+    const RunDev &R = d.runs[r];
+    if (i - R.so >= d.n_alive[r]) continue;
+    const real pos[3] = {P.x[i], P.y[i], DIM == 3 ? P.z[i] : (real)0};
+    const real vel[3] = {P.u[i], P.v[i], DIM == 3 ? P.w[i] : (real)0};
+    d.cell[i] = flight_cell<real, DIM>(Flight<real>(R), pos, vel);
+  }
+}
+
+template <typename real>
+void launch_next_cells(const Geometry &g, const DevPtrs<real> &d, int buf, int64_t so, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  if (g.dim == 3)
+    hipLaunchKernelGGL((k_next_cells<real, 3>), dim3(grid_for(n)), dim3(256), 0, s, d, buf, so, so + n, g.tile);
+  else
+    hipLaunchKernelGGL((k_next_cells<real, 2>), dim3(grid_for(n)), dim3(256), 0, s, d, buf, so, so + n, g.tile);
+}
+
 template <typename real>
 void launch_init(const Geometry &g, const DevPtrs<real> &d, hipStream_t s) {
   hipLaunchKernelGGL(k_init_runs<real>, dim3((g.n_runs + 255) / 256), dim3(256), 0, s, d, g.n_runs);
@@ -2378,6 +2578,7 @@ void launch_init(const Geometry &g, const DevPtrs<real> &d, hipStream_t s) {
   else
     hipLaunchKernelGGL((k_init_particles<real, 2>), dim3(grid_for(g.n_slots)), dim3(256), 0, s, d, g.n_slots,
                        g.tile);
+  launch_next_cells<real>(g, d, 0, 0, g.n_slots, s);
 }
 
 // One lane's share of a step: Generation, Motion, Indexing and Interaction of
@@ -2547,6 +2748,9 @@ void launch_moments(const Geometry &g, const DevPtrs<real> &d, int slot, int eg0
 
 template void launch_init<float>(const Geometry &, const DevPtrs<float> &, hipStream_t);
 template void launch_init<double>(const Geometry &, const DevPtrs<double> &, hipStream_t);
+template void launch_next_cells<float>(const Geometry &, const DevPtrs<float> &, int, int64_t, int64_t, hipStream_t);
+template void launch_next_cells<double>(const Geometry &, const DevPtrs<double> &, int, int64_t, int64_t,
+                                        hipStream_t);
 template void launch_step<float>(const Geometry &, const DevPtrs<float> &, int, hipStream_t, const LaneStreams *,
                                  const Prof *);
 template void launch_step<double>(const Geometry &, const DevPtrs<double> &, int, hipStream_t, const LaneStreams *,
