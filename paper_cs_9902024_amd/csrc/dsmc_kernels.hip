@@ -2095,24 +2095,20 @@ __global__ __launch_bounds__(256) void k_collide_wave(DevPtrs<real> d, int src, 
   }
 }
 
-// Crowded cells in FP32: one 256-thread block walks kPipeCells consecutive
-// cell items.  With more than one, while the collisions of cell j run in LDS
-// the whole of cell j+1 (positions and velocities) is gathered through LCR
-// into registers and the LCR entries of cell j+2 are loaded; the collision
-// chain synchronises with LDS-only barriers, so these loads stay in flight
-// (a vector load is waited for only where its register is read).  Each cell
-// is processed exactly as k_collide_cell does (same selections, order and
-// arithmetic).  The items' bookkeeping (slots, bin range, NTC state, the
-// run's constants) is read once per block into LDS, so the collisions read
-// no global memory; the gather reads are clamped, never masked, so they are
-// issued back to back.
+// Crowded cells in FP32: one 256-thread block per cell.  The cell's
+// bookkeeping (slots, bin range, NTC state, the run's constants) is read once
+// into LDS, so the collisions read no global memory; the gather through LCR
+// goes to registers with clamped, never masked, reads issued back to back,
+// then positions to P' and velocities to LDS, and the collision chain
+// synchronises with LDS-only barriers.  Each cell is processed exactly as
+// k_collide_cell does (same selections, order and arithmetic).
 // One cell per block measured fastest: a cell's gather also reads its
 // neighbours' source ranges, and the blocks of consecutive cells, running at
-// once on one XCD, then find those lines in its L2.  A block that walks its
-// own consecutive cells reads each range again a cell's time later, after
-// the L2 has turned over (16 cells per block: 7.2 ms and 3x the bytes read
-// from memory on the 512 x 1M box, against 6.3 ms and 1x with one).
-constexpr int kPipeCells = 1;
+// once on one XCD, then find those lines in its L2.  A block that walked its
+// own consecutive cells (pipelining the next cell's gather under the current
+// cell's collisions) read each range again a cell's time later, after the L2
+// had turned over (16 cells per block: 7.2 ms and 3x the bytes read from
+// memory on the 512 x 1M box, against 6.3 ms and 1x with one).
 constexpr int kPipeChunks = kCollideCapF32 / 256;
 
 // The run constants the collisions need.
@@ -2310,18 +2306,17 @@ __global__ __launch_bounds__(256) void k_collide_pipe(DevPtrs<float> d, int src,
   constexpr int CAP = kCollideCapF32;
   __shared__ __align__(16) float vel[3 * CAP];
   __shared__ int32_t own[CAP];
-  __shared__ PipeMeta meta[kPipeCells];
+  __shared__ PipeMeta meta;
   __shared__ BlockScratch<float> sh;
   const int tid = threadIdx.x;
-  const int64_t first = ci0 + xcd_block(blockIdx.x, gridDim.x) * kPipeCells;
-  if (first >= ci1) return;
-  const int count = (int)min((int64_t)kPipeCells, ci1 - first);
+  const int64_t item = ci0 + xcd_block(blockIdx.x, gridDim.x);
+  if (item >= ci1) return;
   const Particles<float> A = d.P[src], B = d.P[1 - src];
   const uint32_t step = *d.step;
   const bool sample = *d.sample_slot >= 0;
-  // bookkeeping of the block's items, once
-  if (tid < count) {
-    const int2 it = d.cell_items[first + tid];
+  // the item's bookkeeping, once
+  if (tid == 0) {
+    const int2 it = d.cell_items[item];
     const RunDev &R = d.runs[it.x];
     PipeMeta m;
     m.so = R.so;
@@ -2341,29 +2336,19 @@ __global__ __launch_bounds__(256) void k_collide_pipe(DevPtrs<float> d, int src,
     m.rv.c_ref = R.c_ref;
     m.rv.vhs_exp = R.vhs_exp;
     m.rv.coef = R.coef;
-    meta[tid] = m;
+    meta = m;
   }
   __syncthreads();
+  const PipeMeta m = meta;
   PipeRegs pr;
-  int32_t lc[kPipeChunks];
-  pipe_lcr(d.lcr, meta[0], true, pr.l);
-  pipe_gather<DIM>(d.lcr, A, B, meta[0], true, pr);
-  pipe_lcr(d.lcr, meta[count > 1 ? 1 : 0], count > 1, lc);
-  for (int j = 0; j < count; ++j) {
-    const PipeMeta m = meta[j];
-    const bool has1 = j + 1 < count, has2 = j + 2 < count;
-    // item j: positions to P', velocities to LDS (its gathers return here)
-    PipePos pp;
-    pipe_place<DIM>(B, m, pr, vel, vel + CAP, vel + 2 * CAP, pp);
-    if (m.n > CAP) __threadfence_block();
-    LdsSync::bar();
-    // item j+1's gathers and item j+2's LCR entries start, then item j collides
-#pragma unroll
-    for (int q = 0; q < kPipeChunks; ++q) pr.l[q] = lc[q];
-    pipe_gather<DIM>(d.lcr, A, B, meta[has1 ? j + 1 : j], has1, pr);
-    pipe_lcr(d.lcr, meta[has2 ? j + 2 : j], has2, lc);
-    pipe_collide<DIM>(d, B, m, pp, vel, vel + CAP, vel + 2 * CAP, own, sh, step, sample);
-  }
+  pipe_lcr(d.lcr, m, true, pr.l);
+  pipe_gather<DIM>(d.lcr, A, B, m, true, pr);
+  // positions to P', velocities to LDS (the gathers return here)
+  PipePos pp;
+  pipe_place<DIM>(B, m, pr, vel, vel + CAP, vel + 2 * CAP, pp);
+  if (m.n > CAP) __threadfence_block();
+  LdsSync::bar();
+  pipe_collide<DIM>(d, B, m, pp, vel, vel + CAP, vel + 2 * CAP, own, sh, step, sample);
 }
 
 template <typename real>
@@ -2681,7 +2666,7 @@ static void lane_step(const Geometry &g, const LaneRange &L, const DevPtrs<real>
   }
   if (L.ci1 > L.ci0) {
     if constexpr (std::is_same<real, float>::value) {
-      const int64_t nblk = (L.ci1 - L.ci0 + kPipeCells - 1) / kPipeCells;
+      const int64_t nblk = L.ci1 - L.ci0;
       TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_pipe<DIM>), dim3((unsigned)nblk), dim3(256), 0, s, d, buf,
                                               L.ci0, L.ci1));
     } else {
