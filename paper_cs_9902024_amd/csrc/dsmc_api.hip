@@ -41,7 +41,7 @@ struct Plan {
   size_t off_runs, off_tile_run, off_face_run, off_cgroup_run, off_inflow, off_gen_blk, off_eg_start, off_eg_runs,
       off_eg_acc,
       off_eg_nc, off_samples, off_items, off_cell_items, off_wave_items, off_solid;
-  size_t off_P[2][6];
+  size_t off_P[2][3];  // per buffer: records (x, y, u, v), z (3-D only), w
   size_t off_cell, off_lcr, off_lcr_tmp, off_hist, off_tot, off_bin_start, off_remc, off_gmax, off_ncoll, off_remf,
       off_gencnt, off_stage, off_acc, off_mom, off_nalive, off_nsorted, off_ngen, off_scalars, off_wallq, off_wallq_n,
       off_key_tmp, off_bitem, off_bitem_run, off_bfirst;
@@ -453,8 +453,11 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
   P.off_cell_items = take(sizeof(int2) * P.cell_items.size());
   P.off_wave_items = take(sizeof(int2) * P.wave_items.size());
   P.off_solid = take(P.solid.size());
-  for (int b = 0; b < 2; ++b)
-    for (int a = 0; a < 6; ++a) P.off_P[b][a] = (a == 2 && g.dim == 2) ? (size_t)-1 : take(es * g.n_slots);
+  for (int b = 0; b < 2; ++b) {
+    P.off_P[b][0] = take(4 * es * g.n_slots);
+    P.off_P[b][1] = g.dim == 2 ? (size_t)-1 : take(es * g.n_slots);
+    P.off_P[b][2] = take(es * g.n_slots);
+  }
   P.off_cell = take(4 * g.n_slots);
   P.off_lcr = take(4 * g.n_slots);
   P.off_wallq = take(4 * g.n_slots);
@@ -502,8 +505,9 @@ DevPtrs<real> carve(const Plan &P, char *base) {
   d.wave_items = (const int2 *)(base + P.off_wave_items);
   d.solid = (const uint8_t *)(base + P.off_solid);
   for (int b = 0; b < 2; ++b) {
-    real **c[6] = {&d.P[b].x, &d.P[b].y, &d.P[b].z, &d.P[b].u, &d.P[b].v, &d.P[b].w};
-    for (int a = 0; a < 6; ++a) *c[a] = P.off_P[b][a] == (size_t)-1 ? nullptr : (real *)(base + P.off_P[b][a]);
+    d.P[b].q = (typename Vec4<real>::type *)(base + P.off_P[b][0]);
+    d.P[b].z = P.off_P[b][1] == (size_t)-1 ? nullptr : (real *)(base + P.off_P[b][1]);
+    d.P[b].w = (real *)(base + P.off_P[b][2]);
   }
   d.cell = (int32_t *)(base + P.off_cell);
   d.lcr = (int32_t *)(base + P.off_lcr);
@@ -933,18 +937,21 @@ dsmc_status get_state_t(dsmc_ctx *c, const DevPtrs<real> &d, int32_t run, double
   *n = na;
   if (!out) return DSMC_OK;
   if (cap < na) return set_err(c, DSMC_ESIZE, "output too small");
-  std::vector<real> tmp((size_t)na);
   const Particles<real> &P = d.P[c->buf];
-  real *comp[6] = {P.x, P.y, P.z, P.u, P.v, P.w};
-  for (int a = 0; a < 6; ++a) {
-    if (!comp[a]) {
-      std::fill(out + (size_t)a * na, out + (size_t)(a + 1) * na, 0.0);
-      continue;
-    }
-    if (na) st = download<real>(c, tmp.data(), comp[a] + R.so, (size_t)na);
-    if (!st) st = check_hip(c, hipStreamSynchronize(c->stream), "sync");
-    if (st) return st;
-    for (int64_t i = 0; i < na; ++i) out[(size_t)a * na + i] = (double)tmp[i];
+  std::vector<real> rec((size_t)std::max(4 * na, 1)), z((size_t)std::max(na, 1)), w((size_t)std::max(na, 1));
+  if (na) st = download<real>(c, rec.data(), (const real *)(P.q + R.so), 4 * (size_t)na);
+  if (!st && na && P.z) st = download<real>(c, z.data(), P.z + R.so, (size_t)na);
+  if (!st && na) st = download<real>(c, w.data(), P.w + R.so, (size_t)na);
+  if (!st) st = sync_ctx(c);
+  if (st) return st;
+  // records hold (x, y, u, v); the output is x, y, z, u, v, w
+  for (int64_t i = 0; i < na; ++i) {
+    out[0 * (size_t)na + i] = (double)rec[4 * i];
+    out[1 * (size_t)na + i] = (double)rec[4 * i + 1];
+    out[2 * (size_t)na + i] = P.z ? (double)z[i] : 0.0;
+    out[3 * (size_t)na + i] = (double)rec[4 * i + 2];
+    out[4 * (size_t)na + i] = (double)rec[4 * i + 3];
+    out[5 * (size_t)na + i] = (double)w[i];
   }
   return DSMC_OK;
 }
@@ -955,14 +962,26 @@ dsmc_status set_state_t(dsmc_ctx *c, const DevPtrs<real> &d, int32_t run, const 
   if (n < 0 || n > c->plan.spec_capacity[run]) return set_err(c, DSMC_EINVAL, "n exceeds the run's capacity");
   dsmc_status st = sync_ctx(c);
   if (st) return st;
-  std::vector<real> tmp((size_t)std::max<int64_t>(n, 1));
   const Particles<real> &P = d.P[c->buf];
-  real *comp[6] = {P.x, P.y, P.z, P.u, P.v, P.w};
-  for (int a = 0; a < 6; ++a) {
-    if (!comp[a] || n == 0) continue;
-    for (int64_t i = 0; i < n; ++i) tmp[i] = (real)in[(size_t)a * n + i];
-    st = check_hip(c, hipMemcpyAsync(comp[a] + R.so, tmp.data(), n * sizeof(real), hipMemcpyHostToDevice, c->stream),
+  const size_t m = (size_t)std::max<int64_t>(n, 1);
+  std::vector<real> rec(4 * m), z(m), w(m);
+  for (int64_t i = 0; i < n; ++i) {
+    rec[4 * i] = (real)in[0 * (size_t)n + i];
+    rec[4 * i + 1] = (real)in[1 * (size_t)n + i];
+    rec[4 * i + 2] = (real)in[3 * (size_t)n + i];
+    rec[4 * i + 3] = (real)in[4 * (size_t)n + i];
+    z[i] = (real)in[2 * (size_t)n + i];
+    w[i] = (real)in[5 * (size_t)n + i];
+  }
+  if (n > 0) {
+    st = check_hip(c, hipMemcpyAsync(P.q + R.so, rec.data(), 4 * n * sizeof(real), hipMemcpyHostToDevice, c->stream),
                    "upload state");
+    if (!st && P.z)
+      st = check_hip(c, hipMemcpyAsync(P.z + R.so, z.data(), n * sizeof(real), hipMemcpyHostToDevice, c->stream),
+                     "upload state");
+    if (!st)
+      st = check_hip(c, hipMemcpyAsync(P.w + R.so, w.data(), n * sizeof(real), hipMemcpyHostToDevice, c->stream),
+                     "upload state");
     if (!st) st = check_hip(c, hipStreamSynchronize(c->stream), "sync");
     if (st) return st;
   }

@@ -103,9 +103,40 @@ struct RunDev {
   double slo[3], shi[3];
 };
 
+template <typename real> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+
+template <typename real>
+__host__ __device__ inline typename Vec4<real>::type make_vec4(real a, real b, real c, real d) {
+  typename Vec4<real>::type t;
+  t.x = a;
+  t.y = b;
+  t.z = c;
+  t.w = d;
+  return t;
+}
+
+// One component of the packed (x, y, u, v) records seen as an array.
+template <typename real>
+struct Strided {
+  real *p;
+  __host__ __device__ real &operator[](int64_t i) const { return p[4 * i]; }
+  __host__ __device__ Strided operator+(int64_t k) const { return Strided{p + 4 * k}; }
+};
+
+// The particle array P: per slot a record (x, y, u, v) and the remaining
+// components z (3-D only) and w.  A particle that changed cell is gathered by
+// Interaction from its old place: with the record it costs two cache lines
+// (record, w) instead of one per component.
 template <typename real>
 struct Particles {
-  real *x, *y, *z, *u, *v, *w;
+  typename Vec4<real>::type *q;
+  real *z, *w;
+  __host__ __device__ Strided<real> x() const { return Strided<real>{reinterpret_cast<real *>(q)}; }
+  __host__ __device__ Strided<real> y() const { return Strided<real>{reinterpret_cast<real *>(q) + 1}; }
+  __host__ __device__ Strided<real> u() const { return Strided<real>{reinterpret_cast<real *>(q) + 2}; }
+  __host__ __device__ Strided<real> v() const { return Strided<real>{reinterpret_cast<real *>(q) + 3}; }
 };
 
 // Device pointers of one context, carved out of the caller's arena.

@@ -191,8 +191,8 @@ __global__ __launch_bounds__(256) void k_init_particles(DevPtrs<real> d, int64_t
     box_muller(a0, a1, n0, n1);
     box_muller(a2, a3, n2, n3);
     const real st = (real)R.init_sqrtT;
-    P.u[i] = (real)R.init_U[0] + st * n0;
-    P.v[i] = (real)R.init_U[1] + st * n1;
+    const real u0 = (real)R.init_U[0] + st * n0;
+    const real v0 = (real)R.init_U[1] + st * n1;
     P.w[i] = (real)R.init_U[2] + st * n2;
     real pos[3];
     for (int att = 0;; ++att) {
@@ -206,8 +206,7 @@ __global__ __launch_bounds__(256) void k_init_particles(DevPtrs<real> d, int64_t
       pos[2] = DIM == 3 ? uz * (real)R.L[2] : (real)0;
       if (!R.has_solid || !d.solid[R.sdo + cell_of<real, DIM>(R, pos)]) break;
     }
-    P.x[i] = pos[0];
-    P.y[i] = pos[1];
+    P.q[i] = make_vec4<real>(pos[0], pos[1], u0, v0);
     if (DIM == 3) P.z[i] = pos[2];
   }
 }
@@ -312,11 +311,8 @@ __device__ __forceinline__ void emit_one(const RunDev &R, uint32_t step, int32_t
   const real ut = s();
   const real x0 = -(u * (real)R.dt) * ((real)1 - ut);
   const real st = (real)R.inflow_sqrtT;
-  P.x[o] = x0;
-  P.y[o] = y;
+  P.q[o] = make_vec4<real>(x0, y, u, st * t0);
   if (DIM == 3) P.z[o] = zc;
-  P.u[o] = u;
-  P.v[o] = st * t0;
   P.w[o] = st * t1;
 }
 
@@ -650,9 +646,6 @@ __device__ __forceinline__ void histogram_add(uint32_t *h, uint32_t key, bool ac
   if (active && boundary) atomicAdd(&h[key], (uint32_t)(nxt - lane));
 }
 
-template <typename real> struct Vec4;
-template <> struct Vec4<float> { using type = float4; };
-template <> struct Vec4<double> { using type = double4; };
 
 template <typename real>
 __device__ __forceinline__ void load4(const real *p, int64_t i, real (&o)[4]) {
@@ -693,12 +686,9 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
   const int64_t n = d.n_alive[r];
   const int64_t npre = R.ahead ? n - d.n_gen[r] : 0;  // cells in place from the last Interaction
   const int64_t begin = tl * tile, end = min(begin + tile, n);
-  real *__restrict__ X = d.P[buf].x + R.so;
-  real *__restrict__ Y = d.P[buf].y + R.so;
-  real *__restrict__ Z = d.P[buf].z + R.so;
-  real *__restrict__ Uv = d.P[buf].u + R.so;
-  real *__restrict__ Vv = d.P[buf].v + R.so;
-  real *__restrict__ Wv = d.P[buf].w + R.so;
+  const typename Vec4<real>::type *__restrict__ Q = d.P[buf].q + R.so;
+  const real *__restrict__ Z = DIM == 3 ? d.P[buf].z + R.so : nullptr;
+  const real *__restrict__ Wv = d.P[buf].w + R.so;
   int32_t *__restrict__ cell = d.cell + R.so;
   uint32_t *__restrict__ wq = d.wallq + (int64_t)t * tile;  // this tile's queue segment
   uint32_t qn = 0;
@@ -727,24 +717,28 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
     } else {
     real px[4], py[4], pz[4], vx[4], vy[4], vz[4];
     if (full) {
-      load4(X, i0, px);
-      load4(Y, i0, py);
-      if (DIM == 3) load4(Z, i0, pz);
-      load4(Uv, i0, vx);
-      load4(Vv, i0, vy);
-      if (DIM == 3) load4(Wv, i0, vz);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) act[e] = true;
+      for (int e = 0; e < 4; ++e) {
+        const typename Vec4<real>::type r4 = Q[i0 + e];
+        px[e] = r4.x;
+        py[e] = r4.y;
+        vx[e] = r4.z;
+        vy[e] = r4.w;
+        act[e] = true;
+      }
+      if (DIM == 3) load4(Z, i0, pz);
+      if (DIM == 3) load4(Wv, i0, vz);
     } else {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         act[e] = i0 + e < end;
         if (act[e]) {
-          px[e] = X[i0 + e];
-          py[e] = Y[i0 + e];
+          const typename Vec4<real>::type r4 = Q[i0 + e];
+          px[e] = r4.x;
+          py[e] = r4.y;
+          vx[e] = r4.z;
+          vy[e] = r4.w;
           if (DIM == 3) pz[e] = Z[i0 + e];
-          vx[e] = Uv[i0 + e];
-          vy[e] = Vv[i0 + e];
           if (DIM == 3) vz[e] = Wv[i0 + e];
         }
       }
@@ -811,18 +805,15 @@ __global__ __launch_bounds__(256) void k_motion_walls(DevPtrs<real> d, int buf, 
     if (active) {
       const int64_t loc = wq[i];
       const int64_t gs = R.so + loc;
-      real p3[3] = {P.x[gs], P.y[gs], DIM == 3 ? P.z[gs] : (real)0};
-      real v3[3] = {P.u[gs], P.v[gs], DIM == 3 ? P.w[gs] : (real)0};
+      const typename Vec4<real>::type r4 = P.q[gs];
+      real p3[3] = {r4.x, r4.y, DIM == 3 ? P.z[gs] : (real)0};
+      real v3[3] = {r4.z, r4.w, DIM == 3 ? P.w[gs] : (real)0};
       bool hit, reemit;
       const int32_t c = move_one<real, DIM>(R, d.solid, step, (uint32_t)loc, p3, v3, hit, reemit, d.err);
-      P.x[gs] = p3[0];
-      P.y[gs] = p3[1];
+      // (the velocity is unchanged unless a face was hit)
+      P.q[gs] = make_vec4<real>(p3[0], p3[1], v3[0], v3[1]);
       if (DIM == 3) P.z[gs] = p3[2];
-      if (hit) {
-        P.u[gs] = v3[0];
-        P.v[gs] = v3[1];
-        if (DIM == 3 || reemit) P.w[gs] = v3[2];
-      }
+      if (hit && (DIM == 3 || reemit)) P.w[gs] = v3[2];
       d.cell[gs] = (int32_t)((uint32_t)c | kMovedBit);  // moved here, not by Interaction
       key = SINGLE ? (uint32_t)c : (((uint32_t)c >> shift0) & (kDigits - 1));
     }
@@ -1425,10 +1416,11 @@ __device__ __forceinline__ void scatter_pair(real cr, const Angles<real> &an, re
 }
 
 // Selections [k0, k1) of one cell in order, by one lane, on arrays u/v/w
-// (LDS or global).  Returns the accepted collisions; updates gm.
-template <typename real, typename RunT>
+// (LDS, or P' seen through Strided views).  Returns the accepted collisions;
+// updates gm.
+template <typename real, typename RunT, typename PU, typename PV, typename PW>
 __device__ uint32_t chain_serial(const RunT &R, uint32_t step, uint32_t c, uint32_t N, int64_t k0, int64_t k1,
-                                 real *u, real *v, real *w, real &gm) {
+                                 PU u, PV v, PW w, real &gm) {
   uint32_t ncol = 0;
   for (int64_t k = k0; k < k1; ++k) {
     const Selection<real> s = draw_selection<real>(R, step, c, k, N);
@@ -1464,8 +1456,8 @@ __device__ __forceinline__ int64_t ntc_selections(const RunT &R, int64_t N, real
 }
 
 // Sums of one cell (sequential order, one lane).
-template <typename real>
-__device__ __forceinline__ void sample_cell(const real *u, const real *v, const real *w, int64_t N, double *out) {
+template <typename PU, typename PV, typename PW>
+__device__ __forceinline__ void sample_cell(PU u, PV v, PW w, int64_t N, double *out) {
   double s[kFields] = {0, 0, 0, 0, 0, 0, 0};
   for (int64_t k = 0; k < N; ++k) {
     const double a = (double)u[k], b = (double)v[k], c = (double)w[k];
@@ -1482,9 +1474,8 @@ __device__ __forceinline__ void sample_cell(const real *u, const real *v, const 
 }
 
 // Sums of one cell by a whole wave (strided partial sums, butterfly reduce).
-template <typename real>
-__device__ __forceinline__ void sample_cell_wave(const real *u, const real *v, const real *w, int64_t N,
-                                                 double *out) {
+template <typename PU, typename PV, typename PW>
+__device__ __forceinline__ void sample_cell_wave(PU u, PV v, PW w, int64_t N, double *out) {
   const int lane = threadIdx.x & 63;
   double s[kFields] = {0, 0, 0, 0, 0, 0, 0};
   for (int64_t k = lane; k < N; k += kWave) {
@@ -1516,13 +1507,11 @@ __device__ __forceinline__ real flown(real p, real v, real dt, int32_t entry) {
   return entry < 0 ? p : p + v * dt;
 }
 
-// Gather particles [b, b+n) of a run (sorted positions) through LCR, moving
-// the free ones: positions to P', velocities to LDS (or to P' when to_lds is
-// false).
+// Gather particles [b, b+n) of a run (sorted positions) through LCR into P',
+// whole records, moving the free ones (an item beyond its LDS stage).
 template <typename real, int DIM>
-__device__ __forceinline__ void gather_through_lcr(const RunDev &R, const int32_t *lcr, const Particles<real> &A,
-                                                   const Particles<real> &B, int64_t b, int64_t n, bool to_lds,
-                                                   real *su, real *sv, real *sw) {
+__device__ __forceinline__ void gather_to_p(const RunDev &R, const int32_t *lcr, const Particles<real> &A,
+                                            const Particles<real> &B, int64_t b, int64_t n) {
   const int lane = threadIdx.x & 63;
   constexpr int U = 4;
   // reads clamped into [0, n) instead of masked: no branch whose join would
@@ -1533,15 +1522,13 @@ __device__ __forceinline__ void gather_through_lcr(const RunDev &R, const int32_
     int32_t l[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) l[q] = lp[min(k0 + q * kWave + lane, n - 1)];
-    real x[U], y[U], z[U], uu[U], vv[U], ww[U];
+    typename Vec4<real>::type r4[U];
+    real z[U], ww[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       const int64_t src = R.so + (l[q] & kSlotMask);
-      x[q] = A.x[src];
-      y[q] = A.y[src];
+      r4[q] = A.q[src];
       if (DIM == 3) z[q] = A.z[src];
-      uu[q] = A.u[src];
-      vv[q] = A.v[src];
       ww[q] = A.w[src];
     }
 #pragma unroll
@@ -1549,29 +1536,22 @@ __device__ __forceinline__ void gather_through_lcr(const RunDev &R, const int32_
       const int64_t k = k0 + q * kWave + lane;
       if (k >= n) continue;
       const int64_t dst = R.so + b + k;
-      B.x[dst] = flown(x[q], uu[q], dt, l[q]);
-      B.y[dst] = flown(y[q], vv[q], dt, l[q]);
+      B.q[dst] = make_vec4<real>(flown(r4[q].x, r4[q].z, dt, l[q]), flown(r4[q].y, r4[q].w, dt, l[q]), r4[q].z,
+                                 r4[q].w);
       if (DIM == 3) B.z[dst] = flown(z[q], ww[q], dt, l[q]);
-      if (to_lds) {
-        su[k] = uu[q];
-        sv[k] = vv[q];
-        sw[k] = ww[q];
-      } else {
-        B.u[dst] = uu[q];
-        B.v[dst] = vv[q];
-        B.w[dst] = ww[q];
-      }
+      B.w[dst] = ww[q];
     }
   }
 }
 
-// The LDS case of gather_through_lcr for a stage of at most NH*64 particles,
-// also keeping each lane's final positions (particle j*64 + lane at index j,
-// constant indices: the chunk loop is unrolled) for the look-ahead.
+// Gather into the LDS stage (at most NH*64 particles): velocities to su/sv/sw,
+// and each lane's final positions kept in registers (particle j*64 + lane at
+// index j, constant indices: the chunk loop is unrolled) until the
+// write-back stores the whole record.
 template <typename real, int DIM, int NH>
-__device__ __forceinline__ void gather_hold(const RunDev &R, const int32_t *lcr, const Particles<real> &A,
-                                            const Particles<real> &B, int64_t b, int64_t n, real *su, real *sv,
-                                            real *sw, real (&hx)[NH], real (&hy)[NH], real (&hz)[NH]) {
+__device__ __forceinline__ void gather_hold(const RunDev &R, const int32_t *lcr, const Particles<real> &A, int64_t b,
+                                            int64_t n, real *su, real *sv, real *sw, real (&hx)[NH], real (&hy)[NH],
+                                            real (&hz)[NH]) {
   const int lane = threadIdx.x & 63;
   constexpr int U = 4;
   static_assert(NH % U == 0, "whole chunks");
@@ -1584,81 +1564,71 @@ __device__ __forceinline__ void gather_hold(const RunDev &R, const int32_t *lcr,
     int32_t l[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) l[q] = lp[min(k0 + q * kWave + lane, n - 1)];
-    real x[U], y[U], z[U], uu[U], vv[U], ww[U];
+    typename Vec4<real>::type r4[U];
+    real z[U], ww[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       const int64_t src = R.so + (l[q] & kSlotMask);
-      x[q] = A.x[src];
-      y[q] = A.y[src];
+      r4[q] = A.q[src];
       if (DIM == 3) z[q] = A.z[src];
-      uu[q] = A.u[src];
-      vv[q] = A.v[src];
       ww[q] = A.w[src];
     }
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       const int64_t k = k0 + q * kWave + lane;
       const int j = ch * U + q;
-      hx[j] = flown(x[q], uu[q], dt, l[q]);
-      hy[j] = flown(y[q], vv[q], dt, l[q]);
+      hx[j] = flown(r4[q].x, r4[q].z, dt, l[q]);
+      hy[j] = flown(r4[q].y, r4[q].w, dt, l[q]);
       hz[j] = DIM == 3 ? flown(z[q], ww[q], dt, l[q]) : (real)0;
       if (k >= n) continue;
-      const int64_t dst = R.so + b + k;
-      B.x[dst] = hx[j];
-      B.y[dst] = hy[j];
-      if (DIM == 3) B.z[dst] = hz[j];
-      su[k] = uu[q];
-      sv[k] = vv[q];
+      su[k] = r4[q].z;
+      sv[k] = r4[q].w;
       sw[k] = ww[q];
     }
   }
 }
 
-// The look-ahead (next_cells) from the positions gather_hold kept.
+// Write-back of an item gathered by gather_hold: whole records to P' (held
+// positions, final velocities) and, with the look-ahead, each particle's
+// next flight cell.
 template <typename real, int DIM, int NH>
-__device__ __forceinline__ void next_cells_held(const RunDev &R, int32_t *cell, int64_t b, int64_t n,
-                                                const real *u, const real *v, const real *w, const real (&hx)[NH],
-                                                const real (&hy)[NH], const real (&hz)[NH]) {
+__device__ __forceinline__ void write_back_held(const RunDev &R, const Particles<real> &B, int32_t *cell, int64_t b,
+                                                int64_t n, const real *u, const real *v, const real *w,
+                                                const real (&hx)[NH], const real (&hy)[NH], const real (&hz)[NH]) {
   const int lane = threadIdx.x & 63;
   const Flight<real> F(R);
-  int32_t *gc = cell + R.so + b;
+  const bool ahead = R.ahead;
+  const int64_t base = R.so + b;
 #pragma unroll
   for (int j = 0; j < NH; ++j) {
     const int64_t k = (int64_t)j * kWave + lane;
     if (k < n) {
-      const real pos[3] = {hx[j], hy[j], hz[j]};
-      const real vel[3] = {u[k], v[k], DIM == 3 ? w[k] : (real)0};
-      gc[k] = flight_cell<real, DIM>(F, pos, vel);
+      B.q[base + k] = make_vec4<real>(hx[j], hy[j], u[k], v[k]);
+      if (DIM == 3) B.z[base + k] = hz[j];
+      B.w[base + k] = w[k];
+      if (ahead) {
+        const real pos[3] = {hx[j], hy[j], hz[j]};
+        const real vel[3] = {u[k], v[k], DIM == 3 ? w[k] : (real)0};
+        cell[base + k] = flight_cell<real, DIM>(F, pos, vel);
+      }
     }
   }
 }
 
-template <typename real>
-__device__ __forceinline__ void store_velocities(const RunDev &R, const Particles<real> &B, int64_t b, int64_t n,
-                                                 const real *su, const real *sv, const real *sw) {
-  const int lane = threadIdx.x & 63;
-  for (int64_t k = lane; k < n; k += kWave) {
-    const int64_t dst = R.so + b + k;
-    B.u[dst] = su[k];
-    B.v[dst] = sv[k];
-    B.w[dst] = sw[k];
-  }
-}
-
 // Look-ahead for the next step's Motion over P' positions [b, b+n) of a run
-// (this thread's share: t, t + nt, ...): the cell each particle's next free
-// flight ends in, or the queue mark, from its final position (read back: this
-// same thread wrote it to P' in the gather) and final velocity (u, v, w: the
-// LDS stage or P').
+// whose particles are complete in P' (this thread's share: t, t + nt, ...,
+// the same thread that wrote them): the cell each particle's next free
+// flight ends in, or the queue mark.
 template <typename real, int DIM>
 __device__ __forceinline__ void next_cells(const RunDev &R, const Particles<real> &B, int32_t *cell, int64_t b,
-                                           int64_t n, const real *u, const real *v, const real *w, int t, int nt) {
+                                           int64_t n, int t, int nt) {
   const Flight<real> F(R);
   const int64_t base = R.so + b;
   for (int64_t k = t; k < n; k += nt) {
     const int64_t dst = base + k;
-    const real pos[3] = {B.x[dst], B.y[dst], DIM == 3 ? B.z[dst] : (real)0};
-    const real vel[3] = {u[k], v[k], DIM == 3 ? w[k] : (real)0};
+    const typename Vec4<real>::type r4 = B.q[dst];
+    const real pos[3] = {r4.x, r4.y, DIM == 3 ? B.z[dst] : (real)0};
+    const real vel[3] = {r4.z, r4.w, DIM == 3 ? B.w[dst] : (real)0};
     cell[dst] = flight_cell<real, DIM>(F, pos, vel);
   }
 }
@@ -1687,8 +1657,8 @@ __global__ __launch_bounds__(kCollideWaves * 64) void k_collide(DevPtrs<real> d,
   const bool in_lds = n <= CAP;
   constexpr int NH = (CAP + 4 * kWave - 1) / (4 * kWave) * 4;
   real hx[NH], hy[NH], hz[NH];
-  if (in_lds) gather_hold<real, DIM, NH>(R, d.lcr, A, B, b0, n, su, sv, sw, hx, hy, hz);
-  else gather_through_lcr<real, DIM>(R, d.lcr, A, B, b0, n, false, su, sv, sw);
+  if (in_lds) gather_hold<real, DIM, NH>(R, d.lcr, A, b0, n, su, sv, sw, hx, hy, hz);
+  else gather_to_p<real, DIM>(R, d.lcr, A, B, b0, n);
   if (in_lds) wave_sync();
   else global_sync_wave();
   const uint32_t step = *d.step;
@@ -1699,24 +1669,27 @@ __global__ __launch_bounds__(kCollideWaves * 64) void k_collide(DevPtrs<real> d,
     const int64_t gc = R.co + c;
     const int64_t cb = (int64_t)d.bin_start[R.bo + c] - b0;
     const int64_t N = (int64_t)d.bin_start[R.bo + c + 1] - b0 - cb;
-    real *u = in_lds ? su + cb : B.u + R.so + b0 + cb;
-    real *v = in_lds ? sv + cb : B.v + R.so + b0 + cb;
-    real *w = in_lds ? sw + cb : B.w + R.so + b0 + cb;
     real gm = d.gmax[gc], rem = d.rem_c[gc];
     const int64_t nsel = ntc_selections<real>(R, N, gm, rem, d.err);
-    const uint32_t ncol = chain_serial<real>(R, step, (uint32_t)c, (uint32_t)N, 0, nsel, u, v, w, gm);
+    uint32_t ncol;
+    if (in_lds) {
+      ncol = chain_serial<real>(R, step, (uint32_t)c, (uint32_t)N, 0, nsel, su + cb, sv + cb, sw + cb, gm);
+      if (sample) sample_cell(su + cb, sv + cb, sw + cb, N, d.stage + gc * kFields);
+    } else {
+      const int64_t o = R.so + b0 + cb;
+      ncol = chain_serial<real>(R, step, (uint32_t)c, (uint32_t)N, 0, nsel, B.u() + o, B.v() + o, B.w + o, gm);
+      if (sample) sample_cell(B.u() + o, B.v() + o, B.w + o, N, d.stage + gc * kFields);
+    }
     d.gmax[gc] = gm;
     d.rem_c[gc] = rem;
     d.ncoll[gc] += ncol;
-    if (sample) sample_cell(u, v, w, N, d.stage + gc * kFields);
   }
   if (in_lds) {
     wave_sync();
-    store_velocities<real>(R, B, b0, n, su, sv, sw);
-    if (R.ahead) next_cells_held<real, DIM, NH>(R, d.cell, b0, n, su, sv, sw, hx, hy, hz);
+    write_back_held<real, DIM, NH>(R, B, d.cell, b0, n, su, sv, sw, hx, hy, hz);
   } else if (R.ahead) {
     global_sync_wave();  // every lane's chain on P' is visible
-    next_cells<real, DIM>(R, B, d.cell, b0, n, B.u + R.so + b0, B.v + R.so + b0, B.w + R.so + b0, lane, kWave);
+    next_cells<real, DIM>(R, B, d.cell, b0, n, lane, kWave);
   }
 }
 
@@ -1931,7 +1904,8 @@ __global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, 
   const uint32_t step = *d.step;
   const bool sample = *d.sample_slot >= 0;
   real gm = d.gmax[gc], rem = d.rem_c[gc];
-  // gather through LCR: positions to P', velocities to LDS (or P')
+  // gather through LCR: whole records to P' (their velocities are replaced at
+  // the write-back of an LDS item), velocities to LDS
   {
     constexpr int U = 4;
     const real dt = in_precision<real>(R.dt, R.dt_f);
@@ -1946,15 +1920,13 @@ __global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, 
         ent[q] = ok[q] ? d.lcr[R.so + b0 + k] : 0;
         sidx[q] = R.so + (ent[q] & kSlotMask);
       }
-      real x[U], y[U], z[U], uu[U], vv[U], ww[U];
+      typename Vec4<real>::type r4[U];
+      real z[U], ww[U];
 #pragma unroll
       for (int q = 0; q < U; ++q) {
         if (ok[q]) {
-          x[q] = A.x[sidx[q]];
-          y[q] = A.y[sidx[q]];
+          r4[q] = A.q[sidx[q]];
           if (DIM == 3) z[q] = A.z[sidx[q]];
-          uu[q] = A.u[sidx[q]];
-          vv[q] = A.v[sidx[q]];
           ww[q] = A.w[sidx[q]];
         }
       }
@@ -1963,16 +1935,14 @@ __global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, 
         if (!ok[q]) continue;
         const int64_t k = k0 + q * 256 + tid;
         const int64_t dst = R.so + b0 + k;
-        B.x[dst] = flown(x[q], uu[q], dt, ent[q]);
-        B.y[dst] = flown(y[q], vv[q], dt, ent[q]);
+        B.q[dst] = make_vec4<real>(flown(r4[q].x, r4[q].z, dt, ent[q]), flown(r4[q].y, r4[q].w, dt, ent[q]),
+                                   r4[q].z, r4[q].w);
         if (DIM == 3) B.z[dst] = flown(z[q], ww[q], dt, ent[q]);
         if (in_lds) {
-          su[k] = uu[q];
-          sv[k] = vv[q];
+          su[k] = r4[q].z;
+          sv[k] = r4[q].w;
           sw[k] = ww[q];
         } else {
-          B.u[dst] = uu[q];
-          B.v[dst] = vv[q];
           B.w[dst] = ww[q];
         }
       }
@@ -1980,36 +1950,31 @@ __global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, 
   }
   __syncthreads();
   const int64_t nsel = ntc_selections<real>(R, n, gm, rem, d.err);
-  real *u = in_lds ? su : B.u + R.so + b0;
-  real *v = in_lds ? sv : B.v + R.so + b0;
-  real *w = in_lds ? sw : B.w + R.so + b0;
+  const Strided<real> gu = B.u() + (R.so + b0), gv = B.v() + (R.so + b0);
+  real *gw = B.w + R.so + b0;
   uint32_t ncol = 0;
   if (in_lds) {
     ncol = chain_block<real>(R, step, (uint32_t)c, (uint32_t)n, nsel, su, sv, sw, own, sh, gm);
   } else {
     if (tid == 0) {
-      ncol = chain_serial<real>(R, step, (uint32_t)c, (uint32_t)n, 0, nsel, u, v, w, gm);
+      ncol = chain_serial<real>(R, step, (uint32_t)c, (uint32_t)n, 0, nsel, gu, gv, gw, gm);
       sh.gm = gm;
     }
     __syncthreads();
     gm = sh.gm;
   }
   __syncthreads();
-  if (in_lds) {
+  if (in_lds)
     for (int64_t k = tid; k < n; k += 256) {
-      const int64_t dst = R.so + b0 + k;
-      B.u[dst] = su[k];
-      B.v[dst] = sv[k];
-      B.w[dst] = sw[k];
+      gu[k] = su[k];
+      gv[k] = sv[k];
+      gw[k] = sw[k];
     }
-    if (R.ahead) next_cells<real, DIM>(R, B, d.cell, b0, n, su, sv, sw, tid, 256);
-  } else if (R.ahead) {
-    next_cells<real, DIM>(R, B, d.cell, b0, n, B.u + R.so + b0, B.v + R.so + b0, B.w + R.so + b0, tid, 256);
-  }
+  if (R.ahead) next_cells<real, DIM>(R, B, d.cell, b0, n, tid, 256);  // this thread's own records
   if (sample) {
     double sm[kFields] = {0, 0, 0, 0, 0, 0, 0};
-    for (int64_t k = tid; k < n; k += 256) {
-      const double a = (double)u[k], b = (double)v[k], e = (double)w[k];
+    auto add = [&](real uu, real vv, real ww) {
+      const double a = (double)uu, b = (double)vv, e = (double)ww;
       sm[0] += 1.0;
       sm[1] += a;
       sm[2] += b;
@@ -2017,7 +1982,11 @@ __global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, 
       sm[4] += a * a;
       sm[5] += b * b;
       sm[6] += e * e;
-    }
+    };
+    if (in_lds)
+      for (int64_t k = tid; k < n; k += 256) add(su[k], sv[k], sw[k]);
+    else
+      for (int64_t k = tid; k < n; k += 256) add(gu[k], gv[k], gw[k]);
 #pragma unroll
     for (int f = 0; f < kFields; ++f) {
       double x = sm[f];
@@ -2064,30 +2033,28 @@ __global__ __launch_bounds__(256) void k_collide_wave(DevPtrs<real> d, int src, 
   const Particles<real> A = d.P[src], B = d.P[1 - src];
   constexpr int NH = (CAP + 4 * kWave - 1) / (4 * kWave) * 4;
   real hx[NH], hy[NH], hz[NH];
-  if (in_lds) gather_hold<real, DIM, NH>(R, d.lcr, A, B, b0, n, su, sv, sw, hx, hy, hz);
-  else gather_through_lcr<real, DIM>(R, d.lcr, A, B, b0, n, false, su, sv, sw);
+  if (in_lds) gather_hold<real, DIM, NH>(R, d.lcr, A, b0, n, su, sv, sw, hx, hy, hz);
+  else gather_to_p<real, DIM>(R, d.lcr, A, B, b0, n);
   if (in_lds) WaveSync::bar();
   else global_sync_wave();
   const uint32_t step = *d.step;
   const bool sample = *d.sample_slot >= 0;
   real gm = d.gmax[gc], rem = d.rem_c[gc];
   const int64_t nsel = ntc_selections<real>(R, n, gm, rem, d.err);
-  real *u = in_lds ? su : B.u + R.so + b0;
-  real *v = in_lds ? sv : B.v + R.so + b0;
-  real *w = in_lds ? sw : B.w + R.so + b0;
   uint32_t ncol = 0;
   if (in_lds) {
     ncol = chain_block<real, WaveSync>(R, step, (uint32_t)c, (uint32_t)n, nsel, su, sv, sw, own[wave], shs[wave],
                                        gm);
     WaveSync::bar();
-    store_velocities<real>(R, B, b0, n, su, sv, sw);
-    if (R.ahead) next_cells_held<real, DIM, NH>(R, d.cell, b0, n, su, sv, sw, hx, hy, hz);
+    write_back_held<real, DIM, NH>(R, B, d.cell, b0, n, su, sv, sw, hx, hy, hz);
+    if (sample) sample_cell_wave(su, sv, sw, n, d.stage + gc * kFields);
   } else {
-    if (lane == 0) ncol = chain_serial<real>(R, step, (uint32_t)c, (uint32_t)n, 0, nsel, u, v, w, gm);
+    const int64_t o = R.so + b0;
+    if (lane == 0) ncol = chain_serial<real>(R, step, (uint32_t)c, (uint32_t)n, 0, nsel, B.u() + o, B.v() + o, B.w + o, gm);
     global_sync_wave();
-    if (R.ahead) next_cells<real, DIM>(R, B, d.cell, b0, n, u, v, w, lane, kWave);
+    if (R.ahead) next_cells<real, DIM>(R, B, d.cell, b0, n, lane, kWave);
+    if (sample) sample_cell_wave(B.u() + o, B.v() + o, B.w + o, n, d.stage + gc * kFields);
   }
-  if (sample) sample_cell_wave(u, v, w, n, d.stage + gc * kFields);
   if (lane == 0) {
     d.gmax[gc] = gm;
     d.rem_c[gc] = rem;
@@ -2169,11 +2136,12 @@ __device__ __forceinline__ void pipe_gather(const int32_t *lcr, const Particles<
 #pragma unroll
     for (int q = 0; q < kPipeChunks; ++q) {
       const int64_t sidx = m.so + (pr.l[q] & kSlotMask);  // a valid slot beyond n (unused)
-      pr.x[q] = A.x[sidx];
-      pr.y[q] = A.y[sidx];
+      const float4 r4 = A.q[sidx];
+      pr.x[q] = r4.x;
+      pr.y[q] = r4.y;
+      pr.u[q] = r4.z;
+      pr.v[q] = r4.w;
       if (DIM == 3) pr.z[q] = A.z[sidx];
-      pr.u[q] = A.u[sidx];
-      pr.v[q] = A.v[sidx];
       pr.w[q] = A.w[sidx];
     }
   } else {
@@ -2181,12 +2149,10 @@ __device__ __forceinline__ void pipe_gather(const int32_t *lcr, const Particles<
       const int32_t e = lcr[m.so + m.b0 + k];
       const int64_t sidx = m.so + (e & kSlotMask);
       const int64_t dst = m.so + m.b0 + k;
-      const float u = A.u[sidx], v = A.v[sidx], w = A.w[sidx];
-      B.x[dst] = flown(A.x[sidx], u, m.dt, e);
-      B.y[dst] = flown(A.y[sidx], v, m.dt, e);
+      const float4 r4 = A.q[sidx];
+      const float w = A.w[sidx];
+      B.q[dst] = make_vec4<float>(flown(r4.x, r4.z, m.dt, e), flown(r4.y, r4.w, m.dt, e), r4.z, r4.w);
       if (DIM == 3) B.z[dst] = flown(A.z[sidx], w, m.dt, e);
-      B.u[dst] = u;
-      B.v[dst] = v;
       B.w[dst] = w;
     }
   }
@@ -2194,8 +2160,8 @@ __device__ __forceinline__ void pipe_gather(const int32_t *lcr, const Particles<
 
 // An LDS item's gathered particles: positions to P', velocities to LDS.
 template <int DIM>
-__device__ __forceinline__ void pipe_place(const Particles<float> &B, const PipeMeta &m, const PipeRegs &pr,
-                                           float *su, float *sv, float *sw, PipePos &pp) {
+__device__ __forceinline__ void pipe_place(const PipeMeta &m, const PipeRegs &pr, float *su, float *sv, float *sw,
+                                           PipePos &pp) {
   if (m.n > kCollideCapF32) return;
   const int tid = threadIdx.x;
 #pragma unroll
@@ -2205,10 +2171,6 @@ __device__ __forceinline__ void pipe_place(const Particles<float> &B, const Pipe
     pp.y[q] = flown(pr.y[q], pr.v[q], m.dt, pr.l[q]);
     pp.z[q] = DIM == 3 ? flown(pr.z[q], pr.w[q], m.dt, pr.l[q]) : 0.0f;
     if (k < m.n) {
-      const int64_t dst = m.so + m.b0 + k;
-      B.x[dst] = pp.x[q];
-      B.y[dst] = pp.y[q];
-      if (DIM == 3) B.z[dst] = pp.z[q];
       su[k] = pr.u[q];
       sv[k] = pr.v[q];
       sw[k] = pr.w[q];
@@ -2229,7 +2191,8 @@ __device__ __forceinline__ void pipe_collide(const DevPtrs<float> &d, const Part
   float gm = m.gm, rem = m.rem;
   const int64_t nsel = ntc_selections<float>(m.rv, n, gm, rem, d.err);
   uint32_t ncol = 0;
-  float *gu = B.u + m.so + m.b0, *gv = B.v + m.so + m.b0, *gw = B.w + m.so + m.b0;
+  const Strided<float> gu = B.u() + (m.so + m.b0), gv = B.v() + (m.so + m.b0);
+  float *gw = B.w + m.so + m.b0;
   if (lds) {
     ncol = chain_block<float, LdsSync>(m.rv, step, (uint32_t)m.c, (uint32_t)n, nsel, su, sv, sw, own, sh, gm);
   } else {
@@ -2243,27 +2206,26 @@ __device__ __forceinline__ void pipe_collide(const DevPtrs<float> &d, const Part
   }
   LdsSync::bar();
   if (lds) {
-    for (int64_t k = tid; k < n; k += 256) {
-      gu[k] = su[k];
-      gv[k] = sv[k];
-      gw[k] = sw[k];
-    }
-    if (m.ahead) {
-      // the positions this thread placed are still in its registers
-      const Flight<float> F(*m.run);
-      int32_t *gc = d.cell + m.so + m.b0;
+    // whole records from the positions this thread placed (still in its
+    // registers) and the final velocities, and the look-ahead
+    const Flight<float> F(*m.run);
+    const int64_t base = m.so + m.b0;
 #pragma unroll
-      for (int q = 0; q < kPipeChunks; ++q) {
-        const int64_t k = q * 256 + tid;
-        if (k < n) {
+    for (int q = 0; q < kPipeChunks; ++q) {
+      const int64_t k = q * 256 + tid;
+      if (k < n) {
+        B.q[base + k] = make_vec4<float>(pp.x[q], pp.y[q], su[k], sv[k]);
+        if (DIM == 3) B.z[base + k] = pp.z[q];
+        gw[k] = sw[k];
+        if (m.ahead) {
           const float pos[3] = {pp.x[q], pp.y[q], pp.z[q]};
           const float vel[3] = {su[k], sv[k], sw[k]};
-          gc[k] = flight_cell<float, DIM>(F, pos, vel);
+          d.cell[base + k] = flight_cell<float, DIM>(F, pos, vel);
         }
       }
     }
   } else if (m.ahead) {
-    next_cells<float, DIM>(*m.run, B, d.cell, m.b0, n, gu, gv, gw, tid, 256);
+    next_cells<float, DIM>(*m.run, B, d.cell, m.b0, n, tid, 256);
   }
   if (sample) {
     // LDS and global are summed by separate loops: a pointer to either would
@@ -2345,7 +2307,7 @@ __global__ __launch_bounds__(256) void k_collide_pipe(DevPtrs<float> d, int src,
   pipe_gather<DIM>(d.lcr, A, B, m, true, pr);
   // positions to P', velocities to LDS (the gathers return here)
   PipePos pp;
-  pipe_place<DIM>(B, m, pr, vel, vel + CAP, vel + 2 * CAP, pp);
+  pipe_place<DIM>(m, pr, vel, vel + CAP, vel + 2 * CAP, pp);
   if (m.n > CAP) __threadfence_block();
   LdsSync::bar();
   pipe_collide<DIM>(d, B, m, pp, vel, vel + CAP, vel + 2 * CAP, own, sh, step, sample);
@@ -2361,7 +2323,7 @@ __global__ __launch_bounds__(256) void k_sample_cells(DevPtrs<real> d, int buf, 
   const int64_t b = d.bin_start[R.bo + c];
   const int64_t N = (int64_t)d.bin_start[R.bo + c + 1] - b;
   const Particles<real> P = d.P[buf];
-  sample_cell(P.u + R.so + b, P.v + R.so + b, P.w + R.so + b, N, d.stage + gc * kFields);
+  sample_cell(P.u() + (R.so + b), P.v() + (R.so + b), P.w + R.so + b, N, d.stage + gc * kFields);
 }
 
 // acc[slot][eg][c][f] += sum over the runs of (ensemble, group) eg, in run order.
@@ -2533,8 +2495,9 @@ __global__ __launch_bounds__(256) void k_next_cells(DevPtrs<real> d, int buf, in
     const int r = d.tile_run[i / tile];
     const RunDev &R = d.runs[r];
     if (i - R.so >= d.n_alive[r]) continue;
-    const real pos[3] = {P.x[i], P.y[i], DIM == 3 ? P.z[i] : (real)0};
-    const real vel[3] = {P.u[i], P.v[i], DIM == 3 ? P.w[i] : (real)0};
+    const typename Vec4<real>::type r4 = P.q[i];
+    const real pos[3] = {r4.x, r4.y, DIM == 3 ? P.z[i] : (real)0};
+    const real vel[3] = {r4.z, r4.w, DIM == 3 ? P.w[i] : (real)0};
     d.cell[i] = flight_cell<real, DIM>(Flight<real>(R), pos, vel);
   }
 }
