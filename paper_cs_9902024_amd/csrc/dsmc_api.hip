@@ -41,7 +41,7 @@ struct Plan {
   size_t off_runs, off_tile_run, off_face_run, off_cgroup_run, off_inflow, off_gen_blk, off_eg_start, off_eg_runs,
       off_eg_acc,
       off_eg_nc, off_samples, off_items, off_cell_items, off_wave_items, off_solid;
-  size_t off_P[2][3];  // per buffer: records (x, y, u, v), z (3-D only), w
+  size_t off_P[2][2];  // per buffer: records (x, y, u, v); w (2-D) or (z, w) pairs (3-D)
   size_t off_cell, off_lcr, off_lcr_tmp, off_hist, off_tot, off_bin_start, off_remc, off_gmax, off_ncoll, off_remf,
       off_gencnt, off_stage, off_acc, off_mom, off_nalive, off_nsorted, off_ngen, off_scalars, off_wallq, off_wallq_n,
       off_key_tmp, off_bitem, off_bitem_run, off_bfirst;
@@ -455,8 +455,7 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
   P.off_solid = take(P.solid.size());
   for (int b = 0; b < 2; ++b) {
     P.off_P[b][0] = take(4 * es * g.n_slots);
-    P.off_P[b][1] = g.dim == 2 ? (size_t)-1 : take(es * g.n_slots);
-    P.off_P[b][2] = take(es * g.n_slots);
+    P.off_P[b][1] = take((g.dim == 3 ? 2 : 1) * es * g.n_slots);
   }
   P.off_cell = take(4 * g.n_slots);
   P.off_lcr = take(4 * g.n_slots);
@@ -506,8 +505,8 @@ DevPtrs<real> carve(const Plan &P, char *base) {
   d.solid = (const uint8_t *)(base + P.off_solid);
   for (int b = 0; b < 2; ++b) {
     d.P[b].q = (typename Vec4<real>::type *)(base + P.off_P[b][0]);
-    d.P[b].z = P.off_P[b][1] == (size_t)-1 ? nullptr : (real *)(base + P.off_P[b][1]);
-    d.P[b].w = (real *)(base + P.off_P[b][2]);
+    d.P[b].w = P.g.dim == 3 ? nullptr : (real *)(base + P.off_P[b][1]);
+    d.P[b].zw = P.g.dim == 3 ? (typename Vec2<real>::type *)(base + P.off_P[b][1]) : nullptr;
   }
   d.cell = (int32_t *)(base + P.off_cell);
   d.lcr = (int32_t *)(base + P.off_lcr);
@@ -938,20 +937,21 @@ dsmc_status get_state_t(dsmc_ctx *c, const DevPtrs<real> &d, int32_t run, double
   if (!out) return DSMC_OK;
   if (cap < na) return set_err(c, DSMC_ESIZE, "output too small");
   const Particles<real> &P = d.P[c->buf];
-  std::vector<real> rec((size_t)std::max(4 * na, 1)), z((size_t)std::max(na, 1)), w((size_t)std::max(na, 1));
+  const int nr = P.zw ? 2 : 1;  // the rest: w, or (z, w)
+  std::vector<real> rec((size_t)std::max(4 * na, 1)), rest((size_t)std::max(nr * na, 1));
   if (na) st = download<real>(c, rec.data(), (const real *)(P.q + R.so), 4 * (size_t)na);
-  if (!st && na && P.z) st = download<real>(c, z.data(), P.z + R.so, (size_t)na);
-  if (!st && na) st = download<real>(c, w.data(), P.w + R.so, (size_t)na);
+  if (!st && na)
+    st = download<real>(c, rest.data(), P.zw ? (const real *)(P.zw + R.so) : P.w + R.so, (size_t)nr * na);
   if (!st) st = sync_ctx(c);
   if (st) return st;
   // records hold (x, y, u, v); the output is x, y, z, u, v, w
   for (int64_t i = 0; i < na; ++i) {
     out[0 * (size_t)na + i] = (double)rec[4 * i];
     out[1 * (size_t)na + i] = (double)rec[4 * i + 1];
-    out[2 * (size_t)na + i] = P.z ? (double)z[i] : 0.0;
+    out[2 * (size_t)na + i] = P.zw ? (double)rest[2 * i] : 0.0;
     out[3 * (size_t)na + i] = (double)rec[4 * i + 2];
     out[4 * (size_t)na + i] = (double)rec[4 * i + 3];
-    out[5 * (size_t)na + i] = (double)w[i];
+    out[5 * (size_t)na + i] = (double)rest[(size_t)nr * i + nr - 1];
   }
   return DSMC_OK;
 }
@@ -964,23 +964,22 @@ dsmc_status set_state_t(dsmc_ctx *c, const DevPtrs<real> &d, int32_t run, const 
   if (st) return st;
   const Particles<real> &P = d.P[c->buf];
   const size_t m = (size_t)std::max<int64_t>(n, 1);
-  std::vector<real> rec(4 * m), z(m), w(m);
+  const int nr = P.zw ? 2 : 1;  // the rest: w, or (z, w)
+  std::vector<real> rec(4 * m), rest(nr * m);
   for (int64_t i = 0; i < n; ++i) {
     rec[4 * i] = (real)in[0 * (size_t)n + i];
     rec[4 * i + 1] = (real)in[1 * (size_t)n + i];
     rec[4 * i + 2] = (real)in[3 * (size_t)n + i];
     rec[4 * i + 3] = (real)in[4 * (size_t)n + i];
-    z[i] = (real)in[2 * (size_t)n + i];
-    w[i] = (real)in[5 * (size_t)n + i];
+    if (P.zw) rest[2 * i] = (real)in[2 * (size_t)n + i];
+    rest[(size_t)nr * i + nr - 1] = (real)in[5 * (size_t)n + i];
   }
   if (n > 0) {
     st = check_hip(c, hipMemcpyAsync(P.q + R.so, rec.data(), 4 * n * sizeof(real), hipMemcpyHostToDevice, c->stream),
                    "upload state");
-    if (!st && P.z)
-      st = check_hip(c, hipMemcpyAsync(P.z + R.so, z.data(), n * sizeof(real), hipMemcpyHostToDevice, c->stream),
-                     "upload state");
     if (!st)
-      st = check_hip(c, hipMemcpyAsync(P.w + R.so, w.data(), n * sizeof(real), hipMemcpyHostToDevice, c->stream),
+      st = check_hip(c, hipMemcpyAsync(P.zw ? (void *)(P.zw + R.so) : (void *)(P.w + R.so), rest.data(),
+                                       (size_t)nr * n * sizeof(real), hipMemcpyHostToDevice, c->stream),
                      "upload state");
     if (!st) st = check_hip(c, hipStreamSynchronize(c->stream), "sync");
     if (st) return st;

@@ -106,6 +106,9 @@ struct RunDev {
 template <typename real> struct Vec4;
 template <> struct Vec4<float> { using type = float4; };
 template <> struct Vec4<double> { using type = double4; };
+template <typename real> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
 
 template <typename real>
 __host__ __device__ inline typename Vec4<real>::type make_vec4(real a, real b, real c, real d) {
@@ -117,22 +120,24 @@ __host__ __device__ inline typename Vec4<real>::type make_vec4(real a, real b, r
   return t;
 }
 
-// One component of the packed (x, y, u, v) records seen as an array.
-template <typename real>
+// One component of interleaved records seen as an array (S components per
+// record).
+template <typename real, int S = 4>
 struct Strided {
   real *p;
-  __host__ __device__ real &operator[](int64_t i) const { return p[4 * i]; }
-  __host__ __device__ Strided operator+(int64_t k) const { return Strided{p + 4 * k}; }
+  __host__ __device__ real &operator[](int64_t i) const { return p[S * i]; }
+  __host__ __device__ Strided operator+(int64_t k) const { return Strided{p + S * k}; }
 };
 
-// The particle array P: per slot a record (x, y, u, v) and the remaining
-// components z (3-D only) and w.  A particle that changed cell is gathered by
-// Interaction from its old place: with the record it costs two cache lines
-// (record, w) instead of one per component.
+// The particle array P: per slot a record (x, y, u, v) and the rest, w in 2-D
+// or the pair (z, w) in 3-D.  A particle that changed cell is gathered by
+// Interaction from its old place: with the records it costs two cache lines
+// instead of one per component.
 template <typename real>
 struct Particles {
   typename Vec4<real>::type *q;
-  real *z, *w;
+  real *w;                        // 2-D
+  typename Vec2<real>::type *zw;  // 3-D
   __host__ __device__ Strided<real> x() const { return Strided<real>{reinterpret_cast<real *>(q)}; }
   __host__ __device__ Strided<real> y() const { return Strided<real>{reinterpret_cast<real *>(q) + 1}; }
   __host__ __device__ Strided<real> u() const { return Strided<real>{reinterpret_cast<real *>(q) + 2}; }

@@ -177,6 +177,36 @@ __global__ __launch_bounds__(256) void k_init_runs(DevPtrs<real> d, int n_runs) 
 // Uniform Maxwellian fill: slot i draws from (step 0, INIT, i).  Uniforms 0..3
 // are two Box-Muller pairs for the velocity (last output unused), 4..6 the
 // position, drawn again (7..9, ...) while it lies in a solid cell.
+// z and w of slot i (z = 0 in 2-D), and their store.
+template <int DIM, typename real>
+__device__ __forceinline__ void load_zw(const Particles<real> &P, int64_t i, real &z, real &w) {
+  if constexpr (DIM == 3) {
+    const typename Vec2<real>::type t = P.zw[i];
+    z = t.x;
+    w = t.y;
+  } else {
+    z = (real)0;
+    w = P.w[i];
+  }
+}
+template <int DIM, typename real>
+__device__ __forceinline__ void store_zw(const Particles<real> &P, int64_t i, real z, real w) {
+  if constexpr (DIM == 3) {
+    typename Vec2<real>::type t;
+    t.x = z;
+    t.y = w;
+    P.zw[i] = t;
+  } else {
+    P.w[i] = w;
+  }
+}
+// The w components from slot o on, as an array.
+template <int DIM, typename real>
+__device__ __forceinline__ Strided<real, DIM == 3 ? 2 : 1> w_view(const Particles<real> &P, int64_t o) {
+  if constexpr (DIM == 3) return Strided<real, 2>{reinterpret_cast<real *>(P.zw) + 1} + o;
+  else return Strided<real, 1>{P.w} + o;
+}
+
 template <typename real, int DIM>
 __global__ __launch_bounds__(256) void k_init_particles(DevPtrs<real> d, int64_t n_slots, int64_t tile) {
   Particles<real> P = d.P[0];
@@ -193,7 +223,7 @@ __global__ __launch_bounds__(256) void k_init_particles(DevPtrs<real> d, int64_t
     const real st = (real)R.init_sqrtT;
     const real u0 = (real)R.init_U[0] + st * n0;
     const real v0 = (real)R.init_U[1] + st * n1;
-    P.w[i] = (real)R.init_U[2] + st * n2;
+    const real w0 = (real)R.init_U[2] + st * n2;
     real pos[3];
     for (int att = 0;; ++att) {
       if (att == kMaxInitAttempts) {
@@ -207,7 +237,7 @@ __global__ __launch_bounds__(256) void k_init_particles(DevPtrs<real> d, int64_t
       if (!R.has_solid || !d.solid[R.sdo + cell_of<real, DIM>(R, pos)]) break;
     }
     P.q[i] = make_vec4<real>(pos[0], pos[1], u0, v0);
-    if (DIM == 3) P.z[i] = pos[2];
+    store_zw<DIM>(P, i, pos[2], w0);
   }
 }
 
@@ -312,8 +342,7 @@ __device__ __forceinline__ void emit_one(const RunDev &R, uint32_t step, int32_t
   const real x0 = -(u * (real)R.dt) * ((real)1 - ut);
   const real st = (real)R.inflow_sqrtT;
   P.q[o] = make_vec4<real>(x0, y, u, st * t0);
-  if (DIM == 3) P.z[o] = zc;
-  P.w[o] = st * t1;
+  store_zw<DIM>(P, o, zc, st * t1);
 }
 
 // The last index in [lo, hi] whose start is <= t (start[lo] <= t).
@@ -687,8 +716,7 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
   const int64_t npre = R.ahead ? n - d.n_gen[r] : 0;  // cells in place from the last Interaction
   const int64_t begin = tl * tile, end = min(begin + tile, n);
   const typename Vec4<real>::type *__restrict__ Q = d.P[buf].q + R.so;
-  const real *__restrict__ Z = DIM == 3 ? d.P[buf].z + R.so : nullptr;
-  const real *__restrict__ Wv = d.P[buf].w + R.so;
+  const Particles<real> PP = d.P[buf];
   int32_t *__restrict__ cell = d.cell + R.so;
   uint32_t *__restrict__ wq = d.wallq + (int64_t)t * tile;  // this tile's queue segment
   uint32_t qn = 0;
@@ -726,8 +754,9 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
         vy[e] = r4.w;
         act[e] = true;
       }
-      if (DIM == 3) load4(Z, i0, pz);
-      if (DIM == 3) load4(Wv, i0, vz);
+      if (DIM == 3)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) load_zw<DIM>(PP, R.so + i0 + e, pz[e], vz[e]);
     } else {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
@@ -738,8 +767,7 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
           py[e] = r4.y;
           vx[e] = r4.z;
           vy[e] = r4.w;
-          if (DIM == 3) pz[e] = Z[i0 + e];
-          if (DIM == 3) vz[e] = Wv[i0 + e];
+          if (DIM == 3) load_zw<DIM>(PP, R.so + i0 + e, pz[e], vz[e]);
         }
       }
     }
@@ -806,14 +834,16 @@ __global__ __launch_bounds__(256) void k_motion_walls(DevPtrs<real> d, int buf, 
       const int64_t loc = wq[i];
       const int64_t gs = R.so + loc;
       const typename Vec4<real>::type r4 = P.q[gs];
-      real p3[3] = {r4.x, r4.y, DIM == 3 ? P.z[gs] : (real)0};
-      real v3[3] = {r4.z, r4.w, DIM == 3 ? P.w[gs] : (real)0};
+      real z0, w0;
+      load_zw<DIM>(P, gs, z0, w0);
+      real p3[3] = {r4.x, r4.y, z0};
+      real v3[3] = {r4.z, r4.w, DIM == 3 ? w0 : (real)0};
       bool hit, reemit;
       const int32_t c = move_one<real, DIM>(R, d.solid, step, (uint32_t)loc, p3, v3, hit, reemit, d.err);
       // (the velocity is unchanged unless a face was hit)
       P.q[gs] = make_vec4<real>(p3[0], p3[1], v3[0], v3[1]);
-      if (DIM == 3) P.z[gs] = p3[2];
-      if (hit && (DIM == 3 || reemit)) P.w[gs] = v3[2];
+      if (DIM == 3) store_zw<DIM>(P, gs, p3[2], v3[2]);
+      else if (hit && reemit) P.w[gs] = v3[2];
       d.cell[gs] = (int32_t)((uint32_t)c | kMovedBit);  // moved here, not by Interaction
       key = SINGLE ? (uint32_t)c : (((uint32_t)c >> shift0) & (kDigits - 1));
     }
@@ -1528,8 +1558,7 @@ __device__ __forceinline__ void gather_to_p(const RunDev &R, const int32_t *lcr,
     for (int q = 0; q < U; ++q) {
       const int64_t src = R.so + (l[q] & kSlotMask);
       r4[q] = A.q[src];
-      if (DIM == 3) z[q] = A.z[src];
-      ww[q] = A.w[src];
+      load_zw<DIM>(A, src, z[q], ww[q]);
     }
 #pragma unroll
     for (int q = 0; q < U; ++q) {
@@ -1538,8 +1567,7 @@ __device__ __forceinline__ void gather_to_p(const RunDev &R, const int32_t *lcr,
       const int64_t dst = R.so + b + k;
       B.q[dst] = make_vec4<real>(flown(r4[q].x, r4[q].z, dt, l[q]), flown(r4[q].y, r4[q].w, dt, l[q]), r4[q].z,
                                  r4[q].w);
-      if (DIM == 3) B.z[dst] = flown(z[q], ww[q], dt, l[q]);
-      B.w[dst] = ww[q];
+      store_zw<DIM>(B, dst, DIM == 3 ? flown(z[q], ww[q], dt, l[q]) : (real)0, ww[q]);
     }
   }
 }
@@ -1570,8 +1598,7 @@ __device__ __forceinline__ void gather_hold(const RunDev &R, const int32_t *lcr,
     for (int q = 0; q < U; ++q) {
       const int64_t src = R.so + (l[q] & kSlotMask);
       r4[q] = A.q[src];
-      if (DIM == 3) z[q] = A.z[src];
-      ww[q] = A.w[src];
+      load_zw<DIM>(A, src, z[q], ww[q]);
     }
 #pragma unroll
     for (int q = 0; q < U; ++q) {
@@ -1604,8 +1631,7 @@ __device__ __forceinline__ void write_back_held(const RunDev &R, const Particles
     const int64_t k = (int64_t)j * kWave + lane;
     if (k < n) {
       B.q[base + k] = make_vec4<real>(hx[j], hy[j], u[k], v[k]);
-      if (DIM == 3) B.z[base + k] = hz[j];
-      B.w[base + k] = w[k];
+      store_zw<DIM>(B, base + k, hz[j], w[k]);
       if (ahead) {
         const real pos[3] = {hx[j], hy[j], hz[j]};
         const real vel[3] = {u[k], v[k], DIM == 3 ? w[k] : (real)0};
@@ -1627,8 +1653,10 @@ __device__ __forceinline__ void next_cells(const RunDev &R, const Particles<real
   for (int64_t k = t; k < n; k += nt) {
     const int64_t dst = base + k;
     const typename Vec4<real>::type r4 = B.q[dst];
-    const real pos[3] = {r4.x, r4.y, DIM == 3 ? B.z[dst] : (real)0};
-    const real vel[3] = {r4.z, r4.w, DIM == 3 ? B.w[dst] : (real)0};
+    real z, w;
+    load_zw<DIM>(B, dst, z, w);
+    const real pos[3] = {r4.x, r4.y, z};
+    const real vel[3] = {r4.z, r4.w, DIM == 3 ? w : (real)0};
     cell[dst] = flight_cell<real, DIM>(F, pos, vel);
   }
 }
@@ -1677,8 +1705,9 @@ __global__ __launch_bounds__(kCollideWaves * 64) void k_collide(DevPtrs<real> d,
       if (sample) sample_cell(su + cb, sv + cb, sw + cb, N, d.stage + gc * kFields);
     } else {
       const int64_t o = R.so + b0 + cb;
-      ncol = chain_serial<real>(R, step, (uint32_t)c, (uint32_t)N, 0, nsel, B.u() + o, B.v() + o, B.w + o, gm);
-      if (sample) sample_cell(B.u() + o, B.v() + o, B.w + o, N, d.stage + gc * kFields);
+      ncol = chain_serial<real>(R, step, (uint32_t)c, (uint32_t)N, 0, nsel, B.u() + o, B.v() + o, w_view<DIM>(B, o),
+                                gm);
+      if (sample) sample_cell(B.u() + o, B.v() + o, w_view<DIM>(B, o), N, d.stage + gc * kFields);
     }
     d.gmax[gc] = gm;
     d.rem_c[gc] = rem;
@@ -1926,8 +1955,7 @@ __global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, 
       for (int q = 0; q < U; ++q) {
         if (ok[q]) {
           r4[q] = A.q[sidx[q]];
-          if (DIM == 3) z[q] = A.z[sidx[q]];
-          ww[q] = A.w[sidx[q]];
+          load_zw<DIM>(A, sidx[q], z[q], ww[q]);
         }
       }
 #pragma unroll
@@ -1937,13 +1965,12 @@ __global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, 
         const int64_t dst = R.so + b0 + k;
         B.q[dst] = make_vec4<real>(flown(r4[q].x, r4[q].z, dt, ent[q]), flown(r4[q].y, r4[q].w, dt, ent[q]),
                                    r4[q].z, r4[q].w);
-        if (DIM == 3) B.z[dst] = flown(z[q], ww[q], dt, ent[q]);
+        // w goes to P' now, and again at the write-back of an LDS item
+        store_zw<DIM>(B, dst, DIM == 3 ? flown(z[q], ww[q], dt, ent[q]) : (real)0, ww[q]);
         if (in_lds) {
           su[k] = r4[q].z;
           sv[k] = r4[q].w;
           sw[k] = ww[q];
-        } else {
-          B.w[dst] = ww[q];
         }
       }
     }
@@ -1951,7 +1978,7 @@ __global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, 
   __syncthreads();
   const int64_t nsel = ntc_selections<real>(R, n, gm, rem, d.err);
   const Strided<real> gu = B.u() + (R.so + b0), gv = B.v() + (R.so + b0);
-  real *gw = B.w + R.so + b0;
+  const auto gw = w_view<DIM>(B, R.so + b0);
   uint32_t ncol = 0;
   if (in_lds) {
     ncol = chain_block<real>(R, step, (uint32_t)c, (uint32_t)n, nsel, su, sv, sw, own, sh, gm);
@@ -2050,10 +2077,11 @@ __global__ __launch_bounds__(256) void k_collide_wave(DevPtrs<real> d, int src, 
     if (sample) sample_cell_wave(su, sv, sw, n, d.stage + gc * kFields);
   } else {
     const int64_t o = R.so + b0;
-    if (lane == 0) ncol = chain_serial<real>(R, step, (uint32_t)c, (uint32_t)n, 0, nsel, B.u() + o, B.v() + o, B.w + o, gm);
+    if (lane == 0)
+      ncol = chain_serial<real>(R, step, (uint32_t)c, (uint32_t)n, 0, nsel, B.u() + o, B.v() + o, w_view<DIM>(B, o), gm);
     global_sync_wave();
     if (R.ahead) next_cells<real, DIM>(R, B, d.cell, b0, n, lane, kWave);
-    if (sample) sample_cell_wave(B.u() + o, B.v() + o, B.w + o, n, d.stage + gc * kFields);
+    if (sample) sample_cell_wave(B.u() + o, B.v() + o, w_view<DIM>(B, o), n, d.stage + gc * kFields);
   }
   if (lane == 0) {
     d.gmax[gc] = gm;
@@ -2141,8 +2169,7 @@ __device__ __forceinline__ void pipe_gather(const int32_t *lcr, const Particles<
       pr.y[q] = r4.y;
       pr.u[q] = r4.z;
       pr.v[q] = r4.w;
-      if (DIM == 3) pr.z[q] = A.z[sidx];
-      pr.w[q] = A.w[sidx];
+      load_zw<DIM>(A, sidx, pr.z[q], pr.w[q]);
     }
   } else {
     for (int64_t k = tid; k < m.n; k += 256) {
@@ -2150,10 +2177,10 @@ __device__ __forceinline__ void pipe_gather(const int32_t *lcr, const Particles<
       const int64_t sidx = m.so + (e & kSlotMask);
       const int64_t dst = m.so + m.b0 + k;
       const float4 r4 = A.q[sidx];
-      const float w = A.w[sidx];
+      float z, w;
+      load_zw<DIM>(A, sidx, z, w);
       B.q[dst] = make_vec4<float>(flown(r4.x, r4.z, m.dt, e), flown(r4.y, r4.w, m.dt, e), r4.z, r4.w);
-      if (DIM == 3) B.z[dst] = flown(A.z[sidx], w, m.dt, e);
-      B.w[dst] = w;
+      store_zw<DIM>(B, dst, DIM == 3 ? flown(z, w, m.dt, e) : 0.0f, w);
     }
   }
 }
@@ -2192,7 +2219,7 @@ __device__ __forceinline__ void pipe_collide(const DevPtrs<float> &d, const Part
   const int64_t nsel = ntc_selections<float>(m.rv, n, gm, rem, d.err);
   uint32_t ncol = 0;
   const Strided<float> gu = B.u() + (m.so + m.b0), gv = B.v() + (m.so + m.b0);
-  float *gw = B.w + m.so + m.b0;
+  const auto gw = w_view<DIM>(B, m.so + m.b0);
   if (lds) {
     ncol = chain_block<float, LdsSync>(m.rv, step, (uint32_t)m.c, (uint32_t)n, nsel, su, sv, sw, own, sh, gm);
   } else {
@@ -2215,8 +2242,7 @@ __device__ __forceinline__ void pipe_collide(const DevPtrs<float> &d, const Part
       const int64_t k = q * 256 + tid;
       if (k < n) {
         B.q[base + k] = make_vec4<float>(pp.x[q], pp.y[q], su[k], sv[k]);
-        if (DIM == 3) B.z[base + k] = pp.z[q];
-        gw[k] = sw[k];
+        store_zw<DIM>(B, base + k, pp.z[q], sw[k]);
         if (m.ahead) {
           const float pos[3] = {pp.x[q], pp.y[q], pp.z[q]};
           const float vel[3] = {su[k], sv[k], sw[k]};
@@ -2323,7 +2349,10 @@ __global__ __launch_bounds__(256) void k_sample_cells(DevPtrs<real> d, int buf, 
   const int64_t b = d.bin_start[R.bo + c];
   const int64_t N = (int64_t)d.bin_start[R.bo + c + 1] - b;
   const Particles<real> P = d.P[buf];
-  sample_cell(P.u() + (R.so + b), P.v() + (R.so + b), P.w + R.so + b, N, d.stage + gc * kFields);
+  if (P.zw)
+    sample_cell(P.u() + (R.so + b), P.v() + (R.so + b), w_view<3>(P, R.so + b), N, d.stage + gc * kFields);
+  else
+    sample_cell(P.u() + (R.so + b), P.v() + (R.so + b), w_view<2>(P, R.so + b), N, d.stage + gc * kFields);
 }
 
 // acc[slot][eg][c][f] += sum over the runs of (ensemble, group) eg, in run order.
@@ -2496,8 +2525,10 @@ __global__ __launch_bounds__(256) void k_next_cells(DevPtrs<real> d, int buf, in
     const RunDev &R = d.runs[r];
     if (i - R.so >= d.n_alive[r]) continue;
     const typename Vec4<real>::type r4 = P.q[i];
-    const real pos[3] = {r4.x, r4.y, DIM == 3 ? P.z[i] : (real)0};
-    const real vel[3] = {r4.z, r4.w, DIM == 3 ? P.w[i] : (real)0};
+    real z, w;
+    load_zw<DIM>(P, i, z, w);
+    const real pos[3] = {r4.x, r4.y, z};
+    const real vel[3] = {r4.z, r4.w, DIM == 3 ? w : (real)0};
     d.cell[i] = flight_cell<real, DIM>(Flight<real>(R), pos, vel);
   }
 }
