@@ -185,3 +185,36 @@ def test_fp32_tracks_fp64_statistically(dsmc_gpu):
     n32 = sum(int(E32.cell_state(r)["ncoll"].sum()) for r in range(8))
     n64 = sum(int(E64.cell_state(r)["ncoll"].sum()) for r in range(8))
     assert abs(n32 - n64) < 5 * np.sqrt(n64)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("fp64", [True, False])
+def test_state_round_trip(dsmc_gpu, dim, fp64):
+    """A replaced state reads back component for component (the device keeps
+    (x, y, u, v) records plus w, or the (z, w) pair in 3-D), also in a second
+    run of the batch, and stepping from it matches stepping from the same
+    state in a fresh context."""
+    if dim == 2:
+        runs = [W.box(3000, 1, 1, 1, seed=51, grid=(8, 8)).runs[0],
+                replace(W.box(2000, 1, 1, 1, seed=52, grid=(6, 5)).runs[0], run_id=1, ensemble=1)]
+    else:
+        runs = [W.box3d(4000, 1, grid=(5, 4, 3), seed=53).runs[0],
+                replace(W.box3d(3000, 1, grid=(4, 4, 4), seed=54).runs[0], run_id=1, ensemble=1)]
+    rng = np.random.default_rng(7)
+    E = dsmc_gpu.Ensemble(runs, [], state_fp64=fp64)
+    n = 1500
+    st = np.empty((6, n))
+    st[0] = rng.random(n)
+    st[1] = rng.random(n)
+    st[2] = rng.random(n) if dim == 3 else 0.0
+    st[3:] = rng.normal(size=(3, n))
+    if not fp64:
+        st = st.astype(np.float32).astype(np.float64)
+    E.set_state(1, st)
+    np.testing.assert_array_equal(E.state(1), st)
+    E.step(2)
+    F = dsmc_gpu.Ensemble(runs, [], state_fp64=fp64)
+    F.set_state(1, st)
+    F.step(2)
+    np.testing.assert_array_equal(E.state(1), F.state(1))
+    np.testing.assert_array_equal(E.state(0), F.state(0))
