@@ -111,7 +111,8 @@ typedef struct {
   int32_t use_graph;            /* 1: replay each step from a HIP graph (captured on hip_stream, or on a
                                    stream of the library's own ordered after it by events when
                                    hip_stream is the null stream) */
-  int32_t tile_chunks;          /* tuning: 64-slot rounds per indexing tile (0 = default 256) */
+  int32_t tile_chunks;          /* tuning: 64-slot rounds per indexing tile, a multiple of 4 up to
+                                   4096 (0 = default 256) */
   int32_t collide_mode;         /* tuning: 0 auto, 1 one lane per cell (up to 64 cells per
                                    wavefront), 2 one 256-thread block per cell, 3 one 64-lane
                                    wavefront per cell; auto takes 3 when the expected particles

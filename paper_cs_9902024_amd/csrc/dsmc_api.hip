@@ -62,6 +62,8 @@ dsmc_status validate(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_optio
   if (opt) {
     if (opt->n_groups < 0 || opt->n_samples < 0) return fail(msg, DSMC_EINVAL, "negative n_groups or n_samples");
     if (opt->tile_chunks < 0 || opt->tile_chunks > 4096) return fail(msg, DSMC_EINVAL, "tile_chunks out of range");
+    // Motion reads whole rounds of 256 slots, so a tile holds whole rounds
+    if (opt->tile_chunks % 4) return fail(msg, DSMC_EINVAL, "tile_chunks must be a multiple of 4");
     if (opt->collide_mode < 0 || opt->collide_mode > 3) return fail(msg, DSMC_EINVAL, "collide_mode out of range");
     if (opt->n_streams < 0 || opt->n_streams > kMaxLanes) return fail(msg, DSMC_EINVAL, "n_streams out of range");
   }

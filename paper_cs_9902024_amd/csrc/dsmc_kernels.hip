@@ -688,6 +688,41 @@ __device__ __forceinline__ void store4(real *p, int64_t i, const real (&o)[4]) {
   *reinterpret_cast<typename Vec4<real>::type *>(p + i) = t;
 }
 
+// One round of Motion's counting: the new cell of every free particle into
+// the tile histogram, the others (those that reach a face) into the tile's
+// wall queue, in slot order within the round.
+__device__ __forceinline__ void motion_count(uint32_t *h, uint32_t *wq, uint32_t &qn, int64_t i0,
+                                             const uint32_t (&key)[4], const bool (&fast)[4],
+                                             const bool (&act)[4]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) histogram_add(h, key[e], fast[e]);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const bool mine = act[e] && !fast[e];
+    const uint64_t m = __ballot(mine);
+    if (m == 0ull) continue;
+    if (mine) wq[qn + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)(i0 + e);
+    qn += (uint32_t)__popcll(m);
+  }
+}
+
+// A round whose four cells per lane the last Interaction left in place.
+template <bool SINGLE>
+__device__ __forceinline__ void motion_pre_round(uint32_t *h, uint32_t *wq, uint32_t &qn, int64_t i0, int4 c4,
+                                                 int shift0) {
+  const int32_t oc[4] = {c4.x, c4.y, c4.z, c4.w};
+  const bool act[4] = {true, true, true, true};
+  uint32_t key[4];
+  bool fast[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    fast[e] = !(oc[e] & kQueueBit);
+    key[e] = SINGLE ? (uint32_t)oc[e] : (((uint32_t)oc[e] >> shift0) & (kDigits - 1));
+  }
+  motion_count(h, wq, qn, i0, key, fast, act);
+}
+
 // One wavefront per tile of tile_chunks*64 consecutive slots of one run.
 // Each round covers 256 slots, four consecutive ones per lane, read with
 // 128-bit loads (only a run's last, partial round goes slot by slot).  The
@@ -695,7 +730,9 @@ __device__ __forceinline__ void store4(real *p, int64_t i, const real (&o)[4]) {
 // queue mark) in place: for them Motion reads only that.  The others (those
 // generated this step) are tested here and their cell written.  No position
 // is written: Interaction applies the flight when it moves every particle to
-// its sorted place anyway.  Particles that reach a face go to the tile's wall
+// its sorted place anyway.  The rounds whose cells are all in place come
+// first in a tile; they are read four rounds at a time, so that each
+// wavefront keeps four loads in flight.  Particles that reach a face go to the tile's wall
 // queue (k_motion_walls).  The new cell of every free particle is counted in
 // the tile's histogram of the first indexing digit, kept in wave-private LDS.
 template <typename real, int DIM, bool SINGLE, bool OBST>
@@ -722,27 +759,27 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
   uint32_t qn = 0;
   Flight<real> F(R);
   F.solid = OBST && R.has_solid;
-  for (int64_t b = begin; b < end; b += 4 * kWave) {
+  // rounds [begin, pre_end) have every cell in place (a tile is whole rounds)
+  const int64_t pre_n = min(end, npre) - begin;
+  const int64_t pre_end = begin + (pre_n > 0 ? pre_n / (4 * kWave) * (4 * kWave) : 0);
+  constexpr int PU = 4;
+  int64_t b = begin;
+  for (; b + PU * 4 * kWave <= pre_end; b += PU * 4 * kWave) {
+    int4 c4[PU];
+#pragma unroll
+    for (int u = 0; u < PU; ++u) c4[u] = *reinterpret_cast<const int4 *>(cell + b + u * 4 * kWave + 4 * lane);
+#pragma unroll
+    for (int u = 0; u < PU; ++u) motion_pre_round<SINGLE>(h, wq, qn, b + u * 4 * kWave + 4 * lane, c4[u], shift0);
+  }
+  for (; b < pre_end; b += 4 * kWave)
+    motion_pre_round<SINGLE>(h, wq, qn, b + 4 * lane, *reinterpret_cast<const int4 *>(cell + b + 4 * lane), shift0);
+  for (; b < end; b += 4 * kWave) {
     const int64_t i0 = b + 4 * lane;
     const bool full = b + 4 * kWave <= end;  // wave-uniform
     int32_t oc[4];
     uint32_t key[4];
     bool fast[4];
     bool act[4];
-    if (b + 4 * kWave <= npre) {
-      // every cell of the round is in place
-      const int4 c4 = *reinterpret_cast<const int4 *>(cell + i0);
-      oc[0] = c4.x;
-      oc[1] = c4.y;
-      oc[2] = c4.z;
-      oc[3] = c4.w;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        act[e] = true;
-        fast[e] = !(oc[e] & kQueueBit);
-        key[e] = SINGLE ? (uint32_t)oc[e] : (((uint32_t)oc[e] >> shift0) & (kDigits - 1));
-      }
-    } else {
     real px[4], py[4], pz[4], vx[4], vy[4], vz[4];
     if (full) {
 #pragma unroll
@@ -789,18 +826,7 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
       for (int e = 0; e < 4; ++e)
         if (act[e]) cell[i0 + e] = oc[e];
     }
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) histogram_add(h, key[e], fast[e]);
-    // particles that reach a face go to the tile's segment of the wall queue
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const bool mine = act[e] && !fast[e];
-      const uint64_t m = __ballot(mine);
-      if (m == 0ull) continue;
-      if (mine) wq[qn + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)(i0 + e);
-      qn += (uint32_t)__popcll(m);
-    }
+    motion_count(h, wq, qn, i0, key, fast, act);
   }
   if (lane == 0) d.wallq_n[t] = qn;
   wave_sync();

@@ -59,6 +59,17 @@ def test_stream_lane_option_is_validated(dsmc):
         dsmc.dsmc_required_bytes(specs, dsmc.make_options(True, 1, [], n_streams=ok))
 
 
+def test_tile_option_is_validated(dsmc):
+    # a tile is whole rounds of 256 slots: 64-slot chunks in multiples of 4
+    specs = dsmc._specs(W.plain_box().runs)
+    for bad in (-4, 1, 3, 6, 4097, 4100):
+        with pytest.raises(dsmc.DsmcError) as e:
+            dsmc.dsmc_required_bytes(specs, dsmc.make_options(True, 1, [], tile_chunks=bad))
+        assert e.value.status == -1
+    for ok in (0, 4, 8, 64, 4096):
+        dsmc.dsmc_required_bytes(specs, dsmc.make_options(True, 1, [], tile_chunks=ok))
+
+
 def _bytes(dsmc, wl, fp64=False, groups=None):
     specs = dsmc._specs(wl.runs)
     opt = dsmc.make_options(fp64, groups or wl.n_groups, wl.sample_steps)
