@@ -1198,6 +1198,29 @@ __global__ __launch_bounds__(256) void k_bucket_scan(IndexArgs a) {
   }
 }
 
+// A wave's cursor table: cursor[q] = S[q] + M[q] for q < min(D, valid), 0 for
+// the rest of [0, D).  Eight loads of each source per lane are issued before
+// the first is stored, so the table's set-up is not one memory latency per
+// 64 entries.
+__device__ __forceinline__ void init_cursors(uint32_t *cursor, const uint32_t *S, const uint32_t *M, int D,
+                                             int64_t valid) {
+  constexpr int B = 8;
+  const int lane = threadIdx.x & 63;
+  for (int q0 = 0; q0 < D; q0 += B * kWave) {
+    uint32_t v[B];
+#pragma unroll
+    for (int e = 0; e < B; ++e) {
+      const int q = q0 + e * kWave + lane;
+      v[e] = (q < D && q < valid) ? S[q] + M[q] : 0u;
+    }
+#pragma unroll
+    for (int e = 0; e < B; ++e) {
+      const int q = q0 + e * kWave + lane;
+      if (q < D) cursor[q] = v[e];
+    }
+  }
+}
+
 // Rank of each lane among the active lanes holding the same digit (lanes
 // below it) and the size of that group, from one ballot per distinct digit
 // present.  Inactive lanes hold kNoDigit.
@@ -1255,7 +1278,7 @@ __global__ __launch_bounds__(256) void k_scatter(IndexArgs a) {
     const int64_t c0 = (int64_t)h << kDigitBits;
     const uint32_t *S = a.bin_start + R.bo + c0;
     const int64_t last = R.nc - c0;  // digits beyond are no bins of the run
-    for (int q = lane; q < kDigits; q += kWave) cursor[q] = q <= last ? S[q] + M[q] : 0u;
+    init_cursors(cursor, S, M, kDigits, last + 1);
   } else {
     const int t = a.t0 + (int)blockIdx.x * kWavesPerBlock + wave;
     if (t >= a.t1) return;
@@ -1265,7 +1288,7 @@ __global__ __launch_bounds__(256) void k_scatter(IndexArgs a) {
     const int D = single ? R.nc + 1 : kDigits;
     const uint32_t *Mt = a.hist + R.mo + tl * D;
     const uint32_t *S = a.tot + R.cbo;
-    for (int q = lane; q < D; q += kWave) cursor[q] = S[q] + Mt[q];
+    init_cursors(cursor, S, Mt, D, D);
     begin = tl * a.tile;
     end = min(begin + a.tile, (int64_t)a.n_sorted[r]);
   }
