@@ -101,6 +101,16 @@ __device__ __forceinline__ void set_error(int32_t *err, int code) { (void)atomic
 // also wait for it.
 __device__ __forceinline__ int wave_index() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 
+// Block index remapped so that each XCD (blocks are dealt round-robin over
+// the 8 XCDs) works on one contiguous range of items: neighbouring cells read
+// overlapping source ranges of P, and neighbouring tiles write into each
+// other's ranges of the LCR, which then meet in the same L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblk) {
+  const int64_t q = nblk / 8, rmd = nblk % 8;
+  const int64_t x = b % 8, pos = b / 8;
+  return x < rmd ? x * (q + 1) + pos : rmd * (q + 1) + (x - rmd) * q + pos;
+}
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -1268,8 +1278,9 @@ __global__ __launch_bounds__(256) void k_scatter(IndexArgs a) {
   uint32_t *cursor = lds + wave * a.dstride;
   int r;
   int64_t begin, end;
+  const int blk = (int)xcd_block(blockIdx.x, gridDim.x);
   if (BUCKETED) {
-    const int32_t i = a.b0 + (int)blockIdx.x * kWavesPerBlock + wave;
+    const int32_t i = a.b0 + blk * kWavesPerBlock + wave;
     if (i >= a.b1) return;
     int h;
     if (!bucket_item(a, i, r, h, begin, end)) return;
@@ -1280,7 +1291,7 @@ __global__ __launch_bounds__(256) void k_scatter(IndexArgs a) {
     const int64_t last = R.nc - c0;  // digits beyond are no bins of the run
     init_cursors(cursor, S, M, kDigits, last + 1);
   } else {
-    const int t = a.t0 + (int)blockIdx.x * kWavesPerBlock + wave;
+    const int t = a.t0 + blk * kWavesPerBlock + wave;
     if (t >= a.t1) return;
     r = a.tile_run[t];
     const RunDev &R = a.runs[r];
@@ -1426,15 +1437,6 @@ template <> struct LaneCap<double> { static constexpr int value = kLaneCapF64; }
 template <typename real>
 constexpr int collide_wave_bytes() {
   return ((LaneCap<real>::value * 3 * (int)sizeof(real)) + 15) & ~15;
-}
-
-// Block index remapped so that each XCD (blocks are dealt round-robin over
-// the 8 XCDs) works on one contiguous range of items: neighbouring cells read
-// overlapping source ranges of P, which then meet in the same L2.
-__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblk) {
-  const int64_t q = nblk / 8, rmd = nblk % 8;
-  const int64_t x = b % 8, pos = b / 8;
-  return x < rmd ? x * (q + 1) + pos : rmd * (q + 1) + (x - rmd) * q + pos;
 }
 
 template <typename real>
