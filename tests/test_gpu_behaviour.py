@@ -64,6 +64,35 @@ def test_graph_replay_equals_eager(dsmc_gpu, fp64):
 
 
 @pytest.mark.parametrize("fp64,graph", [(False, True), (True, False)])
+def test_tile_size_does_not_change_results(dsmc_gpu, fp64, graph):
+    """Indexing tiles of 1, 3 and 5 rounds of 256 slots give the same runs,
+    cell states and sample sums as the default 64 rounds: Motion's reads of
+    in-place cells four rounds at a time, their remainder, and the switch to
+    generated particles inside a tile (inflow channels) decide nothing about
+    the result; neither do the tile histograms and wall-queue segments.  The
+    64x64-cell box takes the two-level sort."""
+    import torch
+    big = replace(W.box(30_000, 1, 1, 1, seed=9, grid=(64, 64)).runs[0], run_id=50, ensemble=7)
+    small = replace(W.box(3_001, 1, 1, 1, seed=9, grid=(8, 8)).runs[0], run_id=51, ensemble=8)
+    runs = _small_channel_runs(3) + [big, small]
+    ref = dsmc_gpu.Ensemble(runs, [3, 6], state_fp64=fp64, n_groups=2, use_graph=graph)
+    ref.step(6)
+    torch.cuda.synchronize()
+    for tc in (4, 12, 20):
+        E = dsmc_gpu.Ensemble(runs, [3, 6], state_fp64=fp64, n_groups=2, use_graph=graph, tile_chunks=tc)
+        E.step(6)
+        torch.cuda.synchronize()
+        for r in range(len(runs)):
+            np.testing.assert_array_equal(ref.state(r), E.state(r), err_msg=f"tile_chunks {tc} run {r}")
+            np.testing.assert_array_equal(ref.cell_state(r)["ncoll"], E.cell_state(r)["ncoll"])
+        for ens in (0, 7, 8):
+            for k in range(2):
+                np.testing.assert_array_equal(ref.accum(k, ensemble=ens), E.accum(k, ensemble=ens))
+        np.testing.assert_array_equal(ref.counts(), E.counts())
+        E.close()
+
+
+@pytest.mark.parametrize("fp64,graph", [(False, True), (True, False)])
 def test_stream_lanes_do_not_change_results(dsmc_gpu, fp64, graph):
     """The batch split into 2, 3 or 4 run groups stepped concurrently on
     their own streams (one group's Indexing and Interaction overlapping the
