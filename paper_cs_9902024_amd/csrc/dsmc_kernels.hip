@@ -2687,7 +2687,12 @@ static void lane_step(const Geometry &g, const LaneRange &L, const DevPtrs<real>
         TIMED(kKDigCount, hipLaunchKernelGGL(k_digcount_bucket, dim3(iblocks), dim3(256), lds, s, a));
         const int max_nb = (g.max_nc >> kDigitBits) + 1;
         TIMED(kKBucketScan, hipLaunchKernelGGL(k_bucket_scan, dim3(max_nb, n_runs), dim3(256), 0, s, a));
-        TIMED(kKScatter, hipLaunchKernelGGL((k_scatter<false, true, true>), dim3(iblocks), dim3(256), lds, s, a));
+        // at most three blocks per CU (LDS beyond the cursor tables is
+        // unused): fewer wavefronts writing scattered stretches of the LCR
+        // at once let L2 merge more of those writes into whole lines
+        constexpr size_t kBucketPassLds = 52 * 1024;
+        TIMED(kKScatter, hipLaunchKernelGGL((k_scatter<false, true, true>), dim3(iblocks), dim3(256),
+                                            lds < kBucketPassLds ? kBucketPassLds : lds, s, a));
       }
     } else {
       // bins are carried through the passes: key_tmp and (free after Motion)
