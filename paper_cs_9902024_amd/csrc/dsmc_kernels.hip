@@ -979,8 +979,20 @@ __global__ __launch_bounds__(256) void k_colscan(IndexArgs a) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= D) return;
   uint32_t *col = a.hist + R.mo + q;
+  // one block per 256 digits of a run gives few wavefronts on a large grid,
+  // so each lane keeps 32 rows' loads in flight where it can
   uint32_t sum = 0;
   int t = 0;
+  for (; t + 32 <= R.nt; t += 32) {
+    uint32_t v[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) v[k] = col[(int64_t)(t + k) * D];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+      col[(int64_t)(t + k) * D] = sum;
+      sum += v[k];
+    }
+  }
   for (; t + 8 <= R.nt; t += 8) {
     uint32_t v[8];
 #pragma unroll
