@@ -250,6 +250,28 @@ dsmc_status dsmc_counting_sort_bytes(int64_t n, int32_t nbins, size_t *bytes);
 dsmc_status dsmc_counting_sort(const int32_t *keys, int64_t n, int32_t nbins, int32_t *lcr, uint32_t *start,
                                void *work, size_t work_bytes, void *hip_stream);
 
+/* Largest workspace (dsmc_counting_sort_bytes) dsmc_counting_sort_noalloc
+ * accepts: 32 MiB, e.g. up to 67M keys with at most 2048 bins, or 2.6M keys
+ * with up to 2^22 bins. */
+#define DSMC_SORT_SCRATCH_BYTES ((size_t)32 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * stable counting sort as dsmc_counting_sort, with the same arguments except
+ * the workspace, computing the same lcr and start bit for bit.  Its workspace
+ * is a static device array of DSMC_SORT_SCRATCH_BYTES that the library holds
+ * on every GPU it runs on until the process ends; the call allocates nothing
+ * (no hipMalloc, no allocating library routine).  Returns DSMC_ESIZE, before
+ * anything is enqueued, when dsmc_counting_sort_bytes(n, nbins) exceeds
+ * DSMC_SORT_SCRATCH_BYTES, DSMC_EINVAL for the argument errors of
+ * dsmc_counting_sort, DSMC_EDEVICE when the array's address cannot be found
+ * on the current device.  hip_stream must belong to the current device.
+ * Asynchronous.  Every call on one GPU shares that GPU's array: calls whose
+ * work overlaps on one GPU (two streams, or two host threads) race and give
+ * undefined results; calls queued on one stream are ordered and safe. */
+dsmc_status dsmc_counting_sort_noalloc(const int32_t *keys, int64_t n, int32_t nbins, int32_t *lcr,
+                                       uint32_t *start, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

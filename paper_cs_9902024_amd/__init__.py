@@ -32,7 +32,7 @@ EXPORTS = ("dsmc_required_bytes", "dsmc_init_runs", "dsmc_step", "dsmc_sample", 
            "dsmc_get_state", "dsmc_set_state", "dsmc_get_lcr", "dsmc_get_cell_state",
            "dsmc_get_counts", "dsmc_counting_sort_bytes", "dsmc_counting_sort",
            "dsmc_set_profiling", "dsmc_kernel_times", "dsmc_kernel_name", "dsmc_autotune_bytes",
-           "dsmc_autotune")
+           "dsmc_autotune", "dsmc_counting_sort_noalloc")
 NKERNELS = 19
 NINFO = 10
 
@@ -95,6 +95,7 @@ def lib():
         L.dsmc_get_counts.argtypes = [vp, C.POINTER(i64), i32]
         L.dsmc_counting_sort_bytes.argtypes = [i64, i32, C.POINTER(sz)]
         L.dsmc_counting_sort.argtypes = [vp, i64, i32, vp, vp, vp, sz, vp]
+        L.dsmc_counting_sort_noalloc.argtypes = [vp, i64, i32, vp, vp, vp]
         L.dsmc_set_profiling.argtypes = [vp, i32]
         L.dsmc_kernel_times.argtypes = [vp, dp, C.POINTER(i64), i32]
         L.dsmc_kernel_name.argtypes = [i32]
@@ -318,6 +319,16 @@ def dsmc_counting_sort(keys_ptr: int, n: int, nbins: int, lcr_ptr: int, start_pt
     _check(lib().dsmc_counting_sort(C.c_void_p(keys_ptr), n, nbins, C.c_void_p(lcr_ptr),
                                     C.c_void_p(start_ptr), C.c_void_p(work_ptr), work_bytes,
                                     C.c_void_p(stream)), "dsmc_counting_sort")
+
+
+SORT_SCRATCH_BYTES = 32 << 20  # DSMC_SORT_SCRATCH_BYTES
+
+
+def dsmc_counting_sort_noalloc(keys_ptr: int, n: int, nbins: int, lcr_ptr: int, start_ptr: int,
+                               stream: int):
+    _check(lib().dsmc_counting_sort_noalloc(C.c_void_p(keys_ptr), n, nbins, C.c_void_p(lcr_ptr),
+                                            C.c_void_p(start_ptr), C.c_void_p(stream)),
+           "dsmc_counting_sort_noalloc")
 
 
 # ---------------------------------------------------------------------------

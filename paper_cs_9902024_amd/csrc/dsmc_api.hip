@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1144,6 +1145,50 @@ dsmc_status dsmc_counting_sort(const int32_t *keys, int64_t n, int32_t nbins, in
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// The counting sort without a caller workspace: its scratch memory is this
+// file-scope device array, one copy per GPU.  On the host its name is only a
+// stand-in; the device address of each GPU's copy comes from
+// hipGetSymbolAddress, taken once per device with that device current, and
+// only that address is ever passed to a kernel.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) unsigned char scratch[DSMC_SORT_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of the current device's copy of `scratch`.
+dsmc_status scratch_of_current_device(void **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxScratchDevices) return DSMC_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return DSMC_EDEVICE;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return DSMC_OK;
+}
+}  // namespace
+
+extern "C" dsmc_status dsmc_counting_sort_noalloc(const int32_t *keys, int64_t n, int32_t nbins, int32_t *lcr,
+                                                  uint32_t *start, void *hip_stream) {
+  if (n < 0 || n >= ((int64_t)1 << 31) || nbins < 1 || !start) return DSMC_EINVAL;
+  if (n > 0 && (!keys || !lcr)) return DSMC_EINVAL;
+  if (counting_sort_workspace(n, nbins, 256) > DSMC_SORT_SCRATCH_BYTES) return DSMC_ESIZE;
+  void *work = nullptr;
+  dsmc_status st = scratch_of_current_device(&work);
+  if (st) return st;
+  // every part of the workspace is written by the sort's kernels before it
+  // is read, so the previous call's contents need no clearing
+  launch_counting_sort(keys, n, nbins, lcr, start, work, 256, (hipStream_t)hip_stream);
+  return hipGetLastError() == hipSuccess ? DSMC_OK : DSMC_EDEVICE;
+}
 
 // ---------------------------------------------------------------------------
 // Autotuning of the tuning fields of dsmc_options

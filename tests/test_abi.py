@@ -181,3 +181,21 @@ def test_no_oracle_in_the_product():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "dsmc_oracle" not in txt and "liboracle" not in txt, f
+
+
+def test_no_alloc_sort_validates_on_the_host(dsmc):
+    # size and argument checks come before any device call (none is made here)
+    assert dsmc.dsmc_counting_sort_bytes(4_000_000, 4097) > dsmc.SORT_SCRATCH_BYTES
+    with pytest.raises(dsmc.DsmcError) as e:
+        dsmc.dsmc_counting_sort_noalloc(8, 4_000_000, 4097, 8, 8, 0)
+    assert e.value.status == -2
+    for n, nbins, start in ((-1, 5, 8), (10, 0, 8), (10, 5, 0)):
+        with pytest.raises(dsmc.DsmcError) as e:
+            dsmc.dsmc_counting_sort_noalloc(8, n, nbins, 8, start, 0)
+        assert e.value.status == -1
+
+
+def test_sort_scratch_size_matches_header(dsmc):
+    src = open(os.path.join(ROOT, "include", "dsmc.h")).read()
+    m = re.search(r"#define DSMC_SORT_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", src)
+    assert m and int(m.group(1)) << int(m.group(2)) == dsmc.SORT_SCRATCH_BYTES
