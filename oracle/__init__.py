@@ -97,7 +97,8 @@ def lib():
                                       dp, dp, dp, dp, dp, P, C.c_int64, C.POINTER(C.c_int64)]
         L.or_collide_cell.restype = C.c_int64
         L.or_ensemble.argtypes = [C.POINTER(OrSpec), C.c_int32, C.c_int32, P, C.c_int32,
-                                  C.c_int32, C.c_int32, dp, C.POINTER(C.c_int64)]
+                                  C.c_int32, C.c_int32, C.c_int32, C.c_int32, dp,
+                                  C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.or_ensemble.restype = C.c_int32
         _lib = L
     return _lib
@@ -318,33 +319,43 @@ def collide_cell(rs, step: int, cell: int, vel: np.ndarray, gmax: float, rem: fl
 
 
 def ensemble(workload, n_threads: int = 0, runs: Optional[Sequence] = None,
-             n_steps: Optional[int] = None, n_groups: Optional[int] = None):
+             n_steps: Optional[int] = None, n_groups: Optional[int] = None,
+             window_steps: Optional[int] = None, window_stride: Optional[int] = None):
     """Runs the outer loop over independent runs.  Returns
-    (acc[n_samples][n_groups][nc][7], stats dict)."""
+    (acc[n_samples][n_groups][nc][7], stats dict); stats["n_snap"][k] is the
+    number of snapshots each run added to slot k (the slot's time window:
+    the steps sample_steps[k] - j * window_stride, j < window_steps)."""
     runs = list(workload.runs if runs is None else runs)
     n_steps = workload.n_steps if n_steps is None else n_steps
     G = workload.n_groups if n_groups is None else n_groups
     G = max(1, min(G, len(runs)))
-    samples = np.array([s for s in workload.sample_steps if s <= n_steps], np.int32)
+    W = getattr(workload, "window_steps", 1) if window_steps is None else window_steps
+    q = getattr(workload, "window_stride", 1) if window_stride is None else window_stride
+    W, q = max(1, W), max(1, q)
+    # slots whose window has started by n_steps
+    samples = np.array([s for s in workload.sample_steps if s - (W - 1) * q <= n_steps], np.int32)
     keep = [make_spec(r) for r in runs]       # holds the masks while the C side copies them
     specs = (OrSpec * len(runs))(*keep)
     nc = runs[0].n_cells
     acc = np.zeros((len(samples), G, nc, NFIELD))
+    nsnap = np.zeros(max(len(samples), 1), np.int64)
     stats = (C.c_int64 * 2)()
     if n_threads <= 0:
         n_threads = len(os.sched_getaffinity(0))
-    rc = lib().or_ensemble(specs, len(runs), n_steps, samples.ctypes.data, len(samples), G,
-                           n_threads, _dp(acc), stats)
+    rc = lib().or_ensemble(specs, len(runs), n_steps, samples.ctypes.data, len(samples), W, q, G,
+                           n_threads, _dp(acc), nsnap.ctypes.data_as(C.POINTER(C.c_int64)), stats)
     if rc:
         raise RuntimeError(f"oracle ensemble failed: {STATUS.get(rc, rc)}")
     return acc, {"particle_steps": stats[0], "collisions": stats[1],
-                 "threads": min(n_threads, G), "sample_steps": samples.tolist()}
+                 "threads": min(n_threads, G), "sample_steps": samples.tolist(),
+                 "n_snap": nsnap[:len(samples)].tolist()}
 
 
-def moments(sums: np.ndarray, n_runs: int) -> np.ndarray:
-    """FP64 division of pooled sums [..., 7] (summed over ``n_runs`` runs) into
-    [..., 8] = n (particles per cell per run), ux, uy, uz, T, Tx, Ty, Tz.
-    Cells with no particles give NaN."""
+def moments(sums: np.ndarray, n_runs: int, n_snap: int = 1) -> np.ndarray:
+    """FP64 division of pooled sums [..., 7] (summed over ``n_runs`` runs and
+    ``n_snap`` snapshots of each run) into [..., 8] = n (particles per cell
+    per run and snapshot), ux, uy, uz, T, Tx, Ty, Tz.  Cells with no
+    particles give NaN."""
     s = np.asarray(sums, dtype=np.float64)
     N = s[..., 0]
     with np.errstate(invalid="ignore", divide="ignore"):
@@ -354,5 +365,5 @@ def moments(sums: np.ndarray, n_runs: int) -> np.ndarray:
         Ty = s[..., 5] * inv - uy * uy
         Tz = s[..., 6] * inv - uz * uz
         T = (Tx + Ty + Tz) / 3.0
-    out = np.stack([N / n_runs, ux, uy, uz, T, Tx, Ty, Tz], axis=-1)
+    out = np.stack([N / (n_runs * n_snap), ux, uy, uz, T, Tx, Ty, Tz], axis=-1)
     return out

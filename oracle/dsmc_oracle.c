@@ -782,7 +782,7 @@ void or_get_face_rem(const or_run *R, double *rem)
 typedef struct {
     const or_spec *specs;
     int32_t n_runs, n_steps, n_samples, n_groups, n_threads, tid;
-    const int32_t *sample_steps;
+    const int32_t *slot_of;   /* [n_steps]: sample slot of step s (index s - 1), or -1 */
     double *acc;              /* [n_samples][n_groups][nc][7] */
     int64_t nc;
     int64_t psteps, ncoll;
@@ -799,14 +799,13 @@ static void *ens_worker(void *arg)
             or_run *R = or_run_new(&J->specs[r], &st);
             if (!R) { J->status = st; free(tmp); return NULL; }
             or_init(R);
-            int32_t ks = 0;
             for (int32_t s = 1; s <= J->n_steps; ++s) {
                 or_step(R);
                 J->psteps += R->last_nmoved;
                 J->ncoll += R->last_ncoll;
                 if (R->err) { J->status = R->err; or_run_free(R); free(tmp); return NULL; }
-                while (ks < J->n_samples && J->sample_steps[ks] < s) ks++;
-                if (ks < J->n_samples && J->sample_steps[ks] == s) {
+                const int32_t ks = J->slot_of[s - 1];
+                if (ks >= 0) {
                     or_sample(R, tmp);
                     double *dst = J->acc + ((size_t)ks * J->n_groups + g) * J->nc * 7;
                     for (int64_t e = 0; e < J->nc * 7; ++e) dst[e] += tmp[e];
@@ -823,15 +822,37 @@ static void *ens_worker(void *arg)
  * per-cell sample sums into group r % n_groups, runs taken in ascending order
  * inside a group (so the result does not depend on n_threads).  All runs must
  * share one grid.  stats[0] = particle-steps (particles moved), stats[1] =
- * collisions. */
+ * collisions.
+ *
+ * Sample slot k holds the snapshots taken after the steps
+ * sample_steps[k] - j * stride, j = 0 .. window - 1 (those >= 1 and
+ * <= n_steps): with window = 1 one moment of the unsteady process (Sec. 1.1,
+ * Fig. 1); with a longer window the time average of a steady flow (an
+ * averaging time much longer than dt, Sec. 1.1) on top of the average over
+ * the runs (end of Sec. 3).  A step may belong to one slot only.  nsnap[k]
+ * receives the number of snapshots each run adds to slot k. */
 int32_t or_ensemble(const or_spec *specs, int32_t n_runs, int32_t n_steps,
-                    const int32_t *sample_steps, int32_t n_samples, int32_t n_groups,
-                    int32_t n_threads, double *acc, int64_t stats[2])
+                    const int32_t *sample_steps, int32_t n_samples, int32_t window,
+                    int32_t stride, int32_t n_groups, int32_t n_threads, double *acc,
+                    int64_t *nsnap, int64_t stats[2])
 {
-    if (n_runs < 1 || n_groups < 1 || n_threads < 1) return OR_EINVAL;
+    if (n_runs < 1 || n_groups < 1 || n_threads < 1 || n_steps < 0 || window < 1 || stride < 1)
+        return OR_EINVAL;
     int64_t nc = (int64_t)specs[0].nx * specs[0].ny * specs[0].nz;
     for (int32_t r = 1; r < n_runs; ++r)
         if ((int64_t)specs[r].nx * specs[r].ny * specs[r].nz != nc) return OR_EINVAL;
+    int32_t *slot_of = (int32_t *)malloc((size_t)(n_steps > 0 ? n_steps : 1) * sizeof(int32_t));
+    for (int32_t s = 0; s < n_steps; ++s) slot_of[s] = -1;
+    for (int32_t k = 0; k < n_samples; ++k) {
+        nsnap[k] = 0;
+        for (int32_t j = 0; j < window; ++j) {
+            const int64_t s = (int64_t)sample_steps[k] - (int64_t)j * stride;
+            if (s < 1 || s > n_steps) continue;
+            if (slot_of[s - 1] >= 0) { free(slot_of); return OR_EINVAL; }
+            slot_of[s - 1] = k;
+            nsnap[k]++;
+        }
+    }
     memset(acc, 0, (size_t)n_samples * n_groups * nc * 7 * sizeof(double));
     if (n_threads > n_groups) n_threads = n_groups;
     ens_job *jobs = (ens_job *)calloc((size_t)n_threads, sizeof(ens_job));
@@ -840,7 +861,7 @@ int32_t or_ensemble(const or_spec *specs, int32_t n_runs, int32_t n_steps,
         ens_job *J = &jobs[t];
         J->specs = specs; J->n_runs = n_runs; J->n_steps = n_steps;
         J->n_samples = n_samples; J->n_groups = n_groups; J->n_threads = n_threads;
-        J->tid = t; J->sample_steps = sample_steps; J->acc = acc; J->nc = nc;
+        J->tid = t; J->slot_of = slot_of; J->acc = acc; J->nc = nc;
         pthread_create(&th[t], NULL, ens_worker, J);
     }
     int32_t status = OR_OK;
@@ -853,5 +874,6 @@ int32_t or_ensemble(const or_spec *specs, int32_t n_runs, int32_t n_steps,
     }
     free(jobs);
     free(th);
+    free(slot_of);
     return status;
 }

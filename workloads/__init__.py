@@ -103,6 +103,10 @@ class Workload:
     n_groups: int
     state_fp64: bool = False
     note: str = ""
+    # sampling window: slot k averages the snapshots after steps
+    # sample_steps[k] - j * window_stride, j < window_steps (1 = one snapshot)
+    window_steps: int = 1
+    window_stride: int = 1
 
     @property
     def n_runs(self) -> int:
