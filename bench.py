@@ -18,10 +18,21 @@ candidates on the same batch in a scratch arena; tuning never changes results.
 Beside it the line carries:
   roofline      the dominant kernel's algorithmic bytes per launch over its
                 mean HIP-event duration (events recorded on the streams the
-                kernels run on), against MI355X's 8 TB/s HBM peak;
+                kernels run on), against MI355X's 8 TB/s HBM peak, with the
+                per-particle bytes of the hot-path scope table (Interaction
+                with the permutation: 4 + 20 read + 20 written);
+                roofline_as_built: the same with the bytes this design moves
+                (48: the next flight's cell is also written), and the whole
+                step's bytes per particle-step under both accountings;
   plain_fp64    the plain path: the same problem, one run at a time, FP64
                 state, one launch per kernel;
-  cpu_baseline  the FP64 oracle timed on the host cores on a bounded sample.
+  cpu_baseline  the FP64 oracle timed on the host cores on a bounded sample
+                (128 runs x 20 steps, 16 threads) and on one thread;
+  oracle_match  each macroparameter of the timed batch at step 20 (512 FP32
+                runs, FP64 accumulators) against the oracle's ensemble of
+                the same problem at step 20 (the 128 runs above, other seeds):
+                z = difference / combined standard error per cell, and the
+                relative error; also against the exact equilibrium values.
 
 ``--workload body3d`` times the flow past a body at full size instead (32 runs
 x 60M particles, 2M cells, solid-cell obstacle); ``channel`` (16 runs of the
@@ -58,8 +69,27 @@ WORKLOAD_TEXT = {
 }
 
 
+# Algorithmic bytes per particle-step of the hot-path scope table (2-D, FP32
+# state): Motion with Enumeration 16 read + 12 written, the Indexing scatter
+# 4 + 4, Interaction with the permutation 4 + 20 read + 20 written.
+SCOPE_BYTES = {"motion": 28, "scatter": 8, "collide": 44}
+
+
+def scope_bytes(kind: str, n_particles: int, n_cells: int, es: int) -> float:
+    """Bytes per launch by the hot-path scope table's per-particle figures,
+    plus the same per-cell terms as below."""
+    if kind == "motion":
+        return n_particles * SCOPE_BYTES["motion"]
+    if kind == "scatter":
+        return n_particles * SCOPE_BYTES["scatter"]
+    if kind in ("collide_cells", "collide_waves", "collide_lanes"):
+        return n_particles * SCOPE_BYTES["collide"] + n_cells * (4 + 4 * es + 8)
+    return 0.0
+
+
 def algorithmic_bytes(kind: str, n_particles: int, n_cells: int, dim: int, es: int) -> float:
-    """Bytes a kernel must move per launch (each byte once, no re-reads).
+    """Bytes a kernel of this design must move per launch (each byte once, no
+    re-reads).
 
     motion         reads the cell the last Interaction found for the
                    particle's flight (4); only particles generated in the
@@ -185,6 +215,15 @@ def run_gpu(args):
         psteps = (n0 + n1) // 2 * args.steps
     value = psteps / elapsed
 
+    # the timed batch's moments at the first sample step (FP64 division of
+    # the FP64 accumulators), for the comparison with the oracle
+    match_gpu = None
+    if args.workload == "ensemble_box" and wl.sample_steps and warmup + args.steps >= wl.sample_steps[0]:
+        m, se = E.moments(0)
+        tot = E.accum(0).sum(axis=(0, 1))
+        match_gpu = {"step": wl.sample_steps[0], "m": m, "se": se, "tot": tot, "runs": n_runs,
+                     "groups": wl.n_groups}
+
     # per-kernel HIP-event durations over a second, profiled window
     E.profiling(True)
     E.step(args.prof_steps)
@@ -200,16 +239,25 @@ def run_gpu(args):
     # launches per step
     kernels = {k: {"ms_total": ms, "launches": n, "ms_avg": ms / n} for k, (ms, n) in kt.items()}
     dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
-    rl = None
-    per_step = algorithmic_bytes(dom, n0, n_runs * nc, dim, 4)
-    if per_step > 0:
+    rl = rl_built = None
+    tr = measured_traffic(dom, info["lanes"], info["slots"] // info["tiles"]) \
+        if args.workload == "ensemble_box" else None
+    for acct, fn in (("scope", lambda k: scope_bytes(k, n0, n_runs * nc, 4) if dim == 2 else 0.0),
+                     ("built", lambda k: algorithmic_bytes(k, n0, n_runs * nc, dim, 4))):
+        per_step = fn(dom)
+        if per_step <= 0:
+            continue
         ab = per_step * args.prof_steps / kernels[dom]["launches"]
         ach = ab / (kernels[dom]["ms_avg"] * 1e-3) / 1e9
-        tr = measured_traffic(dom, info["lanes"], info["slots"] // info["tiles"]) \
-            if args.workload == "ensemble_box" else None
-        rl = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-              "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": tr, "kernel": dom,
-              "algorithmic_bytes_per_launch": ab, "avg_launch_ms": kernels[dom]["ms_avg"]}
+        obj = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": tr, "kernel": dom,
+               "algorithmic_bytes_per_launch": ab, "avg_launch_ms": kernels[dom]["ms_avg"]}
+        if acct == "scope":
+            rl = obj
+        else:
+            rl_built = obj
+    if rl is None:
+        rl, rl_built = rl_built, None
     for k, v in kernels.items():
         b = algorithmic_bytes(k, n0, n_runs * nc, dim, 4)
         if b > 0:
@@ -219,9 +267,16 @@ def run_gpu(args):
     plain = None
     if args.plain_runs > 0 and args.workload == "ensemble_box":
         plain = run_plain_fp64(args, P, W)
+    # the whole step's bytes per particle-step, both accountings
+    step_bytes = None
+    if args.workload == "ensemble_box":
+        bpp = {"scope": sum(SCOPE_BYTES.values()), "built": 4 + 8 + 48}
+        step_bytes = {a: {"bytes_per_particle_step": b, "GBs": round(b * value / 1e9, 1),
+                          "frac": round(b * value / 1e9 / HBM_PEAK_GBS, 4)} for a, b in bpp.items()}
     return {"value": value, "elapsed": elapsed, "psteps": psteps, "n_runs": n_runs, "nc": nc, "tuned": tuned,
-            "warmup": warmup, "n_mean": psteps // args.steps,
-            "kernels": kernels, "roofline": rl, "plain": plain, "info": info, "calib": calib}
+            "warmup": warmup, "n_mean": psteps // args.steps, "rl_built": rl_built, "step_bytes": step_bytes,
+            "kernels": kernels, "roofline": rl, "plain": plain, "info": info, "calib": calib,
+            "match_gpu": match_gpu}
 
 
 def run_plain_fp64(args, P, W):
@@ -249,34 +304,83 @@ def run_plain_fp64(args, P, W):
             "note": "same box problem, one run per context, FP64 state, no graph"}
 
 
+ORACLE_SEED = 1003   # the oracle's runs: same problem, seeds disjoint from the GPU batch's
+
+
 def cpu_baseline(args):
     """The FP64 oracle on the host cores, on a bounded sample of the same
-    problem: `threads` runs of per_run particles, S steps each (init
-    included), one thread per run."""
+    problem: `oracle_runs` runs of per_run particles for 20 steps (init
+    included), one run per thread at a time on `threads` threads, sampled at
+    step 20 into 32 run groups; and one run's steps on one thread (the
+    per-core rate).  Returns (baseline, the oracle's sums at step 20)."""
     import oracle
     import workloads as W
     oracle.build(force=False)
-    cores = len(os.sched_getaffinity(0))
-    threads = max(1, min(16, cores))
-    # calibrate on one run: time of 1 and of 3 steps (init included in both)
-    wl1 = W.ensemble_box(n_runs=1, n_per_run=args.per_run, n_steps=3, sample_every=1000, seed=3)
+    affinity = len(os.sched_getaffinity(0))
+    threads = max(1, min(16, affinity))
+    # one thread: one run for 1 and for k steps (init included in both), k
+    # giving about 2e7 particle-steps
+    k = max(3, -(-20_000_000 // args.per_run))
+    wl1 = W.ensemble_box(n_runs=1, n_per_run=args.per_run, n_steps=k, sample_every=1000, seed=ORACLE_SEED)
     t0 = time.perf_counter()
     oracle.ensemble(wl1, n_threads=1, n_steps=1)
     t1 = time.perf_counter() - t0
     t0 = time.perf_counter()
-    oracle.ensemble(wl1, n_threads=1, n_steps=3)
-    t3 = time.perf_counter() - t0
-    per_step = max((t3 - t1) / 2, 1e-3)
-    steps = int(max(2, min(300, (args.cpu_seconds - t1) / per_step)))
-    wl = W.ensemble_box(n_runs=threads, n_per_run=args.per_run, n_steps=steps, sample_every=1000,
-                        seed=3)
+    oracle.ensemble(wl1, n_threads=1, n_steps=k)
+    tk = time.perf_counter() - t0
+    per_core = (k - 1) * args.per_run / max(tk - t1, 1e-6)
+    steps = 20
+    wl = W.ensemble_box(n_runs=args.oracle_runs, n_per_run=args.per_run, n_steps=steps, sample_every=20,
+                        seed=ORACLE_SEED)
     t0 = time.perf_counter()
-    _, st = oracle.ensemble(wl, n_threads=threads, n_steps=steps)
+    acc, st = oracle.ensemble(wl, n_threads=threads, n_steps=steps)
     el = time.perf_counter() - t0
-    return {"value": st["particle_steps"] / el, "unit": "particle-steps/s", "cores": st["threads"],
-            "kind": "oracle",
-            "sample": f"{threads} runs x {args.per_run} particles x {steps} steps of the same box "
-                      f"problem (init included), one thread per run, {el:.1f} s"}
+    base = {"value": st["particle_steps"] / el, "unit": "particle-steps/s", "cores": st["threads"],
+            "kind": "oracle", "affinity_cpus": affinity, "per_core_value": per_core,
+            "sample": f"{args.oracle_runs} runs x {args.per_run} particles x {steps} steps of the same box "
+                      f"problem (init included), {st['threads']} threads, one run per thread at a time, "
+                      f"{el:.1f} s; per_core_value: one run's steps 2-{k} on one thread"}
+    return base, {"acc": acc[0], "runs": args.oracle_runs, "step": st["sample_steps"][0]}
+
+
+def oracle_match(gpu, ora, rs):
+    """Per macroparameter (n, ux, uy, T): z = (GPU - oracle) / combined
+    batch-means standard error over the cells, the fraction of |z| > 3, the
+    mean z and the largest relative error (velocities relative to the thermal
+    speed sqrt(3T)); against the oracle's ensemble and against the exact
+    equilibrium (n = N/cells per run, zero velocity, the gas's T)."""
+    import math
+    import numpy as np
+    import oracle
+    acc = ora["acc"]                                   # [groups][cell][7]
+    G = acc.shape[0]
+    mo = oracle.moments(acc.sum(axis=0), ora["runs"])
+    per = oracle.moments(acc, ora["runs"] // G)
+    so = per.std(axis=0, ddof=1) / math.sqrt(G)
+    mg, sg, tot = gpu["m"], gpu["se"], gpu["tot"]
+    u_all = tot[1:4] / tot[0]
+    T_all = ((tot[4] + tot[5] + tot[6]) / tot[0] - float(u_all @ u_all)) / 3.0
+    exact = {0: rs.n_init / rs.n_cells, 1: 0.0, 2: 0.0, 4: T_all}
+    scale = {0: exact[0], 1: math.sqrt(3 * T_all), 2: math.sqrt(3 * T_all), 4: T_all}
+    out = {}
+    for f, name in ((0, "n"), (1, "ux"), (2, "uy"), (4, "T")):
+        z = (mg[:, f] - mo[:, f]) / np.sqrt(sg[:, f] ** 2 + so[:, f] ** 2)
+        ze = (mg[:, f] - exact[f]) / sg[:, f]
+        rel = np.abs(mg[:, f] - mo[:, f]) / scale[f]
+        out[name] = {"max_abs_z": round(float(np.max(np.abs(z))), 3),
+                     "frac_abs_z_gt_3": round(float(np.mean(np.abs(z) > 3)), 5),
+                     "mean_z": round(float(np.mean(z)), 4),
+                     "max_rel_err": float(rel.max()),
+                     "frac_cells_within_1pct": round(float(np.mean(rel < 0.01)), 5),
+                     "median_3se_comb_rel": float(np.median(3 * np.sqrt(sg[:, f] ** 2 + so[:, f] ** 2)) / scale[f]),
+                     "vs_exact_max_abs_z": round(float(np.max(np.abs(ze))), 3),
+                     "vs_exact_max_rel_err": float(np.max(np.abs(mg[:, f] - exact[f])) / scale[f])}
+    return {"step": gpu["step"], "gpu_runs": gpu["runs"], "gpu_groups": gpu["groups"],
+            "oracle_runs": ora["runs"], "oracle_groups": G, "cells": int(mg.shape[0]),
+            "fields": out, "max_frac_abs_z_gt_3": max(out[k]["frac_abs_z_gt_3"] for k in out),
+            "vs_exact_all_within_1pct": bool(all(out[k]["vs_exact_max_rel_err"] < 0.01 for k in out)),
+            "note": "GPU: FP32 state, FP64 accumulators and division; oracle: FP64 throughout, "
+                    "independent seeds; standard errors from run groups (batch means)"}
 
 
 def main():
@@ -299,7 +403,8 @@ def main():
                          "3 a wavefront per cell")
     ap.add_argument("--plain-runs", type=int, default=2)
     ap.add_argument("--plain-steps", type=int, default=10)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--oracle-runs", type=int, default=128,
+                    help="runs of the oracle leg (20 steps each), a multiple of 32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -309,7 +414,12 @@ def main():
         sys.exit(2)
 
     g = run_gpu(args)
-    cpu = None if (args.no_cpu_baseline or args.workload != "ensemble_box") else cpu_baseline(args)
+    cpu = match = None
+    if not args.no_cpu_baseline and args.workload == "ensemble_box":
+        cpu, ora = cpu_baseline(args)
+        if g["match_gpu"] is not None and ora["step"] == g["match_gpu"]["step"]:
+            import workloads as W
+            match = oracle_match(g["match_gpu"], ora, W.ensemble_box(n_runs=1, n_per_run=args.per_run).runs[0])
     ms_per_step = g["elapsed"] / args.steps * 1e3
     line = {
         "metric": METRIC,
@@ -333,7 +443,10 @@ def main():
                    "parallelism": "one GPU; runs batched in each launch, split into "
                                   f"{g['info']['lanes']} concurrent stream lanes"},
         "roofline": g["roofline"],
+        "roofline_as_built": g["rl_built"],
+        "step_bytes": g["step_bytes"],
         "cpu_baseline": cpu,
+        "oracle_match": match,
         "plain_fp64": g["plain"],
         "batched_over_plain": (g["value"] / g["plain"]["value"]) if g["plain"] else None,
         "kernels": g["kernels"],

@@ -5,7 +5,7 @@
  * The operation is the sequential unsteady-DSMC algorithm of Sec. 1.1 of
  * Bogdanov, Bykov, Grishin, Khanlarov, Lukianov and Zakharov, "Algorithms of
  * Two-Level Parallelization for DSMC of Unsteady Flows in Molecular
- * Gasdynamics" (general flowchart of the sequential algorithm): an inner loop
+ * Gasdynamics" (Fig. 1): an inner loop
  * over time steps dt of one run -- Generation, Motion, Enumeration/Indexing
  * (the readdressing array LCR), Interaction, and Sampling at given moments --
  * and an outer loop over n statistically independent runs whose random number
@@ -60,7 +60,9 @@ typedef int32_t dsmc_status;
 #define DSMC_EBOUNCE (-7)      /* more than 64 wall interactions of one particle in one step */
 #define DSMC_EREJECT (-8)      /* inflow velocity sampler or the fill of a run with solid cells exceeded
                                   its attempt limit */
-#define DSMC_ENUMERIC (-9)     /* non-finite particle state or >= 1e9 pair selections in one cell and step */
+#define DSMC_ENUMERIC (-9)     /* a non-finite coordinate or velocity met by Motion's flight (in 2-D, w
+                                  only through a pair selection), or >= 1e9 pair selections in one cell
+                                  and step (e.g. an infinite relative speed) */
 
 /* Boundary kind of a face; faces are ordered -x, +x, -y, +y, -z, +z. */
 #define DSMC_BC_SPECULAR 0     /* mirror reflection */
@@ -123,6 +125,15 @@ typedef struct {
                                    The runs are split into contiguous groups of about equal slot
                                    counts; one group's Indexing and Interaction overlap the next
                                    group's Motion.  Results do not depend on it. */
+  int32_t window_steps;         /* sampling window (0 or 1 = one snapshot per slot): slot k accumulates
+                                   the snapshots after steps sample_steps[k] - j * window_stride,
+                                   j = 0 .. window_steps - 1 (those >= 1), so that its moments average
+                                   over time as well as over the runs -- the steady-flow variant: an
+                                   averaging time much longer than dt once the flow is steady (Sec.
+                                   1.1), with ensemble averaging of runs of fewer particles on top
+                                   (end of Sec. 3).  Windows of different slots may share no step
+                                   (DSMC_EINVAL). */
+  int32_t window_stride;        /* steps between the snapshots of a window (0 = 1) */
 } dsmc_options;
 
 /* Arena size for these runs/options.  Pure host computation.
@@ -133,7 +144,11 @@ dsmc_status dsmc_required_bytes(const dsmc_run_spec *runs, int32_t n_runs, const
 /* Create a context: lays the runs out in the arena (device memory of at
  * least dsmc_required_bytes bytes, 256-byte aligned), fills each run with its
  * initial state (Philox stream "INIT" of its key) and returns the context.
- * hip_stream is a hipStream_t (NULL = default stream).  Synchronises. */
+ * The runs are the n statistically independent runs of the outer loop of
+ * Sec. 1.1 (Fig. 1), each with its own shift of the random number generator
+ * (here its Philox key); their arrays P, LCR and C (Sec. 1.1) live in the
+ * arena.  hip_stream is a hipStream_t (NULL = default stream).
+ * Synchronises. */
 dsmc_status dsmc_init_runs(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_options *opt, void *arena,
                            size_t arena_bytes, void *hip_stream, dsmc_ctx **out);
 
@@ -142,15 +157,20 @@ dsmc_status dsmc_init_runs(const dsmc_run_spec *runs, int32_t n_runs, const dsmc
  * Asynchronous. */
 dsmc_status dsmc_step(dsmc_ctx *ctx, int32_t n_steps);
 
-/* Accumulate the current state of every run into sample slot k.  Valid after
- * at least one step.  Asynchronous. */
+/* Sampling (Sec. 1.1, Fig. 1): add the per-cell sums of the current state of
+ * every run into sample slot k -- the cross-run accumulation of the
+ * statistical data at a given moment of the unsteady process -- and count one
+ * more snapshot of slot k.  Valid after at least one step.  Asynchronous. */
 dsmc_status dsmc_sample(dsmc_ctx *ctx, int32_t sample_index);
 
-/* Cell moments of one ensemble at sample slot k, FP64 (the final division of
- * the cross-run sums): out[cell][DSMC_NMOM] on the host; out_se (may be NULL)
- * the batch-means standard error over the ensemble's run groups (NaN with one
- * group).  capacity_doubles is the size of each host array.  Cells with no
- * particles give NaN.  Synchronises. */
+/* Cell moments of one ensemble at sample slot k, FP64: the macroparameters
+ * averaged over the particles of each cell and over the runs (Sec. 1.1), the
+ * final division of the cross-run sums.  out[cell][DSMC_NMOM] on the host:
+ * n = particles per cell per run and snapshot, the mean velocity, T and the
+ * directional temperatures (pooled over runs, no N/(N-1) correction); out_se
+ * (may be NULL) the batch-means standard error over the ensemble's run groups
+ * (NaN with one group).  capacity_doubles is the size of each host array.
+ * Cells with no particles give NaN.  Synchronises. */
 dsmc_status dsmc_read_moments(dsmc_ctx *ctx, int32_t sample_index, int32_t ensemble, double *out,
                               double *out_se, size_t capacity_doubles);
 
@@ -180,7 +200,10 @@ dsmc_status dsmc_get_info(dsmc_ctx *ctx, int64_t info[DSMC_NINFO]);
 dsmc_status dsmc_get_state(dsmc_ctx *ctx, int32_t run, double *out, int64_t cap, int64_t *n);
 
 /* Replace the particle state of one run (in[6][n], FP64; converted to the
- * state precision). */
+ * state precision).  Returns DSMC_EINVAL, with nothing changed, for a
+ * non-finite coordinate or velocity, a position outside the box (x in
+ * [0, lx], y in [0, ly], and z in [0, lz] in 3-D) or n above the run's
+ * capacity. */
 dsmc_status dsmc_set_state(dsmc_ctx *ctx, int32_t run, const double *in, int64_t n);
 
 /* Indexing of the last step of one run: lcr[n] (run-local slots in stable
@@ -195,6 +218,47 @@ dsmc_status dsmc_get_cell_state(dsmc_ctx *ctx, int32_t run, double *rem, double 
 
 /* Per run: [r][0] particles now, [r][1] particles generated in the last step. */
 dsmc_status dsmc_get_counts(dsmc_ctx *ctx, int64_t *out, int32_t n_runs);
+
+/* Snapshots accumulated so far in each sample slot (scheduled and by
+ * dsmc_sample): out[k] for k < n_samples (n_samples must equal the
+ * context's).  Synchronises. */
+dsmc_status dsmc_get_sample_counts(dsmc_ctx *ctx, int64_t *out, int32_t n_samples);
+
+/* Per-run diagnostics computed on the device from the current state, FP64:
+ * out[r][DSMC_NDIAG] = particles, particles generated in the last step,
+ * accepted collisions since init (over the run's cells), sum u, sum v, sum w
+ * (momentum per unit mass) and sum |c|^2 (twice the kinetic energy per unit
+ * mass) over the run's particles.  n_runs must equal the context's.  The
+ * sums are in a fixed order: repeated calls give the same bits.
+ * Synchronises. */
+#define DSMC_NDIAG 7
+dsmc_status dsmc_get_diag(dsmc_ctx *ctx, double *out, int32_t n_runs);
+
+/* ---- checkpoint / resume --------------------------------------------------- */
+
+/* Size in bytes of a checkpoint of the current state (it grows with the
+ * particles alive).  Synchronises. */
+dsmc_status dsmc_checkpoint_bytes(dsmc_ctx *ctx, size_t *bytes);
+
+/* Copy everything a later step reads into the host buffer `host` (at least
+ * dsmc_checkpoint_bytes, 8-byte aligned): per run the particles (P in its
+ * cell-sorted order, in the state precision, bit for bit) and their count, the
+ * per-cell interaction state (remainder, (sigma c_r)_max, collision counter)
+ * and bin starts, the inflow faces' carried remainders; the accumulators and
+ * snapshot counts of every sample slot; the step counter.  The steps of the
+ * runs are replayable from their Philox keys and the step counter (Sec. 1.1:
+ * runs made independent by shifting the generator), so a context restored
+ * from it continues bit-identically.  Synchronises. */
+dsmc_status dsmc_checkpoint(dsmc_ctx *ctx, void *host, size_t bytes);
+
+/* Put a checkpoint back into a context made by dsmc_init_runs from the same
+ * run specs, precision, run groups, sample schedule and window (tuning
+ * fields may differ: results do not depend on them).  Returns DSMC_EINVAL,
+ * with nothing changed, when the buffer is not a checkpoint of such a
+ * context (magic, version, fingerprint of the specs, sizes).  The next
+ * dsmc_step continues exactly where the checkpointed context would have.
+ * Synchronises. */
+dsmc_status dsmc_restore(dsmc_ctx *ctx, const void *host, size_t bytes);
 
 /* ---- per-kernel timing ----------------------------------------------------- */
 

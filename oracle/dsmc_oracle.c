@@ -1,8 +1,8 @@
 /*
  * DSMC oracle: a plain, sequential, FP64 implementation of one time step of
  * unsteady DSMC -- Generation, Motion, Enumeration/Indexing, Interaction and
- * Sampling -- in the order of the sequential algorithm of Sec. 1.1 (the
- * "general flowchart of sequential algorithm" figure) of Bogdanov, Bykov,
+ * Sampling -- in the order of the sequential algorithm of Sec. 1.1 (Fig. 1)
+ * of Bogdanov, Bykov,
  * Grishin, Khanlarov, Lukianov and Zakharov, "Algorithms of Two-Level
  * Parallelization for DSMC of Unsteady Flows in Molecular Gasdynamics".
  *

@@ -32,9 +32,12 @@ EXPORTS = ("dsmc_required_bytes", "dsmc_init_runs", "dsmc_step", "dsmc_sample", 
            "dsmc_get_state", "dsmc_set_state", "dsmc_get_lcr", "dsmc_get_cell_state",
            "dsmc_get_counts", "dsmc_counting_sort_bytes", "dsmc_counting_sort",
            "dsmc_set_profiling", "dsmc_kernel_times", "dsmc_kernel_name", "dsmc_autotune_bytes",
-           "dsmc_autotune", "dsmc_counting_sort_noalloc")
+           "dsmc_autotune", "dsmc_counting_sort_noalloc", "dsmc_get_sample_counts", "dsmc_get_diag",
+           "dsmc_checkpoint_bytes", "dsmc_checkpoint", "dsmc_restore")
 NKERNELS = 19
 NINFO = 10
+NDIAG = 7
+DIAG_NAMES = ("particles", "generated", "collisions", "sum_u", "sum_v", "sum_w", "sum_c2")
 
 
 class DsmcError(RuntimeError):
@@ -58,7 +61,8 @@ class dsmc_run_spec(C.Structure):
 class dsmc_options(C.Structure):
     _fields_ = [("state_fp64", C.c_int32), ("n_groups", C.c_int32), ("n_samples", C.c_int32),
                 ("sample_steps", C.POINTER(C.c_int32)), ("use_graph", C.c_int32),
-                ("tile_chunks", C.c_int32), ("collide_mode", C.c_int32), ("n_streams", C.c_int32)]
+                ("tile_chunks", C.c_int32), ("collide_mode", C.c_int32), ("n_streams", C.c_int32),
+                ("window_steps", C.c_int32), ("window_stride", C.c_int32)]
 
 
 _lib = None
@@ -96,6 +100,11 @@ def lib():
         L.dsmc_counting_sort_bytes.argtypes = [i64, i32, C.POINTER(sz)]
         L.dsmc_counting_sort.argtypes = [vp, i64, i32, vp, vp, vp, sz, vp]
         L.dsmc_counting_sort_noalloc.argtypes = [vp, i64, i32, vp, vp, vp]
+        L.dsmc_get_sample_counts.argtypes = [vp, C.POINTER(i64), i32]
+        L.dsmc_get_diag.argtypes = [vp, dp, i32]
+        L.dsmc_checkpoint_bytes.argtypes = [vp, C.POINTER(sz)]
+        L.dsmc_checkpoint.argtypes = [vp, vp, sz]
+        L.dsmc_restore.argtypes = [vp, vp, sz]
         L.dsmc_set_profiling.argtypes = [vp, i32]
         L.dsmc_kernel_times.argtypes = [vp, dp, C.POINTER(i64), i32]
         L.dsmc_kernel_name.argtypes = [i32]
@@ -150,7 +159,7 @@ def make_run_spec(rs) -> dsmc_run_spec:
 
 def make_options(state_fp64: bool, n_groups: int, sample_steps: Sequence[int],
                  use_graph: bool = False, tile_chunks: int = 0, collide_mode: int = 0,
-                 n_streams: int = 0):
+                 n_streams: int = 0, window_steps: int = 0, window_stride: int = 0):
     steps = (C.c_int32 * max(1, len(sample_steps)))(*sample_steps)
     o = dsmc_options()
     o.state_fp64 = int(bool(state_fp64))
@@ -161,6 +170,8 @@ def make_options(state_fp64: bool, n_groups: int, sample_steps: Sequence[int],
     o.tile_chunks = int(tile_chunks)
     o.collide_mode = int(collide_mode)
     o.n_streams = int(n_streams)
+    o.window_steps = int(window_steps)
+    o.window_stride = int(window_stride)
     o._keep = steps
     return o
 
@@ -289,6 +300,43 @@ def dsmc_get_counts(ctx, n_runs: int) -> np.ndarray:
     return out
 
 
+def dsmc_get_sample_counts(ctx, n_samples: int) -> np.ndarray:
+    out = np.zeros(max(n_samples, 1), np.int64)
+    _check(lib().dsmc_get_sample_counts(ctx, out.ctypes.data_as(C.POINTER(C.c_int64)), n_samples),
+           "dsmc_get_sample_counts", ctx)
+    return out[:n_samples]
+
+
+def dsmc_get_diag(ctx, n_runs: int) -> np.ndarray:
+    out = np.zeros((n_runs, NDIAG))
+    _check(lib().dsmc_get_diag(ctx, out.ctypes.data_as(C.POINTER(C.c_double)), n_runs),
+           "dsmc_get_diag", ctx)
+    return out
+
+
+def dsmc_checkpoint_bytes(ctx) -> int:
+    n = C.c_size_t(0)
+    _check(lib().dsmc_checkpoint_bytes(ctx, C.byref(n)), "dsmc_checkpoint_bytes", ctx)
+    return n.value
+
+
+def dsmc_checkpoint(ctx) -> np.ndarray:
+    """The checkpoint as a host byte array (8-byte aligned)."""
+    n = dsmc_checkpoint_bytes(ctx)
+    buf = np.zeros((n + 7) // 8, np.uint64).view(np.uint8)[:n]
+    _check(lib().dsmc_checkpoint(ctx, buf.ctypes.data, n), "dsmc_checkpoint", ctx)
+    return buf
+
+
+def dsmc_restore(ctx, buf: np.ndarray):
+    b = np.ascontiguousarray(buf, dtype=np.uint8)
+    if b.ctypes.data % 8:      # the library wants an 8-byte aligned buffer
+        al = np.zeros((b.size + 7) // 8, np.uint64).view(np.uint8)[:b.size]
+        al[:] = b
+        b = al
+    _check(lib().dsmc_restore(ctx, b.ctypes.data, b.size), "dsmc_restore", ctx)
+
+
 def dsmc_set_profiling(ctx, on: bool):
     _check(lib().dsmc_set_profiling(ctx, int(bool(on))), "dsmc_set_profiling", ctx)
 
@@ -341,14 +389,15 @@ class Ensemble:
 
     def __init__(self, runs, sample_steps: Sequence[int] = (), state_fp64: bool = False,
                  n_groups: int = 1, use_graph: bool = False, tile_chunks: int = 0,
-                 collide_mode: int = 0, n_streams: int = 0, device=None, stream=None):
+                 collide_mode: int = 0, n_streams: int = 0, window_steps: int = 0,
+                 window_stride: int = 0, device=None, stream=None):
         import torch
         if not torch.cuda.is_available():
             raise DsmcError(-4, "Ensemble", "no GPU visible to torch")
         self.runs = list(runs)
         self.specs = _specs(self.runs)
         self.opt = make_options(state_fp64, n_groups, list(sample_steps), use_graph, tile_chunks,
-                                collide_mode, n_streams)
+                                collide_mode, n_streams, window_steps, window_stride)
         self.nbytes = dsmc_required_bytes(self.specs, self.opt)
         dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.arena = torch.empty(self.nbytes, dtype=torch.uint8, device=dev)
@@ -386,6 +435,8 @@ class Ensemble:
     def from_workload(cls, wl, **kw):
         kw.setdefault("state_fp64", wl.state_fp64)
         kw.setdefault("n_groups", wl.n_groups)
+        kw.setdefault("window_steps", getattr(wl, "window_steps", 1))
+        kw.setdefault("window_stride", getattr(wl, "window_stride", 1))
         return cls(wl.runs, wl.sample_steps, **kw)
 
     def close(self):
@@ -440,6 +491,19 @@ class Ensemble:
 
     def counts(self) -> np.ndarray:
         return dsmc_get_counts(self.ctx, len(self.runs))
+
+    def sample_counts(self) -> np.ndarray:
+        return dsmc_get_sample_counts(self.ctx, self.opt.n_samples)
+
+    def diag(self) -> np.ndarray:
+        """[run][7]: particles, generated, collisions, sum u, v, w, |c|^2."""
+        return dsmc_get_diag(self.ctx, len(self.runs))
+
+    def checkpoint(self) -> np.ndarray:
+        return dsmc_checkpoint(self.ctx)
+
+    def restore(self, buf: np.ndarray):
+        dsmc_restore(self.ctx, buf)
 
     def profiling(self, on: bool):
         dsmc_set_profiling(self.ctx, on)

@@ -39,6 +39,8 @@ struct Plan {
   std::vector<uint8_t> solid;
   std::vector<Ensemble> ens;
   std::vector<int64_t> spec_capacity;
+  uint64_t fingerprint = 0;  // of everything a checkpoint must agree on (not the tuning fields)
+  size_t off_nsnap, off_diag;
   size_t off_runs, off_tile_run, off_face_run, off_cgroup_run, off_inflow, off_gen_blk, off_eg_start, off_eg_runs,
       off_eg_acc,
       off_eg_nc, off_samples, off_items, off_cell_items, off_wave_items, off_solid;
@@ -67,6 +69,22 @@ dsmc_status validate(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_optio
     if (opt->tile_chunks % 4) return fail(msg, DSMC_EINVAL, "tile_chunks must be a multiple of 4");
     if (opt->collide_mode < 0 || opt->collide_mode > 3) return fail(msg, DSMC_EINVAL, "collide_mode out of range");
     if (opt->n_streams < 0 || opt->n_streams > kMaxLanes) return fail(msg, DSMC_EINVAL, "n_streams out of range");
+    if (opt->window_steps < 0 || opt->window_stride < 0) return fail(msg, DSMC_EINVAL, "negative sampling window");
+    if (opt->n_samples > 0 && opt->window_steps > 1) {
+      // the windows' steps: each may belong to one slot only
+      const int64_t W = opt->window_steps, q = opt->window_stride > 0 ? opt->window_stride : 1;
+      if ((int64_t)opt->n_samples * W > ((int64_t)1 << 24))
+        return fail(msg, DSMC_EINVAL, "sampling windows of more than 2^24 snapshots in all");
+      std::vector<int64_t> steps;
+      for (int k = 0; k < opt->n_samples; ++k) {
+        const int64_t last = opt->sample_steps ? opt->sample_steps[k] : 0;
+        if (last < 1) continue;
+        for (int64_t j = 0; j < W && last - j * q >= 1; ++j) steps.push_back(last - j * q);
+      }
+      std::sort(steps.begin(), steps.end());
+      for (size_t i = 1; i < steps.size(); ++i)
+        if (steps[i] == steps[i - 1]) return fail(msg, DSMC_EINVAL, "sampling windows share step %d", (int)steps[i]);
+    }
   }
   const int dim = runs[0].dim;
   for (int r = 0; r < n_runs; ++r) {
@@ -118,6 +136,51 @@ bool any_solid(const dsmc_run_spec &s) {
   return false;
 }
 
+// FNV-1a over the bytes of a value.
+struct Fnv {
+  uint64_t h = 1469598103934665603ull;
+  void bytes(const void *p, size_t n) {
+    const unsigned char *b = (const unsigned char *)p;
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  }
+  template <typename T> void add(const T &v) { bytes(&v, sizeof v); }
+};
+
+// What a checkpoint and the context it is restored into must share: the run
+// specs (with their masks), the precision, the run groups, the sample
+// schedule and window.  Tuning fields are left out: results do not depend on
+// them.
+uint64_t plan_fingerprint(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_options &opt) {
+  Fnv f;
+  f.add(n_runs);
+  f.add(opt.state_fp64 ? 1 : 0);
+  f.add(opt.n_groups > 0 ? opt.n_groups : 1);
+  f.add(opt.n_samples);
+  for (int k = 0; k < opt.n_samples; ++k) f.add(opt.sample_steps ? opt.sample_steps[k] : 0);
+  f.add(std::max(1, opt.window_steps));
+  f.add(std::max(1, opt.window_stride));
+  for (int r = 0; r < n_runs; ++r) {
+    const dsmc_run_spec &s = runs[r];
+    f.add(s.dim); f.add(s.nx); f.add(s.ny); f.add(s.nz);
+    f.add(s.lx); f.add(s.ly); f.add(s.lz); f.add(s.dt); f.add(s.fnum_sigma); f.add(s.omega); f.add(s.c_ref);
+    for (int k = 0; k < 6; ++k) {
+      f.add(s.face_bc[k]);
+      f.add(s.face_T[k]);
+    }
+    f.add(s.inflow_n); f.add(s.inflow_U); f.add(s.inflow_T);
+    f.add(s.capacity); f.add(s.n_init);
+    for (int a = 0; a < 3; ++a) f.add(s.init_U[a]);
+    f.add(s.init_T); f.add(s.run_id); f.add(s.seed); f.add(s.ensemble);
+    const int has = s.solid_mask ? 1 : 0;
+    f.add(has);
+    if (has) {
+      f.bytes(s.solid_mask, (size_t)s.nx * s.ny * s.nz);
+      f.add(s.solid_T);
+    }
+  }
+  return f.h;
+}
+
 // Same initial (sigma c_r)_max rule as everywhere: g at c0 = |U| + 3 sqrt(2 T_max),
 // T_max over the initial gas, the inflow, the diffuse faces and the obstacle.
 double initial_gmax(const dsmc_run_spec &s) {
@@ -148,6 +211,9 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
   g.tile = (int64_t)g.tile_chunks * kWave;
   g.n_runs = n_runs;
   g.n_samples = opt.n_samples;
+  g.window_steps = std::max(1, opt.window_steps);
+  g.window_stride = std::max(1, opt.window_stride);
+  P.fingerprint = plan_fingerprint(runs, n_runs, opt);
   const int G = opt.n_groups > 0 ? opt.n_groups : 1;
 
   int max_nc = 0;
@@ -479,6 +545,8 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
   P.off_gencnt = take(4 * g.n_faces);
   P.off_stage = take(8 * kFields * g.n_cells);
   P.off_acc = take(8 * (size_t)g.acc_stride * g.n_samples);
+  P.off_nsnap = take(4 * (size_t)g.n_samples);
+  P.off_diag = take(8 * (size_t)kDiag * n_runs);
   P.off_mom = take(8 * 2 * (size_t)max_nc * kMoments);
   P.off_nalive = take(4 * n_runs);
   P.off_nsorted = take(4 * n_runs);
@@ -525,6 +593,8 @@ DevPtrs<real> carve(const Plan &P, char *base) {
   d.gen_count = (int32_t *)(base + P.off_gencnt);
   d.stage = (double *)(base + P.off_stage);
   d.acc = (double *)(base + P.off_acc);
+  d.nsnap = (uint32_t *)(base + P.off_nsnap);
+  d.diag = (double *)(base + P.off_diag);
   d.mom = (double *)(base + P.off_mom);
   d.n_alive = (int32_t *)(base + P.off_nalive);
   d.n_sorted = (int32_t *)(base + P.off_nsorted);
@@ -566,7 +636,8 @@ struct dsmc_ctx {
   DevPtrs<double> dd{};
   int buf = 0;
   int64_t steps_done = 0;
-  bool sorted = false;
+  bool sorted = false;     // P is cell-sorted by a step (sampling is valid)
+  bool lcr_valid = false;  // LCR and bin starts are those of the last step
   dsmc_status latched = DSMC_OK;
   std::string msg;
   bool use_graph = false;
@@ -828,6 +899,7 @@ dsmc_status dsmc_step(dsmc_ctx *c, int32_t n_steps) {
     c->buf ^= 1;
     c->steps_done++;
     c->sorted = true;
+    c->lcr_valid = true;
   }
   if (graph && c->gstream) {
     dsmc_status st = check_hip(c, hipEventRecord(c->g_out, gs), "hipEventRecord");
@@ -963,6 +1035,16 @@ template <typename real>
 dsmc_status set_state_t(dsmc_ctx *c, const DevPtrs<real> &d, int32_t run, const double *in, int64_t n) {
   const RunDev &R = c->plan.runs[run];
   if (n < 0 || n > c->plan.spec_capacity[run]) return set_err(c, DSMC_EINVAL, "n exceeds the run's capacity");
+  const int dim = c->plan.g.dim;
+  for (int64_t i = 0; i < n; ++i) {
+    for (int a = 0; a < 6; ++a)
+      if (!std::isfinite(in[(size_t)a * n + i]))
+        return set_err(c, DSMC_EINVAL, "set_state: non-finite coordinate or velocity");
+    for (int a = 0; a < dim; ++a) {
+      const double x = in[(size_t)a * n + i];
+      if (!(x >= 0.0 && x <= R.L[a])) return set_err(c, DSMC_EINVAL, "set_state: position outside the box");
+    }
+  }
   dsmc_status st = sync_ctx(c);
   if (st) return st;
   const Particles<real> &P = d.P[c->buf];
@@ -996,6 +1078,7 @@ dsmc_status set_state_t(dsmc_ctx *c, const DevPtrs<real> &d, int32_t run, const 
   }
   if (!st) st = sync_ctx(c);
   c->sorted = false;
+  c->lcr_valid = false;
   return st;
 }
 
@@ -1037,7 +1120,7 @@ dsmc_status dsmc_get_lcr(dsmc_ctx *c, int32_t run, int32_t *lcr, int32_t *cell, 
                          int64_t *n) {
   if (!c || !n || run < 0 || run >= c->plan.g.n_runs) return DSMC_EINVAL;
   if (c->latched) return c->latched;
-  if (c->steps_done == 0) return set_err(c, DSMC_ESTATE, "no step done yet");
+  if (!c->lcr_valid) return set_err(c, DSMC_ESTATE, "no step done since init, set_state or restore");
   const RunDev &R = c->plan.runs[run];
   const bool f64 = c->plan.g.fp64;
   const int32_t *d_ns = f64 ? c->dd.n_sorted : c->df.n_sorted;
@@ -1093,6 +1176,237 @@ dsmc_status dsmc_get_counts(dsmc_ctx *c, int64_t *out, int32_t n_runs) {
     out[2 * r + 1] = b[r];
   }
   return DSMC_OK;
+}
+
+dsmc_status dsmc_get_sample_counts(dsmc_ctx *c, int64_t *out, int32_t n_samples) {
+  if (!c || n_samples != c->plan.g.n_samples || (n_samples > 0 && !out)) return DSMC_EINVAL;
+  if (c->latched) return c->latched;
+  if (n_samples == 0) return sync_ctx(c);
+  std::vector<uint32_t> k((size_t)n_samples);
+  dsmc_status st = download<uint32_t>(c, k.data(), c->plan.g.fp64 ? c->dd.nsnap : c->df.nsnap, n_samples);
+  if (!st) st = sync_ctx(c);
+  if (st) return st;
+  for (int i = 0; i < n_samples; ++i) out[i] = k[i];
+  return DSMC_OK;
+}
+
+dsmc_status dsmc_get_diag(dsmc_ctx *c, double *out, int32_t n_runs) {
+  if (!c || !out || n_runs != c->plan.g.n_runs) return DSMC_EINVAL;
+  if (c->latched) return c->latched;
+  const bool f64 = c->plan.g.fp64;
+  if (f64) launch_diag<double>(c->plan.g, c->dd, c->buf, c->stream);
+  else launch_diag<float>(c->plan.g, c->df, c->buf, c->stream);
+  dsmc_status st = check_hip(c, hipGetLastError(), "launch(diag)");
+  if (!st) st = download<double>(c, out, f64 ? c->dd.diag : c->df.diag, (size_t)kDiag * n_runs);
+  if (!st) st = sync_ctx(c);
+  return st;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Checkpoint / restore: a header, then the sections below in this order, each
+// padded to 8 bytes.  Per-run sections are run-local (slots from the run's
+// first), so a checkpoint does not depend on the tile size or other tuning.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct CkptHeader {
+  char magic[8];           // "DSMCCKP1"
+  uint32_t version;        // 1
+  int32_t fp64;
+  uint64_t fingerprint;    // Plan::fingerprint of the context it came from
+  int64_t total;           // bytes of the whole checkpoint
+  int64_t steps_done;
+  uint32_t step;           // device step counter
+  int32_t n_runs;
+  int32_t sorted;
+  int32_t n_samples;
+  int64_t particles;       // over all runs
+  int64_t reserved[2];
+};
+static_assert(sizeof(CkptHeader) == 80, "checkpoint header layout");
+const char kCkptMagic[8] = {'D', 'S', 'M', 'C', 'C', 'K', 'P', '1'};
+
+size_t pad8(size_t x) { return (x + 7) & ~(size_t)7; }
+
+// Bytes of a checkpoint with these per-run particle counts.
+size_t ckpt_bytes(const Plan &P, const std::vector<int32_t> &na) {
+  const Geometry &g = P.g;
+  const size_t es = g.fp64 ? 8 : 4;
+  const size_t nr = g.dim == 3 ? 2 : 1;
+  size_t o = sizeof(CkptHeader);
+  o += pad8(4 * (size_t)g.n_runs) * 2;  // n_alive, n_gen
+  for (int r = 0; r < g.n_runs; ++r) o += pad8(4 * es * (size_t)na[r]) + pad8(nr * es * (size_t)na[r]);
+  for (int r = 0; r < g.n_runs; ++r) {
+    const size_t nc = (size_t)P.runs[r].nc;
+    o += 2 * pad8(es * nc) + pad8(4 * nc) + pad8(4 * (nc + 2));
+  }
+  o += pad8(8 * (size_t)g.n_faces);
+  o += pad8(8 * (size_t)g.acc_stride * g.n_samples);
+  o += pad8(4 * (size_t)g.n_samples);
+  return o;
+}
+
+template <typename real>
+dsmc_status read_counts(dsmc_ctx *c, const DevPtrs<real> &d, std::vector<int32_t> &na, std::vector<int32_t> &ng) {
+  const int n = c->plan.g.n_runs;
+  na.assign((size_t)n, 0);
+  ng.assign((size_t)n, 0);
+  dsmc_status st = download<int32_t>(c, na.data(), d.n_alive, n);
+  if (!st) st = download<int32_t>(c, ng.data(), d.n_gen, n);
+  if (!st) st = sync_ctx(c);
+  return st;
+}
+
+// Moves every section between the device and the checkpoint bytes at `host`
+// (to the host when `save`).  Enqueues only; the caller synchronises.
+template <typename real>
+dsmc_status ckpt_sections(dsmc_ctx *c, const DevPtrs<real> &d, char *host, const std::vector<int32_t> &na,
+                          const std::vector<int32_t> &ng, bool save) {
+  const Plan &P = c->plan;
+  const Geometry &g = P.g;
+  const size_t es = sizeof(real);
+  const int nr = g.dim == 3 ? 2 : 1;
+  size_t o = sizeof(CkptHeader);
+  dsmc_status st = DSMC_OK;
+  auto move = [&](void *dev, size_t bytes) {
+    if (st || bytes == 0) {
+      o += pad8(bytes);
+      return;
+    }
+    st = check_hip(c,
+                   save ? hipMemcpyAsync(host + o, dev, bytes, hipMemcpyDeviceToHost, c->stream)
+                        : hipMemcpyAsync(dev, host + o, bytes, hipMemcpyHostToDevice, c->stream),
+                   save ? "checkpoint copy" : "restore copy");
+    o += pad8(bytes);
+  };
+  if (save) {
+    std::memcpy(host + o, na.data(), 4 * na.size());
+    std::memcpy(host + o + pad8(4 * na.size()), ng.data(), 4 * ng.size());
+  }
+  o += 2 * pad8(4 * (size_t)g.n_runs);
+  const Particles<real> &B = d.P[c->buf];
+  for (int r = 0; r < g.n_runs; ++r) {
+    const RunDev &R = P.runs[r];
+    move(B.q + R.so, 4 * es * (size_t)na[r]);
+    move(B.zw ? (void *)(B.zw + R.so) : (void *)(B.w + R.so), (size_t)nr * es * na[r]);
+  }
+  for (int r = 0; r < g.n_runs; ++r) {
+    const RunDev &R = P.runs[r];
+    move(d.rem_c + R.co, es * R.nc);
+    move(d.gmax + R.co, es * R.nc);
+    move(d.ncoll + R.co, 4 * (size_t)R.nc);
+    move(d.bin_start + R.bo, 4 * ((size_t)R.nc + 2));
+  }
+  move(d.rem_f, 8 * (size_t)g.n_faces);
+  move(d.acc, 8 * (size_t)g.acc_stride * g.n_samples);
+  move(d.nsnap, 4 * (size_t)g.n_samples);
+  return st;
+}
+
+template <typename real>
+dsmc_status checkpoint_t(dsmc_ctx *c, const DevPtrs<real> &d, void *host, size_t bytes, size_t *size_only) {
+  std::vector<int32_t> na, ng;
+  dsmc_status st = read_counts(c, d, na, ng);
+  if (st) return st;
+  const size_t need = ckpt_bytes(c->plan, na);
+  if (size_only) {
+    *size_only = need;
+    return DSMC_OK;
+  }
+  if (bytes < need) return set_err(c, DSMC_ESIZE, "checkpoint buffer too small");
+  uint32_t step = 0;
+  st = download<uint32_t>(c, &step, d.step, 1);
+  if (!st) st = ckpt_sections(c, d, (char *)host, na, ng, true);
+  if (!st) st = sync_ctx(c);
+  if (st) return st;
+  CkptHeader h{};
+  std::memcpy(h.magic, kCkptMagic, 8);
+  h.version = 1;
+  h.fp64 = c->plan.g.fp64;
+  h.fingerprint = c->plan.fingerprint;
+  h.total = (int64_t)need;
+  h.steps_done = c->steps_done;
+  h.step = step;
+  h.n_runs = c->plan.g.n_runs;
+  h.sorted = c->sorted ? 1 : 0;
+  h.n_samples = c->plan.g.n_samples;
+  for (int32_t v : na) h.particles += v;
+  std::memcpy(host, &h, sizeof h);
+  return DSMC_OK;
+}
+
+template <typename real>
+dsmc_status restore_t(dsmc_ctx *c, const DevPtrs<real> &d, const void *host, size_t bytes) {
+  const Plan &P = c->plan;
+  const Geometry &g = P.g;
+  CkptHeader h;
+  if (bytes < sizeof h) return set_err(c, DSMC_EINVAL, "restore: buffer smaller than a checkpoint header");
+  std::memcpy(&h, host, sizeof h);
+  if (std::memcmp(h.magic, kCkptMagic, 8) || h.version != 1)
+    return set_err(c, DSMC_EINVAL, "restore: not a checkpoint of this library");
+  if (h.fp64 != g.fp64 || h.fingerprint != P.fingerprint || h.n_runs != g.n_runs || h.n_samples != g.n_samples)
+    return set_err(c, DSMC_EINVAL, "restore: checkpoint of a context with other runs, precision or schedule");
+  if ((size_t)h.total > bytes || (size_t)h.total < sizeof h + 8 * (size_t)g.n_runs)
+    return set_err(c, DSMC_EINVAL, "restore: truncated checkpoint");
+  const char *b = (const char *)host;
+  std::vector<int32_t> na((size_t)g.n_runs), ng((size_t)g.n_runs);
+  std::memcpy(na.data(), b + sizeof h, 4 * na.size());
+  std::memcpy(ng.data(), b + sizeof h + pad8(4 * na.size()), 4 * ng.size());
+  int64_t total_p = 0;
+  for (int r = 0; r < g.n_runs; ++r) {
+    if (na[r] < 0 || na[r] > P.spec_capacity[r] || ng[r] < 0 || ng[r] > na[r])
+      return set_err(c, DSMC_EINVAL, "restore: particle count out of range");
+    total_p += na[r];
+  }
+  if (total_p != h.particles || ckpt_bytes(P, na) != (size_t)h.total)
+    return set_err(c, DSMC_EINVAL, "restore: inconsistent checkpoint sizes");
+  dsmc_status st = sync_ctx(c);
+  if (st) return st;
+  st = ckpt_sections(c, d, const_cast<char *>(b), na, ng, false);
+  if (!st) st = check_hip(c, hipMemcpyAsync(d.n_alive, na.data(), 4 * na.size(), hipMemcpyHostToDevice, c->stream),
+                          "restore copy");
+  if (!st) st = check_hip(c, hipMemcpyAsync(d.n_gen, ng.data(), 4 * ng.size(), hipMemcpyHostToDevice, c->stream),
+                          "restore copy");
+  if (!st) st = check_hip(c, hipMemcpyAsync(d.step, &h.step, 4, hipMemcpyHostToDevice, c->stream), "restore copy");
+  // the copies above read host memory that must stay put until they finish
+  if (!st) st = check_hip(c, hipStreamSynchronize(c->stream), "sync");
+  if (!st) {
+    // the next Motion reads each particle's flight cell, which the last
+    // Interaction wrote: the same function computes it again here
+    launch_next_cells<real>(g, d, c->buf, 0, g.n_slots, c->stream);
+    st = check_hip(c, hipGetLastError(), "launch(next cells)");
+  }
+  if (!st) st = sync_ctx(c);
+  if (st) return st;
+  c->steps_done = h.steps_done;
+  c->sorted = h.sorted != 0;
+  c->lcr_valid = false;
+  return DSMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dsmc_status dsmc_checkpoint_bytes(dsmc_ctx *c, size_t *bytes) {
+  if (!c || !bytes) return DSMC_EINVAL;
+  if (c->latched) return c->latched;
+  return c->plan.g.fp64 ? checkpoint_t(c, c->dd, nullptr, 0, bytes) : checkpoint_t(c, c->df, nullptr, 0, bytes);
+}
+
+dsmc_status dsmc_checkpoint(dsmc_ctx *c, void *host, size_t bytes) {
+  if (!c || !host || ((uintptr_t)host & 7)) return DSMC_EINVAL;
+  if (c->latched) return c->latched;
+  return c->plan.g.fp64 ? checkpoint_t(c, c->dd, host, bytes, nullptr) : checkpoint_t(c, c->df, host, bytes, nullptr);
+}
+
+dsmc_status dsmc_restore(dsmc_ctx *c, const void *host, size_t bytes) {
+  if (!c || !host || ((uintptr_t)host & 7)) return DSMC_EINVAL;
+  if (c->latched) return c->latched;
+  return c->plan.g.fp64 ? restore_t(c, c->dd, host, bytes) : restore_t(c, c->df, host, bytes);
 }
 
 dsmc_status dsmc_set_profiling(dsmc_ctx *c, int32_t on) {
@@ -1196,11 +1510,6 @@ extern "C" dsmc_status dsmc_counting_sort_noalloc(const int32_t *keys, int64_t n
 
 namespace {
 
-// Candidate settings of (tile_chunks, collide_mode, n_streams) for these runs,
-// the default first: tile sizes of 16384, 8192 and 4096 slots; both
-// interaction modes when some run's expected particles per cell lie where
-// either could win (16..256); two stream lanes when there are enough runs to
-// split.
 // Expected particles per cell of a run (initial fill, or the inflow's fill).
 double fill_ppc(const dsmc_run_spec &s) {
   double fill = (double)s.n_init;
@@ -1208,9 +1517,12 @@ double fill_ppc(const dsmc_run_spec &s) {
   return fill / ((double)s.nx * s.ny * s.nz);
 }
 
-// The interaction modes worth timing: auto, plus every explicit mode when
-// some run's cells lie near a threshold of the auto rule (a quarter of the
-// wavefront threshold up to twice the block threshold).
+// Candidate settings of (tile_chunks, collide_mode, n_streams) for these runs,
+// the default first: tile sizes of 16384, 8192 and 4096 slots; auto plus
+// every explicit interaction mode when some run's expected particles per
+// cell lie near a threshold of the auto rule (a quarter of the wavefront
+// threshold up to twice the block threshold: 28..576); one or two stream
+// lanes when there are at least 8 runs to split.
 std::vector<dsmc_options> tune_candidates(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_options &base) {
   bool ambiguous = false;
   for (int r = 0; r < n_runs; ++r) {

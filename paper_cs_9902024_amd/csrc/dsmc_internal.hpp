@@ -45,6 +45,7 @@ static_assert(4 * kMaxGenAttempts + 5 <= (int)kGenUniforms, "a particle's draws 
 constexpr int kMaxInitAttempts = 100;      // initial position draws that land in solid cells
 constexpr int kFields = 7;                 // N, sum u, v, w, u^2, v^2, w^2
 constexpr int kMoments = 8;                // n, ux, uy, uz, T, Tx, Ty, Tz
+constexpr int kDiag = 7;                   // particles, generated, collisions, sum u, v, w, |c|^2
 
 // Philox counter word 1: what the stream is for.
 enum : uint32_t { kInit = 0, kGen = 1, kWall = 2, kColl = 3 };
@@ -177,6 +178,8 @@ struct DevPtrs {
   double *stage;               // [cells][7] per-run sample sums of one sample
   double *acc;                 // [n_samples][acc_stride]
   double *mom;                 // [2][max_nc][8]
+  uint32_t *nsnap;             // [n_samples] snapshots accumulated in each sample slot
+  double *diag;                // [runs][kDiag] per-run diagnostics (dsmc_get_diag)
   int32_t *n_alive;            // [runs]
   int32_t *n_sorted;           // [runs]
   int32_t *n_gen;              // [runs]
@@ -225,6 +228,8 @@ struct Geometry {
   int n_eg;
   int64_t acc_stride;
   int n_samples;
+  int window_steps;      // snapshots per sample slot (time window of a steady flow; 1 = one)
+  int window_stride;     // steps between the snapshots of a window
   int64_t n_items;      // lane-per-cell interaction items (up to 64 cells each)
   int64_t n_cell_items; // block-per-cell interaction items
   int64_t n_wave_items; // wavefront-per-cell interaction items
@@ -277,6 +282,9 @@ void launch_sample(const Geometry &g, const DevPtrs<real> &d, int buf, int slot,
 template <typename real>
 void launch_moments(const Geometry &g, const DevPtrs<real> &d, int slot, int eg0, int n_groups,
                     int nc, int n_runs_ens, hipStream_t s);
+// Per-run diagnostics of the particles in buffer buf into d.diag.
+template <typename real>
+void launch_diag(const Geometry &g, const DevPtrs<real> &d, int buf, hipStream_t s);
 
 // Stand-alone stable counting sort of keys[0..n) into lcr (device pointers).
 size_t counting_sort_workspace(int64_t n, int32_t nbins, int tile_chunks);

@@ -255,15 +255,22 @@ __global__ __launch_bounds__(256) void k_init_particles(DevPtrs<real> d, int64_t
 // Step bookkeeping
 // ---------------------------------------------------------------------------
 
-__global__ void k_step_begin(uint32_t *step, int32_t *slot, const int32_t *sample_steps, int n_samples) {
+// Advances the step counter and finds the sample slot of the new step: slot
+// k takes the snapshots after steps sample_steps[k] - j * stride, j = 0 ..
+// window - 1 (one snapshot when window = 1; a time window of a steady flow
+// otherwise).  Windows of different slots share no step (checked on the host).
+__global__ void k_step_begin(uint32_t *step, int32_t *slot, const int32_t *sample_steps, int n_samples, int window,
+                             int stride) {
   const uint32_t s = *step + 1u;
   *step = s;
   int k = -1;
-  for (int i = 0; i < n_samples; ++i)
-    if ((uint32_t)sample_steps[i] == s) {
+  for (int i = 0; i < n_samples; ++i) {
+    const int64_t back = (int64_t)sample_steps[i] - (int64_t)s;  // steps before the window's last snapshot
+    if (sample_steps[i] >= 1 && back >= 0 && back % stride == 0 && back / stride < window) {
       k = i;
       break;
     }
+  }
   *slot = k;
 }
 
@@ -874,8 +881,14 @@ __global__ __launch_bounds__(256) void k_motion_walls(DevPtrs<real> d, int buf, 
       load_zw<DIM>(P, gs, z0, w0);
       real p3[3] = {r4.x, r4.y, z0};
       real v3[3] = {r4.z, r4.w, DIM == 3 ? w0 : (real)0};
-      bool hit, reemit;
-      const int32_t c = move_one<real, DIM>(R, d.solid, step, (uint32_t)loc, p3, v3, hit, reemit, d.err);
+      bool hit = false, reemit = false;
+      // a non-finite coordinate or velocity fails Motion's free-flight test
+      // and so arrives here: report it and remove the particle
+      const bool finite = isfinite(r4.x) && isfinite(r4.y) && isfinite(z0) && isfinite(r4.z) && isfinite(r4.w) &&
+                          isfinite(w0);
+      if (!finite) set_error(d.err, kErrNumeric);
+      const int32_t c =
+          finite ? move_one<real, DIM>(R, d.solid, step, (uint32_t)loc, p3, v3, hit, reemit, d.err) : R.nc;
       // (the velocity is unchanged unless a face was hit)
       P.q[gs] = make_vec4<real>(p3[0], p3[1], v3[0], v3[1]);
       if (DIM == 3) store_zw<DIM>(P, gs, p3[2], v3[2]);
@@ -2439,6 +2452,7 @@ template <typename real>
 __global__ __launch_bounds__(256) void k_accumulate(DevPtrs<real> d, int slot_arg, int64_t stride, int n_eg) {
   const int slot = slot_arg >= 0 ? slot_arg : *d.sample_slot;
   if (slot < 0) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) d.nsnap[slot] += 1u;  // one more snapshot of every run
   double *acc = d.acc + (int64_t)slot * stride;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < stride;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -2460,15 +2474,16 @@ __global__ __launch_bounds__(256) void k_accumulate(DevPtrs<real> d, int slot_ar
   }
 }
 
-// FP64 division of sums into n (per run), mean velocity and temperatures.
-__device__ __forceinline__ void moments_of(const double *S, double n_runs, double *m) {
+// FP64 division of sums into n (per run and snapshot), mean velocity and
+// temperatures.  `samples` = runs x snapshots of each run in the sums.
+__device__ __forceinline__ void moments_of(const double *S, double samples, double *m) {
   const double N = S[0];
   const double inv = N > 0.0 ? 1.0 / N : __builtin_nan("");
   const double ux = S[1] * inv, uy = S[2] * inv, uz = S[3] * inv;
   const double Tx = S[4] * inv - ux * ux;
   const double Ty = S[5] * inv - uy * uy;
   const double Tz = S[6] * inv - uz * uz;
-  m[0] = N / n_runs;
+  m[0] = samples > 0.0 ? N / samples : __builtin_nan("");
   m[1] = ux;
   m[2] = uy;
   m[3] = uz;
@@ -2484,6 +2499,7 @@ __global__ __launch_bounds__(256) void k_moments(DevPtrs<real> d, int slot, int6
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nc) return;
   const double *acc = d.acc + (int64_t)slot * stride;
+  const double snaps = (double)d.nsnap[slot];
   double S[kFields] = {0, 0, 0, 0, 0, 0, 0};
   for (int g = 0; g < G; ++g) {
     const double *e = acc + d.eg_acc[eg0 + g] + (int64_t)c * kFields;
@@ -2491,7 +2507,7 @@ __global__ __launch_bounds__(256) void k_moments(DevPtrs<real> d, int slot, int6
     for (int f = 0; f < kFields; ++f) S[f] += e[f];
   }
   double m[kMoments];
-  moments_of(S, (double)n_runs_ens, m);
+  moments_of(S, (double)n_runs_ens * snaps, m);
   double *out = d.mom + (int64_t)c * kMoments;
   double *se = d.mom + (int64_t)max_nc * kMoments + (int64_t)c * kMoments;
 #pragma unroll
@@ -2501,7 +2517,7 @@ __global__ __launch_bounds__(256) void k_moments(DevPtrs<real> d, int slot, int6
   for (int g = 0; g < G; ++g) {
     const double *e = acc + d.eg_acc[eg0 + g] + (int64_t)c * kFields;
     double mg[kMoments];
-    moments_of(e, (double)(d.eg_start[eg0 + g + 1] - d.eg_start[eg0 + g]), mg);
+    moments_of(e, (double)(d.eg_start[eg0 + g + 1] - d.eg_start[eg0 + g]) * snaps, mg);
 #pragma unroll
     for (int f = 0; f < kMoments; ++f) {
       const double delta = mg[f] - mean[f];
@@ -2512,6 +2528,52 @@ __global__ __launch_bounds__(256) void k_moments(DevPtrs<real> d, int slot, int6
 #pragma unroll
   for (int f = 0; f < kMoments; ++f)
     se[f] = G > 1 ? sqrt(m2[f] / (double)(G - 1) / (double)G) : __builtin_nan("");
+}
+
+// Per-run diagnostics, one block per run: particles, particles generated in
+// the last step, accepted collisions so far (over the run's cells), and the
+// sums of u, v, w and |c|^2 over its particles in FP64 (each thread a fixed
+// stride, then a fixed-order tree: the same bits on every call).
+template <typename real, int DIM>
+__global__ __launch_bounds__(256) void k_diag(DevPtrs<real> d, int buf) {
+  __shared__ double red[5][256];
+  const int r = blockIdx.x, tid = threadIdx.x;
+  const RunDev &R = d.runs[r];
+  const Particles<real> P = d.P[buf];
+  const int64_t n = d.n_alive[r];
+  double su = 0.0, sv = 0.0, sw = 0.0, se = 0.0, sc = 0.0;
+  for (int64_t i = tid; i < n; i += 256) {
+    const typename Vec4<real>::type r4 = P.q[R.so + i];
+    real z, w;
+    load_zw<DIM>(P, R.so + i, z, w);
+    const double u = (double)r4.z, v = (double)r4.w, ww = (double)w;
+    su += u;
+    sv += v;
+    sw += ww;
+    se += u * u + v * v + ww * ww;
+  }
+  for (int64_t c = tid; c < R.nc; c += 256) sc += (double)d.ncoll[R.co + c];
+  red[0][tid] = su;
+  red[1][tid] = sv;
+  red[2][tid] = sw;
+  red[3][tid] = se;
+  red[4][tid] = sc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o)
+      for (int f = 0; f < 5; ++f) red[f][tid] += red[f][tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double *out = d.diag + (int64_t)r * kDiag;
+    out[0] = (double)n;
+    out[1] = (double)d.n_gen[r];
+    out[2] = red[4][0];
+    out[3] = red[0][0];
+    out[4] = red[1][0];
+    out[5] = red[2][0];
+    out[6] = red[3][0];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -2632,9 +2694,11 @@ void launch_init(const Geometry &g, const DevPtrs<real> &d, hipStream_t s) {
   hipLaunchKernelGGL(k_init_cells<real>, dim3(grid_for(g.n_cells)), dim3(256), 0, s, d, g.n_cells);
   if (g.n_faces > 0)
     hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(g.n_faces)), dim3(256), 0, s, d.rem_f, g.n_faces, 0.0);
-  if (g.n_samples > 0)
+  if (g.n_samples > 0) {
     hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(g.acc_stride * g.n_samples)), dim3(256), 0, s, d.acc,
                        g.acc_stride * g.n_samples, 0.0);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, d.nsnap, (int64_t)g.n_samples, 0u);
+  }
   if (g.dim == 3)
     hipLaunchKernelGGL((k_init_particles<real, 3>), dim3(grid_for(g.n_slots)), dim3(256), 0, s, d, g.n_slots,
                        g.tile);
@@ -2765,7 +2829,7 @@ template <typename real, int DIM>
 static void step_dim(const Geometry &g, const DevPtrs<real> &d, int buf, hipStream_t s, const LaneStreams *ls,
                      const Prof *prof) {
   TIMED(kKStepBegin, hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(1), 0, s, d.step, d.sample_slot,
-                                        d.sample_steps, g.n_samples));
+                                        d.sample_steps, g.n_samples, g.window_steps, g.window_stride));
   if (g.n_lanes <= 1 || !ls) {
     LaneRange all = g.lane[0];
     if (g.n_lanes > 1) {
@@ -2773,8 +2837,11 @@ static void step_dim(const Geometry &g, const DevPtrs<real> &d, int buf, hipStre
       all.t1 = g.lane[g.n_lanes - 1].t1;
       all.f1 = g.lane[g.n_lanes - 1].f1;
       all.i1 = g.lane[g.n_lanes - 1].i1;
+      all.g1 = g.lane[g.n_lanes - 1].g1;
       all.it1 = g.lane[g.n_lanes - 1].it1;
       all.ci1 = g.lane[g.n_lanes - 1].ci1;
+      all.wi1 = g.lane[g.n_lanes - 1].wi1;
+      all.b1 = g.lane[g.n_lanes - 1].b1;
     }
     lane_step<real, DIM>(g, all, d, buf, s, nullptr, prof);
   } else {
@@ -2815,7 +2882,15 @@ void launch_moments(const Geometry &g, const DevPtrs<real> &d, int slot, int eg0
                      n_groups, nc, n_runs_ens, g.max_nc);
 }
 
+template <typename real>
+void launch_diag(const Geometry &g, const DevPtrs<real> &d, int buf, hipStream_t s) {
+  if (g.dim == 3) hipLaunchKernelGGL((k_diag<real, 3>), dim3(g.n_runs), dim3(256), 0, s, d, buf);
+  else hipLaunchKernelGGL((k_diag<real, 2>), dim3(g.n_runs), dim3(256), 0, s, d, buf);
+}
+
 template void launch_init<float>(const Geometry &, const DevPtrs<float> &, hipStream_t);
+template void launch_diag<float>(const Geometry &, const DevPtrs<float> &, int, hipStream_t);
+template void launch_diag<double>(const Geometry &, const DevPtrs<double> &, int, hipStream_t);
 template void launch_init<double>(const Geometry &, const DevPtrs<double> &, hipStream_t);
 template void launch_next_cells<float>(const Geometry &, const DevPtrs<float> &, int, int64_t, int64_t, hipStream_t);
 template void launch_next_cells<double>(const Geometry &, const DevPtrs<double> &, int, int64_t, int64_t,

@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported(dsmc):
 def test_struct_sizes_match_header(dsmc):
     # layout of the two public structs (x86-64 SysV ABI)
     assert C.sizeof(dsmc.dsmc_run_spec) == 248
-    assert C.sizeof(dsmc.dsmc_options) == 40
+    assert C.sizeof(dsmc.dsmc_options) == 48
 
 
 def test_array_lengths_match_header(dsmc):
@@ -46,6 +46,7 @@ def test_array_lengths_match_header(dsmc):
     defs = dict(re.findall(r"#define (DSMC_N[A-Z]+) (\d+)", src))
     assert int(defs["DSMC_NINFO"]) == dsmc.NINFO
     assert int(defs["DSMC_NKERNELS"]) == dsmc.NKERNELS
+    assert int(defs["DSMC_NDIAG"]) == dsmc.NDIAG == len(dsmc.DIAG_NAMES)
 
 
 def test_stream_lane_option_is_validated(dsmc):
@@ -199,3 +200,17 @@ def test_sort_scratch_size_matches_header(dsmc):
     src = open(os.path.join(ROOT, "include", "dsmc.h")).read()
     m = re.search(r"#define DSMC_SORT_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", src)
     assert m and int(m.group(1)) << int(m.group(2)) == dsmc.SORT_SCRATCH_BYTES
+
+
+def test_sampling_windows_are_validated(dsmc):
+    specs = dsmc._specs(W.plain_box().runs)
+    ok = [([10, 20], 5, 2), ([3, 20], 5, 1), ([10, 20], 0, 0), ([0, 20], 30, 1)]
+    for steps, w, q in ok:
+        dsmc.dsmc_required_bytes(specs, dsmc.make_options(True, 1, steps, window_steps=w, window_stride=q))
+    # windows that share a step, and negative fields
+    bad = [([10, 12], 3, 1), ([10, 20], 6, 2), ([10, 20], -1, 1), ([10, 20], 2, -3)]
+    for steps, w, q in bad:
+        with pytest.raises(dsmc.DsmcError) as e:
+            dsmc.dsmc_required_bytes(specs, dsmc.make_options(True, 1, steps, window_steps=w,
+                                                              window_stride=q))
+        assert e.value.status == -1

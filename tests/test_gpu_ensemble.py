@@ -24,6 +24,9 @@ pytestmark = pytest.mark.gpu
 
 
 def _z_gate(z, label):
+    # a zero standard error on both sides with different means is a failure,
+    # not a missing entry (entries masked out on purpose are NaN)
+    assert not np.any(np.isinf(z)), (label, "zero standard error but different means")
     z = z[np.isfinite(z)]
     M = z.size
     assert M > 200, label
@@ -69,6 +72,55 @@ def test_channel_fp32_ensemble_matches_oracle_ensemble(dsmc_gpu, oracle_lib):
         zf = z[..., f][np.isfinite(z[..., f])]
         assert abs(zf.mean()) <= 3 / math.sqrt(zf.size) + 0.05, (f, zf.mean())
     assert M > 1000
+    _library_moments_equal_oracle_division(E, acc_g, n_runs)
+
+
+def _library_moments_equal_oracle_division(E, acc, n_runs):
+    """dsmc_read_moments (FP64 division on the device) element by element
+    against the oracle's division of the same sums, values and batch-means
+    errors (one group per run here)."""
+    import oracle
+    for k in range(acc.shape[0]):
+        m, se = E.moments(k)
+        G = acc.shape[1]
+        np.testing.assert_allclose(m, oracle.moments(acc[k].sum(axis=0), n_runs), rtol=1e-12, atol=1e-14,
+                                   equal_nan=True)
+        per = oracle.moments(acc[k], n_runs // G)
+        with np.errstate(invalid="ignore"):
+            se_o = np.nanstd(per, axis=0, ddof=1) / math.sqrt(G)
+        # cells without particles in some group: NaN on both sides
+        se_o = np.where(np.isnan(per).any(axis=0), np.nan, se_o)
+        np.testing.assert_allclose(se, se_o, rtol=1e-9, atol=1e-14, equal_nan=True)
+
+
+def test_channel_fp32_at_122_per_cell_matches_oracle_ensemble(dsmc_gpu, oracle_lib):
+    """The channel at its free-stream fill of 122 particles per cell, where
+    the auto mode gives each cell a wavefront: 64 runs on each side, three
+    sample times, the same 3-standard-error gate, and the library's moments
+    equal to the oracle's division of the same sums."""
+    n_runs = 64
+    base = W.channel(n_runs=n_runs, nx=32, ny=8, ppc_inf=122.0, n_steps=120, sample_every=40,
+                     seed=111, n_groups=n_runs)
+    E = dsmc_gpu.Ensemble.from_workload(base, state_fp64=False)
+    assert E.info()["runs"] == n_runs
+    E.step(base.n_steps)
+    acc_g = np.stack([E.accum(k) for k in range(len(base.sample_steps))])
+    acc_o, _ = oracle_lib.ensemble(base.with_seed(222), n_threads=16)
+    fields = [0, 1, 2, 4]
+    mg, sg, ng = _per_run_moments(acc_g, fields)
+    mo, so, no = _per_run_moments(acc_o, fields)
+    ok = (np.nanmean(ng, axis=1) >= 5) & (np.nanmean(no, axis=1) >= 5)
+    z = (mg - mo) / np.sqrt(sg ** 2 + so ** 2)
+    z = np.where(ok[..., None], z, np.nan)
+    M = _z_gate(z, "channel at 122 per cell")
+    for f in range(len(fields)):
+        zf = z[..., f][np.isfinite(z[..., f])]
+        assert abs(zf.mean()) <= 3 / math.sqrt(zf.size) + 0.05, (f, zf.mean())
+    assert M > 1000
+    # the fill the auto rule saw: cells behind the front hold ~122 per run
+    full = mg[-1][..., 0][ok[-1]]
+    assert np.nanmax(full) > 100
+    _library_moments_equal_oracle_division(E, acc_g, n_runs)
 
 
 def test_box_fp32_ensemble_equilibrium_closed_form(dsmc_gpu):
@@ -94,8 +146,9 @@ def test_box_fp32_ensemble_equilibrium_closed_form(dsmc_gpu):
 
 def test_uneven_batch_fp32_matches_oracle_runs(dsmc_gpu, oracle_lib):
     """Uneven runs (different grids, counts, HS/VHS, Mach numbers) in one
-    launch: each run's sampled density profile agrees with the oracle's
-    ensemble of the same run spec (disjoint seeds), integrated over columns."""
+    launch: each run's per-cell density, velocity and temperature agree with
+    the oracle's ensemble of the same run spec (disjoint seeds) within the
+    3-standard-error gate."""
     wl = W.uneven(n_runs=4, n_steps=60, n_samples=1, seed=4, count_range=(20e3, 60e3),
                   grids=((32, 32), (64, 32)))
     reps = 24
@@ -106,15 +159,17 @@ def test_uneven_batch_fp32_matches_oracle_runs(dsmc_gpu, oracle_lib):
             ora_runs.append(replace(rs, run_id=1000 * r + k, seed=8, ensemble=r))
     E = dsmc_gpu.Ensemble(gpu_runs, wl.sample_steps, state_fp64=False, n_groups=reps)
     E.step(wl.n_steps)
+    zs = []
     for r, rs in enumerate(wl.runs):
         ag = E.accum(0, ensemble=r)                                    # [reps][cell][7]
         sub = W.Workload("u", ora_runs[r * reps:(r + 1) * reps], wl.n_steps, wl.sample_steps, reps)
         ao, _ = oracle_lib.ensemble(sub, n_threads=16)
-        cols_g = ag[..., 0].reshape(reps, rs.ny, rs.nx).sum(axis=1)   # per run, per column
-        cols_o = ao[0, ..., 0].reshape(reps, rs.ny, rs.nx).sum(axis=1)
-        d = cols_g.mean(0) - cols_o.mean(0)
-        se = np.sqrt(cols_g.var(0, ddof=1) / reps + cols_o.var(0, ddof=1) / reps)
-        ok = se > 0
-        z = d[ok] / se[ok]
-        assert np.max(np.abs(z)) < 5.0, (r, z)
-        assert np.mean(np.abs(z) > 3) < 0.05, (r, z)
+        # per cell: n, ux, uy, T with run-to-run standard errors
+        mg, sg, ng = _per_run_moments(ag[None], [0, 1, 2, 4])
+        mo, so, no = _per_run_moments(ao, [0, 1, 2, 4])
+        ok = (np.nanmean(ng, axis=1) >= 5) & (np.nanmean(no, axis=1) >= 5)
+        z = (mg - mo) / np.sqrt(sg ** 2 + so ** 2)
+        zs.append(np.where(ok[..., None], z, np.nan).ravel())
+    z = np.concatenate(zs)
+    M = _z_gate(z, "uneven runs, per cell")
+    assert M > 1000

@@ -10,7 +10,8 @@ the oracle can compute one by one, and properties that hold at any size.
 - Whole ensemble: particle counts and energies conserved in the specular box,
   collisions per step at the hard-sphere equilibrium rate, and every cell's
   density and temperature within 1 % of the exact equilibrium values (about
-  977 particles per cell per run).
+  977 particles per cell per run) and within 3 of the returned batch-means
+  standard errors.
 """
 import math
 
@@ -111,3 +112,20 @@ def test_full_size_conservation_and_equilibrium_moments(full, dsmc_gpu):
     assert np.all(np.abs(m[:, 1:4]) < 0.01 * math.sqrt(3 * T))
     # batch-means errors are small and finite
     assert np.all(np.isfinite(se)) and np.all(se[:, 0] < 0.005 * n_exact)
+    # within 3 standard errors of the exact equilibrium: n = N/1024 per run,
+    # zero mean velocity, and the temperature of the whole gas (energy is
+    # conserved, so every cell's expected T is the realised one, taken from
+    # the sums over all cells and runs); 32 run groups: Student t with 31
+    # degrees of freedom, whose |t| > 3 rate is 0.53 %
+    tot = E.accum(1).sum(axis=(0, 1))
+    u_all = tot[1:4] / tot[0]
+    T_all = ((tot[4] + tot[5] + tot[6]) / tot[0] - float(u_all @ u_all)) / 3.0
+    assert tot[0] == 512 * N_PER
+    exact = np.array([n_exact, 0.0, 0.0, T_all])
+    z = (m[:, [0, 1, 2, 4]] - exact) / se[:, [0, 1, 2, 4]]
+    assert np.all(np.isfinite(z))
+    M = z.size
+    assert np.mean(np.abs(z) > 3) <= 0.0053 + 3 * math.sqrt(0.0053 / M), np.mean(np.abs(z) > 3)
+    assert np.max(np.abs(z)) < 6.5, np.max(np.abs(z))
+    for f in range(4):
+        assert abs(z[:, f].mean()) <= 3 / math.sqrt(z.shape[0]) + 0.05, (f, z[:, f].mean())
