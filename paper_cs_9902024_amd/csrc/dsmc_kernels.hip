@@ -705,11 +705,28 @@ __device__ __forceinline__ void store4(real *p, int64_t i, const real (&o)[4]) {
   *reinterpret_cast<typename Vec4<real>::type *>(p + i) = t;
 }
 
+// Wall-queue entries a Motion wavefront stages in LDS before writing them to
+// the tile's queue: stores to global memory inside the round loop would also
+// hold back the waits for the loads issued before them (one counter for
+// vector loads and stores), so they go out in coalesced batches instead.
+constexpr int kMotionQueueStage = 384;
+
+// Moves the wavefront's staged queue entries qb[0, ql) to the tile's queue
+// wq[qn, ...).
+__device__ __forceinline__ void motion_flush(uint32_t *qb, uint32_t &ql, uint32_t *wq, uint32_t &qn) {
+  const int lane = threadIdx.x & 63;
+  for (uint32_t k = lane; k < ql; k += kWave) wq[qn + k] = qb[k];
+  qn += ql;
+  ql = 0;
+  wave_sync();
+}
+
 // One round of Motion's counting: the new cell of every free particle into
-// the tile histogram, the others (those that reach a face) into the tile's
-// wall queue, in slot order within the round.
-__device__ __forceinline__ void motion_count(uint32_t *h, uint32_t *wq, uint32_t &qn, int64_t i0,
-                                             const uint32_t (&key)[4], const bool (&fast)[4],
+// the tile histogram, the others (those that reach a face) into the staged
+// wall queue, in slot order within the round; the stage goes out when the
+// next round might not fit it.
+__device__ __forceinline__ void motion_count(uint32_t *h, uint32_t *qb, uint32_t &ql, uint32_t *wq, uint32_t &qn,
+                                             int64_t i0, const uint32_t (&key)[4], const bool (&fast)[4],
                                              const bool (&act)[4]) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -719,15 +736,16 @@ __device__ __forceinline__ void motion_count(uint32_t *h, uint32_t *wq, uint32_t
     const bool mine = act[e] && !fast[e];
     const uint64_t m = __ballot(mine);
     if (m == 0ull) continue;
-    if (mine) wq[qn + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)(i0 + e);
-    qn += (uint32_t)__popcll(m);
+    if (mine) qb[ql + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)(i0 + e);
+    ql += (uint32_t)__popcll(m);
   }
+  if (ql > (uint32_t)(kMotionQueueStage - 4 * kWave)) motion_flush(qb, ql, wq, qn);
 }
 
 // A round whose four cells per lane the last Interaction left in place.
 template <bool SINGLE>
-__device__ __forceinline__ void motion_pre_round(uint32_t *h, uint32_t *wq, uint32_t &qn, int64_t i0, int4 c4,
-                                                 int shift0) {
+__device__ __forceinline__ void motion_pre_round(uint32_t *h, uint32_t *qb, uint32_t &ql, uint32_t *wq, uint32_t &qn,
+                                                 int64_t i0, int4 c4, int shift0) {
   const int32_t oc[4] = {c4.x, c4.y, c4.z, c4.w};
   const bool act[4] = {true, true, true, true};
   uint32_t key[4];
@@ -737,7 +755,7 @@ __device__ __forceinline__ void motion_pre_round(uint32_t *h, uint32_t *wq, uint
     fast[e] = !(oc[e] & kQueueBit);
     key[e] = SINGLE ? (uint32_t)oc[e] : (((uint32_t)oc[e] >> shift0) & (kDigits - 1));
   }
-  motion_count(h, wq, qn, i0, key, fast, act);
+  motion_count(h, qb, ql, wq, qn, i0, key, fast, act);
 }
 
 // One wavefront per tile of tile_chunks*64 consecutive slots of one run.
@@ -764,6 +782,8 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
   const int64_t tl = t - R.to;
   const int D = SINGLE ? R.nc + 1 : kDigits;
   uint32_t *h = lds + wave * dstride;
+  uint32_t *qb = lds + kWavesPerBlock * dstride + wave * kMotionQueueStage;  // staged queue entries
+  uint32_t ql = 0;
   for (int q = lane; q < D; q += kWave) h[q] = 0;
   wave_sync();
   const int64_t n = d.n_alive[r];
@@ -786,10 +806,12 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
 #pragma unroll
     for (int u = 0; u < PU; ++u) c4[u] = *reinterpret_cast<const int4 *>(cell + b + u * 4 * kWave + 4 * lane);
 #pragma unroll
-    for (int u = 0; u < PU; ++u) motion_pre_round<SINGLE>(h, wq, qn, b + u * 4 * kWave + 4 * lane, c4[u], shift0);
+    for (int u = 0; u < PU; ++u)
+      motion_pre_round<SINGLE>(h, qb, ql, wq, qn, b + u * 4 * kWave + 4 * lane, c4[u], shift0);
   }
   for (; b < pre_end; b += 4 * kWave)
-    motion_pre_round<SINGLE>(h, wq, qn, b + 4 * lane, *reinterpret_cast<const int4 *>(cell + b + 4 * lane), shift0);
+    motion_pre_round<SINGLE>(h, qb, ql, wq, qn, b + 4 * lane, *reinterpret_cast<const int4 *>(cell + b + 4 * lane),
+                             shift0);
   for (; b < end; b += 4 * kWave) {
     const int64_t i0 = b + 4 * lane;
     const bool full = b + 4 * kWave <= end;  // wave-uniform
@@ -843,8 +865,9 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
       for (int e = 0; e < 4; ++e)
         if (act[e]) cell[i0 + e] = oc[e];
     }
-    motion_count(h, wq, qn, i0, key, fast, act);
+    motion_count(h, qb, ql, wq, qn, i0, key, fast, act);
   }
+  if (ql) motion_flush(qb, ql, wq, qn);
   if (lane == 0) d.wallq_n[t] = qn;
   wave_sync();
   uint32_t *Mt = d.hist + R.mo + tl * D;
@@ -1241,12 +1264,22 @@ __device__ __forceinline__ void init_cursors(uint32_t *cursor, const uint32_t *S
                                              int64_t valid) {
   constexpr int B = 8;
   const int lane = threadIdx.x & 63;
+  // loads from an index clamped into [0, lim) and no condition around them:
+  // a load inside a branch is waited for at the branch's join, which would
+  // serialise the eight
+  const int lim = (int)(valid < (int64_t)D ? valid : (int64_t)D);  // >= 1
   for (int q0 = 0; q0 < D; q0 += B * kWave) {
     uint32_t v[B];
 #pragma unroll
     for (int e = 0; e < B; ++e) {
       const int q = q0 + e * kWave + lane;
-      v[e] = (q < D && q < valid) ? S[q] + M[q] : 0u;
+      const int qc = q < lim ? q : lim - 1;
+      v[e] = S[qc] + M[qc];
+    }
+#pragma unroll
+    for (int e = 0; e < B; ++e) {
+      const int q = q0 + e * kWave + lane;
+      if (q >= lim) v[e] = 0u;
     }
 #pragma unroll
     for (int e = 0; e < B; ++e) {
@@ -2722,6 +2755,7 @@ static void lane_step(const Geometry &g, const LaneRange &L, const DevPtrs<real>
                                         L.i1));
   }
   const size_t lds = (size_t)kWavesPerBlock * g.dstride * sizeof(uint32_t);
+  const size_t mlds = lds + (size_t)kWavesPerBlock * kMotionQueueStage * sizeof(uint32_t);
   const int wblocks = (n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
   IndexArgs a = index_args(g, d);
   a.t0 = L.t0;
@@ -2729,10 +2763,10 @@ static void lane_step(const Geometry &g, const LaneRange &L, const DevPtrs<real>
   a.r0 = L.r0;
   if (g.npass == 1) {
     if (g.any_solid)
-      TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, true, true>), dim3(wblocks), dim3(256), lds, s, d, buf,
+      TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, true, true>), dim3(wblocks), dim3(256), mlds, s, d, buf,
                                          L.t0, L.t1, g.tile, g.dstride, 0));
     else
-      TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, true, false>), dim3(wblocks), dim3(256), lds, s, d,
+      TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, true, false>), dim3(wblocks), dim3(256), mlds, s, d,
                                          buf, L.t0, L.t1, g.tile, g.dstride, 0));
     TIMED(kKMotionWalls, hipLaunchKernelGGL((k_motion_walls<real, DIM, true>), dim3(n_tiles), dim3(256), 0, s, d,
                                             buf, L.t0, L.t1, g.tile, 0));
@@ -2742,10 +2776,10 @@ static void lane_step(const Geometry &g, const LaneRange &L, const DevPtrs<real>
     // the first digit: the bucket (two-level sort) or the lowest 11 bits
     const int shift0 = g.bucketed ? kDigitBits : 0;
     if (g.any_solid)
-      TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, false, true>), dim3(wblocks), dim3(256), lds, s, d,
+      TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, false, true>), dim3(wblocks), dim3(256), mlds, s, d,
                                          buf, L.t0, L.t1, g.tile, g.dstride, shift0));
     else
-      TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, false, false>), dim3(wblocks), dim3(256), lds, s, d,
+      TIMED(kKMotion, hipLaunchKernelGGL((k_motion<real, DIM, false, false>), dim3(wblocks), dim3(256), mlds, s, d,
                                          buf, L.t0, L.t1, g.tile, g.dstride, shift0));
     TIMED(kKMotionWalls, hipLaunchKernelGGL((k_motion_walls<real, DIM, false>), dim3(n_tiles), dim3(256), 0, s, d,
                                             buf, L.t0, L.t1, g.tile, shift0));
