@@ -54,7 +54,8 @@ class OrSpec(C.Structure):
                 ("solid", C.c_void_p), ("solid_T", C.c_double),
                 ("capacity", C.c_int64), ("n_init", C.c_int64),
                 ("init_U", C.c_double * 3), ("init_T", C.c_double),
-                ("run_id", C.c_uint32), ("seed", C.c_uint32)]
+                ("run_id", C.c_uint32), ("seed", C.c_uint32), ("subcells", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 _lib = None
@@ -94,7 +95,7 @@ def lib():
         L.or_set_cell_state.argtypes = [P, dp, dp]
         L.or_counting_sort.argtypes = [P, C.c_int64, C.c_int64, P, P, P]
         L.or_collide_cell.argtypes = [C.POINTER(OrSpec), C.c_uint32, C.c_uint32, C.c_int64,
-                                      dp, dp, dp, dp, dp, P, C.c_int64, C.POINTER(C.c_int64)]
+                                      dp, dp, dp, dp, dp, P, P, C.c_int64, C.POINTER(C.c_int64)]
         L.or_collide_cell.restype = C.c_int64
         L.or_ensemble.argtypes = [C.POINTER(OrSpec), C.c_int32, C.c_int32, P, C.c_int32,
                                   C.c_int32, C.c_int32, C.c_int32, C.c_int32, dp,
@@ -133,6 +134,7 @@ def make_spec(rs) -> OrSpec:
         s.init_U[a] = rs.init_U[a]
     s.init_T = rs.init_T
     s.run_id, s.seed = rs.run_id & 0xFFFFFFFF, rs.seed & 0xFFFFFFFF
+    s.subcells = getattr(rs, "subcells", 1)
     return s
 
 
@@ -216,10 +218,10 @@ class OracleRun:
 
     # -- accessors -------------------------------------------------------------
     def info(self) -> dict:
-        a = (C.c_int64 * 10)()
+        a = (C.c_int64 * 11)()
         lib().or_get_info(self._h, a)
         keys = ("n", "step", "err", "nc", "n_sorted", "ncoll", "ngen", "nremoved", "nmoved",
-                "nface")
+                "nface", "nbin")
         return dict(zip(keys, list(a)))
 
     def consts(self) -> dict:
@@ -248,8 +250,10 @@ class OracleRun:
         lib().or_set_step(self._h, step)
 
     def cells(self) -> dict:
+        """The last Indexing: bin of each slot (cell, or sub-cell with
+        sub-cells; nbin = DEAD), LCR, bin starts [nbin+2] and counts [nbin+1]."""
         info = self.info()
-        ns, nc = info["n_sorted"], info["nc"]
+        ns, nc = info["n_sorted"], info["nbin"]
         cell = np.zeros(ns, np.int32)
         lcr = np.zeros(ns, np.int32)
         cstart = np.zeros(nc + 2, np.int64)
@@ -300,18 +304,21 @@ def counting_sort(keys: np.ndarray, nbins: int):
 
 
 def collide_cell(rs, step: int, cell: int, vel: np.ndarray, gmax: float, rem: float = 0.0,
-                 trace_cap: int = 0):
+                 trace_cap: int = 0, sub_off: Optional[Sequence[int]] = None):
     """Interaction in one cell with given velocities [3][N] (modified copy
-    returned).  Returns dict(vel, gmax, rem, ncoll, nsel, trace[nsel][3])."""
+    returned); with sub-cells (rs.subcells > 1) sub_off holds the S + 1
+    sub-cell starts of the N particles.  Returns dict(vel, gmax, rem, ncoll,
+    nsel, trace[nsel][3])."""
     spec = make_spec(rs)
     v = np.array(vel, dtype=np.float64, copy=True)
     u, vv, w = (np.ascontiguousarray(v[a]) for a in range(3))
     g = np.array([gmax]); r = np.array([rem])
     tr = np.zeros((max(trace_cap, 1), 3), np.int32)
     nsel = C.c_int64(0)
+    off = None if sub_off is None else np.ascontiguousarray(sub_off, dtype=np.int64)
     k = lib().or_collide_cell(C.byref(spec), step, cell, u.size, _dp(u), _dp(vv), _dp(w), _dp(g),
-                              _dp(r), tr.ctypes.data if trace_cap else None, trace_cap,
-                              C.byref(nsel))
+                              _dp(r), off.ctypes.data if off is not None else None,
+                              tr.ctypes.data if trace_cap else None, trace_cap, C.byref(nsel))
     if k < 0:
         raise ValueError(STATUS.get(k, k))
     return {"vel": np.stack([u, vv, w]), "gmax": g[0], "rem": r[0], "ncoll": k,

@@ -85,11 +85,17 @@ typedef struct {
     double init_U[3];
     double init_T;
     uint32_t run_id, seed;
+    int32_t subcells;    /* collision partners from sub-cells: k per axis (0 or 1 = none) */
+    int32_t pad;
 } or_spec;
 
 typedef struct {
     or_spec sp;
-    int64_t nc;          /* cells; the DEAD bin is nc */
+    int64_t nc;          /* cells */
+    int64_t sub;         /* sub-cells per axis (1 = none) */
+    int64_t S;           /* sub-cells per cell, sub^dim */
+    int64_t nbin;        /* Indexing bins (sub-cells), nc * S; the DEAD bin is nbin */
+    double inv_f[3];     /* sub-cells per unit length along each axis */
     int64_t nface;       /* inflow face elements, 0 without inflow */
     double L[3];
     double inv_d[3];     /* cells per unit length along each axis */
@@ -101,11 +107,11 @@ typedef struct {
     int64_t n;           /* particles in P */
     double *p[6];        /* x, y, z, u, v, w (z is 0 in 2-D) */
     double *q[6];        /* scratch for the permutation */
-    int32_t *cell;       /* cell of each slot after Motion (nc = DEAD) */
+    int32_t *cell;       /* bin (sub-cell) of each slot after Motion (nbin = DEAD) */
     int32_t *lcr;        /* readdressing array */
     int64_t n_sorted;    /* number of entries of lcr (particles before removal) */
-    int64_t *cstart;     /* nc + 2 */
-    int64_t *ccount;     /* nc + 1 */
+    int64_t *cstart;     /* nbin + 2 bin starts */
+    int64_t *ccount;     /* nbin + 1 */
     double *rem_c, *gmax;
     int64_t *ncoll;
     double *rem_f;
@@ -205,6 +211,22 @@ static int64_t cell_of(const or_run *R, const double pos[3])
     return (iz * R->sp.ny + iy) * R->sp.nx + ix;
 }
 
+/* The Indexing bin of a position: its cell when there are no sub-cells;
+ * otherwise the sub-cell grid (sub per axis) is indexed cell by cell, bin =
+ * cell * S + (sz * sub + sy) * sub + sx, the cell being the sub-cell index
+ * divided by sub along each axis. */
+static int64_t bin_of(const or_run *R, const double pos[3])
+{
+    if (R->sub == 1) return cell_of(R, pos);
+    const int64_t k = R->sub;
+    int64_t fx = axis_index(pos[0], R->inv_f[0], (int32_t)(R->sp.nx * k));
+    int64_t fy = axis_index(pos[1], R->inv_f[1], (int32_t)(R->sp.ny * k));
+    int64_t fz = (R->sp.dim == 3) ? axis_index(pos[2], R->inv_f[2], (int32_t)(R->sp.nz * k)) : 0;
+    int64_t c = ((fz / k) * R->sp.ny + fy / k) * R->sp.nx + fx / k;
+    int64_t s = ((fz % k) * k + fy % k) * k + fx % k;
+    return c * R->S + s;
+}
+
 /* g = sigma(c_r)/sigma_ref * c_r for HS / VHS. */
 static double g_of(const or_run *R, double cr)
 {
@@ -242,11 +264,19 @@ or_run *or_run_new(const or_spec *sp, int32_t *status)
         if (bc < 0 || bc > 3) { *status = OR_EINVAL; return NULL; }
         if (bc == OR_BC_INFLOW && f != 0) { *status = OR_EINVAL; return NULL; }
     }
+    if (sp->subcells < 0 || sp->subcells > 4) { *status = OR_EINVAL; return NULL; }
+    if (sp->subcells > 1 && sp->solid) { *status = OR_EUNSUPPORTED; return NULL; }
     or_run *R = (or_run *)calloc(1, sizeof(or_run));
     if (!R) { *status = OR_ENOMEM; return NULL; }
     R->sp = *sp;
     R->sp.solid = NULL;
     R->nc = (int64_t)sp->nx * sp->ny * sp->nz;
+    R->sub = sp->subcells > 1 ? sp->subcells : 1;
+    R->S = R->sub * R->sub * (sp->dim == 3 ? R->sub : 1);
+    R->nbin = R->nc * R->S;
+    R->inv_f[0] = (double)(sp->nx * R->sub) / sp->lx;
+    R->inv_f[1] = (double)(sp->ny * R->sub) / sp->ly;
+    R->inv_f[2] = (double)(sp->nz * R->sub) / sp->lz;
     R->L[0] = sp->lx; R->L[1] = sp->ly; R->L[2] = sp->lz;
     R->inv_d[0] = (double)sp->nx / sp->lx;
     R->inv_d[1] = (double)sp->ny / sp->ly;
@@ -305,8 +335,8 @@ or_run *or_run_new(const or_spec *sp, int32_t *status)
     }
     R->cell = (int32_t *)calloc((size_t)cap, sizeof(int32_t));
     R->lcr = (int32_t *)calloc((size_t)cap, sizeof(int32_t));
-    R->cstart = (int64_t *)calloc((size_t)(R->nc + 2), sizeof(int64_t));
-    R->ccount = (int64_t *)calloc((size_t)(R->nc + 1), sizeof(int64_t));
+    R->cstart = (int64_t *)calloc((size_t)(R->nbin + 2), sizeof(int64_t));
+    R->ccount = (int64_t *)calloc((size_t)(R->nbin + 1), sizeof(int64_t));
     R->rem_c = (double *)calloc((size_t)R->nc, sizeof(double));
     R->gmax = (double *)calloc((size_t)R->nc, sizeof(double));
     R->ncoll = (int64_t *)calloc((size_t)R->nc, sizeof(int64_t));
@@ -553,7 +583,8 @@ void or_motion(or_run *R)
         int64_t c = move_one(R, i, pos, vel);
         R->p[0][i] = pos[0]; R->p[1][i] = pos[1]; R->p[2][i] = pos[2];
         R->p[3][i] = vel[0]; R->p[4][i] = vel[1]; R->p[5][i] = vel[2];
-        R->cell[i] = (int32_t)c;
+        /* Enumeration: the particle's bin (its sub-cell, or its cell) */
+        R->cell[i] = (int32_t)(c == R->nc ? R->nbin : (R->sub == 1 ? c : bin_of(R, pos)));
         if (c == R->nc) removed++;
     }
     R->last_nremoved = removed;
@@ -581,14 +612,14 @@ void or_counting_sort(const int32_t *key, int64_t n, int64_t nbins, int32_t *lcr
 
 void or_indexing(or_run *R)
 {
-    or_counting_sort(R->cell, R->n, R->nc + 1, R->lcr, R->cstart, R->ccount);
+    or_counting_sort(R->cell, R->n, R->nbin + 1, R->lcr, R->cstart, R->ccount);
     R->n_sorted = R->n;
 }
 
 /* P <- P[LCR[0 : n - #DEAD]]: P becomes cell-sorted and the DEAD bin drops. */
 void or_permute(or_run *R)
 {
-    int64_t keep = R->n - R->ccount[R->nc];
+    int64_t keep = R->n - R->ccount[R->nbin];
     for (int a = 0; a < 6; ++a) {
         for (int64_t p = 0; p < keep; ++p) R->q[a][p] = R->p[a][R->lcr[p]];
         double *t = R->p[a];
@@ -602,11 +633,32 @@ void or_permute(or_run *R)
 /* Interaction: NTC collisions in one cell                                    */
 /* ------------------------------------------------------------------------- */
 
-/* Collides the N particles whose velocities are u[0..N), v[..], w[..].
+/* The second partner of selection k given the first, i: with sub-cells
+ * (off = the S + 1 sub-cell starts of the cell, relative to its first
+ * particle) another particle of i's sub-cell when it holds two or more,
+ * drawn uniformly; otherwise, and without sub-cells, another particle of the
+ * cell, drawn uniformly.  Either way one index draw, from word a. */
+static int64_t second_partner(uint32_t a, int64_t i, int64_t N, const int64_t *off)
+{
+    if (off) {
+        int64_t s = 0;
+        while (off[s + 1] <= i) s++;
+        int64_t ns = off[s + 1] - off[s];
+        if (ns >= 2) {
+            int64_t jp = off[s] + or_index(a, (uint32_t)(ns - 1));
+            return jp + (jp >= i ? 1 : 0);
+        }
+    }
+    int64_t jp = or_index(a, (uint32_t)(N - 1));
+    return jp + (jp >= i ? 1 : 0);
+}
+
+/* Collides the N particles whose velocities are u[0..N), v[..], w[..]; off
+ * (NULL without sub-cells) holds the S + 1 sub-cell starts.
  * trace (optional) receives (i, j, accepted) per selection, at most
  * trace_cap selections. Returns the number of accepted collisions. */
 static int64_t collide_cell(const or_run *R, uint32_t cell, int64_t N, double *u, double *v,
-                            double *w, double *gmax, double *rem, int32_t *trace,
+                            double *w, double *gmax, double *rem, const int64_t *off, int32_t *trace,
                             int64_t trace_cap, int64_t *nsel_out)
 {
     double npairs = 0.5 * (double)(N * (N - 1));
@@ -624,8 +676,7 @@ static int64_t collide_cell(const or_run *R, uint32_t cell, int64_t N, double *u
         or_philox4x32_10(c0, (const uint32_t[2]){R->sp.run_id, R->sp.seed}, b0);
         or_philox4x32_10(c1, (const uint32_t[2]){R->sp.run_id, R->sp.seed}, b1);
         int64_t i = or_index(b0[0], (uint32_t)N);
-        int64_t jp = or_index(b0[1], (uint32_t)(N - 1));
-        int64_t j = jp + (jp >= i ? 1 : 0);
+        int64_t j = second_partner(b0[1], i, N, off);
         double du = u[i] - u[j], dv = v[i] - v[j], dw = w[i] - w[j];
         double cr = sqrt(du * du + dv * dv + dw * dw);
         double g = g_of(R, cr);
@@ -652,21 +703,25 @@ static int64_t collide_cell(const or_run *R, uint32_t cell, int64_t N, double *u
 void or_interaction(or_run *R)
 {
     int64_t total = 0;
+    int64_t *off = (int64_t *)malloc((size_t)(R->S + 1) * sizeof(int64_t));
     for (int64_t c = 0; c < R->nc; ++c) {
-        int64_t b = R->cstart[c], N = R->ccount[c];
+        /* the cell's particles: its S bins, consecutive in LCR order */
+        int64_t b = R->cstart[c * R->S], N = R->cstart[(c + 1) * R->S] - b;
+        for (int64_t s = 0; s <= R->S; ++s) off[s] = R->cstart[c * R->S + s] - b;
         int64_t k = collide_cell(R, (uint32_t)c, N, R->p[3] + b, R->p[4] + b, R->p[5] + b,
-                                 &R->gmax[c], &R->rem_c[c], NULL, 0, NULL);
+                                 &R->gmax[c], &R->rem_c[c], R->sub > 1 ? off : NULL, NULL, 0, NULL);
         R->ncoll[c] += k;
         total += k;
     }
+    free(off);
     R->last_ncoll = total;
 }
 
 /* Stand-alone single-cell interaction for brute-force tests: the velocities
  * are updated in place, (gmax, rem) are in/out, trace as in collide_cell. */
 int64_t or_collide_cell(const or_spec *sp, uint32_t step, uint32_t cell, int64_t N, double *u,
-                        double *v, double *w, double *gmax, double *rem, int32_t *trace,
-                        int64_t trace_cap, int64_t *nsel_out)
+                        double *v, double *w, double *gmax, double *rem, const int64_t *sub_off,
+                        int32_t *trace, int64_t trace_cap, int64_t *nsel_out)
 {
     int32_t st;
     or_spec s2 = *sp;
@@ -675,7 +730,8 @@ int64_t or_collide_cell(const or_spec *sp, uint32_t step, uint32_t cell, int64_t
     or_run *R = or_run_new(&s2, &st);
     if (!R) return st;
     R->step = step;
-    int64_t k = collide_cell(R, cell, N, u, v, w, gmax, rem, trace, trace_cap, nsel_out);
+    int64_t k = collide_cell(R, cell, N, u, v, w, gmax, rem, R->sub > 1 ? sub_off : NULL, trace,
+                             trace_cap, nsel_out);
     or_run_free(R);
     return k;
 }
@@ -689,7 +745,7 @@ void or_sample(const or_run *R, double *out)
 {
     for (int64_t c = 0; c < R->nc; ++c) {
         double s[7] = {0, 0, 0, 0, 0, 0, 0};
-        int64_t b = R->cstart[c], N = R->ccount[c];
+        int64_t b = R->cstart[c * R->S], N = R->cstart[(c + 1) * R->S] - b;
         for (int64_t k = b; k < b + N; ++k) {
             double u = R->p[3][k], v = R->p[4][k], w = R->p[5][k];
             s[0] += 1.0;
@@ -716,12 +772,14 @@ void or_step(or_run *R)
 
 void or_step_begin(or_run *R) { R->step++; }
 
-/* info: n, step, err, nc, n_sorted, last_ncoll, last_ngen, last_nremoved, last_nmoved, nface */
-void or_get_info(const or_run *R, int64_t info[10])
+/* info: n, step, err, nc, n_sorted, last_ncoll, last_ngen, last_nremoved, last_nmoved, nface,
+ * nbin */
+void or_get_info(const or_run *R, int64_t info[11])
 {
     info[0] = R->n; info[1] = R->step; info[2] = R->err; info[3] = R->nc;
     info[4] = R->n_sorted; info[5] = R->last_ncoll; info[6] = R->last_ngen;
     info[7] = R->last_nremoved; info[8] = R->last_nmoved; info[9] = R->nface;
+    info[10] = R->nbin;
 }
 
 /* derived constants: coef, vhs_exp, gmax0, mbar, beta, s_inf, p_branch */
@@ -747,12 +805,12 @@ int32_t or_set_state(or_run *R, int64_t n, const double *in /* [6][n] */)
 void or_set_step(or_run *R, uint32_t step) { R->step = step; }
 
 void or_get_cells(const or_run *R, int32_t *cell /* n_sorted */, int32_t *lcr /* n_sorted */,
-                  int64_t *cstart /* nc+2 */, int64_t *ccount /* nc+1 */)
+                  int64_t *cstart /* nbin+2 */, int64_t *ccount /* nbin+1 */)
 {
     if (cell) memcpy(cell, R->cell, (size_t)R->n_sorted * sizeof(int32_t));
     if (lcr) memcpy(lcr, R->lcr, (size_t)R->n_sorted * sizeof(int32_t));
-    if (cstart) memcpy(cstart, R->cstart, (size_t)(R->nc + 2) * sizeof(int64_t));
-    if (ccount) memcpy(ccount, R->ccount, (size_t)(R->nc + 1) * sizeof(int64_t));
+    if (cstart) memcpy(cstart, R->cstart, (size_t)(R->nbin + 2) * sizeof(int64_t));
+    if (ccount) memcpy(ccount, R->ccount, (size_t)(R->nbin + 1) * sizeof(int64_t));
 }
 
 void or_get_cell_state(const or_run *R, double *rem, double *gmax, int64_t *ncoll)

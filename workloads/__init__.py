@@ -80,6 +80,7 @@ class RunSpec:
     ensemble: int = 0
     solid: Optional[np.ndarray] = None   # uint8 [nz][ny][nx], 1 = solid voxel
     solid_T: float = 1.0
+    subcells: int = 1             # collision partners from k x k (x k) sub-cells (1 = none)
 
     @property
     def n_cells(self) -> int:
