@@ -181,14 +181,16 @@ def run_gpu(args):
                             seed=3, state_fp64=False)
     dim = wl.runs[0].dim
     tuned = None
-    kw = {"n_streams": args.streams, "tile_chunks": args.tile_chunks, "collide_mode": args.collide_mode}
+    kw = {"n_streams": args.streams, "tile_chunks": args.tile_chunks, "collide_mode": args.collide_mode,
+          "sched": args.sched, "sched_blocks": args.sched_blocks}
     unsteady = args.workload in ("channel", "uneven")
     if not args.no_tune and not unsteady:
         # the library's autotuner times its candidate settings on this batch
         # (a scratch arena, before the timed region); tuning never changes results
         tuned = P.Ensemble.autotune(wl.runs, wl.sample_steps, state_fp64=False, n_groups=wl.n_groups,
-                                    use_graph=True, n_steps=3)
-        kw = {k: tuned[k] for k in ("tile_chunks", "collide_mode", "n_streams")}
+                                    use_graph=True, n_steps=3, tune_cache=args.tune_cache)
+        kw = {k: tuned[k] for k in ("tile_chunks", "collide_mode", "n_streams", "sched", "sched_blocks")
+              if k in tuned}
     E = P.Ensemble.from_workload(wl, use_graph=True, **kw)
     n_runs = wl.n_runs
     nc = wl.runs[0].n_cells
@@ -304,6 +306,104 @@ def run_plain_fp64(args, P, W):
             "note": "same box problem, one run per context, FP64 state, no graph"}
 
 
+def interaction_ms(E, steps: int) -> float:
+    """Mean Interaction time per step (all interaction kernels) over `steps`
+    profiled steps of context E."""
+    E.profiling(True)
+    E.step(steps)
+    kt = E.kernel_times()
+    E.profiling(False)
+    return sum(ms for k, (ms, n) in kt.items() if k.startswith("collide")) / steps
+
+
+def amdahl_beta(units, times):
+    """Least-squares beta of T(p) = T(1) (beta + (1 - beta) / p): 1/S is
+    linear in 1/p with intercept beta."""
+    import numpy as np
+    p = np.asarray(units, float)
+    S = times[0] / np.asarray(times, float)
+    A = np.stack([np.ones_like(p), 1.0 / p], axis=1)
+    coef, *_ = np.linalg.lstsq(A, 1.0 / S, rcond=None)
+    return float(min(max(coef[0], 0.0), 1.0))
+
+
+def balance_experiment(args):
+    """Dynamic against static allocation of Interaction's workgroups to the
+    runs of the uneven batch (the two-level split of Sec. 2 against the
+    dynamic processor reallocation of Sec. 3), every run in the lane-per-cell
+    mode (one kernel; its processors are wavefronts).
+
+    - beta of sampled runs: each run alone, its Interaction timed on persistent
+      grids of 1 .. 2048 wavefronts drawing from its queue; Amdahl fit.
+    - the batch after the fill: static (sched 2: p2 wavefronts tied to each
+      run) and dynamic (sched 1: p2 x runs wavefronts drawing from one queue)
+      for p2 = 1, 2, 4, 8; achieved level-2 speedups S = T_static(1) / T.
+    - beside them eq. (11), S_p2 = 1 / (beta + (1 - beta) / (p2 (1 + PRI))),
+      at PRI = 0 and at PRI* = beta / (1 - beta) (p2 - 1) from eq. (13)."""
+    import numpy as np
+    import paper_cs_9902024_amd as P
+    import workloads as W
+    wl = W.uneven()
+    R = wl.n_runs
+    wpb = 2  # wavefronts per workgroup of the lane-per-cell kernel
+    kw = dict(collide_mode=1, use_graph=False)
+    base = P.Ensemble.from_workload(wl, sched=1, **kw)
+    base.step(FILL_STEPS)
+    counts = base.counts()[:, 0]
+    ck = base.checkpoint()
+    base.close()
+    # sampled runs: smallest, two middle, largest by particles at fill
+    order = np.argsort(counts)
+    sample = [int(order[0]), int(order[R // 3]), int(order[2 * R // 3]), int(order[-1])]
+    runs_beta = []
+    for r in sample:
+        one = W.Workload("one", [wl.runs[r]], wl.n_steps, wl.sample_steps, 1)
+        E = P.Ensemble.from_workload(one, sched=1, **kw)
+        E.step(FILL_STEPS)
+        ck1 = E.checkpoint()
+        E.close()
+        units, times = [], []
+        for G in (1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024):
+            E = P.Ensemble.from_workload(one, sched=1, sched_blocks=G, **kw)
+            E.restore(ck1)
+            E.step(1)
+            units.append(G * wpb)
+            times.append(interaction_ms(E, 3))
+            E.close()
+        runs_beta.append({"run": r, "particles": int(counts[r]), "cells": wl.runs[r].n_cells,
+                          "beta": amdahl_beta(units, times),
+                          "wavefronts": units, "ms": [round(t, 4) for t in times]})
+    beta = float(np.mean([b["beta"] for b in runs_beta]))
+    rows = []
+    t_static_1 = None
+    for p2 in (1, 2, 4, 8):
+        row = {"p2": p2}
+        for name, sched in (("static", 2), ("dynamic", 1)):
+            E = P.Ensemble.from_workload(wl, sched=sched, sched_blocks=max(1, p2 * R // wpb), **kw)
+            E.restore(ck)
+            E.step(1)
+            row[name + "_ms"] = round(interaction_ms(E, 3), 4)
+            E.close()
+        if t_static_1 is None:
+            t_static_1 = row["static_ms"]
+        pri = beta / (1 - beta) * (p2 - 1) if beta < 1 else 0.0
+        row.update({"S_static": round(t_static_1 / row["static_ms"], 3),
+                    "S_dynamic": round(t_static_1 / row["dynamic_ms"], 3),
+                    "eq11_PRI0": round(1 / (beta + (1 - beta) / p2), 3),
+                    "PRI_star_eq13": round(pri, 3),
+                    "eq11_PRI_star": round(1 / (beta + (1 - beta) / (p2 * (1 + pri))), 3)})
+        rows.append(row)
+    E = P.Ensemble.from_workload(wl, sched=0, **kw)
+    E.restore(ck)
+    E.step(1)
+    grid_ms = interaction_ms(E, 3)
+    E.close()
+    return {"workload": "uneven, 256 runs after %d steps from vacuum, every run a lane per cell" % FILL_STEPS,
+            "runs": R, "processors": "wavefronts of the persistent lane-per-cell Interaction grid",
+            "beta_sampled_runs": runs_beta, "beta_mean": beta, "p2_rows": rows,
+            "hardware_grid_ms": round(grid_ms, 4)}
+
+
 ORACLE_SEED = 1003   # the oracle's runs: same problem, seeds disjoint from the GPU batch's
 
 
@@ -401,6 +501,15 @@ def main():
     ap.add_argument("--collide-mode", type=int, default=0,
                     help="interaction work item: 0 auto, 1 a lane per cell, 2 a block per cell, "
                          "3 a wavefront per cell")
+    ap.add_argument("--sched", type=int, default=0,
+                    help="Interaction work distribution (with --no-tune): 0 a workgroup per item, 1 a "
+                         "persistent grid drawing from a queue shared by all runs, 2 workgroups tied to runs")
+    ap.add_argument("--sched-blocks", type=int, default=0,
+                    help="workgroups of each persistent grid (0 = as many as fit)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="file of earlier autotune results to reuse and extend (default: none, always time)")
+    ap.add_argument("--balance", action="store_true",
+                    help="with --workload uneven: also run the static vs dynamic allocation experiment")
     ap.add_argument("--plain-runs", type=int, default=2)
     ap.add_argument("--plain-steps", type=int, default=10)
     ap.add_argument("--oracle-runs", type=int, default=128,
@@ -414,6 +523,7 @@ def main():
         sys.exit(2)
 
     g = run_gpu(args)
+    balance = balance_experiment(args) if (args.balance and args.workload == "uneven") else None
     cpu = match = None
     if not args.no_cpu_baseline and args.workload == "ensemble_box":
         cpu, ora = cpu_baseline(args)
@@ -452,6 +562,8 @@ def main():
         "kernels": g["kernels"],
         "stream_copy": g["calib"],
     }
+    if balance is not None:
+        line["balance"] = balance
     print(json.dumps(line))
 
 

@@ -94,7 +94,14 @@ typedef struct {
   double init_T;                /* initial temperature */
   uint32_t run_id, seed;        /* Philox key of the run: runs are independent and replayable */
   int32_t ensemble;             /* runs with the same id are averaged together; they share a grid */
-  int32_t reserved;
+  int32_t subcells;             /* collision partners from sub-cells, k per axis (0 or 1 = none, at most 4):
+                                   each particle's Indexing bin is its sub-cell (cell * k^dim + the
+                                   sub-cell within it, from the floor on the k-times finer grid), and
+                                   the second partner of a selection is drawn from the first one's
+                                   sub-cell when it holds two or more particles, else from the cell (a
+                                   refinement of the collision-partner choice of the DSMC method of
+                                   Sec. 1.1, after Bird); the NTC count stays the cell's.  Not with
+                                   solid_mask (DSMC_EUNSUPPORTED). */
   const uint8_t *solid_mask;    /* host [nz][ny][nx] (cell (iz*ny + iy)*nx + ix), nonzero = solid cell, or
                                    NULL.  Solid cells are an obstacle with diffuse faces at solid_T: a
                                    path is followed cell by cell in the time order of its plane crossings
@@ -134,6 +141,17 @@ typedef struct {
                                    (end of Sec. 3).  Windows of different slots may share no step
                                    (DSMC_EINVAL). */
   int32_t window_stride;        /* steps between the snapshots of a window (0 = 1) */
+  int32_t sched;                /* tuning: how Interaction's workgroups get their items (cells or groups
+                                   of cells, of every run): 0 = one per workgroup (or wavefront) of a
+                                   grid covering all items, handed to CUs by the hardware; 1 = a
+                                   persistent grid drawing items from a device queue shared by all runs
+                                   (dynamic reallocation of workgroups between runs, Sec. 3); 2 = a
+                                   persistent grid whose workgroups are tied to runs (the static two-level
+                                   split of Sec. 2: of U workgroups, g serves run g mod runs when U is at
+                                   least the number of runs, else runs g, g + U, ... in turn).
+                                   Results do not depend on it. */
+  int32_t sched_blocks;         /* tuning: workgroups of each persistent grid (0 = as many as fit on
+                                   the GPU at once) */
 } dsmc_options;
 
 /* Arena size for these runs/options.  Pure host computation.
@@ -207,8 +225,9 @@ dsmc_status dsmc_get_state(dsmc_ctx *ctx, int32_t run, double *out, int64_t cap,
 dsmc_status dsmc_set_state(dsmc_ctx *ctx, int32_t run, const double *in, int64_t n);
 
 /* Indexing of the last step of one run: lcr[n] (run-local slots in stable
- * cell order, DEAD last) and cell[n] (cell of each slot, nc = DEAD) for the n
- * particles present before removal; start[nc + 2] bin starts (may be NULL). */
+ * bin order, DEAD last) and cell[n] (bin of each slot: its cell, or with
+ * sub-cells its sub-cell bin; nbin = nc * k^dim = DEAD) for the n particles
+ * present before removal; start[nbin + 2] bin starts (may be NULL). */
 dsmc_status dsmc_get_lcr(dsmc_ctx *ctx, int32_t run, int32_t *lcr, int32_t *cell, int64_t *start,
                          int64_t cap, int64_t *n);
 
@@ -286,19 +305,27 @@ dsmc_status dsmc_autotune_bytes(const dsmc_run_spec *runs, int32_t n_runs, const
                                 size_t *bytes);
 
 /* Chooses the tuning fields of dsmc_options (tile_chunks, collide_mode,
- * n_streams) for these runs by measurement.  None of them changes any result
- * (every setting computes the same sequential order bit for bit); they only
- * change speed.  Candidates: tiles of 4096, 8192 and 16384 slots; all three
- * interaction modes when a run's expected particles per cell lie in 28..576;
- * one or two stream lanes when n_runs >= 8.  Each candidate is initialised in
- * the caller's arena (at least dsmc_autotune_bytes, 256-byte aligned), stepped
- * once to warm up (graph capture included when opt->use_graph), then n_steps
- * (>= 1) steps are timed with HIP events on hip_stream.  *best receives *opt
- * with the fastest tuning fields; *best_ms_per_step (may be NULL) its time per
- * step.  The arena holds no usable context afterwards.  Synchronises. */
+ * n_streams, sched, sched_blocks) for these runs by measurement.  None of
+ * them changes any result (every setting computes the same sequential order
+ * bit for bit); they only change speed.  Candidates: tiles of 4096, 8192 and
+ * 16384 slots; all three interaction modes when a run's expected particles
+ * per cell lie in 28..576; one or two stream lanes when n_runs >= 8; the
+ * default tile with Interaction on persistent grids drawing from one queue
+ * for all runs (sched 1) at two occupancies (as many workgroups as fit, and
+ * 1024).  Each candidate is initialised in the caller's arena (at least
+ * dsmc_autotune_bytes, 256-byte aligned), stepped once to warm up (graph
+ * capture included when opt->use_graph), then n_steps (>= 1) steps are timed
+ * with HIP events on hip_stream.  *best receives *opt with the fastest tuning
+ * fields; *best_ms_per_step (may be NULL) its time per step.  tune_cache (may
+ * be NULL) names a text file of earlier results: when it holds a result for
+ * the same run specs, precision, groups, schedule, window, graph replay and
+ * device, that result is returned without timing (and without touching the
+ * arena); otherwise the new result is appended to it.  Concurrent writers of
+ * one cache file are not supported.  The arena holds no usable context
+ * afterwards.  Synchronises. */
 dsmc_status dsmc_autotune(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_options *opt, void *arena,
-                          size_t arena_bytes, void *hip_stream, int32_t n_steps, dsmc_options *best,
-                          double *best_ms_per_step);
+                          size_t arena_bytes, void *hip_stream, int32_t n_steps, const char *tune_cache,
+                          dsmc_options *best, double *best_ms_per_step);
 
 /* ---- Indexing alone ------------------------------------------------------ */
 

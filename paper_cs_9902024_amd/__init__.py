@@ -54,7 +54,7 @@ class dsmc_run_spec(C.Structure):
                 ("inflow_n", C.c_double), ("inflow_U", C.c_double), ("inflow_T", C.c_double),
                 ("capacity", C.c_int64), ("n_init", C.c_int64), ("init_U", C.c_double * 3),
                 ("init_T", C.c_double), ("run_id", C.c_uint32), ("seed", C.c_uint32),
-                ("ensemble", C.c_int32), ("reserved", C.c_int32), ("solid_mask", C.c_void_p),
+                ("ensemble", C.c_int32), ("subcells", C.c_int32), ("solid_mask", C.c_void_p),
                 ("solid_T", C.c_double)]
 
 
@@ -62,7 +62,8 @@ class dsmc_options(C.Structure):
     _fields_ = [("state_fp64", C.c_int32), ("n_groups", C.c_int32), ("n_samples", C.c_int32),
                 ("sample_steps", C.POINTER(C.c_int32)), ("use_graph", C.c_int32),
                 ("tile_chunks", C.c_int32), ("collide_mode", C.c_int32), ("n_streams", C.c_int32),
-                ("window_steps", C.c_int32), ("window_stride", C.c_int32)]
+                ("window_steps", C.c_int32), ("window_stride", C.c_int32), ("sched", C.c_int32),
+                ("sched_blocks", C.c_int32)]
 
 
 _lib = None
@@ -111,7 +112,7 @@ def lib():
         L.dsmc_autotune_bytes.argtypes = [C.POINTER(dsmc_run_spec), i32, C.POINTER(dsmc_options),
                                           C.POINTER(sz)]
         L.dsmc_autotune.argtypes = [C.POINTER(dsmc_run_spec), i32, C.POINTER(dsmc_options), vp, sz, vp, i32,
-                                    C.POINTER(dsmc_options), dp]
+                                    C.c_char_p, C.POINTER(dsmc_options), dp]
         L.dsmc_kernel_name.restype = C.c_char_p
         for f in EXPORTS:
             if f not in ("dsmc_destroy", "dsmc_last_error", "dsmc_kernel_name"):
@@ -154,12 +155,14 @@ def make_run_spec(rs) -> dsmc_run_spec:
     s.init_T = rs.init_T
     s.run_id, s.seed = rs.run_id & 0xFFFFFFFF, rs.seed & 0xFFFFFFFF
     s.ensemble = rs.ensemble
+    s.subcells = getattr(rs, "subcells", 1)
     return s
 
 
 def make_options(state_fp64: bool, n_groups: int, sample_steps: Sequence[int],
                  use_graph: bool = False, tile_chunks: int = 0, collide_mode: int = 0,
-                 n_streams: int = 0, window_steps: int = 0, window_stride: int = 0):
+                 n_streams: int = 0, window_steps: int = 0, window_stride: int = 0, sched: int = 0,
+                 sched_blocks: int = 0):
     steps = (C.c_int32 * max(1, len(sample_steps)))(*sample_steps)
     o = dsmc_options()
     o.state_fp64 = int(bool(state_fp64))
@@ -172,6 +175,8 @@ def make_options(state_fp64: bool, n_groups: int, sample_steps: Sequence[int],
     o.n_streams = int(n_streams)
     o.window_steps = int(window_steps)
     o.window_stride = int(window_stride)
+    o.sched = int(sched)
+    o.sched_blocks = int(sched_blocks)
     o._keep = steps
     return o
 
@@ -193,12 +198,14 @@ def dsmc_autotune_bytes(specs, opt) -> int:
     return n.value
 
 
-def dsmc_autotune(specs, opt, arena_ptr: int, arena_bytes: int, stream: int, n_steps: int):
+def dsmc_autotune(specs, opt, arena_ptr: int, arena_bytes: int, stream: int, n_steps: int,
+                  tune_cache: Optional[str] = None):
     """Returns (best dsmc_options, ms per step)."""
     best = dsmc_options()
     ms = C.c_double(0)
+    path = tune_cache.encode() if tune_cache else None
     _check(lib().dsmc_autotune(specs, len(specs), C.byref(opt), C.c_void_p(arena_ptr), arena_bytes,
-                               C.c_void_p(stream), n_steps, C.byref(best), C.byref(ms)), "dsmc_autotune")
+                               C.c_void_p(stream), n_steps, path, C.byref(best), C.byref(ms)), "dsmc_autotune")
     best._keep = getattr(opt, "_keep", None)
     return best, ms.value
 
@@ -390,14 +397,16 @@ class Ensemble:
     def __init__(self, runs, sample_steps: Sequence[int] = (), state_fp64: bool = False,
                  n_groups: int = 1, use_graph: bool = False, tile_chunks: int = 0,
                  collide_mode: int = 0, n_streams: int = 0, window_steps: int = 0,
-                 window_stride: int = 0, device=None, stream=None):
+                 window_stride: int = 0, sched: int = 0, sched_blocks: int = 0, device=None,
+                 stream=None):
         import torch
         if not torch.cuda.is_available():
             raise DsmcError(-4, "Ensemble", "no GPU visible to torch")
         self.runs = list(runs)
         self.specs = _specs(self.runs)
         self.opt = make_options(state_fp64, n_groups, list(sample_steps), use_graph, tile_chunks,
-                                collide_mode, n_streams, window_steps, window_stride)
+                                collide_mode, n_streams, window_steps, window_stride, sched,
+                                sched_blocks)
         self.nbytes = dsmc_required_bytes(self.specs, self.opt)
         dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.arena = torch.empty(self.nbytes, dtype=torch.uint8, device=dev)
@@ -411,25 +420,37 @@ class Ensemble:
 
     @staticmethod
     def autotune(runs, sample_steps: Sequence[int] = (), state_fp64: bool = False, n_groups: int = 1,
-                 use_graph: bool = False, n_steps: int = 5, device=None, stream=None) -> dict:
+                 use_graph: bool = False, n_steps: int = 5, device=None, stream=None,
+                 tune_cache: Optional[str] = None, window_steps: int = 0, window_stride: int = 0) -> dict:
         """Measures the library's candidate tuning settings on these runs
-        (dsmc_autotune) in a scratch arena; returns the fastest as keyword
-        arguments for Ensemble (tile_chunks, collide_mode, n_streams) plus its
-        ms_per_step.  Tuning never changes results."""
+        (dsmc_autotune) in a scratch arena, or takes them from the tune cache
+        file when it holds this problem; returns the fastest as keyword
+        arguments for Ensemble (tile_chunks, collide_mode, n_streams, sched,
+        sched_blocks) plus its ms_per_step and whether it came from the cache.
+        Tuning never changes results."""
         import torch
         if not torch.cuda.is_available():
             raise DsmcError(-4, "autotune", "no GPU visible to torch")
         specs = _specs(list(runs))
-        opt = make_options(state_fp64, n_groups, list(sample_steps), use_graph)
-        nbytes = dsmc_autotune_bytes(specs, opt)
+        opt = make_options(state_fp64, n_groups, list(sample_steps), use_graph,
+                           window_steps=window_steps, window_stride=window_stride)
         dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
-        arena = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         st = stream if stream is not None else torch.cuda.current_stream(dev)
-        best, ms = dsmc_autotune(specs, opt, arena.data_ptr(), nbytes, st.cuda_stream, n_steps)
-        del arena
-        torch.cuda.empty_cache()
+        cached = True
+        try:      # a cached result needs no arena
+            best, ms = dsmc_autotune(specs, opt, 0, 0, st.cuda_stream, n_steps, tune_cache)
+        except DsmcError as e:
+            if e.status != -2:
+                raise
+            cached = False
+            nbytes = dsmc_autotune_bytes(specs, opt)
+            arena = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+            best, ms = dsmc_autotune(specs, opt, arena.data_ptr(), nbytes, st.cuda_stream, n_steps, tune_cache)
+            del arena
+            torch.cuda.empty_cache()
         return {"tile_chunks": best.tile_chunks, "collide_mode": best.collide_mode,
-                "n_streams": best.n_streams, "ms_per_step": ms}
+                "n_streams": best.n_streams, "sched": best.sched, "sched_blocks": best.sched_blocks,
+                "ms_per_step": ms, "from_cache": cached}
 
     @classmethod
     def from_workload(cls, wl, **kw):
@@ -483,8 +504,11 @@ class Ensemble:
         dsmc_set_state(self.ctx, run, st)
 
     def lcr(self, run: int):
+        """(lcr, bin of each slot, bin starts) of the run's last Indexing; the
+        bins are the cells, or the sub-cells with sub-cells."""
         rs = self.runs[run]
-        return dsmc_get_lcr(self.ctx, run, rs.capacity + 64 * 1024, rs.n_cells)
+        k = max(1, getattr(rs, "subcells", 1))
+        return dsmc_get_lcr(self.ctx, run, rs.capacity + 64 * 1024, rs.n_cells * k ** rs.dim)
 
     def cell_state(self, run: int) -> dict:
         return dsmc_get_cell_state(self.ctx, run, self.runs[run].n_cells)

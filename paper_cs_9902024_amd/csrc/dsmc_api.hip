@@ -40,7 +40,8 @@ struct Plan {
   std::vector<Ensemble> ens;
   std::vector<int64_t> spec_capacity;
   uint64_t fingerprint = 0;  // of everything a checkpoint must agree on (not the tuning fields)
-  size_t off_nsnap, off_diag;
+  std::vector<int64_t> sched_first;  // per interaction mode: first item of each run with items, then the end
+  size_t off_nsnap, off_diag, off_sched_ctr, off_sched_first;
   size_t off_runs, off_tile_run, off_face_run, off_cgroup_run, off_inflow, off_gen_blk, off_eg_start, off_eg_runs,
       off_eg_acc,
       off_eg_nc, off_samples, off_items, off_cell_items, off_wave_items, off_solid;
@@ -70,6 +71,8 @@ dsmc_status validate(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_optio
     if (opt->collide_mode < 0 || opt->collide_mode > 3) return fail(msg, DSMC_EINVAL, "collide_mode out of range");
     if (opt->n_streams < 0 || opt->n_streams > kMaxLanes) return fail(msg, DSMC_EINVAL, "n_streams out of range");
     if (opt->window_steps < 0 || opt->window_stride < 0) return fail(msg, DSMC_EINVAL, "negative sampling window");
+    if (opt->sched < 0 || opt->sched > 2) return fail(msg, DSMC_EINVAL, "sched out of range");
+    if (opt->sched_blocks < 0) return fail(msg, DSMC_EINVAL, "negative sched_blocks");
     if (opt->n_samples > 0 && opt->window_steps > 1) {
       // the windows' steps: each may belong to one slot only
       const int64_t W = opt->window_steps, q = opt->window_stride > 0 ? opt->window_stride : 1;
@@ -94,7 +97,12 @@ dsmc_status validate(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_optio
     if (s.nx < 1 || s.ny < 1 || s.nz < 1 || (dim == 2 && s.nz != 1))
       return fail(msg, DSMC_EINVAL, "run %d: bad grid", r);
     const int64_t nc = (int64_t)s.nx * s.ny * s.nz;
-    if (nc + 2 >= ((int64_t)1 << 30)) return fail(msg, DSMC_EINVAL, "run %d: too many cells", r);  // kQueueBit
+    if (s.subcells < 0 || s.subcells > 4) return fail(msg, DSMC_EINVAL, "run %d: subcells must be in 0..4", r);
+    const int64_t sub = s.subcells > 1 ? s.subcells : 1;
+    const int64_t S = sub * sub * (s.dim == 3 ? sub : 1);
+    if (nc * S + 2 >= ((int64_t)1 << 30))  // kQueueBit
+      return fail(msg, DSMC_EINVAL, "run %d: too many cells (times sub-cells)", r);
+    if (sub > 1 && s.solid_mask) return fail(msg, DSMC_EUNSUPPORTED, "run %d: sub-cells with solid cells", r);
     if (!(s.lx > 0) || !(s.ly > 0) || !(s.lz > 0)) return fail(msg, DSMC_EINVAL, "run %d: bad box size", r);
     if (!(s.dt > 0) || !std::isfinite(s.dt)) return fail(msg, DSMC_EINVAL, "run %d: dt must be > 0", r);
     if (!(s.fnum_sigma >= 0)) return fail(msg, DSMC_EINVAL, "run %d: fnum_sigma must be >= 0", r);
@@ -170,7 +178,7 @@ uint64_t plan_fingerprint(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_
     f.add(s.inflow_n); f.add(s.inflow_U); f.add(s.inflow_T);
     f.add(s.capacity); f.add(s.n_init);
     for (int a = 0; a < 3; ++a) f.add(s.init_U[a]);
-    f.add(s.init_T); f.add(s.run_id); f.add(s.seed); f.add(s.ensemble);
+    f.add(s.init_T); f.add(s.run_id); f.add(s.seed); f.add(s.ensemble); f.add(s.subcells > 1 ? s.subcells : 1);
     const int has = s.solid_mask ? 1 : 0;
     f.add(has);
     if (has) {
@@ -211,15 +219,22 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
   g.tile = (int64_t)g.tile_chunks * kWave;
   g.n_runs = n_runs;
   g.n_samples = opt.n_samples;
+  g.sched = opt.sched;
   g.window_steps = std::max(1, opt.window_steps);
   g.window_stride = std::max(1, opt.window_stride);
   P.fingerprint = plan_fingerprint(runs, n_runs, opt);
   const int G = opt.n_groups > 0 ? opt.n_groups : 1;
 
-  int max_nc = 0;
-  for (int r = 0; r < n_runs; ++r) max_nc = std::max<int>(max_nc, runs[r].nx * runs[r].ny * runs[r].nz);
+  int max_nc = 0, max_nbin = 0;
+  for (int r = 0; r < n_runs; ++r) {
+    const int sub = runs[r].subcells > 1 ? runs[r].subcells : 1;
+    const int nc = runs[r].nx * runs[r].ny * runs[r].nz;
+    max_nc = std::max<int>(max_nc, nc);
+    max_nbin = std::max<int>(max_nbin, nc * sub * sub * (runs[r].dim == 3 ? sub : 1));
+  }
   g.max_nc = max_nc;
-  const int64_t maxbins = (int64_t)max_nc + 1;
+  g.max_nbin = max_nbin;
+  const int64_t maxbins = (int64_t)max_nbin + 1;
   if (maxbins <= kDigits) {
     g.npass = 1;
   } else {
@@ -227,7 +242,7 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
     while (((int64_t)1 << bits) < maxbins) ++bits;
     g.npass = (bits + kDigitBits - 1) / kDigitBits;
   }
-  g.dstride = g.npass == 1 ? max_nc + 1 : kDigits;
+  g.dstride = g.npass == 1 ? max_nbin + 1 : kDigits;
   // two passes: buckets of 2048 bins first (the bins of nearly sorted input
   // then reach a few buckets per tile), then each bucket by its low digit
   g.bucketed = g.npass == 2;
@@ -236,6 +251,7 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
   P.spec_capacity.resize(n_runs);
   // end of each run's share of the per-run lists (for the lane split)
   std::vector<LaneRange> ends(n_runs);
+  std::vector<int64_t> mode_first[3];  // per interaction mode: first item of each run with items
   int64_t so = 0, co = 0, bo = 0, mo = 0, cbo = 0, fo = 0;
   int32_t to = 0, io = 0;
   for (int r = 0; r < n_runs; ++r) {
@@ -247,6 +263,10 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
     R.cap = cap;
     R.cap_spec = s.capacity;
     R.nc = s.nx * s.ny * s.nz;
+    R.sub = s.subcells > 1 ? s.subcells : 1;
+    R.S = R.sub * R.sub * (s.dim == 3 ? R.sub : 1);
+    R.nbin = R.nc * R.S;
+    if (R.sub > 1) g.any_sub = 1;
     R.nx = s.nx;
     R.ny = s.ny;
     R.nz = s.nz;
@@ -254,12 +274,12 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
     R.bo = bo;
     R.to = to;
     R.nt = (int32_t)(cap / g.tile);
-    R.ndig = g.npass == 1 ? R.nc + 1 : kDigits;
+    R.ndig = g.npass == 1 ? R.nbin + 1 : kDigits;
     R.mo = mo;
     if (g.bucketed) {
       // the run's histogram rows: its tiles (first pass), then its bucket
       // items (second pass) in the same private region
-      R.nb = (R.nc >> kDigitBits) + 1;
+      R.nb = (R.nbin >> kDigitBits) + 1;
       R.icap = R.nt + R.nb;
       R.io = io;
       R.mo = (int64_t)io * kDigits;
@@ -303,6 +323,8 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
         for (size_t k = 0; k < keyed.size(); ++k) starts[k] = keyed[k].second;
       }
       std::vector<int2> &list = R.coll_mode == 2 ? P.cell_items : (R.coll_mode == 1 ? P.wave_items : P.items);
+      const int m = R.coll_mode == 2 ? 2 : (R.coll_mode == 1 ? 1 : 0);
+      if (!starts.empty()) mode_first[m].push_back((int64_t)list.size());
       for (int32_t c : starts) list.push_back(make_int2(r, c));
     }
     for (int f = 0; f < 6; ++f) {
@@ -318,6 +340,9 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
     R.inv_d[0] = (double)s.nx / s.lx;
     R.inv_d[1] = (double)s.ny / s.ly;
     R.inv_d[2] = (double)s.nz / s.lz;
+    R.inv_bin[0] = (double)(s.nx * R.sub) / s.lx;
+    R.inv_bin[1] = (double)(s.ny * R.sub) / s.ly;
+    R.inv_bin[2] = (double)(s.nz * R.sub) / s.lz;
     R.dt = s.dt;
     const double vc = (s.lx / s.nx) * (s.ly / s.ny) * (s.lz / s.nz);
     R.coef = s.fnum_sigma * s.dt / vc;
@@ -362,6 +387,7 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
     for (int a = 0; a < 3; ++a) {
       R.L_f[a] = (float)R.L[a];
       R.inv_f[a] = (float)R.inv_d[a];
+      R.inv_bin_f[a] = (float)R.inv_bin[a];
     }
     R.has_solid = any_solid(s) ? 1 : 0;
     if (R.has_solid) g.any_solid = 1;
@@ -405,10 +431,11 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
     ends[r].ci1 = (int64_t)P.cell_items.size();
     ends[r].wi1 = (int64_t)P.wave_items.size();
     ends[r].b1 = io + R.icap;
+    for (int m = 0; m < 3; ++m) ends[r].sr1[m] = (int32_t)mode_first[m].size();
     so += cap;
     to += R.nt;
     co += round_up(R.nc, 64);
-    bo += R.nc + 2;
+    bo += R.nbin + 2;
     mo += (int64_t)R.nt * R.ndig;
     io += R.icap;
     if (g.bucketed) mo = (int64_t)io * kDigits;
@@ -455,6 +482,7 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
       L.ci0 = prev ? prev->ci1 : 0;
       L.wi0 = prev ? prev->wi1 : 0;
       L.b0 = prev ? prev->b1 : 0;
+      for (int m = 0; m < 3; ++m) L.sr0[m] = prev ? prev->sr1[m] : 0;
       const LaneRange &e = ends[L.r1 - 1];
       L.t1 = e.t1;
       L.f1 = e.f1;
@@ -464,7 +492,24 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
       L.ci1 = e.ci1;
       L.wi1 = e.wi1;
       L.b1 = e.b1;
+      for (int m = 0; m < 3; ++m) L.sr1[m] = e.sr1[m];
     }
+  }
+
+  // persistent Interaction grids: each mode's runs with items and their first
+  // items (the end of the mode's list after the last), and the counters
+  {
+    const int64_t mode_items[3] = {g.n_items, g.n_wave_items, g.n_cell_items};
+    int64_t off = 0, coff = (int64_t)3 * kMaxLanes * 8;
+    for (int m = 0; m < 3; ++m) {
+      g.sched_first_off[m] = off;
+      g.sched_ctr_off[m] = coff;
+      for (int64_t f : mode_first[m]) P.sched_first.push_back(f);
+      P.sched_first.push_back(mode_items[m]);
+      off += (int64_t)mode_first[m].size() + 1;
+      coff += (int64_t)mode_first[m].size();
+    }
+    g.n_sched_ctr = coff;
   }
 
   // ensembles in order of first appearance; group of a run = its index in the ensemble mod G
@@ -502,9 +547,13 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
   // arena layout
   const size_t es = g.fp64 ? 8 : 4;
   size_t o = 0;
+  // arrays of 2 MiB or more start on a 2 MiB boundary of the arena (the
+  // large-page size), so their placement does not depend on the sizes of the
+  // small tables before them
   auto take = [&](size_t bytes) {
-    size_t at = o;
-    o = align256(o + std::max<size_t>(bytes, 1));
+    constexpr size_t kBig = (size_t)2 << 20;
+    size_t at = bytes >= kBig ? (o + kBig - 1) & ~(kBig - 1) : o;
+    o = align256(at + std::max<size_t>(bytes, 1));
     return at;
   };
   P.off_runs = take(sizeof(RunDev) * n_runs);
@@ -546,6 +595,8 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
   P.off_stage = take(8 * kFields * g.n_cells);
   P.off_acc = take(8 * (size_t)g.acc_stride * g.n_samples);
   P.off_nsnap = take(4 * (size_t)g.n_samples);
+  P.off_sched_ctr = take(4 * (size_t)g.n_sched_ctr);
+  P.off_sched_first = take(8 * P.sched_first.size());
   P.off_diag = take(8 * (size_t)kDiag * n_runs);
   P.off_mom = take(8 * 2 * (size_t)max_nc * kMoments);
   P.off_nalive = take(4 * n_runs);
@@ -594,6 +645,8 @@ DevPtrs<real> carve(const Plan &P, char *base) {
   d.stage = (double *)(base + P.off_stage);
   d.acc = (double *)(base + P.off_acc);
   d.nsnap = (uint32_t *)(base + P.off_nsnap);
+  d.sched_ctr = (uint32_t *)(base + P.off_sched_ctr);
+  d.sched_first = (const int64_t *)(base + P.off_sched_first);
   d.diag = (double *)(base + P.off_diag);
   d.mom = (double *)(base + P.off_mom);
   d.n_alive = (int32_t *)(base + P.off_nalive);
@@ -846,6 +899,19 @@ dsmc_status dsmc_init_runs(const dsmc_run_spec *runs, int32_t n_runs, const dsmc
   if (!st) st = upload(c, P.off_cell_items, P.cell_items);
   if (!st) st = upload(c, P.off_wave_items, P.wave_items);
   if (!st) st = upload(c, P.off_solid, P.solid);
+  if (!st) st = upload(c, P.off_sched_first, P.sched_first);
+  if (!st && c->plan.g.sched != kSchedGrid) {
+    // the persistent grids: as many workgroups as fit on the GPU at once, or
+    // as asked
+    int dev = 0, cus = 0;
+    st = check_hip(c, hipGetDevice(&dev), "hipGetDevice");
+    if (!st) st = check_hip(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev),
+                            "hipDeviceGetAttribute");
+    int occ[3] = {1, 1, 1};
+    if (!st) collide_occupancy(c->plan.g, occ);
+    const int want = opt ? opt->sched_blocks : 0;
+    for (int m = 0; m < 3 && !st; ++m) c->plan.g.sched_blocks[m] = want > 0 ? want : std::max(1, cus) * occ[m];
+  }
   if (!st) st = make_streams(c);
   if (!st) {
     if (P.g.fp64) launch_init<double>(P.g, c->dd, c->stream);
@@ -1133,9 +1199,9 @@ dsmc_status dsmc_get_lcr(dsmc_ctx *c, int32_t run, int32_t *lcr, int32_t *cell, 
   *n = ns;
   if (cap < ns) return set_err(c, DSMC_ESIZE, "output too small");
   std::vector<int32_t> l((size_t)std::max(ns, 1));
-  std::vector<uint32_t> s((size_t)R.nc + 2);
+  std::vector<uint32_t> s((size_t)R.nbin + 2);
   if (ns) st = download<int32_t>(c, l.data(), d_lcr + R.so, ns);
-  if (!st) st = download<uint32_t>(c, s.data(), d_start + R.bo, (size_t)R.nc + 2);
+  if (!st) st = download<uint32_t>(c, s.data(), d_start + R.bo, (size_t)R.nbin + 2);
   if (!st) st = sync_ctx(c);
   if (st) return st;
   // the slots without the marks of particles the wall queue moved
@@ -1143,12 +1209,12 @@ dsmc_status dsmc_get_lcr(dsmc_ctx *c, int32_t run, int32_t *lcr, int32_t *cell, 
   if (lcr)
     for (int64_t p = 0; p < ns; ++p) lcr[p] = l[p];
   if (start)
-    for (int i = 0; i < R.nc + 2; ++i) start[i] = s[i];
+    for (int i = 0; i < R.nbin + 2; ++i) start[i] = s[i];
   if (cell) {
-    // the cell array now holds the next step's flight cells: each slot's cell
-    // of this step is the bin whose range of LCR holds it (nc = DEAD)
-    for (int32_t b = 0; b <= R.nc; ++b) {
-      const int64_t hi = b < R.nc ? (int64_t)s[b + 1] : ns;
+    // the cell array now holds the next step's flight bins: each slot's bin
+    // of this step is the bin whose range of LCR holds it (nbin = DEAD)
+    for (int32_t b = 0; b <= R.nbin; ++b) {
+      const int64_t hi = b < R.nbin ? (int64_t)s[b + 1] : ns;
       for (int64_t p = s[b]; p < hi; ++p)
         if (l[p] < ns) cell[l[p]] = b;
     }
@@ -1241,7 +1307,7 @@ size_t ckpt_bytes(const Plan &P, const std::vector<int32_t> &na) {
   for (int r = 0; r < g.n_runs; ++r) o += pad8(4 * es * (size_t)na[r]) + pad8(nr * es * (size_t)na[r]);
   for (int r = 0; r < g.n_runs; ++r) {
     const size_t nc = (size_t)P.runs[r].nc;
-    o += 2 * pad8(es * nc) + pad8(4 * nc) + pad8(4 * (nc + 2));
+    o += 2 * pad8(es * nc) + pad8(4 * nc) + pad8(4 * ((size_t)P.runs[r].nbin + 2));
   }
   o += pad8(8 * (size_t)g.n_faces);
   o += pad8(8 * (size_t)g.acc_stride * g.n_samples);
@@ -1298,7 +1364,7 @@ dsmc_status ckpt_sections(dsmc_ctx *c, const DevPtrs<real> &d, char *host, const
     move(d.rem_c + R.co, es * R.nc);
     move(d.gmax + R.co, es * R.nc);
     move(d.ncoll + R.co, 4 * (size_t)R.nc);
-    move(d.bin_start + R.bo, 4 * ((size_t)R.nc + 2));
+    move(d.bin_start + R.bo, 4 * ((size_t)R.nbin + 2));
   }
   move(d.rem_f, 8 * (size_t)g.n_faces);
   move(d.acc, 8 * (size_t)g.acc_stride * g.n_samples);
@@ -1539,9 +1605,71 @@ std::vector<dsmc_options> tune_candidates(const dsmc_run_spec *runs, int32_t n_r
         o.tile_chunks = tc;
         o.collide_mode = m;
         o.n_streams = l;
+        o.sched = 0;
+        o.sched_blocks = 0;
         out.push_back(o);
       }
+  // Interaction on persistent grids drawing from one queue for all runs, at
+  // two occupancies: as many workgroups as fit, and 1024
+  for (int32_t m : modes)
+    for (int32_t blocks : {0, 1024}) {
+      dsmc_options o = base;
+      o.tile_chunks = 256;
+      o.collide_mode = m;
+      o.n_streams = 1;
+      o.sched = 1;
+      o.sched_blocks = blocks;
+      out.push_back(o);
+    }
   return out;
+}
+
+// The tune cache: one line per tuned problem, "fingerprint device tile_chunks
+// collide_mode n_streams sched sched_blocks ms_per_step"; the fingerprint
+// covers the run specs, precision, groups, schedule, window and graph replay.
+std::string tune_key(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_options &base) {
+  char buf[128];
+  hipDeviceProp_t prop{};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    snprintf(prop.gcnArchName, sizeof prop.gcnArchName, "unknown");
+  const uint64_t fp = plan_fingerprint(runs, n_runs, base) * 31u + (uint64_t)(base.use_graph != 0);
+  std::string arch = prop.gcnArchName;
+  for (char &ch : arch)
+    if (ch == ' ') ch = '_';
+  snprintf(buf, sizeof buf, "%016llx %s-%dcu", (unsigned long long)fp, arch.c_str(), prop.multiProcessorCount);
+  return buf;
+}
+
+bool tune_cache_find(const char *path, const std::string &key, dsmc_options &o, double &ms) {
+  FILE *f = path ? fopen(path, "r") : nullptr;
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (fgets(line, sizeof line, f)) {
+    char fp[64], devname[128];
+    int tc, cm, ns, sc, sb;
+    double t;
+    if (sscanf(line, "%63s %127s %d %d %d %d %d %lf", fp, devname, &tc, &cm, &ns, &sc, &sb, &t) != 8) continue;
+    if (key != std::string(fp) + " " + devname) continue;
+    o.tile_chunks = tc;
+    o.collide_mode = cm;
+    o.n_streams = ns;
+    o.sched = sc;
+    o.sched_blocks = sb;
+    ms = t;
+    found = true;  // the last matching line wins
+  }
+  fclose(f);
+  return found;
+}
+
+void tune_cache_add(const char *path, const std::string &key, const dsmc_options &o, double ms) {
+  FILE *f = path ? fopen(path, "a") : nullptr;
+  if (!f) return;
+  fprintf(f, "%s %d %d %d %d %d %.6f\n", key.c_str(), o.tile_chunks, o.collide_mode, o.n_streams, o.sched,
+          o.sched_blocks, ms);
+  fclose(f);
 }
 
 }  // namespace
@@ -1567,15 +1695,25 @@ dsmc_status dsmc_autotune_bytes(const dsmc_run_spec *runs, int32_t n_runs, const
 }
 
 dsmc_status dsmc_autotune(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_options *opt, void *arena,
-                          size_t arena_bytes, void *hip_stream, int32_t n_steps, dsmc_options *best,
-                          double *best_ms_per_step) {
+                          size_t arena_bytes, void *hip_stream, int32_t n_steps, const char *tune_cache,
+                          dsmc_options *best, double *best_ms_per_step) {
   if (!best || n_steps < 1) return DSMC_EINVAL;
   size_t need = 0;
   dsmc_status st = dsmc_autotune_bytes(runs, n_runs, opt, &need);
   if (st) return st;
-  if (!arena || ((uintptr_t)arena & 255) || arena_bytes < need) return DSMC_ESIZE;
   dsmc_options base{};
   if (opt) base = *opt;
+  const std::string key = tune_cache ? tune_key(runs, n_runs, base) : std::string();
+  if (tune_cache) {
+    dsmc_options cached = base;
+    double ms = -1.0;
+    if (tune_cache_find(tune_cache, key, cached, ms)) {
+      *best = cached;
+      if (best_ms_per_step) *best_ms_per_step = ms;
+      return DSMC_OK;
+    }
+  }
+  if (!arena || ((uintptr_t)arena & 255) || arena_bytes < need) return DSMC_ESIZE;
   hipStream_t s = (hipStream_t)hip_stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -1613,6 +1751,7 @@ dsmc_status dsmc_autotune(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_
   if (st) return st;
   *best = pick;
   if (best_ms_per_step) *best_ms_per_step = best_ms;
+  if (tune_cache) tune_cache_add(tune_cache, key, pick, best_ms);
   return DSMC_OK;
 }
 

@@ -76,6 +76,8 @@ struct RunDev {
   int32_t to;        // first tile of the run
   int32_t nt;        // tiles of the run
   int32_t nc, nx, ny, nz;
+  int32_t sub, S;    // collision partners from sub-cells: sub per axis, S = sub^dim per cell (1, 1 = none)
+  int32_t nbin;      // Indexing bins: nc * S (a cell's S sub-cells consecutive); the DEAD bin is nbin
   int32_t nface;     // inflow face elements (0 without inflow)
   int32_t ndig;      // digits of the first indexing pass
   int32_t hs;        // hard sphere (omega == 0.5)
@@ -102,6 +104,20 @@ struct RunDev {
   // length, and the solid cells' bounding box widened by two cells
   float dt_f, L_f[3], inv_f[3], slo_f[3], shi_f[3];
   double slo[3], shi[3];
+  double inv_bin[3];     // Indexing bins per unit length along each axis: cells, or sub-cells with
+  float inv_bin_f[3];    // sub-cells (equal to inv_d without them)
+};
+
+// How an Interaction kernel's workgroups get their items (see the kernels).
+enum : int32_t { kSchedGrid = 0, kSchedQueue = 1, kSchedPerRun = 2 };
+
+struct Sched {
+  int32_t mode;           // kSchedGrid, kSchedQueue or kSchedPerRun
+  int32_t pad0;
+  uint32_t *ctr;          // kSchedQueue: one counter per XCD; kSchedPerRun: one per run of the list
+  const int64_t *first;   // kSchedPerRun: first item of each run of the list (nr + 1 entries)
+  int32_t nr;             // kSchedPerRun: runs with items in the list
+  int32_t pad;
 };
 
 template <typename real> struct Vec4;
@@ -179,6 +195,8 @@ struct DevPtrs {
   double *acc;                 // [n_samples][acc_stride]
   double *mom;                 // [2][max_nc][8]
   uint32_t *nsnap;             // [n_samples] snapshots accumulated in each sample slot
+  uint32_t *sched_ctr;         // work counters of the persistent Interaction grids, zeroed every step
+  const int64_t *sched_first;  // per interaction mode, the first item of each run with items in it
   double *diag;                // [runs][kDiag] per-run diagnostics (dsmc_get_diag)
   int32_t *n_alive;            // [runs]
   int32_t *n_sorted;           // [runs]
@@ -207,6 +225,8 @@ struct LaneRange {
   int64_t ci0, ci1;  // block-per-cell interaction items
   int64_t wi0, wi1;  // wavefront-per-cell interaction items
   int32_t b0, b1;    // bucket-item slots (two-level Indexing)
+  int32_t sr0[3], sr1[3];  // per interaction mode (lane, wave, cell items): the lane's runs in the mode's
+                           // list of runs with items (persistent per-run scheduling)
 };
 
 struct Geometry {
@@ -225,6 +245,7 @@ struct Geometry {
   int32_t n_bitems;      // bucket-item slots
   int dstride;           // LDS words per wave for one histogram
   int max_nc;
+  int max_nbin;          // Indexing bins of the largest run (cells times sub-cells)
   int n_eg;
   int64_t acc_stride;
   int n_samples;
@@ -235,7 +256,13 @@ struct Geometry {
   int64_t n_wave_items; // wavefront-per-cell interaction items
   int collide_mode;      // 0 auto, 1 lane per cell, 2 wave per cell
   int any_solid;         // some run has solid cells (Motion checks paths against them)
+  int any_sub;           // some run has sub-cells
   int n_lanes;           // run groups per step (1: everything on the caller's stream)
+  int sched;             // Interaction work distribution: kSchedGrid, kSchedQueue or kSchedPerRun
+  int sched_blocks[3];   // persistent grid (workgroups) per interaction mode (lane, wave, cell kernels)
+  int64_t sched_first_off[3];  // offset of each mode's list of run starts in sched_first
+  int64_t sched_ctr_off[3];    // offset of each mode's per-run counters in sched_ctr
+  int64_t n_sched_ctr;   // counters in sched_ctr: [mode][lane][XCD] queue counters, then the per-run ones
   LaneRange lane[kMaxLanes];
 };
 
@@ -282,6 +309,9 @@ void launch_sample(const Geometry &g, const DevPtrs<real> &d, int buf, int slot,
 template <typename real>
 void launch_moments(const Geometry &g, const DevPtrs<real> &d, int slot, int eg0, int n_groups,
                     int nc, int n_runs_ens, hipStream_t s);
+// Resident workgroups per CU of each Interaction kernel of this geometry
+// (lane, wave, cell items), from the occupancy calculator.
+void collide_occupancy(const Geometry &g, int out[3]);
 // Per-run diagnostics of the particles in buffer buf into d.diag.
 template <typename real>
 void launch_diag(const Geometry &g, const DevPtrs<real> &d, int buf, hipStream_t s);

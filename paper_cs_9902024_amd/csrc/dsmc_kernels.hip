@@ -143,6 +143,28 @@ __device__ __forceinline__ int32_t cell_of(const RunDev &R, const real (&pos)[3]
   return (iz * R.ny + iy) * R.nx + ix;
 }
 
+// The Indexing bin of a position on the sub-cell grid (sub per axis): cell *
+// S + (sz * sub + sy) * sub + sx, the cell being the sub-cell index divided
+// by sub along each axis.  inv: sub-cells per unit length; n: cells per axis.
+template <typename real, int DIM>
+__device__ __forceinline__ int32_t subcell_bin(const real (&pos)[3], const real (&inv)[3], const int32_t (&n)[3],
+                                               int32_t sub, int32_t S) {
+  const int32_t fx = axis_index(pos[0], inv[0], n[0] * sub);
+  const int32_t fy = axis_index(pos[1], inv[1], n[1] * sub);
+  const int32_t fz = (DIM == 3) ? axis_index(pos[2], inv[2], n[2] * sub) : 0;
+  const int32_t c = ((fz / sub) * n[1] + fy / sub) * n[0] + fx / sub;
+  return c * S + ((fz % sub) * sub + fy % sub) * sub + fx % sub;
+}
+
+// The bin of a position: its cell, or its sub-cell with sub-cells.
+template <typename real, int DIM>
+__device__ __forceinline__ int32_t bin_of(const RunDev &R, const real (&pos)[3]) {
+  if (R.sub == 1) return cell_of<real, DIM>(R, pos);
+  const real inv[3] = {(real)R.inv_bin[0], (real)R.inv_bin[1], (real)R.inv_bin[2]};
+  const int32_t n[3] = {R.nx, R.ny, R.nz};
+  return subcell_bin<real, DIM>(pos, inv, n, R.sub, R.S);
+}
+
 // ---------------------------------------------------------------------------
 // Initialisation
 // ---------------------------------------------------------------------------
@@ -576,14 +598,15 @@ __device__ __forceinline__ int32_t move_one(const RunDev &R, const uint8_t *soli
       reemit = true;
       diffuse_emit<real>(R, step, slot, hits, (real)R.face_T[f], (real)R.face_sqrtT[f], ax, side, vel);
     } else {
-      return R.nc;  // inflow plane crossed outward, or outflow
+      return R.nbin;  // inflow plane crossed outward, or outflow
     }
     if (++hits == kMaxWallHits) {
       set_error(err, kErrBounce);
       break;
     }
   }
-  if (pos[0] < (real)0) return R.nc;  // generated upstream and never entered
+  if (pos[0] < (real)0) return R.nbin;  // generated upstream and never entered
+  if (R.sub > 1) return bin_of<real, DIM>(R, pos);  // (no solid cells with sub-cells)
   int32_t c = cell_of<real, DIM>(R, pos);
   if (R.has_solid && solid[R.sdo + c]) {
     // rounding put the end point across the face of a solid cell: it belongs
@@ -647,12 +670,18 @@ struct Flight {
   real dt, L[3], inv[3], slo[3], shi[3];
   int32_t n[3];
   bool solid;
+  int32_t sub, S;  // sub-cells per axis and per cell (1, 1 without)
+  Flight() = default;
   __device__ __forceinline__ explicit Flight(const RunDev &R) {
     dt = in_precision<real>(R.dt, R.dt_f);
+    sub = R.sub;
+    S = R.S;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       L[a] = in_precision<real>(R.L[a], R.L_f[a]);
-      inv[a] = in_precision<real>(R.inv_d[a], R.inv_f[a]);
+      // the grid the flight's end is placed on: the cells, or the sub-cells
+      // (one load, independent of sub)
+      inv[a] = in_precision<real>(R.inv_bin[a], R.inv_bin_f[a]);
       slo[a] = in_precision<real>(R.slo[a], R.slo_f[a]);
       shi[a] = in_precision<real>(R.shi[a], R.shi_f[a]);
     }
@@ -666,13 +695,17 @@ struct Flight {
 // Motion's test for one particle: the cell its free flight ends in, or
 // kQueueBit when it must take the full flight (it reaches a face, or passes
 // near a body).  Motion and Interaction's look-ahead both call this, so they
-// decide identically.
-template <typename real, int DIM>
+// decide identically.  SUB = false: a kernel instantiated for batches
+// without sub-cells (no sub-cell code in its write-back).
+template <typename real, int DIM, bool SUB = true>
 __device__ __forceinline__ int32_t flight_cell(const Flight<real> &F, const real (&pos)[3], const real (&vel)[3]) {
   real out[3];
   bool fast = free_flight<real, DIM>(F.dt, F.L, pos, vel, out);
   if (F.solid && fast) fast = !near_solid<real, DIM>(pos, out, F.slo, F.shi);
   if (!fast) return kQueueBit;
+  if constexpr (SUB) {
+    if (F.sub > 1) return subcell_bin<real, DIM>(out, F.inv, F.n, F.sub, F.S);
+  }
   const int32_t ix = axis_index(out[0], F.inv[0], F.n[0]);
   const int32_t iy = axis_index(out[1], F.inv[1], F.n[1]);
   const int32_t iz = (DIM == 3) ? axis_index(out[2], F.inv[2], F.n[2]) : 0;
@@ -780,7 +813,7 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
   const int r = d.tile_run[t];
   const RunDev &R = d.runs[r];
   const int64_t tl = t - R.to;
-  const int D = SINGLE ? R.nc + 1 : kDigits;
+  const int D = SINGLE ? R.nbin + 1 : kDigits;
   uint32_t *h = lds + wave * dstride;
   uint32_t *qb = lds + kWavesPerBlock * dstride + wave * kMotionQueueStage;  // staged queue entries
   uint32_t ql = 0;
@@ -886,7 +919,7 @@ __global__ __launch_bounds__(256) void k_motion_walls(DevPtrs<real> d, int buf, 
   if (nq == 0) return;
   const RunDev &R = d.runs[d.tile_run[t]];
   const uint32_t step = *d.step;
-  const int D = SINGLE ? R.nc + 1 : kDigits;
+  const int D = SINGLE ? R.nbin + 1 : kDigits;
   uint32_t *Mt = d.hist + R.mo + (int64_t)(t - R.to) * D;
   const uint32_t *wq = d.wallq + (int64_t)t * tile;
   const Particles<real> P = d.P[buf];
@@ -911,7 +944,7 @@ __global__ __launch_bounds__(256) void k_motion_walls(DevPtrs<real> d, int buf, 
                           isfinite(w0);
       if (!finite) set_error(d.err, kErrNumeric);
       const int32_t c =
-          finite ? move_one<real, DIM>(R, d.solid, step, (uint32_t)loc, p3, v3, hit, reemit, d.err) : R.nc;
+          finite ? move_one<real, DIM>(R, d.solid, step, (uint32_t)loc, p3, v3, hit, reemit, d.err) : R.nbin;
       // (the velocity is unchanged unless a face was hit)
       P.q[gs] = make_vec4<real>(p3[0], p3[1], v3[0], v3[1]);
       if (DIM == 3) store_zw<DIM>(P, gs, p3[2], v3[2]);
@@ -939,7 +972,7 @@ struct IndexArgs {
   int32_t *kout;           // bins in the order of `out`, or null
   uint32_t *hist;          // tile histograms, tile-major: [tile][digit]
   uint32_t *tot;           // per run digit totals -> digit starts
-  uint32_t *bin_start;     // per run nc + 2 bin starts (single pass / bounds)
+  uint32_t *bin_start;     // per run nbin + 2 bin starts (single pass / bounds)
   int32_t *n_sorted;
   int32_t *n_alive;
   int32_t t0, t1;          // tiles [t0, t1)
@@ -971,7 +1004,7 @@ __global__ __launch_bounds__(256) void k_digcount(IndexArgs a, int use_n_alive) 
   const RunDev &R = a.runs[r];
   const int64_t tl = t - R.to;
   const bool single = a.single;
-  const int D = single ? R.nc + 1 : kDigits;
+  const int D = single ? R.nbin + 1 : kDigits;
   uint32_t *h = lds + wave * a.dstride;
   for (int q = lane; q < D; q += kWave) h[q] = 0;
   wave_sync();
@@ -1011,7 +1044,7 @@ __global__ __launch_bounds__(256) void k_digcount(IndexArgs a, int use_n_alive) 
 // (in place) and the digit total.  Coalesced across digits.
 __global__ __launch_bounds__(256) void k_colscan(IndexArgs a) {
   const RunDev &R = a.runs[a.r0 + blockIdx.y];
-  const int D = a.single ? R.nc + 1 : kDigits;
+  const int D = a.single ? R.nbin + 1 : kDigits;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= D) return;
   uint32_t *col = a.hist + R.mo + q;
@@ -1055,7 +1088,7 @@ __global__ __launch_bounds__(256) void k_digscan(IndexArgs a) {
   const int r = a.r0 + (int)blockIdx.x;
   const RunDev &R = a.runs[r];
   const bool single = a.single;
-  const int D = single ? R.nc + 1 : kDigits;
+  const int D = single ? R.nbin + 1 : kDigits;
   uint32_t *tot = a.tot + R.cbo;
   const int per = (D + 255) / 256;  // <= 8
   const int tid = threadIdx.x;
@@ -1083,14 +1116,14 @@ __global__ __launch_bounds__(256) void k_digscan(IndexArgs a) {
       tot[q0 + k] = run;
       if (single) {
         a.bin_start[R.bo + q0 + k] = run;
-        if (q0 + k == R.nc) a.n_alive[r] = (int32_t)run;  // everything before the DEAD bin
+        if (q0 + k == R.nbin) a.n_alive[r] = (int32_t)run;  // everything before the DEAD bin
       }
       run += v[k];
     }
   }
   if (tid == 0) {
     a.n_sorted[r] = (int32_t)total;
-    if (single) a.bin_start[R.bo + R.nc + 1] = total;
+    if (single) a.bin_start[R.bo + R.nbin + 1] = total;
   }
 }
 
@@ -1252,7 +1285,7 @@ __global__ __launch_bounds__(256) void k_bucket_scan(IndexArgs a) {
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     const int q = tid + 256 * e;
-    if (c0 + q <= R.nc) bs[q] = col[q];
+    if (c0 + q <= R.nbin) bs[q] = col[q];
   }
 }
 
@@ -1346,7 +1379,7 @@ __global__ __launch_bounds__(256) void k_scatter(IndexArgs a) {
     const uint32_t *M = a.hist + (int64_t)i * kDigits;
     const int64_t c0 = (int64_t)h << kDigitBits;
     const uint32_t *S = a.bin_start + R.bo + c0;
-    const int64_t last = R.nc - c0;  // digits beyond are no bins of the run
+    const int64_t last = R.nbin - c0;  // digits beyond are no bins of the run
     init_cursors(cursor, S, M, kDigits, last + 1);
   } else {
     const int t = a.t0 + blk * kWavesPerBlock + wave;
@@ -1354,7 +1387,7 @@ __global__ __launch_bounds__(256) void k_scatter(IndexArgs a) {
     r = a.tile_run[t];
     const RunDev &R = a.runs[r];
     const int64_t tl = t - R.to;
-    const int D = single ? R.nc + 1 : kDigits;
+    const int D = single ? R.nbin + 1 : kDigits;
     const uint32_t *Mt = a.hist + R.mo + tl * D;
     const uint32_t *S = a.tot + R.cbo;
     init_cursors(cursor, S, Mt, D, D);
@@ -1451,7 +1484,7 @@ __global__ __launch_bounds__(256) void k_bin_bounds(IndexArgs a, const int32_t *
       if (loc >= end) break;
       for (int32_t q = prev + 1; q <= k[e]; ++q) bs[q] = (uint32_t)loc;
       if (loc == n - 1)
-        for (int32_t q = k[e] + 1; q <= R.nc + 1; ++q) bs[q] = (uint32_t)n;
+        for (int32_t q = k[e] + 1; q <= R.nbin + 1; ++q) bs[q] = (uint32_t)n;
       prev = k[e];
     }
   }
@@ -1462,10 +1495,10 @@ __global__ void k_bin_finalize(IndexArgs a, int r1, int set_alive) {
   if (r >= r1) return;
   const RunDev &R = a.runs[r];
   if (a.n_sorted[r] == 0)
-    for (int32_t q = 0; q <= R.nc + 1; ++q) a.bin_start[R.bo + q] = 0;
+    for (int32_t q = 0; q <= R.nbin + 1; ++q) a.bin_start[R.bo + q] = 0;
   // (the two-level sort's bucket scans end at bin nc)
-  a.bin_start[R.bo + R.nc + 1] = (uint32_t)a.n_sorted[r];
-  if (set_alive) a.n_alive[r] = (int32_t)a.bin_start[R.bo + R.nc];
+  a.bin_start[R.bo + R.nbin + 1] = (uint32_t)a.n_sorted[r];
+  if (set_alive) a.n_alive[r] = (int32_t)a.bin_start[R.bo + R.nbin];
 }
 
 // ---------------------------------------------------------------------------
@@ -1503,16 +1536,36 @@ struct Selection {
   real ua, uc, ue;
 };
 
+// The sub-cells of one cell, for the choice of the second partner: the
+// cell's S + 1 bin starts (run-local positions, in global memory) and its
+// first position; no sub-cells when start is null.
+struct SubCells {
+  const uint32_t *start = nullptr;
+  uint32_t base = 0;
+};
+
 // Selection k of cell c: pair (i, j != i) and the acceptance and scattering
 // uniforms, from Philox blocks (step, COLL, c, 2k) and (step, COLL, c, 2k+1).
+// The second partner comes from the first one's sub-cell when it holds two or
+// more particles (with sub-cells), else from the cell.
 template <typename real, typename RunT>
 __device__ __forceinline__ Selection<real> draw_selection(const RunT &R, uint32_t step, uint32_t c, int64_t k,
-                                                          uint32_t N) {
+                                                          uint32_t N, const SubCells &sub = SubCells{}) {
   const uint4 b0 = philox(make_uint4(step, kColl, c, (uint32_t)(2 * k)), R.key0, R.key1);
   const uint4 b1 = philox(make_uint4(step, kColl, c, (uint32_t)(2 * k + 1)), R.key0, R.key1);
   Selection<real> s;
   s.i = __umulhi(b0.x, N);
-  const uint32_t jp = __umulhi(b0.y, N - 1u);
+  uint32_t lo = 0, span = N;  // the second partner: one of [lo, lo + span) other than i
+  if (sub.start) {
+    uint32_t q = 0;
+    while (sub.start[q + 1] - sub.base <= s.i) ++q;
+    const uint32_t ns = sub.start[q + 1] - sub.start[q];
+    if (ns >= 2) {
+      lo = sub.start[q] - sub.base;
+      span = ns;
+    }
+  }
+  const uint32_t jp = lo + __umulhi(b0.y, span - 1u);
   s.j = jp + (jp >= s.i ? 1u : 0u);
   s.ua = u01<real>(b0.z, b0.w);
   s.uc = u01<real>(b1.x, b1.y);
@@ -1559,10 +1612,10 @@ __device__ __forceinline__ void scatter_pair(real cr, const Angles<real> &an, re
 // updates gm.
 template <typename real, typename RunT, typename PU, typename PV, typename PW>
 __device__ uint32_t chain_serial(const RunT &R, uint32_t step, uint32_t c, uint32_t N, int64_t k0, int64_t k1,
-                                 PU u, PV v, PW w, real &gm) {
+                                 PU u, PV v, PW w, real &gm, const SubCells &sub = SubCells{}) {
   uint32_t ncol = 0;
   for (int64_t k = k0; k < k1; ++k) {
-    const Selection<real> s = draw_selection<real>(R, step, c, k, N);
+    const Selection<real> s = draw_selection<real>(R, step, c, k, N, sub);
     const real du = u[s.i] - u[s.j], dv = v[s.i] - v[s.j], dw = w[s.i] - w[s.j];
     const real cr = sqrt(du * du + dv * dv + dw * dw);
     const real g = g_of<real>(R, cr);
@@ -1727,7 +1780,7 @@ __device__ __forceinline__ void gather_hold(const RunDev &R, const int32_t *lcr,
 // Write-back of an item gathered by gather_hold: whole records to P' (held
 // positions, final velocities) and, with the look-ahead, each particle's
 // next flight cell.
-template <typename real, int DIM, int NH>
+template <typename real, int DIM, int NH, bool SUB = true>
 __device__ __forceinline__ void write_back_held(const RunDev &R, const Particles<real> &B, int32_t *cell, int64_t b,
                                                 int64_t n, const real *u, const real *v, const real *w,
                                                 const real (&hx)[NH], const real (&hy)[NH], const real (&hz)[NH]) {
@@ -1744,7 +1797,7 @@ __device__ __forceinline__ void write_back_held(const RunDev &R, const Particles
       if (ahead) {
         const real pos[3] = {hx[j], hy[j], hz[j]};
         const real vel[3] = {u[k], v[k], DIM == 3 ? w[k] : (real)0};
-        cell[base + k] = flight_cell<real, DIM>(F, pos, vel);
+        cell[base + k] = flight_cell<real, DIM, SUB>(F, pos, vel);
       }
     }
   }
@@ -1754,7 +1807,7 @@ __device__ __forceinline__ void write_back_held(const RunDev &R, const Particles
 // whose particles are complete in P' (this thread's share: t, t + nt, ...,
 // the same thread that wrote them): the cell each particle's next free
 // flight ends in, or the queue mark.
-template <typename real, int DIM>
+template <typename real, int DIM, bool SUB = true>
 __device__ __forceinline__ void next_cells(const RunDev &R, const Particles<real> &B, int32_t *cell, int64_t b,
                                            int64_t n, int t, int nt) {
   const Flight<real> F(R);
@@ -1766,7 +1819,7 @@ __device__ __forceinline__ void next_cells(const RunDev &R, const Particles<real
     load_zw<DIM>(B, dst, z, w);
     const real pos[3] = {r4.x, r4.y, z};
     const real vel[3] = {r4.z, r4.w, DIM == 3 ? w : (real)0};
-    cell[dst] = flight_cell<real, DIM>(F, pos, vel);
+    cell[dst] = flight_cell<real, DIM, SUB>(F, pos, vel);
   }
 }
 
@@ -1775,13 +1828,90 @@ __device__ __forceinline__ void global_sync_wave() {
   __builtin_amdgcn_wave_barrier();
 }
 
-template <typename real, int DIM>
-__global__ __launch_bounds__(kCollideWaves * 64) void k_collide(DevPtrs<real> d, int src, int64_t it0, int64_t it1) {
-  extern __shared__ __align__(16) unsigned char lds_bytes[];
+// ---------------------------------------------------------------------------
+// Work distribution of an Interaction kernel over its items [i0, i1)
+// ---------------------------------------------------------------------------
+//
+// kSchedGrid: one item per workgroup (or wavefront) from the grid index, the
+// hardware dispatcher handing workgroups to CUs as they free up.
+// kSchedQueue: a persistent grid whose workgroups draw items from a device
+// queue shared by all runs (the GPU form of dynamic processor reallocation:
+// a workgroup done with one run's work takes any run's next item).  The list
+// is split into eight contiguous shares with a counter each, one per XCD
+// (neighbouring cells stay on one L2); a workgroup draws from its own XCD's
+// share, then from the others'.
+// kSchedPerRun: a persistent grid whose workgroups are tied to runs (the
+// static two-level split): of U units (workgroups, or wavefronts), unit g
+// serves run g mod nr when U >= nr (p2 = U / nr units per run), else runs g,
+// g + U, g + 2U, ... one after the other.
+// The item a workgroup draws never changes what is computed for it.
+constexpr int kXcds = 8;
+
+// A draw takes kSchedBatch consecutive items of one share: [first, end) with
+// end - first <= kSchedBatch; first = i1 when the queue is used up.
+constexpr int kSchedBatch = 4;
+
+struct Draw {
+  int64_t first, end;
+};
+
+// The draw state x of unit `unit`: its XCD (kSchedQueue), its first run
+// (kSchedPerRun).
+__device__ __forceinline__ int sched_start(const Sched &s, int unit) {
+  if (s.mode == kSchedPerRun) return s.nr > 0 ? unit % s.nr : 0;
+  return (int)(blockIdx.x % kXcds);
+}
+
+// `units`: U, the persistent grid's units (kSchedPerRun).
+__device__ __forceinline__ Draw sched_draw(const Sched &s, int64_t i0, int64_t i1, int units, int &x, int &tries) {
+  if (s.mode == kSchedPerRun) {
+    while (x < s.nr) {
+      const int64_t item = s.first[x] + (int64_t)atomicAdd(&s.ctr[x], 1u) * kSchedBatch;
+      const int64_t lim = s.first[x + 1];
+      if (item < lim) return Draw{item, min(item + kSchedBatch, lim)};
+      x += units;  // this run's items are all taken: the unit's next run
+    }
+    return Draw{i1, i1};
+  }
+  const int64_t N = i1 - i0;
+  while (tries < kXcds) {
+    // XCD x's share: a contiguous 1/8 of the list (as the grid's block order
+    // gives it), so neighbouring cells, whose gathers share lines, meet in
+    // one L2
+    const int64_t q = N / kXcds, rmd = N % kXcds;
+    const int64_t lo = x < rmd ? x * (q + 1) : rmd * (q + 1) + (x - rmd) * q;
+    const int64_t hi = lo + (x < rmd ? q + 1 : q);
+    const int64_t item = lo + (int64_t)atomicAdd(&s.ctr[x], 1u) * kSchedBatch;
+    if (item < hi) return Draw{i0 + item, i0 + min(item + kSchedBatch, hi)};
+    // this XCD's share is used up: take from the next one's
+    x = (x + 1) % kXcds;
+    ++tries;
+  }
+  return Draw{i1, i1};
+}
+
+__device__ __forceinline__ int64_t first_lane_i64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// A wavefront's next draw (lane 0 draws, every lane gets it).
+__device__ __forceinline__ Draw sched_next_wave(const Sched &s, int64_t i0, int64_t i1, int units, int &x,
+                                                int &tries) {
+  Draw d{0, 0};
+  if ((threadIdx.x & 63) == 0) d = sched_draw(s, i0, i1, units, x, tries);
+  x = __builtin_amdgcn_readfirstlane(x);
+  tries = __builtin_amdgcn_readfirstlane(tries);
+  return Draw{first_lane_i64(d.first), first_lane_i64(d.end)};
+}
+
+// SUB = false: instantiated for batches without sub-cells.
+template <typename real, int DIM, bool SUB>
+__device__ __forceinline__ void collide_lanes_item(const DevPtrs<real> &d, int src, int64_t item,
+                                                   unsigned char *lds_bytes) {
   constexpr int CAP = LaneCap<real>::value;
   const int wave = wave_index(), lane = threadIdx.x & 63;
-  const int64_t item = it0 + xcd_block(blockIdx.x, gridDim.x) * kCollideWaves + wave;
-  if (item >= it1) return;
   const int2 it = d.items[item];
   const RunDev &R = d.runs[it.x];
   const int32_t c0 = it.y;
@@ -1789,8 +1919,9 @@ __global__ __launch_bounds__(kCollideWaves * 64) void k_collide(DevPtrs<real> d,
   real *su = (real *)(lds_bytes + wave * collide_wave_bytes<real>());
   real *sv = su + CAP, *sw = sv + CAP;
   const Particles<real> A = d.P[src], B = d.P[1 - src];
-  const int64_t b0 = d.bin_start[R.bo + c0];
-  const int64_t n = (int64_t)d.bin_start[R.bo + c0 + ncell] - b0;
+  const int S = R.S;  // a cell's bins: S consecutive sub-cells (1 without sub-cells)
+  const int64_t b0 = d.bin_start[R.bo + (int64_t)c0 * S];
+  const int64_t n = (int64_t)d.bin_start[R.bo + (int64_t)(c0 + ncell) * S] - b0;
   const bool in_lds = n <= CAP;
   constexpr int NH = (CAP + 4 * kWave - 1) / (4 * kWave) * 4;
   real hx[NH], hy[NH], hz[NH];
@@ -1804,18 +1935,24 @@ __global__ __launch_bounds__(kCollideWaves * 64) void k_collide(DevPtrs<real> d,
   if (lane < ncell) {
     const int32_t c = c0 + lane;
     const int64_t gc = R.co + c;
-    const int64_t cb = (int64_t)d.bin_start[R.bo + c] - b0;
-    const int64_t N = (int64_t)d.bin_start[R.bo + c + 1] - b0 - cb;
+    const int64_t cs = (int64_t)d.bin_start[R.bo + (int64_t)c * S];
+    const int64_t cb = cs - b0;
+    const int64_t N = (int64_t)d.bin_start[R.bo + (int64_t)(c + 1) * S] - cs;
+    SubCells sub;
+    if (SUB && S > 1) {
+      sub.start = d.bin_start + R.bo + (int64_t)c * S;
+      sub.base = (uint32_t)cs;
+    }
     real gm = d.gmax[gc], rem = d.rem_c[gc];
     const int64_t nsel = ntc_selections<real>(R, N, gm, rem, d.err);
     uint32_t ncol;
     if (in_lds) {
-      ncol = chain_serial<real>(R, step, (uint32_t)c, (uint32_t)N, 0, nsel, su + cb, sv + cb, sw + cb, gm);
+      ncol = chain_serial<real>(R, step, (uint32_t)c, (uint32_t)N, 0, nsel, su + cb, sv + cb, sw + cb, gm, sub);
       if (sample) sample_cell(su + cb, sv + cb, sw + cb, N, d.stage + gc * kFields);
     } else {
       const int64_t o = R.so + b0 + cb;
       ncol = chain_serial<real>(R, step, (uint32_t)c, (uint32_t)N, 0, nsel, B.u() + o, B.v() + o, w_view<DIM>(B, o),
-                                gm);
+                                gm, sub);
       if (sample) sample_cell(B.u() + o, B.v() + o, w_view<DIM>(B, o), N, d.stage + gc * kFields);
     }
     d.gmax[gc] = gm;
@@ -1824,10 +1961,37 @@ __global__ __launch_bounds__(kCollideWaves * 64) void k_collide(DevPtrs<real> d,
   }
   if (in_lds) {
     wave_sync();
-    write_back_held<real, DIM, NH>(R, B, d.cell, b0, n, su, sv, sw, hx, hy, hz);
+    write_back_held<real, DIM, NH, SUB>(R, B, d.cell, b0, n, su, sv, sw, hx, hy, hz);
   } else if (R.ahead) {
     global_sync_wave();  // every lane's chain on P' is visible
-    next_cells<real, DIM>(R, B, d.cell, b0, n, lane, kWave);
+    next_cells<real, DIM, SUB>(R, B, d.cell, b0, n, lane, kWave);
+  }
+}
+
+// PERSIST: the persistent grid (Sched); otherwise one item per wavefront of
+// the grid.  Separate instantiations: the loop's state would cost the grid
+// kernel registers.
+template <typename real, int DIM, bool PERSIST, bool SUB>
+__global__ __launch_bounds__(kCollideWaves * 64) void k_collide(DevPtrs<real> d, int src, int64_t it0, int64_t it1,
+                                                                Sched sc) {
+  extern __shared__ __align__(16) unsigned char lds_bytes[];
+  const int wave = wave_index();
+  if constexpr (!PERSIST) {
+    const int64_t item = it0 + xcd_block(blockIdx.x, gridDim.x) * kCollideWaves + wave;
+    if (item < it1) collide_lanes_item<real, DIM, SUB>(d, src, item, lds_bytes);
+    return;
+  }
+  const int units = (int)gridDim.x * kCollideWaves;
+  int x = sched_start(sc, (int)blockIdx.x * kCollideWaves + wave), tries = 0;
+  Draw cur = sched_next_wave(sc, it0, it1, units, x, tries);
+  while (cur.first < it1) {
+    // the next draw goes out before this one's items, so its latency overlaps them
+    const Draw nxt = sched_next_wave(sc, it0, it1, units, x, tries);
+    for (int64_t item = cur.first; item < cur.end; ++item) {
+      collide_lanes_item<real, DIM, SUB>(d, src, item, lds_bytes);
+      wave_sync();  // the stage is free again
+    }
+    cur = nxt;
   }
 }
 
@@ -1923,7 +2087,8 @@ constexpr int collide_cell_bytes() {
 
 template <typename real, typename Sync = FullSync, typename RunT = RunDev>
 __device__ uint32_t chain_block(const RunT &R, uint32_t step, uint32_t c, uint32_t N, int64_t nsel, real *u,
-                                real *v, real *w, int32_t *own, BlockScratch<real> &sh, real &gm) {
+                                real *v, real *w, int32_t *own, BlockScratch<real> &sh, real &gm,
+                                const SubCells &sub = SubCells{}) {
   const int tid = Sync::tid();
   uint32_t ncol = 0;
   int64_t w0 = 0;
@@ -1933,7 +2098,7 @@ __device__ uint32_t chain_block(const RunT &R, uint32_t step, uint32_t c, uint32
     Selection<real> s{0u, 0u, (real)0, (real)0, (real)0};
     Angles<real> an{(real)1, (real)0, (real)1, (real)0};
     if (act) {
-      s = draw_selection<real>(R, step, c, w0 + tid, N);
+      s = draw_selection<real>(R, step, c, w0 + tid, N, sub);
       // deflection angles once per selection, not once per conflict round
       an = angles_of(s.uc, s.ue);
     }
@@ -2019,13 +2184,10 @@ __device__ uint32_t chain_block(const RunT &R, uint32_t step, uint32_t c, uint32
 }
 
 template <typename real, int DIM>
-__global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, int64_t ci0, int64_t ci1) {
-  extern __shared__ __align__(16) unsigned char lds_bytes[];
-  __shared__ BlockScratch<real> sh;
+__device__ __forceinline__ void collide_cell_item(const DevPtrs<real> &d, int src, int64_t item,
+                                                  unsigned char *lds_bytes, BlockScratch<real> &sh) {
   constexpr int CAP = CollideCap<real>::value;
   const int tid = threadIdx.x;
-  const int64_t item = ci0 + xcd_block(blockIdx.x, gridDim.x);
-  if (item >= ci1) return;
   const int2 it = d.cell_items[item];
   const RunDev &R = d.runs[it.x];
   const int32_t c = it.y;
@@ -2034,9 +2196,14 @@ __global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, 
   real *sv = su + CAP, *sw = sv + CAP;
   int32_t *own = (int32_t *)(sw + CAP);
   const Particles<real> A = d.P[src], B = d.P[1 - src];
-  const int64_t b0 = d.bin_start[R.bo + c];
-  const int64_t n = (int64_t)d.bin_start[R.bo + c + 1] - b0;
+  const int64_t b0 = d.bin_start[R.bo + (int64_t)c * R.S];
+  const int64_t n = (int64_t)d.bin_start[R.bo + (int64_t)(c + 1) * R.S] - b0;
   const bool in_lds = n <= CAP;
+  SubCells sub;
+  if (R.S > 1) {
+    sub.start = d.bin_start + R.bo + (int64_t)c * R.S;
+    sub.base = (uint32_t)b0;
+  }
   // cell state and step facts are loaded up front, their latency hidden
   // behind the gather
   const uint32_t step = *d.step;
@@ -2090,10 +2257,10 @@ __global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, 
   const auto gw = w_view<DIM>(B, R.so + b0);
   uint32_t ncol = 0;
   if (in_lds) {
-    ncol = chain_block<real>(R, step, (uint32_t)c, (uint32_t)n, nsel, su, sv, sw, own, sh, gm);
+    ncol = chain_block<real>(R, step, (uint32_t)c, (uint32_t)n, nsel, su, sv, sw, own, sh, gm, sub);
   } else {
     if (tid == 0) {
-      ncol = chain_serial<real>(R, step, (uint32_t)c, (uint32_t)n, 0, nsel, gu, gv, gw, gm);
+      ncol = chain_serial<real>(R, step, (uint32_t)c, (uint32_t)n, 0, nsel, gu, gv, gw, gm, sub);
       sh.gm = gm;
     }
     __syncthreads();
@@ -2139,6 +2306,41 @@ __global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, 
   }
 }
 
+// A workgroup's next draw: thread 0 issues it (into a register) and, after
+// the current draw's items, publishes it; the block reads it.
+__device__ __forceinline__ Draw sched_publish(const Draw &mine, Draw *slot) {
+  if (threadIdx.x == 0) *slot = mine;
+  __syncthreads();
+  const Draw d = *slot;
+  __syncthreads();  // every thread has it before thread 0 publishes again
+  return d;
+}
+
+template <typename real, int DIM, bool PERSIST>
+__global__ __launch_bounds__(256) void k_collide_cell(DevPtrs<real> d, int src, int64_t ci0, int64_t ci1, Sched sc) {
+  extern __shared__ __align__(16) unsigned char lds_bytes[];
+  __shared__ BlockScratch<real> sh;
+  __shared__ Draw next;
+  if constexpr (!PERSIST) {
+    const int64_t item = ci0 + xcd_block(blockIdx.x, gridDim.x);
+    if (item < ci1) collide_cell_item<real, DIM>(d, src, item, lds_bytes, sh);
+    return;
+  }
+  int x = sched_start(sc, (int)blockIdx.x), tries = 0;
+  Draw mine{ci1, ci1};
+  if (threadIdx.x == 0) mine = sched_draw(sc, ci0, ci1, (int)gridDim.x, x, tries);
+  Draw cur = sched_publish(mine, &next);
+  while (cur.first < ci1) {
+    // the next draw goes out before this one's items, so its latency overlaps them
+    if (threadIdx.x == 0) mine = sched_draw(sc, ci0, ci1, (int)gridDim.x, x, tries);
+    for (int64_t item = cur.first; item < cur.end; ++item) {
+      collide_cell_item<real, DIM>(d, src, item, lds_bytes, sh);
+      __syncthreads();  // LDS and the scratch are free again
+    }
+    cur = sched_publish(mine, &next);
+  }
+}
+
 // Cells of a few hundred particles: one wavefront per cell, four cells per
 // block.  The wavefront gathers its cell through LCR (positions to P',
 // velocities to its LDS stage), runs the same collision chain as the block
@@ -2149,23 +2351,32 @@ template <typename real> struct WaveCap;
 template <> struct WaveCap<float> { static constexpr int value = kWaveCapF32; };
 template <> struct WaveCap<double> { static constexpr int value = kWaveCapF64; };
 
-template <typename real, int DIM>
-__global__ __launch_bounds__(256) void k_collide_wave(DevPtrs<real> d, int src, int64_t wi0, int64_t wi1) {
+template <typename real> struct WaveStage {
+  real vel[kWavesPerBlock][3 * WaveCap<real>::value];
+  int32_t own[kWavesPerBlock][WaveCap<real>::value];
+  BlockScratch<real> shs[kWavesPerBlock];
+};
+
+template <typename real, int DIM, bool SUB>
+__device__ __forceinline__ void collide_wave_item(const DevPtrs<real> &d, int src, int64_t item,
+                                                  WaveStage<real> &st) {
   constexpr int CAP = WaveCap<real>::value;
-  __shared__ __align__(16) real vel[kWavesPerBlock][3 * CAP];
-  __shared__ int32_t own[kWavesPerBlock][CAP];
-  __shared__ BlockScratch<real> shs[kWavesPerBlock];
+  auto &own = st.own;
+  auto &shs = st.shs;
   const int wave = wave_index(), lane = threadIdx.x & 63;
-  const int64_t item = wi0 + xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wave;
-  if (item >= wi1) return;
   const int2 it = d.wave_items[item];
   const RunDev &R = d.runs[it.x];
   const int32_t c = it.y;
   const int64_t gc = R.co + c;
-  const int64_t b0 = d.bin_start[R.bo + c];
-  const int64_t n = (int64_t)d.bin_start[R.bo + c + 1] - b0;
+  const int64_t b0 = d.bin_start[R.bo + (int64_t)c * R.S];
+  const int64_t n = (int64_t)d.bin_start[R.bo + (int64_t)(c + 1) * R.S] - b0;
   const bool in_lds = n <= CAP;
-  real *su = vel[wave], *sv = su + CAP, *sw = sv + CAP;
+  SubCells sub;
+  if (SUB && R.S > 1) {
+    sub.start = d.bin_start + R.bo + (int64_t)c * R.S;
+    sub.base = (uint32_t)b0;
+  }
+  real *su = st.vel[wave], *sv = su + CAP, *sw = sv + CAP;
   const Particles<real> A = d.P[src], B = d.P[1 - src];
   constexpr int NH = (CAP + 4 * kWave - 1) / (4 * kWave) * 4;
   real hx[NH], hy[NH], hz[NH];
@@ -2180,22 +2391,46 @@ __global__ __launch_bounds__(256) void k_collide_wave(DevPtrs<real> d, int src, 
   uint32_t ncol = 0;
   if (in_lds) {
     ncol = chain_block<real, WaveSync>(R, step, (uint32_t)c, (uint32_t)n, nsel, su, sv, sw, own[wave], shs[wave],
-                                       gm);
+                                       gm, sub);
     WaveSync::bar();
-    write_back_held<real, DIM, NH>(R, B, d.cell, b0, n, su, sv, sw, hx, hy, hz);
+    write_back_held<real, DIM, NH, SUB>(R, B, d.cell, b0, n, su, sv, sw, hx, hy, hz);
     if (sample) sample_cell_wave(su, sv, sw, n, d.stage + gc * kFields);
   } else {
     const int64_t o = R.so + b0;
     if (lane == 0)
-      ncol = chain_serial<real>(R, step, (uint32_t)c, (uint32_t)n, 0, nsel, B.u() + o, B.v() + o, w_view<DIM>(B, o), gm);
+      ncol = chain_serial<real>(R, step, (uint32_t)c, (uint32_t)n, 0, nsel, B.u() + o, B.v() + o, w_view<DIM>(B, o), gm,
+                                sub);
     global_sync_wave();
-    if (R.ahead) next_cells<real, DIM>(R, B, d.cell, b0, n, lane, kWave);
+    if (R.ahead) next_cells<real, DIM, SUB>(R, B, d.cell, b0, n, lane, kWave);
     if (sample) sample_cell_wave(B.u() + o, B.v() + o, w_view<DIM>(B, o), n, d.stage + gc * kFields);
   }
   if (lane == 0) {
     d.gmax[gc] = gm;
     d.rem_c[gc] = rem;
     d.ncoll[gc] += ncol;
+  }
+}
+
+template <typename real, int DIM, bool PERSIST, bool SUB>
+__global__ __launch_bounds__(256) void k_collide_wave(DevPtrs<real> d, int src, int64_t wi0, int64_t wi1, Sched sc) {
+  __shared__ __align__(16) WaveStage<real> st;
+  const int wave = wave_index();
+  if constexpr (!PERSIST) {
+    const int64_t item = wi0 + xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wave;
+    if (item < wi1) collide_wave_item<real, DIM, SUB>(d, src, item, st);
+    return;
+  }
+  const int units = (int)gridDim.x * kWavesPerBlock;
+  int x = sched_start(sc, (int)blockIdx.x * kWavesPerBlock + wave), tries = 0;
+  Draw cur = sched_next_wave(sc, wi0, wi1, units, x, tries);
+  while (cur.first < wi1) {
+    // the next draw goes out before this one's items, so its latency overlaps them
+    const Draw nxt = sched_next_wave(sc, wi0, wi1, units, x, tries);
+    for (int64_t item = cur.first; item < cur.end; ++item) {
+      collide_wave_item<real, DIM, SUB>(d, src, item, st);
+      wave_sync();  // the wavefront's stage is free again
+    }
+    cur = nxt;
   }
 }
 
@@ -2224,6 +2459,7 @@ struct RunView {
 
 struct PipeMeta {
   int64_t so, b0, n, gc;
+  const uint32_t *sub_start;  // the cell's sub-cell bin starts, null without sub-cells
   int32_t c;
   uint32_t ncoll;
   float gm, rem, dt;
@@ -2317,10 +2553,13 @@ __device__ __forceinline__ void pipe_place(const PipeMeta &m, const PipeRegs &pr
 // Collisions, write-back (with the next step's flight cells), sampling and
 // cell state of one item whose data is in place (LDS su/sv/sw, or P' for an
 // item beyond the LDS capacity).
-template <int DIM>
+// SUB: some run of the batch has sub-cells (a separate instantiation: the
+// sub-cell search would cost the plain kernel registers).
+template <int DIM, bool SUB>
 __device__ __forceinline__ void pipe_collide(const DevPtrs<float> &d, const Particles<float> &B, const PipeMeta &m,
-                                             const PipePos &pp, float *su, float *sv, float *sw, int32_t *own,
-                                             BlockScratch<float> &sh, uint32_t step, bool sample) {
+                                             const Flight<float> &fl, const PipePos &pp, float *su, float *sv,
+                                             float *sw, int32_t *own, BlockScratch<float> &sh, uint32_t step,
+                                             bool sample) {
   const int tid = threadIdx.x;
   const int64_t n = m.n;
   const bool lds = n <= kCollideCapF32;
@@ -2330,11 +2569,13 @@ __device__ __forceinline__ void pipe_collide(const DevPtrs<float> &d, const Part
   const Strided<float> gu = B.u() + (m.so + m.b0), gv = B.v() + (m.so + m.b0);
   const auto gw = w_view<DIM>(B, m.so + m.b0);
   if (lds) {
-    ncol = chain_block<float, LdsSync>(m.rv, step, (uint32_t)m.c, (uint32_t)n, nsel, su, sv, sw, own, sh, gm);
+    ncol = chain_block<float, LdsSync>(m.rv, step, (uint32_t)m.c, (uint32_t)n, nsel, su, sv, sw, own, sh, gm,
+                                       SUB ? SubCells{m.sub_start, (uint32_t)m.b0} : SubCells{});
   } else {
     __syncthreads();  // every thread's stores to P' are visible
     if (tid == 0) {
-      ncol = chain_serial<float>(m.rv, step, (uint32_t)m.c, (uint32_t)n, 0, nsel, gu, gv, gw, gm);
+      ncol = chain_serial<float>(m.rv, step, (uint32_t)m.c, (uint32_t)n, 0, nsel, gu, gv, gw, gm,
+                                 SUB ? SubCells{m.sub_start, (uint32_t)m.b0} : SubCells{});
       sh.gm = gm;
     }
     __syncthreads();
@@ -2343,8 +2584,9 @@ __device__ __forceinline__ void pipe_collide(const DevPtrs<float> &d, const Part
   LdsSync::bar();
   if (lds) {
     // whole records from the positions this thread placed (still in its
-    // registers) and the final velocities, and the look-ahead
-    const Flight<float> F(*m.run);
+    // registers) and the final velocities, and the look-ahead (the run's
+    // flight constants from LDS, where the item's bookkeeping put them)
+    const Flight<float> F = fl;
     const int64_t base = m.so + m.b0;
 #pragma unroll
     for (int q = 0; q < kPipeChunks; ++q) {
@@ -2355,12 +2597,12 @@ __device__ __forceinline__ void pipe_collide(const DevPtrs<float> &d, const Part
         if (m.ahead) {
           const float pos[3] = {pp.x[q], pp.y[q], pp.z[q]};
           const float vel[3] = {su[k], sv[k], sw[k]};
-          d.cell[base + k] = flight_cell<float, DIM>(F, pos, vel);
+          d.cell[base + k] = flight_cell<float, DIM, SUB>(F, pos, vel);
         }
       }
     }
   } else if (m.ahead) {
-    next_cells<float, DIM>(*m.run, B, d.cell, m.b0, n, tid, 256);
+    next_cells<float, DIM, SUB>(*m.run, B, d.cell, m.b0, n, tid, 256);
   }
   if (sample) {
     // LDS and global are summed by separate loops: a pointer to either would
@@ -2398,16 +2640,15 @@ __device__ __forceinline__ void pipe_collide(const DevPtrs<float> &d, const Part
   LdsSync::bar();  // LDS, own[] and sh are free again
 }
 
-template <int DIM>
-__device__ __forceinline__ void collide_pipe_body(DevPtrs<float> d, int src, int64_t ci0, int64_t ci1) {
+template <int DIM, bool SUB>
+__device__ __forceinline__ void collide_pipe_body(const DevPtrs<float> &d, int src, int64_t item) {
   constexpr int CAP = kCollideCapF32;
   __shared__ __align__(16) float vel[3 * CAP];
   __shared__ int32_t own[CAP];
   __shared__ PipeMeta meta;
+  __shared__ Flight<float> flight;
   __shared__ BlockScratch<float> sh;
   const int tid = threadIdx.x;
-  const int64_t item = ci0 + xcd_block(blockIdx.x, gridDim.x);
-  if (item >= ci1) return;
   const Particles<float> A = d.P[src], B = d.P[1 - src];
   const uint32_t step = *d.step;
   const bool sample = *d.sample_slot >= 0;
@@ -2418,8 +2659,9 @@ __device__ __forceinline__ void collide_pipe_body(DevPtrs<float> d, int src, int
     PipeMeta m;
     m.so = R.so;
     m.c = it.y;
-    m.b0 = d.bin_start[R.bo + it.y];
-    m.n = (int64_t)d.bin_start[R.bo + it.y + 1] - m.b0;
+    m.b0 = d.bin_start[R.bo + (int64_t)it.y * R.S];
+    m.n = (int64_t)d.bin_start[R.bo + (int64_t)(it.y + 1) * R.S] - m.b0;
+    m.sub_start = R.S > 1 ? d.bin_start + R.bo + (int64_t)it.y * R.S : nullptr;
     m.gc = R.co + it.y;
     m.ncoll = d.ncoll[m.gc];
     m.gm = d.gmax[m.gc];
@@ -2434,6 +2676,7 @@ __device__ __forceinline__ void collide_pipe_body(DevPtrs<float> d, int src, int
     m.rv.vhs_exp = R.vhs_exp;
     m.rv.coef = R.coef;
     meta = m;
+    flight = Flight<float>(R);
   }
   __syncthreads();
   const PipeMeta m = meta;
@@ -2445,24 +2688,62 @@ __device__ __forceinline__ void collide_pipe_body(DevPtrs<float> d, int src, int
   pipe_place<DIM>(m, pr, vel, vel + CAP, vel + 2 * CAP, pp);
   if (m.n > CAP) __threadfence_block();
   LdsSync::bar();
-  pipe_collide<DIM>(d, B, m, pp, vel, vel + CAP, vel + 2 * CAP, own, sh, step, sample);
+  pipe_collide<DIM, SUB>(d, B, m, flight, pp, vel, vel + CAP, vel + 2 * CAP, own, sh, step, sample);
 }
 
 // The kernel per dimension.  The 2-D one asks for six wavefronts per SIMD
 // (80 VGPRs): the compiler fits that with no scratch, and with the gather
 // bound by requests in flight it runs 10 % faster than at five (86 VGPRs).
 // The 3-D one would spill at six and keeps the compiler's choice.
-template <int DIM>
-__global__ void k_collide_pipe(DevPtrs<float> d, int src, int64_t ci0, int64_t ci1);
+template <int DIM, bool PERSIST, bool SUB>
+__device__ __forceinline__ void collide_pipe_sched(const DevPtrs<float> &d, int src, int64_t ci0, int64_t ci1,
+                                                   const Sched &sc) {
+  __shared__ Draw next;
+  if constexpr (!PERSIST) {
+    const int64_t item = ci0 + xcd_block(blockIdx.x, gridDim.x);
+    if (item < ci1) collide_pipe_body<DIM, SUB>(d, src, item);
+    return;
+  }
+  int x = sched_start(sc, (int)blockIdx.x), tries = 0;
+  Draw mine{ci1, ci1};
+  if (threadIdx.x == 0) mine = sched_draw(sc, ci0, ci1, (int)gridDim.x, x, tries);
+  Draw cur = sched_publish(mine, &next);
+  while (cur.first < ci1) {
+    // the next draw goes out before this one's items, so its latency overlaps them
+    if (threadIdx.x == 0) mine = sched_draw(sc, ci0, ci1, (int)gridDim.x, x, tries);
+    for (int64_t item = cur.first; item < cur.end; ++item)
+      collide_pipe_body<DIM, SUB>(d, src, item);  // ends with a barrier: LDS is free again
+    cur = sched_publish(mine, &next);
+  }
+}
+
+template <int DIM, bool PERSIST, bool SUB>
+__global__ void k_collide_pipe(DevPtrs<float> d, int src, int64_t ci0, int64_t ci1, Sched sc);
 template <>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_collide_pipe<2>(
-    DevPtrs<float> d, int src, int64_t ci0, int64_t ci1) {
-  collide_pipe_body<2>(d, src, ci0, ci1);
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_collide_pipe<2, false, false>(
+    DevPtrs<float> d, int src, int64_t ci0, int64_t ci1, Sched sc) {
+  collide_pipe_sched<2, false, false>(d, src, ci0, ci1, sc);
 }
 template <>
-__global__ __launch_bounds__(256) void k_collide_pipe<3>(DevPtrs<float> d, int src, int64_t ci0, int64_t ci1) {
-  collide_pipe_body<3>(d, src, ci0, ci1);
+__global__ __launch_bounds__(256) void k_collide_pipe<3, false, false>(DevPtrs<float> d, int src, int64_t ci0,
+                                                                       int64_t ci1, Sched sc) {
+  collide_pipe_sched<3, false, false>(d, src, ci0, ci1, sc);
 }
+// the persistent loop's state, or the sub-cell search, does not fit six
+// wavefronts per SIMD without spilling: the compiler's choice
+#define DSMC_PIPE_KERNEL(D, P, S)                                                                              \
+  template <>                                                                                                  \
+  __global__ __launch_bounds__(256) void k_collide_pipe<D, P, S>(DevPtrs<float> d, int src, int64_t ci0,      \
+                                                                 int64_t ci1, Sched sc) {                      \
+    collide_pipe_sched<D, P, S>(d, src, ci0, ci1, sc);                                                         \
+  }
+DSMC_PIPE_KERNEL(2, true, false)
+DSMC_PIPE_KERNEL(3, true, false)
+DSMC_PIPE_KERNEL(2, false, true)
+DSMC_PIPE_KERNEL(3, false, true)
+DSMC_PIPE_KERNEL(2, true, true)
+DSMC_PIPE_KERNEL(3, true, true)
+#undef DSMC_PIPE_KERNEL
 
 template <typename real>
 __global__ __launch_bounds__(256) void k_sample_cells(DevPtrs<real> d, int buf, int64_t n_cells) {
@@ -2471,8 +2752,8 @@ __global__ __launch_bounds__(256) void k_sample_cells(DevPtrs<real> d, int buf, 
   const RunDev &R = d.runs[d.cgroup_run[gc >> 6]];
   const int32_t c = (int32_t)(gc - R.co);
   if (c >= R.nc) return;
-  const int64_t b = d.bin_start[R.bo + c];
-  const int64_t N = (int64_t)d.bin_start[R.bo + c + 1] - b;
+  const int64_t b = d.bin_start[R.bo + (int64_t)c * R.S];
+  const int64_t N = (int64_t)d.bin_start[R.bo + (int64_t)(c + 1) * R.S] - b;
   const Particles<real> P = d.P[buf];
   if (P.zw)
     sample_cell(P.u() + (R.so + b), P.v() + (R.so + b), w_view<3>(P, R.so + b), N, d.stage + gc * kFields);
@@ -2741,11 +3022,37 @@ void launch_init(const Geometry &g, const DevPtrs<real> &d, hipStream_t s) {
   launch_next_cells<real>(g, d, 0, 0, g.n_slots, s);
 }
 
+// The work distribution of interaction mode m (0 lane, 1 wave, 2 cell items)
+// in lane L.
+template <typename real>
+static Sched sched_of(const Geometry &g, const DevPtrs<real> &d, int m, const LaneRange &L, int lane_id) {
+  Sched sc{};
+  sc.mode = g.sched;
+  if (g.sched == kSchedQueue) {
+    sc.ctr = d.sched_ctr + ((int64_t)m * kMaxLanes + lane_id) * kXcds;
+  } else if (g.sched == kSchedPerRun) {
+    sc.ctr = d.sched_ctr + g.sched_ctr_off[m] + L.sr0[m];
+    sc.first = d.sched_first + g.sched_first_off[m] + L.sr0[m];
+    sc.nr = L.sr1[m] - L.sr0[m];
+  }
+  return sc;
+}
+
+// Workgroups of a launch: one per `per` items on the grid; the persistent
+// grid of mode m otherwise (per-run scheduling: at least one workgroup, or
+// wavefront, per run).
+static int64_t sched_grid(const Geometry &g, const Sched &sc, int m, int64_t grid_blocks, int per) {
+  if (sc.mode == kSchedGrid) return grid_blocks;
+  const int64_t b = std::max<int64_t>(1, g.sched_blocks[m]);
+  if (sc.mode == kSchedPerRun) return std::max<int64_t>(b, (sc.nr + per - 1) / per);
+  return std::min<int64_t>(b, grid_blocks);  // never more workgroups than items
+}
+
 // One lane's share of a step: Generation, Motion, Indexing and Interaction of
 // the runs [L.r0, L.r1) on stream s.  `moved` (may be null) is recorded once
 // Motion is complete.
 template <typename real, int DIM>
-static void lane_step(const Geometry &g, const LaneRange &L, const DevPtrs<real> &d, int buf, hipStream_t s,
+static void lane_step(const Geometry &g, const LaneRange &L, int lane_id, const DevPtrs<real> &d, int buf, hipStream_t s,
                       hipEvent_t moved, const Prof *prof) {
   const int n_runs = L.r1 - L.r0;
   const int32_t n_tiles = L.t1 - L.t0;
@@ -2771,7 +3078,7 @@ static void lane_step(const Geometry &g, const LaneRange &L, const DevPtrs<real>
     TIMED(kKMotionWalls, hipLaunchKernelGGL((k_motion_walls<real, DIM, true>), dim3(n_tiles), dim3(256), 0, s, d,
                                             buf, L.t0, L.t1, g.tile, 0));
     if (moved) (void)hipEventRecord(moved, s);
-    index_pass(a, g.max_nc + 1, n_runs, 0, nullptr, d.lcr, s, prof);
+    index_pass(a, g.max_nbin + 1, n_runs, 0, nullptr, d.lcr, s, prof);
   } else {
     // the first digit: the bucket (two-level sort) or the lowest 11 bits
     const int shift0 = g.bucketed ? kDigitBits : 0;
@@ -2800,7 +3107,7 @@ static void lane_step(const Geometry &g, const LaneRange &L, const DevPtrs<real>
       TIMED(kKBucketItems, hipLaunchKernelGGL(k_bucket_items, dim3(n_runs), dim3(256), 0, s, a));
       if (iblocks > 0) {
         TIMED(kKDigCount, hipLaunchKernelGGL(k_digcount_bucket, dim3(iblocks), dim3(256), lds, s, a));
-        const int max_nb = (g.max_nc >> kDigitBits) + 1;
+        const int max_nb = (g.max_nbin >> kDigitBits) + 1;
         TIMED(kKBucketScan, hipLaunchKernelGGL(k_bucket_scan, dim3(max_nb, n_runs), dim3(256), 0, s, a));
         // at most three blocks per CU (LDS beyond the cursor tables is
         // unused): with fewer wavefronts writing scattered stretches of the
@@ -2837,24 +3144,68 @@ static void lane_step(const Geometry &g, const LaneRange &L, const DevPtrs<real>
   }
   if (L.it1 > L.it0) {
     const int64_t nblk = (L.it1 - L.it0 + kCollideWaves - 1) / kCollideWaves;
-    TIMED(kKCollide, hipLaunchKernelGGL((k_collide<real, DIM>), dim3((unsigned)nblk), dim3(kCollideWaves * 64),
-                                        (size_t)kCollideWaves * collide_wave_bytes<real>(), s, d, buf, L.it0,
-                                        L.it1));
+    const Sched sc = sched_of(g, d, 0, L, lane_id);
+    const int64_t grid = sched_grid(g, sc, 0, nblk, kCollideWaves);
+    const size_t lb = (size_t)kCollideWaves * collide_wave_bytes<real>();
+    const dim3 gr((unsigned)grid), bl(kCollideWaves * 64);
+    if (sc.mode == kSchedGrid && !g.any_sub)
+      TIMED(kKCollide, hipLaunchKernelGGL((k_collide<real, DIM, false, false>), gr, bl, lb, s, d, buf, L.it0, L.it1,
+                                          sc));
+    else if (sc.mode == kSchedGrid)
+      TIMED(kKCollide, hipLaunchKernelGGL((k_collide<real, DIM, false, true>), gr, bl, lb, s, d, buf, L.it0, L.it1,
+                                          sc));
+    else if (!g.any_sub)
+      TIMED(kKCollide, hipLaunchKernelGGL((k_collide<real, DIM, true, false>), gr, bl, lb, s, d, buf, L.it0, L.it1,
+                                          sc));
+    else
+      TIMED(kKCollide, hipLaunchKernelGGL((k_collide<real, DIM, true, true>), gr, bl, lb, s, d, buf, L.it0, L.it1,
+                                          sc));
   }
   if (L.wi1 > L.wi0) {
     const int64_t nblk = (L.wi1 - L.wi0 + kWavesPerBlock - 1) / kWavesPerBlock;
-    TIMED(kKCollideWave, hipLaunchKernelGGL((k_collide_wave<real, DIM>), dim3((unsigned)nblk), dim3(256), 0, s, d,
-                                            buf, L.wi0, L.wi1));
+    const Sched sc = sched_of(g, d, 1, L, lane_id);
+    const int64_t grid = sched_grid(g, sc, 1, nblk, kWavesPerBlock);
+    const dim3 gr((unsigned)grid), bl(256);
+    if (sc.mode == kSchedGrid && !g.any_sub)
+      TIMED(kKCollideWave, hipLaunchKernelGGL((k_collide_wave<real, DIM, false, false>), gr, bl, 0, s, d, buf, L.wi0,
+                                              L.wi1, sc));
+    else if (sc.mode == kSchedGrid)
+      TIMED(kKCollideWave, hipLaunchKernelGGL((k_collide_wave<real, DIM, false, true>), gr, bl, 0, s, d, buf, L.wi0,
+                                              L.wi1, sc));
+    else if (!g.any_sub)
+      TIMED(kKCollideWave, hipLaunchKernelGGL((k_collide_wave<real, DIM, true, false>), gr, bl, 0, s, d, buf, L.wi0,
+                                              L.wi1, sc));
+    else
+      TIMED(kKCollideWave, hipLaunchKernelGGL((k_collide_wave<real, DIM, true, true>), gr, bl, 0, s, d, buf, L.wi0,
+                                              L.wi1, sc));
   }
   if (L.ci1 > L.ci0) {
+    const int64_t nblk = L.ci1 - L.ci0;
+    const Sched sc = sched_of(g, d, 2, L, lane_id);
+    const int64_t grid = sched_grid(g, sc, 2, nblk, 1);
+    const bool grid_mode = sc.mode == kSchedGrid;
     if constexpr (std::is_same<real, float>::value) {
-      const int64_t nblk = L.ci1 - L.ci0;
-      TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_pipe<DIM>), dim3((unsigned)nblk), dim3(256), 0, s, d, buf,
-                                              L.ci0, L.ci1));
+      const dim3 gr((unsigned)grid), bl(256);
+      if (grid_mode && !g.any_sub)
+        TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_pipe<DIM, false, false>), gr, bl, 0, s, d, buf, L.ci0,
+                                                L.ci1, sc));
+      else if (grid_mode)
+        TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_pipe<DIM, false, true>), gr, bl, 0, s, d, buf, L.ci0,
+                                                L.ci1, sc));
+      else if (!g.any_sub)
+        TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_pipe<DIM, true, false>), gr, bl, 0, s, d, buf, L.ci0,
+                                                L.ci1, sc));
+      else
+        TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_pipe<DIM, true, true>), gr, bl, 0, s, d, buf, L.ci0,
+                                                L.ci1, sc));
     } else {
-      TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_cell<real, DIM>), dim3((unsigned)(L.ci1 - L.ci0)),
-                                              dim3(256), (size_t)collide_cell_bytes<real>(), s, d, buf, L.ci0,
-                                              L.ci1));
+      const size_t cb = (size_t)collide_cell_bytes<real>();
+      if (grid_mode)
+        TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_cell<real, DIM, false>), dim3((unsigned)grid), dim3(256),
+                                                cb, s, d, buf, L.ci0, L.ci1, sc));
+      else
+        TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_cell<real, DIM, true>), dim3((unsigned)grid), dim3(256),
+                                                cb, s, d, buf, L.ci0, L.ci1, sc));
     }
   }
 }
@@ -2864,6 +3215,8 @@ static void step_dim(const Geometry &g, const DevPtrs<real> &d, int buf, hipStre
                      const Prof *prof) {
   TIMED(kKStepBegin, hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(1), 0, s, d.step, d.sample_slot,
                                         d.sample_steps, g.n_samples, g.window_steps, g.window_stride));
+  if (g.sched != kSchedGrid)  // the persistent grids' work counters start at zero every step
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(g.n_sched_ctr)), dim3(256), 0, s, d.sched_ctr, g.n_sched_ctr, 0u);
   if (g.n_lanes <= 1 || !ls) {
     LaneRange all = g.lane[0];
     if (g.n_lanes > 1) {
@@ -2876,15 +3229,16 @@ static void step_dim(const Geometry &g, const DevPtrs<real> &d, int buf, hipStre
       all.ci1 = g.lane[g.n_lanes - 1].ci1;
       all.wi1 = g.lane[g.n_lanes - 1].wi1;
       all.b1 = g.lane[g.n_lanes - 1].b1;
+      for (int m = 0; m < 3; ++m) all.sr1[m] = g.lane[g.n_lanes - 1].sr1[m];
     }
-    lane_step<real, DIM>(g, all, d, buf, s, nullptr, prof);
+    lane_step<real, DIM>(g, all, 0, d, buf, s, nullptr, prof);
   } else {
     (void)hipEventRecord(ls->fork, s);
     for (int l = 0; l < g.n_lanes; ++l) {
       hipStream_t q = ls->s[l];
       (void)hipStreamWaitEvent(q, ls->fork, 0);
       if (l > 0) (void)hipStreamWaitEvent(q, ls->moved[l - 1], 0);
-      lane_step<real, DIM>(g, g.lane[l], d, buf, q, ls->moved[l], prof);
+      lane_step<real, DIM>(g, g.lane[l], l, d, buf, q, ls->moved[l], prof);
       (void)hipEventRecord(ls->done[l], q);
     }
     for (int l = 0; l < g.n_lanes; ++l) (void)hipStreamWaitEvent(s, ls->done[l], 0);
@@ -2920,6 +3274,34 @@ template <typename real>
 void launch_diag(const Geometry &g, const DevPtrs<real> &d, int buf, hipStream_t s) {
   if (g.dim == 3) hipLaunchKernelGGL((k_diag<real, 3>), dim3(g.n_runs), dim3(256), 0, s, d, buf);
   else hipLaunchKernelGGL((k_diag<real, 2>), dim3(g.n_runs), dim3(256), 0, s, d, buf);
+}
+
+template <typename real, int DIM, bool SUB>
+static void occupancy_dim(int out[3]) {
+  auto occ = [](const void *k, int threads, size_t lds) {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, threads, lds) != hipSuccess) b = 1;
+    return b > 0 ? b : 1;
+  };
+  out[0] = occ(reinterpret_cast<const void *>(&k_collide<real, DIM, true, SUB>), kCollideWaves * 64,
+               (size_t)kCollideWaves * collide_wave_bytes<real>());
+  out[1] = occ(reinterpret_cast<const void *>(&k_collide_wave<real, DIM, true, SUB>), 256, 0);
+  if constexpr (std::is_same<real, float>::value)
+    out[2] = occ(reinterpret_cast<const void *>(&k_collide_pipe<DIM, true, SUB>), 256, 0);
+  else
+    out[2] = occ(reinterpret_cast<const void *>(&k_collide_cell<real, DIM, true>), 256,
+                 (size_t)collide_cell_bytes<real>());
+}
+
+// Workgroups per CU of the persistent Interaction kernels the batch launches.
+void collide_occupancy(const Geometry &g, int out[3]) {
+  if (g.fp64) {
+    if (g.dim == 3) g.any_sub ? occupancy_dim<double, 3, true>(out) : occupancy_dim<double, 3, false>(out);
+    else g.any_sub ? occupancy_dim<double, 2, true>(out) : occupancy_dim<double, 2, false>(out);
+  } else {
+    if (g.dim == 3) g.any_sub ? occupancy_dim<float, 3, true>(out) : occupancy_dim<float, 3, false>(out);
+    else g.any_sub ? occupancy_dim<float, 2, true>(out) : occupancy_dim<float, 2, false>(out);
+  }
 }
 
 template void launch_init<float>(const Geometry &, const DevPtrs<float> &, hipStream_t);
@@ -3011,6 +3393,9 @@ void launch_counting_sort(const int32_t *keys, int64_t n, int32_t nbins, int32_t
   rd.so = 0;
   rd.cap = (int64_t)L.nt * L.tile;
   rd.nc = nbins - 1;
+  rd.nbin = nbins - 1;
+  rd.sub = 1;
+  rd.S = 1;
   rd.nt = L.nt;
   RunDev *runs = (RunDev *)(w + L.off_run);
   int32_t *tile_run = (int32_t *)(w + L.off_tile_run);

@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported(dsmc):
 def test_struct_sizes_match_header(dsmc):
     # layout of the two public structs (x86-64 SysV ABI)
     assert C.sizeof(dsmc.dsmc_run_spec) == 248
-    assert C.sizeof(dsmc.dsmc_options) == 48
+    assert C.sizeof(dsmc.dsmc_options) == 56
 
 
 def test_array_lengths_match_header(dsmc):
@@ -129,10 +129,13 @@ def test_init_rejects_before_touching_the_device(dsmc):
 def test_obstacle_specs(dsmc):
     """Solid masks are sized into the arena and validated on the host."""
     from dataclasses import replace
+    # masks of 2 x 2M cells: larger than the 2 MiB alignment of the arena's
+    # large arrays, so the difference shows
+    big = W.body3d(n_runs=2, grid=(200, 100, 100), n_per_run=100_000, n_steps=1, n_samples=1)
+    with_mask = _bytes(dsmc, big)
+    without = _bytes(dsmc, big.with_runs([replace(r, solid=None) for r in big.runs]))
+    assert with_mask - without >= 2 * 200 * 100 * 100 - (2 << 20)
     wl = W.body3d(n_runs=2, grid=(40, 20, 20), n_per_run=100_000, n_steps=1, n_samples=1)
-    with_mask = _bytes(dsmc, wl)
-    without = _bytes(dsmc, wl.with_runs([replace(r, solid=None) for r in wl.runs]))
-    assert with_mask - without >= 2 * 40 * 20 * 20
     bad_T = replace(wl.runs[0], solid_T=0.0)
     with pytest.raises(dsmc.DsmcError) as e:
         _bytes(dsmc, wl.with_runs([bad_T]))
@@ -144,6 +147,25 @@ def test_obstacle_specs(dsmc):
     assert e.value.status == -1
     with pytest.raises(dsmc.DsmcError):
         dsmc.make_run_spec(replace(wl.runs[0], solid=m[:, :, :5]))
+
+
+def test_subcell_specs(dsmc):
+    """Sub-cells: 0..4 per axis; the LCR and bin starts are sized by bin
+    (cells x k^dim); a body with sub-cells is refused as unsupported."""
+    from dataclasses import replace
+    wl = W.plain_box()
+    plain = _bytes(dsmc, wl)
+    sub = _bytes(dsmc, wl.with_runs([replace(wl.runs[0], subcells=4)]))
+    assert sub - plain >= 4 * 32 * 32 * 15
+    assert _bytes(dsmc, wl.with_runs([replace(wl.runs[0], subcells=1)])) == plain
+    for k in (-1, 5):
+        with pytest.raises(dsmc.DsmcError) as e:
+            _bytes(dsmc, wl.with_runs([replace(wl.runs[0], subcells=k)]))
+        assert e.value.status == -1
+    body = W.body3d(n_runs=1, grid=(20, 10, 10), n_per_run=10_000, n_steps=1, n_samples=1)
+    with pytest.raises(dsmc.DsmcError) as e:
+        _bytes(dsmc, body.with_runs([replace(body.runs[0], subcells=2)]))
+    assert e.value.status == -6
 
 
 def test_autotune_workspace_covers_every_candidate(dsmc):
@@ -160,9 +182,9 @@ def test_autotune_workspace_covers_every_candidate(dsmc):
                 assert dsmc.dsmc_required_bytes(specs, o) <= tune
     # argument errors before any device work
     best = dsmc.dsmc_options()
-    assert dsmc.lib().dsmc_autotune(specs, len(specs), C.byref(opt), None, 0, None, 0, C.byref(best),
+    assert dsmc.lib().dsmc_autotune(specs, len(specs), C.byref(opt), None, 0, None, 0, None, C.byref(best),
                                     None) == -1
-    assert dsmc.lib().dsmc_autotune(specs, len(specs), C.byref(opt), None, 0, None, 3, C.byref(best),
+    assert dsmc.lib().dsmc_autotune(specs, len(specs), C.byref(opt), None, 0, None, 3, None, C.byref(best),
                                     None) == -2
 
 

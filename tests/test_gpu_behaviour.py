@@ -128,7 +128,8 @@ def test_autotuned_settings_give_identical_results(dsmc_gpu):
     tuned = dsmc_gpu.Ensemble.autotune(runs, [3, 6], state_fp64=False, n_groups=2, use_graph=True, n_steps=2)
     assert tuned["tile_chunks"] in (64, 128, 256) and tuned["n_streams"] in (1, 2)
     assert tuned["collide_mode"] in (0, 1, 2, 3) and tuned["ms_per_step"] > 0
-    kw = {k: tuned[k] for k in ("tile_chunks", "collide_mode", "n_streams")}
+    assert tuned["sched"] in (0, 1) and tuned["sched_blocks"] in (0, 1024) and not tuned["from_cache"]
+    kw = {k: tuned[k] for k in ("tile_chunks", "collide_mode", "n_streams", "sched", "sched_blocks")}
     A = dsmc_gpu.Ensemble(runs, [3, 6], state_fp64=False, n_groups=2, use_graph=True)
     B = dsmc_gpu.Ensemble(runs, [3, 6], state_fp64=False, n_groups=2, use_graph=True, **kw)
     A.step(6)
@@ -247,3 +248,76 @@ def test_state_round_trip(dsmc_gpu, dim, fp64):
     F.step(2)
     np.testing.assert_array_equal(E.state(1), F.state(1))
     np.testing.assert_array_equal(E.state(0), F.state(0))
+
+
+def _mixed_mode_runs():
+    """Runs whose cells take each Interaction mode (a lane, a wavefront and a
+    block per cell: ~30, ~150 and ~400 particles per cell), plus a channel
+    with inflow, in one batch."""
+    lane = replace(W.box(64 * 30, 1, 1, 1, seed=71, grid=(8, 8)).runs[0], run_id=0, ensemble=0)
+    wave = replace(W.box(64 * 150, 1, 1, 1, seed=72, grid=(8, 8)).runs[0], run_id=1, ensemble=1)
+    cell = replace(W.box(64 * 400, 1, 1, 1, seed=73, grid=(8, 8)).runs[0], run_id=2, ensemble=2)
+    ch = replace(W.channel_run(nx=32, ny=8, lx=2.0, ly=0.5, ppc_inf=30.0, run_id=3, seed=74), ensemble=3)
+    lane2 = replace(lane, run_id=4, ensemble=4)
+    return [lane, wave, cell, ch, lane2]
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+@pytest.mark.parametrize("sched,streams", [(1, 1), (2, 1), (1, 2), (2, 2)])
+def test_interaction_scheduling_gives_identical_results(dsmc_gpu, fp64, sched, streams):
+    """Persistent Interaction grids drawing items from a device queue shared
+    by all runs (1) or from per-run queues (2) compute every item exactly as
+    the grid with one item per workgroup does (0); with one workgroup per
+    grid (fewer units than runs with items) every run is still served."""
+    runs = _mixed_mode_runs()
+    A = dsmc_gpu.Ensemble(runs, [3], state_fp64=fp64, n_groups=1, sched=0)
+    B = dsmc_gpu.Ensemble(runs, [3], state_fp64=fp64, n_groups=1, sched=sched, n_streams=streams,
+                          use_graph=True)
+    C = dsmc_gpu.Ensemble(runs, [3], state_fp64=fp64, n_groups=1, sched=sched, sched_blocks=7)
+    A2 = dsmc_gpu.Ensemble(runs, [3], state_fp64=fp64, n_groups=1, sched=0, collide_mode=2)
+    D = dsmc_gpu.Ensemble(runs, [3], state_fp64=fp64, n_groups=1, sched=sched, sched_blocks=1,
+                          collide_mode=2)
+    for E in (A, B, C, A2, D):
+        E.step(4)
+    for r in range(len(runs)):
+        for X, E in ((A, B), (A, C), (A2, D)):
+            np.testing.assert_array_equal(X.state(r), E.state(r))
+            np.testing.assert_array_equal(X.cell_state(r)["ncoll"], E.cell_state(r)["ncoll"])
+    for e in range(len(runs)):
+        np.testing.assert_array_equal(A.accum(0, ensemble=e), B.accum(0, ensemble=e))
+
+
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_subcell_interaction_modes_give_identical_results(dsmc_gpu, mode):
+    """With 2 x 2 sub-cells the FP32 lane, block (the pipelined FP32 kernel)
+    and wavefront kernels, on the hardware grid and on the persistent queue,
+    make the same selections in the same order: identical results."""
+    runs = [replace(r, subcells=2) for r in _mixed_mode_runs()]
+    A = dsmc_gpu.Ensemble(runs, [3], state_fp64=False, n_groups=1, collide_mode=0)
+    B = dsmc_gpu.Ensemble(runs, [3], state_fp64=False, n_groups=1, collide_mode=mode)
+    C = dsmc_gpu.Ensemble(runs, [3], state_fp64=False, n_groups=1, collide_mode=mode, sched=1,
+                          use_graph=True)
+    for E in (A, B, C):
+        E.step(4)
+    for r in range(len(runs)):
+        for E in (B, C):
+            np.testing.assert_array_equal(A.state(r), E.state(r))
+            np.testing.assert_array_equal(A.cell_state(r)["ncoll"], E.cell_state(r)["ncoll"])
+    assert sum(int(A.cell_state(r)["ncoll"].sum()) for r in range(len(runs))) > 1000
+
+
+def test_tune_cache_returns_the_stored_result(dsmc_gpu, tmp_path):
+    """The first autotune of a problem times the candidates and appends its
+    pick to the cache file; the second finds it there (no timing); another
+    problem (other seed) is not taken from it."""
+    runs = _small_channel_runs(4)
+    path = str(tmp_path / "tune.txt")
+    a = dsmc_gpu.Ensemble.autotune(runs, [3], n_steps=1, tune_cache=path)
+    b = dsmc_gpu.Ensemble.autotune(runs, [3], n_steps=1, tune_cache=path)
+    assert not a["from_cache"] and b["from_cache"]
+    for k in ("tile_chunks", "collide_mode", "n_streams", "sched", "sched_blocks"):
+        assert a[k] == b[k]
+    assert abs(a["ms_per_step"] - b["ms_per_step"]) < 1e-3 * a["ms_per_step"]
+    c = dsmc_gpu.Ensemble.autotune(_small_channel_runs(4, seed=32), [3], n_steps=1, tune_cache=path)
+    assert not c["from_cache"]
+    assert len(open(path).read().splitlines()) == 2

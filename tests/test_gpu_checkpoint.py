@@ -35,13 +35,14 @@ def _same(A, B, n_runs, tag):
     np.testing.assert_array_equal(A.diag(), B.diag(), err_msg=tag)
 
 
-@pytest.mark.parametrize("fp64", [False, True])
-def test_checkpoint_resume_is_bit_identical(dsmc_gpu, fp64):
+@pytest.mark.parametrize("fp64,sub", [(False, 1), (True, 1), (False, 3)])
+def test_checkpoint_resume_is_bit_identical(dsmc_gpu, fp64, sub):
     """Checkpoint after 7 steps, restore into a fresh context with another
     tile size and graph replay, and step both 9 more: identical particles,
     cell state, accumulators (slots on both sides of the checkpoint and one
-    window across it), counts and diagnostics; LCR of the next step too."""
-    runs = _channel_runs(5)
+    window across it), counts and diagnostics; LCR of the next step too
+    (with 3 x 3 sub-cells: the LCR and bin starts are by sub-cell)."""
+    runs = [replace(r, subcells=sub) for r in _channel_runs(5)]
     kw = dict(state_fp64=fp64, n_groups=2, window_steps=3, window_stride=2)
     A = dsmc_gpu.Ensemble(runs, [4, 9, 16], **kw)
     A.step(7)

@@ -30,7 +30,7 @@ def _compare_run(E, r, O, rs, where):
     assert lcr.size == cl["lcr"].size, where
     np.testing.assert_array_equal(cell, cl["cell"], err_msg=where)
     np.testing.assert_array_equal(lcr, cl["lcr"], err_msg=where)
-    np.testing.assert_array_equal(start[: rs.n_cells + 2], cl["start"], err_msg=where)
+    np.testing.assert_array_equal(start[: cl["start"].size], cl["start"], err_msg=where)
     g, o = E.state(r), O.state()
     assert g.shape == o.shape, where
     L = np.array([rs.lx, rs.ly, rs.lz])[:, None]
@@ -215,6 +215,45 @@ def test_box3d_cells_beyond_lds_capacity_fp64(dsmc_gpu, oracle_lib):
     _parity(dsmc_gpu, oracle_lib, big, 2, collide_mode=3)
     grp = W.box3d(n_per_run=2000, n_runs=1, grid=(8, 8, 2), seed=76).runs
     _parity(dsmc_gpu, oracle_lib, grp, 3, squeeze=0.1)
+
+
+def _sub(runs, k):
+    return [replace(r, subcells=k) for r in runs]
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+@pytest.mark.parametrize("ppc", [30, 150, 400])
+def test_subcell_partners_fp64(dsmc_gpu, oracle_lib, mode, ppc):
+    """Sub-cell partner choice (2 x 2 sub-cells): Enumeration bins by
+    sub-cell, the LCR is sorted by bin, and every selection's second partner
+    comes from the first one's sub-cell when it holds two or more; ~30, ~150
+    and ~400 particles per cell in the auto mode and every forced mode."""
+    wl = W.box(ppc * 64, 2, 4, 4, seed=90 + ppc + mode, grid=(8, 8))
+    O = _parity(dsmc_gpu, oracle_lib, _sub(wl.runs, 2), 4, collide_mode=mode)
+    assert O[0].info()["nbin"] == 64 * 4 and O[0].info()["ncoll"] > 50
+
+
+@pytest.mark.parametrize("mode", [0, 1, 3])
+def test_subcell_partners_3d_fp64(dsmc_gpu, oracle_lib, mode):
+    """3-D, 2 x 2 x 2 sub-cells per cell, diffuse walls."""
+    wl = W.box3d(n_per_run=150 * 120, n_runs=2, grid=(6, 5, 4), seed=95 + mode, wall="diffuse", wall_T=1.2)
+    O = _parity(dsmc_gpu, oracle_lib, _sub(wl.runs, 2), 4, collide_mode=mode)
+    assert O[0].info()["nbin"] == 120 * 8
+
+
+def test_subcell_partners_channel_and_beyond_lds_fp64(dsmc_gpu, oracle_lib):
+    """3 x 3 sub-cells in a channel with inflow, diffuse wall and outflow;
+    cells beyond each mode's LDS stage (1250 per cell: block and wavefront
+    modes) take the global-memory fallbacks with sub-cells too; more than
+    2047 bins (2304 and 4096) take the two-level Indexing."""
+    ch = W.channel_run(nx=32, ny=8, lx=2.0, ly=0.5, ppc_inf=30.0, run_id=0, seed=97)
+    ch = replace(ch, subcells=3, n_init=4000, init_U=(ch.inflow_U, 0.0, 0.0))
+    _parity(dsmc_gpu, oracle_lib, [ch], 5)
+    big = _sub(W.box(20_000, 1, 3, 3, seed=98, grid=(4, 4)).runs, 4)
+    _parity(dsmc_gpu, oracle_lib, big, 3)
+    _parity(dsmc_gpu, oracle_lib, big, 2, collide_mode=3)
+    wide = _sub(W.box(30_000, 1, 3, 3, seed=99, grid=(32, 32)).runs, 2)     # 4096 bins
+    _parity(dsmc_gpu, oracle_lib, wide, 3)
 
 
 def test_zz_worst_parity_differences():
