@@ -32,15 +32,21 @@ Beside it the line carries:
                 runs, FP64 accumulators) against the oracle's ensemble of
                 the same problem at step 20 (the 128 runs above, other seeds):
                 z = difference / combined standard error per cell, and the
-                relative error; also against the exact equilibrium values.
+                relative error; also against the exact equilibrium values;
+  accumulator_precision  per macroparameter, the error FP32 accumulators and
+                division would have added to the batch's first sample (its
+                run groups' sums added and divided in FP32) against the FP64
+                ones, beside the sample's relative standard error (box and
+                body flow).
 
 ``--workload body3d`` times the flow past a body at full size instead (32 runs
 x 60M particles, 2M cells, solid-cell obstacle); ``channel`` (16 runs of the
 impulsively started Mach-2 channel, 256x64 cells, ~2M particles each at fill)
 and ``uneven`` (256 runs of uneven grids, particle counts, collision models
 and inflow speeds) start from vacuum and are timed after FILL_STEPS steps, by
-when the flow has crossed the domain.  These are informational, not the
-benchmark line; they run untuned (the autotuner would time the empty start).
+when the flow has crossed the domain; the autotuner then times its candidates
+from a checkpoint of that state (not from the empty start).  These are
+informational, not the benchmark line.
 """
 import argparse
 import json
@@ -184,19 +190,35 @@ def run_gpu(args):
     kw = {"n_streams": args.streams, "tile_chunks": args.tile_chunks, "collide_mode": args.collide_mode,
           "sched": args.sched, "sched_blocks": args.sched_blocks}
     unsteady = args.workload in ("channel", "uneven")
+    tune_kw = dict(state_fp64=False, n_groups=wl.n_groups, use_graph=True, n_steps=3, tune_cache=args.tune_cache,
+                   window_steps=getattr(wl, "window_steps", 1), window_stride=getattr(wl, "window_stride", 1))
     if not args.no_tune and not unsteady:
         # the library's autotuner times its candidate settings on this batch
         # (a scratch arena, before the timed region); tuning never changes results
-        tuned = P.Ensemble.autotune(wl.runs, wl.sample_steps, state_fp64=False, n_groups=wl.n_groups,
-                                    use_graph=True, n_steps=3, tune_cache=args.tune_cache)
+        tuned = P.Ensemble.autotune(wl.runs, wl.sample_steps, **tune_kw)
         kw = {k: tuned[k] for k in ("tile_chunks", "collide_mode", "n_streams", "sched", "sched_blocks")
               if k in tuned}
     E = P.Ensemble.from_workload(wl, use_graph=True, **kw)
     n_runs = wl.n_runs
     nc = wl.runs[0].n_cells
 
-    warmup = max(args.warmup, FILL_STEPS) if unsteady else args.warmup
-    E.step(warmup)
+    warmup = args.warmup
+    if unsteady:
+        # fill from vacuum; then tune at the filled state (every candidate
+        # restored from its checkpoint) and carry on from the same state
+        E.step(FILL_STEPS)
+        warmup += FILL_STEPS
+        if not args.no_tune:
+            ck = E.checkpoint()
+            E.close()
+            del E
+            torch.cuda.empty_cache()
+            tuned = P.Ensemble.autotune(wl.runs, wl.sample_steps, start=ck, **tune_kw)
+            kw = {k: tuned[k] for k in ("tile_chunks", "collide_mode", "n_streams", "sched", "sched_blocks")}
+            E = P.Ensemble.from_workload(wl, use_graph=True, **kw)
+            E.restore(ck)
+            del ck
+    E.step(args.warmup)
     E.sync()
     torch.cuda.synchronize()
     n0 = int(E.counts()[:, 0].sum())
@@ -232,6 +254,17 @@ def run_gpu(args):
     kt = E.kernel_times()
     E.profiling(False)
     info = E.info()
+    # FP64 against FP32 accumulation of the batch's first sample, per
+    # macroparameter (after the timed and profiled steps; the body flow steps
+    # on to its first sample step)
+    acc_prec = None
+    if args.workload in ("ensemble_box", "body3d") and wl.sample_steps:
+        done = warmup + args.steps + args.prof_steps
+        if done < wl.sample_steps[0]:
+            E.step(wl.sample_steps[0] - done)
+        m64, se = E.moments(0)
+        acc_prec = accumulator_precision(E.accum(0), m64, se, n_runs)
+        acc_prec["step"] = wl.sample_steps[0]
     E.close()
     del E
     torch.cuda.empty_cache()
@@ -278,7 +311,7 @@ def run_gpu(args):
     return {"value": value, "elapsed": elapsed, "psteps": psteps, "n_runs": n_runs, "nc": nc, "tuned": tuned,
             "warmup": warmup, "n_mean": psteps // args.steps, "rl_built": rl_built, "step_bytes": step_bytes,
             "kernels": kernels, "roofline": rl, "plain": plain, "info": info, "calib": calib,
-            "match_gpu": match_gpu}
+            "match_gpu": match_gpu, "acc_prec": acc_prec}
 
 
 def run_plain_fp64(args, P, W):
@@ -314,6 +347,42 @@ def interaction_ms(E, steps: int) -> float:
     kt = E.kernel_times()
     E.profiling(False)
     return sum(ms for k, (ms, n) in kt.items() if k.startswith("collide")) / steps
+
+
+def accumulator_precision(acc, m64, se, n_runs: int) -> dict:
+    """What FP32 sampling accumulators would have cost, per macroparameter:
+    the run groups' sums (FP64, [groups][cells][7]) rounded to FP32 and added
+    in FP32 in group order, then divided in FP32 (n = N/R, u = sum c / N,
+    T = mean over axes of sum c_a^2 / N - u_a^2), against the library's FP64
+    moments m64 of the same sums.  Errors over the cells holding particles:
+    n and T relative, u, v, w relative to sqrt(T); beside them the median
+    relative standard error (run groups) for scale."""
+    import numpy as np
+    acc = np.asarray(acc).reshape(-1, acc.shape[-2], acc.shape[-1])
+    f = np.float32
+    tot = np.zeros(acc.shape[1:], f)
+    for g in range(acc.shape[0]):
+        tot = (tot + acc[g].astype(f)).astype(f)
+    N = tot[:, 0]
+    ok = (N > 0) & (m64[:, 0] > 0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        n32 = N / f(n_runs)
+        u32 = tot[:, 1:4] / N[:, None]
+        T32 = ((tot[:, 4:7] / N[:, None]) - u32 * u32).mean(axis=1, dtype=f)
+    T64 = m64[:, 4]
+    scale = np.sqrt(np.maximum(T64, 1e-300))
+    out = {"cells": int(ok.sum()), "runs": n_runs, "groups": int(acc.shape[0])}
+    errs = {"n": np.abs(n32 - m64[:, 0]) / np.abs(m64[:, 0]),
+            "u": np.abs(u32[:, 0] - m64[:, 1]) / scale, "v": np.abs(u32[:, 1] - m64[:, 2]) / scale,
+            "w": np.abs(u32[:, 2] - m64[:, 3]) / scale, "T": np.abs(T32 - T64) / np.abs(T64)}
+    cols = {"n": 0, "u": 1, "v": 2, "w": 3, "T": 4}
+    for k, e in errs.items():
+        e = e[ok & np.isfinite(e)]
+        c = cols[k]
+        rel_se = se[ok, c] / (np.abs(m64[ok, c]) if k in ("n", "T") else scale[ok])
+        out[k] = {"max_err": float(e.max()) if e.size else None, "median_err": float(np.median(e)) if e.size else None,
+                  "median_rel_se": float(np.nanmedian(rel_se)) if rel_se.size else None}
+    return out
 
 
 def amdahl_beta(units, times):
@@ -557,6 +626,7 @@ def main():
         "step_bytes": g["step_bytes"],
         "cpu_baseline": cpu,
         "oracle_match": match,
+        "accumulator_precision": g["acc_prec"],
         "plain_fp64": g["plain"],
         "batched_over_plain": (g["value"] / g["plain"]["value"]) if g["plain"] else None,
         "kernels": g["kernels"],

@@ -126,7 +126,10 @@ typedef struct {
                                    wavefront), 2 one 256-thread block per cell, 3 one 64-lane
                                    wavefront per cell; auto takes 3 when the expected particles
                                    per cell (initial fill or inflow fill) reach 112 and 2 when
-                                   they reach 288 */
+                                   they reach 288.  Results do not depend on it: every mode
+                                   runs a cell's selections in the sequential order and adds
+                                   its sample sums in one shared order (chunks of 16
+                                   particles, each in order, then the chunk sums in order). */
   int32_t n_streams;            /* tuning: run groups stepped concurrently, each on a HIP stream of the
                                    library's own (0 = auto = 1, 1..4; 1 = every launch on hip_stream).
                                    The runs are split into contiguous groups of about equal slot
@@ -313,19 +316,25 @@ dsmc_status dsmc_autotune_bytes(const dsmc_run_spec *runs, int32_t n_runs, const
  * default tile with Interaction on persistent grids drawing from one queue
  * for all runs (sched 1) at two occupancies (as many workgroups as fit, and
  * 1024).  Each candidate is initialised in the caller's arena (at least
- * dsmc_autotune_bytes, 256-byte aligned), stepped once to warm up (graph
- * capture included when opt->use_graph), then n_steps (>= 1) steps are timed
- * with HIP events on hip_stream.  *best receives *opt with the fastest tuning
- * fields; *best_ms_per_step (may be NULL) its time per step.  tune_cache (may
- * be NULL) names a text file of earlier results: when it holds a result for
- * the same run specs, precision, groups, schedule, window, graph replay and
- * device, that result is returned without timing (and without touching the
- * arena); otherwise the new result is appended to it.  Concurrent writers of
- * one cache file are not supported.  The arena holds no usable context
- * afterwards.  Synchronises. */
+ * dsmc_autotune_bytes, 256-byte aligned), restored from `start` when given,
+ * stepped once to warm up (graph capture included when opt->use_graph), then
+ * n_steps (>= 1) steps are timed with HIP events on hip_stream.  start (host
+ * memory, start_bytes long; NULL and 0 for the initial fill) is a checkpoint
+ * written by dsmc_checkpoint for the same run specs, precision, groups,
+ * schedule and window: an unsteady problem that starts from vacuum is then
+ * tuned at the state it will run in (DSMC_EINVAL if it is not a checkpoint
+ * of this problem).  *best receives *opt with
+ * the fastest tuning fields; *best_ms_per_step (may be NULL) its time per
+ * step.  tune_cache (may be NULL) names a text file of earlier results: when
+ * it holds a result for the same run specs, precision, groups, schedule,
+ * window, graph replay, device and starting step, that result is returned
+ * without timing (and without touching the arena); otherwise the new result
+ * is appended to it.  Concurrent writers of one cache file are not
+ * supported.  The arena holds no usable context afterwards.  Synchronises. */
 dsmc_status dsmc_autotune(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_options *opt, void *arena,
-                          size_t arena_bytes, void *hip_stream, int32_t n_steps, const char *tune_cache,
-                          dsmc_options *best, double *best_ms_per_step);
+                          size_t arena_bytes, void *hip_stream, int32_t n_steps, const void *start,
+                          size_t start_bytes, const char *tune_cache, dsmc_options *best,
+                          double *best_ms_per_step);
 
 /* ---- Indexing alone ------------------------------------------------------ */
 

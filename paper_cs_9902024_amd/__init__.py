@@ -112,7 +112,7 @@ def lib():
         L.dsmc_autotune_bytes.argtypes = [C.POINTER(dsmc_run_spec), i32, C.POINTER(dsmc_options),
                                           C.POINTER(sz)]
         L.dsmc_autotune.argtypes = [C.POINTER(dsmc_run_spec), i32, C.POINTER(dsmc_options), vp, sz, vp, i32,
-                                    C.c_char_p, C.POINTER(dsmc_options), dp]
+                                    vp, sz, C.c_char_p, C.POINTER(dsmc_options), dp]
         L.dsmc_kernel_name.restype = C.c_char_p
         for f in EXPORTS:
             if f not in ("dsmc_destroy", "dsmc_last_error", "dsmc_kernel_name"):
@@ -199,13 +199,18 @@ def dsmc_autotune_bytes(specs, opt) -> int:
 
 
 def dsmc_autotune(specs, opt, arena_ptr: int, arena_bytes: int, stream: int, n_steps: int,
-                  tune_cache: Optional[str] = None):
-    """Returns (best dsmc_options, ms per step)."""
+                  tune_cache: Optional[str] = None, start: Optional[np.ndarray] = None):
+    """Returns (best dsmc_options, ms per step).  start: a checkpoint (uint8
+    array from dsmc_checkpoint) every candidate is restored from."""
     best = dsmc_options()
     ms = C.c_double(0)
     path = tune_cache.encode() if tune_cache else None
+    if start is not None:
+        start = np.ascontiguousarray(start, dtype=np.uint8)
+    sp, sb = (start.ctypes.data, start.size) if start is not None else (None, 0)
     _check(lib().dsmc_autotune(specs, len(specs), C.byref(opt), C.c_void_p(arena_ptr), arena_bytes,
-                               C.c_void_p(stream), n_steps, path, C.byref(best), C.byref(ms)), "dsmc_autotune")
+                               C.c_void_p(stream), n_steps, C.c_void_p(sp), sb, path, C.byref(best),
+                               C.byref(ms)), "dsmc_autotune")
     best._keep = getattr(opt, "_keep", None)
     return best, ms.value
 
@@ -421,13 +426,15 @@ class Ensemble:
     @staticmethod
     def autotune(runs, sample_steps: Sequence[int] = (), state_fp64: bool = False, n_groups: int = 1,
                  use_graph: bool = False, n_steps: int = 5, device=None, stream=None,
-                 tune_cache: Optional[str] = None, window_steps: int = 0, window_stride: int = 0) -> dict:
+                 tune_cache: Optional[str] = None, window_steps: int = 0, window_stride: int = 0,
+                 start: Optional[np.ndarray] = None) -> dict:
         """Measures the library's candidate tuning settings on these runs
-        (dsmc_autotune) in a scratch arena, or takes them from the tune cache
-        file when it holds this problem; returns the fastest as keyword
-        arguments for Ensemble (tile_chunks, collide_mode, n_streams, sched,
-        sched_blocks) plus its ms_per_step and whether it came from the cache.
-        Tuning never changes results."""
+        (dsmc_autotune) in a scratch arena, from the initial fill or from the
+        checkpoint `start` (Ensemble.checkpoint() of the same problem), or
+        takes them from the tune cache file when it holds this problem;
+        returns the fastest as keyword arguments for Ensemble (tile_chunks,
+        collide_mode, n_streams, sched, sched_blocks) plus its ms_per_step and
+        whether it came from the cache.  Tuning never changes results."""
         import torch
         if not torch.cuda.is_available():
             raise DsmcError(-4, "autotune", "no GPU visible to torch")
@@ -438,14 +445,15 @@ class Ensemble:
         st = stream if stream is not None else torch.cuda.current_stream(dev)
         cached = True
         try:      # a cached result needs no arena
-            best, ms = dsmc_autotune(specs, opt, 0, 0, st.cuda_stream, n_steps, tune_cache)
+            best, ms = dsmc_autotune(specs, opt, 0, 0, st.cuda_stream, n_steps, tune_cache, start)
         except DsmcError as e:
             if e.status != -2:
                 raise
             cached = False
             nbytes = dsmc_autotune_bytes(specs, opt)
             arena = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-            best, ms = dsmc_autotune(specs, opt, arena.data_ptr(), nbytes, st.cuda_stream, n_steps, tune_cache)
+            best, ms = dsmc_autotune(specs, opt, arena.data_ptr(), nbytes, st.cuda_stream, n_steps, tune_cache,
+                                     start)
             del arena
             torch.cuda.empty_cache()
         return {"tile_chunks": best.tile_chunks, "collide_mode": best.collide_mode,

@@ -1695,15 +1695,26 @@ dsmc_status dsmc_autotune_bytes(const dsmc_run_spec *runs, int32_t n_runs, const
 }
 
 dsmc_status dsmc_autotune(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_options *opt, void *arena,
-                          size_t arena_bytes, void *hip_stream, int32_t n_steps, const char *tune_cache,
-                          dsmc_options *best, double *best_ms_per_step) {
+                          size_t arena_bytes, void *hip_stream, int32_t n_steps, const void *start,
+                          size_t start_bytes, const char *tune_cache, dsmc_options *best,
+                          double *best_ms_per_step) {
   if (!best || n_steps < 1) return DSMC_EINVAL;
+  if ((start == nullptr) != (start_bytes == 0)) return DSMC_EINVAL;
   size_t need = 0;
   dsmc_status st = dsmc_autotune_bytes(runs, n_runs, opt, &need);
   if (st) return st;
   dsmc_options base{};
   if (opt) base = *opt;
-  const std::string key = tune_cache ? tune_key(runs, n_runs, base) : std::string();
+  uint32_t start_step = 0;  // the tuned state: the initial fill, or the checkpoint's step
+  if (start) {
+    CkptHeader h{};
+    if (start_bytes < sizeof h) return DSMC_EINVAL;
+    memcpy(&h, start, sizeof h);
+    if (memcmp(h.magic, kCkptMagic, 8) != 0 || (size_t)h.total != start_bytes) return DSMC_EINVAL;
+    start_step = h.step;
+  }
+  std::string key = tune_cache ? tune_key(runs, n_runs, base) : std::string();
+  if (tune_cache && start) key += "@" + std::to_string(start_step);
   if (tune_cache) {
     dsmc_options cached = base;
     double ms = -1.0;
@@ -1725,6 +1736,7 @@ dsmc_status dsmc_autotune(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_
   for (const dsmc_options &o : tune_candidates(runs, n_runs, base)) {
     dsmc_ctx *c = nullptr;
     st = dsmc_init_runs(runs, n_runs, &o, arena, arena_bytes, hip_stream, &c);
+    if (!st && start) st = dsmc_restore(c, start, start_bytes);
     if (!st) st = dsmc_step(c, 1);  // warm-up (and graph capture)
     if (!st) st = dsmc_sync(c);
     float ms = 0.f;

@@ -1647,44 +1647,58 @@ __device__ __forceinline__ int64_t ntc_selections(const RunT &R, int64_t N, real
   return N < 2 ? 0 : nsel;
 }
 
-// Sums of one cell (sequential order, one lane).
+// Per-cell sample sums (count, sum u, v, w, sum u^2, v^2, w^2) in one order
+// that every Interaction mode reproduces exactly, so the sums do not depend
+// on the mode: the cell's particles (in P' order) in chunks of kSampleChunk,
+// each chunk summed in order, the chunk sums added in chunk order.
+
+constexpr int kSampleChunk = 16;
+
+template <typename PU, typename PV, typename PW>
+__device__ __forceinline__ void chunk_sums(PU u, PV v, PW w, int64_t k0, int64_t k1, double (&c)[kFields]) {
+#pragma unroll
+  for (int f = 0; f < kFields; ++f) c[f] = 0.0;
+  for (int64_t k = k0; k < k1; ++k) {
+    const double a = (double)u[k], b = (double)v[k], e = (double)w[k];
+    c[0] += 1.0;
+    c[1] += a;
+    c[2] += b;
+    c[3] += e;
+    c[4] += a * a;
+    c[5] += b * b;
+    c[6] += e * e;
+  }
+}
+
+// One lane.
 template <typename PU, typename PV, typename PW>
 __device__ __forceinline__ void sample_cell(PU u, PV v, PW w, int64_t N, double *out) {
   double s[kFields] = {0, 0, 0, 0, 0, 0, 0};
-  for (int64_t k = 0; k < N; ++k) {
-    const double a = (double)u[k], b = (double)v[k], c = (double)w[k];
-    s[0] += 1.0;
-    s[1] += a;
-    s[2] += b;
-    s[3] += c;
-    s[4] += a * a;
-    s[5] += b * b;
-    s[6] += c * c;
+  for (int64_t k0 = 0; k0 < N; k0 += kSampleChunk) {
+    double c[kFields];
+    chunk_sums(u, v, w, k0, min(k0 + (int64_t)kSampleChunk, N), c);
+#pragma unroll
+    for (int f = 0; f < kFields; ++f) s[f] += c[f];
   }
 #pragma unroll
   for (int f = 0; f < kFields; ++f) out[f] = s[f];
 }
 
-// Sums of one cell by a whole wave (strided partial sums, butterfly reduce).
+// One wavefront (every lane calls it): lane l sums chunk 64r + l of round r,
+// then the round's chunk sums are added in chunk order (every lane adds the
+// same values in the same order; lane 0 writes).
 template <typename PU, typename PV, typename PW>
 __device__ __forceinline__ void sample_cell_wave(PU u, PV v, PW w, int64_t N, double *out) {
   const int lane = threadIdx.x & 63;
   double s[kFields] = {0, 0, 0, 0, 0, 0, 0};
-  for (int64_t k = lane; k < N; k += kWave) {
-    const double a = (double)u[k], b = (double)v[k], c = (double)w[k];
-    s[0] += 1.0;
-    s[1] += a;
-    s[2] += b;
-    s[3] += c;
-    s[4] += a * a;
-    s[5] += b * b;
-    s[6] += c * c;
-  }
+  for (int64_t base = 0; base < N; base += (int64_t)kWave * kSampleChunk) {
+    const int64_t k0 = min(base + (int64_t)lane * kSampleChunk, N);
+    double c[kFields];
+    chunk_sums(u, v, w, k0, min(k0 + (int64_t)kSampleChunk, N), c);
+    const int nchunk = (int)min((int64_t)kWave, (N - base + kSampleChunk - 1) / kSampleChunk);
+    for (int j = 0; j < nchunk; ++j)
 #pragma unroll
-  for (int f = 0; f < kFields; ++f) {
-    double x = s[f];
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    s[f] = x;
+      for (int f = 0; f < kFields; ++f) s[f] += __shfl(c[f], j);
   }
   if (lane == 0)
 #pragma unroll
@@ -2274,30 +2288,9 @@ __device__ __forceinline__ void collide_cell_item(const DevPtrs<real> &d, int sr
       gw[k] = sw[k];
     }
   if (R.ahead) next_cells<real, DIM>(R, B, d.cell, b0, n, tid, 256);  // this thread's own records
-  if (sample) {
-    double sm[kFields] = {0, 0, 0, 0, 0, 0, 0};
-    auto add = [&](real uu, real vv, real ww) {
-      const double a = (double)uu, b = (double)vv, e = (double)ww;
-      sm[0] += 1.0;
-      sm[1] += a;
-      sm[2] += b;
-      sm[3] += e;
-      sm[4] += a * a;
-      sm[5] += b * b;
-      sm[6] += e * e;
-    };
-    if (in_lds)
-      for (int64_t k = tid; k < n; k += 256) add(su[k], sv[k], sw[k]);
-    else
-      for (int64_t k = tid; k < n; k += 256) add(gu[k], gv[k], gw[k]);
-#pragma unroll
-    for (int f = 0; f < kFields; ++f) {
-      double x = sm[f];
-      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-      if ((tid & 63) == 0) sh.red[tid >> 6][f] = x;
-    }
-    __syncthreads();
-    if (tid < kFields) d.stage[gc * kFields + tid] = ((sh.red[0][tid] + sh.red[1][tid]) + sh.red[2][tid]) + sh.red[3][tid];
+  if (sample && tid < kWave) {  // the first wavefront, in the order all modes share
+    if (in_lds) sample_cell_wave(su, sv, sw, n, d.stage + gc * kFields);
+    else sample_cell_wave(gu, gv, gw, n, d.stage + gc * kFields);
   }
   if (tid == 0) {
     d.gmax[gc] = gm;
@@ -2604,33 +2597,12 @@ __device__ __forceinline__ void pipe_collide(const DevPtrs<float> &d, const Part
   } else if (m.ahead) {
     next_cells<float, DIM, SUB>(*m.run, B, d.cell, m.b0, n, tid, 256);
   }
-  if (sample) {
-    // LDS and global are summed by separate loops: a pointer to either would
-    // be a flat access the compiler must also wait for as a global one
-    double sm[kFields] = {0, 0, 0, 0, 0, 0, 0};
-    auto add = [&](float uu, float vv, float ww) {
-      const double a = (double)uu, b = (double)vv, e = (double)ww;
-      sm[0] += 1.0;
-      sm[1] += a;
-      sm[2] += b;
-      sm[3] += e;
-      sm[4] += a * a;
-      sm[5] += b * b;
-      sm[6] += e * e;
-    };
-    if (lds)
-      for (int64_t k = tid; k < n; k += 256) add(su[k], sv[k], sw[k]);
-    else
-      for (int64_t k = tid; k < n; k += 256) add(gu[k], gv[k], gw[k]);
-#pragma unroll
-    for (int f = 0; f < kFields; ++f) {
-      double x = sm[f];
-      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-      if ((tid & 63) == 0) sh.red[tid >> 6][f] = x;
-    }
-    LdsSync::bar();
-    if (tid < kFields)
-      d.stage[m.gc * kFields + tid] = ((sh.red[0][tid] + sh.red[1][tid]) + sh.red[2][tid]) + sh.red[3][tid];
+  if (sample && tid < kWave) {
+    // the first wavefront, in the order all modes share; LDS and global are
+    // summed by separate calls: a pointer to either would be a flat access
+    // the compiler must also wait for as a global one
+    if (lds) sample_cell_wave(su, sv, sw, n, d.stage + m.gc * kFields);
+    else sample_cell_wave(gu, gv, gw, n, d.stage + m.gc * kFields);
   }
   if (tid == 0) {
     d.gmax[m.gc] = gm;

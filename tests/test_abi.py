@@ -182,10 +182,16 @@ def test_autotune_workspace_covers_every_candidate(dsmc):
                 assert dsmc.dsmc_required_bytes(specs, o) <= tune
     # argument errors before any device work
     best = dsmc.dsmc_options()
-    assert dsmc.lib().dsmc_autotune(specs, len(specs), C.byref(opt), None, 0, None, 0, None, C.byref(best),
-                                    None) == -1
-    assert dsmc.lib().dsmc_autotune(specs, len(specs), C.byref(opt), None, 0, None, 3, None, C.byref(best),
-                                    None) == -2
+    assert dsmc.lib().dsmc_autotune(specs, len(specs), C.byref(opt), None, 0, None, 0, None, 0, None,
+                                    C.byref(best), None) == -1
+    assert dsmc.lib().dsmc_autotune(specs, len(specs), C.byref(opt), None, 0, None, 3, None, 0, None,
+                                    C.byref(best), None) == -2
+    # a starting state that is not a checkpoint, or a pointer without a size
+    junk = (C.c_uint8 * 200)()
+    assert dsmc.lib().dsmc_autotune(specs, len(specs), C.byref(opt), None, 0, None, 3, junk, 200, None,
+                                    C.byref(best), None) == -1
+    assert dsmc.lib().dsmc_autotune(specs, len(specs), C.byref(opt), None, 0, None, 3, junk, 0, None,
+                                    C.byref(best), None) == -1
 
 
 def test_counting_sort_workspace_query(dsmc):

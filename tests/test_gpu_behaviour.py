@@ -144,18 +144,22 @@ def test_autotuned_settings_give_identical_results(dsmc_gpu):
 @pytest.mark.parametrize("mode", [1, 2, 3])
 def test_interaction_modes_give_identical_results(dsmc_gpu, mode):
     """The lane-per-cell, block-per-cell and wavefront-per-cell interaction
-    kernels all run each cell's selections in the sequential order: FP32
-    results are identical."""
+    kernels all run each cell's selections in the sequential order and add
+    each cell's sample sums in one shared order: FP32 states, collision
+    counts and sample sums are identical, and so are FP64 ones."""
     import torch
     runs = _small_channel_runs(3)
-    A = dsmc_gpu.Ensemble(runs, [4], state_fp64=False, n_groups=1, collide_mode=0)
-    B = dsmc_gpu.Ensemble(runs, [4], state_fp64=False, n_groups=1, collide_mode=mode)
-    A.step(4)
-    B.step(4)
-    torch.cuda.synchronize()
-    for r in range(len(runs)):
-        np.testing.assert_array_equal(A.state(r), B.state(r))
-        np.testing.assert_array_equal(A.cell_state(r)["ncoll"], B.cell_state(r)["ncoll"])
+    for fp64 in (False, True):
+        A = dsmc_gpu.Ensemble(runs, [2, 4], state_fp64=fp64, n_groups=1, collide_mode=0)
+        B = dsmc_gpu.Ensemble(runs, [2, 4], state_fp64=fp64, n_groups=1, collide_mode=mode)
+        A.step(4)
+        B.step(4)
+        torch.cuda.synchronize()
+        for r in range(len(runs)):
+            np.testing.assert_array_equal(A.state(r), B.state(r))
+            np.testing.assert_array_equal(A.cell_state(r)["ncoll"], B.cell_state(r)["ncoll"])
+        for k in range(2):
+            np.testing.assert_array_equal(A.accum(k), B.accum(k))
 
 
 def test_capacity_overflow_is_reported(dsmc_gpu):
@@ -284,7 +288,8 @@ def test_interaction_scheduling_gives_identical_results(dsmc_gpu, fp64, sched, s
             np.testing.assert_array_equal(X.state(r), E.state(r))
             np.testing.assert_array_equal(X.cell_state(r)["ncoll"], E.cell_state(r)["ncoll"])
     for e in range(len(runs)):
-        np.testing.assert_array_equal(A.accum(0, ensemble=e), B.accum(0, ensemble=e))
+        for X, E in ((A, B), (A, C), (A, D), (A2, D)):
+            np.testing.assert_array_equal(X.accum(0, ensemble=e), E.accum(0, ensemble=e))
 
 
 @pytest.mark.parametrize("mode", [1, 2, 3])
@@ -303,6 +308,9 @@ def test_subcell_interaction_modes_give_identical_results(dsmc_gpu, mode):
         for E in (B, C):
             np.testing.assert_array_equal(A.state(r), E.state(r))
             np.testing.assert_array_equal(A.cell_state(r)["ncoll"], E.cell_state(r)["ncoll"])
+    for e in range(len(runs)):
+        for E in (B, C):
+            np.testing.assert_array_equal(A.accum(0, ensemble=e), E.accum(0, ensemble=e))
     assert sum(int(A.cell_state(r)["ncoll"].sum()) for r in range(len(runs))) > 1000
 
 
@@ -321,3 +329,30 @@ def test_tune_cache_returns_the_stored_result(dsmc_gpu, tmp_path):
     c = dsmc_gpu.Ensemble.autotune(_small_channel_runs(4, seed=32), [3], n_steps=1, tune_cache=path)
     assert not c["from_cache"]
     assert len(open(path).read().splitlines()) == 2
+
+
+def test_autotune_from_a_checkpoint(dsmc_gpu, tmp_path):
+    """The autotuner restores every candidate from a checkpoint (a filled
+    unsteady state, not the start) and caches the pick under that state's
+    step; its settings then continue the checkpointed run bit for bit."""
+    runs = [replace(r, n_init=0) for r in _small_channel_runs(4)]     # from vacuum
+    E = dsmc_gpu.Ensemble(runs, [60], state_fp64=False, n_groups=2)
+    E.step(40)
+    ck = E.checkpoint()
+    path = str(tmp_path / "tune.txt")
+    a = dsmc_gpu.Ensemble.autotune(runs, [60], n_groups=2, n_steps=1, tune_cache=path, start=ck)
+    b = dsmc_gpu.Ensemble.autotune(runs, [60], n_groups=2, n_steps=1, tune_cache=path, start=ck)
+    c = dsmc_gpu.Ensemble.autotune(runs, [60], n_groups=2, n_steps=1, tune_cache=path)
+    assert not a["from_cache"] and b["from_cache"] and not c["from_cache"]
+    kw = {k: a[k] for k in ("tile_chunks", "collide_mode", "n_streams", "sched", "sched_blocks")}
+    F = dsmc_gpu.Ensemble(runs, [60], state_fp64=False, n_groups=2, **kw)
+    F.restore(ck)
+    E.step(25)
+    F.step(25)
+    for r in range(len(runs)):
+        np.testing.assert_array_equal(E.state(r), F.state(r))
+    np.testing.assert_array_equal(E.accum(0), F.accum(0))
+    # a checkpoint of another problem is refused
+    with pytest.raises(dsmc_gpu.DsmcError) as e:
+        dsmc_gpu.Ensemble.autotune(runs, [60], n_groups=3, n_steps=1, start=ck)
+    assert e.value.status == -1
