@@ -1647,58 +1647,30 @@ __device__ __forceinline__ int64_t ntc_selections(const RunT &R, int64_t N, real
   return N < 2 ? 0 : nsel;
 }
 
-// Per-cell sample sums (count, sum u, v, w, sum u^2, v^2, w^2) in one order
-// that every Interaction mode reproduces exactly, so the sums do not depend
-// on the mode: the cell's particles (in P' order) in chunks of kSampleChunk,
-// each chunk summed in order, the chunk sums added in chunk order.
-
-constexpr int kSampleChunk = 16;
-
-template <typename PU, typename PV, typename PW>
-__device__ __forceinline__ void chunk_sums(PU u, PV v, PW w, int64_t k0, int64_t k1, double (&c)[kFields]) {
-#pragma unroll
-  for (int f = 0; f < kFields; ++f) c[f] = 0.0;
-  for (int64_t k = k0; k < k1; ++k) {
-    const double a = (double)u[k], b = (double)v[k], e = (double)w[k];
-    c[0] += 1.0;
-    c[1] += a;
-    c[2] += b;
-    c[3] += e;
-    c[4] += a * a;
-    c[5] += b * b;
-    c[6] += e * e;
-  }
-}
-
-// One lane.
-template <typename PU, typename PV, typename PW>
-__device__ __forceinline__ void sample_cell(PU u, PV v, PW w, int64_t N, double *out) {
-  double s[kFields] = {0, 0, 0, 0, 0, 0, 0};
-  for (int64_t k0 = 0; k0 < N; k0 += kSampleChunk) {
-    double c[kFields];
-    chunk_sums(u, v, w, k0, min(k0 + (int64_t)kSampleChunk, N), c);
-#pragma unroll
-    for (int f = 0; f < kFields; ++f) s[f] += c[f];
-  }
-#pragma unroll
-  for (int f = 0; f < kFields; ++f) out[f] = s[f];
-}
-
-// One wavefront (every lane calls it): lane l sums chunk 64r + l of round r,
-// then the round's chunk sums are added in chunk order (every lane adds the
-// same values in the same order; lane 0 writes).
+// Per-cell sample sums (count, sum u, v, w, sum u^2, v^2, w^2), taken by one
+// whole wavefront in every Interaction mode, so the sums do not depend on the
+// mode: lane l adds the cell's particles l, l + 64, ... (P' order) in order,
+// then the 64 partial sums are added by the xor butterfly (offsets 32, 16,
+// ..., 1); lane 0 writes.
 template <typename PU, typename PV, typename PW>
 __device__ __forceinline__ void sample_cell_wave(PU u, PV v, PW w, int64_t N, double *out) {
   const int lane = threadIdx.x & 63;
   double s[kFields] = {0, 0, 0, 0, 0, 0, 0};
-  for (int64_t base = 0; base < N; base += (int64_t)kWave * kSampleChunk) {
-    const int64_t k0 = min(base + (int64_t)lane * kSampleChunk, N);
-    double c[kFields];
-    chunk_sums(u, v, w, k0, min(k0 + (int64_t)kSampleChunk, N), c);
-    const int nchunk = (int)min((int64_t)kWave, (N - base + kSampleChunk - 1) / kSampleChunk);
-    for (int j = 0; j < nchunk; ++j)
+  for (int64_t k = lane; k < N; k += kWave) {
+    const double a = (double)u[k], b = (double)v[k], c = (double)w[k];
+    s[0] += 1.0;
+    s[1] += a;
+    s[2] += b;
+    s[3] += c;
+    s[4] += a * a;
+    s[5] += b * b;
+    s[6] += c * c;
+  }
 #pragma unroll
-      for (int f = 0; f < kFields; ++f) s[f] += __shfl(c[f], j);
+  for (int f = 0; f < kFields; ++f) {
+    double x = s[f];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    s[f] = x;
   }
   if (lane == 0)
 #pragma unroll
@@ -1962,16 +1934,31 @@ __device__ __forceinline__ void collide_lanes_item(const DevPtrs<real> &d, int s
     uint32_t ncol;
     if (in_lds) {
       ncol = chain_serial<real>(R, step, (uint32_t)c, (uint32_t)N, 0, nsel, su + cb, sv + cb, sw + cb, gm, sub);
-      if (sample) sample_cell(su + cb, sv + cb, sw + cb, N, d.stage + gc * kFields);
     } else {
       const int64_t o = R.so + b0 + cb;
       ncol = chain_serial<real>(R, step, (uint32_t)c, (uint32_t)N, 0, nsel, B.u() + o, B.v() + o, w_view<DIM>(B, o),
                                 gm, sub);
-      if (sample) sample_cell(B.u() + o, B.v() + o, w_view<DIM>(B, o), N, d.stage + gc * kFields);
     }
     d.gmax[gc] = gm;
     d.rem_c[gc] = rem;
     d.ncoll[gc] += ncol;
+  }
+  if (sample) {
+    // the whole wavefront samples the item's cells one after the other
+    if (in_lds) wave_sync();
+    else global_sync_wave();
+    for (int32_t j = 0; j < ncell; ++j) {
+      const int32_t c = c0 + j;
+      const int64_t cs = (int64_t)d.bin_start[R.bo + (int64_t)c * S];
+      const int64_t N = (int64_t)d.bin_start[R.bo + (int64_t)(c + 1) * S] - cs;
+      double *out = d.stage + (R.co + c) * kFields;
+      if (in_lds) {
+        sample_cell_wave(su + (cs - b0), sv + (cs - b0), sw + (cs - b0), N, out);
+      } else {
+        const int64_t o = R.so + cs;
+        sample_cell_wave(B.u() + o, B.v() + o, w_view<DIM>(B, o), N, out);
+      }
+    }
   }
   if (in_lds) {
     wave_sync();
@@ -2719,7 +2706,8 @@ DSMC_PIPE_KERNEL(3, true, true)
 
 template <typename real>
 __global__ __launch_bounds__(256) void k_sample_cells(DevPtrs<real> d, int buf, int64_t n_cells) {
-  const int64_t gc = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  // one wavefront per cell, as in the Interaction kernels
+  const int64_t gc = (int64_t)blockIdx.x * (256 / kWave) + wave_index();
   if (gc >= n_cells) return;
   const RunDev &R = d.runs[d.cgroup_run[gc >> 6]];
   const int32_t c = (int32_t)(gc - R.co);
@@ -2728,9 +2716,9 @@ __global__ __launch_bounds__(256) void k_sample_cells(DevPtrs<real> d, int buf, 
   const int64_t N = (int64_t)d.bin_start[R.bo + (int64_t)(c + 1) * R.S] - b;
   const Particles<real> P = d.P[buf];
   if (P.zw)
-    sample_cell(P.u() + (R.so + b), P.v() + (R.so + b), w_view<3>(P, R.so + b), N, d.stage + gc * kFields);
+    sample_cell_wave(P.u() + (R.so + b), P.v() + (R.so + b), w_view<3>(P, R.so + b), N, d.stage + gc * kFields);
   else
-    sample_cell(P.u() + (R.so + b), P.v() + (R.so + b), w_view<2>(P, R.so + b), N, d.stage + gc * kFields);
+    sample_cell_wave(P.u() + (R.so + b), P.v() + (R.so + b), w_view<2>(P, R.so + b), N, d.stage + gc * kFields);
 }
 
 // acc[slot][eg][c][f] += sum over the runs of (ensemble, group) eg, in run order.
@@ -3229,7 +3217,7 @@ void launch_step(const Geometry &g, const DevPtrs<real> &d, int buf, hipStream_t
 
 template <typename real>
 void launch_sample(const Geometry &g, const DevPtrs<real> &d, int buf, int slot, hipStream_t s, const Prof *prof) {
-  TIMED(kKSample, hipLaunchKernelGGL(k_sample_cells<real>, dim3((unsigned)((g.n_cells + 255) / 256)), dim3(256), 0,
+  TIMED(kKSample, hipLaunchKernelGGL(k_sample_cells<real>, dim3((unsigned)((g.n_cells + 3) / 4)), dim3(256), 0,
                                      s, d, buf, g.n_cells));
   TIMED(kKAccumulate, hipLaunchKernelGGL(k_accumulate<real>, dim3(grid_for(g.acc_stride)), dim3(256), 0, s, d, slot,
                                          g.acc_stride, g.n_eg));
