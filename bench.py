@@ -385,15 +385,28 @@ def accumulator_precision(acc, m64, se, n_runs: int) -> dict:
     return out
 
 
-def amdahl_beta(units, times):
-    """Least-squares beta of T(p) = T(1) (beta + (1 - beta) / p): 1/S is
-    linear in 1/p with intercept beta."""
+def amdahl_fit(units, times) -> dict:
+    """Amdahl's beta from times T(p) on p processors (wavefronts): a
+    least-squares fit, in relative terms (each point weighted by 1/T(p)), of
+    T(p) = A + B/p + C p -- the part more processors do not shorten, the
+    part they share, and a per-processor cost of starting and draining the
+    persistent grid that shows at large p.  With T(1) = A + B + C: beta =
+    A / T(1) and overhead = C / T(1) (both clamped to [0, 1]).  The smallest
+    p need not be 1."""
     import numpy as np
     p = np.asarray(units, float)
-    S = times[0] / np.asarray(times, float)
-    A = np.stack([np.ones_like(p), 1.0 / p], axis=1)
-    coef, *_ = np.linalg.lstsq(A, 1.0 / S, rcond=None)
-    return float(min(max(coef[0], 0.0), 1.0))
+    T = np.asarray(times, float)
+    X = np.stack([np.ones_like(p), 1.0 / p, p], axis=1) / T[:, None]
+    (A, B, C), *_ = np.linalg.lstsq(X, np.ones_like(T), rcond=None)
+    T1 = A + B + C
+    if T1 <= 0:
+        return {"beta": 1.0 if A > 0 else 0.0, "overhead": 0.0}
+    clamp = lambda x: float(min(max(x, 0.0), 1.0))
+    return {"beta": clamp(A / T1), "overhead": clamp(C / T1)}
+
+
+def amdahl_beta(units, times) -> float:
+    return amdahl_fit(units, times)["beta"]
 
 
 def balance_experiment(args):
@@ -421,9 +434,14 @@ def balance_experiment(args):
     counts = base.counts()[:, 0]
     ck = base.checkpoint()
     base.close()
-    # sampled runs: smallest, two middle, largest by particles at fill
+    # sampled runs: smallest, two middle, largest by particles at fill, and
+    # the most crowded (particles per cell: in the lane mode a cell's chain
+    # grows as N^2, so it is the run a static split waits for)
     order = np.argsort(counts)
+    ppc = counts / np.array([r.n_cells for r in wl.runs], float)
     sample = [int(order[0]), int(order[R // 3]), int(order[2 * R // 3]), int(order[-1])]
+    if int(np.argmax(ppc)) not in sample:
+        sample.append(int(np.argmax(ppc)))
     runs_beta = []
     for r in sample:
         one = W.Workload("one", [wl.runs[r]], wl.n_steps, wl.sample_steps, 1)
@@ -439,8 +457,9 @@ def balance_experiment(args):
             units.append(G * wpb)
             times.append(interaction_ms(E, 3))
             E.close()
+        fit = amdahl_fit(units, times)
         runs_beta.append({"run": r, "particles": int(counts[r]), "cells": wl.runs[r].n_cells,
-                          "beta": amdahl_beta(units, times),
+                          "beta": fit["beta"], "overhead_per_wavefront": fit["overhead"],
                           "wavefronts": units, "ms": [round(t, 4) for t in times]})
     beta = float(np.mean([b["beta"] for b in runs_beta]))
     rows = []
