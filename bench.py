@@ -618,7 +618,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(runs would shard across GPUs, with one final reduction of the accumulators)",
               file=sys.stderr)
         sys.exit(2)
