@@ -55,7 +55,7 @@ class OrSpec(C.Structure):
                 ("capacity", C.c_int64), ("n_init", C.c_int64),
                 ("init_U", C.c_double * 3), ("init_T", C.c_double),
                 ("run_id", C.c_uint32), ("seed", C.c_uint32), ("subcells", C.c_int32),
-                ("pad", C.c_int32)]
+                ("pad", C.c_int32), ("nbar_alpha", C.c_double)]
 
 
 _lib = None
@@ -93,6 +93,8 @@ def lib():
         L.or_get_solid_hits.argtypes = [P]
         L.or_get_solid_hits.restype = C.c_int64
         L.or_set_cell_state.argtypes = [P, dp, dp]
+        L.or_get_nbar.argtypes = [P, dp]
+        L.or_set_nbar.argtypes = [P, dp]
         L.or_counting_sort.argtypes = [P, C.c_int64, C.c_int64, P, P, P]
         L.or_collide_cell.argtypes = [C.POINTER(OrSpec), C.c_uint32, C.c_uint32, C.c_int64,
                                       dp, dp, dp, dp, dp, P, P, C.c_int64, C.POINTER(C.c_int64)]
@@ -135,6 +137,7 @@ def make_spec(rs) -> OrSpec:
     s.init_T = rs.init_T
     s.run_id, s.seed = rs.run_id & 0xFFFFFFFF, rs.seed & 0xFFFFFFFF
     s.subcells = getattr(rs, "subcells", 1)
+    s.nbar_alpha = getattr(rs, "ntc_nbar_alpha", 0.0)
     return s
 
 
@@ -265,13 +268,19 @@ class OracleRun:
     def cell_state(self) -> dict:
         rem = np.zeros(self.nc); gmax = np.zeros(self.nc); ncoll = np.zeros(self.nc, np.int64)
         lib().or_get_cell_state(self._h, rem.ctypes.data, gmax.ctypes.data, ncoll.ctypes.data)
-        return {"rem": rem, "gmax": gmax, "ncoll": ncoll}
+        nbar = np.zeros(self.nc)
+        lib().or_get_nbar(self._h, _dp(nbar))
+        return {"rem": rem, "gmax": gmax, "ncoll": ncoll, "nbar": nbar}
 
-    def set_cell_state(self, rem: np.ndarray, gmax: np.ndarray):
+    def set_cell_state(self, rem: np.ndarray, gmax: np.ndarray, nbar: np.ndarray = None):
         rem = np.ascontiguousarray(rem, dtype=np.float64)
         gmax = np.ascontiguousarray(gmax, dtype=np.float64)
         assert rem.size == self.nc and gmax.size == self.nc
         lib().or_set_cell_state(self._h, _dp(rem), _dp(gmax))
+        if nbar is not None:
+            nbar = np.ascontiguousarray(nbar, dtype=np.float64)
+            assert nbar.size == self.nc
+            lib().or_set_nbar(self._h, _dp(nbar))
 
     def face_rem(self) -> np.ndarray:
         nf = self.info()["nface"]

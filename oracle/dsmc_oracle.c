@@ -87,6 +87,8 @@ typedef struct {
     uint32_t run_id, seed;
     int32_t subcells;    /* collision partners from sub-cells: k per axis (0 or 1 = none) */
     int32_t pad;
+    double nbar_alpha;   /* 0: NTC count from N(N-1)/2; in (0, 1]: from N * Nbar / 2, Nbar a running
+                            mean of the cell's count with weight nbar_alpha */
 } or_spec;
 
 typedef struct {
@@ -113,6 +115,7 @@ typedef struct {
     int64_t *cstart;     /* nbin + 2 bin starts */
     int64_t *ccount;     /* nbin + 1 */
     double *rem_c, *gmax;
+    double *nbar;        /* running mean of each cell's particle count (with nbar_alpha > 0) */
     int64_t *ncoll;
     double *rem_f;
     uint32_t step;
@@ -243,7 +246,7 @@ void or_run_free(or_run *R)
         free(R->q[a]);
     }
     free(R->cell); free(R->lcr); free(R->cstart); free(R->ccount);
-    free(R->rem_c); free(R->gmax); free(R->ncoll); free(R->rem_f);
+    free(R->rem_c); free(R->gmax); free(R->nbar); free(R->ncoll); free(R->rem_f);
     free(R->solid);
     free(R);
 }
@@ -266,6 +269,7 @@ or_run *or_run_new(const or_spec *sp, int32_t *status)
     }
     if (sp->subcells < 0 || sp->subcells > 4) { *status = OR_EINVAL; return NULL; }
     if (sp->subcells > 1 && sp->solid) { *status = OR_EUNSUPPORTED; return NULL; }
+    if (!(sp->nbar_alpha >= 0.0 && sp->nbar_alpha <= 1.0)) { *status = OR_EINVAL; return NULL; }
     or_run *R = (or_run *)calloc(1, sizeof(or_run));
     if (!R) { *status = OR_ENOMEM; return NULL; }
     R->sp = *sp;
@@ -339,13 +343,18 @@ or_run *or_run_new(const or_spec *sp, int32_t *status)
     R->ccount = (int64_t *)calloc((size_t)(R->nbin + 1), sizeof(int64_t));
     R->rem_c = (double *)calloc((size_t)R->nc, sizeof(double));
     R->gmax = (double *)calloc((size_t)R->nc, sizeof(double));
+    R->nbar = (double *)calloc((size_t)R->nc, sizeof(double));
     R->ncoll = (int64_t *)calloc((size_t)R->nc, sizeof(int64_t));
     R->rem_f = (double *)calloc((size_t)(R->nface > 0 ? R->nface : 1), sizeof(double));
-    int ok = R->cell && R->lcr && R->cstart && R->ccount && R->rem_c && R->gmax &&
+    int ok = R->cell && R->lcr && R->cstart && R->ccount && R->rem_c && R->gmax && R->nbar &&
              R->ncoll && R->rem_f;
     for (int a = 0; a < 6; ++a) ok = ok && R->p[a] && R->q[a];
     if (!ok) { or_run_free(R); *status = OR_ENOMEM; return NULL; }
-    for (int64_t c = 0; c < R->nc; ++c) R->gmax[c] = R->gmax0;
+    /* the running mean starts at the expected count of the initial fill */
+    for (int64_t c = 0; c < R->nc; ++c) {
+        R->gmax[c] = R->gmax0;
+        R->nbar[c] = (double)sp->n_init / (double)R->nc;
+    }
     return R;
 }
 
@@ -654,14 +663,24 @@ static int64_t second_partner(uint32_t a, int64_t i, int64_t N, const int64_t *o
 }
 
 /* Collides the N particles whose velocities are u[0..N), v[..], w[..]; off
- * (NULL without sub-cells) holds the S + 1 sub-cell starts.
+ * (NULL without sub-cells) holds the S + 1 sub-cell starts.  The number of
+ * selections (NTC, Bird): M = pairs * Fnum sigma_ref dt / V_c * (sigma
+ * c_r)_max + the cell's remainder, pairs = N(N-1)/2, or with nbar (not NULL)
+ * N * Nbar / 2 where the running mean Nbar is first moved towards this
+ * step's N by the weight nbar_alpha.
  * trace (optional) receives (i, j, accepted) per selection, at most
  * trace_cap selections. Returns the number of accepted collisions. */
 static int64_t collide_cell(const or_run *R, uint32_t cell, int64_t N, double *u, double *v,
-                            double *w, double *gmax, double *rem, const int64_t *off, int32_t *trace,
-                            int64_t trace_cap, int64_t *nsel_out)
+                            double *w, double *gmax, double *rem, double *nbar, const int64_t *off,
+                            int32_t *trace, int64_t trace_cap, int64_t *nsel_out)
 {
-    double npairs = 0.5 * (double)(N * (N - 1));
+    double npairs;
+    if (nbar) {
+        *nbar = *nbar + R->sp.nbar_alpha * ((double)N - *nbar);
+        npairs = 0.5 * (double)N * (*nbar);
+    } else {
+        npairs = 0.5 * (double)(N * (N - 1));
+    }
     double M = npairs * R->coef * (*gmax) + *rem;
     double fl = floor(M);
     int64_t nsel = (int64_t)fl;
@@ -709,7 +728,8 @@ void or_interaction(or_run *R)
         int64_t b = R->cstart[c * R->S], N = R->cstart[(c + 1) * R->S] - b;
         for (int64_t s = 0; s <= R->S; ++s) off[s] = R->cstart[c * R->S + s] - b;
         int64_t k = collide_cell(R, (uint32_t)c, N, R->p[3] + b, R->p[4] + b, R->p[5] + b,
-                                 &R->gmax[c], &R->rem_c[c], R->sub > 1 ? off : NULL, NULL, 0, NULL);
+                                 &R->gmax[c], &R->rem_c[c], R->sp.nbar_alpha > 0.0 ? &R->nbar[c] : NULL,
+                                 R->sub > 1 ? off : NULL, NULL, 0, NULL);
         R->ncoll[c] += k;
         total += k;
     }
@@ -718,7 +738,8 @@ void or_interaction(or_run *R)
 }
 
 /* Stand-alone single-cell interaction for brute-force tests: the velocities
- * are updated in place, (gmax, rem) are in/out, trace as in collide_cell. */
+ * are updated in place, (gmax, rem) are in/out, trace as in collide_cell;
+ * the count is always the N(N-1)/2 form (no running mean). */
 int64_t or_collide_cell(const or_spec *sp, uint32_t step, uint32_t cell, int64_t N, double *u,
                         double *v, double *w, double *gmax, double *rem, const int64_t *sub_off,
                         int32_t *trace, int64_t trace_cap, int64_t *nsel_out)
@@ -730,7 +751,7 @@ int64_t or_collide_cell(const or_spec *sp, uint32_t step, uint32_t cell, int64_t
     or_run *R = or_run_new(&s2, &st);
     if (!R) return st;
     R->step = step;
-    int64_t k = collide_cell(R, cell, N, u, v, w, gmax, rem, R->sub > 1 ? sub_off : NULL, trace,
+    int64_t k = collide_cell(R, cell, N, u, v, w, gmax, rem, NULL, R->sub > 1 ? sub_off : NULL, trace,
                              trace_cap, nsel_out);
     or_run_free(R);
     return k;
@@ -825,6 +846,10 @@ void or_set_cell_state(or_run *R, const double *rem, const double *gmax)
     if (rem) memcpy(R->rem_c, rem, (size_t)R->nc * sizeof(double));
     if (gmax) memcpy(R->gmax, gmax, (size_t)R->nc * sizeof(double));
 }
+
+void or_get_nbar(const or_run *R, double *nbar) { memcpy(nbar, R->nbar, (size_t)R->nc * sizeof(double)); }
+
+void or_set_nbar(or_run *R, const double *nbar) { memcpy(R->nbar, nbar, (size_t)R->nc * sizeof(double)); }
 
 int64_t or_get_solid_hits(const or_run *R) { return R->last_nsolid; }
 

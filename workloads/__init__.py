@@ -81,6 +81,7 @@ class RunSpec:
     solid: Optional[np.ndarray] = None   # uint8 [nz][ny][nx], 1 = solid voxel
     solid_T: float = 1.0
     subcells: int = 1             # collision partners from k x k (x k) sub-cells (1 = none)
+    ntc_nbar_alpha: float = 0.0   # NTC count N * Nbar / 2 with this running-mean weight (0 = N(N-1)/2)
 
     @property
     def n_cells(self) -> int:
