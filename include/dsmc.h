@@ -109,6 +109,11 @@ typedef struct {
                                    the crossed face.  Copied by dsmc_init_runs.  With inflow, the first
                                    layer of cells (ix = 0) must be fluid. */
   double solid_T;               /* temperature of the solid faces (> 0 when solid_mask is given) */
+  double ntc_nbar_alpha;        /* NTC selection count of a cell (Sec. 1.1's collision step, after Bird):
+                                   0 = N(N-1)/2 pairs times Fnum sigma_ref dt / V_c (sigma c_r)_max plus
+                                   the remainder; in (0, 1] = N Nbar / 2 pairs instead, Nbar a running
+                                   mean of the cell's count moved by Nbar += alpha (N - Nbar) before each
+                                   count and started at n_init / cells (1: Nbar = N) */
 } dsmc_run_spec;
 
 typedef struct {
@@ -235,8 +240,11 @@ dsmc_status dsmc_get_lcr(dsmc_ctx *ctx, int32_t run, int32_t *lcr, int32_t *cell
                          int64_t cap, int64_t *n);
 
 /* Per-cell interaction state of one run: remainder, (sigma c_r)_max in units
- * of sigma_ref, cumulative accepted collisions (each array [nc], may be NULL). */
-dsmc_status dsmc_get_cell_state(dsmc_ctx *ctx, int32_t run, double *rem, double *gmax, int64_t *ncoll);
+ * of sigma_ref, cumulative accepted collisions and the running mean of the
+ * count (ntc_nbar_alpha; its start value when the run does not use it)
+ * (each array [nc], may be NULL). */
+dsmc_status dsmc_get_cell_state(dsmc_ctx *ctx, int32_t run, double *rem, double *gmax, int64_t *ncoll,
+                                double *nbar);
 
 /* Per run: [r][0] particles now, [r][1] particles generated in the last step. */
 dsmc_status dsmc_get_counts(dsmc_ctx *ctx, int64_t *out, int32_t n_runs);
@@ -265,7 +273,8 @@ dsmc_status dsmc_checkpoint_bytes(dsmc_ctx *ctx, size_t *bytes);
 /* Copy everything a later step reads into the host buffer `host` (at least
  * dsmc_checkpoint_bytes, 8-byte aligned): per run the particles (P in its
  * cell-sorted order, in the state precision, bit for bit) and their count, the
- * per-cell interaction state (remainder, (sigma c_r)_max, collision counter)
+ * per-cell interaction state (remainder, (sigma c_r)_max, running mean of the
+ * count, collision counter)
  * and bin starts, the inflow faces' carried remainders; the accumulators and
  * snapshot counts of every sample slot; the step counter.  The steps of the
  * runs are replayable from their Philox keys and the step counter (Sec. 1.1:

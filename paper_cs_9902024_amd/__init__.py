@@ -55,7 +55,7 @@ class dsmc_run_spec(C.Structure):
                 ("capacity", C.c_int64), ("n_init", C.c_int64), ("init_U", C.c_double * 3),
                 ("init_T", C.c_double), ("run_id", C.c_uint32), ("seed", C.c_uint32),
                 ("ensemble", C.c_int32), ("subcells", C.c_int32), ("solid_mask", C.c_void_p),
-                ("solid_T", C.c_double)]
+                ("solid_T", C.c_double), ("ntc_nbar_alpha", C.c_double)]
 
 
 class dsmc_options(C.Structure):
@@ -96,7 +96,7 @@ def lib():
         L.dsmc_get_state.argtypes = [vp, i32, dp, i64, C.POINTER(i64)]
         L.dsmc_set_state.argtypes = [vp, i32, dp, i64]
         L.dsmc_get_lcr.argtypes = [vp, i32, vp, vp, vp, i64, C.POINTER(i64)]
-        L.dsmc_get_cell_state.argtypes = [vp, i32, vp, vp, vp]
+        L.dsmc_get_cell_state.argtypes = [vp, i32, vp, vp, vp, vp]
         L.dsmc_get_counts.argtypes = [vp, C.POINTER(i64), i32]
         L.dsmc_counting_sort_bytes.argtypes = [i64, i32, C.POINTER(sz)]
         L.dsmc_counting_sort.argtypes = [vp, i64, i32, vp, vp, vp, sz, vp]
@@ -156,6 +156,7 @@ def make_run_spec(rs) -> dsmc_run_spec:
     s.run_id, s.seed = rs.run_id & 0xFFFFFFFF, rs.seed & 0xFFFFFFFF
     s.ensemble = rs.ensemble
     s.subcells = getattr(rs, "subcells", 1)
+    s.ntc_nbar_alpha = getattr(rs, "ntc_nbar_alpha", 0.0)
     return s
 
 
@@ -298,11 +299,11 @@ def dsmc_get_lcr(ctx, run: int, capacity: int, n_cells: int):
 
 
 def dsmc_get_cell_state(ctx, run: int, n_cells: int) -> dict:
-    rem, gmax = np.zeros(n_cells), np.zeros(n_cells)
+    rem, gmax, nbar = np.zeros(n_cells), np.zeros(n_cells), np.zeros(n_cells)
     ncoll = np.zeros(n_cells, np.int64)
-    _check(lib().dsmc_get_cell_state(ctx, run, rem.ctypes.data, gmax.ctypes.data, ncoll.ctypes.data),
-           "dsmc_get_cell_state", ctx)
-    return {"rem": rem, "gmax": gmax, "ncoll": ncoll}
+    _check(lib().dsmc_get_cell_state(ctx, run, rem.ctypes.data, gmax.ctypes.data, ncoll.ctypes.data,
+                                     nbar.ctypes.data), "dsmc_get_cell_state", ctx)
+    return {"rem": rem, "gmax": gmax, "ncoll": ncoll, "nbar": nbar}
 
 
 def dsmc_get_counts(ctx, n_runs: int) -> np.ndarray:

@@ -46,7 +46,7 @@ struct Plan {
       off_eg_acc,
       off_eg_nc, off_samples, off_items, off_cell_items, off_wave_items, off_solid;
   size_t off_P[2][2];  // per buffer: records (x, y, u, v); w (2-D) or (z, w) pairs (3-D)
-  size_t off_cell, off_lcr, off_lcr_tmp, off_hist, off_tot, off_bin_start, off_remc, off_gmax, off_ncoll, off_remf,
+  size_t off_cell, off_lcr, off_lcr_tmp, off_hist, off_tot, off_bin_start, off_remc, off_gmax, off_nbar, off_ncoll, off_remf,
       off_gencnt, off_stage, off_acc, off_mom, off_nalive, off_nsorted, off_ngen, off_scalars, off_wallq, off_wallq_n,
       off_key_tmp, off_bitem, off_bitem_run, off_bfirst;
   size_t total;
@@ -103,6 +103,8 @@ dsmc_status validate(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_optio
     if (nc * S + 2 >= ((int64_t)1 << 30))  // kQueueBit
       return fail(msg, DSMC_EINVAL, "run %d: too many cells (times sub-cells)", r);
     if (sub > 1 && s.solid_mask) return fail(msg, DSMC_EUNSUPPORTED, "run %d: sub-cells with solid cells", r);
+    if (!(s.ntc_nbar_alpha >= 0.0 && s.ntc_nbar_alpha <= 1.0))
+      return fail(msg, DSMC_EINVAL, "run %d: ntc_nbar_alpha must be in [0, 1]", r);
     if (!(s.lx > 0) || !(s.ly > 0) || !(s.lz > 0)) return fail(msg, DSMC_EINVAL, "run %d: bad box size", r);
     if (!(s.dt > 0) || !std::isfinite(s.dt)) return fail(msg, DSMC_EINVAL, "run %d: dt must be > 0", r);
     if (!(s.fnum_sigma >= 0)) return fail(msg, DSMC_EINVAL, "run %d: fnum_sigma must be >= 0", r);
@@ -179,6 +181,7 @@ uint64_t plan_fingerprint(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_
     f.add(s.capacity); f.add(s.n_init);
     for (int a = 0; a < 3; ++a) f.add(s.init_U[a]);
     f.add(s.init_T); f.add(s.run_id); f.add(s.seed); f.add(s.ensemble); f.add(s.subcells > 1 ? s.subcells : 1);
+    f.add(s.ntc_nbar_alpha);
     const int has = s.solid_mask ? 1 : 0;
     f.add(has);
     if (has) {
@@ -349,6 +352,8 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
     R.vhs_exp = 1.0 - 2.0 * s.omega;
     R.c_ref = s.c_ref;
     R.gmax0 = initial_gmax(s);
+    R.nbar_alpha = s.ntc_nbar_alpha;
+    R.nbar0 = (double)s.n_init / (double)R.nc;
     R.dy = s.ly / s.ny;
     R.dz = s.lz / s.nz;
     R.fo = fo;
@@ -589,6 +594,7 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
   P.off_bin_start = take(4 * (size_t)bo);
   P.off_remc = take(es * g.n_cells);
   P.off_gmax = take(es * g.n_cells);
+  P.off_nbar = take(es * g.n_cells);
   P.off_ncoll = take(4 * g.n_cells);
   P.off_remf = take(8 * g.n_faces);
   P.off_gencnt = take(4 * g.n_faces);
@@ -639,6 +645,7 @@ DevPtrs<real> carve(const Plan &P, char *base) {
   d.bin_start = (uint32_t *)(base + P.off_bin_start);
   d.rem_c = (real *)(base + P.off_remc);
   d.gmax = (real *)(base + P.off_gmax);
+  d.nbar = (real *)(base + P.off_nbar);
   d.ncoll = (uint32_t *)(base + P.off_ncoll);
   d.rem_f = (double *)(base + P.off_remf);
   d.gen_count = (int32_t *)(base + P.off_gencnt);
@@ -1150,12 +1157,13 @@ dsmc_status set_state_t(dsmc_ctx *c, const DevPtrs<real> &d, int32_t run, const 
 
 template <typename real>
 dsmc_status cell_state_t(dsmc_ctx *c, const DevPtrs<real> &d, int32_t run, double *rem, double *gmax,
-                         int64_t *ncoll) {
+                         int64_t *ncoll, double *nbar) {
   const RunDev &R = c->plan.runs[run];
-  std::vector<real> a((size_t)R.nc), b((size_t)R.nc);
+  std::vector<real> a((size_t)R.nc), b((size_t)R.nc), e((size_t)R.nc);
   std::vector<uint32_t> k((size_t)R.nc);
   dsmc_status st = download<real>(c, a.data(), d.rem_c + R.co, R.nc);
   if (!st) st = download<real>(c, b.data(), d.gmax + R.co, R.nc);
+  if (!st) st = download<real>(c, e.data(), d.nbar + R.co, R.nc);
   if (!st) st = download<uint32_t>(c, k.data(), d.ncoll + R.co, R.nc);
   if (!st) st = sync_ctx(c);
   if (st) return st;
@@ -1163,6 +1171,7 @@ dsmc_status cell_state_t(dsmc_ctx *c, const DevPtrs<real> &d, int32_t run, doubl
     if (rem) rem[i] = (double)a[i];
     if (gmax) gmax[i] = (double)b[i];
     if (ncoll) ncoll[i] = (int64_t)k[i];
+    if (nbar) nbar[i] = (double)e[i];
   }
   return DSMC_OK;
 }
@@ -1222,10 +1231,12 @@ dsmc_status dsmc_get_lcr(dsmc_ctx *c, int32_t run, int32_t *lcr, int32_t *cell, 
   return DSMC_OK;
 }
 
-dsmc_status dsmc_get_cell_state(dsmc_ctx *c, int32_t run, double *rem, double *gmax, int64_t *ncoll) {
+dsmc_status dsmc_get_cell_state(dsmc_ctx *c, int32_t run, double *rem, double *gmax, int64_t *ncoll,
+                                double *nbar) {
   if (!c || run < 0 || run >= c->plan.g.n_runs) return DSMC_EINVAL;
   if (c->latched) return c->latched;
-  return c->plan.g.fp64 ? cell_state_t(c, c->dd, run, rem, gmax, ncoll) : cell_state_t(c, c->df, run, rem, gmax, ncoll);
+  return c->plan.g.fp64 ? cell_state_t(c, c->dd, run, rem, gmax, ncoll, nbar)
+                        : cell_state_t(c, c->df, run, rem, gmax, ncoll, nbar);
 }
 
 dsmc_status dsmc_get_counts(dsmc_ctx *c, int64_t *out, int32_t n_runs) {
@@ -1280,7 +1291,7 @@ namespace {
 
 struct CkptHeader {
   char magic[8];           // "DSMCCKP1"
-  uint32_t version;        // 1
+  uint32_t version;        // 2 (per-cell running means of the count added)
   int32_t fp64;
   uint64_t fingerprint;    // Plan::fingerprint of the context it came from
   int64_t total;           // bytes of the whole checkpoint
@@ -1307,7 +1318,7 @@ size_t ckpt_bytes(const Plan &P, const std::vector<int32_t> &na) {
   for (int r = 0; r < g.n_runs; ++r) o += pad8(4 * es * (size_t)na[r]) + pad8(nr * es * (size_t)na[r]);
   for (int r = 0; r < g.n_runs; ++r) {
     const size_t nc = (size_t)P.runs[r].nc;
-    o += 2 * pad8(es * nc) + pad8(4 * nc) + pad8(4 * ((size_t)P.runs[r].nbin + 2));
+    o += 3 * pad8(es * nc) + pad8(4 * nc) + pad8(4 * ((size_t)P.runs[r].nbin + 2));
   }
   o += pad8(8 * (size_t)g.n_faces);
   o += pad8(8 * (size_t)g.acc_stride * g.n_samples);
@@ -1363,6 +1374,7 @@ dsmc_status ckpt_sections(dsmc_ctx *c, const DevPtrs<real> &d, char *host, const
     const RunDev &R = P.runs[r];
     move(d.rem_c + R.co, es * R.nc);
     move(d.gmax + R.co, es * R.nc);
+    move(d.nbar + R.co, es * R.nc);
     move(d.ncoll + R.co, 4 * (size_t)R.nc);
     move(d.bin_start + R.bo, 4 * ((size_t)R.nbin + 2));
   }
@@ -1390,7 +1402,7 @@ dsmc_status checkpoint_t(dsmc_ctx *c, const DevPtrs<real> &d, void *host, size_t
   if (st) return st;
   CkptHeader h{};
   std::memcpy(h.magic, kCkptMagic, 8);
-  h.version = 1;
+  h.version = 2;
   h.fp64 = c->plan.g.fp64;
   h.fingerprint = c->plan.fingerprint;
   h.total = (int64_t)need;
@@ -1411,7 +1423,7 @@ dsmc_status restore_t(dsmc_ctx *c, const DevPtrs<real> &d, const void *host, siz
   CkptHeader h;
   if (bytes < sizeof h) return set_err(c, DSMC_EINVAL, "restore: buffer smaller than a checkpoint header");
   std::memcpy(&h, host, sizeof h);
-  if (std::memcmp(h.magic, kCkptMagic, 8) || h.version != 1)
+  if (std::memcmp(h.magic, kCkptMagic, 8) || h.version != 2)
     return set_err(c, DSMC_EINVAL, "restore: not a checkpoint of this library");
   if (h.fp64 != g.fp64 || h.fingerprint != P.fingerprint || h.n_runs != g.n_runs || h.n_samples != g.n_samples)
     return set_err(c, DSMC_EINVAL, "restore: checkpoint of a context with other runs, precision or schedule");

@@ -90,6 +90,8 @@ struct RunDev {
   uint32_t key0, key1;   // Philox key: run id, seed
   double L[3], inv_d[3];
   double dt, coef, vhs_exp, c_ref, gmax0;
+  double nbar_alpha;     // NTC count from N * Nbar / 2 with this running-mean weight (0: N(N-1)/2)
+  double nbar0;          // start of the running mean: the expected count of the initial fill
   double face_T[6], face_sqrtT[6];
   double mbar, beta, s_inf, p_branch, inflow_sqrtT, dy, dz;
   double init_U[3], init_sqrtT;
@@ -188,6 +190,7 @@ struct DevPtrs {
   uint32_t *digit_tot;         // per run digit totals / digit starts
   uint32_t *bin_start;         // per run nc + 2 entries, run-local
   real *rem_c, *gmax;          // [cells]
+  real *nbar;                  // [cells] running mean of the count (runs with nbar_alpha > 0)
   uint32_t *ncoll;             // [cells] cumulative accepted collisions
   double *rem_f;               // [faces]
   int32_t *gen_count;          // [faces] this step's first entrant of each face element (run-local)

@@ -177,6 +177,7 @@ __global__ __launch_bounds__(256) void k_init_cells(DevPtrs<real> d, int64_t n_c
     if (gc - R.co >= R.nc) continue;
     d.rem_c[gc] = (real)0;
     d.gmax[gc] = (real)R.gmax0;
+    d.nbar[gc] = (real)R.nbar0;
     d.ncoll[gc] = 0;
   }
 }
@@ -1631,9 +1632,18 @@ __device__ uint32_t chain_serial(const RunT &R, uint32_t step, uint32_t c, uint3
 }
 
 // NTC bookkeeping: number of selections this step and the new remainder.
+// The pairs are N(N-1)/2, or with a running mean of the count (nbar_alpha >
+// 0, Bird's variant) N * Nbar / 2 after Nbar has moved towards N.
 template <typename real, typename RunT>
-__device__ __forceinline__ int64_t ntc_selections(const RunT &R, int64_t N, real gm, real &rem, int32_t *err) {
-  const real npairs = (real)0.5 * (real)(N * (N - 1));
+__device__ __forceinline__ int64_t ntc_selections(const RunT &R, int64_t N, real gm, real &rem, real &nb,
+                                                  int32_t *err) {
+  real npairs;
+  if (R.nbar_alpha > 0.0) {
+    nb = nb + (real)R.nbar_alpha * ((real)N - nb);
+    npairs = (real)0.5 * (real)N * nb;
+  } else {
+    npairs = (real)0.5 * (real)(N * (N - 1));
+  }
   const real M = npairs * (real)R.coef * gm + rem;
   int64_t nsel = 0;
   if (M >= (real)0 && M < (real)kMaxSelections) {
@@ -1930,7 +1940,9 @@ __device__ __forceinline__ void collide_lanes_item(const DevPtrs<real> &d, int s
       sub.base = (uint32_t)cs;
     }
     real gm = d.gmax[gc], rem = d.rem_c[gc];
-    const int64_t nsel = ntc_selections<real>(R, N, gm, rem, d.err);
+    real nb = R.nbar_alpha > 0.0 ? d.nbar[gc] : (real)0;
+    const int64_t nsel = ntc_selections<real>(R, N, gm, rem, nb, d.err);
+    if (R.nbar_alpha > 0.0) d.nbar[gc] = nb;
     uint32_t ncol;
     if (in_lds) {
       ncol = chain_serial<real>(R, step, (uint32_t)c, (uint32_t)N, 0, nsel, su + cb, sv + cb, sw + cb, gm, sub);
@@ -2210,6 +2222,7 @@ __device__ __forceinline__ void collide_cell_item(const DevPtrs<real> &d, int sr
   const uint32_t step = *d.step;
   const bool sample = *d.sample_slot >= 0;
   real gm = d.gmax[gc], rem = d.rem_c[gc];
+  real nb = R.nbar_alpha > 0.0 ? d.nbar[gc] : (real)0;
   // gather through LCR: whole records to P' (their velocities are replaced at
   // the write-back of an LDS item), velocities to LDS
   {
@@ -2253,7 +2266,8 @@ __device__ __forceinline__ void collide_cell_item(const DevPtrs<real> &d, int sr
     }
   }
   __syncthreads();
-  const int64_t nsel = ntc_selections<real>(R, n, gm, rem, d.err);
+  const int64_t nsel = ntc_selections<real>(R, n, gm, rem, nb, d.err);
+  if (tid == 0 && R.nbar_alpha > 0.0) d.nbar[gc] = nb;
   const Strided<real> gu = B.u() + (R.so + b0), gv = B.v() + (R.so + b0);
   const auto gw = w_view<DIM>(B, R.so + b0);
   uint32_t ncol = 0;
@@ -2367,7 +2381,9 @@ __device__ __forceinline__ void collide_wave_item(const DevPtrs<real> &d, int sr
   const uint32_t step = *d.step;
   const bool sample = *d.sample_slot >= 0;
   real gm = d.gmax[gc], rem = d.rem_c[gc];
-  const int64_t nsel = ntc_selections<real>(R, n, gm, rem, d.err);
+  real nb = R.nbar_alpha > 0.0 ? d.nbar[gc] : (real)0;
+  const int64_t nsel = ntc_selections<real>(R, n, gm, rem, nb, d.err);
+  if (lane == 0 && R.nbar_alpha > 0.0) d.nbar[gc] = nb;
   uint32_t ncol = 0;
   if (in_lds) {
     ncol = chain_block<real, WaveSync>(R, step, (uint32_t)c, (uint32_t)n, nsel, su, sv, sw, own[wave], shs[wave],
@@ -2434,7 +2450,7 @@ constexpr int kPipeChunks = kCollideCapF32 / 256;
 struct RunView {
   uint32_t key0, key1;
   int32_t hs;
-  double c_ref, vhs_exp, coef;
+  double c_ref, vhs_exp, coef, nbar_alpha;
 };
 
 struct PipeMeta {
@@ -2442,7 +2458,7 @@ struct PipeMeta {
   const uint32_t *sub_start;  // the cell's sub-cell bin starts, null without sub-cells
   int32_t c;
   uint32_t ncoll;
-  float gm, rem, dt;
+  float gm, rem, dt, nb;
   int32_t ahead;
   RunView rv;
   const RunDev *run;
@@ -2543,8 +2559,9 @@ __device__ __forceinline__ void pipe_collide(const DevPtrs<float> &d, const Part
   const int tid = threadIdx.x;
   const int64_t n = m.n;
   const bool lds = n <= kCollideCapF32;
-  float gm = m.gm, rem = m.rem;
-  const int64_t nsel = ntc_selections<float>(m.rv, n, gm, rem, d.err);
+  float gm = m.gm, rem = m.rem, nb = m.nb;
+  const int64_t nsel = ntc_selections<float>(m.rv, n, gm, rem, nb, d.err);
+  if (tid == 0 && m.rv.nbar_alpha > 0.0) d.nbar[m.gc] = nb;  // final now: not held through the chain
   uint32_t ncol = 0;
   const Strided<float> gu = B.u() + (m.so + m.b0), gv = B.v() + (m.so + m.b0);
   const auto gw = w_view<DIM>(B, m.so + m.b0);
@@ -2625,6 +2642,7 @@ __device__ __forceinline__ void collide_pipe_body(const DevPtrs<float> &d, int s
     m.ncoll = d.ncoll[m.gc];
     m.gm = d.gmax[m.gc];
     m.rem = d.rem_c[m.gc];
+    m.nb = R.nbar_alpha > 0.0 ? d.nbar[m.gc] : 0.f;
     m.dt = R.dt_f;
     m.ahead = R.ahead;
     m.run = &R;
@@ -2634,6 +2652,7 @@ __device__ __forceinline__ void collide_pipe_body(const DevPtrs<float> &d, int s
     m.rv.c_ref = R.c_ref;
     m.rv.vhs_exp = R.vhs_exp;
     m.rv.coef = R.coef;
+    m.rv.nbar_alpha = R.nbar_alpha;
     meta = m;
     flight = Flight<float>(R);
   }

@@ -3,6 +3,7 @@ include/dsmc.h declares, and validates / sizes run specs on the host."""
 import ctypes as C
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -35,10 +36,30 @@ def test_every_declared_symbol_is_exported(dsmc):
     assert sorted(dsmc.EXPORTS) == syms
 
 
-def test_struct_sizes_match_header(dsmc):
-    # layout of the two public structs (x86-64 SysV ABI)
-    assert C.sizeof(dsmc.dsmc_run_spec) == 248
-    assert C.sizeof(dsmc.dsmc_options) == 56
+def test_struct_sizes_match_header(dsmc, tmp_path):
+    """The binding's ctypes layouts equal the C compiler's for the header:
+    size and every field offset of the two public structs."""
+    fields = {"dsmc_run_spec": [f for f, _ in dsmc.dsmc_run_spec._fields_],
+              "dsmc_options": [f for f, _ in dsmc.dsmc_options._fields_]}
+    src = ["#include <stddef.h>", "#include <stdio.h>", '#include "dsmc.h"', "int main(void) {"]
+    for st, fs in fields.items():
+        src.append(f'  printf("{st} %zu\\n", sizeof({st}));')
+        for f in fs:
+            src.append(f'  printf("{st}.{f} %zu\\n", offsetof({st}, {f}));')
+    src.append("  return 0; }")
+    c_file = tmp_path / "layout.c"
+    c_file.write_text("\n".join(src) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(c_file), "-o", str(exe)],
+                   check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                        check=True).stdout.splitlines())
+    for st, fs in fields.items():
+        cls = getattr(dsmc, st)
+        assert int(out[st]) == C.sizeof(cls), st
+        for f in fs:
+            assert int(out[f"{st}.{f}"]) == getattr(cls, f).offset, (st, f)
+    assert C.sizeof(dsmc.dsmc_run_spec) == 256 and C.sizeof(dsmc.dsmc_options) == 56
 
 
 def test_array_lengths_match_header(dsmc):
@@ -89,7 +110,8 @@ def test_required_bytes_scale_with_the_workload(dsmc):
 
 @pytest.mark.parametrize("field,value", [("dim", 4), ("nx", 0), ("dt", 0.0), ("dt", -1.0),
                                          ("omega", 0.3), ("capacity", 10), ("n_init", -1),
-                                         ("fnum_sigma", -1.0)])
+                                         ("fnum_sigma", -1.0), ("ntc_nbar_alpha", -0.1),
+                                         ("ntc_nbar_alpha", 1.5), ("ntc_nbar_alpha", float("nan"))])
 def test_invalid_specs_are_rejected_on_the_host(dsmc, field, value):
     from dataclasses import replace
     rs = replace(W.plain_box().runs[0], **{field: value})

@@ -314,6 +314,24 @@ def test_subcell_interaction_modes_give_identical_results(dsmc_gpu, mode):
     assert sum(int(A.cell_state(r)["ncoll"].sum()) for r in range(len(runs))) > 1000
 
 
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_running_mean_count_modes_give_identical_results(dsmc_gpu, mode):
+    """With Bird's N * Nbar / 2 count the FP32 lane, block and wavefront
+    kernels still make the same selections: identical states, collision
+    counts, running means and sample sums."""
+    runs = [replace(r, ntc_nbar_alpha=0.2) for r in _mixed_mode_runs()]
+    A = dsmc_gpu.Ensemble(runs, [3], state_fp64=False, n_groups=1, collide_mode=0)
+    B = dsmc_gpu.Ensemble(runs, [3], state_fp64=False, n_groups=1, collide_mode=mode, sched=1)
+    for E in (A, B):
+        E.step(4)
+    for r in range(len(runs)):
+        np.testing.assert_array_equal(A.state(r), B.state(r))
+        for k in ("ncoll", "nbar", "rem"):
+            np.testing.assert_array_equal(A.cell_state(r)[k], B.cell_state(r)[k])
+    for e in range(len(runs)):
+        np.testing.assert_array_equal(A.accum(0, ensemble=e), B.accum(0, ensemble=e))
+
+
 def test_tune_cache_returns_the_stored_result(dsmc_gpu, tmp_path):
     """The first autotune of a problem times the candidates and appends its
     pick to the cache file; the second finds it there (no timing); another

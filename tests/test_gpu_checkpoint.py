@@ -26,7 +26,7 @@ def _same(A, B, n_runs, tag):
     for r in range(n_runs):
         np.testing.assert_array_equal(A.state(r), B.state(r), err_msg=f"{tag}: state of run {r}")
         ca, cb = A.cell_state(r), B.cell_state(r)
-        for k in ("rem", "gmax", "ncoll"):
+        for k in ("rem", "gmax", "ncoll", "nbar"):
             np.testing.assert_array_equal(ca[k], cb[k], err_msg=f"{tag}: {k} of run {r}")
     np.testing.assert_array_equal(A.counts(), B.counts(), err_msg=tag)
     np.testing.assert_array_equal(A.sample_counts(), B.sample_counts(), err_msg=tag)
@@ -35,14 +35,16 @@ def _same(A, B, n_runs, tag):
     np.testing.assert_array_equal(A.diag(), B.diag(), err_msg=tag)
 
 
-@pytest.mark.parametrize("fp64,sub", [(False, 1), (True, 1), (False, 3)])
-def test_checkpoint_resume_is_bit_identical(dsmc_gpu, fp64, sub):
+@pytest.mark.parametrize("fp64,sub,alpha", [(False, 1, 0.0), (True, 1, 0.0), (False, 3, 0.0), (True, 1, 0.4),
+                                            (False, 1, 0.4)])
+def test_checkpoint_resume_is_bit_identical(dsmc_gpu, fp64, sub, alpha):
     """Checkpoint after 7 steps, restore into a fresh context with another
     tile size and graph replay, and step both 9 more: identical particles,
     cell state, accumulators (slots on both sides of the checkpoint and one
     window across it), counts and diagnostics; LCR of the next step too
-    (with 3 x 3 sub-cells: the LCR and bin starts are by sub-cell)."""
-    runs = [replace(r, subcells=sub) for r in _channel_runs(5)]
+    (with 3 x 3 sub-cells: the LCR and bin starts are by sub-cell; with the
+    running-mean count: the per-cell means too)."""
+    runs = [replace(r, subcells=sub, ntc_nbar_alpha=alpha) for r in _channel_runs(5)]
     kw = dict(state_fp64=fp64, n_groups=2, window_steps=3, window_stride=2)
     A = dsmc_gpu.Ensemble(runs, [4, 9, 16], **kw)
     A.step(7)

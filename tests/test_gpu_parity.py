@@ -46,6 +46,7 @@ def _compare_run(E, r, O, rs, where):
     np.testing.assert_array_equal(cg["ncoll"], co["ncoll"], err_msg=where)
     np.testing.assert_allclose(cg["gmax"], co["gmax"], rtol=TOL, err_msg=where)
     np.testing.assert_allclose(cg["rem"], co["rem"], rtol=0, atol=TOL, err_msg=where)
+    np.testing.assert_allclose(cg["nbar"], co["nbar"], rtol=TOL, atol=TOL, err_msg=where)
 
 
 def _parity(dsmc_gpu, oracle_lib, runs, n_steps, check_every=1, squeeze=None, **kw):
@@ -254,6 +255,32 @@ def test_subcell_partners_channel_and_beyond_lds_fp64(dsmc_gpu, oracle_lib):
     _parity(dsmc_gpu, oracle_lib, big, 2, collide_mode=3)
     wide = _sub(W.box(30_000, 1, 3, 3, seed=99, grid=(32, 32)).runs, 2)     # 4096 bins
     _parity(dsmc_gpu, oracle_lib, wide, 3)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+@pytest.mark.parametrize("alpha", [0.3, 1.0])
+def test_ntc_running_mean_count_fp64(dsmc_gpu, oracle_lib, mode, alpha):
+    """Bird's N * Nbar / 2 count with a running mean per cell, in the auto
+    mode and every forced mode, on cells of ~150 particles (2-D) and ~40
+    (3-D): the running means and remainders within 1e-12, everything else as
+    for the pair count."""
+    wl = W.box(150 * 64, 2, 4, 4, seed=110 + mode, grid=(8, 8))
+    runs = [replace(r, ntc_nbar_alpha=alpha) for r in wl.runs]
+    O = _parity(dsmc_gpu, oracle_lib, runs, 4, collide_mode=mode)
+    nb = O[0].cell_state()["nbar"]
+    assert not np.allclose(nb, 150.0)      # the means moved with the counts
+    w3 = W.box3d(n_per_run=40 * 120, n_runs=1, grid=(6, 5, 4), seed=115 + mode, wall="diffuse", wall_T=1.2)
+    _parity(dsmc_gpu, oracle_lib, [replace(r, ntc_nbar_alpha=alpha) for r in w3.runs], 3, collide_mode=mode)
+
+
+def test_ntc_running_mean_count_channel_fp64(dsmc_gpu, oracle_lib):
+    """A channel filling through its inflow face (counts change step by step,
+    empty cells start at a zero mean) with a slow running mean, next to a run
+    that keeps the pair count."""
+    a = W.channel_run(nx=32, ny=8, lx=2.0, ly=0.5, ppc_inf=30.0, run_id=0, seed=118)
+    a = replace(a, n_init=3000, init_U=(a.inflow_U, 0.0, 0.0), ntc_nbar_alpha=0.1)
+    b = replace(a, run_id=1, ntc_nbar_alpha=0.0)
+    _parity(dsmc_gpu, oracle_lib, [a, b], 6)
 
 
 def test_zz_worst_parity_differences():
