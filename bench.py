@@ -36,8 +36,8 @@ Beside it the line carries:
   accumulator_precision  per macroparameter, the error FP32 accumulators and
                 division would have added to the batch's first sample (its
                 run groups' sums added and divided in FP32) against the FP64
-                ones, beside the sample's relative standard error (box and
-                body flow).
+                ones, beside the sample's relative standard error (the
+                first ensemble of the batch).
 
 ``--workload body3d`` times the flow past a body at full size instead (32 runs
 x 60M particles, 2M cells, solid-cell obstacle); ``channel`` (16 runs of the
@@ -258,13 +258,14 @@ def run_gpu(args):
     # macroparameter (after the timed and profiled steps; the body flow steps
     # on to its first sample step)
     acc_prec = None
-    if args.workload in ("ensemble_box", "body3d") and wl.sample_steps:
+    if wl.sample_steps:
         done = warmup + args.steps + args.prof_steps
         if done < wl.sample_steps[0]:
             E.step(wl.sample_steps[0] - done)
-        m64, se = E.moments(0)
-        acc_prec = accumulator_precision(E.accum(0), m64, se, n_runs)
+        m64, se = E.moments(0)                         # ensemble 0
+        acc_prec = accumulator_precision(E.accum(0), m64, se, sum(1 for r in wl.runs if r.ensemble == 0))
         acc_prec["step"] = wl.sample_steps[0]
+        acc_prec["ensemble"] = 0
     E.close()
     del E
     torch.cuda.empty_cache()
@@ -392,9 +393,11 @@ def accumulator_precision(acc, m64, se, n_runs: int) -> dict:
     for k, e in errs.items():
         e = e[ok & np.isfinite(e)]
         c = cols[k]
-        rel_se = se[ok, c] / (np.abs(m64[ok, c]) if k in ("n", "T") else scale[ok])
+        with np.errstate(divide="ignore", invalid="ignore"):
+            rel_se = se[ok, c] / (np.abs(m64[ok, c]) if k in ("n", "T") else scale[ok])
+        rel_se = rel_se[np.isfinite(rel_se)]      # none with a single run group
         out[k] = {"max_err": float(e.max()) if e.size else None, "median_err": float(np.median(e)) if e.size else None,
-                  "median_rel_se": float(np.nanmedian(rel_se)) if rel_se.size else None}
+                  "median_rel_se": float(np.median(rel_se)) if rel_se.size else None}
     return out
 
 
@@ -584,6 +587,18 @@ def oracle_match(gpu, ora, rs):
                     "independent seeds; standard errors from run groups (batch means)"}
 
 
+def _json_safe(x):
+    """The line as strict JSON: non-finite numbers become null."""
+    import math
+    if isinstance(x, dict):
+        return {k: _json_safe(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [_json_safe(v) for v in x]
+    if isinstance(x, float) and not math.isfinite(x):
+        return None
+    return x
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -666,7 +681,7 @@ def main():
     }
     if balance is not None:
         line["balance"] = balance
-    print(json.dumps(line))
+    print(json.dumps(_json_safe(line)))
 
 
 if __name__ == "__main__":

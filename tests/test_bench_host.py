@@ -108,3 +108,10 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_line_is_strict_json(bench):
+    import json
+    line = {"a": float("nan"), "b": [1.0, float("inf")], "c": {"d": 2, "e": -float("inf")}}
+    out = json.dumps(bench._json_safe(line), allow_nan=False)
+    assert json.loads(out) == {"a": None, "b": [1.0, None], "c": {"d": 2, "e": None}}
