@@ -13,7 +13,8 @@ constexpr int kWavesPerBlock = 4;          // 256-thread blocks
 constexpr int kCollideWaves = 2;           // waves per block of the collide kernel
 constexpr int kCollideCapF32 = 1280;       // particles staged in LDS per collide wavefront
 constexpr int kCollideCapF64 = 1024;
-constexpr int kWaveCapF32 = 512;           // particles staged in LDS per wavefront-per-cell item
+constexpr int kWaveCapF32 = 384;           // particles staged in LDS per wavefront-per-cell item (a larger
+                                           // stage fits fewer blocks per CU)
 constexpr int kWaveCapF64 = 256;
 constexpr int kLaneCapF32 = 640;           // particles staged in LDS per lane-per-cell wavefront
 constexpr int kLaneCapF64 = 512;

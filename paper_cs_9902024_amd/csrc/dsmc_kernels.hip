@@ -2020,7 +2020,6 @@ __global__ __launch_bounds__(kCollideWaves * 64) void k_collide(DevPtrs<real> d,
 // the window restarts at ks + 1.
 template <typename real>
 struct BlockScratch {
-  double red[4][kFields];
   int32_t vote[2][kWavesPerBlock];  // per-wavefront partial results of LdsSync::any / count
   int32_t ks;
   uint32_t ncol;
