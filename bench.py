@@ -33,6 +33,8 @@ Beside it the line carries:
                 the same problem at step 20 (the 128 runs above, other seeds):
                 z = difference / combined standard error per cell, and the
                 relative error; also against the exact equilibrium values;
+  paper_figures the paper's own speedup and efficiency parameters with the
+                machine it names (context: a whole program on an SPP-1600);
   accumulator_precision  per macroparameter, the error FP32 accumulators and
                 division would have added to the batch's first sample (its
                 run groups' sums added and divided in FP32) against the FP64
@@ -60,6 +62,18 @@ sys.path.insert(0, ROOT)
 METRIC = "particle-steps/sec (batched FP32 vs plain FP64) at 3σ/1% oracle match; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 FILL_STEPS = 600  # steps from vacuum before the unsteady workloads are timed
+# The paper's own figures, with the machine it names: parallel-efficiency
+# parameters of a whole DSMC program on a shared-memory multiprocessor (Sec.
+# 2-3), not throughputs of this path, so they are context, not a baseline.
+PAPER_FIGURES = {
+    "machine": "HP/Convex Exemplar SPP-1600: 8 processors, 2 GB memory, 1600 Mflops peak",
+    "tlp_comet_flow": {"problem": "unsteady 3-D water-vapour flow in a comet's inner atmosphere",
+                       "p1": 6, "p2": "1..6", "alpha1": 0.998, "alpha2": 0.97},
+    "tlpdpr_body_flow": {"problem": "unsteady flow past a body", "beta": 0.437, "p1": 6, "p": 36,
+                         "max_level2_speedup_eq11": 2.3, "tlp_fraction_of_max": 0.80,
+                         "tlpdpr_fraction_of_max_at_optimal_pri": 0.93,
+                         "tlpdpr_equivalent_tlp_processors": 120},
+}
 WORKLOAD_TEXT = {
     "ensemble_box": ("ensemble_box: {runs} independent runs x {per_run} hard-sphere particles, 2-D 1x1 "
                      "specular box, 32x32 cells, Kn 0.05, dt = 0.2 mean collision times, FP32 state, FP64 "
@@ -432,7 +446,7 @@ def balance_experiment(args):
     mode (one kernel; its processors are wavefronts).
 
     - beta of sampled runs: each run alone, its Interaction timed on persistent
-      grids of 1 .. 2048 wavefronts drawing from its queue; Amdahl fit.
+      grids of 2 .. 2048 wavefronts drawing from its queue; Amdahl fit.
     - the batch after the fill: static (sched 2: p2 wavefronts tied to each
       run) and dynamic (sched 1: p2 x runs wavefronts drawing from one queue)
       for p2 = 1, 2, 4, 8; achieved level-2 speedups S = T_static(1) / T.
@@ -674,6 +688,7 @@ def main():
         "cpu_baseline": cpu,
         "oracle_match": match,
         "accumulator_precision": g["acc_prec"],
+        "paper_figures": PAPER_FIGURES,
         "plain_fp64": g["plain"],
         "batched_over_plain": (g["value"] / g["plain"]["value"]) if g["plain"] else None,
         "kernels": g["kernels"],
