@@ -105,23 +105,30 @@ dsmc_status validate(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_optio
     if (sub > 1 && s.solid_mask) return fail(msg, DSMC_EUNSUPPORTED, "run %d: sub-cells with solid cells", r);
     if (!(s.ntc_nbar_alpha >= 0.0 && s.ntc_nbar_alpha <= 1.0))
       return fail(msg, DSMC_EINVAL, "run %d: ntc_nbar_alpha must be in [0, 1]", r);
-    if (!(s.lx > 0) || !(s.ly > 0) || !(s.lz > 0)) return fail(msg, DSMC_EINVAL, "run %d: bad box size", r);
+    if (!(s.lx > 0) || !(s.ly > 0) || !(s.lz > 0) || !std::isfinite(s.lx) || !std::isfinite(s.ly) ||
+        !std::isfinite(s.lz))
+      return fail(msg, DSMC_EINVAL, "run %d: bad box size", r);
     if (!(s.dt > 0) || !std::isfinite(s.dt)) return fail(msg, DSMC_EINVAL, "run %d: dt must be > 0", r);
-    if (!(s.fnum_sigma >= 0)) return fail(msg, DSMC_EINVAL, "run %d: fnum_sigma must be >= 0", r);
+    if (!(s.fnum_sigma >= 0) || !std::isfinite(s.fnum_sigma))
+      return fail(msg, DSMC_EINVAL, "run %d: fnum_sigma must be finite and >= 0", r);
     if (!(s.omega >= 0.5 && s.omega <= 1.0)) return fail(msg, DSMC_EINVAL, "run %d: omega must be in [0.5, 1]", r);
-    if (!(s.c_ref > 0)) return fail(msg, DSMC_EINVAL, "run %d: c_ref must be > 0", r);
+    if (!(s.c_ref > 0) || !std::isfinite(s.c_ref)) return fail(msg, DSMC_EINVAL, "run %d: c_ref must be > 0", r);
     for (int f = 0; f < 2 * dim; ++f) {
       const int bc = s.face_bc[f];
       if (bc < 0 || bc > 3) return fail(msg, DSMC_EINVAL, "run %d: face %d: unknown boundary", r, f);
       if (bc == DSMC_BC_INFLOW && f != 0) return fail(msg, DSMC_EINVAL, "run %d: inflow only on -x (face %d)", r, f);
-      if (bc == DSMC_BC_DIFFUSE && !(s.face_T[f] > 0))
-        return fail(msg, DSMC_EINVAL, "run %d: face %d: diffuse wall needs T > 0", r, f);
+      if (bc == DSMC_BC_DIFFUSE && (!(s.face_T[f] > 0) || !std::isfinite(s.face_T[f])))
+        return fail(msg, DSMC_EINVAL, "run %d: face %d: diffuse wall needs a finite T > 0", r, f);
     }
-    if (s.face_bc[0] == DSMC_BC_INFLOW && (!(s.inflow_n >= 0) || !(s.inflow_U >= 0) || !(s.inflow_T > 0)))
+    if (s.face_bc[0] == DSMC_BC_INFLOW &&
+        (!(s.inflow_n >= 0) || !(s.inflow_U >= 0) || !(s.inflow_T > 0) || !std::isfinite(s.inflow_n) ||
+         !std::isfinite(s.inflow_U) || !std::isfinite(s.inflow_T)))
       return fail(msg, DSMC_EINVAL, "run %d: bad inflow state", r);
     if (s.n_init < 0 || s.capacity < s.n_init || s.capacity >= ((int64_t)1 << 31) - (1 << 22))
       return fail(msg, DSMC_EINVAL, "run %d: need 0 <= n_init <= capacity < 2^31 - 2^22", r);
-    if (s.n_init > 0 && !(s.init_T > 0)) return fail(msg, DSMC_EINVAL, "run %d: init_T must be > 0", r);
+    if (s.n_init > 0 && (!(s.init_T > 0) || !std::isfinite(s.init_T) || !std::isfinite(s.init_U[0]) ||
+                         !std::isfinite(s.init_U[1]) || !std::isfinite(s.init_U[2])))
+      return fail(msg, DSMC_EINVAL, "run %d: the initial gas needs a finite init_U and init_T > 0", r);
     if (s.solid_mask) {
       if (!(s.solid_T > 0) || !std::isfinite(s.solid_T))
         return fail(msg, DSMC_EINVAL, "run %d: solid_T must be > 0", r);

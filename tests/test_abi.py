@@ -108,10 +108,15 @@ def test_required_bytes_scale_with_the_workload(dsmc):
     assert big64 > 1.6 * big
 
 
-@pytest.mark.parametrize("field,value", [("dim", 4), ("nx", 0), ("dt", 0.0), ("dt", -1.0),
+INF, NAN = float("inf"), float("nan")
+
+
+@pytest.mark.parametrize("field,value", [("dim", 4), ("nx", 0), ("dt", 0.0), ("dt", -1.0), ("dt", INF),
                                          ("omega", 0.3), ("capacity", 10), ("n_init", -1),
-                                         ("fnum_sigma", -1.0), ("ntc_nbar_alpha", -0.1),
-                                         ("ntc_nbar_alpha", 1.5), ("ntc_nbar_alpha", float("nan"))])
+                                         ("fnum_sigma", -1.0), ("fnum_sigma", INF), ("ntc_nbar_alpha", -0.1),
+                                         ("ntc_nbar_alpha", 1.5), ("ntc_nbar_alpha", NAN), ("lx", INF),
+                                         ("ly", NAN), ("c_ref", INF), ("init_T", INF),
+                                         ("init_U", (NAN, 0.0, 0.0)), ("init_U", (0.0, INF, 0.0))])
 def test_invalid_specs_are_rejected_on_the_host(dsmc, field, value):
     from dataclasses import replace
     rs = replace(W.plain_box().runs[0], **{field: value})
@@ -126,6 +131,19 @@ def test_inflow_only_on_minus_x(dsmc):
     bad = replace(rs, face_bc=("specular", "inflow") + rs.face_bc[2:])
     with pytest.raises(dsmc.DsmcError):
         _bytes(dsmc, W.plain_box().with_runs([bad]))
+
+
+@pytest.mark.parametrize("field,value", [("inflow_n", INF), ("inflow_U", NAN), ("inflow_T", INF),
+                                         ("face_T", (INF,) * 6)])
+def test_non_finite_boundary_state_is_rejected(dsmc, field, value):
+    from dataclasses import replace
+    rs = W.channel_run(nx=16, ny=8, lx=1.0)
+    if field == "face_T":
+        rs = replace(rs, face_bc=("inflow", "outflow", "diffuse", "diffuse", "specular", "specular"))
+    _bytes(dsmc, W.plain_box().with_runs([rs]))
+    with pytest.raises(dsmc.DsmcError) as e:
+        _bytes(dsmc, W.plain_box().with_runs([replace(rs, **{field: value})]))
+    assert e.value.status == -1
 
 
 def test_ensemble_runs_must_share_a_grid(dsmc):
