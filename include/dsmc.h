@@ -336,10 +336,11 @@ dsmc_status dsmc_autotune_bytes(const dsmc_run_spec *runs, int32_t n_runs, const
  * the fastest tuning fields; *best_ms_per_step (may be NULL) its time per
  * step.  tune_cache (may be NULL) names a text file of earlier results: when
  * it holds a result for the same run specs, precision, groups, schedule,
- * window, graph replay, device and starting step, that result is returned
- * without timing (and without touching the arena); otherwise the new result
- * is appended to it.  Concurrent writers of one cache file are not
- * supported.  The arena holds no usable context afterwards.  Synchronises. */
+ * window, graph replay, device and starting step, that result (the last
+ * such line) is returned without timing (and without touching the arena);
+ * otherwise, or when that line holds settings dsmc_init_runs would refuse,
+ * the candidates are timed and the new result is appended to it.
+ * Concurrent writers of one cache file are not supported.  The arena holds no usable context afterwards.  Synchronises. */
 dsmc_status dsmc_autotune(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_options *opt, void *arena,
                           size_t arena_bytes, void *hip_stream, int32_t n_steps, const void *start,
                           size_t start_bytes, const char *tune_cache, dsmc_options *best,

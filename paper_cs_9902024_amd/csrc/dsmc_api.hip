@@ -1737,7 +1737,9 @@ dsmc_status dsmc_autotune(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_
   if (tune_cache) {
     dsmc_options cached = base;
     double ms = -1.0;
-    if (tune_cache_find(tune_cache, key, cached, ms)) {
+    // (a line whose settings the library would refuse, say an edited
+    // file, is no answer: the candidates are timed again)
+    if (tune_cache_find(tune_cache, key, cached, ms) && validate(runs, n_runs, &cached, nullptr) == DSMC_OK) {
       *best = cached;
       if (best_ms_per_step) *best_ms_per_step = ms;
       return DSMC_OK;

@@ -347,6 +347,13 @@ def test_tune_cache_returns_the_stored_result(dsmc_gpu, tmp_path):
     c = dsmc_gpu.Ensemble.autotune(_small_channel_runs(4, seed=32), [3], n_steps=1, tune_cache=path)
     assert not c["from_cache"]
     assert len(open(path).read().splitlines()) == 2
+    # a later line for the same problem with settings the library refuses
+    # (tile_chunks 3) is no answer: the problem is timed again
+    key = " ".join(open(path).read().splitlines()[0].split()[:2])
+    with open(path, "a") as f:
+        f.write(f"{key} 3 0 1 0 0 0.5\n")
+    d = dsmc_gpu.Ensemble.autotune(runs, [3], n_steps=1, tune_cache=path)
+    assert not d["from_cache"] and d["tile_chunks"] in (64, 128, 256)
 
 
 def test_autotune_from_a_checkpoint(dsmc_gpu, tmp_path):
