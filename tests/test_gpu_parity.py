@@ -150,6 +150,30 @@ def test_uneven_runs_fp64(dsmc_gpu, oracle_lib):
         np.testing.assert_allclose(E.accum(0, ensemble=r)[0], O[r].sample(), rtol=TOL, atol=TOL)
 
 
+@pytest.mark.parametrize("graph,lanes", [(False, 1), (True, 1), (False, 2)])
+def test_mixed_interaction_modes_fp64(dsmc_gpu, oracle_lib, graph, lanes):
+    """One batch whose runs need all three Interaction modes (~20, ~160 and
+    ~620 expected particles per cell: a lane, a wavefront and a block per
+    cell), eagerly and replayed from a graph, in one or two stream lanes:
+    step by step equal to the oracle."""
+    sparse = W.box(5000, 1, 4, 4, seed=16, grid=(16, 16)).runs[0]
+    mid = replace(W.box(40000, 1, 4, 4, seed=16, grid=(16, 16)).runs[0], run_id=1, ensemble=1)
+    dense = replace(W.box(40000, 1, 4, 4, seed=16, grid=(8, 8)).runs[0], run_id=2, ensemble=2)
+    runs = [sparse, mid, dense, replace(sparse, run_id=3, ensemble=3)]
+    E = dsmc_gpu.Ensemble(runs, sample_steps=[4], state_fp64=True, n_groups=1, use_graph=graph,
+                          n_streams=lanes)
+    O = [oracle_lib.OracleRun(r) for r in runs]
+    for s in range(1, 5):
+        E.step(1)
+        for o in O:
+            o.step()
+        for r, rs in enumerate(runs):
+            _compare_run(E, r, O[r], rs, f"run {r} step {s}")
+    for r in range(len(runs)):
+        np.testing.assert_allclose(E.accum(0, ensemble=r)[0], O[r].sample(), rtol=TOL, atol=TOL)
+    E.close()
+
+
 def test_dense_cells_one_wave_per_cell_fp64(dsmc_gpu, oracle_lib):
     """~390 particles per cell: one 256-thread block per cell (the auto
     mode), 256 selections per window in conflict-free levels; the first steps
