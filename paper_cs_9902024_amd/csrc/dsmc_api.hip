@@ -424,6 +424,20 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
             }
           }
       P.solid.resize(round_up((int64_t)P.solid.size(), 256), 0);
+      {
+        // bit 1: within two cells (Chebyshev) of a solid cell
+        uint8_t *m = P.solid.data() + R.sdo;
+        const int32_t nx = s.nx, ny = s.ny, nz = s.nz, rz = s.dim == 3 ? 2 : 0;
+        for (int32_t iz = 0; iz < nz; ++iz)
+          for (int32_t iy = 0; iy < ny; ++iy)
+            for (int32_t ix = 0; ix < nx; ++ix) {
+              if (!(m[((int64_t)iz * ny + iy) * nx + ix] & kMaskSolid)) continue;
+              for (int32_t jz = std::max(0, iz - rz); jz <= std::min(nz - 1, iz + rz); ++jz)
+                for (int32_t jy = std::max(0, iy - 2); jy <= std::min(ny - 1, iy + 2); ++jy)
+                  for (int32_t jx = std::max(0, ix - 2); jx <= std::min(nx - 1, ix + 2); ++jx)
+                    m[((int64_t)jz * ny + jy) * nx + jx] |= kMaskNearSolid;
+            }
+      }
       for (int a = 0; a < 3; ++a) {
         R.slo[a] = (R.sb_lo[a] - 2) * R.d[a];
         R.shi[a] = (R.sb_hi[a] + 3) * R.d[a];
@@ -897,7 +911,12 @@ dsmc_status dsmc_init_runs(const dsmc_run_spec *runs, int32_t n_runs, const dsmc
   const Plan &P = c->plan;
   if (P.g.fp64) c->dd = carve<double>(P, c->arena);
   else c->df = carve<float>(P, c->arena);
-  st = upload(c, P.off_runs, P.runs);
+  {
+    // the runs' device pointers to their cell masks
+    std::vector<RunDev> runs = P.runs;
+    for (RunDev &R : runs) R.mask = R.has_solid ? (const uint8_t *)(c->arena + P.off_solid + R.sdo) : nullptr;
+    st = upload(c, P.off_runs, runs);
+  }
   if (!st) st = upload(c, P.off_tile_run, P.tile_run);
   if (!st) st = upload(c, P.off_bitem_run, P.bitem_run);
   if (!st) st = upload(c, P.off_face_run, P.face_run);

@@ -109,7 +109,14 @@ struct RunDev {
   double slo[3], shi[3];
   double inv_bin[3];     // Indexing bins per unit length along each axis: cells, or sub-cells with
   float inv_bin_f[3];    // sub-cells (equal to inv_d without them)
+  // the run's cell mask in device memory (null without solid cells): bit 0
+  // the cell is solid, bit 1 a solid cell lies within two cells of it
+  // (Chebyshev distance, the solid cells included)
+  const uint8_t *mask;
 };
+
+constexpr uint8_t kMaskSolid = 1;
+constexpr uint8_t kMaskNearSolid = 2;
 
 // How an Interaction kernel's workgroups get their items (see the kernels).
 enum : int32_t { kSchedGrid = 0, kSchedQueue = 1, kSchedPerRun = 2 };

@@ -267,7 +267,7 @@ __global__ __launch_bounds__(256) void k_init_particles(DevPtrs<real> d, int64_t
       pos[0] = ux * (real)R.L[0];
       pos[1] = uy * (real)R.L[1];
       pos[2] = DIM == 3 ? uz * (real)R.L[2] : (real)0;
-      if (!R.has_solid || !d.solid[R.sdo + cell_of<real, DIM>(R, pos)]) break;
+      if (!R.has_solid || !(d.solid[R.sdo + cell_of<real, DIM>(R, pos)] & kMaskSolid)) break;
     }
     P.q[i] = make_vec4<real>(pos[0], pos[1], u0, v0);
     store_zw<DIM>(P, i, pos[2], w0);
@@ -457,7 +457,7 @@ __device__ __forceinline__ int solid_walk(const RunDev &R, const uint8_t *solid,
     for (int a = 0; a < DIM; ++a)
       if (a == ax) na = nv[a];
     if (na < 0 || na >= n[ax]) return -1;  // a domain face: not the walk's
-    if (solid[R.sdo + ((int64_t)nv[2] * R.ny + nv[1]) * R.nx + nv[0]]) {
+    if (solid[R.sdo + ((int64_t)nv[2] * R.ny + nv[1]) * R.nx + nv[0]] & kMaskSolid) {
       th = tn > (real)0 ? tn : (real)0;
       return ax;
     }
@@ -609,7 +609,7 @@ __device__ __forceinline__ int32_t move_one(const RunDev &R, const uint8_t *soli
   if (pos[0] < (real)0) return R.nbin;  // generated upstream and never entered
   if (R.sub > 1) return bin_of<real, DIM>(R, pos);  // (no solid cells with sub-cells)
   int32_t c = cell_of<real, DIM>(R, pos);
-  if (R.has_solid && solid[R.sdo + c]) {
+  if (R.has_solid && (solid[R.sdo + c] & kMaskSolid)) {
     // rounding put the end point across the face of a solid cell: it belongs
     // to the fluid cell the path ended in
     const int32_t n[3] = {R.nx, R.ny, R.nz};
@@ -671,6 +671,7 @@ struct Flight {
   real dt, L[3], inv[3], slo[3], shi[3];
   int32_t n[3];
   bool solid;
+  const uint8_t *mask;  // the run's cell mask (runs with solid cells)
   int32_t sub, S;  // sub-cells per axis and per cell (1, 1 without)
   Flight() = default;
   __device__ __forceinline__ explicit Flight(const RunDev &R) {
@@ -690,6 +691,7 @@ struct Flight {
     n[1] = R.ny;
     n[2] = R.nz;
     solid = R.has_solid;
+    mask = R.mask;
   }
 };
 
@@ -702,7 +704,20 @@ template <typename real, int DIM, bool SUB = true>
 __device__ __forceinline__ int32_t flight_cell(const Flight<real> &F, const real (&pos)[3], const real (&vel)[3]) {
   real out[3];
   bool fast = free_flight<real, DIM>(F.dt, F.L, pos, vel, out);
-  if (F.solid && fast) fast = !near_solid<real, DIM>(pos, out, F.slo, F.shi);
+  if (F.solid && fast && near_solid<real, DIM>(pos, out, F.slo, F.shi)) {
+    // near the body's box: still free if the flight moves at most one cell
+    // along each axis from a cell with no solid cell within two cells (every
+    // cell it touches, or its end rounds into, is then at least one cell
+    // away from a solid one; runs with solid cells have no sub-cells, so the
+    // bins are the cells)
+    bool short_flight = true;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) short_flight = short_flight && fabs(out[a] - pos[a]) * F.inv[a] <= (real)1;
+    const int32_t ix = axis_index(pos[0], F.inv[0], F.n[0]);
+    const int32_t iy = axis_index(pos[1], F.inv[1], F.n[1]);
+    const int32_t iz = (DIM == 3) ? axis_index(pos[2], F.inv[2], F.n[2]) : 0;
+    fast = short_flight && !(F.mask[((int64_t)iz * F.n[1] + iy) * F.n[0] + ix] & kMaskNearSolid);
+  }
   if (!fast) return kQueueBit;
   if constexpr (SUB) {
     if (F.sub > 1) return subcell_bin<real, DIM>(out, F.inv, F.n, F.sub, F.S);
