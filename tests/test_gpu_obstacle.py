@@ -31,6 +31,24 @@ def test_body3d_fp64_parity(dsmc_gpu, oracle_lib):
     assert O[0].info()["ngen"] > 0
 
 
+def test_large_sphere_fp64_parity(dsmc_gpu, oracle_lib):
+    """A sphere of radius ~7 cells: flights inside its box of solid cells
+    (widened by two) but starting three or more cells from every solid cell
+    take Motion's fast path instead of the full flight; step by step equal to
+    the oracle's full flight for every particle."""
+    from scipy.ndimage import binary_dilation
+    grid = (48, 24, 24)
+    runs = _body_runs(2, grid=grid, n_per_run=60_000, radius=0.3, seed=7)
+    m = np.asarray(runs[0].solid, bool).reshape(grid[2], grid[1], grid[0])
+    near = binary_dilation(m, structure=np.ones((5, 5, 5), bool))
+    idx = np.argwhere(m)
+    box = np.zeros_like(m)
+    lo, hi = idx.min(0) - 2, idx.max(0) + 3
+    box[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]] = True
+    assert (box & ~near).sum() > 1000      # cells of the box the fast path serves
+    _parity(dsmc_gpu, oracle_lib, runs, 4)
+
+
 def test_channel_with_block_2d_fp64_parity(dsmc_gpu, oracle_lib):
     """2-D channel (inflow, diffuse floor at T = 2, outflow) with a 4x6-cell
     block at T = 1.5 in the stream, started half full and drifting."""
