@@ -4,7 +4,8 @@ counting sort of the same cell array, bit for bit, step after step: after the
 initial fill and in steady stepping, with tiles of 256, 768 and 16384 slots
 (bucket items cut by many tile edges, buckets inside one tile), for a channel
 filling from vacuum (empty buckets, most particles generated), with
-sub-cells, in 2-D and 3-D; and after a run's state was replaced by a
+sub-cells, in 2-D and 3-D; at the largest two-level grid and the first
+grid past it (three LSD passes); and after a run's state was replaced by a
 shuffled, shorter one, where the next steps must equal those of a context
 restored from the same checkpoint and given the same state."""
 from dataclasses import replace
@@ -80,3 +81,16 @@ def test_two_level_sort_after_state_replacement(dsmc_gpu, oracle_lib, dim):
             np.testing.assert_array_equal(E.state(r), F.state(r), err_msg=f"run {r} step {s}")
     E.close()
     F.close()
+
+
+@pytest.mark.parametrize("ny", [2047, 2049])
+def test_largest_two_level_and_first_three_pass_grids(dsmc_gpu, oracle_lib, ny):
+    """2048 x 2047 cells (4,192,257 bins with the DEAD bin: the largest
+    two-level sort, 2047 buckets) and 2048 x 2049 (past 2^22 bins: three LSD
+    passes), 1M particles: the step's LCR is the stable counting sort."""
+    rs = replace(W.box(1_000_000, 1, 1, 1, seed=37, grid=(2048, ny)).runs[0], run_id=0)
+    E = dsmc_gpu.Ensemble([rs], [], state_fp64=False, n_groups=1)
+    for s in range(2):
+        E.step(1)
+        _check_lcr(E, [rs], oracle_lib, f"{ny} rows, step {s + 1}")
+    E.close()
