@@ -284,12 +284,14 @@ dsmc_status make_plan(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_opti
     R.bo = bo;
     R.to = to;
     R.nt = (int32_t)(cap / g.tile);
-    R.ndig = g.npass == 1 ? R.nbin + 1 : kDigits;
+    // first-pass digits: the bins (one pass), the buckets (two-level sort:
+    // rows and scans only as wide as the run has buckets), or 11 bits (LSD)
+    if (g.bucketed) R.nb = (R.nbin >> kDigitBits) + 1;
+    R.ndig = g.npass == 1 ? R.nbin + 1 : g.bucketed ? R.nb : kDigits;
     R.mo = mo;
     if (g.bucketed) {
       // the run's histogram rows: its tiles (first pass), then its bucket
       // items (second pass) in the same private region
-      R.nb = (R.nbin >> kDigitBits) + 1;
       R.icap = R.nt + R.nb;
       R.io = io;
       R.mo = (int64_t)io * kDigits;

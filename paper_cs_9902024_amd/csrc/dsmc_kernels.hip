@@ -829,7 +829,7 @@ __global__ __launch_bounds__(256) void k_motion(DevPtrs<real> d, int buf, int32_
   const int r = d.tile_run[t];
   const RunDev &R = d.runs[r];
   const int64_t tl = t - R.to;
-  const int D = SINGLE ? R.nbin + 1 : kDigits;
+  const int D = R.ndig;
   uint32_t *h = lds + wave * dstride;
   uint32_t *qb = lds + kWavesPerBlock * dstride + wave * kMotionQueueStage;  // staged queue entries
   uint32_t ql = 0;
@@ -935,7 +935,7 @@ __global__ __launch_bounds__(256) void k_motion_walls(DevPtrs<real> d, int buf, 
   if (nq == 0) return;
   const RunDev &R = d.runs[d.tile_run[t]];
   const uint32_t step = *d.step;
-  const int D = SINGLE ? R.nbin + 1 : kDigits;
+  const int D = R.ndig;
   uint32_t *Mt = d.hist + R.mo + (int64_t)(t - R.to) * D;
   const uint32_t *wq = d.wallq + (int64_t)t * tile;
   const Particles<real> P = d.P[buf];
@@ -1020,7 +1020,7 @@ __global__ __launch_bounds__(256) void k_digcount(IndexArgs a, int use_n_alive) 
   const RunDev &R = a.runs[r];
   const int64_t tl = t - R.to;
   const bool single = a.single;
-  const int D = single ? R.nbin + 1 : kDigits;
+  const int D = R.ndig;
   uint32_t *h = lds + wave * a.dstride;
   for (int q = lane; q < D; q += kWave) h[q] = 0;
   wave_sync();
@@ -1060,7 +1060,7 @@ __global__ __launch_bounds__(256) void k_digcount(IndexArgs a, int use_n_alive) 
 // (in place) and the digit total.  Coalesced across digits.
 __global__ __launch_bounds__(256) void k_colscan(IndexArgs a) {
   const RunDev &R = a.runs[a.r0 + blockIdx.y];
-  const int D = a.single ? R.nbin + 1 : kDigits;
+  const int D = R.ndig;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= D) return;
   uint32_t *col = a.hist + R.mo + q;
@@ -1104,7 +1104,7 @@ __global__ __launch_bounds__(256) void k_digscan(IndexArgs a) {
   const int r = a.r0 + (int)blockIdx.x;
   const RunDev &R = a.runs[r];
   const bool single = a.single;
-  const int D = single ? R.nbin + 1 : kDigits;
+  const int D = R.ndig;
   uint32_t *tot = a.tot + R.cbo;
   const int per = (D + 255) / 256;  // <= 8
   const int tid = threadIdx.x;
@@ -1403,7 +1403,7 @@ __global__ __launch_bounds__(256) void k_scatter(IndexArgs a) {
     r = a.tile_run[t];
     const RunDev &R = a.runs[r];
     const int64_t tl = t - R.to;
-    const int D = single ? R.nbin + 1 : kDigits;
+    const int D = R.ndig;
     const uint32_t *Mt = a.hist + R.mo + tl * D;
     const uint32_t *S = a.tot + R.cbo;
     init_cursors(cursor, S, Mt, D, D);
@@ -3390,6 +3390,7 @@ void launch_counting_sort(const int32_t *keys, int64_t n, int32_t nbins, int32_t
   rd.sub = 1;
   rd.S = 1;
   rd.nt = L.nt;
+  rd.ndig = L.D;
   RunDev *runs = (RunDev *)(w + L.off_run);
   int32_t *tile_run = (int32_t *)(w + L.off_tile_run);
   int32_t *ns = (int32_t *)(w + L.off_ns);
