@@ -209,7 +209,10 @@ dsmc_status dsmc_sync(dsmc_ctx *ctx);
 
 void dsmc_destroy(dsmc_ctx *ctx);
 
-/* Message of the last failed call on this context (NULL-safe; static text for NULL). */
+/* Message of the last failed call on this context; for NULL, of the last failed
+ * call on this thread that had no context to hold it (dsmc_required_bytes,
+ * dsmc_init_runs, dsmc_autotune).  The text stays valid until the next call on
+ * the context (or, for NULL, on the thread). */
 const char *dsmc_last_error(const dsmc_ctx *ctx);
 
 /* ---- inspection (tests, diagnostics); all synchronise ---------------------- */

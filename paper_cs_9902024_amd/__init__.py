@@ -123,7 +123,7 @@ def lib():
 
 def _check(st: int, where: str, ctx=None):
     if st != DSMC_OK:
-        msg = lib().dsmc_last_error(ctx).decode() if ctx else ""
+        msg = lib().dsmc_last_error(ctx).decode()
         raise DsmcError(st, where, msg)
 
 

@@ -752,6 +752,15 @@ dsmc_status set_err(dsmc_ctx *c, dsmc_status st, const std::string &m) {
   return st;
 }
 
+// Message of the last failed call on this thread that had no context to
+// hold it (dsmc_required_bytes, dsmc_init_runs, dsmc_autotune).
+thread_local std::string g_free_msg;
+
+dsmc_status free_fail(dsmc_status st, const std::string &m) {
+  g_free_msg = m;
+  return st;
+}
+
 dsmc_status check_hip(dsmc_ctx *c, hipError_t e, const char *what) {
   if (e == hipSuccess) return DSMC_OK;
   c->latched = DSMC_EDEVICE;
@@ -883,10 +892,11 @@ int find_ensemble(const dsmc_ctx *c, int32_t id) {
 extern "C" {
 
 dsmc_status dsmc_required_bytes(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_options *opt, size_t *bytes) {
-  if (!bytes) return DSMC_EINVAL;
+  if (!bytes) return free_fail(DSMC_EINVAL, "dsmc_required_bytes: null bytes");
   Plan P;
-  dsmc_status st = make_plan(runs, n_runs, opt, P, nullptr);
-  if (st) return st;
+  std::string msg;
+  dsmc_status st = make_plan(runs, n_runs, opt, P, &msg);
+  if (st) return free_fail(st, "dsmc_required_bytes: " + msg);
   *bytes = P.total;
   return DSMC_OK;
 }
@@ -901,11 +911,12 @@ dsmc_status dsmc_init_runs(const dsmc_run_spec *runs, int32_t n_runs, const dsmc
   dsmc_status st = make_plan(runs, n_runs, opt, c->plan, &msg);
   if (st) {
     delete c;
-    return st;
+    return free_fail(st, "dsmc_init_runs: " + msg);
   }
   if (!arena || ((uintptr_t)arena & 255) || arena_bytes < c->plan.total) {
     delete c;
-    return DSMC_ESIZE;
+    return free_fail(DSMC_ESIZE, "dsmc_init_runs: arena null, not 256-byte aligned or smaller than "
+                                 "dsmc_required_bytes");
   }
   c->arena = (char *)arena;
   c->stream = (hipStream_t)hip_stream;
@@ -955,6 +966,7 @@ dsmc_status dsmc_init_runs(const dsmc_run_spec *runs, int32_t n_runs, const dsmc
   }
   if (!st) st = sync_ctx(c);
   if (st) {
+    g_free_msg = "dsmc_init_runs: " + c->msg;
     free_streams(c);
     delete c;
     return st;
@@ -984,7 +996,13 @@ dsmc_status dsmc_step(dsmc_ctx *c, int32_t n_steps) {
         dsmc_status st = check_hip(c, hipStreamBeginCapture(gs, hipStreamCaptureModeRelaxed), "capture");
         if (st) return st;
         launch_one_step(c, c->buf, gs);
+        // a launch refused while capturing would be missing from the graph
+        const hipError_t le = hipGetLastError();
         st = check_hip(c, hipStreamEndCapture(gs, &gr), "end capture");
+        if (!st && le != hipSuccess) {
+          (void)hipGraphDestroy(gr);
+          st = check_hip(c, le, "launch(step, captured)");
+        }
         if (st) return st;
         st = check_hip(c, hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0), "graph instantiate");
         (void)hipGraphDestroy(gr);
@@ -1078,7 +1096,7 @@ void dsmc_destroy(dsmc_ctx *c) {
 }
 
 const char *dsmc_last_error(const dsmc_ctx *c) {
-  if (!c) return "no context";
+  if (!c) return g_free_msg.empty() ? "no context" : g_free_msg.c_str();
   return c->msg.empty() ? "ok" : c->msg.c_str();
 }
 
@@ -1738,8 +1756,9 @@ dsmc_status dsmc_autotune(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_
                           size_t arena_bytes, void *hip_stream, int32_t n_steps, const void *start,
                           size_t start_bytes, const char *tune_cache, dsmc_options *best,
                           double *best_ms_per_step) {
-  if (!best || n_steps < 1) return DSMC_EINVAL;
-  if ((start == nullptr) != (start_bytes == 0)) return DSMC_EINVAL;
+  if (!best || n_steps < 1) return free_fail(DSMC_EINVAL, "dsmc_autotune: null best or n_steps < 1");
+  if ((start == nullptr) != (start_bytes == 0))
+    return free_fail(DSMC_EINVAL, "dsmc_autotune: start and start_bytes disagree");
   size_t need = 0;
   dsmc_status st = dsmc_autotune_bytes(runs, n_runs, opt, &need);
   if (st) return st;
@@ -1748,9 +1767,10 @@ dsmc_status dsmc_autotune(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_
   uint32_t start_step = 0;  // the tuned state: the initial fill, or the checkpoint's step
   if (start) {
     CkptHeader h{};
-    if (start_bytes < sizeof h) return DSMC_EINVAL;
+    if (start_bytes < sizeof h) return free_fail(DSMC_EINVAL, "dsmc_autotune: start is not a checkpoint");
     memcpy(&h, start, sizeof h);
-    if (memcmp(h.magic, kCkptMagic, 8) != 0 || (size_t)h.total != start_bytes) return DSMC_EINVAL;
+    if (memcmp(h.magic, kCkptMagic, 8) != 0 || (size_t)h.total != start_bytes)
+      return free_fail(DSMC_EINVAL, "dsmc_autotune: start is not a checkpoint");
     start_step = h.step;
   }
   std::string key = tune_cache ? tune_key(runs, n_runs, base) : std::string();
@@ -1796,6 +1816,12 @@ dsmc_status dsmc_autotune(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_
           pick = o;
         }
       }
+    }
+    if (st) {
+      char what[160];
+      snprintf(what, sizeof what, "dsmc_autotune: candidate tile_chunks %d collide_mode %d n_streams %d sched %d: ",
+               o.tile_chunks, o.collide_mode, o.n_streams, o.sched);
+      g_free_msg = what + std::string(c ? dsmc_last_error(c) : g_free_msg.c_str());
     }
     if (c) dsmc_destroy(c);
     if (st) break;

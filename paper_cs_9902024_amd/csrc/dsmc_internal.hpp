@@ -10,6 +10,8 @@ namespace dsmc {
 
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;          // 256-thread blocks
+constexpr int kMaxGridBlocks = 1 << 23;    // workgroups per launch over items (2^31 work-items at 256 each;
+                                           // a dispatch holds fewer than 2^32)
 constexpr int kCollideWaves = 2;           // waves per block of the collide kernel
 constexpr int kCollideCapF32 = 1280;       // particles staged in LDS per collide wavefront
 constexpr int kCollideCapF64 = 1024;

@@ -2738,9 +2738,9 @@ DSMC_PIPE_KERNEL(3, true, true)
 #undef DSMC_PIPE_KERNEL
 
 template <typename real>
-__global__ __launch_bounds__(256) void k_sample_cells(DevPtrs<real> d, int buf, int64_t n_cells) {
+__global__ __launch_bounds__(256) void k_sample_cells(DevPtrs<real> d, int buf, int64_t gc0, int64_t n_cells) {
   // one wavefront per cell, as in the Interaction kernels
-  const int64_t gc = (int64_t)blockIdx.x * (256 / kWave) + wave_index();
+  const int64_t gc = gc0 + (int64_t)blockIdx.x * (256 / kWave) + wave_index();
   if (gc >= n_cells) return;
   const RunDev &R = d.runs[d.cgroup_run[gc >> 6]];
   const int32_t c = (int32_t)(gc - R.co);
@@ -3135,70 +3135,96 @@ static void lane_step(const Geometry &g, const LaneRange &L, int lane_id, const 
     TIMED(kKBinFinalize,
           hipLaunchKernelGGL(k_bin_finalize, dim3((n_runs + 255) / 256), dim3(256), 0, s, a, L.r1, 1));
   }
+  // Interaction.  A grid-mode launch has one workgroup per `per` items; more
+  // than kMaxGridBlocks workgroups are split into launches over consecutive
+  // item ranges (a dispatch holds fewer than 2^32 work-items).
+  auto for_chunks = [](int64_t i0, int64_t i1, int per, auto &&launch) {
+    const int64_t span = (int64_t)kMaxGridBlocks * per;
+    for (int64_t c0 = i0; c0 < i1; c0 += span) {
+      const int64_t c1 = std::min(c0 + span, i1);
+      launch(c0, c1, dim3((unsigned)((c1 - c0 + per - 1) / per)));
+    }
+  };
   if (L.it1 > L.it0) {
     const int64_t nblk = (L.it1 - L.it0 + kCollideWaves - 1) / kCollideWaves;
     const Sched sc = sched_of(g, d, 0, L, lane_id);
-    const int64_t grid = sched_grid(g, sc, 0, nblk, kCollideWaves);
     const size_t lb = (size_t)kCollideWaves * collide_wave_bytes<real>();
-    const dim3 gr((unsigned)grid), bl(kCollideWaves * 64);
-    if (sc.mode == kSchedGrid && !g.any_sub)
-      TIMED(kKCollide, hipLaunchKernelGGL((k_collide<real, DIM, false, false>), gr, bl, lb, s, d, buf, L.it0, L.it1,
-                                          sc));
-    else if (sc.mode == kSchedGrid)
-      TIMED(kKCollide, hipLaunchKernelGGL((k_collide<real, DIM, false, true>), gr, bl, lb, s, d, buf, L.it0, L.it1,
-                                          sc));
-    else if (!g.any_sub)
-      TIMED(kKCollide, hipLaunchKernelGGL((k_collide<real, DIM, true, false>), gr, bl, lb, s, d, buf, L.it0, L.it1,
-                                          sc));
-    else
-      TIMED(kKCollide, hipLaunchKernelGGL((k_collide<real, DIM, true, true>), gr, bl, lb, s, d, buf, L.it0, L.it1,
-                                          sc));
+    const dim3 bl(kCollideWaves * 64);
+    if (sc.mode == kSchedGrid) {
+      for_chunks(L.it0, L.it1, kCollideWaves, [&](int64_t c0, int64_t c1, dim3 gr) {
+        if (!g.any_sub)
+          TIMED(kKCollide, hipLaunchKernelGGL((k_collide<real, DIM, false, false>), gr, bl, lb, s, d, buf, c0, c1, sc));
+        else
+          TIMED(kKCollide, hipLaunchKernelGGL((k_collide<real, DIM, false, true>), gr, bl, lb, s, d, buf, c0, c1, sc));
+      });
+    } else {
+      const dim3 gr((unsigned)sched_grid(g, sc, 0, nblk, kCollideWaves));
+      if (!g.any_sub)
+        TIMED(kKCollide, hipLaunchKernelGGL((k_collide<real, DIM, true, false>), gr, bl, lb, s, d, buf, L.it0, L.it1,
+                                            sc));
+      else
+        TIMED(kKCollide, hipLaunchKernelGGL((k_collide<real, DIM, true, true>), gr, bl, lb, s, d, buf, L.it0, L.it1,
+                                            sc));
+    }
   }
   if (L.wi1 > L.wi0) {
     const int64_t nblk = (L.wi1 - L.wi0 + kWavesPerBlock - 1) / kWavesPerBlock;
     const Sched sc = sched_of(g, d, 1, L, lane_id);
-    const int64_t grid = sched_grid(g, sc, 1, nblk, kWavesPerBlock);
-    const dim3 gr((unsigned)grid), bl(256);
-    if (sc.mode == kSchedGrid && !g.any_sub)
-      TIMED(kKCollideWave, hipLaunchKernelGGL((k_collide_wave<real, DIM, false, false>), gr, bl, 0, s, d, buf, L.wi0,
-                                              L.wi1, sc));
-    else if (sc.mode == kSchedGrid)
-      TIMED(kKCollideWave, hipLaunchKernelGGL((k_collide_wave<real, DIM, false, true>), gr, bl, 0, s, d, buf, L.wi0,
-                                              L.wi1, sc));
-    else if (!g.any_sub)
-      TIMED(kKCollideWave, hipLaunchKernelGGL((k_collide_wave<real, DIM, true, false>), gr, bl, 0, s, d, buf, L.wi0,
-                                              L.wi1, sc));
-    else
-      TIMED(kKCollideWave, hipLaunchKernelGGL((k_collide_wave<real, DIM, true, true>), gr, bl, 0, s, d, buf, L.wi0,
-                                              L.wi1, sc));
+    const dim3 bl(256);
+    if (sc.mode == kSchedGrid) {
+      for_chunks(L.wi0, L.wi1, kWavesPerBlock, [&](int64_t c0, int64_t c1, dim3 gr) {
+        if (!g.any_sub)
+          TIMED(kKCollideWave, hipLaunchKernelGGL((k_collide_wave<real, DIM, false, false>), gr, bl, 0, s, d, buf, c0,
+                                                  c1, sc));
+        else
+          TIMED(kKCollideWave, hipLaunchKernelGGL((k_collide_wave<real, DIM, false, true>), gr, bl, 0, s, d, buf, c0,
+                                                  c1, sc));
+      });
+    } else {
+      const dim3 gr((unsigned)sched_grid(g, sc, 1, nblk, kWavesPerBlock));
+      if (!g.any_sub)
+        TIMED(kKCollideWave, hipLaunchKernelGGL((k_collide_wave<real, DIM, true, false>), gr, bl, 0, s, d, buf, L.wi0,
+                                                L.wi1, sc));
+      else
+        TIMED(kKCollideWave, hipLaunchKernelGGL((k_collide_wave<real, DIM, true, true>), gr, bl, 0, s, d, buf, L.wi0,
+                                                L.wi1, sc));
+    }
   }
   if (L.ci1 > L.ci0) {
     const int64_t nblk = L.ci1 - L.ci0;
     const Sched sc = sched_of(g, d, 2, L, lane_id);
-    const int64_t grid = sched_grid(g, sc, 2, nblk, 1);
     const bool grid_mode = sc.mode == kSchedGrid;
+    const dim3 bl(256);
     if constexpr (std::is_same<real, float>::value) {
-      const dim3 gr((unsigned)grid), bl(256);
-      if (grid_mode && !g.any_sub)
-        TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_pipe<DIM, false, false>), gr, bl, 0, s, d, buf, L.ci0,
-                                                L.ci1, sc));
-      else if (grid_mode)
-        TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_pipe<DIM, false, true>), gr, bl, 0, s, d, buf, L.ci0,
-                                                L.ci1, sc));
-      else if (!g.any_sub)
-        TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_pipe<DIM, true, false>), gr, bl, 0, s, d, buf, L.ci0,
-                                                L.ci1, sc));
-      else
-        TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_pipe<DIM, true, true>), gr, bl, 0, s, d, buf, L.ci0,
-                                                L.ci1, sc));
+      if (grid_mode) {
+        for_chunks(L.ci0, L.ci1, 1, [&](int64_t c0, int64_t c1, dim3 gr) {
+          if (!g.any_sub)
+            TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_pipe<DIM, false, false>), gr, bl, 0, s, d, buf, c0, c1,
+                                                    sc));
+          else
+            TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_pipe<DIM, false, true>), gr, bl, 0, s, d, buf, c0, c1,
+                                                    sc));
+        });
+      } else {
+        const dim3 gr((unsigned)sched_grid(g, sc, 2, nblk, 1));
+        if (!g.any_sub)
+          TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_pipe<DIM, true, false>), gr, bl, 0, s, d, buf, L.ci0,
+                                                  L.ci1, sc));
+        else
+          TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_pipe<DIM, true, true>), gr, bl, 0, s, d, buf, L.ci0,
+                                                  L.ci1, sc));
+      }
     } else {
       const size_t cb = (size_t)collide_cell_bytes<real>();
       if (grid_mode)
-        TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_cell<real, DIM, false>), dim3((unsigned)grid), dim3(256),
-                                                cb, s, d, buf, L.ci0, L.ci1, sc));
+        for_chunks(L.ci0, L.ci1, 1, [&](int64_t c0, int64_t c1, dim3 gr) {
+          TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_cell<real, DIM, false>), gr, bl, cb, s, d, buf, c0, c1,
+                                                  sc));
+        });
       else
-        TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_cell<real, DIM, true>), dim3((unsigned)grid), dim3(256),
-                                                cb, s, d, buf, L.ci0, L.ci1, sc));
+        TIMED(kKCollideCell, hipLaunchKernelGGL((k_collide_cell<real, DIM, true>),
+                                                dim3((unsigned)sched_grid(g, sc, 2, nblk, 1)), bl, cb, s, d, buf,
+                                                L.ci0, L.ci1, sc));
     }
   }
 }
@@ -3250,8 +3276,13 @@ void launch_step(const Geometry &g, const DevPtrs<real> &d, int buf, hipStream_t
 
 template <typename real>
 void launch_sample(const Geometry &g, const DevPtrs<real> &d, int buf, int slot, hipStream_t s, const Prof *prof) {
-  TIMED(kKSample, hipLaunchKernelGGL(k_sample_cells<real>, dim3((unsigned)((g.n_cells + 3) / 4)), dim3(256), 0,
-                                     s, d, buf, g.n_cells));
+  // (a dispatch holds fewer than 2^32 work-items: kMaxGridBlocks workgroups
+  // of four cells at a time)
+  for (int64_t c0 = 0; c0 < g.n_cells; c0 += (int64_t)kMaxGridBlocks * 4) {
+    const int64_t nb = std::min<int64_t>((g.n_cells - c0 + 3) / 4, kMaxGridBlocks);
+    TIMED(kKSample, hipLaunchKernelGGL(k_sample_cells<real>, dim3((unsigned)nb), dim3(256), 0, s, d, buf, c0,
+                                       g.n_cells));
+  }
   TIMED(kKAccumulate, hipLaunchKernelGGL(k_accumulate<real>, dim3(grid_for(g.acc_stride)), dim3(256), 0, s, d, slot,
                                          g.acc_stride, g.n_eg));
 }

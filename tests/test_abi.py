@@ -125,6 +125,15 @@ def test_invalid_specs_are_rejected_on_the_host(dsmc, field, value):
     assert e.value.status == -1
 
 
+def test_failures_without_a_context_carry_a_message(dsmc):
+    from dataclasses import replace
+    rs = replace(W.plain_box().runs[0], omega=0.3)
+    with pytest.raises(dsmc.DsmcError) as e:
+        _bytes(dsmc, W.plain_box().with_runs([rs]))
+    assert "omega" in str(e.value)
+    assert "omega" in dsmc.lib().dsmc_last_error(None).decode()
+
+
 def test_inflow_only_on_minus_x(dsmc):
     from dataclasses import replace
     rs = W.channel_run(nx=16, ny=8, lx=1.0)

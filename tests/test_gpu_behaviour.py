@@ -381,3 +381,24 @@ def test_autotune_from_a_checkpoint(dsmc_gpu, tmp_path):
     with pytest.raises(dsmc_gpu.DsmcError) as e:
         dsmc_gpu.Ensemble.autotune(runs, [60], n_groups=3, n_steps=1, start=ck)
     assert e.value.status == -1
+
+
+def test_forced_block_mode_beyond_one_launch(dsmc_gpu):
+    """3000 x 3000 cells with the block-per-cell mode forced: 9M cell items
+    are more workgroups than one launch takes (2^23), so the Interaction
+    kernel goes out as two launches over consecutive items, eagerly and in a
+    graph; the run equals the lane-per-cell mode's, sample sums included."""
+    import torch
+    rs = replace(W.box(1_000_000, 1, 1, 1, seed=38, grid=(3000, 3000)).runs[0], run_id=0)
+    for graph in (False, True):
+        A = dsmc_gpu.Ensemble([rs], [2], state_fp64=False, n_groups=1, collide_mode=1, use_graph=graph)
+        B = dsmc_gpu.Ensemble([rs], [2], state_fp64=False, n_groups=1, collide_mode=2, use_graph=graph)
+        A.step(2)
+        B.step(2)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(A.state(0), B.state(0))
+        np.testing.assert_array_equal(A.cell_state(0)["ncoll"], B.cell_state(0)["ncoll"])
+        np.testing.assert_array_equal(A.accum(0), B.accum(0))
+        A.close()
+        B.close()
+
