@@ -121,9 +121,14 @@ def lib():
     return _lib
 
 
+# calls whose failures without a context leave their message for
+# dsmc_last_error(NULL)
+_FREE_MSG = ("dsmc_required_bytes", "dsmc_init_runs", "dsmc_autotune", "dsmc_autotune_bytes")
+
+
 def _check(st: int, where: str, ctx=None):
     if st != DSMC_OK:
-        msg = lib().dsmc_last_error(ctx).decode()
+        msg = lib().dsmc_last_error(ctx).decode() if ctx or where in _FREE_MSG else ""
         raise DsmcError(st, where, msg)
 
 

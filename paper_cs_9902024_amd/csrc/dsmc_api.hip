@@ -903,10 +903,10 @@ dsmc_status dsmc_required_bytes(const dsmc_run_spec *runs, int32_t n_runs, const
 
 dsmc_status dsmc_init_runs(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_options *opt, void *arena,
                            size_t arena_bytes, void *hip_stream, dsmc_ctx **out) {
-  if (!out) return DSMC_EINVAL;
+  if (!out) return free_fail(DSMC_EINVAL, "dsmc_init_runs: null out");
   *out = nullptr;
   dsmc_ctx *c = new (std::nothrow) dsmc_ctx();
-  if (!c) return DSMC_EINVAL;
+  if (!c) return free_fail(DSMC_EINVAL, "dsmc_init_runs: out of host memory");
   std::string msg;
   dsmc_status st = make_plan(runs, n_runs, opt, c->plan, &msg);
   if (st) {
@@ -1735,12 +1735,12 @@ void tune_cache_add(const char *path, const std::string &key, const dsmc_options
 extern "C" {
 
 dsmc_status dsmc_autotune_bytes(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_options *opt, size_t *bytes) {
-  if (!bytes) return DSMC_EINVAL;
+  if (!bytes) return free_fail(DSMC_EINVAL, "dsmc_autotune_bytes: null bytes");
   dsmc_options base{};
   if (opt) base = *opt;
   std::string msg;
   dsmc_status st = validate(runs, n_runs, &base, &msg);
-  if (st) return st;
+  if (st) return free_fail(st, "dsmc_autotune_bytes: " + msg);
   size_t most = 0;
   for (const dsmc_options &o : tune_candidates(runs, n_runs, base)) {
     size_t b = 0;
@@ -1786,12 +1786,14 @@ dsmc_status dsmc_autotune(const dsmc_run_spec *runs, int32_t n_runs, const dsmc_
       return DSMC_OK;
     }
   }
-  if (!arena || ((uintptr_t)arena & 255) || arena_bytes < need) return DSMC_ESIZE;
+  if (!arena || ((uintptr_t)arena & 255) || arena_bytes < need)
+    return free_fail(DSMC_ESIZE, "dsmc_autotune: arena null, not 256-byte aligned or smaller than "
+                                 "dsmc_autotune_bytes");
   hipStream_t s = (hipStream_t)hip_stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
-    return DSMC_EDEVICE;
+    return free_fail(DSMC_EDEVICE, "dsmc_autotune: hipEventCreate failed");
   }
   double best_ms = -1.0;
   dsmc_options pick = base;
