@@ -11,7 +11,8 @@ at any size.
   step particle by particle (FP32 vs FP64 rounding only).
 - Sampling: upstream of the body the ensemble moments equal the free-stream
   values (density, drift, temperature) the inflow and the fill are drawn
-  from; solid cells hold no particles.
+  from; solid cells hold no particles; an explicit sample over all 64M cells
+  adds exactly the per-cell sums of the particle state.
 """
 import math
 
@@ -118,3 +119,25 @@ def test_body3d_full_size_free_stream_moments(body):
     assert abs(np.mean(m[up, 1]) / rs.inflow_U - 1) < 0.002
     assert abs(np.mean(m[up, 4]) - rs.inflow_T) < 0.005
     assert np.all(np.abs(m[up, 2:4]).mean(axis=0) < 0.05)
+
+
+def test_body3d_full_size_explicit_sample_matches_the_particles(body):
+    """dsmc_sample over 64M cells (more workgroups than one launch takes, so
+    the sampling kernel goes out in two launches): the sums it adds to a
+    slot equal, run by run (each run its own group), per-cell sums of the
+    particle state computed on the host."""
+    wl, E = body
+    rs = wl.runs[0]
+    nc = rs.n_cells
+    before = E.accum(1)
+    E.sample(1)
+    snap = E.accum(1) - before
+    for r in SAMPLED:
+        st = E.state(r)
+        _, _, start = E.lcr(r)
+        cells = np.repeat(np.arange(nc), np.diff(start[: nc + 1]))
+        assert cells.size == st.shape[1]
+        u, v, w = st[3], st[4], st[5]
+        ref = np.stack([np.bincount(cells, weights=x, minlength=nc)
+                        for x in (np.ones_like(u), u, v, w, u * u, v * v, w * w)], axis=1)
+        np.testing.assert_allclose(snap[r], ref, rtol=1e-9, atol=1e-6, err_msg=f"run {r}")
